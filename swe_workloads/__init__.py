@@ -1,0 +1,364 @@
+"""Seeded synthetic problem generators for the steady shallow-water Newton-multigrid path.
+
+This module only *describes* problems: domains, analytic bottom and width
+functions (with their derivatives), boundary data, grid sizes, solver parameters
+and initial guesses.  It holds none of the discretisation's arithmetic (no
+reconstruction, flux, quadrature, Jacobian or multigrid step), so both the CPU
+oracle and the GPU path can take their inputs from it without sharing code.
+
+Problem shapes follow the paper's experiments (section 5): the smooth
+subcritical channel of 5.1.1 (eq. 26-27), the bump of 5.1.2 (eq. 28) with
+optional contraction, and the wedge jump of 5.2.2.  Random draws use
+``numpy.random.default_rng([cfg, i])`` in the documented order.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional, Sequence, Tuple
+
+import numpy as np
+
+G = 9.812  # gravitational acceleration used throughout the paper (section 2)
+
+# boundary-condition kinds (shared vocabulary; numeric codes match the C headers)
+BC_DISCHARGE = 0   # prescribed discharge Q (hu); depth extrapolated unless supercritical
+BC_DEPTH = 1       # prescribed depth h; discharge extrapolated; free if supercritical
+BC_EXTRAP = 2      # zeroth-order extrapolation of all conserved variables
+BC_WALL = 3        # reflective wall: mirror with the normal momentum negated
+BC_STATE = 4       # prescribed full state (h, hu, hv) -- supercritical inflow (2D)
+
+Fn = Callable[[np.ndarray], Tuple[np.ndarray, np.ndarray]]
+
+
+@dataclasses.dataclass
+class BC:
+    kind: int
+    q: float = 0.0   # discharge (1D) / normal discharge
+    h: float = 0.0   # depth
+    u: float = 0.0   # 2D state inflow velocity
+    v: float = 0.0
+
+
+@dataclasses.dataclass
+class Params:
+    """Solver constants of section 5 (alpha, tau, nu1..nu3, omega) plus eps and tol."""
+    alpha: float = 3.0
+    tau: float = 0.6
+    eps: float = 0.01
+    omega: float = 1.0
+    nu1: int = 2
+    nu2: int = 2
+    nu3: int = 2
+    tol: float = 1e-10
+    n_max: int = 2000
+
+
+@dataclasses.dataclass
+class Problem1D:
+    """Quasi-1D steady SWE problem (eq. 3-4) on a uniform grid of ``n`` cells."""
+    name: str
+    x0: float
+    x1: float
+    n: int
+    levels: int                 # L+1 grid levels of the multigrid hierarchy
+    bottom: Fn                  # x -> (b(x), b_x(x))
+    width: Fn                   # x -> (sigma(x), sigma_x(x))
+    bc_left: BC
+    bc_right: BC
+    params: Params
+    surface0: float = 1.0       # initial guess: h + b = surface0 (point values at centres)
+    q0: float = 1.0             # initial guess: Q = q0
+    g: float = G
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def dx(self) -> float:
+        return (self.x1 - self.x0) / self.n
+
+    def centres(self) -> np.ndarray:
+        return self.x0 + (np.arange(self.n) + 0.5) * self.dx
+
+    def initial_guess(self) -> np.ndarray:
+        """U0 = (H, Q)[2, n]: still surface at ``surface0`` and uniform discharge ``q0``,
+        sampled at cell centres (an initial guess need not be a cell average)."""
+        x = self.centres()
+        b, _ = self.bottom(x)
+        s, _ = self.width(x)
+        U = np.empty((2, self.n))
+        U[0] = s * (self.surface0 - b)
+        U[1] = self.q0
+        return U
+
+
+@dataclasses.dataclass
+class Problem2D:
+    """2D steady SWE problem (eq. 1-2) on an ``nx`` x ``ny`` grid."""
+    name: str
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    nx: int
+    ny: int
+    levels: int
+    bottom: Callable[[np.ndarray, np.ndarray], Tuple[np.ndarray, np.ndarray, np.ndarray]]
+    bc: Sequence[BC]            # left, right, bottom, top
+    params: Params
+    wall_x: float = 0.0         # bottom side: extrapolation for x < wall_x, wall beyond
+    init_state: Tuple[float, float, float] = (1.0, 1.0, 0.0)  # (h, hu, hv) initial guess
+    g: float = G
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def dx(self) -> float:
+        return (self.x1 - self.x0) / self.nx
+
+    @property
+    def dy(self) -> float:
+        return (self.y1 - self.y0) / self.ny
+
+    def initial_guess(self) -> np.ndarray:
+        U = np.empty((3, self.ny, self.nx))
+        U[0] = self.init_state[0]
+        U[1] = self.init_state[1]
+        U[2] = self.init_state[2]
+        return U
+
+
+# ----------------------------------------------------------------------------------------
+# analytic bottoms and widths
+# ----------------------------------------------------------------------------------------
+
+def flat(x):
+    x = np.asarray(x, dtype=np.float64)
+    return np.zeros_like(x), np.zeros_like(x)
+
+
+def unit_width(x):
+    x = np.asarray(x, dtype=np.float64)
+    return np.ones_like(x), np.zeros_like(x)
+
+
+def gaussian_bump(A: float, c: float, w2: float = 1.0) -> Fn:
+    """b = A exp(-(x-c)^2 / w2)."""
+    def f(x):
+        x = np.asarray(x, dtype=np.float64)
+        e = np.exp(-(x - c) ** 2 / w2)
+        return A * e, A * e * (-2.0 * (x - c) / w2)
+    return f
+
+
+def e1_bottom(x):
+    """Bottom of the smooth subcritical test, eq. (26)."""
+    x = np.asarray(x, dtype=np.float64)
+    e1 = np.exp(-(x + 1.0) ** 2 / 2.0)
+    e2 = np.exp(-(x - 1.5) ** 2)
+    b = 0.2 * e1 + 0.3 * e2
+    bx = 0.2 * e1 * (-(x + 1.0)) + 0.3 * e2 * (-2.0 * (x - 1.5))
+    return b, bx
+
+
+def parabolic_bump(scale: float = 1.0) -> Fn:
+    """Bump of eq. (28), scaled: b = s*max(0, 0.2 - 0.05 (x-10)^2); one-sided derivative 0
+    outside [8, 12]."""
+    def f(x):
+        x = np.asarray(x, dtype=np.float64)
+        inside = np.abs(x - 10.0) < 2.0
+        b = np.where(inside, scale * (0.2 - 0.05 * (x - 10.0) ** 2), 0.0)
+        bx = np.where(inside, scale * (-0.1 * (x - 10.0)), 0.0)
+        return b, bx
+    return f
+
+
+def cosine_contraction(sigma0: float, xl: float, xr: float) -> Fn:
+    """Width contraction of section 5.1.2: 1 - s0 (1 + cos(2 pi (x - xm)/(xr - xl))) on [xl, xr]."""
+    def f(x):
+        x = np.asarray(x, dtype=np.float64)
+        inside = (x >= xl) & (x <= xr)
+        k = 2.0 * math.pi / (xr - xl)
+        arg = k * (x - 0.5 * (xl + xr))
+        s = np.where(inside, 1.0 - sigma0 * (1.0 + np.cos(arg)), 1.0)
+        sx = np.where(inside, sigma0 * k * np.sin(arg), 0.0)
+        return s, sx
+    return f
+
+
+def sine_width(kw: int, length: float = 25.0, amp: float = 0.2) -> Fn:
+    """sigma = 1 + amp sin(2 pi k x / length)."""
+    def f(x):
+        x = np.asarray(x, dtype=np.float64)
+        k = 2.0 * math.pi * kw / length
+        return 1.0 + amp * np.sin(k * x), amp * k * np.cos(k * x)
+    return f
+
+
+def eps_for_n(n: int) -> float:
+    """Perturbation of the finite-difference Jacobian by grid size (section 5.1): 0.2, 0.15,
+    0.1, 0.05 for 96..768 cells, 0.01 finer; sizes between the listed ones take the value of
+    the next listed size up."""
+    if n <= 128:
+        return 0.2
+    if n <= 256:
+        return 0.15
+    if n <= 512:
+        return 0.1
+    if n <= 1024:
+        return 0.05
+    return 0.01
+
+
+# ----------------------------------------------------------------------------------------
+# problems of the paper and the seeded configurations
+# ----------------------------------------------------------------------------------------
+
+def e1_problem(n: int, levels: int = 4, params: Optional[Params] = None) -> Problem1D:
+    """Section 5.1.1: sigma = 1, bottom eq. (26) on [-10, 10]; hu = 1 imposed upstream,
+    h = 1 downstream."""
+    p = params or Params(eps=eps_for_n(n), tol=1e-11)
+    return Problem1D("e1", -10.0, 10.0, n, levels, e1_bottom, unit_width,
+                     BC(BC_DISCHARGE, q=1.0), BC(BC_DEPTH, h=1.0), p,
+                     surface0=1.0, q0=1.0)
+
+
+def config1(i: int) -> Problem1D:
+    """Smooth subcritical channel, [0,25], N=200, 3 levels.  Draws (in order) from
+    default_rng([1, i]): A ~ U(0.05, 0.2), q ~ U(4, 4.5), h_out ~ U(1.8, 2.2),
+    omega ~ U(1, 1.5)."""
+    rng = np.random.default_rng([1, i])
+    A = rng.uniform(0.05, 0.2)
+    q = rng.uniform(4.0, 4.5)
+    h_out = rng.uniform(1.8, 2.2)
+    omega = rng.uniform(1.0, 1.5)
+    p = Params(eps=eps_for_n(200), omega=omega)
+    return Problem1D(f"cfg1[{i}]", 0.0, 25.0, 200, 3, gaussian_bump(A, 10.0), unit_width,
+                     BC(BC_DISCHARGE, q=q), BC(BC_DEPTH, h=h_out), p,
+                     surface0=h_out, q0=q, meta=dict(A=A, q=q, h_out=h_out, omega=omega))
+
+
+def config2(i: int, variant: str = "sub", n: int = 12800, levels: int = 8) -> Problem1D:
+    """Flow over the eq. (28) hump on [0,25] scaled by s ~ U(0.8, 1.2) from default_rng([2, i]);
+    subcritical (q = 4.42, h_out = 2) or transcritical (q = 1.53, h_out = 0.66)."""
+    rng = np.random.default_rng([2, i])
+    s = rng.uniform(0.8, 1.2)
+    if variant == "sub":
+        q, h_out = 4.42, 2.0
+    elif variant == "trans":
+        q, h_out = 1.53, 0.66
+    else:
+        raise ValueError(variant)
+    p = Params(eps=eps_for_n(n))
+    return Problem1D(f"cfg2-{variant}[{i}]", 0.0, 25.0, n, levels, parabolic_bump(s), unit_width,
+                     BC(BC_DISCHARGE, q=q), BC(BC_DEPTH, h=h_out), p,
+                     surface0=h_out, q0=q, meta=dict(s=s, q=q, h_out=h_out, variant=variant))
+
+
+def _subcritical_everywhere(q, h_out, bottom, width, margin=0.02, x0=0.0, x1=25.0):
+    """True if the flow with discharge q and downstream depth h_out stays subcritical over the
+    whole channel with the given relative energy margin (specific-energy test per unit width)."""
+    x = np.linspace(x0, x1, 4001)
+    b, _ = bottom(x)
+    s, _ = width(x)
+    b_out, _ = bottom(np.array([x1]))
+    s_out, _ = width(np.array([x1]))
+    E0 = h_out + b_out[0] + (q / (s_out[0] * h_out)) ** 2 / (2 * G)
+    qs = q / s                                   # discharge per unit width
+    hc = (qs * qs / G) ** (1.0 / 3.0)            # critical depth
+    Emin = 1.5 * hc + b                          # minimum specific energy + bottom
+    return bool(np.all(E0 > (1.0 + margin) * Emin))
+
+
+def config4_instance(i: int, n_min: int = 256, n_max: int = 16384):
+    """One instance of the uneven batch: N = m 2^k nearest to exp(U(ln n_min, ln n_max)) with
+    m in [32, 64); draws from default_rng([4, i]) in order: log-size, A, (q, h_out) redrawn
+    until subcritical with a 2% energy margin, k_w in {0, 1, 2}."""
+    rng = np.random.default_rng([4, i])
+    target = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
+    best = None
+    for k in range(0, 16):
+        for m in range(32, 64):
+            n = m << k
+            d = abs(math.log(n) - math.log(target))
+            if best is None or d < best[0]:
+                best = (d, n, k)
+    _, n, k = best
+    A = rng.uniform(0.05, 0.2)
+    kw = int(rng.integers(0, 3))
+    bottom = gaussian_bump(A, 10.0)
+    width = sine_width(kw) if kw > 0 else unit_width
+    rejections = 0
+    while True:
+        q = rng.uniform(1.5, 4.5)
+        h_out = rng.uniform(0.6, 2.2)
+        if _subcritical_everywhere(q, h_out, bottom, width):
+            break
+        rejections += 1
+    p = Params(eps=eps_for_n(n))
+    s_out = width(np.array([25.0]))[0][0]
+    return Problem1D(f"cfg4[{i}]", 0.0, 25.0, n, k + 1, bottom, width,
+                     BC(BC_DISCHARGE, q=q), BC(BC_DEPTH, h=h_out), p,
+                     surface0=h_out, q0=q,
+                     meta=dict(A=A, q=q, h_out=h_out, kw=kw, rejections=rejections, s_out=s_out))
+
+
+def wedge_problem(nx: int = 1024, ny: int = 512, levels: Optional[int] = None, seed: int = 0,
+                  n_bumps: int = 16, amp: float = 1e-3, nu: int = 20) -> Problem2D:
+    """Hydraulic jump over a wedge-like wall (section 5.2.2 rescaled): channel [0,40]x[0,30],
+    inflow h = 1, (u, v) = 8.57 (cos t, -sin t), t = 8.95 deg on the left and top; extrapolation
+    on the right; bottom side: extrapolation for x < 10, reflective wall beyond.  Flat bottom
+    plus ``n_bumps`` seeded Gaussians of amplitude ``amp`` (centres ~ U over the box, unit
+    variance).  Coarsest grid 8x4."""
+    th = math.radians(8.95)
+    u, v = 8.57 * math.cos(th), -8.57 * math.sin(th)
+    rng = np.random.default_rng([3, seed])
+    cx = rng.uniform(0.0, 40.0, n_bumps)
+    cy = rng.uniform(0.0, 30.0, n_bumps)
+
+    def bottom(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        b = np.zeros(np.broadcast(x, y).shape)
+        bx = np.zeros_like(b)
+        by = np.zeros_like(b)
+        for k in range(n_bumps):
+            e = amp * np.exp(-((x - cx[k]) ** 2 + (y - cy[k]) ** 2) / 2.0)
+            b += e
+            bx += -e * (x - cx[k])
+            by += -e * (y - cy[k])
+        return b, bx, by
+
+    if levels is None:
+        levels = 1
+        while (nx >> levels) >= 8 and (ny >> levels) >= 4 and (nx >> (levels - 1)) > 8:
+            levels += 1
+    inflow = BC(BC_STATE, h=1.0, u=u, v=v)
+    p = Params(eps=1e-6, omega=0.1, nu1=nu, nu2=nu, nu3=3)
+    return Problem2D("wedge", 0.0, 40.0, 0.0, 30.0, nx, ny, levels, bottom,
+                     [inflow, BC(BC_EXTRAP), BC(BC_EXTRAP), inflow], p, wall_x=10.0,
+                     init_state=(1.0, u, v), meta=dict(theta=th, seed=seed))
+
+
+def parabolic_bump_2d(nx: int = 16, ny: int = 8, levels: Optional[int] = None,
+                      nu: Optional[int] = None) -> Problem2D:
+    """Section 5.2.1: [-4,4]x[0,4], bottom eq. (29), hu = 1 inflow, h = 1 outflow,
+    reflective side walls; initial state eq. (30)."""
+    def bottom(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        r2 = x ** 2 + (y - 2.0) ** 2
+        inside = r2 < 1.0
+        b = np.where(inside, 0.4 - 0.4 * r2, 0.0)
+        bx = np.where(inside, -0.8 * x, 0.0)
+        by = np.where(inside, -0.8 * (y - 2.0), 0.0)
+        return b, bx, by
+
+    if levels is None:
+        levels = 1
+        while (nx >> levels) >= 8 and (ny >> levels) >= 4:
+            levels += 1
+    if nu is None:
+        nu = {16: 10, 32: 15, 64: 20}.get(nx, 20)
+    p = Params(eps=1e-6, omega=0.1, nu1=nu, nu2=nu, nu3=3)
+    return Problem2D("bump2d", -4.0, 4.0, 0.0, 4.0, nx, ny, levels, bottom,
+                     [BC(BC_DISCHARGE, q=1.0), BC(BC_DEPTH, h=1.0), BC(BC_WALL), BC(BC_WALL)], p,
+                     init_state=(1.0, 1.0, 0.0))
