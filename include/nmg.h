@@ -1,0 +1,164 @@
+/*
+ * nmg.h -- C ABI of libnmg, the MI355X (gfx950) Newton multigrid solver for steady shallow
+ * water equations with third-order WENO finite volumes and a simplified block Jacobian
+ * (Hu, Li, Wang, Wang, "A high-order Newton multigrid method with a simplified Jacobian for
+ * steady-state shallow water equations").
+ *
+ * Every entry point is extern "C", takes plain pointers and sizes, and never throws.  Device
+ * pointers are caller-owned device memory (hipMalloc or a torch tensor's data_ptr); host
+ * pointers are marked "host".  `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  All calls except nmg_newton_solve / nmg_plan_solve are asynchronous on `stream`;
+ * errors a kernel produces later surface on the next call that synchronises.  On failure a
+ * call returns a negative nmg_status and nmg_last_error() describes the cause (thread-local).
+ * Outputs never alias inputs.
+ *
+ * Data layout (all FP64 unless the precision field says otherwise):
+ *  - 1D state U: component-major [2][nx]: U[0*nx + j] = H_j = sigma h, U[1*nx + j] = Q_j
+ *    (section 2, eq. 3-4).  2D state: [3][ny][nx] = (h, hu, hv) (eq. 1-2).
+ *  - Residual R: same layout as U.  rn[j] = ||R_j||_1 (eq. 13).
+ *  - Jacobian J (1D): block-entry-major [nb][2][2][nx]: J[((b*2 + l)*2 + m)*nx + j] =
+ *    dR_j^l / dU_i^m with i = j + b - nb/2; nb = 3 (simplified J3) or 5 (full J5).
+ *    Blocks whose column cell lies outside the grid are zero.
+ *  - 2D Jacobian J9: [9][3][3][ny][nx], blocks ordered (centre, x-2, x-1, x+1, x+2, y-2, y-1,
+ *    y+1, y+2) following eq. (21).
+ */
+#ifndef NMG_H
+#define NMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nmg_status;
+#define NMG_OK 0
+#define NMG_NOT_CONVERGED 1   /* result valid, but res >= tol after n_max Newton steps */
+#define NMG_EINVAL (-1)       /* bad argument: null pointer, size not m*2^(levels-1), ... */
+#define NMG_ENOMEM_WS (-2)    /* workspace smaller than nmg_workspace_bytes() */
+#define NMG_EHIP (-3)         /* HIP launch or runtime error */
+#define NMG_ENONFINITE (-4)   /* NaN/Inf residual, or non-positive depth */
+
+/* boundary kinds (per side) */
+#define NMG_BC_DISCHARGE 0    /* prescribed discharge q; depth extrapolated unless supercritical (then h if > 0) */
+#define NMG_BC_DEPTH 1        /* prescribed depth h when subcritical; discharge extrapolated */
+#define NMG_BC_EXTRAP 2       /* zeroth-order extrapolation */
+#define NMG_BC_WALL 3         /* reflective: mirror, normal momentum negated */
+#define NMG_BC_STATE 4        /* prescribed state (h, u, v) (2D supercritical inflow) */
+
+/* precision of the Jacobian and multigrid */
+#define NMG_FP64 0
+#define NMG_FP32_MG 1         /* J, D^-1, rhs and dU in FP32; residual, update and test in FP64 */
+
+typedef struct {
+    int32_t kind;
+    int32_t pad;
+    double q, h, u, v;
+} nmg_bc;
+
+/* Problem description (host struct; geometry arrays are device pointers).
+ * 1D (dim = 1, section 3): nx cells on [x0, x1]; bc[0] left, bc[1] right.
+ *   sig_face [nx+1]: channel width sigma at faces x_{j-1/2}, j = 0..nx.
+ *   sig_gp, sigx_gp, bx_gp [2*nx]: sigma, d sigma/dx and d b/dx at the two Gauss points
+ *   x_j -/+ dx/(2 sqrt 3) of cell j (entries 2j, 2j+1) -- the points of eq. (9).
+ * 2D (dim = 2, section 4): nx*ny cells on [x0,x1]x[y0,y1]; bc[0..3] = left, right, bottom, top;
+ *   the bottom side is EXTRAP for x < wall_x and WALL beyond when bc[2].kind == NMG_BC_WALL
+ *   and wall_x > x0.  bx_gp, by_gp [ny][nx][2][2]: b_x, b_y at the tensor Gauss points
+ *   (y point beta, x point gamma) of each cell.
+ * levels = L + 1 grid levels (eq. 15 / 23): nx (and ny) must be divisible by 2^(levels-1).
+ * jac = 3 or 5 (1D), 9 (2D): which Jacobian blocks are assembled (section 3.3 / 4.1). */
+typedef struct {
+    int32_t dim, nx, ny, levels, jac, pad;
+    double x0, x1, y0, y1, g;
+    nmg_bc bc[4];
+    double wall_x;
+    const double *sig_face;
+    const double *sig_gp;
+    const double *sigx_gp;
+    const double *bx_gp;
+    const double *by_gp;
+} nmg_desc;
+
+/* Solver parameters (section 3.2, 3.4, 5): alpha regularisation (eq. 13), tau damping
+ * (eq. 14), eps FD perturbation (eq. 12), omega SOR relaxation (eq. 19/22), nu1/nu2 symmetric
+ * smoothing steps, nu3 V-cycles per Newton step, tol on res = mean ||R_j||_1, n_max Newton
+ * steps.  check_every: Newton steps between host reads of the convergence state in
+ * nmg_newton_solve / nmg_plan_solve (>= 1). */
+typedef struct {
+    double alpha, tau, eps, omega, tol;
+    int32_t nu1, nu2, nu3, n_max;
+    int32_t precision;
+    int32_t check_every;
+} nmg_params;
+
+typedef struct {
+    int32_t iters;     /* Newton steps taken */
+    int32_t status;    /* NMG_OK, NMG_NOT_CONVERGED or NMG_ENONFINITE */
+    double res;        /* final res */
+} nmg_stats;
+
+/* Bytes of device workspace nmg_mg_vcycle and nmg_newton_solve need for this problem
+ * (multigrid hierarchy, Jacobian, residual buffers, tables).  0 on invalid input. */
+size_t nmg_workspace_bytes(const nmg_desc *desc, const nmg_params *params);
+
+/* Residual of eq. (10) (1D, not divided by dx) or eq. (20) (2D) for every cell, the cell norms
+ * rn[j] = ||R_j||_1 and res_dev[0] = (1/N) sum_j rn[j] (Algorithm 1).  U, R, rn, res_dev are
+ * device pointers. */
+nmg_status nmg_residual(const nmg_desc *desc, const double *U, double *R, double *rn,
+                        double *res_dev, void *stream);
+
+/* Finite-difference Jacobian of eq. (12) with the regularisation alpha*||R_j||_1*I of eq. (13),
+ * assembled on the reduced stencil of section 3.3 (J3; desc->jac = 5 gives J5) or section 4.1
+ * (J9).  R and rn must be nmg_residual's output for the same U.  J (device, FP64) receives the
+ * blocks in the layout above. */
+nmg_status nmg_jacobian_assemble_simplified(const nmg_desc *desc, const nmg_params *params,
+                                            const double *U, const double *R, const double *rn,
+                                            double *J, void *stream);
+
+/* One multigrid V-cycle (Algorithm 2) for  sum_i J_ji dU_i = -rhs_j  with the regularised
+ * Jacobian J (layout above), multicolour block SOR smoothing (eq. 19/22), restriction and
+ * coarse operators of eq. (17)/(24), injection prolongation (eq. 18/25) and a direct solve on
+ * the coarsest grid.  setup = 1 copies J into the workspace and builds every coarse operator
+ * and diagonal inverse (needed once per J); setup = 0 reuses them.  rhs and dU (in/out) are
+ * device arrays in the U layout; precision NMG_FP32_MG makes rhs/dU float arrays. */
+nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
+                         const void *J, const void *rhs, void *dU, int32_t setup, void *stream);
+
+/* Algorithm 1 driven to res < tol or n_max steps: each step assembles the Jacobian, runs nu3
+ * V-cycles from dU = 0, updates U += tau dU (eq. 14) and re-evaluates res.  U (device) is the
+ * initial guess on entry and the result on exit.  stats (host) and hist (host, res after each
+ * step, up to max_hist entries; may be NULL) are filled on return.  Synchronises `stream`. */
+nmg_status nmg_newton_solve(const nmg_desc *desc, const nmg_params *params, void *ws,
+                            size_t ws_bytes, double *U, nmg_stats *stats, double *hist,
+                            int32_t max_hist, void *stream);
+
+/* ---- batched form: many independent 1D instances (any sizes) per launch ----------------
+ * A plan fixes n instances (descs/params host arrays of length n) and the workspace layout.
+ * nmg_plan_solve runs Algorithm 1 on all of them together: every kernel launch covers every
+ * still-active instance; converged instances drop out without disturbing the others (no
+ * cross-instance arithmetic, so each result is bitwise the same alone or in a batch).
+ * U[k] (host array of device pointers) is instance k's state, updated in place.  use_graph = 1
+ * captures one Newton step as a HIP graph and replays it. */
+typedef struct nmg_plan nmg_plan;
+nmg_status nmg_plan_create(const nmg_desc *descs, const nmg_params *params, int32_t n,
+                           nmg_plan **out);
+size_t nmg_plan_workspace_bytes(const nmg_plan *plan);
+nmg_status nmg_plan_solve(nmg_plan *plan, void *ws, size_t ws_bytes, double *const *U,
+                          nmg_stats *stats, int32_t use_graph, void *stream);
+/* Run exactly `steps` Newton steps (or fewer for instances that stop earlier) without
+ * re-initialising; nmg_plan_begin evaluates the initial residual.  For step-wise drivers such
+ * as a serving loop.  active_out (host, length n; may be NULL) receives 1 for still-active
+ * instances; stats (host, may be NULL) the per-instance state. */
+nmg_status nmg_plan_begin(nmg_plan *plan, void *ws, size_t ws_bytes, double *const *U, void *stream);
+nmg_status nmg_plan_steps(nmg_plan *plan, void *ws, int32_t steps, int32_t use_graph,
+                          int32_t *active_out, nmg_stats *stats, void *stream);
+void nmg_plan_destroy(nmg_plan *plan);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *nmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NMG_H */

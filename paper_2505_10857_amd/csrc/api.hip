@@ -1,0 +1,582 @@
+// libnmg host side: argument checking, workspace layout, the Newton driver of Algorithm 1 and
+// the batched plan.  All device work is launched from here onto the caller's stream.
+//
+// Workspace layout (byte offsets, each 256-byte aligned):
+//   tables   : Inst1D[n] | Level1D[nlev] | Tile[...] | int inst_list[n]
+//   state    : NewtonState[n]
+//   partial  : double[res tiles]            (per-tile sums of ||R_j||_1)
+//   hist     : double[n][max_hist]
+//   R, rn    : double, per instance [2N] and [N]
+//   mg       : per instance and level: J [nb*4][n_l], Dinv [4][n_l], rhs [2][n_l], dU [2][n_l]
+//              in double (NMG_FP64) or float (NMG_FP32_MG)
+//   lu, piv  : coarsest-level band factors, kLuStride doubles and one int per coarse row
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nmg_common.h"
+
+using namespace nmg;
+
+namespace {
+
+thread_local std::string g_err;
+
+nmg_status fail(nmg_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(NMG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+nmg_status check_desc1d(const nmg_desc *d, const nmg_params *p)
+{
+    if (!d || !p) return fail(NMG_EINVAL, "null desc or params");
+    if (d->dim != 1) return fail(NMG_EINVAL, "only dim = 1 is handled by this entry point");
+    if (d->nx < 4) return fail(NMG_EINVAL, "nx must be >= 4");
+    if (d->levels < 2 || d->levels > kMaxLevels) return fail(NMG_EINVAL, "levels must be in [2, 16]");
+    if (d->nx % (1 << (d->levels - 1)) != 0)
+        return fail(NMG_EINVAL, "nx must be divisible by 2^(levels-1)");
+    if ((d->nx >> (d->levels - 1)) > kMaxCoarse)
+        return fail(NMG_EINVAL, "coarsest level has more than 256 cells; add levels");
+    if (d->jac != 3 && d->jac != 5) return fail(NMG_EINVAL, "1D jac must be 3 or 5");
+    if (!d->sig_face || !d->sig_gp || !d->sigx_gp || !d->bx_gp)
+        return fail(NMG_EINVAL, "null geometry pointer");
+    if (!(d->x1 > d->x0)) return fail(NMG_EINVAL, "x1 must exceed x0");
+    if (!(p->eps > 0.0)) return fail(NMG_EINVAL, "eps must be positive");
+    if (p->nu1 < 0 || p->nu2 < 0 || p->nu3 < 1 || p->n_max < 0)
+        return fail(NMG_EINVAL, "bad nu1/nu2/nu3/n_max");
+    if (p->nu1 > 8 || p->nu2 > 8)
+        return fail(NMG_EINVAL, "nu1/nu2 above 8 are not supported by the fused 1D smoother");
+    if (p->precision != NMG_FP64 && p->precision != NMG_FP32_MG)
+        return fail(NMG_EINVAL, "bad precision");
+    return NMG_OK;
+}
+
+Inst1D make_inst(const nmg_desc *d, const nmg_params *p)
+{
+    Inst1D I;
+    memset(&I, 0, sizeof(I));
+    I.N = d->nx;
+    I.levels = d->levels;
+    I.nb = d->jac;
+    I.dx = (d->x1 - d->x0) / d->nx;
+    I.g = d->g;
+    for (int s = 0; s < 2; s++) {
+        I.bc_kind[s] = d->bc[s].kind;
+        I.bc_q[s] = d->bc[s].q;
+        I.bc_h[s] = d->bc[s].h;
+    }
+    I.sig_face = d->sig_face;
+    I.sig_gp = d->sig_gp;
+    I.sigx_gp = d->sigx_gp;
+    I.bx_gp = d->bx_gp;
+    I.alpha = p->alpha;
+    I.tau = p->tau;
+    I.eps = p->eps;
+    I.omega = p->omega;
+    I.tol = p->tol;
+    I.nu1 = p->nu1;
+    I.nu2 = p->nu2;
+    I.nu3 = p->nu3;
+    I.n_max = p->n_max;
+    return I;
+}
+
+}  // namespace
+
+struct nmg_plan {
+    int n = 0;
+    int prec = NMG_FP64;
+    int nu3 = 1;
+    int check_every = 1;
+    std::vector<Inst1D> insts;
+    std::vector<Level1D> levs;
+    std::vector<Tile> tiles;                  // all tile lists, concatenated
+    int res_t0 = 0, res_nt = 0;               // residual / Jacobian tiles
+    std::vector<std::pair<int, int>> coarsen; // (t0, nt) per coarsening pass
+    std::vector<std::pair<int, int>> smooth;  // (t0, nt) per depth
+    std::vector<int> smooth_mask;             // stencil widths present per depth (bit0: 3, bit1: 5)
+    int jac_mask = 0;
+    int depth = 0;
+    size_t off_insts = 0, off_levs = 0, off_tiles = 0, off_list = 0, off_state = 0, off_partial = 0,
+           off_hist = 0, off_R = 0, off_mg = 0, off_lu = 0, off_piv = 0, total = 0;
+    std::vector<size_t> R_off;                // per instance byte offset of R (rn follows)
+    int max_hist = 0;
+    // graph cache
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    void *g_ws = nullptr;
+    hipStream_t own_stream = nullptr;
+    NewtonState *host_state = nullptr;        // pinned
+    ~nmg_plan()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
+        if (host_state) (void)hipHostFree(host_state);
+    }
+};
+
+namespace {
+
+nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *params, int n)
+{
+    if (n <= 0) return fail(NMG_EINVAL, "need at least one instance");
+    P->n = n;
+    P->prec = params[0].precision;
+    P->nu3 = params[0].nu3;
+    P->check_every = std::max(1, params[0].check_every);
+    for (int k = 0; k < n; k++) {
+        nmg_status st = check_desc1d(&descs[k], &params[k]);
+        if (st != NMG_OK) return fail(st, "instance " + std::to_string(k) + ": " + g_err);
+        if (params[k].precision != P->prec) return fail(NMG_EINVAL, "mixed precisions in one plan");
+        if (params[k].nu3 != P->nu3) return fail(NMG_EINVAL, "mixed nu3 in one plan");
+    }
+    const size_t vsz = P->prec == NMG_FP32_MG ? sizeof(float) : sizeof(double);
+    P->insts.clear();
+    P->levs.clear();
+    P->tiles.clear();
+    int max_levels = 0;
+    P->max_hist = 0;
+    for (int k = 0; k < n; k++) {
+        max_levels = std::max(max_levels, descs[k].levels);
+        P->max_hist = std::max(P->max_hist, std::min(params[k].n_max, 100000));
+    }
+    P->depth = max_levels - 1;
+
+    // levels and multigrid element offsets
+    long long mg_elems = 0, lu_elems = 0;
+    std::vector<std::vector<int>> lev_index(n);
+    for (int k = 0; k < n; k++) {
+        Inst1D I = make_inst(&descs[k], &params[k]);
+        I.active_idx = k;
+        I.lev0 = (int)P->levs.size();
+        for (int l = 0; l < I.levels; l++) {
+            Level1D L;
+            memset(&L, 0, sizeof(L));
+            L.inst = k;
+            L.l = l;
+            L.n = I.N >> l;
+            L.nb = l == 0 ? I.nb : 3;
+            L.coarsest = l == I.levels - 1;
+            L.halo = halo_cells(L.nb, std::max(I.nu1, I.nu2));
+            L.V = kTile - 2 * L.halo;
+            L.child = L.coarsest ? -1 : (int)P->levs.size() + 1;
+            L.J = mg_elems; mg_elems += (long long)L.nb * 4 * L.n;
+            L.Dinv = mg_elems; mg_elems += 4LL * L.n;
+            L.rhs = mg_elems; mg_elems += 2LL * L.n;
+            L.dU = mg_elems; mg_elems += 2LL * L.n;
+            mg_elems = (mg_elems + 63) & ~63LL;
+            lev_index[k].push_back((int)P->levs.size());
+            P->levs.push_back(L);
+        }
+        I.levc = (int)P->levs.size() - 1;
+        I.lu = lu_elems;
+        lu_elems += (long long)2 * (I.N >> (I.levels - 1)) * kLuStride;
+        I.max_hist = std::min(params[k].n_max, 100000);
+        P->insts.push_back(I);
+    }
+    // residual / Jacobian tiles
+    P->res_t0 = 0;
+    P->jac_mask = 0;
+    for (int k = 0; k < n; k++) {
+        P->insts[k].res_tile0 = (int)P->tiles.size();
+        int nt = (P->insts[k].N + kTile - 1) / kTile;
+        P->insts[k].res_tiles = nt;
+        for (int t = 0; t < nt; t++) P->tiles.push_back({k, t * kTile});
+        P->jac_mask |= P->insts[k].nb == 5 ? 2 : 1;
+    }
+    P->res_nt = (int)P->tiles.size();
+    // coarsening passes: each pass starts at level 10*p and builds up to ten more levels
+    P->coarsen.clear();
+    const int span = kTile * kCoarsenCells;
+    for (int l0 = 0; l0 < max_levels; l0 += 10) {
+        int t0 = (int)P->tiles.size();
+        for (int k = 0; k < n; k++) {
+            if (l0 >= P->insts[k].levels) continue;
+            const Level1D &L = P->levs[lev_index[k][l0]];
+            for (int a = 0; a < L.n; a += span) P->tiles.push_back({lev_index[k][l0], a});
+        }
+        P->coarsen.push_back({t0, (int)P->tiles.size() - t0});
+    }
+    // smoothing tiles per depth
+    P->smooth.clear();
+    P->smooth_mask.clear();
+    for (int d = 0; d < P->depth; d++) {
+        int t0 = (int)P->tiles.size(), mask = 0;
+        for (int k = 0; k < n; k++) {
+            if (d >= P->insts[k].levels - 1) continue;
+            const Level1D &L = P->levs[lev_index[k][d]];
+            if (L.V < 2) return fail(NMG_EINVAL, "smoothing halo exceeds the tile");
+            for (int a = 0; a < L.n; a += L.V) P->tiles.push_back({lev_index[k][d], a});
+            mask |= L.nb == 5 ? 2 : 1;
+        }
+        P->smooth.push_back({t0, (int)P->tiles.size() - t0});
+        P->smooth_mask.push_back(mask);
+    }
+    // byte layout
+    size_t o = 0;
+    P->off_insts = o; o = align256(o + sizeof(Inst1D) * n);
+    P->off_levs = o; o = align256(o + sizeof(Level1D) * P->levs.size());
+    P->off_tiles = o; o = align256(o + sizeof(Tile) * std::max<size_t>(1, P->tiles.size()));
+    P->off_list = o; o = align256(o + sizeof(int) * n);
+    P->off_state = o; o = align256(o + sizeof(NewtonState) * n);
+    P->off_partial = o; o = align256(o + sizeof(double) * std::max(1, P->res_nt));
+    P->off_hist = o; o = align256(o + sizeof(double) * (size_t)n * std::max(1, P->max_hist));
+    P->R_off.resize(n);
+    for (int k = 0; k < n; k++) {
+        P->R_off[k] = o;
+        o = align256(o + sizeof(double) * 3 * (size_t)P->insts[k].N);
+    }
+    P->off_mg = o; o = align256(o + vsz * (size_t)mg_elems);
+    P->off_lu = o; o = align256(o + sizeof(double) * (size_t)std::max(1LL, lu_elems));
+    P->off_piv = o; o = align256(o + sizeof(int) * (size_t)std::max(1LL, lu_elems / kLuStride));
+    P->total = o;
+    return NMG_OK;
+}
+
+MGArgs mg_args(const nmg_plan *P, char *ws, bool with_state)
+{
+    MGArgs a;
+    a.insts = reinterpret_cast<const Inst1D *>(ws + P->off_insts);
+    a.levs = reinterpret_cast<const Level1D *>(ws + P->off_levs);
+    a.state = with_state ? reinterpret_cast<NewtonState *>(ws + P->off_state) : nullptr;
+    a.mg = ws + P->off_mg;
+    a.lu = reinterpret_cast<double *>(ws + P->off_lu);
+    a.piv = reinterpret_cast<int *>(ws + P->off_piv);
+    return a;
+}
+
+// Upload the tables with the device pointers of this workspace and these states.
+nmg_status upload_tables(nmg_plan *P, char *ws, double *const *U, hipStream_t s)
+{
+    std::vector<char> h(P->off_state, 0);
+    for (int k = 0; k < P->n; k++) {
+        Inst1D I = P->insts[k];
+        I.U = U ? U[k] : nullptr;
+        I.R = reinterpret_cast<double *>(ws + P->R_off[k]);
+        I.rn = I.R + 2 * (size_t)I.N;
+        I.hist = reinterpret_cast<double *>(ws + P->off_hist) + (size_t)k * std::max(1, P->max_hist);
+        memcpy(h.data() + P->off_insts + sizeof(Inst1D) * k, &I, sizeof(Inst1D));
+    }
+    memcpy(h.data() + P->off_levs, P->levs.data(), sizeof(Level1D) * P->levs.size());
+    if (!P->tiles.empty()) memcpy(h.data() + P->off_tiles, P->tiles.data(), sizeof(Tile) * P->tiles.size());
+    std::vector<int> list(P->n);
+    for (int k = 0; k < P->n; k++) list[k] = k;
+    memcpy(h.data() + P->off_list, list.data(), sizeof(int) * P->n);
+    HIP_TRY(hipMemcpyAsync(ws, h.data(), h.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return NMG_OK;
+}
+
+const Tile *tiles_at(const nmg_plan *P, char *ws, int t0)
+{
+    return reinterpret_cast<const Tile *>(ws + P->off_tiles) + t0;
+}
+
+// Coarse operators of every level, diagonal inverses and the coarsest factorisation.
+nmg_status enqueue_setup(nmg_plan *P, char *ws, const MGArgs &mg, hipStream_t s)
+{
+    for (auto &c : P->coarsen) HIP_TRY(launch_coarsen1d(mg, tiles_at(P, ws, c.first), c.second, P->prec, s));
+    const int *list = reinterpret_cast<const int *>(ws + P->off_list);
+    HIP_TRY(launch_coarse_factor(mg, list, P->n, P->prec, s));
+    return NMG_OK;
+}
+
+// One V-cycle (Algorithm 2) over every instance.
+nmg_status enqueue_vcycle(nmg_plan *P, char *ws, const MGArgs &mg, bool zero_init0, bool final_update,
+                          hipStream_t s)
+{
+    const int *list = reinterpret_cast<const int *>(ws + P->off_list);
+    for (int d = 0; d < P->depth; d++)
+        HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
+                                P->smooth_mask[d], 0, (d > 0 || zero_init0) ? 1 : 0, 0, P->prec, s));
+    HIP_TRY(launch_coarse_solve(mg, list, P->n, P->prec, s));
+    for (int d = P->depth - 1; d >= 0; d--)
+        HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
+                                P->smooth_mask[d], 1, 0, (d == 0 && final_update) ? 1 : 0, P->prec, s));
+    return NMG_OK;
+}
+
+// One Newton step of Algorithm 1 for every active instance.
+nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s)
+{
+    MGArgs mg = mg_args(P, ws, true);
+    const Inst1D *insts = mg.insts;
+    const Tile *rt = tiles_at(P, ws, P->res_t0);
+    NewtonState *state = mg.state;
+    double *partial = reinterpret_cast<double *>(ws + P->off_partial);
+    HIP_TRY(launch_jacobian1d(insts, rt, P->res_nt, nullptr, nullptr, mg, P->prec, P->jac_mask, s));
+    nmg_status st = enqueue_setup(P, ws, mg, s);
+    if (st != NMG_OK) return st;
+    for (int v = 0; v < P->nu3; v++) {
+        st = enqueue_vcycle(P, ws, mg, v == 0, v == P->nu3 - 1, s);
+        if (st != NMG_OK) return st;
+    }
+    HIP_TRY(launch_residual1d(insts, rt, P->res_nt, nullptr, state, partial, s));
+    HIP_TRY(launch_res_finalize(insts, P->n, state, partial, 0, s));
+    return NMG_OK;
+}
+
+nmg_status plan_begin(nmg_plan *P, char *ws, size_t ws_bytes, double *const *U, hipStream_t s)
+{
+    if (!ws) return fail(NMG_EINVAL, "null workspace");
+    if (ws_bytes < P->total) return fail(NMG_ENOMEM_WS, "workspace too small");
+    if (!U) return fail(NMG_EINVAL, "null state array");
+    for (int k = 0; k < P->n; k++)
+        if (!U[k]) return fail(NMG_EINVAL, "null state pointer");
+    nmg_status st = upload_tables(P, ws, U, s);
+    if (st != NMG_OK) return st;
+    if (P->g_ws != ws && P->gexec) {   // a graph captured on another workspace is stale
+        (void)hipGraphExecDestroy(P->gexec);
+        (void)hipGraphDestroy(P->graph);
+        P->gexec = nullptr;
+        P->graph = nullptr;
+    }
+    MGArgs mg = mg_args(P, ws, true);
+    const Tile *rt = tiles_at(P, ws, P->res_t0);
+    double *partial = reinterpret_cast<double *>(ws + P->off_partial);
+    HIP_TRY(launch_residual1d(mg.insts, rt, P->res_nt, nullptr, nullptr, partial, s));
+    HIP_TRY(launch_res_finalize(mg.insts, P->n, mg.state, partial, 1, s));
+    return NMG_OK;
+}
+
+nmg_status read_state(nmg_plan *P, char *ws, hipStream_t s)
+{
+    if (!P->host_state) HIP_TRY(hipHostMalloc((void **)&P->host_state, sizeof(NewtonState) * P->n));
+    HIP_TRY(hipMemcpyAsync(P->host_state, ws + P->off_state, sizeof(NewtonState) * P->n,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return NMG_OK;
+}
+
+nmg_status plan_steps(nmg_plan *P, char *ws, int steps, int use_graph, hipStream_t s)
+{
+    if (use_graph) {
+        if (!P->gexec || P->g_ws != ws) {
+            hipStream_t cs = s;
+            if (cs == nullptr) {
+                if (!P->own_stream) HIP_TRY(hipStreamCreateWithFlags(&P->own_stream, hipStreamNonBlocking));
+                cs = P->own_stream;
+                HIP_TRY(hipDeviceSynchronize());
+            }
+            HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            nmg_status st = enqueue_step(P, ws, cs);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(cs, &g);
+            if (st != NMG_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+            if (e != hipSuccess) return fail(NMG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+            if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+            if (P->graph) (void)hipGraphDestroy(P->graph);
+            P->graph = g;
+            HIP_TRY(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0));
+            P->g_ws = ws;
+        }
+        hipStream_t ls = s ? s : P->own_stream;
+        if (s == nullptr) HIP_TRY(hipDeviceSynchronize());
+        for (int k = 0; k < steps; k++) HIP_TRY(hipGraphLaunch(P->gexec, ls));
+        if (s == nullptr) HIP_TRY(hipStreamSynchronize(ls));
+        return NMG_OK;
+    }
+    for (int k = 0; k < steps; k++) {
+        nmg_status st = enqueue_step(P, ws, s);
+        if (st != NMG_OK) return st;
+    }
+    return NMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nmg_last_error(void) { return g_err.c_str(); }
+
+nmg_status nmg_plan_create(const nmg_desc *descs, const nmg_params *params, int32_t n, nmg_plan **out)
+{
+    if (!descs || !params || !out) return fail(NMG_EINVAL, "null argument");
+    nmg_plan *P = new (std::nothrow) nmg_plan();
+    if (!P) return fail(NMG_EINVAL, "out of host memory");
+    nmg_status st = build_plan(P, descs, params, n);
+    if (st != NMG_OK) { delete P; return st; }
+    *out = P;
+    return NMG_OK;
+}
+
+size_t nmg_plan_workspace_bytes(const nmg_plan *plan) { return plan ? plan->total : 0; }
+
+void nmg_plan_destroy(nmg_plan *plan) { delete plan; }
+
+nmg_status nmg_plan_begin(nmg_plan *P, void *ws, size_t ws_bytes, double *const *U, void *stream)
+{
+    if (!P) return fail(NMG_EINVAL, "null plan");
+    return plan_begin(P, (char *)ws, ws_bytes, U, (hipStream_t)stream);
+}
+
+nmg_status nmg_plan_steps(nmg_plan *P, void *ws, int32_t steps, int32_t use_graph, int32_t *active_out,
+                          nmg_stats *stats, void *stream)
+{
+    if (!P || !ws) return fail(NMG_EINVAL, "null plan or workspace");
+    hipStream_t s = (hipStream_t)stream;
+    nmg_status st = plan_steps(P, (char *)ws, steps, use_graph, s);
+    if (st != NMG_OK) return st;
+    if (active_out || stats) {
+        st = read_state(P, (char *)ws, s ? s : P->own_stream);
+        if (st != NMG_OK) return st;
+        for (int k = 0; k < P->n; k++) {
+            if (active_out) active_out[k] = P->host_state[k].active;
+            if (stats) {
+                stats[k].iters = P->host_state[k].n;
+                stats[k].status = P->host_state[k].status;
+                stats[k].res = P->host_state[k].res;
+            }
+        }
+    }
+    return NMG_OK;
+}
+
+nmg_status nmg_plan_solve(nmg_plan *P, void *ws, size_t ws_bytes, double *const *U, nmg_stats *stats,
+                          int32_t use_graph, void *stream)
+{
+    if (!P) return fail(NMG_EINVAL, "null plan");
+    hipStream_t s = (hipStream_t)stream;
+    nmg_status st = plan_begin(P, (char *)ws, ws_bytes, U, s);
+    if (st != NMG_OK) return st;
+    int max_steps = 0;
+    for (auto &I : P->insts) max_steps = std::max(max_steps, I.n_max);
+    int done = 0;
+    st = read_state(P, (char *)ws, s);
+    if (st != NMG_OK) return st;
+    for (;;) {
+        bool any = false;
+        for (int k = 0; k < P->n; k++) any = any || P->host_state[k].active;
+        if (!any || done >= max_steps) break;
+        int chunk = std::min(P->check_every, max_steps - done);
+        st = plan_steps(P, (char *)ws, chunk, use_graph, s);
+        if (st != NMG_OK) return st;
+        done += chunk;
+        st = read_state(P, (char *)ws, s ? s : (use_graph ? P->own_stream : s));
+        if (st != NMG_OK) return st;
+    }
+    nmg_status worst = NMG_OK;
+    for (int k = 0; k < P->n; k++) {
+        if (stats) {
+            stats[k].iters = P->host_state[k].n;
+            stats[k].status = P->host_state[k].status;
+            stats[k].res = P->host_state[k].res;
+        }
+        if (P->host_state[k].status == NMG_ENONFINITE) worst = NMG_ENONFINITE;
+        else if (P->host_state[k].status == NMG_NOT_CONVERGED && worst == NMG_OK) worst = NMG_NOT_CONVERGED;
+    }
+    if (worst == NMG_ENONFINITE) g_err = "non-finite residual in at least one instance";
+    return worst;
+}
+
+size_t nmg_workspace_bytes(const nmg_desc *desc, const nmg_params *params)
+{
+    nmg_plan P;
+    if (build_plan(&P, desc, params, 1) != NMG_OK) return 0;
+    return P.total;
+}
+
+nmg_status nmg_residual(const nmg_desc *desc, const double *U, double *R, double *rn,
+                        double *res_dev, void *stream)
+{
+    nmg_params p;
+    memset(&p, 0, sizeof(p));
+    p.eps = 1.0; p.nu3 = 1;
+    nmg_status st = check_desc1d(desc, &p);
+    if (st != NMG_OK) return st;
+    if (!U || !R || !rn) return fail(NMG_EINVAL, "null U/R/rn");
+    Inst1D I = make_inst(desc, &p);
+    I.U = const_cast<double *>(U);
+    I.R = R;
+    I.rn = rn;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_residual1d(nullptr, nullptr, 0, &I, nullptr, nullptr, s));
+    if (res_dev) HIP_TRY(launch_sum_res(rn, I.N, res_dev, s));
+    return NMG_OK;
+}
+
+nmg_status nmg_jacobian_assemble_simplified(const nmg_desc *desc, const nmg_params *params,
+                                            const double *U, const double *R, const double *rn,
+                                            double *J, void *stream)
+{
+    nmg_status st = check_desc1d(desc, params);
+    if (st != NMG_OK) return st;
+    if (!U || !R || !rn || !J) return fail(NMG_EINVAL, "null U/R/rn/J");
+    Inst1D I = make_inst(desc, params);
+    I.U = const_cast<double *>(U);
+    I.R = const_cast<double *>(R);
+    I.rn = const_cast<double *>(rn);
+    MGArgs none;
+    memset(&none, 0, sizeof(none));
+    HIP_TRY(launch_jacobian1d(nullptr, nullptr, 0, &I, J, none, NMG_FP64, 0, (hipStream_t)stream));
+    return NMG_OK;
+}
+
+nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
+                         const void *J, const void *rhs, void *dU, int32_t setup, void *stream)
+{
+    if (!ws || !rhs || !dU || (setup && !J)) return fail(NMG_EINVAL, "null argument");
+    nmg_plan P;
+    nmg_status st = build_plan(&P, desc, params, 1);
+    if (st != NMG_OK) return st;
+    if (ws_bytes < P.total) return fail(NMG_ENOMEM_WS, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    st = upload_tables(&P, w, nullptr, s);
+    if (st != NMG_OK) return st;
+    MGArgs mg = mg_args(&P, w, false);
+    const Level1D &L0 = P.levs[0];
+    const size_t vsz = P.prec == NMG_FP32_MG ? 4 : 8;
+    char *mgb = w + P.off_mg;
+    const long long n0 = L0.n;
+    if (setup) {
+        HIP_TRY(launch_convert(J, NMG_FP64, mgb + vsz * L0.J, P.prec, (long long)L0.nb * 4 * n0, s));
+        st = enqueue_setup(&P, w, mg, s);
+        if (st != NMG_OK) return st;
+    }
+    HIP_TRY(launch_convert(rhs, P.prec, mgb + vsz * L0.rhs, P.prec, 2 * n0, s));
+    HIP_TRY(launch_convert(dU, P.prec, mgb + vsz * L0.dU, P.prec, 2 * n0, s));
+    st = enqueue_vcycle(&P, w, mg, false, false, s);
+    if (st != NMG_OK) return st;
+    HIP_TRY(launch_convert(mgb + vsz * L0.dU, P.prec, dU, P.prec, 2 * n0, s));
+    HIP_TRY(hipStreamSynchronize(s));   // the tables above live in this call's plan
+    return NMG_OK;
+}
+
+nmg_status nmg_newton_solve(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
+                            double *U, nmg_stats *stats, double *hist, int32_t max_hist, void *stream)
+{
+    nmg_plan P;
+    nmg_status st = build_plan(&P, desc, params, 1);
+    if (st != NMG_OK) return st;
+    double *Us[1] = {U};
+    nmg_stats local;
+    st = nmg_plan_solve(&P, ws, ws_bytes, Us, stats ? stats : &local, params->check_every > 1 ? 1 : 0,
+                        stream);
+    if (hist && max_hist > 0) {
+        nmg_stats &S = stats ? *stats : local;
+        int cnt = std::min(std::min((int)max_hist, S.iters), P.max_hist);
+        if (cnt > 0) {
+            hipStream_t s = (hipStream_t)stream;
+            if (hipMemcpyAsync(hist, (char *)ws + P.off_hist, sizeof(double) * cnt, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(NMG_EHIP, "history copy failed");
+        }
+    }
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,457 @@
+// Geometric multigrid for the 1D regularised Newton systems (section 3.4, eq. 15-19,
+// Algorithm 2) on gfx950.
+//
+//  * k_coarsen: coarse operators of eq. (17) for up to ten levels in one launch.  A workgroup
+//    owns an aligned run of 1024 cells of the starting level and reduces them level by level
+//    in LDS (each coarse cell aggregates two children, eq. 15), writing every level's blocks
+//    and the closed-form 2x2 inverses of the diagonal blocks used by eq. (19).
+//  * k_smooth: all nu multicolour block-SOR half-sweeps of one smoothing phase fused in one
+//    launch.  Each workgroup loads its cells' block rows, inverse and right-hand side into
+//    registers once, keeps dU in LDS, and runs the half-sweeps with a halo wide enough that
+//    the cells it writes are exact; the pre-smoothing kernel then forms the restricted
+//    right-hand side of eq. (17), the post-smoothing kernel first adds the prolongation of
+//    eq. (18) (and, at the finest level after the last cycle, applies the Newton update of
+//    eq. 14).  HBM traffic per level and phase is one read of the operator.
+//  * k_coarse_factor / k_coarse_solve: the coarsest system is solved exactly by Gaussian
+//    elimination with partial pivoting on its band (rows 2j+c, c the component), factored once
+//    per operator and re-used by every cycle.
+#include "nmg_common.h"
+
+namespace nmg {
+
+template <typename T>
+__device__ __forceinline__ double ld(const T *p, long long i) { return (double)p[i]; }
+
+__device__ __forceinline__ bool active_of(const MGArgs &mg, int inst)
+{
+    return mg.state == nullptr || mg.state[mg.insts[inst].active_idx].active;
+}
+
+__device__ __forceinline__ void inv2(const double A[4], double B[4])
+{
+    double det = A[0] * A[3] - A[1] * A[2];
+    B[0] = A[3] / det;
+    B[1] = -A[1] / det;
+    B[2] = -A[2] / det;
+    B[3] = A[0] / det;
+}
+
+// ---- coarse operators --------------------------------------------------------------------
+
+// Children blocks (b = 0..nb-1 <-> column offsets -nb/2..nb/2) of cells 2jc and 2jc+1 ->
+// coarse tridiagonal row of cell jc, summing the fine blocks of eq. (17) in order of the
+// child row and then the child column.
+__device__ __forceinline__ void coarse_row(int nb, const double (*f0)[4], const double (*f1)[4],
+                                           double Wc[4], double Dc[4], double Ec[4])
+{
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        if (nb == 5) {
+            Wc[e] = f0[0][e] + f0[1][e] + f1[0][e];
+            Dc[e] = f0[2][e] + f0[3][e] + f1[1][e] + f1[2][e];
+            Ec[e] = f0[4][e] + f1[3][e] + f1[4][e];
+        } else {
+            Wc[e] = f0[0][e];
+            Dc[e] = f0[1][e] + f0[2][e] + f1[0][e] + f1[1][e];
+            Ec[e] = f1[2][e];
+        }
+    }
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void first_coarse(const Level1D &L0, const Level1D &Lc, T *base, int c0,
+                                             int t, double (*blk)[12])
+{
+    for (int k = 0; k < kCoarsenCells / 2; k++) {
+        const int jl = t * (kCoarsenCells / 2) + k;   // local coarse index
+        const int jc = c0 + jl;
+        if (jc >= Lc.n) break;
+        double f0[5][4], f1[5][4];
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                f0[b][e] = ld(base + L0.J, (b * 4 + e) * (long long)L0.n + 2 * jc);
+                f1[b][e] = ld(base + L0.J, (b * 4 + e) * (long long)L0.n + 2 * jc + 1);
+            }
+        double W[4], D[4], E[4], B[4];
+        coarse_row(NB, f0, f1, W, D, E);
+        inv2(D, B);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            blk[jl][e] = W[e]; blk[jl][4 + e] = D[e]; blk[jl][8 + e] = E[e];
+            base[Lc.J + (0 * 4 + e) * (long long)Lc.n + jc] = (T)W[e];
+            base[Lc.J + (1 * 4 + e) * (long long)Lc.n + jc] = (T)D[e];
+            base[Lc.J + (2 * 4 + e) * (long long)Lc.n + jc] = (T)E[e];
+            base[Lc.Dinv + e * (long long)Lc.n + jc] = (T)B[e];
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTile) k_coarsen(MGArgs mg, const Tile *tiles)
+{
+    constexpr int CPT = kCoarsenCells;           // level-l0 cells per thread
+    constexpr int SPAN = kTile * CPT;             // level-l0 cells per workgroup
+    __shared__ double blk[SPAN / 2][12];          // current coarse level: W, D, E per cell
+    const Tile tl = tiles[blockIdx.x];
+    const Level1D L0 = mg.levs[tl.lev];
+    if (!active_of(mg, L0.inst)) return;
+    T *base = reinterpret_cast<T *>(mg.mg);
+    const int t = threadIdx.x;
+    const int nb = L0.nb;
+
+    // diagonal inverses of the starting level
+    for (int k = 0; k < CPT; k++) {
+        const int j = tl.a + t * CPT + k;
+        if (j >= L0.n) break;
+        double A[4], B[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) A[e] = ld(base + L0.J, ((nb / 2) * 4 + e) * (long long)L0.n + j);
+        inv2(A, B);
+        for (int e = 0; e < 4; e++) base[L0.Dinv + e * (long long)L0.n + j] = (T)B[e];
+    }
+    if (L0.coarsest) return;
+
+    // first coarse level from the starting level (global reads)
+    int lev = L0.child;
+    Level1D Lc = mg.levs[lev];
+    const int c0 = tl.a / 2;                      // first coarse cell of this tile
+    if (nb == 5) first_coarse<T, 5>(L0, Lc, base, c0, t, blk);
+    else first_coarse<T, 3>(L0, Lc, base, c0, t, blk);
+    __syncthreads();
+
+    // further levels from LDS
+    int cnt = SPAN / 2;     // cells of the current level held by this tile
+    int cstart = c0;        // first cell (level index) of the current level in this tile
+    while (!Lc.coarsest && cnt >= 2) {
+        const int nlev = Lc.child;
+        const Level1D Ln = mg.levs[nlev];
+        const int nstart = cstart / 2;
+        const int ncnt = cnt / 2;
+        double W[4], D[4], E[4], B[4];
+        const int jc = nstart + t;
+        const bool mine = t < ncnt && jc < Ln.n;
+        if (mine) {
+            double f0[5][4], f1[5][4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                f0[0][e] = blk[2 * t][e]; f0[1][e] = blk[2 * t][4 + e]; f0[2][e] = blk[2 * t][8 + e];
+                f1[0][e] = blk[2 * t + 1][e]; f1[1][e] = blk[2 * t + 1][4 + e]; f1[2][e] = blk[2 * t + 1][8 + e];
+            }
+            coarse_row(3, f0, f1, W, D, E);
+            inv2(D, B);
+        }
+        __syncthreads();
+        if (mine) {
+            for (int e = 0; e < 4; e++) {
+                blk[t][e] = W[e]; blk[t][4 + e] = D[e]; blk[t][8 + e] = E[e];
+                base[Ln.J + (0 * 4 + e) * (long long)Ln.n + jc] = (T)W[e];
+                base[Ln.J + (1 * 4 + e) * (long long)Ln.n + jc] = (T)D[e];
+                base[Ln.J + (2 * 4 + e) * (long long)Ln.n + jc] = (T)E[e];
+                base[Ln.Dinv + e * (long long)Ln.n + jc] = (T)B[e];
+            }
+        }
+        __syncthreads();
+        Lc = Ln;
+        cnt = ncnt;
+        cstart = nstart;
+    }
+}
+
+// ---- fused smoother ------------------------------------------------------------------------
+
+// mode 0: (zero or loaded) dU -> nu1 symmetric steps -> write dU, restrict rhs to the child.
+// mode 1: dU + prolongated child dU -> nu2 symmetric steps -> write dU (or update U).
+template <typename T, int NB>
+__global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, int mode,
+                                                  int zero_init, int final_update)
+{
+    constexpr int HW = NB / 2;
+    constexpr int C = NB == 5 ? 3 : 2;
+    __shared__ double s0[kTile + 2 * HW], s1[kTile + 2 * HW];
+    const Tile tl = tiles[blockIdx.x];
+    const Level1D L = mg.levs[tl.lev];
+    if (L.nb != NB) return;
+    if (!active_of(mg, L.inst)) return;
+    const Inst1D &I = mg.insts[L.inst];
+    T *base = reinterpret_cast<T *>(mg.mg);
+    const int n = L.n, h = L.halo;
+    const int t = threadIdx.x;
+    const int j = tl.a - h + t;
+    const bool in = j >= 0 && j < n;
+
+    double Jr[NB][4], D[4], r0 = 0.0, r1 = 0.0, du0 = 0.0, du1 = 0.0;
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) Jr[b][e] = in ? ld(base + L.J, (b * 4 + e) * (long long)n + j) : 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; e++) D[e] = in ? ld(base + L.Dinv, e * (long long)n + j) : 0.0;
+    if (in) {
+        r0 = ld(base + L.rhs, j);
+        r1 = ld(base + L.rhs, n + (long long)j);
+        if (!(mode == 0 && zero_init)) {
+            du0 = ld(base + L.dU, j);
+            du1 = ld(base + L.dU, n + (long long)j);
+        }
+        if (mode == 1) {
+            const Level1D &Lc = mg.levs[L.child];
+            du0 = du0 + ld(base + Lc.dU, j >> 1);
+            du1 = du1 + ld(base + Lc.dU, Lc.n + (long long)(j >> 1));
+        }
+    }
+    s0[t + HW] = du0;
+    s1[t + HW] = du1;
+    if (t < HW) { s0[t] = 0.0; s1[t] = 0.0; s0[kTile + HW + t] = 0.0; s1[kTile + HW + t] = 0.0; }
+    __syncthreads();
+
+    const int steps = mode == 0 ? I.nu1 : I.nu2;
+    const double w = I.omega;
+    const int col = ((j % C) + C) % C;
+    for (int s = 0; s < steps; s++) {
+        for (int hs = 0; hs < 2 * C; hs++) {
+            const int c = hs < C ? hs : 2 * C - 1 - hs;
+            if (in && col == c) {
+                // eq. (19): dU_j <- (1-w) dU_j - w J_jj^{-1} (rhs_j + sum_{i != j} J_ji dU_i)
+                double a0 = r0, a1 = r1;
+#pragma unroll
+                for (int b = 0; b < NB; b++) {
+                    if (b == HW) continue;
+                    const double x0 = s0[t + b], x1 = s1[t + b];
+                    a0 = a0 + (Jr[b][0] * x0 + Jr[b][1] * x1);
+                    a1 = a1 + (Jr[b][2] * x0 + Jr[b][3] * x1);
+                }
+                const double t0 = D[0] * a0 + D[1] * a1;
+                const double t1 = D[2] * a0 + D[3] * a1;
+                du0 = (1.0 - w) * du0 - w * t0;
+                du1 = (1.0 - w) * du1 - w * t1;
+                s0[t + HW] = du0;
+                s1[t + HW] = du1;
+            }
+            __syncthreads();
+        }
+    }
+
+    const bool valid = in && t >= h && t < h + L.V;
+    if (mode == 0) {
+        // restriction, eq. (17): rhs_c = sum over the two children of (rhs + sum_i J dU_i)
+        double a0 = r0, a1 = r1;
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            const double x0 = s0[t + b], x1 = s1[t + b];
+            a0 = a0 + (Jr[b][0] * x0 + Jr[b][1] * x1);
+            a1 = a1 + (Jr[b][2] * x0 + Jr[b][3] * x1);
+        }
+        const double p0 = __shfl_xor(a0, 1, 64);
+        const double p1 = __shfl_xor(a1, 1, 64);
+        if (valid) {
+            base[L.dU + j] = (T)du0;
+            base[L.dU + n + (long long)j] = (T)du1;
+            if ((j & 1) == 0 && !L.coarsest) {
+                const Level1D &Lc = mg.levs[L.child];
+                base[Lc.rhs + (j >> 1)] = (T)(a0 + p0);
+                base[Lc.rhs + Lc.n + (long long)(j >> 1)] = (T)(a1 + p1);
+            }
+        }
+    } else if (valid) {
+        if (final_update) {
+            // eq. (14): U <- U + tau dU
+            I.U[j] = I.U[j] + I.tau * du0;
+            I.U[I.N + j] = I.U[I.N + j] + I.tau * du1;
+        } else {
+            base[L.dU + j] = (T)du0;
+            base[L.dU + n + (long long)j] = (T)du1;
+        }
+    }
+}
+
+// ---- coarsest level ------------------------------------------------------------------------
+// Band storage: row r (= 2j + c) keeps columns r-3 .. r+6 at index col - r + 3.  The factor
+// stores, per pivot step k, the upper row (columns k .. k+6), the three multipliers of rows
+// k+1 .. k+3 and the pivot row, in a layout the solve kernel reads sequentially.
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_coarse_factor(MGArgs mg, const int *inst_list)
+{
+    __shared__ double A[2 * kMaxCoarse][kBandW];
+    __shared__ int piv_s;
+    const int inst = inst_list[blockIdx.x];
+    if (!active_of(mg, inst)) return;
+    const Inst1D &I = mg.insts[inst];
+    const Level1D L = mg.levs[I.levc];
+    const T *base = reinterpret_cast<const T *>(mg.mg);
+    const int n = L.n, M = 2 * n;
+    double *lu = mg.lu + I.lu;
+    int *piv = mg.piv + I.lu / kLuStride;
+    const int t = threadIdx.x;
+
+    for (int r = t; r < M; r += 64)
+        for (int k = 0; k < kBandW; k++) A[r][k] = 0.0;
+    __syncthreads();
+    // scatter the block-tridiagonal rows: block b couples cell j to cell j + b - 1
+    for (int j = t; j < n; j += 64)
+        for (int b = 0; b < 3; b++) {
+            const int i = j + b - 1;
+            if (i < 0 || i >= n) continue;
+            for (int l = 0; l < 2; l++)
+                for (int m = 0; m < 2; m++) {
+                    const int r = 2 * j + l, c = 2 * i + m;
+                    A[r][c - r + 3] = ld(base + L.J, (b * 4 + l * 2 + m) * (long long)n + j);
+                }
+        }
+    __syncthreads();
+    for (int k = 0; k < M; k++) {
+        if (t == 0) {
+            int p = k;
+            for (int r = k + 1; r <= k + 3 && r < M; r++)
+                if (fabs(A[r][k - r + 3]) > fabs(A[p][k - p + 3])) p = r;
+            piv_s = p;
+            piv[k] = p;
+        }
+        __syncthreads();
+        const int p = piv_s;
+        if (p != k && t < 7) {
+            // swap columns k .. k+6 of rows k and p (both hold them in their band)
+            const int c = k + t;
+            if (c < M && c - p + 3 < kBandW) {
+                double x = A[k][c - k + 3];
+                A[k][c - k + 3] = A[p][c - p + 3];
+                A[p][c - p + 3] = x;
+            } else if (c < M) {
+                A[k][c - k + 3] = 0.0;
+            }
+        }
+        __syncthreads();
+        // multipliers
+        double f = 0.0;
+        const int rr = k + 1 + (t / 7), cc = k + (t % 7);
+        if (t < 21 && rr < M) f = A[rr][k - rr + 3] / A[k][3];
+        __syncthreads();
+        if (t < 21 && rr < M && f != 0.0 && cc < M) A[rr][cc - rr + 3] -= f * A[k][cc - k + 3];
+        if (t < 21 && (t % 7) == 0) lu[(long long)k * kLuStride + 7 + t / 7] = rr < M ? f : 0.0;
+        __syncthreads();
+        if (t < 7) lu[(long long)k * kLuStride + t] = (k + t < M) ? A[k][t + 3] : 0.0;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_coarse_solve(MGArgs mg, const int *inst_list)
+{
+    __shared__ double x[2 * kMaxCoarse];
+    const int inst = inst_list[blockIdx.x];
+    if (!active_of(mg, inst)) return;
+    const Inst1D &I = mg.insts[inst];
+    const Level1D L = mg.levs[I.levc];
+    T *base = reinterpret_cast<T *>(mg.mg);
+    const int n = L.n, M = 2 * n;
+    const double *lu = mg.lu + I.lu;
+    const int *piv = mg.piv + I.lu / kLuStride;
+    const int t = threadIdx.x;
+    for (int j = t; j < n; j += 64) {
+        x[2 * j] = -ld(base + L.rhs, j);
+        x[2 * j + 1] = -ld(base + L.rhs, n + (long long)j);
+    }
+    __syncthreads();
+    if (t == 0) {
+        // forward elimination with the recorded pivots and multipliers
+        for (int k = 0; k < M; k++) {
+            const int p = piv[k];
+            if (p != k) { double y = x[k]; x[k] = x[p]; x[p] = y; }
+            const double xk = x[k];
+            for (int q = 0; q < 3; q++) {
+                const int r = k + 1 + q;
+                const double f = lu[(long long)k * kLuStride + 7 + q];
+                if (r < M && f != 0.0) x[r] -= f * xk;
+            }
+        }
+        // back substitution
+        for (int k = M - 1; k >= 0; k--) {
+            double s = x[k];
+            for (int c = k + 1; c <= k + 6 && c < M; c++) s -= lu[(long long)k * kLuStride + (c - k)] * x[c];
+            x[k] = s / lu[(long long)k * kLuStride];
+        }
+    }
+    __syncthreads();
+    for (int j = t; j < n; j += 64) {
+        base[L.dU + j] = (T)x[2 * j];
+        base[L.dU + n + (long long)j] = (T)x[2 * j + 1];
+    }
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S *src, D *dst, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (D)src[i];
+}
+
+// ---- launchers ---------------------------------------------------------------------------
+
+hipError_t launch_coarsen1d(const MGArgs &mg, const Tile *tiles, int ntiles, int prec, hipStream_t s)
+{
+    if (ntiles == 0) return hipSuccess;
+    if (prec == NMG_FP32_MG)
+        hipLaunchKernelGGL(k_coarsen<float>, dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+    else
+        hipLaunchKernelGGL(k_coarsen<double>, dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_factor(const MGArgs &mg, const int *inst_list, int n, int prec, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    if (prec == NMG_FP32_MG)
+        hipLaunchKernelGGL(k_coarse_factor<float>, dim3(n), dim3(64), 0, s, mg, inst_list);
+    else
+        hipLaunchKernelGGL(k_coarse_factor<double>, dim3(n), dim3(64), 0, s, mg, inst_list);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_solve(const MGArgs &mg, const int *inst_list, int n, int prec, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    if (prec == NMG_FP32_MG)
+        hipLaunchKernelGGL(k_coarse_solve<float>, dim3(n), dim3(64), 0, s, mg, inst_list);
+    else
+        hipLaunchKernelGGL(k_coarse_solve<double>, dim3(n), dim3(64), 0, s, mg, inst_list);
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_mask, int mode,
+                           int zero_init, int final_update, int prec, hipStream_t s)
+{
+    if (ntiles == 0) return hipSuccess;
+    if (prec == NMG_FP32_MG) {
+        if (nb_mask & 1)
+            hipLaunchKernelGGL((k_smooth<float, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, mode, zero_init, final_update);
+        if (nb_mask & 2)
+            hipLaunchKernelGGL((k_smooth<float, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, mode, zero_init, final_update);
+    } else {
+        if (nb_mask & 1)
+            hipLaunchKernelGGL((k_smooth<double, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, mode, zero_init, final_update);
+        if (nb_mask & 2)
+            hipLaunchKernelGGL((k_smooth<double, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, mode, zero_init, final_update);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const void *src, int src_prec, void *dst, int dst_prec, long long n,
+                          hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (src_prec == NMG_FP64 && dst_prec == NMG_FP64)
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(blocks), dim3(256), 0, s, (const double *)src, (double *)dst, n);
+    else if (src_prec == NMG_FP64)
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(blocks), dim3(256), 0, s, (const double *)src, (float *)dst, n);
+    else if (dst_prec == NMG_FP64)
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(blocks), dim3(256), 0, s, (const float *)src, (double *)dst, n);
+    else
+        hipLaunchKernelGGL((k_convert<float, float>), dim3(blocks), dim3(256), 0, s, (const float *)src, (float *)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace nmg

@@ -1,0 +1,423 @@
+// 1D finite-volume WENO residual (section 3.1, eq. 5-10) and its finite-difference block
+// Jacobian (section 3.2-3.3, eq. 12-13) for gfx950.
+//
+// One thread per cell; a 256-cell tile stages U (+2 halo cells per side) in LDS so that the
+// five-cell stencil of eq. (10) is read from HBM once.  Each thread keeps its stencil in
+// registers and evaluates the local residual R_j for the base state and for every column
+// perturbation of the kept blocks.  The arithmetic follows the paper's formulas in their
+// printed order with FMA contraction disabled (-ffp-contract=off), so the residual is
+// reproducible bit for bit by any IEEE-754 FP64 evaluation of the same formulas.
+#include "nmg_common.h"
+
+namespace nmg {
+
+// ---- WENO3 reconstruction (eq. 7-8) ----------------------------------------------------
+// Linear weights paired for third order: the central two-cell candidate takes 2/3 (the
+// printed d_r labels of eq. 8 are swapped; with them the scheme is second order).
+
+__device__ __forceinline__ double weno_plus(double um, double u0, double up)
+{
+    // right state U+_{j-1/2} at the left face of cell j
+    double c0 = 1.5 * u0 - 0.5 * up;   // T0 = {j, j+1}
+    double c1 = 0.5 * um + 0.5 * u0;   // T1 = {j-1, j}
+    double b0 = (up - u0) * (up - u0);
+    double b1 = (u0 - um) * (u0 - um);
+    double a0 = (1.0 / 3.0) / ((kZeta + b0) * (kZeta + b0));
+    double a1 = (2.0 / 3.0) / ((kZeta + b1) * (kZeta + b1));
+    double w0 = a0 / (a0 + a1);
+    double w1 = a1 / (a0 + a1);
+    return w0 * c0 + w1 * c1;
+}
+
+__device__ __forceinline__ double weno_minus(double um, double u0, double up)
+{
+    // left state U-_{j+1/2} at the right face of cell j
+    double c0 = 0.5 * u0 + 0.5 * up;
+    double c1 = -0.5 * um + 1.5 * u0;
+    double b0 = (up - u0) * (up - u0);
+    double b1 = (u0 - um) * (u0 - um);
+    double a0 = (2.0 / 3.0) / ((kZeta + b0) * (kZeta + b0));
+    double a1 = (1.0 / 3.0) / ((kZeta + b1) * (kZeta + b1));
+    double w0 = a0 / (a0 + a1);
+    double w1 = a1 / (a0 + a1);
+    return w0 * c0 + w1 * c1;
+}
+
+// ---- HLL flux for eq. (4) with Davis wave-speed bounds ----------------------------------
+
+__device__ __forceinline__ void hll(double HL, double QL, double HR, double QR, double sig,
+                                    double g, double &F0, double &F1)
+{
+    double hl = HL / sig, hr = HR / sig;
+    double FL0 = QL, FL1 = QL * QL / HL + 0.5 * g * sig * hl * hl;
+    double FR0 = QR, FR1 = QR * QR / HR + 0.5 * g * sig * hr * hr;
+    double uL = QL / HL, uR = QR / HR;
+    double cL = sqrt(g * hl), cR = sqrt(g * hr);
+    double sl1 = uL - cL, sl2 = uR - cR;
+    double sr1 = uL + cL, sr2 = uR + cR;
+    double SL = sl1 < sl2 ? sl1 : sl2;
+    double SR = sr1 > sr2 ? sr1 : sr2;
+    if (SL >= 0.0) {
+        F0 = FL0; F1 = FL1;
+    } else if (SR <= 0.0) {
+        F0 = FR0; F1 = FR1;
+    } else {
+        F0 = (SR * FL0 - SL * FR0 + SL * SR * (HR - HL)) / (SR - SL);
+        F1 = (SR * FL1 - SL * FR1 + SL * SR * (QR - QL)) / (SR - SL);
+    }
+}
+
+// Lagrange weights of the cubic through x_{j-3/2}, x_{j-1/2}, x_{j+1/2}, x_{j+3/2} at the two
+// Gauss points x_j -/+ dx/(2 sqrt 3) (eq. 9), from the product form of the basis.
+struct CubicGauss {
+    double w[2][4];
+    __device__ CubicGauss()
+    {
+        const double t[4] = {-1.5, -0.5, 0.5, 1.5};
+        const double tg0 = -1.0 / (2.0 * sqrt(3.0));
+        const double tg1 = 1.0 / (2.0 * sqrt(3.0));
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            double x = q == 0 ? tg0 : tg1;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                double v = 1.0;
+#pragma unroll
+                for (int m = 0; m < 4; m++)
+                    if (m != k) v *= (x - t[m]) / (t[k] - t[m]);
+                w[q][k] = v;
+            }
+        }
+    }
+};
+
+// Geometry of one cell: faces j-1/2, j+1/2 and the two Gauss points.
+struct CellGeom {
+    double sfm, sfp;
+    double sg[2], sxg[2], bxg[2];
+};
+
+__device__ __forceinline__ CellGeom load_geom(const Inst1D &I, int j)
+{
+    CellGeom G;
+    G.sfm = I.sig_face[j];
+    G.sfp = I.sig_face[j + 1];
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        G.sg[q] = I.sig_gp[2 * j + q];
+        G.sxg[q] = I.sigx_gp[2 * j + q];
+        G.bxg[q] = I.bx_gp[2 * j + q];
+    }
+    return G;
+}
+
+__device__ __forceinline__ bool subcrit(double H, double Q, double sig, double g)
+{
+    double h = H / sig;
+    double u = Q / H;
+    return u * u < g * h;
+}
+
+// Boundary ghosts from the boundary cell (c0) and its neighbour (c1): first and second ghost.
+__device__ __forceinline__ void ghost_pair(int kind, double q, double hb, double sig, double g,
+                                           double H0, double Q0, double H1, double Q1,
+                                           double &Hg0, double &Qg0, double &Hg1, double &Qg1)
+{
+    Hg0 = H0; Qg0 = Q0; Hg1 = H0; Qg1 = Q0;
+    if (kind == NMG_BC_DISCHARGE) {
+        Qg0 = q; Qg1 = q;
+        if (!subcrit(H0, Q0, sig, g) && hb > 0.0) { Hg0 = sig * hb; Hg1 = sig * hb; }
+    } else if (kind == NMG_BC_DEPTH) {
+        if (subcrit(H0, Q0, sig, g)) { Hg0 = sig * hb; Hg1 = sig * hb; }
+    } else if (kind == NMG_BC_WALL) {
+        Hg0 = H0; Qg0 = -Q0; Hg1 = H1; Qg1 = -Q1;
+    }
+}
+
+// Fill the ghost entries of a stencil (cells j-2..j+2 at positions 0..4) from its own interior
+// entries, so that ghosts follow any perturbation of the boundary cells.
+__device__ __forceinline__ void stencil_ghosts(double H[5], double Q[5], int j, const Inst1D &I)
+{
+    const int N = I.N;
+    if (j < 2) {
+        const int p0 = 2 - j;  // position of cell 0
+        double Hg0, Qg0, Hg1, Qg1;
+        double H0 = p0 == 1 ? H[1] : H[2], Q0 = p0 == 1 ? Q[1] : Q[2];
+        double H1 = p0 == 1 ? H[2] : H[3], Q1 = p0 == 1 ? Q[2] : Q[3];
+        ghost_pair(I.bc_kind[0], I.bc_q[0], I.bc_h[0], I.sig_face[0], I.g, H0, Q0, H1, Q1,
+                   Hg0, Qg0, Hg1, Qg1);
+        if (p0 == 1) { H[0] = Hg0; Q[0] = Qg0; }
+        else { H[1] = Hg0; Q[1] = Qg0; H[0] = Hg1; Q[0] = Qg1; }
+    }
+    if (j > N - 3) {
+        const int pb = N - 1 - j + 2;  // position of cell N-1 (2 or 3)
+        double Hg0, Qg0, Hg1, Qg1;
+        double H0 = pb == 3 ? H[3] : H[2], Q0 = pb == 3 ? Q[3] : Q[2];
+        double H1 = pb == 3 ? H[2] : H[1], Q1 = pb == 3 ? Q[2] : Q[1];
+        ghost_pair(I.bc_kind[1], I.bc_q[1], I.bc_h[1], I.sig_face[N], I.g, H0, Q0, H1, Q1,
+                   Hg0, Qg0, Hg1, Qg1);
+        if (pb == 3) { H[4] = Hg0; Q[4] = Qg0; }
+        else { H[3] = Hg0; Q[3] = Qg0; H[4] = Hg1; Q[4] = Qg1; }
+    }
+}
+
+// Local residual of eq. (10) from a ghost-complete stencil.
+__device__ __forceinline__ void local_residual(const double H[5], const double Q[5],
+                                               const CellGeom &G, const CubicGauss &W,
+                                               double dx, double g, double &R0, double &R1)
+{
+    // face j-1/2: left state from cell j-1, right state from cell j
+    double Hm_l = weno_minus(H[0], H[1], H[2]), Qm_l = weno_minus(Q[0], Q[1], Q[2]);
+    double Hp_l = weno_plus(H[1], H[2], H[3]), Qp_l = weno_plus(Q[1], Q[2], Q[3]);
+    // face j+1/2: left state from cell j, right state from cell j+1
+    double Hm_r = weno_minus(H[1], H[2], H[3]), Qm_r = weno_minus(Q[1], Q[2], Q[3]);
+    double Hp_r = weno_plus(H[2], H[3], H[4]), Qp_r = weno_plus(Q[2], Q[3], Q[4]);
+    // outer nodes of the source cubic: H+_{j-3/2} (cell j-1) and H-_{j+3/2} (cell j+1)
+    double Hp_ll = weno_plus(H[0], H[1], H[2]);
+    double Hm_rr = weno_minus(H[2], H[3], H[4]);
+
+    double Fm0, Fm1, Fp0, Fp1;
+    hll(Hm_l, Qm_l, Hp_l, Qp_l, G.sfm, g, Fm0, Fm1);
+    hll(Hm_r, Qm_r, Hp_r, Qp_r, G.sfp, g, Fp0, Fp1);
+
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        double Hg = W.w[q][0] * Hp_ll + W.w[q][1] * Hp_l + W.w[q][2] * Hm_r + W.w[q][3] * Hm_rr;
+        double hg = Hg / G.sg[q];
+        double s = 0.5 * g * hg * hg * G.sxg[q] - g * G.sg[q] * hg * G.bxg[q];
+        sum = sum + s;
+    }
+    double S = 0.5 * dx * sum;
+    R0 = Fp0 - Fm0;
+    R1 = Fp1 - Fm1 - S;
+}
+
+// Stage U[a-2 .. a+kTile+1] of one instance into LDS (zeros outside the grid).
+__device__ __forceinline__ void stage_state(const Inst1D &I, int a, double (*sH), double (*sQ))
+{
+    for (int k = threadIdx.x; k < kTile + 4; k += kTile) {
+        int c = a - 2 + k;
+        bool ok = c >= 0 && c < I.N;
+        sH[k] = ok ? I.U[c] : 0.0;
+        sQ[k] = ok ? I.U[I.N + c] : 0.0;
+    }
+}
+
+__device__ __forceinline__ bool inst_active(const NewtonState *state, const Inst1D &I)
+{
+    return state == nullptr || state[I.active_idx].active;
+}
+
+__device__ double block_sum(double v, double *scratch)
+{
+    // wavefront reduction then a fixed-order sum over the 4 wavefronts
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kTile / 64; w++) s += scratch[w];
+    return s;
+}
+
+__device__ void residual_tile(const Inst1D &I, int a, double *partial_out)
+{
+    __shared__ double sH[kTile + 4], sQ[kTile + 4];
+    __shared__ double red[kTile / 64];
+    stage_state(I, a, sH, sQ);
+    __syncthreads();
+    const int j = a + threadIdx.x;
+    double n1 = 0.0;
+    if (j < I.N) {
+        double H[5], Q[5];
+#pragma unroll
+        for (int p = 0; p < 5; p++) { H[p] = sH[threadIdx.x + p]; Q[p] = sQ[threadIdx.x + p]; }
+        stencil_ghosts(H, Q, j, I);
+        CellGeom G = load_geom(I, j);
+        CubicGauss W;
+        double R0, R1;
+        local_residual(H, Q, G, W, I.dx, I.g, R0, R1);
+        I.R[j] = R0;
+        I.R[I.N + j] = R1;
+        n1 = fabs(R0) + fabs(R1);
+        I.rn[j] = n1;
+    }
+    double s = block_sum(n1, red);
+    if (threadIdx.x == 0 && partial_out) *partial_out = s;
+}
+
+__global__ void __launch_bounds__(kTile) k_residual_batch(const Inst1D *insts, const Tile *tiles,
+                                                          NewtonState *state, double *partial)
+{
+    const Tile t = tiles[blockIdx.x];
+    const Inst1D &I = insts[t.lev];
+    if (!inst_active(state, I)) return;
+    residual_tile(I, t.a, partial + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kTile) k_residual_single(Inst1D I)
+{
+    residual_tile(I, blockIdx.x * kTile, nullptr);
+}
+
+// res = (1/N) sum_j rn_j for a single instance: one workgroup, fixed order.
+__global__ void __launch_bounds__(kTile) k_sum_res(const double *rn, int N, double *res)
+{
+    __shared__ double red[kTile / 64];
+    double v = 0.0;
+    for (int j = threadIdx.x; j < N; j += kTile) v += rn[j];
+    double s = block_sum(v, red);
+    if (threadIdx.x == 0) *res = s / N;
+}
+
+// Per instance: res from the tile partials (fixed order), Newton counter and stopping test of
+// Algorithm 1 (res < tol or n >= n_max; non-finite res stops with an error).
+__global__ void k_res_finalize(const Inst1D *insts, int ninst, NewtonState *state,
+                               const double *partial, int init)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= ninst) return;
+    const Inst1D &I = insts[b];
+    NewtonState &S = state[I.active_idx];
+    if (!init && !S.active) return;
+    double s = 0.0;
+    for (int k = 0; k < I.res_tiles; k++) s += partial[I.res_tile0 + k];
+    const double res = s / I.N;
+    S.res = res;
+    if (init) {
+        S.n = 0;
+        S.active = 1;
+        S.status = NMG_NOT_CONVERGED;
+        if (!(res == res) || res > 1e300) { S.active = 0; S.status = NMG_ENONFINITE; }
+        return;
+    }
+    if (I.hist && S.n < I.max_hist) I.hist[S.n] = res;
+    S.n += 1;
+    if (!(res == res) || res > 1e300) { S.active = 0; S.status = NMG_ENONFINITE; }
+    else if (res < I.tol) { S.active = 0; S.status = NMG_OK; }
+    else if (S.n >= I.n_max) { S.active = 0; S.status = NMG_NOT_CONVERGED; }
+}
+
+// ---- Jacobian --------------------------------------------------------------------------
+
+template <typename T, int NB>
+__device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride)
+{
+    __shared__ double sH[kTile + 4], sQ[kTile + 4];
+    stage_state(I, a, sH, sQ);
+    __syncthreads();
+    const int j = a + threadIdx.x;
+    if (j >= I.N) return;
+    constexpr int HW = NB / 2;
+    double H[5], Q[5];
+#pragma unroll
+    for (int p = 0; p < 5; p++) { H[p] = sH[threadIdx.x + p]; Q[p] = sQ[threadIdx.x + p]; }
+    const CellGeom G = load_geom(I, j);
+    const CubicGauss W;
+    const double R0 = I.R[j], R1 = I.R[I.N + j], rn = I.rn[j];
+    const double eps = I.eps;
+    for (int b = 0; b < NB; b++) {
+        const int i = j + b - HW;
+        const bool col_ok = i >= 0 && i < I.N;
+        const int pp = 2 + b - HW;  // stencil position of the perturbed cell
+        for (int m = 0; m < 2; m++) {
+            double e0 = 0.0, e1 = 0.0;
+            if (col_ok) {
+                double Hp[5], Qp[5];
+#pragma unroll
+                for (int p = 0; p < 5; p++) {
+                    Hp[p] = (p == pp && m == 0) ? H[p] + eps : H[p];
+                    Qp[p] = (p == pp && m == 1) ? Q[p] + eps : Q[p];
+                }
+                stencil_ghosts(Hp, Qp, j, I);
+                double P0, P1;
+                local_residual(Hp, Qp, G, W, I.dx, I.g, P0, P1);
+                e0 = (P0 - R0) / eps;
+                e1 = (P1 - R1) / eps;
+                if (b == HW) {
+                    if (m == 0) e0 += I.alpha * rn;
+                    else e1 += I.alpha * rn;
+                }
+            }
+            J[((b * 2 + 0) * 2 + m) * (long long)stride + j] = (T)e0;
+            J[((b * 2 + 1) * 2 + m) * (long long)stride + j] = (T)e1;
+        }
+    }
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(kTile) k_jacobian_batch(MGArgs mg, const Tile *tiles)
+{
+    const Tile t = tiles[blockIdx.x];
+    const Inst1D &I = mg.insts[t.lev];
+    if (!inst_active(mg.state, I)) return;
+    const Level1D &L = mg.levs[I.lev0];
+    if (L.nb != NB) return;
+    jacobian_tile<T, NB>(I, t.a, reinterpret_cast<T *>(mg.mg) + L.J, L.n);
+}
+
+template <int NB>
+__global__ void __launch_bounds__(kTile) k_jacobian_single(Inst1D I, double *J)
+{
+    jacobian_tile<double, NB>(I, blockIdx.x * kTile, J, I.N);
+}
+
+// ---- launchers ---------------------------------------------------------------------------
+
+hipError_t launch_residual1d(const Inst1D *insts_dev, const Tile *tiles, int ntiles,
+                             const Inst1D *single, NewtonState *state, double *partial,
+                             hipStream_t s)
+{
+    if (single) {
+        int nt = (single->N + kTile - 1) / kTile;
+        hipLaunchKernelGGL(k_residual_single, dim3(nt), dim3(kTile), 0, s, *single);
+    } else {
+        if (ntiles == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_residual_batch, dim3(ntiles), dim3(kTile), 0, s, insts_dev, tiles,
+                           state, partial);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_res_finalize(const Inst1D *insts_dev, int ninst, NewtonState *state,
+                               const double *partial, int init, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_res_finalize, dim3((ninst + 63) / 64), dim3(64), 0, s, insts_dev, ninst,
+                       state, partial, init);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_res(const double *rn, int N, double *res, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_res, dim3(1), dim3(kTile), 0, s, rn, N, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobian1d(const Inst1D *insts_dev, const Tile *tiles, int ntiles,
+                             const Inst1D *single, double *J_single, const MGArgs &mg, int prec,
+                             int nb_mask, hipStream_t s)
+{
+    if (single) {
+        int nt = (single->N + kTile - 1) / kTile;
+        if (single->nb == 5)
+            hipLaunchKernelGGL(k_jacobian_single<5>, dim3(nt), dim3(kTile), 0, s, *single, J_single);
+        else
+            hipLaunchKernelGGL(k_jacobian_single<3>, dim3(nt), dim3(kTile), 0, s, *single, J_single);
+        return hipGetLastError();
+    }
+    if (ntiles == 0) return hipSuccess;
+    (void)insts_dev;
+    // one launch per stencil width present; each tile runs only the one its instance uses
+    if (prec == NMG_FP32_MG) {
+        if (nb_mask & 1) hipLaunchKernelGGL((k_jacobian_batch<float, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+        if (nb_mask & 2) hipLaunchKernelGGL((k_jacobian_batch<float, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+    } else {
+        if (nb_mask & 1) hipLaunchKernelGGL((k_jacobian_batch<double, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+        if (nb_mask & 2) hipLaunchKernelGGL((k_jacobian_batch<double, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace nmg

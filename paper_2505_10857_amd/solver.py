@@ -1,0 +1,201 @@
+"""Python binding of libnmg: marshals problems and torch device tensors into the C ABI.
+
+Every step of the solver runs in the HIP library; this module only samples the problem's
+geometry at the points the discretisation uses, allocates device memory through torch and
+passes pointers and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+
+def _stream_ptr() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def params_struct(p, precision: int = A.NMG_FP64, check_every: int = 4) -> A.nmg_params:
+    s = A.nmg_params()
+    s.alpha, s.tau, s.eps, s.omega, s.tol = p.alpha, p.tau, p.eps, p.omega, p.tol
+    s.nu1, s.nu2, s.nu3, s.n_max = p.nu1, p.nu2, p.nu3, p.n_max
+    s.precision = precision
+    s.check_every = check_every
+    return s
+
+
+class Problem1DDevice:
+    """Device-resident description of one quasi-1D problem (eq. 3-4): geometry sampled at the
+    faces and at the two Gauss points x_j -/+ dx/(2 sqrt 3) of each cell (eq. 9)."""
+
+    def __init__(self, prob, device="cuda", jac: int = 3):
+        self.prob = prob
+        n, dx = prob.n, prob.dx
+        xf = prob.x0 + np.arange(n + 1) * dx
+        xc = prob.x0 + (np.arange(n) + 0.5) * dx
+        off = dx / (2.0 * math.sqrt(3.0))
+        xg = np.empty(2 * n)
+        xg[0::2] = xc - off
+        xg[1::2] = xc + off
+        s, sx = prob.width(xg)
+        _, bx = prob.bottom(xg)
+        f64 = dict(dtype=torch.float64, device=device)
+        self.sig_face = torch.tensor(np.ascontiguousarray(prob.width(xf)[0]), **f64)
+        self.sig_gp = torch.tensor(np.ascontiguousarray(s), **f64)
+        self.sigx_gp = torch.tensor(np.ascontiguousarray(sx), **f64)
+        self.bx_gp = torch.tensor(np.ascontiguousarray(bx), **f64)
+        d = A.nmg_desc()
+        d.dim, d.nx, d.ny, d.levels, d.jac = 1, n, 1, prob.levels, jac
+        d.x0, d.x1, d.y0, d.y1, d.g = prob.x0, prob.x1, 0.0, 1.0, prob.g
+        for k, bc in enumerate((prob.bc_left, prob.bc_right)):
+            d.bc[k].kind, d.bc[k].q, d.bc[k].h = bc.kind, bc.q, bc.h
+        d.sig_face = self.sig_face.data_ptr()
+        d.sig_gp = self.sig_gp.data_ptr()
+        d.sigx_gp = self.sigx_gp.data_ptr()
+        d.bx_gp = self.bx_gp.data_ptr()
+        self.desc = d
+        self.n = n
+        self.device = device
+
+    def with_jac(self, jac: int) -> "Problem1DDevice":
+        self.desc.jac = jac
+        return self
+
+
+class Solver1D:
+    """Single-instance entry points of the C ABI for one problem."""
+
+    def __init__(self, prob, device="cuda", jac: int = 3, precision: int = A.NMG_FP64,
+                 check_every: int = 4, **param_overrides):
+        A.load()
+        self.dev = Problem1DDevice(prob, device, jac)
+        p = prob.params
+        if param_overrides:
+            import dataclasses
+            p = dataclasses.replace(p, **param_overrides)
+        self.p = p
+        self.params = params_struct(p, precision, check_every)
+        self.precision = precision
+        self.n = prob.n
+        self.jac = jac
+        self.device = device
+        self._ws = None
+
+    @property
+    def L(self):
+        return A.load()
+
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            nbytes = self.L.nmg_workspace_bytes(C.byref(self.dev.desc), C.byref(self.params))
+            if nbytes == 0:
+                raise A.NmgError(A.NMG_EINVAL, self.L.nmg_last_error().decode())
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def state(self, U=None) -> torch.Tensor:
+        U = self.dev.prob.initial_guess() if U is None else U
+        if isinstance(U, torch.Tensor):
+            return U.to(device=self.device, dtype=torch.float64).contiguous().clone()
+        return torch.tensor(np.ascontiguousarray(U), dtype=torch.float64, device=self.device)
+
+    def residual(self, U: torch.Tensor):
+        """R [2, N], rn [N], res (0-d tensor) on the device (eq. 10, Algorithm 1)."""
+        R = torch.empty_like(U)
+        rn = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        res = torch.empty((), dtype=torch.float64, device=self.device)
+        A.check(self.L.nmg_residual(C.byref(self.dev.desc), _dptr(U), _dptr(R), _dptr(rn),
+                                    _dptr(res), C.c_void_p(_stream_ptr())))
+        return R, rn, res
+
+    def jacobian(self, U, R, rn) -> torch.Tensor:
+        """Blocks J [nb, 2, 2, N] (eq. 12-13) on the device."""
+        J = torch.empty((self.jac, 2, 2, self.n), dtype=torch.float64, device=self.device)
+        A.check(self.L.nmg_jacobian_assemble_simplified(
+            C.byref(self.dev.desc), C.byref(self.params), _dptr(U), _dptr(R), _dptr(rn), _dptr(J),
+            C.c_void_p(_stream_ptr())))
+        return J
+
+    def vcycle(self, J: Optional[torch.Tensor], rhs: torch.Tensor, dU: torch.Tensor, setup: bool):
+        """One V-cycle for sum_i J_ji dU_i = -rhs_j; dU is updated in place."""
+        ws = self.workspace()
+        A.check(self.L.nmg_mg_vcycle(C.byref(self.dev.desc), C.byref(self.params), _dptr(ws),
+                                     ws.numel(), _dptr(J) if J is not None else None, _dptr(rhs),
+                                     _dptr(dU), 1 if setup else 0, C.c_void_p(_stream_ptr())))
+        return dU
+
+    def newton_solve(self, U: torch.Tensor, max_hist: int = 0):
+        """Algorithm 1 in place on U.  Returns (stats, history ndarray)."""
+        ws = self.workspace()
+        st = A.nmg_stats()
+        hist = (C.c_double * max(1, max_hist))()
+        status = self.L.nmg_newton_solve(C.byref(self.dev.desc), C.byref(self.params), _dptr(ws),
+                                         ws.numel(), _dptr(U), C.byref(st),
+                                         hist if max_hist > 0 else None, max_hist,
+                                         C.c_void_p(_stream_ptr()))
+        A.check(status, ok=(A.NMG_OK, A.NMG_NOT_CONVERGED, A.NMG_ENONFINITE))
+        h = np.array(hist[:min(max_hist, st.iters)]) if max_hist > 0 else np.zeros(0)
+        return st, h
+
+
+class BatchSolver1D:
+    """Many independent 1D problems solved together (one launch per kernel per step)."""
+
+    def __init__(self, probs: Sequence, device="cuda", jac: int = 3, precision: int = A.NMG_FP64,
+                 check_every: int = 4, jacs: Optional[Sequence[int]] = None):
+        A.load()
+        self.devs = [Problem1DDevice(p, device, (jacs[k] if jacs else jac)) for k, p in enumerate(probs)]
+        self.probs = list(probs)
+        n = len(probs)
+        self.descs = (A.nmg_desc * n)(*[d.desc for d in self.devs])
+        self.params = (A.nmg_params * n)(*[params_struct(p.params, precision, check_every) for p in probs])
+        self.device = device
+        self.n = n
+        self.plan = C.c_void_p()
+        A.check(A.load().nmg_plan_create(self.descs, self.params, n, C.byref(self.plan)))
+        self.ws_bytes = A.load().nmg_plan_workspace_bytes(self.plan)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def __del__(self):
+        try:
+            if self.plan:
+                A.load().nmg_plan_destroy(self.plan)
+        except Exception:
+            pass
+
+    def states(self, Us=None) -> List[torch.Tensor]:
+        out = []
+        for k, p in enumerate(self.probs):
+            U = p.initial_guess() if Us is None else Us[k]
+            out.append(torch.tensor(np.ascontiguousarray(U), dtype=torch.float64, device=self.device)
+                       if not isinstance(U, torch.Tensor) else U)
+        return out
+
+    def solve(self, Us: List[torch.Tensor], use_graph: bool = True):
+        ptrs = (C.c_void_p * self.n)(*[u.data_ptr() for u in Us])
+        stats = (A.nmg_stats * self.n)()
+        st = A.load().nmg_plan_solve(self.plan, _dptr(self.ws), self.ws_bytes, ptrs, stats,
+                                     1 if use_graph else 0, C.c_void_p(_stream_ptr()))
+        A.check(st, ok=(A.NMG_OK, A.NMG_NOT_CONVERGED, A.NMG_ENONFINITE))
+        return [(s.iters, s.status, s.res) for s in stats]
+
+    def begin(self, Us: List[torch.Tensor]):
+        self._ptrs = (C.c_void_p * self.n)(*[u.data_ptr() for u in Us])
+        A.check(A.load().nmg_plan_begin(self.plan, _dptr(self.ws), self.ws_bytes, self._ptrs,
+                                        C.c_void_p(_stream_ptr())))
+
+    def steps(self, k: int, use_graph: bool = True):
+        active = (C.c_int32 * self.n)()
+        stats = (A.nmg_stats * self.n)()
+        A.check(A.load().nmg_plan_steps(self.plan, _dptr(self.ws), k, 1 if use_graph else 0, active,
+                                        stats, C.c_void_p(_stream_ptr())))
+        return list(active), [(s.iters, s.status, s.res) for s in stats]

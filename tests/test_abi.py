@@ -1,0 +1,93 @@
+"""The C-ABI library loads and exports every entry point include/nmg.h declares (CPU only:
+no compute call is made without a GPU); host-side argument checks reject bad input."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nmg.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(nmg_\w+)\s*\(", txt)))
+
+
+def _lib():
+    from paper_2505_10857_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.skip("libnmg.so not built (run __graft_entry__.build())")
+    return _abi, _abi.load()
+
+
+def test_header_declares_the_four_paper_calls():
+    names = _declared()
+    for n in ("nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle", "nmg_newton_solve"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    abi, L = _lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(abi.EXPORTS) <= set(_declared())
+
+
+def test_struct_sizes_match_header_layout():
+    abi, _ = _lib()
+    assert ctypes.sizeof(abi.nmg_bc) == 40
+    assert ctypes.sizeof(abi.nmg_desc) == 24 + 40 + 4 * 40 + 8 + 5 * 8
+    assert ctypes.sizeof(abi.nmg_params) == 5 * 8 + 6 * 4
+
+
+def _desc(abi, nx=64, levels=3, jac=3):
+    d = abi.nmg_desc()
+    d.dim, d.nx, d.ny, d.levels, d.jac = 1, nx, 1, levels, jac
+    d.x0, d.x1, d.g = 0.0, 1.0, 9.812
+    d.sig_face = d.sig_gp = d.sigx_gp = d.bx_gp = 8   # non-null placeholders; never dereferenced
+    p = abi.nmg_params()
+    p.alpha, p.tau, p.eps, p.omega, p.tol = 3.0, 0.6, 0.01, 1.0, 1e-10
+    p.nu1 = p.nu2 = p.nu3 = 2
+    p.n_max = 100
+    p.check_every = 1
+    return d, p
+
+
+def test_workspace_query_and_argument_checks():
+    abi, L = _lib()
+    d, p = _desc(abi)
+    assert L.nmg_workspace_bytes(ctypes.byref(d), ctypes.byref(p)) > 0
+    bad = [dict(nx=60, levels=4),      # not divisible by 2^(levels-1)
+           dict(nx=4096, levels=2),    # coarsest level too large
+           dict(jac=4), dict(levels=1)]
+    for kw in bad:
+        d2, p2 = _desc(abi, **kw)
+        assert L.nmg_workspace_bytes(ctypes.byref(d2), ctypes.byref(p2)) == 0
+        assert L.nmg_last_error()
+    d3, p3 = _desc(abi)
+    p3.eps = 0.0
+    assert L.nmg_workspace_bytes(ctypes.byref(d3), ctypes.byref(p3)) == 0
+    # residual with a null state pointer fails on the host before any launch
+    assert L.nmg_residual(ctypes.byref(d), None, None, None, None, None) == abi.NMG_EINVAL
+    # workspace too small
+    st = abi.nmg_stats()
+    assert L.nmg_newton_solve(ctypes.byref(d), ctypes.byref(p), ctypes.c_void_p(256), 16,
+                              ctypes.c_void_p(512), ctypes.byref(st), None, 0, None) == abi.NMG_ENOMEM_WS
+
+
+def test_plan_rejects_mixed_precision():
+    abi, L = _lib()
+    d1, p1 = _desc(abi)
+    d2, p2 = _desc(abi, nx=128, levels=4)
+    p2.precision = abi.NMG_FP32_MG
+    descs = (abi.nmg_desc * 2)(d1, d2)
+    params = (abi.nmg_params * 2)(p1, p2)
+    plan = ctypes.c_void_p()
+    assert L.nmg_plan_create(descs, params, 2, ctypes.byref(plan)) == abi.NMG_EINVAL
+    params[1].precision = abi.NMG_FP64
+    assert L.nmg_plan_create(descs, params, 2, ctypes.byref(plan)) == abi.NMG_OK
+    assert L.nmg_plan_workspace_bytes(plan) > L.nmg_workspace_bytes(ctypes.byref(d1), ctypes.byref(p1))
+    L.nmg_plan_destroy(plan)
