@@ -303,7 +303,7 @@ __global__ void k_res_finalize(const Inst1D *insts, int ninst, NewtonState *stat
 // ---- Jacobian --------------------------------------------------------------------------
 
 template <typename T, int NB>
-__device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride)
+__device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs)
 {
     __shared__ double sH[kTile + 4], sQ[kTile + 4];
     stage_state(I, a, sH, sQ);
@@ -318,6 +318,10 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride)
     const CubicGauss W;
     const double R0 = I.R[j], R1 = I.R[I.N + j], rn = I.rn[j];
     const double eps = I.eps;
+    if (rhs) {   // the finest level's right-hand side of eq. (16) is R itself
+        rhs[j] = (T)R0;
+        rhs[stride + j] = (T)R1;
+    }
     for (int b = 0; b < NB; b++) {
         const int i = j + b - HW;
         const bool col_ok = i >= 0 && i < I.N;
@@ -355,13 +359,14 @@ __global__ void __launch_bounds__(kTile) k_jacobian_batch(MGArgs mg, const Tile 
     if (!inst_active(mg.state, I)) return;
     const Level1D &L = mg.levs[I.lev0];
     if (L.nb != NB) return;
-    jacobian_tile<T, NB>(I, t.a, reinterpret_cast<T *>(mg.mg) + L.J, L.n);
+    T *base = reinterpret_cast<T *>(mg.mg);
+    jacobian_tile<T, NB>(I, t.a, base + L.J, L.n, base + L.rhs);
 }
 
 template <int NB>
 __global__ void __launch_bounds__(kTile) k_jacobian_single(Inst1D I, double *J)
 {
-    jacobian_tile<double, NB>(I, blockIdx.x * kTile, J, I.N);
+    jacobian_tile<double, NB>(I, blockIdx.x * kTile, J, I.N, (double *)nullptr);
 }
 
 // ---- launchers ---------------------------------------------------------------------------

@@ -122,7 +122,7 @@ def test_newton_trajectory_parity(name, prob):
         U = s2.state()
         st, _ = s2.newton_solve(U)
         Uo, ito, reso, _ = o.newton_solve(n_max=steps)
-        assert st.iters == ito
+        assert st.iters == ito, (st.iters, st.status, st.res, ito, reso)
         err = np.abs(U.cpu().numpy() - Uo).max()
         print(f"{name}: after {steps} steps |U_gpu - U_oracle| = {err:.3e}")
         assert err <= 1e-10
