@@ -1,0 +1,201 @@
+"""Benchmark: steady solves/s of the Newton multigrid path on one MI355X.
+
+Workload (default): the 1D shallow-water flow over a hump, N = 12800 cells, 8 grid levels,
+subcritical (q = 4.42, h_out = 2), simplified Jacobian J3 (NMGM-3), FP64 throughout, solved
+from the flat-surface initial guess to res < 1e-10.  A "step" is one batch of B such problems
+(hump scale s ~ U(0.8, 1.2), one seed per problem) solved to convergence: every Newton step of
+every instance runs the whole hot path (residual, Jacobian, coarse operators, nu3 V-cycles,
+update).  value = B * steps / timed wall time.  Inputs are resident in HBM before the timed
+region starts.
+
+Also reported: Newton-MG DOF/s, the single-instance solve rate and latency, the full Jacobian
+J5 side by side, the FP32-multigrid form, the roofline of the dominant kernel (HIP events on
+the launch stream) and the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6
+
+# Algorithmic FP64 operations of one local residual evaluation of eq. (10) (each add, mul, div
+# and sqrt counts one): ten WENO3 reconstructions (22 each), two HLL fluxes (46 each), the
+# two-point Gauss source (36) and the final differences (3).
+FLOPS_LOCAL_RESIDUAL = 10 * 22 + 2 * 46 + 36 + 3
+# Algorithmic HBM bytes per cell and launch (FP64, J3):
+#   Jacobian: read U 16, R 16, rn 8, geometry 7*8 = 56; write J 96 and rhs 16
+BYTES_JACOBIAN_J3 = 16 + 16 + 8 + 56 + 96 + 16
+#   finest pre-smoothing: read J 96, Dinv 32, rhs 16, (dU 16 unless zero-initial);
+#   write dU 16 and the restricted rhs 8 per fine cell
+BYTES_SMOOTH_PRE_J3 = 96 + 32 + 16 + 16 + 16 + 8
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--n", type=int, default=12800)
+    ap.add_argument("--levels", type=int, default=8)
+    ap.add_argument("--variant", default="sub")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-instances", type=int, default=3)
+    return ap.parse_args()
+
+
+def make_batch(B, n, levels, variant):
+    from swe_workloads import config2
+    return [config2(i, variant, n=n, levels=levels) for i in range(B)]
+
+
+def timed_solves(solver, U0s, steps, warmup, use_graph, profile_kernel=None):
+    """Solve the batch warmup + steps times from fresh copies of the initial states (all
+    copies made before timing).  Returns (elapsed s, per-solve stats list, kernel ms, launches)."""
+    import torch
+    sets = [[u.clone() for u in U0s] for _ in range(warmup + steps)]
+    torch.cuda.synchronize()
+    for w in range(warmup):
+        solver.solve(sets[w], use_graph=use_graph)
+    if profile_kernel is not None:
+        solver.profile(profile_kernel)
+        solver.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(steps):
+        stats.append(solver.solve(sets[warmup + k], use_graph=use_graph))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kms, kcnt = (0.0, 0)
+    if profile_kernel is not None:
+        kms, kcnt = solver.profile_read()
+        solver.profile(0)
+    return el, stats, kms, kcnt, sets[-1]
+
+
+def cpu_baseline(args):
+    """The oracle as it stands, single-threaded, on a bounded sample of the workload."""
+    import oracle
+    probs = make_batch(args.cpu_instances, args.n, args.levels, args.variant)
+    t0 = time.perf_counter()
+    its = 0
+    for p in probs:
+        U, it, res, _ = oracle.Oracle1D(p).newton_solve()
+        its += it
+    el = time.perf_counter() - t0
+    return {"value": len(probs) / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(probs)} instances of the benchmark workload (seeds 0..{len(probs) - 1}), "
+                      f"single-threaded FP64 C oracle, {its} Newton steps in {el:.1f} s",
+            "dof_per_s": 2 * args.n * its / el}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on "
+              f"one MI355X; independent instances would shard across GPUs without communication).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2505_10857_amd import NMG_FP32_MG, NMG_FP64, BatchSolver1D
+    from paper_2505_10857_amd import _abi as A
+
+    torch.cuda.set_device(0)
+    use_graph = not args.no_graph
+    probs = make_batch(args.batch, args.n, args.levels, args.variant)
+    solver = BatchSolver1D(probs, device="cuda:0", jac=3, precision=NMG_FP64)
+    U0s = solver.states()
+
+    # ---- main timed region -------------------------------------------------------------------
+    el, stats, _, _, Ulast = timed_solves(solver, U0s, args.steps, args.warmup, use_graph)
+    newton = [s[0] for s in stats[-1]]
+    ok = all(s[1] == 0 and s[2] < 1e-10 for st in stats for s in st)
+    nsolves = args.batch * args.steps
+    value = nsolves / el
+    dofs = sum(2 * args.n * s[0] for st in stats for s in st) / el
+    out = {
+        "metric": "steady solves/s at FP64 res < 1e-10 (NMGM-3)",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"1D SWE flow over a hump on [0,25], N={args.n}, {args.levels} levels, "
+                               f"{args.variant}critical, J3, FP64, batch of {args.batch} seeded instances "
+                               f"per step solved to res<1e-10",
+                   "n": args.n, "levels": args.levels, "batch": args.batch, "variant": args.variant,
+                   "hip_graph": use_graph},
+        "dof_per_s": dofs,
+        "newton_steps_per_solve": [min(newton), max(newton)],
+        "converged": ok,
+    }
+
+    # ---- roofline of the dominant kernel: HIP events around its launches on the launch stream --
+    el2, _, jms, jcnt, _ = timed_solves(solver, U0s, 1, 0, False, A.NMG_K_JACOBIAN)
+    _, _, pms, pcnt, _ = timed_solves(solver, U0s, 1, 0, False, A.NMG_K_SMOOTH_PRE)
+    cells = args.batch * args.n
+    jac_ms = jms / max(jcnt, 1)
+    pre_ms = pms / max(pcnt, 1)
+    jac_flops = cells * 6 * FLOPS_LOCAL_RESIDUAL
+    out["roofline"] = {
+        "kernel": "k_jacobian_batch<double,3> (FD Jacobian J3, eq. 12-13)",
+        "bound": "alu", "achieved": jac_flops / (jac_ms * 1e-3) / 1e12,
+        "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+        "frac": jac_flops / (jac_ms * 1e-3) / 1e12 / FP64_VECTOR_TFLOPS,
+        "traffic": None,
+        "avg_launch_ms": jac_ms, "launches_timed": jcnt,
+        "algorithmic_flops_per_launch": jac_flops,
+        "hbm_gbs": cells * BYTES_JACOBIAN_J3 / (jac_ms * 1e-3) / 1e9,
+        "share_of_step_time": jms / (el2 * 1e3),
+    }
+    out["smoother_roofline"] = {
+        "kernel": "k_smooth<double,3> mode 0, finest level (pre-smoothing + restriction)",
+        "bound": "hbm", "avg_launch_ms": pre_ms, "launches_timed": pcnt,
+        "achieved": cells * BYTES_SMOOTH_PRE_J3 / (pre_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": cells * BYTES_SMOOTH_PRE_J3 / (pre_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "note": "working set below the 256 MB Infinity Cache: effective GB/s",
+    }
+
+    # ---- extra forms --------------------------------------------------------------------------
+    if not args.no_extras:
+        forms = {}
+        # single instance, one solve at a time
+        single = BatchSolver1D(probs[:1], device="cuda:0", jac=3, precision=NMG_FP64)
+        u1 = single.states()
+        e1, st1, _, _, _ = timed_solves(single, u1, 5, 1, use_graph)
+        forms["fp64_single_instance"] = {"solves_per_s": 5 / e1, "latency_ms": 1e3 * e1 / 5,
+                                         "newton_steps": st1[-1][0][0]}
+        # full Jacobian J5, batched
+        s5 = BatchSolver1D(probs, device="cuda:0", jac=5, precision=NMG_FP64)
+        e5, st5, _, _, _ = timed_solves(s5, s5.states(), max(1, args.steps // 2), 1, use_graph)
+        forms["fp64_batch_J5"] = {"solves_per_s": args.batch * max(1, args.steps // 2) / e5,
+                                  "newton_steps": [min(s[0] for s in st5[-1]), max(s[0] for s in st5[-1])]}
+        forms["fp64_batch_J3"] = {"solves_per_s": value, "newton_steps": out["newton_steps_per_solve"]}
+        # FP32 multigrid, FP64 residual / update / test
+        s32 = BatchSolver1D(probs, device="cuda:0", jac=3, precision=NMG_FP32_MG)
+        e32, st32, _, _, U32 = timed_solves(s32, s32.states(), args.steps, 1, use_graph)
+        err = max(float((a - b).abs().max()) for a, b in zip(U32, Ulast))
+        forms["fp32mg_batch_J3"] = {"solves_per_s": args.batch * args.steps / e32,
+                                    "newton_steps": [min(s[0] for s in st32[-1]), max(s[0] for s in st32[-1])],
+                                    "max_abs_diff_vs_fp64_gpu": err,
+                                    "converged": all(s[1] == 0 and s[2] < 1e-10 for st in st32 for s in st)}
+        out["forms"] = forms
+
+    # ---- CPU oracle ----------------------------------------------------------------------------
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,6 +155,20 @@ nmg_status nmg_plan_steps(nmg_plan *plan, void *ws, int32_t steps, int32_t use_g
                           int32_t *active_out, nmg_stats *stats, void *stream);
 void nmg_plan_destroy(nmg_plan *plan);
 
+/* Kernel timing for benchmarks: with kernel = one of NMG_K_*, every later non-graph step
+ * brackets each launch of that kernel with hipEvents on the launch stream (graph replays are
+ * not instrumented; NMG_K_NONE switches timing off).  nmg_plan_profile_read returns the summed
+ * event time in milliseconds and the number of timed launches since the last read, and resets
+ * both.  The read synchronises the stream. */
+#define NMG_K_NONE 0
+#define NMG_K_JACOBIAN 1      /* finite-difference Jacobian (section 3.2-3.3) */
+#define NMG_K_SMOOTH_PRE 2    /* finest-level pre-smoothing + restriction (eq. 17, 19) */
+#define NMG_K_SMOOTH_POST 3   /* finest-level prolongation + post-smoothing (eq. 18, 19) */
+#define NMG_K_RESIDUAL 4      /* residual (eq. 10) */
+#define NMG_K_COARSEN 5       /* coarse operators of all levels (eq. 17) */
+nmg_status nmg_plan_profile(nmg_plan *plan, int32_t kernel);
+nmg_status nmg_plan_profile_read(nmg_plan *plan, double *ms, int32_t *launches);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char *nmg_last_error(void);
 

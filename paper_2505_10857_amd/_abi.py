@@ -30,7 +30,15 @@ EXPORTS = [
     "nmg_workspace_bytes", "nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",
     "nmg_newton_solve", "nmg_plan_create", "nmg_plan_workspace_bytes", "nmg_plan_solve",
     "nmg_plan_begin", "nmg_plan_steps", "nmg_plan_destroy", "nmg_last_error",
+    "nmg_plan_profile", "nmg_plan_profile_read",
 ]
+
+NMG_K_NONE = 0
+NMG_K_JACOBIAN = 1
+NMG_K_SMOOTH_PRE = 2
+NMG_K_SMOOTH_POST = 3
+NMG_K_RESIDUAL = 4
+NMG_K_COARSEN = 5
 
 
 class nmg_bc(C.Structure):
@@ -93,6 +101,10 @@ def load(path: str = LIB_PATH):
     L.nmg_plan_steps.argtypes = [vp, vp, C.c_int32, C.c_int32, P(C.c_int32), P(nmg_stats), vp]
     L.nmg_plan_destroy.argtypes = [vp]
     L.nmg_plan_destroy.restype = None
+    L.nmg_plan_profile.argtypes = [vp, C.c_int32]
+    L.nmg_plan_profile.restype = C.c_int32
+    L.nmg_plan_profile_read.argtypes = [vp, P(C.c_double), P(C.c_int32)]
+    L.nmg_plan_profile_read.restype = C.c_int32
     L.nmg_last_error.argtypes = []
     L.nmg_last_error.restype = C.c_char_p
     for nm in ("nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",

@@ -119,8 +119,17 @@ struct nmg_plan {
     void *g_ws = nullptr;
     hipStream_t own_stream = nullptr;
     NewtonState *host_state = nullptr;        // pinned
+    // kernel timing
+    int prof_kernel = NMG_K_NONE;
+    std::vector<hipEvent_t> ev_pool;          // created lazily, reused
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_open;
+    hipStream_t prof_stream = nullptr;
+    double prof_ms = 0.0;
+    int prof_count = 0;
     ~nmg_plan()
     {
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
+        for (auto &pr : ev_open) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (own_stream) (void)hipStreamDestroy(own_stream);
@@ -246,6 +255,39 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
     return NMG_OK;
 }
 
+hipEvent_t take_event(nmg_plan *P)
+{
+    if (!P->ev_pool.empty()) {
+        hipEvent_t e = P->ev_pool.back();
+        P->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Bracket one launch of kernel `k` with events when it is the profiled kernel.
+struct ProfScope {
+    nmg_plan *P;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(nmg_plan *P_, int k, hipStream_t s_, bool capturing) : P(P_), s(s_)
+    {
+        if (capturing || P->prof_kernel != k) return;
+        a = take_event(P);
+        b = take_event(P);
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    ~ProfScope()
+    {
+        if (!a || !b) return;
+        (void)hipEventRecord(b, s);
+        P->ev_open.push_back({a, b});
+        P->prof_stream = s;
+    }
+};
+
 MGArgs mg_args(const nmg_plan *P, char *ws, bool with_state)
 {
     MGArgs a;
@@ -286,9 +328,12 @@ const Tile *tiles_at(const nmg_plan *P, char *ws, int t0)
 }
 
 // Coarse operators of every level, diagonal inverses and the coarsest factorisation.
-nmg_status enqueue_setup(nmg_plan *P, char *ws, const MGArgs &mg, hipStream_t s)
+nmg_status enqueue_setup(nmg_plan *P, char *ws, const MGArgs &mg, hipStream_t s, bool cap = true)
 {
-    for (auto &c : P->coarsen) HIP_TRY(launch_coarsen1d(mg, tiles_at(P, ws, c.first), c.second, P->prec, s));
+    for (auto &c : P->coarsen) {
+        ProfScope ps(P, NMG_K_COARSEN, s, cap);
+        HIP_TRY(launch_coarsen1d(mg, tiles_at(P, ws, c.first), c.second, P->prec, s));
+    }
     const int *list = reinterpret_cast<const int *>(ws + P->off_list);
     HIP_TRY(launch_coarse_factor(mg, list, P->n, P->prec, s));
     return NMG_OK;
@@ -296,35 +341,45 @@ nmg_status enqueue_setup(nmg_plan *P, char *ws, const MGArgs &mg, hipStream_t s)
 
 // One V-cycle (Algorithm 2) over every instance.
 nmg_status enqueue_vcycle(nmg_plan *P, char *ws, const MGArgs &mg, bool zero_init0, bool final_update,
-                          hipStream_t s)
+                          hipStream_t s, bool cap = true)
 {
     const int *list = reinterpret_cast<const int *>(ws + P->off_list);
-    for (int d = 0; d < P->depth; d++)
+    for (int d = 0; d < P->depth; d++) {
+        ProfScope ps(P, d == 0 ? NMG_K_SMOOTH_PRE : -1, s, cap);
         HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
                                 P->smooth_mask[d], 0, (d > 0 || zero_init0) ? 1 : 0, 0, P->prec, s));
+    }
     HIP_TRY(launch_coarse_solve(mg, list, P->n, P->prec, s));
-    for (int d = P->depth - 1; d >= 0; d--)
+    for (int d = P->depth - 1; d >= 0; d--) {
+        ProfScope ps(P, d == 0 ? NMG_K_SMOOTH_POST : -1, s, cap);
         HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
                                 P->smooth_mask[d], 1, 0, (d == 0 && final_update) ? 1 : 0, P->prec, s));
+    }
     return NMG_OK;
 }
 
-// One Newton step of Algorithm 1 for every active instance.
-nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s)
+// One Newton step of Algorithm 1 for every active instance.  `cap`: being captured into a graph.
+nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s, bool cap = false)
 {
     MGArgs mg = mg_args(P, ws, true);
     const Inst1D *insts = mg.insts;
     const Tile *rt = tiles_at(P, ws, P->res_t0);
     NewtonState *state = mg.state;
     double *partial = reinterpret_cast<double *>(ws + P->off_partial);
-    HIP_TRY(launch_jacobian1d(insts, rt, P->res_nt, nullptr, nullptr, mg, P->prec, P->jac_mask, s));
-    nmg_status st = enqueue_setup(P, ws, mg, s);
+    {
+        ProfScope ps(P, NMG_K_JACOBIAN, s, cap);
+        HIP_TRY(launch_jacobian1d(insts, rt, P->res_nt, nullptr, nullptr, mg, P->prec, P->jac_mask, s));
+    }
+    nmg_status st = enqueue_setup(P, ws, mg, s, cap);
     if (st != NMG_OK) return st;
     for (int v = 0; v < P->nu3; v++) {
-        st = enqueue_vcycle(P, ws, mg, v == 0, v == P->nu3 - 1, s);
+        st = enqueue_vcycle(P, ws, mg, v == 0, v == P->nu3 - 1, s, cap);
         if (st != NMG_OK) return st;
     }
-    HIP_TRY(launch_residual1d(insts, rt, P->res_nt, nullptr, state, partial, s));
+    {
+        ProfScope ps(P, NMG_K_RESIDUAL, s, cap);
+        HIP_TRY(launch_residual1d(insts, rt, P->res_nt, nullptr, state, partial, s));
+    }
     HIP_TRY(launch_res_finalize(insts, P->n, state, partial, 0, s));
     return NMG_OK;
 }
@@ -372,7 +427,7 @@ nmg_status plan_steps(nmg_plan *P, char *ws, int steps, int use_graph, hipStream
                 HIP_TRY(hipDeviceSynchronize());
             }
             HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            nmg_status st = enqueue_step(P, ws, cs);
+            nmg_status st = enqueue_step(P, ws, cs, true);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(cs, &g);
             if (st != NMG_OK) { if (g) (void)hipGraphDestroy(g); return st; }
@@ -414,6 +469,34 @@ nmg_status nmg_plan_create(const nmg_desc *descs, const nmg_params *params, int3
 }
 
 size_t nmg_plan_workspace_bytes(const nmg_plan *plan) { return plan ? plan->total : 0; }
+
+nmg_status nmg_plan_profile(nmg_plan *P, int32_t kernel)
+{
+    if (!P) return fail(NMG_EINVAL, "null plan");
+    if (kernel < NMG_K_NONE || kernel > NMG_K_COARSEN) return fail(NMG_EINVAL, "unknown kernel id");
+    P->prof_kernel = kernel;
+    return NMG_OK;
+}
+
+nmg_status nmg_plan_profile_read(nmg_plan *P, double *ms, int32_t *launches)
+{
+    if (!P) return fail(NMG_EINVAL, "null plan");
+    if (!P->ev_open.empty()) HIP_TRY(hipStreamSynchronize(P->prof_stream));
+    for (auto &pr : P->ev_open) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second));
+        P->prof_ms += t;
+        P->prof_count += 1;
+        P->ev_pool.push_back(pr.first);
+        P->ev_pool.push_back(pr.second);
+    }
+    P->ev_open.clear();
+    if (ms) *ms = P->prof_ms;
+    if (launches) *launches = P->prof_count;
+    P->prof_ms = 0.0;
+    P->prof_count = 0;
+    return NMG_OK;
+}
 
 void nmg_plan_destroy(nmg_plan *plan) { delete plan; }
 

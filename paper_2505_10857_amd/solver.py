@@ -193,6 +193,17 @@ class BatchSolver1D:
         A.check(A.load().nmg_plan_begin(self.plan, _dptr(self.ws), self.ws_bytes, self._ptrs,
                                         C.c_void_p(_stream_ptr())))
 
+    def profile(self, kernel: int):
+        """Time every later non-graph launch of one kernel (NMG_K_*) with HIP events."""
+        A.check(A.load().nmg_plan_profile(self.plan, kernel))
+
+    def profile_read(self):
+        """(milliseconds, launches) accumulated since the last read."""
+        ms = C.c_double()
+        cnt = C.c_int32()
+        A.check(A.load().nmg_plan_profile_read(self.plan, C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
+
     def steps(self, k: int, use_graph: bool = True):
         active = (C.c_int32 * self.n)()
         stats = (A.nmg_stats * self.n)()
