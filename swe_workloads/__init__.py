@@ -247,7 +247,10 @@ def config2(i: int, variant: str = "sub", n: int = 12800, levels: int = 8) -> Pr
         q, h_out = 1.53, 0.66
     else:
         raise ValueError(variant)
-    p = Params(eps=eps_for_n(n))
+    # eps: the paper's fine-grid value 0.01 diverges from the flat-surface guess for hump scales
+    # above ~1.16 (too small a perturbation, as section 5.1 warns); 0.02, the value the paper
+    # itself uses for the transcritical bump, converges for every seed.
+    p = Params(eps=0.02 if n > 1024 else eps_for_n(n))
     return Problem1D(f"cfg2-{variant}[{i}]", 0.0, 25.0, n, levels, parabolic_bump(s), unit_width,
                      BC(BC_DISCHARGE, q=q), BC(BC_DEPTH, h=h_out), p,
                      surface0=h_out, q0=q, meta=dict(s=s, q=q, h_out=h_out, variant=variant))
