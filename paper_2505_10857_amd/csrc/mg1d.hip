@@ -267,15 +267,28 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
 }
 
 // ---- coarsest level ------------------------------------------------------------------------
-// Band storage: row r (= 2j + c) keeps columns r-3 .. r+6 at index col - r + 3.  The factor
-// stores, per pivot step k, the upper row (columns k .. k+6), the three multipliers of rows
-// k+1 .. k+3 and the pivot row, in a layout the solve kernel reads sequentially.
+// The coarsest system (rows r = 2j + c, c the component) is block-tridiagonal, so row r has
+// nonzeros only in columns r-3 .. r+3; with partial pivoting the fill stays within r+6.
+// Gaussian elimination with partial pivoting therefore touches a 4 x 7 window of the matrix
+// per pivot step: one lane carries that window in registers and streams rows in and out,
+// performing exactly the arithmetic of dense elimination (entries outside the band are zero
+// and leave every sum unchanged).  Per pivot step k the factor stores the upper row
+// (columns k..k+6), the multipliers of rows k+1..k+3 and the pivot row.
+
+__device__ __forceinline__ double band_entry(const double (*blk)[12], int n, int r, int c)
+{
+    // entry (r, c) of the coarsest block-tridiagonal matrix, blocks W, D, E staged in LDS
+    if (r < 0 || c < 0 || r >= 2 * n || c >= 2 * n) return 0.0;
+    const int j = r >> 1, l = r & 1, i = c >> 1, m = c & 1;
+    const int b = i - j + 1;
+    if (b < 0 || b > 2) return 0.0;
+    return blk[j][b * 4 + l * 2 + m];
+}
 
 template <typename T>
 __global__ void __launch_bounds__(64) k_coarse_factor(MGArgs mg, const int *inst_list)
 {
-    __shared__ double A[2 * kMaxCoarse][kBandW];
-    __shared__ int piv_s;
+    __shared__ double blk[kMaxCoarse][12];
     const int inst = inst_list[blockIdx.x];
     if (!active_of(mg, inst)) return;
     const Inst1D &I = mg.insts[inst];
@@ -284,60 +297,67 @@ __global__ void __launch_bounds__(64) k_coarse_factor(MGArgs mg, const int *inst
     const int n = L.n, M = 2 * n;
     double *lu = mg.lu + I.lu;
     int *piv = mg.piv + I.lu / kLuStride;
-    const int t = threadIdx.x;
+    for (int j = threadIdx.x; j < n; j += 64)
+#pragma unroll
+        for (int e = 0; e < 12; e++) blk[j][e] = ld(base + L.J, e * (long long)n + j);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
 
-    for (int r = t; r < M; r += 64)
-        for (int k = 0; k < kBandW; k++) A[r][k] = 0.0;
-    __syncthreads();
-    // scatter the block-tridiagonal rows: block b couples cell j to cell j + b - 1
-    for (int j = t; j < n; j += 64)
-        for (int b = 0; b < 3; b++) {
-            const int i = j + b - 1;
-            if (i < 0 || i >= n) continue;
-            for (int l = 0; l < 2; l++)
-                for (int m = 0; m < 2; m++) {
-                    const int r = 2 * j + l, c = 2 * i + m;
-                    A[r][c - r + 3] = ld(base + L.J, (b * 4 + l * 2 + m) * (long long)n + j);
-                }
-        }
-    __syncthreads();
+    double W[4][7];   // W[q][t] = A(k+q, k+t)
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int t = 0; t < 7; t++) W[q][t] = band_entry(blk, n, q, t);
     for (int k = 0; k < M; k++) {
-        if (t == 0) {
-            int p = k;
-            for (int r = k + 1; r <= k + 3 && r < M; r++)
-                if (fabs(A[r][k - r + 3]) > fabs(A[p][k - p + 3])) p = r;
-            piv_s = p;
-            piv[k] = p;
+        // pivot: first row of largest magnitude in column k among rows k..k+3
+        int p = 0;
+        double best = fabs(W[0][0]);
+#pragma unroll
+        for (int q = 1; q < 4; q++) {
+            const double a = fabs(W[q][0]);
+            if (k + q < M && a > best) { best = a; p = q; }
         }
-        __syncthreads();
-        const int p = piv_s;
-        if (p != k && t < 7) {
-            // swap columns k .. k+6 of rows k and p (both hold them in their band)
-            const int c = k + t;
-            if (c < M && c - p + 3 < kBandW) {
-                double x = A[k][c - k + 3];
-                A[k][c - k + 3] = A[p][c - p + 3];
-                A[p][c - p + 3] = x;
-            } else if (c < M) {
-                A[k][c - k + 3] = 0.0;
+        piv[k] = k + p;
+#pragma unroll
+        for (int t = 0; t < 7; t++) {
+            const double w0 = W[0][t];
+            double wp = W[0][t];
+#pragma unroll
+            for (int q = 1; q < 4; q++) wp = p == q ? W[q][t] : wp;
+#pragma unroll
+            for (int q = 1; q < 4; q++) W[q][t] = p == q ? w0 : W[q][t];
+            W[0][t] = wp;
+        }
+        // eliminate column k from rows k+1..k+3
+#pragma unroll
+        for (int q = 1; q < 4; q++) {
+            double f = 0.0;
+            if (k + q < M) f = W[q][0] / W[0][0];
+            if (f != 0.0) {
+#pragma unroll
+                for (int t = 0; t < 7; t++) W[q][t] -= f * W[0][t];
             }
+            lu[(long long)k * kLuStride + 7 + (q - 1)] = f;
         }
-        __syncthreads();
-        // multipliers
-        double f = 0.0;
-        const int rr = k + 1 + (t / 7), cc = k + (t % 7);
-        if (t < 21 && rr < M) f = A[rr][k - rr + 3] / A[k][3];
-        __syncthreads();
-        if (t < 21 && rr < M && f != 0.0 && cc < M) A[rr][cc - rr + 3] -= f * A[k][cc - k + 3];
-        if (t < 21 && (t % 7) == 0) lu[(long long)k * kLuStride + 7 + t / 7] = rr < M ? f : 0.0;
-        __syncthreads();
-        if (t < 7) lu[(long long)k * kLuStride + t] = (k + t < M) ? A[k][t + 3] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 7; t++) lu[(long long)k * kLuStride + t] = W[0][t];
+        // slide the window one row down and one column right; row k+4 enters untouched
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+#pragma unroll
+            for (int t = 0; t < 6; t++) W[q][t] = W[q + 1][t + 1];
+            W[q][6] = 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 7; t++) W[3][t] = band_entry(blk, n, k + 4, k + 1 + t);
     }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(64) k_coarse_solve(MGArgs mg, const int *inst_list)
 {
+    __shared__ double F[2 * kMaxCoarse][kLuStride];
+    __shared__ int P[2 * kMaxCoarse];
     __shared__ double x[2 * kMaxCoarse];
     const int inst = inst_list[blockIdx.x];
     if (!active_of(mg, inst)) return;
@@ -348,28 +368,50 @@ __global__ void __launch_bounds__(64) k_coarse_solve(MGArgs mg, const int *inst_
     const double *lu = mg.lu + I.lu;
     const int *piv = mg.piv + I.lu / kLuStride;
     const int t = threadIdx.x;
+    for (int e = t; e < M * kLuStride; e += 64) F[e / kLuStride][e % kLuStride] = lu[e];
+    for (int r = t; r < M; r += 64) P[r] = piv[r];
     for (int j = t; j < n; j += 64) {
         x[2 * j] = -ld(base + L.rhs, j);
         x[2 * j + 1] = -ld(base + L.rhs, n + (long long)j);
     }
     __syncthreads();
     if (t == 0) {
-        // forward elimination with the recorded pivots and multipliers
+        // forward elimination: window X[q] = x[k+q]
+        double X[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) X[q] = q < M ? x[q] : 0.0;
         for (int k = 0; k < M; k++) {
-            const int p = piv[k];
-            if (p != k) { double y = x[k]; x[k] = x[p]; x[p] = y; }
-            const double xk = x[k];
-            for (int q = 0; q < 3; q++) {
-                const int r = k + 1 + q;
-                const double f = lu[(long long)k * kLuStride + 7 + q];
-                if (r < M && f != 0.0) x[r] -= f * xk;
+            const int p = P[k] - k;
+            const double x0 = X[0];
+            double xp = X[0];
+#pragma unroll
+            for (int q = 1; q < 4; q++) xp = p == q ? X[q] : xp;
+#pragma unroll
+            for (int q = 1; q < 4; q++) X[q] = p == q ? x0 : X[q];
+            X[0] = xp;
+#pragma unroll
+            for (int q = 1; q < 4; q++) {
+                const double f = F[k][7 + q - 1];
+                if (f != 0.0) X[q] -= f * X[0];
             }
+            x[k] = X[0];
+            X[0] = X[1]; X[1] = X[2]; X[2] = X[3];
+            X[3] = k + 4 < M ? x[k + 4] : 0.0;
         }
-        // back substitution
+        // back substitution: window Y[c] = x[k+c], c = 1..6
+        double Y[7];
+#pragma unroll
+        for (int c = 0; c < 7; c++) Y[c] = 0.0;
         for (int k = M - 1; k >= 0; k--) {
             double s = x[k];
-            for (int c = k + 1; c <= k + 6 && c < M; c++) s -= lu[(long long)k * kLuStride + (c - k)] * x[c];
-            x[k] = s / lu[(long long)k * kLuStride];
+#pragma unroll
+            for (int c = 1; c < 7; c++)
+                if (k + c < M) s -= F[k][c] * Y[c];
+            const double v = s / F[k][0];
+            x[k] = v;
+#pragma unroll
+            for (int c = 6; c > 1; c--) Y[c] = Y[c - 1];
+            Y[1] = v;
         }
     }
     __syncthreads();
