@@ -9,7 +9,7 @@
 //   R, rn    : double, per instance [2N] and [N]
 //   mg       : per instance and level: J [nb*4][n_l], Dinv [4][n_l], rhs [2][n_l], dU [2][n_l]
 //              in double (NMG_FP64) or float (NMG_FP32_MG)
-//   lu, piv  : coarsest-level band factors, kLuStride doubles and one int per coarse row
+//   lu       : coarsest-level cyclic-reduction factors, kFactorPerCell doubles per coarse cell
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -104,13 +104,14 @@ struct nmg_plan {
     std::vector<Level1D> levs;
     std::vector<Tile> tiles;                  // all tile lists, concatenated
     int res_t0 = 0, res_nt = 0;               // residual / Jacobian tiles
-    std::vector<std::pair<int, int>> coarsen; // (t0, nt) per coarsening pass
+    std::vector<std::pair<int, int>> coarsen; // (t0, nt) per coarsening pass from level 0
+    std::vector<std::pair<int, int>> coarsen8;// (t0, nt) per pass from level 8 (Newton path)
     std::vector<std::pair<int, int>> smooth;  // (t0, nt) per depth
     std::vector<int> smooth_mask;             // stencil widths present per depth (bit0: 3, bit1: 5)
     int jac_mask = 0;
     int depth = 0;
     size_t off_insts = 0, off_levs = 0, off_tiles = 0, off_list = 0, off_state = 0, off_partial = 0,
-           off_hist = 0, off_R = 0, off_mg = 0, off_lu = 0, off_piv = 0, total = 0;
+           off_hist = 0, off_R = 0, off_mg = 0, off_lu = 0, total = 0;
     std::vector<size_t> R_off;                // per instance byte offset of R (rn follows)
     int max_hist = 0;
     // graph cache
@@ -192,7 +193,7 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
         }
         I.levc = (int)P->levs.size() - 1;
         I.lu = lu_elems;
-        lu_elems += (long long)2 * (I.N >> (I.levels - 1)) * kLuStride;
+        lu_elems += (long long)kFactorPerCell * (I.N >> (I.levels - 1));
         I.max_hist = std::min(params[k].n_max, 100000);
         P->insts.push_back(I);
     }
@@ -218,6 +219,17 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
             for (int a = 0; a < L.n; a += span) P->tiles.push_back({lev_index[k][l0], a});
         }
         P->coarsen.push_back({t0, (int)P->tiles.size() - t0});
+    }
+    // the Jacobian tiles (256 cells) build levels 1..8 themselves; deeper levels start at 8
+    P->coarsen8.clear();
+    for (int l0 = 8; l0 < max_levels - 1; l0 += 10) {
+        int t0 = (int)P->tiles.size();
+        for (int k = 0; k < n; k++) {
+            if (l0 >= P->insts[k].levels - 1) continue;
+            const Level1D &L = P->levs[lev_index[k][l0]];
+            for (int a = 0; a < L.n; a += span) P->tiles.push_back({lev_index[k][l0], a});
+        }
+        P->coarsen8.push_back({t0, (int)P->tiles.size() - t0});
     }
     // smoothing tiles per depth
     P->smooth.clear();
@@ -250,7 +262,6 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
     }
     P->off_mg = o; o = align256(o + vsz * (size_t)mg_elems);
     P->off_lu = o; o = align256(o + sizeof(double) * (size_t)std::max(1LL, lu_elems));
-    P->off_piv = o; o = align256(o + sizeof(int) * (size_t)std::max(1LL, lu_elems / kLuStride));
     P->total = o;
     return NMG_OK;
 }
@@ -296,7 +307,6 @@ MGArgs mg_args(const nmg_plan *P, char *ws, bool with_state)
     a.state = with_state ? reinterpret_cast<NewtonState *>(ws + P->off_state) : nullptr;
     a.mg = ws + P->off_mg;
     a.lu = reinterpret_cast<double *>(ws + P->off_lu);
-    a.piv = reinterpret_cast<int *>(ws + P->off_piv);
     return a;
 }
 
@@ -328,9 +338,10 @@ const Tile *tiles_at(const nmg_plan *P, char *ws, int t0)
 }
 
 // Coarse operators of every level, diagonal inverses and the coarsest factorisation.
-nmg_status enqueue_setup(nmg_plan *P, char *ws, const MGArgs &mg, hipStream_t s, bool cap = true)
+nmg_status enqueue_setup(nmg_plan *P, char *ws, const MGArgs &mg, hipStream_t s, bool cap = true,
+                         bool from_jacobian = false)
 {
-    for (auto &c : P->coarsen) {
+    for (auto &c : (from_jacobian ? P->coarsen8 : P->coarsen)) {
         ProfScope ps(P, NMG_K_COARSEN, s, cap);
         HIP_TRY(launch_coarsen1d(mg, tiles_at(P, ws, c.first), c.second, P->prec, s));
     }
@@ -370,7 +381,7 @@ nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s, bool cap = false)
         ProfScope ps(P, NMG_K_JACOBIAN, s, cap);
         HIP_TRY(launch_jacobian1d(insts, rt, P->res_nt, nullptr, nullptr, mg, P->prec, P->jac_mask, s));
     }
-    nmg_status st = enqueue_setup(P, ws, mg, s, cap);
+    nmg_status st = enqueue_setup(P, ws, mg, s, cap, true);
     if (st != NMG_OK) return st;
     for (int v = 0; v < P->nu3; v++) {
         st = enqueue_vcycle(P, ws, mg, v == 0, v == P->nu3 - 1, s, cap);

@@ -12,9 +12,8 @@
 //    right-hand side of eq. (17), the post-smoothing kernel first adds the prolongation of
 //    eq. (18) (and, at the finest level after the last cycle, applies the Newton update of
 //    eq. 14).  HBM traffic per level and phase is one read of the operator.
-//  * k_coarse_factor / k_coarse_solve: the coarsest system is solved exactly by Gaussian
-//    elimination with partial pivoting on its band (rows 2j+c, c the component), factored once
-//    per operator and re-used by every cycle.
+//  * k_coarse_factor / k_coarse_solve: the coarsest system is solved exactly (up to rounding)
+//    by block parallel cyclic reduction, factored once per operator and re-used by every cycle.
 #include "nmg_common.h"
 
 namespace nmg {
@@ -267,157 +266,141 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
 }
 
 // ---- coarsest level ------------------------------------------------------------------------
-// The coarsest system (rows r = 2j + c, c the component) is block-tridiagonal, so row r has
-// nonzeros only in columns r-3 .. r+3; with partial pivoting the fill stays within r+6.
-// Gaussian elimination with partial pivoting therefore touches a 4 x 7 window of the matrix
-// per pivot step: one lane carries that window in registers and streams rows in and out,
-// performing exactly the arithmetic of dense elimination (entries outside the band are zero
-// and leave every sum unchanged).  Per pivot step k the factor stores the upper row
-// (columns k..k+6), the multipliers of rows k+1..k+3 and the pivot row.
+// The coarsest system  W_j x_{j-1} + D_j x_j + E_j x_{j+1} = -rhs_j  (2x2 blocks) is solved
+// exactly by block parallel cyclic reduction: step k (stride s = 2^k) eliminates the couplings
+// at distance s from every row at once,
+//     a_j = -W_j D_{j-s}^{-1},  g_j = -E_j D_{j+s}^{-1},
+//     W_j <- a_j W_{j-s},  E_j <- g_j E_{j+s},  D_j <- D_j + a_j E_{j-s} + g_j W_{j+s},
+// and the same combination of right-hand sides; after ceil(log2 n) steps every row is
+// decoupled and x_j = D_j^{-1} b_j.  One thread per cell, 2x2 blocks in LDS.  The factor
+// kernel runs once per operator and stores a_j, g_j per step and the final D_j^{-1}; the solve
+// kernel replays them on the right-hand side of every cycle.
 
-__device__ __forceinline__ double band_entry(const double (*blk)[12], int n, int r, int c)
+__device__ __forceinline__ void mul2(const double A[4], const double B[4], double C[4])
 {
-    // entry (r, c) of the coarsest block-tridiagonal matrix, blocks W, D, E staged in LDS
-    if (r < 0 || c < 0 || r >= 2 * n || c >= 2 * n) return 0.0;
-    const int j = r >> 1, l = r & 1, i = c >> 1, m = c & 1;
-    const int b = i - j + 1;
-    if (b < 0 || b > 2) return 0.0;
-    return blk[j][b * 4 + l * 2 + m];
+    C[0] = A[0] * B[0] + A[1] * B[2];
+    C[1] = A[0] * B[1] + A[1] * B[3];
+    C[2] = A[2] * B[0] + A[3] * B[2];
+    C[3] = A[2] * B[1] + A[3] * B[3];
 }
 
 template <typename T>
-__global__ void __launch_bounds__(64) k_coarse_factor(MGArgs mg, const int *inst_list)
+__global__ void __launch_bounds__(kMaxCoarse) k_coarse_factor(MGArgs mg, const int *inst_list)
 {
-    __shared__ double blk[kMaxCoarse][12];
+    __shared__ double sW[kMaxCoarse][4], sD[kMaxCoarse][4], sE[kMaxCoarse][4], sDi[kMaxCoarse][4];
     const int inst = inst_list[blockIdx.x];
     if (!active_of(mg, inst)) return;
     const Inst1D &I = mg.insts[inst];
     const Level1D L = mg.levs[I.levc];
     const T *base = reinterpret_cast<const T *>(mg.mg);
-    const int n = L.n, M = 2 * n;
-    double *lu = mg.lu + I.lu;
-    int *piv = mg.piv + I.lu / kLuStride;
-    for (int j = threadIdx.x; j < n; j += 64)
+    const int n = L.n, j = threadIdx.x;
+    double *fac = mg.lu + I.lu;   // [step][8][n] multipliers, then [4][n] final inverses
+    double W[4] = {0, 0, 0, 0}, D[4] = {1, 0, 0, 1}, E[4] = {0, 0, 0, 0};
+    if (j < n) {
 #pragma unroll
-        for (int e = 0; e < 12; e++) blk[j][e] = ld(base + L.J, e * (long long)n + j);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-
-    double W[4][7];   // W[q][t] = A(k+q, k+t)
-#pragma unroll
-    for (int q = 0; q < 4; q++)
-#pragma unroll
-        for (int t = 0; t < 7; t++) W[q][t] = band_entry(blk, n, q, t);
-    for (int k = 0; k < M; k++) {
-        // pivot: first row of largest magnitude in column k among rows k..k+3
-        int p = 0;
-        double best = fabs(W[0][0]);
-#pragma unroll
-        for (int q = 1; q < 4; q++) {
-            const double a = fabs(W[q][0]);
-            if (k + q < M && a > best) { best = a; p = q; }
+        for (int e = 0; e < 4; e++) {
+            W[e] = ld(base + L.J, (0 * 4 + e) * (long long)n + j);
+            D[e] = ld(base + L.J, (1 * 4 + e) * (long long)n + j);
+            E[e] = ld(base + L.J, (2 * 4 + e) * (long long)n + j);
         }
-        piv[k] = k + p;
+    }
+    int k = 0;
+    for (int st = 1; st < n; st <<= 1, k++) {
+        double Di[4];
+        inv2(D, Di);
 #pragma unroll
-        for (int t = 0; t < 7; t++) {
-            const double w0 = W[0][t];
-            double wp = W[0][t];
+        for (int e = 0; e < 4; e++) { sW[j][e] = W[e]; sD[j][e] = D[e]; sE[j][e] = E[e]; sDi[j][e] = Di[e]; }
+        __syncthreads();
+        double a[4] = {0, 0, 0, 0}, g[4] = {0, 0, 0, 0};
+        if (j < n) {
+            double Wn[4] = {0, 0, 0, 0}, En[4] = {0, 0, 0, 0}, Dn[4], t[4];
 #pragma unroll
-            for (int q = 1; q < 4; q++) wp = p == q ? W[q][t] : wp;
+            for (int e = 0; e < 4; e++) Dn[e] = D[e];
+            if (j - st >= 0) {
+                mul2(W, sDi[j - st], t);
 #pragma unroll
-            for (int q = 1; q < 4; q++) W[q][t] = p == q ? w0 : W[q][t];
-            W[0][t] = wp;
-        }
-        // eliminate column k from rows k+1..k+3
+                for (int e = 0; e < 4; e++) a[e] = -t[e];
+                mul2(a, sW[j - st], Wn);
+                mul2(a, sE[j - st], t);
 #pragma unroll
-        for (int q = 1; q < 4; q++) {
-            double f = 0.0;
-            if (k + q < M) f = W[q][0] / W[0][0];
-            if (f != 0.0) {
-#pragma unroll
-                for (int t = 0; t < 7; t++) W[q][t] -= f * W[0][t];
+                for (int e = 0; e < 4; e++) Dn[e] = Dn[e] + t[e];
             }
-            lu[(long long)k * kLuStride + 7 + (q - 1)] = f;
+            if (j + st < n) {
+                mul2(E, sDi[j + st], t);
+#pragma unroll
+                for (int e = 0; e < 4; e++) g[e] = -t[e];
+                mul2(g, sE[j + st], En);
+                mul2(g, sW[j + st], t);
+#pragma unroll
+                for (int e = 0; e < 4; e++) Dn[e] = Dn[e] + t[e];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                W[e] = Wn[e]; E[e] = En[e]; D[e] = Dn[e];
+                fac[((long long)k * 8 + e) * n + j] = a[e];
+                fac[((long long)k * 8 + 4 + e) * n + j] = g[e];
+            }
         }
+        __syncthreads();
+    }
+    if (j < n) {
+        double Di[4];
+        inv2(D, Di);
 #pragma unroll
-        for (int t = 0; t < 7; t++) lu[(long long)k * kLuStride + t] = W[0][t];
-        // slide the window one row down and one column right; row k+4 enters untouched
-#pragma unroll
-        for (int q = 0; q < 3; q++) {
-#pragma unroll
-            for (int t = 0; t < 6; t++) W[q][t] = W[q + 1][t + 1];
-            W[q][6] = 0.0;
-        }
-#pragma unroll
-        for (int t = 0; t < 7; t++) W[3][t] = band_entry(blk, n, k + 4, k + 1 + t);
+        for (int e = 0; e < 4; e++) fac[((long long)kPcrSteps * 8 + e) * n + j] = Di[e];
     }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(64) k_coarse_solve(MGArgs mg, const int *inst_list)
+__global__ void __launch_bounds__(kMaxCoarse) k_coarse_solve(MGArgs mg, const int *inst_list)
 {
-    __shared__ double F[2 * kMaxCoarse][kLuStride];
-    __shared__ int P[2 * kMaxCoarse];
-    __shared__ double x[2 * kMaxCoarse];
+    __shared__ double sb[kMaxCoarse][2];
     const int inst = inst_list[blockIdx.x];
     if (!active_of(mg, inst)) return;
     const Inst1D &I = mg.insts[inst];
     const Level1D L = mg.levs[I.levc];
     T *base = reinterpret_cast<T *>(mg.mg);
-    const int n = L.n, M = 2 * n;
-    const double *lu = mg.lu + I.lu;
-    const int *piv = mg.piv + I.lu / kLuStride;
-    const int t = threadIdx.x;
-    for (int e = t; e < M * kLuStride; e += 64) F[e / kLuStride][e % kLuStride] = lu[e];
-    for (int r = t; r < M; r += 64) P[r] = piv[r];
-    for (int j = t; j < n; j += 64) {
-        x[2 * j] = -ld(base + L.rhs, j);
-        x[2 * j + 1] = -ld(base + L.rhs, n + (long long)j);
+    const int n = L.n, j = threadIdx.x;
+    const double *fac = mg.lu + I.lu;
+    int K = 0;
+    while ((1 << K) < n) K++;
+    // all multipliers of this row up front: independent loads, one latency
+    double f[kPcrSteps][8];
+#pragma unroll
+    for (int k = 0; k < kPcrSteps; k++)
+#pragma unroll
+        for (int e = 0; e < 8; e++) f[k][e] = (j < n && k < K) ? fac[((long long)k * 8 + e) * n + j] : 0.0;
+    double b0 = 0.0, b1 = 0.0;
+    if (j < n) {
+        b0 = -ld(base + L.rhs, j);
+        b1 = -ld(base + L.rhs, n + (long long)j);
     }
-    __syncthreads();
-    if (t == 0) {
-        // forward elimination: window X[q] = x[k+q]
-        double X[4];
 #pragma unroll
-        for (int q = 0; q < 4; q++) X[q] = q < M ? x[q] : 0.0;
-        for (int k = 0; k < M; k++) {
-            const int p = P[k] - k;
-            const double x0 = X[0];
-            double xp = X[0];
-#pragma unroll
-            for (int q = 1; q < 4; q++) xp = p == q ? X[q] : xp;
-#pragma unroll
-            for (int q = 1; q < 4; q++) X[q] = p == q ? x0 : X[q];
-            X[0] = xp;
-#pragma unroll
-            for (int q = 1; q < 4; q++) {
-                const double f = F[k][7 + q - 1];
-                if (f != 0.0) X[q] -= f * X[0];
+    for (int k = 0; k < kPcrSteps; k++) {
+        if (k >= K) break;
+        const int st = 1 << k;
+        sb[j][0] = b0;
+        sb[j][1] = b1;
+        __syncthreads();
+        if (j < n) {
+            if (j - st >= 0) {
+                const double c0 = sb[j - st][0], c1 = sb[j - st][1];
+                b0 = b0 + (f[k][0] * c0 + f[k][1] * c1);
+                b1 = b1 + (f[k][2] * c0 + f[k][3] * c1);
             }
-            x[k] = X[0];
-            X[0] = X[1]; X[1] = X[2]; X[2] = X[3];
-            X[3] = k + 4 < M ? x[k + 4] : 0.0;
+            if (j + st < n) {
+                const double c0 = sb[j + st][0], c1 = sb[j + st][1];
+                b0 = b0 + (f[k][4] * c0 + f[k][5] * c1);
+                b1 = b1 + (f[k][6] * c0 + f[k][7] * c1);
+            }
         }
-        // back substitution: window Y[c] = x[k+c], c = 1..6
-        double Y[7];
-#pragma unroll
-        for (int c = 0; c < 7; c++) Y[c] = 0.0;
-        for (int k = M - 1; k >= 0; k--) {
-            double s = x[k];
-#pragma unroll
-            for (int c = 1; c < 7; c++)
-                if (k + c < M) s -= F[k][c] * Y[c];
-            const double v = s / F[k][0];
-            x[k] = v;
-#pragma unroll
-            for (int c = 6; c > 1; c--) Y[c] = Y[c - 1];
-            Y[1] = v;
-        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int j = t; j < n; j += 64) {
-        base[L.dU + j] = (T)x[2 * j];
-        base[L.dU + n + (long long)j] = (T)x[2 * j + 1];
+    if (j < n) {
+        const double d0 = fac[((long long)kPcrSteps * 8 + 0) * n + j], d1 = fac[((long long)kPcrSteps * 8 + 1) * n + j];
+        const double d2 = fac[((long long)kPcrSteps * 8 + 2) * n + j], d3 = fac[((long long)kPcrSteps * 8 + 3) * n + j];
+        base[L.dU + j] = (T)(d0 * b0 + d1 * b1);
+        base[L.dU + n + (long long)j] = (T)(d2 * b0 + d3 * b1);
     }
 }
 
@@ -445,9 +428,9 @@ hipError_t launch_coarse_factor(const MGArgs &mg, const int *inst_list, int n, i
 {
     if (n == 0) return hipSuccess;
     if (prec == NMG_FP32_MG)
-        hipLaunchKernelGGL(k_coarse_factor<float>, dim3(n), dim3(64), 0, s, mg, inst_list);
+        hipLaunchKernelGGL(k_coarse_factor<float>, dim3(n), dim3(kMaxCoarse), 0, s, mg, inst_list);
     else
-        hipLaunchKernelGGL(k_coarse_factor<double>, dim3(n), dim3(64), 0, s, mg, inst_list);
+        hipLaunchKernelGGL(k_coarse_factor<double>, dim3(n), dim3(kMaxCoarse), 0, s, mg, inst_list);
     return hipGetLastError();
 }
 
@@ -455,9 +438,9 @@ hipError_t launch_coarse_solve(const MGArgs &mg, const int *inst_list, int n, in
 {
     if (n == 0) return hipSuccess;
     if (prec == NMG_FP32_MG)
-        hipLaunchKernelGGL(k_coarse_solve<float>, dim3(n), dim3(64), 0, s, mg, inst_list);
+        hipLaunchKernelGGL(k_coarse_solve<float>, dim3(n), dim3(kMaxCoarse), 0, s, mg, inst_list);
     else
-        hipLaunchKernelGGL(k_coarse_solve<double>, dim3(n), dim3(64), 0, s, mg, inst_list);
+        hipLaunchKernelGGL(k_coarse_solve<double>, dim3(n), dim3(kMaxCoarse), 0, s, mg, inst_list);
     return hipGetLastError();
 }
 

@@ -12,8 +12,8 @@ namespace nmg {
 constexpr int kTile = 256;        // threads (= cells) per 1D tile
 constexpr int kCoarsenCells = 4;  // level-l0 cells per thread in the coarsening kernel
 constexpr int kMaxLevels = 16;
-constexpr int kMaxCoarse = 256;   // cells on the coarsest 1D level (band LU lives in LDS)
-constexpr int kBandW = 10;        // band width of the coarsest LU: columns r-3 .. r+6
+constexpr int kMaxCoarse = 256;   // cells on the coarsest 1D level (one thread per cell)
+constexpr int kPcrSteps = 8;      // cyclic-reduction steps for up to kMaxCoarse cells
 constexpr double kZeta = 1e-6;    // WENO epsilon of eq. (8)
 
 // One 1D instance as the kernels see it.
@@ -31,7 +31,7 @@ struct Inst1D {
     int lev0;          // index of level 0 in the level table
     int levc;          // index of the coarsest level
     int res_tile0, res_tiles;  // residual tiles of this instance (contiguous)
-    long long lu;      // element offset (doubles) of the coarsest-level LU factors in the LU region
+    long long lu;      // element offset (doubles) of the coarsest-level factor in the factor region
     int max_hist, pad;
     double *hist;      // device history of res, [max_hist] (may be null)
 };
@@ -59,11 +59,12 @@ struct MGArgs {
     const Level1D *levs;
     NewtonState *state;   // may be null: every instance active
     void *mg;             // base of the multigrid value arrays (double or float)
-    double *lu;           // base of the LU region (doubles)
-    int *piv;             // base of the pivot region (ints, same element offsets as lu / kLuStride)
+    double *lu;           // base of the coarsest-level factor region (doubles)
 };
 
-constexpr int kLuStride = 10;     // doubles per coarse row in the LU region: 7 upper + 3 multipliers
+// doubles per coarsest cell in the factor region: two 2x2 multipliers per reduction step and
+// the final inverse
+constexpr int kFactorPerCell = 8 * kPcrSteps + 4;
 
 __host__ __device__ inline int halo_cells(int nb, int nu)
 {

@@ -161,25 +161,11 @@ __device__ __forceinline__ void stencil_ghosts(double H[5], double Q[5], int j, 
     }
 }
 
-// Local residual of eq. (10) from a ghost-complete stencil.
-__device__ __forceinline__ void local_residual(const double H[5], const double Q[5],
-                                               const CellGeom &G, const CubicGauss &W,
-                                               double dx, double g, double &R0, double &R1)
+// Source of eq. (9) from the four face values of H feeding the cubic U_h.
+__device__ __forceinline__ double source_term(double Hp_ll, double Hp_l, double Hm_r, double Hm_rr,
+                                              const CellGeom &G, const CubicGauss &W, double dx,
+                                              double g)
 {
-    // face j-1/2: left state from cell j-1, right state from cell j
-    double Hm_l = weno_minus(H[0], H[1], H[2]), Qm_l = weno_minus(Q[0], Q[1], Q[2]);
-    double Hp_l = weno_plus(H[1], H[2], H[3]), Qp_l = weno_plus(Q[1], Q[2], Q[3]);
-    // face j+1/2: left state from cell j, right state from cell j+1
-    double Hm_r = weno_minus(H[1], H[2], H[3]), Qm_r = weno_minus(Q[1], Q[2], Q[3]);
-    double Hp_r = weno_plus(H[2], H[3], H[4]), Qp_r = weno_plus(Q[2], Q[3], Q[4]);
-    // outer nodes of the source cubic: H+_{j-3/2} (cell j-1) and H-_{j+3/2} (cell j+1)
-    double Hp_ll = weno_plus(H[0], H[1], H[2]);
-    double Hm_rr = weno_minus(H[2], H[3], H[4]);
-
-    double Fm0, Fm1, Fp0, Fp1;
-    hll(Hm_l, Qm_l, Hp_l, Qp_l, G.sfm, g, Fm0, Fm1);
-    hll(Hm_r, Qm_r, Hp_r, Qp_r, G.sfp, g, Fp0, Fp1);
-
     double sum = 0.0;
 #pragma unroll
     for (int q = 0; q < 2; q++) {
@@ -188,9 +174,55 @@ __device__ __forceinline__ void local_residual(const double H[5], const double Q
         double s = 0.5 * g * hg * hg * G.sxg[q] - g * G.sg[q] * hg * G.bxg[q];
         sum = sum + s;
     }
-    double S = 0.5 * dx * sum;
+    return 0.5 * dx * sum;
+}
+
+// The reconstructions a local residual needs (section 3.1, Figure 1b): for each component the
+// two states at x_{j-1/2} and at x_{j+1/2}; for H also the outer nodes of the source cubic.
+struct Recon {
+    double Hm_l, Hp_l, Hm_r, Hp_r, Hp_ll, Hm_rr;
+    double Qm_l, Qp_l, Qm_r, Qp_r;
+};
+
+__device__ __forceinline__ void recon_H(const double H[5], Recon &r)
+{
+    r.Hm_l = weno_minus(H[0], H[1], H[2]);   // U-_{j-1/2}, from cell j-1
+    r.Hp_l = weno_plus(H[1], H[2], H[3]);    // U+_{j-1/2}, from cell j
+    r.Hm_r = weno_minus(H[1], H[2], H[3]);   // U-_{j+1/2}, from cell j
+    r.Hp_r = weno_plus(H[2], H[3], H[4]);    // U+_{j+1/2}, from cell j+1
+    r.Hp_ll = weno_plus(H[0], H[1], H[2]);   // U+_{j-3/2}, from cell j-1
+    r.Hm_rr = weno_minus(H[2], H[3], H[4]);  // U-_{j+3/2}, from cell j+1
+}
+
+__device__ __forceinline__ void recon_Q(const double Q[5], Recon &r)
+{
+    r.Qm_l = weno_minus(Q[0], Q[1], Q[2]);
+    r.Qp_l = weno_plus(Q[1], Q[2], Q[3]);
+    r.Qm_r = weno_minus(Q[1], Q[2], Q[3]);
+    r.Qp_r = weno_plus(Q[2], Q[3], Q[4]);
+}
+
+// R_j = F(U-_{j+1/2}, U+_{j+1/2}) - F(U-_{j-1/2}, U+_{j-1/2}) - S_j  (eq. 10)
+__device__ __forceinline__ void assemble_residual(const Recon &r, double S, const CellGeom &G,
+                                                  double g, double &R0, double &R1)
+{
+    double Fm0, Fm1, Fp0, Fp1;
+    hll(r.Hm_l, r.Qm_l, r.Hp_l, r.Qp_l, G.sfm, g, Fm0, Fm1);
+    hll(r.Hm_r, r.Qm_r, r.Hp_r, r.Qp_r, G.sfp, g, Fp0, Fp1);
     R0 = Fp0 - Fm0;
     R1 = Fp1 - Fm1 - S;
+}
+
+// Local residual of eq. (10) from a ghost-complete stencil.
+__device__ __forceinline__ void local_residual(const double H[5], const double Q[5],
+                                               const CellGeom &G, const CubicGauss &W,
+                                               double dx, double g, double &R0, double &R1)
+{
+    Recon r;
+    recon_H(H, r);
+    recon_Q(Q, r);
+    const double S = source_term(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, dx, g);
+    assemble_residual(r, S, G, g, R0, R1);
 }
 
 // Stage U[a-2 .. a+kTile+1] of one instance into LDS (zeros outside the grid).
@@ -272,19 +304,22 @@ __global__ void __launch_bounds__(kTile) k_sum_res(const double *rn, int N, doub
     if (threadIdx.x == 0) *res = s / N;
 }
 
-// Per instance: res from the tile partials (fixed order), Newton counter and stopping test of
-// Algorithm 1 (res < tol or n >= n_max; non-finite res stops with an error).
-__global__ void k_res_finalize(const Inst1D *insts, int ninst, NewtonState *state,
-                               const double *partial, int init)
+// Per instance (one wavefront each): res from the tile partials (fixed order: lane-strided
+// sums, then a fixed shuffle tree), the Newton counter and the stopping test of Algorithm 1
+// (res < tol or n >= n_max; a non-finite res stops the instance with an error).
+__global__ void __launch_bounds__(64) k_res_finalize(const Inst1D *insts, int ninst, NewtonState *state,
+                                                     const double *partial, int init)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.x;
     if (b >= ninst) return;
     const Inst1D &I = insts[b];
     NewtonState &S = state[I.active_idx];
     if (!init && !S.active) return;
-    double s = 0.0;
-    for (int k = 0; k < I.res_tiles; k++) s += partial[I.res_tile0 + k];
-    const double res = s / I.N;
+    double v = 0.0;
+    for (int k = threadIdx.x; k < I.res_tiles; k += 64) v += partial[I.res_tile0 + k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (threadIdx.x != 0) return;
+    const double res = v / I.N;
     S.res = res;
     if (init) {
         S.n = 0;
@@ -301,53 +336,199 @@ __global__ void k_res_finalize(const Inst1D *insts, int ninst, NewtonState *stat
 }
 
 // ---- Jacobian --------------------------------------------------------------------------
+// Column (i, m) of eq. (12) perturbs component m of cell i.  Away from the boundaries the
+// ghosts do not move, so a perturbation of H leaves every Q reconstruction unchanged, a
+// perturbation of Q leaves every H reconstruction and the source unchanged, and only the
+// reconstructions whose three-cell stencil contains cell i change.  Those are recomputed from
+// the same inputs the full evaluation would use, so the result is identical to re-evaluating
+// the whole local residual (which the boundary cells still do).
 
+__device__ __forceinline__ void perturbed_residual(const double H[5], const double Q[5], int pp, int m,
+                                                   double eps, const Recon &base, double S0,
+                                                   const CellGeom &G, const CubicGauss &W, double dx,
+                                                   double g, double &R0, double &R1)
+{
+    Recon r = base;
+    double S = S0;
+    double X[5];
+    const double *src = m == 0 ? H : Q;
+#pragma unroll
+    for (int p = 0; p < 5; p++) X[p] = p == pp ? src[p] + eps : src[p];
+    const bool left = pp <= 2, mid = pp >= 1 && pp <= 3, right = pp >= 2;
+    if (m == 0) {
+        if (left) { r.Hm_l = weno_minus(X[0], X[1], X[2]); r.Hp_ll = weno_plus(X[0], X[1], X[2]); }
+        if (mid) { r.Hp_l = weno_plus(X[1], X[2], X[3]); r.Hm_r = weno_minus(X[1], X[2], X[3]); }
+        if (right) { r.Hp_r = weno_plus(X[2], X[3], X[4]); r.Hm_rr = weno_minus(X[2], X[3], X[4]); }
+        S = source_term(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, dx, g);
+    } else {
+        if (left) r.Qm_l = weno_minus(X[0], X[1], X[2]);
+        if (mid) { r.Qp_l = weno_plus(X[1], X[2], X[3]); r.Qm_r = weno_minus(X[1], X[2], X[3]); }
+        if (right) r.Qp_r = weno_plus(X[2], X[3], X[4]);
+    }
+    assemble_residual(r, S, G, g, R0, R1);
+}
+
+__device__ __forceinline__ void inv2d(const double A[4], double B[4])
+{
+    double det = A[0] * A[3] - A[1] * A[2];
+    B[0] = A[3] / det;
+    B[1] = -A[1] / det;
+    B[2] = -A[2] / det;
+    B[3] = A[0] / det;
+}
+
+// Rows of cells 2jc, 2jc+1 (fine blocks b = 0..nb-1) -> coarse tridiagonal row (eq. 17),
+// summed in the order of child row, then child column.
+template <int NB>
+__device__ __forceinline__ void coarse_from_children(const double *f0, const double *f1,
+                                                     double Wc[4], double Dc[4], double Ec[4])
+{
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        if (NB == 5) {
+            Wc[e] = f0[0 * 4 + e] + f0[1 * 4 + e] + f1[0 * 4 + e];
+            Dc[e] = f0[2 * 4 + e] + f0[3 * 4 + e] + f1[1 * 4 + e] + f1[2 * 4 + e];
+            Ec[e] = f0[4 * 4 + e] + f1[3 * 4 + e] + f1[4 * 4 + e];
+        } else {
+            Wc[e] = f0[0 * 4 + e];
+            Dc[e] = f0[1 * 4 + e] + f0[2 * 4 + e] + f1[0 * 4 + e] + f1[1 * 4 + e];
+            Ec[e] = f1[2 * 4 + e];
+        }
+    }
+}
+
+// Jacobian rows of one tile.  With `mg` levels (batched path) the tile also writes the finest
+// right-hand side, every level's diagonal inverse and the coarse operators of all levels that
+// lie inside the tile (up to eight: 256 -> 1 cells).
 template <typename T, int NB>
-__device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs)
+__device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs, T *Dinv,
+                              const MGArgs *mg, const Level1D *L0)
 {
     __shared__ double sH[kTile + 4], sQ[kTile + 4];
+    __shared__ double rows[kTile * NB * 4];
     stage_state(I, a, sH, sQ);
     __syncthreads();
-    const int j = a + threadIdx.x;
-    if (j >= I.N) return;
+    const int t = threadIdx.x;
+    const int j = a + t;
     constexpr int HW = NB / 2;
-    double H[5], Q[5];
+    double *myrow = &rows[t * NB * 4];   // this cell's block row, in LDS
 #pragma unroll
-    for (int p = 0; p < 5; p++) { H[p] = sH[threadIdx.x + p]; Q[p] = sQ[threadIdx.x + p]; }
-    const CellGeom G = load_geom(I, j);
-    const CubicGauss W;
-    const double R0 = I.R[j], R1 = I.R[I.N + j], rn = I.rn[j];
-    const double eps = I.eps;
-    if (rhs) {   // the finest level's right-hand side of eq. (16) is R itself
-        rhs[j] = (T)R0;
-        rhs[stride + j] = (T)R1;
-    }
-    for (int b = 0; b < NB; b++) {
-        const int i = j + b - HW;
-        const bool col_ok = i >= 0 && i < I.N;
-        const int pp = 2 + b - HW;  // stencil position of the perturbed cell
-        for (int m = 0; m < 2; m++) {
-            double e0 = 0.0, e1 = 0.0;
-            if (col_ok) {
-                double Hp[5], Qp[5];
+    for (int e = 0; e < NB * 4; e++) myrow[e] = 0.0;
+    if (j < I.N) {
+        double H[5], Q[5];
 #pragma unroll
-                for (int p = 0; p < 5; p++) {
-                    Hp[p] = (p == pp && m == 0) ? H[p] + eps : H[p];
-                    Qp[p] = (p == pp && m == 1) ? Q[p] + eps : Q[p];
-                }
-                stencil_ghosts(Hp, Qp, j, I);
-                double P0, P1;
-                local_residual(Hp, Qp, G, W, I.dx, I.g, P0, P1);
-                e0 = (P0 - R0) / eps;
-                e1 = (P1 - R1) / eps;
-                if (b == HW) {
-                    if (m == 0) e0 += I.alpha * rn;
-                    else e1 += I.alpha * rn;
-                }
-            }
-            J[((b * 2 + 0) * 2 + m) * (long long)stride + j] = (T)e0;
-            J[((b * 2 + 1) * 2 + m) * (long long)stride + j] = (T)e1;
+        for (int p = 0; p < 5; p++) { H[p] = sH[t + p]; Q[p] = sQ[t + p]; }
+        const CellGeom G = load_geom(I, j);
+        const CubicGauss W;
+        const double R0 = I.R[j], R1 = I.R[I.N + j], rn = I.rn[j];
+        const double eps = I.eps;
+        if (rhs) {   // the finest level's right-hand side of eq. (16) is R itself
+            rhs[j] = (T)R0;
+            rhs[stride + j] = (T)R1;
         }
+        const bool interior = j >= 2 && j <= I.N - 3;
+        Recon base;
+        double S0 = 0.0;
+        if (interior) {
+            recon_H(H, base);
+            recon_Q(Q, base);
+            S0 = source_term(base.Hp_ll, base.Hp_l, base.Hm_r, base.Hm_rr, G, W, I.dx, I.g);
+        }
+        for (int b = 0; b < NB; b++) {
+            const int i = j + b - HW;
+            const bool col_ok = i >= 0 && i < I.N;
+            const int pp = 2 + b - HW;  // stencil position of the perturbed cell
+            for (int m = 0; m < 2; m++) {
+                double e0 = 0.0, e1 = 0.0;
+                if (col_ok) {
+                    double P0, P1;
+                    if (interior) {
+                        perturbed_residual(H, Q, pp, m, eps, base, S0, G, W, I.dx, I.g, P0, P1);
+                    } else {
+                        double Hp[5], Qp[5];
+#pragma unroll
+                        for (int p = 0; p < 5; p++) {
+                            Hp[p] = (p == pp && m == 0) ? H[p] + eps : H[p];
+                            Qp[p] = (p == pp && m == 1) ? Q[p] + eps : Q[p];
+                        }
+                        stencil_ghosts(Hp, Qp, j, I);
+                        local_residual(Hp, Qp, G, W, I.dx, I.g, P0, P1);
+                    }
+                    e0 = (P0 - R0) / eps;
+                    e1 = (P1 - R1) / eps;
+                    if (b == HW) {
+                        if (m == 0) e0 += I.alpha * rn;
+                        else e1 += I.alpha * rn;
+                    }
+                }
+                myrow[(b * 2 + 0) * 2 + m] = e0;
+                myrow[(b * 2 + 1) * 2 + m] = e1;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < NB * 4; e++) J[e * (long long)stride + j] = (T)myrow[e];
+        if (Dinv) {
+            double D[4], Di[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) D[e] = myrow[HW * 4 + e];
+            inv2d(D, Di);
+#pragma unroll
+            for (int e = 0; e < 4; e++) Dinv[e * (long long)stride + j] = (T)Di[e];
+        }
+    }
+    if (!mg || L0->coarsest) return;
+
+    // coarse operators of the levels inside this tile (eq. 17), reduced in LDS
+    __syncthreads();
+    T *base_mg = reinterpret_cast<T *>(mg->mg);
+    Level1D Lc = mg->levs[L0->child];
+    int cnt = kTile / 2, cstart = a / 2;
+    {
+        const int jc = cstart + t;
+        const bool mine = t < cnt && jc < Lc.n;
+        double Wc[4], Dc[4], Ec[4], Bi[4];
+        if (mine) {
+            coarse_from_children<NB>(&rows[(2 * t) * NB * 4], &rows[(2 * t + 1) * NB * 4], Wc, Dc, Ec);
+            inv2d(Dc, Bi);
+        }
+        __syncthreads();
+        if (mine) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                rows[t * 12 + e] = Wc[e]; rows[t * 12 + 4 + e] = Dc[e]; rows[t * 12 + 8 + e] = Ec[e];
+                base_mg[Lc.J + (0 * 4 + e) * (long long)Lc.n + jc] = (T)Wc[e];
+                base_mg[Lc.J + (1 * 4 + e) * (long long)Lc.n + jc] = (T)Dc[e];
+                base_mg[Lc.J + (2 * 4 + e) * (long long)Lc.n + jc] = (T)Ec[e];
+                base_mg[Lc.Dinv + e * (long long)Lc.n + jc] = (T)Bi[e];
+            }
+        }
+        __syncthreads();
+    }
+    while (!Lc.coarsest && cnt >= 2) {
+        const Level1D Ln = mg->levs[Lc.child];
+        const int nstart = cstart / 2, ncnt = cnt / 2;
+        const int jc = nstart + t;
+        const bool mine = t < ncnt && jc < Ln.n;
+        double Wc[4], Dc[4], Ec[4], Bi[4];
+        if (mine) {
+            coarse_from_children<3>(&rows[(2 * t) * 12], &rows[(2 * t + 1) * 12], Wc, Dc, Ec);
+            inv2d(Dc, Bi);
+        }
+        __syncthreads();
+        if (mine) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                rows[t * 12 + e] = Wc[e]; rows[t * 12 + 4 + e] = Dc[e]; rows[t * 12 + 8 + e] = Ec[e];
+                base_mg[Ln.J + (0 * 4 + e) * (long long)Ln.n + jc] = (T)Wc[e];
+                base_mg[Ln.J + (1 * 4 + e) * (long long)Ln.n + jc] = (T)Dc[e];
+                base_mg[Ln.J + (2 * 4 + e) * (long long)Ln.n + jc] = (T)Ec[e];
+                base_mg[Ln.Dinv + e * (long long)Ln.n + jc] = (T)Bi[e];
+            }
+        }
+        __syncthreads();
+        Lc = Ln;
+        cnt = ncnt;
+        cstart = nstart;
     }
 }
 
@@ -357,16 +538,17 @@ __global__ void __launch_bounds__(kTile) k_jacobian_batch(MGArgs mg, const Tile 
     const Tile t = tiles[blockIdx.x];
     const Inst1D &I = mg.insts[t.lev];
     if (!inst_active(mg.state, I)) return;
-    const Level1D &L = mg.levs[I.lev0];
+    const Level1D L = mg.levs[I.lev0];
     if (L.nb != NB) return;
     T *base = reinterpret_cast<T *>(mg.mg);
-    jacobian_tile<T, NB>(I, t.a, base + L.J, L.n, base + L.rhs);
+    jacobian_tile<T, NB>(I, t.a, base + L.J, L.n, base + L.rhs, base + L.Dinv, &mg, &L);
 }
 
 template <int NB>
 __global__ void __launch_bounds__(kTile) k_jacobian_single(Inst1D I, double *J)
 {
-    jacobian_tile<double, NB>(I, blockIdx.x * kTile, J, I.N, (double *)nullptr);
+    jacobian_tile<double, NB>(I, blockIdx.x * kTile, J, I.N, (double *)nullptr, (double *)nullptr,
+                              (const MGArgs *)nullptr, (const Level1D *)nullptr);
 }
 
 // ---- launchers ---------------------------------------------------------------------------
@@ -389,8 +571,8 @@ hipError_t launch_residual1d(const Inst1D *insts_dev, const Tile *tiles, int nti
 hipError_t launch_res_finalize(const Inst1D *insts_dev, int ninst, NewtonState *state,
                                const double *partial, int init, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_res_finalize, dim3((ninst + 63) / 64), dim3(64), 0, s, insts_dev, ninst,
-                       state, partial, init);
+    hipLaunchKernelGGL(k_res_finalize, dim3(ninst), dim3(64), 0, s, insts_dev, ninst, state,
+                       partial, init);
     return hipGetLastError();
 }
 
