@@ -9,7 +9,6 @@
 //   R, rn    : double, per instance [2N] and [N]
 //   mg       : per instance and level: J [nb*4][n_l], Dinv [4][n_l], rhs [2][n_l], dU [2][n_l]
 //              in double (NMG_FP64) or float (NMG_FP32_MG)
-//   lu       : coarsest-level cyclic-reduction factors, kFactorPerCell doubles per coarse cell
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -111,7 +110,7 @@ struct nmg_plan {
     int jac_mask = 0;
     int depth = 0;
     size_t off_insts = 0, off_levs = 0, off_tiles = 0, off_list = 0, off_state = 0, off_partial = 0,
-           off_hist = 0, off_R = 0, off_mg = 0, off_lu = 0, total = 0;
+           off_hist = 0, off_R = 0, off_mg = 0, total = 0;
     std::vector<size_t> R_off;                // per instance byte offset of R (rn follows)
     int max_hist = 0;
     // graph cache
@@ -166,7 +165,7 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
     P->depth = max_levels - 1;
 
     // levels and multigrid element offsets
-    long long mg_elems = 0, lu_elems = 0;
+    long long mg_elems = 0;
     std::vector<std::vector<int>> lev_index(n);
     for (int k = 0; k < n; k++) {
         Inst1D I = make_inst(&descs[k], &params[k]);
@@ -192,8 +191,10 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
             P->levs.push_back(L);
         }
         I.levc = (int)P->levs.size() - 1;
-        I.lu = lu_elems;
-        lu_elems += (long long)kFactorPerCell * (I.N >> (I.levels - 1));
+        // bottom kernel: from the first three-block level with at most kBottomCells cells
+        I.lbot = I.levels - 1;
+        for (int l = 0; l < I.levels; l++)
+            if ((I.N >> l) <= kBottomCells && (l > 0 || I.nb == 3)) { I.lbot = l; break; }
         I.max_hist = std::min(params[k].n_max, 100000);
         P->insts.push_back(I);
     }
@@ -237,7 +238,7 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
     for (int d = 0; d < P->depth; d++) {
         int t0 = (int)P->tiles.size(), mask = 0;
         for (int k = 0; k < n; k++) {
-            if (d >= P->insts[k].levels - 1) continue;
+            if (d >= P->insts[k].lbot) continue;
             const Level1D &L = P->levs[lev_index[k][d]];
             if (L.V < 2) return fail(NMG_EINVAL, "smoothing halo exceeds the tile");
             for (int a = 0; a < L.n; a += L.V) P->tiles.push_back({lev_index[k][d], a});
@@ -261,7 +262,6 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
         o = align256(o + sizeof(double) * 3 * (size_t)P->insts[k].N);
     }
     P->off_mg = o; o = align256(o + vsz * (size_t)mg_elems);
-    P->off_lu = o; o = align256(o + sizeof(double) * (size_t)std::max(1LL, lu_elems));
     P->total = o;
     return NMG_OK;
 }
@@ -306,7 +306,6 @@ MGArgs mg_args(const nmg_plan *P, char *ws, bool with_state)
     a.levs = reinterpret_cast<const Level1D *>(ws + P->off_levs);
     a.state = with_state ? reinterpret_cast<NewtonState *>(ws + P->off_state) : nullptr;
     a.mg = ws + P->off_mg;
-    a.lu = reinterpret_cast<double *>(ws + P->off_lu);
     return a;
 }
 
@@ -337,7 +336,7 @@ const Tile *tiles_at(const nmg_plan *P, char *ws, int t0)
     return reinterpret_cast<const Tile *>(ws + P->off_tiles) + t0;
 }
 
-// Coarse operators of every level, diagonal inverses and the coarsest factorisation.
+// Coarse operators of every level and their diagonal inverses.
 nmg_status enqueue_setup(nmg_plan *P, char *ws, const MGArgs &mg, hipStream_t s, bool cap = true,
                          bool from_jacobian = false)
 {
@@ -345,8 +344,6 @@ nmg_status enqueue_setup(nmg_plan *P, char *ws, const MGArgs &mg, hipStream_t s,
         ProfScope ps(P, NMG_K_COARSEN, s, cap);
         HIP_TRY(launch_coarsen1d(mg, tiles_at(P, ws, c.first), c.second, P->prec, s));
     }
-    const int *list = reinterpret_cast<const int *>(ws + P->off_list);
-    HIP_TRY(launch_coarse_factor(mg, list, P->n, P->prec, s));
     return NMG_OK;
 }
 
@@ -356,12 +353,14 @@ nmg_status enqueue_vcycle(nmg_plan *P, char *ws, const MGArgs &mg, bool zero_ini
 {
     const int *list = reinterpret_cast<const int *>(ws + P->off_list);
     for (int d = 0; d < P->depth; d++) {
+        if (P->smooth[d].second == 0) continue;
         ProfScope ps(P, d == 0 ? NMG_K_SMOOTH_PRE : -1, s, cap);
         HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
                                 P->smooth_mask[d], 0, (d > 0 || zero_init0) ? 1 : 0, 0, P->prec, s));
     }
-    HIP_TRY(launch_coarse_solve(mg, list, P->n, P->prec, s));
+    HIP_TRY(launch_bottom(mg, list, P->n, zero_init0 ? 1 : 0, final_update ? 1 : 0, P->prec, s));
     for (int d = P->depth - 1; d >= 0; d--) {
+        if (P->smooth[d].second == 0) continue;
         ProfScope ps(P, d == 0 ? NMG_K_SMOOTH_POST : -1, s, cap);
         HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
                                 P->smooth_mask[d], 1, 0, (d == 0 && final_update) ? 1 : 0, P->prec, s));

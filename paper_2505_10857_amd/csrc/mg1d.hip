@@ -12,8 +12,9 @@
 //    right-hand side of eq. (17), the post-smoothing kernel first adds the prolongation of
 //    eq. (18) (and, at the finest level after the last cycle, applies the Newton update of
 //    eq. 14).  HBM traffic per level and phase is one read of the operator.
-//  * k_coarse_factor / k_coarse_solve: the coarsest system is solved exactly (up to rounding)
-//    by block parallel cyclic reduction, factored once per operator and re-used by every cycle.
+//  * k_bottom: all small levels of one instance in one workgroup: smoothing and restriction
+//    down, the coarsest system solved exactly (up to rounding) by block parallel cyclic
+//    reduction, prolongation and smoothing back up.
 #include "nmg_common.h"
 
 namespace nmg {
@@ -272,9 +273,8 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
 //     a_j = -W_j D_{j-s}^{-1},  g_j = -E_j D_{j+s}^{-1},
 //     W_j <- a_j W_{j-s},  E_j <- g_j E_{j+s},  D_j <- D_j + a_j E_{j-s} + g_j W_{j+s},
 // and the same combination of right-hand sides; after ceil(log2 n) steps every row is
-// decoupled and x_j = D_j^{-1} b_j.  One thread per cell, 2x2 blocks in LDS.  The factor
-// kernel runs once per operator and stores a_j, g_j per step and the final D_j^{-1}; the solve
-// kernel replays them on the right-hand side of every cycle.
+// decoupled and x_j = D_j^{-1} b_j.  One thread per cell, 2x2 blocks in LDS, inside the
+// bottom-of-cycle kernel below.
 
 __device__ __forceinline__ void mul2(const double A[4], const double B[4], double C[4])
 {
@@ -284,123 +284,281 @@ __device__ __forceinline__ void mul2(const double A[4], const double B[4], doubl
     C[3] = A[2] * B[1] + A[3] * B[3];
 }
 
+// ---- bottom of the V-cycle -----------------------------------------------------------------
+// Every level with at most kBottomCells cells (always including the coarsest) is handled by one
+// 1024-thread workgroup per instance in a single launch: pre-smoothing and restriction down to
+// the coarsest level, the cyclic-reduction solve there, prolongation and post-smoothing back
+// up.  Thread t owns cells t and t + 1024 of every level; dU of the current level lives in LDS,
+// the restricted right-hand sides of all levels below the first stay in LDS, and the
+// pre-smoothed dU of each level goes to HBM and comes back to the thread that wrote it.
+// Same arithmetic, in the same order, as the per-level kernels.
+
 template <typename T>
-__global__ void __launch_bounds__(kMaxCoarse) k_coarse_factor(MGArgs mg, const int *inst_list)
+__device__ __forceinline__ void bottom_load(const T *base, const Level1D &L, int c, double Jr[12], double D[4])
 {
+#pragma unroll
+    for (int e = 0; e < 12; e++) Jr[e] = ld(base + L.J, e * (long long)L.n + c);
+#pragma unroll
+    for (int e = 0; e < 4; e++) D[e] = ld(base + L.Dinv, e * (long long)L.n + c);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBottomThreads) k_bottom(MGArgs mg, const int *inst_list, int zero_init0,
+                                                           int final_update)
+{
+    constexpr int NT = kBottomThreads;
+    __shared__ double u0[kBottomCells + 2], u1[kBottomCells + 2];   // dU of the current level, index c+1
+    __shared__ double q0[kBottomCells], q1[kBottomCells];           // rhs of the levels below the first
     __shared__ double sW[kMaxCoarse][4], sD[kMaxCoarse][4], sE[kMaxCoarse][4], sDi[kMaxCoarse][4];
     const int inst = inst_list[blockIdx.x];
     if (!active_of(mg, inst)) return;
     const Inst1D &I = mg.insts[inst];
-    const Level1D L = mg.levs[I.levc];
-    const T *base = reinterpret_cast<const T *>(mg.mg);
-    const int n = L.n, j = threadIdx.x;
-    double *fac = mg.lu + I.lu;   // [step][8][n] multipliers, then [4][n] final inverses
-    double W[4] = {0, 0, 0, 0}, D[4] = {1, 0, 0, 1}, E[4] = {0, 0, 0, 0};
-    if (j < n) {
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            W[e] = ld(base + L.J, (0 * 4 + e) * (long long)n + j);
-            D[e] = ld(base + L.J, (1 * 4 + e) * (long long)n + j);
-            E[e] = ld(base + L.J, (2 * 4 + e) * (long long)n + j);
-        }
-    }
-    int k = 0;
-    for (int st = 1; st < n; st <<= 1, k++) {
-        double Di[4];
-        inv2(D, Di);
-#pragma unroll
-        for (int e = 0; e < 4; e++) { sW[j][e] = W[e]; sD[j][e] = D[e]; sE[j][e] = E[e]; sDi[j][e] = Di[e]; }
-        __syncthreads();
-        double a[4] = {0, 0, 0, 0}, g[4] = {0, 0, 0, 0};
-        if (j < n) {
-            double Wn[4] = {0, 0, 0, 0}, En[4] = {0, 0, 0, 0}, Dn[4], t[4];
-#pragma unroll
-            for (int e = 0; e < 4; e++) Dn[e] = D[e];
-            if (j - st >= 0) {
-                mul2(W, sDi[j - st], t);
-#pragma unroll
-                for (int e = 0; e < 4; e++) a[e] = -t[e];
-                mul2(a, sW[j - st], Wn);
-                mul2(a, sE[j - st], t);
-#pragma unroll
-                for (int e = 0; e < 4; e++) Dn[e] = Dn[e] + t[e];
-            }
-            if (j + st < n) {
-                mul2(E, sDi[j + st], t);
-#pragma unroll
-                for (int e = 0; e < 4; e++) g[e] = -t[e];
-                mul2(g, sE[j + st], En);
-                mul2(g, sW[j + st], t);
-#pragma unroll
-                for (int e = 0; e < 4; e++) Dn[e] = Dn[e] + t[e];
-            }
+    T *base = reinterpret_cast<T *>(mg.mg);
+    const int t = threadIdx.x;
+    const int lb = I.lev0 + I.lbot;           // level-table index of the first bottom level
+    const double w = I.omega;
+    if (t == 0) { u0[0] = u1[0] = 0.0; }
+    {   // the coarsest operator, staged once (read at the end of the descent)
+        const Level1D Lc = mg.levs[I.levc];
+        if (t < Lc.n) {
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                W[e] = Wn[e]; E[e] = En[e]; D[e] = Dn[e];
-                fac[((long long)k * 8 + e) * n + j] = a[e];
-                fac[((long long)k * 8 + 4 + e) * n + j] = g[e];
+                sW[t][e] = ld(base + Lc.J, (0 * 4 + e) * (long long)Lc.n + t);
+                sD[t][e] = ld(base + Lc.J, (1 * 4 + e) * (long long)Lc.n + t);
+                sE[t][e] = ld(base + Lc.J, (2 * 4 + e) * (long long)Lc.n + t);
             }
         }
-        __syncthreads();
     }
-    if (j < n) {
-        double Di[4];
-        inv2(D, Di);
-#pragma unroll
-        for (int e = 0; e < 4; e++) fac[((long long)kPcrSteps * 8 + e) * n + j] = Di[e];
-    }
-}
 
-template <typename T>
-__global__ void __launch_bounds__(kMaxCoarse) k_coarse_solve(MGArgs mg, const int *inst_list)
-{
-    __shared__ double sb[kMaxCoarse][2];
-    const int inst = inst_list[blockIdx.x];
-    if (!active_of(mg, inst)) return;
-    const Inst1D &I = mg.insts[inst];
-    const Level1D L = mg.levs[I.levc];
-    T *base = reinterpret_cast<T *>(mg.mg);
-    const int n = L.n, j = threadIdx.x;
-    const double *fac = mg.lu + I.lu;
-    int K = 0;
-    while ((1 << K) < n) K++;
-    // all multipliers of this row up front: independent loads, one latency
-    double f[kPcrSteps][8];
+    // ---- down: pre-smoothing and restriction -------------------------------------------
+    int li = lb, qoff = 0;                    // qoff: LDS offset of this level's rhs (levels > lb)
+    while (true) {
+        const Level1D L = mg.levs[li];
+        if (L.coarsest) break;
+        const int n = L.n;
+        double Jr[2][12], D[2][4], r[2][2], du[2][2];
 #pragma unroll
-    for (int k = 0; k < kPcrSteps; k++)
-#pragma unroll
-        for (int e = 0; e < 8; e++) f[k][e] = (j < n && k < K) ? fac[((long long)k * 8 + e) * n + j] : 0.0;
-    double b0 = 0.0, b1 = 0.0;
-    if (j < n) {
-        b0 = -ld(base + L.rhs, j);
-        b1 = -ld(base + L.rhs, n + (long long)j);
-    }
-#pragma unroll
-    for (int k = 0; k < kPcrSteps; k++) {
-        if (k >= K) break;
-        const int st = 1 << k;
-        sb[j][0] = b0;
-        sb[j][1] = b1;
-        __syncthreads();
-        if (j < n) {
-            if (j - st >= 0) {
-                const double c0 = sb[j - st][0], c1 = sb[j - st][1];
-                b0 = b0 + (f[k][0] * c0 + f[k][1] * c1);
-                b1 = b1 + (f[k][2] * c0 + f[k][3] * c1);
+        for (int k = 0; k < 2; k++) {
+            const int c = t + k * NT;
+            du[k][0] = du[k][1] = 0.0;
+            r[k][0] = r[k][1] = 0.0;
+            if (c < n) {
+                bottom_load(base, L, c, Jr[k], D[k]);
+                if (li == lb) {
+                    r[k][0] = ld(base + L.rhs, c);
+                    r[k][1] = ld(base + L.rhs, n + (long long)c);
+                    if (li == I.lev0 && !zero_init0) {
+                        du[k][0] = ld(base + L.dU, c);
+                        du[k][1] = ld(base + L.dU, n + (long long)c);
+                    }
+                } else {
+                    r[k][0] = q0[qoff + c];
+                    r[k][1] = q1[qoff + c];
+                }
+                u0[c + 1] = du[k][0];
+                u1[c + 1] = du[k][1];
             }
-            if (j + st < n) {
-                const double c0 = sb[j + st][0], c1 = sb[j + st][1];
-                b0 = b0 + (f[k][4] * c0 + f[k][5] * c1);
-                b1 = b1 + (f[k][6] * c0 + f[k][7] * c1);
+        }
+        if (t == 0) { u0[n + 1] = 0.0; u1[n + 1] = 0.0; }
+        __syncthreads();
+        for (int s = 0; s < I.nu1; s++)
+            for (int hs = 0; hs < 4; hs++) {
+                const int col = hs < 2 ? hs : 3 - hs;
+#pragma unroll
+                for (int k = 0; k < 2; k++) {
+                    const int c = t + k * NT;
+                    if (c < n && (c & 1) == col) {
+                        const double x0 = u0[c], x1 = u1[c], y0 = u0[c + 2], y1 = u1[c + 2];
+                        double a0 = r[k][0], a1 = r[k][1];
+                        a0 = a0 + (Jr[k][0] * x0 + Jr[k][1] * x1);
+                        a1 = a1 + (Jr[k][2] * x0 + Jr[k][3] * x1);
+                        a0 = a0 + (Jr[k][8] * y0 + Jr[k][9] * y1);
+                        a1 = a1 + (Jr[k][10] * y0 + Jr[k][11] * y1);
+                        const double t0 = D[k][0] * a0 + D[k][1] * a1;
+                        const double t1 = D[k][2] * a0 + D[k][3] * a1;
+                        du[k][0] = (1.0 - w) * du[k][0] - w * t0;
+                        du[k][1] = (1.0 - w) * du[k][1] - w * t1;
+                        u0[c + 1] = du[k][0];
+                        u1[c + 1] = du[k][1];
+                    }
+                }
+                __syncthreads();
+            }
+        // restriction to the child (eq. 17) into LDS; pre-smoothed dU to HBM
+        const int qn = li == lb ? 0 : qoff + n;
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int c = t + k * NT;
+            double a0 = r[k][0], a1 = r[k][1];
+            if (c < n) {
+                const double x0 = u0[c], x1 = u1[c], y0 = u0[c + 2], y1 = u1[c + 2];
+                a0 = a0 + (Jr[k][0] * x0 + Jr[k][1] * x1);
+                a1 = a1 + (Jr[k][2] * x0 + Jr[k][3] * x1);
+                a0 = a0 + (Jr[k][4] * du[k][0] + Jr[k][5] * du[k][1]);
+                a1 = a1 + (Jr[k][6] * du[k][0] + Jr[k][7] * du[k][1]);
+                a0 = a0 + (Jr[k][8] * y0 + Jr[k][9] * y1);
+                a1 = a1 + (Jr[k][10] * y0 + Jr[k][11] * y1);
+            }
+            const double p0 = __shfl_xor(a0, 1, 64), p1 = __shfl_xor(a1, 1, 64);
+            if (c < n) {
+                if ((c & 1) == 0) { q0[qn + (c >> 1)] = a0 + p0; q1[qn + (c >> 1)] = a1 + p1; }
+                base[L.dU + c] = (T)du[k][0];
+                base[L.dU + n + (long long)c] = (T)du[k][1];
+            }
+        }
+        __syncthreads();
+        qoff = qn;
+        li = L.child;
+    }
+
+    // ---- coarsest: block parallel cyclic reduction on the staged operator ---------------------
+    {
+        const Level1D L = mg.levs[li];
+        const int n = L.n;
+        double W[4] = {0, 0, 0, 0}, Dm[4] = {1, 0, 0, 1}, E[4] = {0, 0, 0, 0};
+        double b0 = 0.0, b1 = 0.0;
+        if (t < n) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) { W[e] = sW[t][e]; Dm[e] = sD[t][e]; E[e] = sE[t][e]; }
+            if (li == lb) { b0 = -ld(base + L.rhs, t); b1 = -ld(base + L.rhs, n + (long long)t); }
+            else { b0 = -q0[qoff + t]; b1 = -q1[qoff + t]; }
+        }
+        for (int st = 1; st < n; st <<= 1) {
+            double Di[4];
+            inv2(Dm, Di);
+            __syncthreads();
+            if (t < n) {
+#pragma unroll
+                for (int e = 0; e < 4; e++) { sW[t][e] = W[e]; sD[t][e] = Dm[e]; sE[t][e] = E[e]; sDi[t][e] = Di[e]; }
+                u0[t + 1] = b0;
+                u1[t + 1] = b1;
+            }
+            __syncthreads();
+            if (t < n) {
+                double Wn[4] = {0, 0, 0, 0}, En[4] = {0, 0, 0, 0}, Dn[4], a[4], g[4], tm[4];
+#pragma unroll
+                for (int e = 0; e < 4; e++) Dn[e] = Dm[e];
+                double bn0 = b0, bn1 = b1;
+                if (t - st >= 0) {
+                    mul2(W, sDi[t - st], tm);
+#pragma unroll
+                    for (int e = 0; e < 4; e++) a[e] = -tm[e];
+                    mul2(a, sW[t - st], Wn);
+                    mul2(a, sE[t - st], tm);
+#pragma unroll
+                    for (int e = 0; e < 4; e++) Dn[e] = Dn[e] + tm[e];
+                    const double c0 = u0[t - st + 1], c1 = u1[t - st + 1];
+                    bn0 = bn0 + (a[0] * c0 + a[1] * c1);
+                    bn1 = bn1 + (a[2] * c0 + a[3] * c1);
+                }
+                if (t + st < n) {
+                    mul2(E, sDi[t + st], tm);
+#pragma unroll
+                    for (int e = 0; e < 4; e++) g[e] = -tm[e];
+                    mul2(g, sE[t + st], En);
+                    mul2(g, sW[t + st], tm);
+#pragma unroll
+                    for (int e = 0; e < 4; e++) Dn[e] = Dn[e] + tm[e];
+                    const double c0 = u0[t + st + 1], c1 = u1[t + st + 1];
+                    bn0 = bn0 + (g[0] * c0 + g[1] * c1);
+                    bn1 = bn1 + (g[2] * c0 + g[3] * c1);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; e++) { W[e] = Wn[e]; E[e] = En[e]; Dm[e] = Dn[e]; }
+                b0 = bn0;
+                b1 = bn1;
+            }
+        }
+        __syncthreads();
+        if (t < n) {
+            double Di[4];
+            inv2(Dm, Di);
+            const double x0 = Di[0] * b0 + Di[1] * b1;
+            const double x1 = Di[2] * b0 + Di[3] * b1;
+            u0[t + 1] = x0;
+            u1[t + 1] = x1;
+            if (li == lb) {   // a one-level bottom (the whole hierarchy is the coarsest level)
+                base[L.dU + t] = (T)x0;
+                base[L.dU + n + (long long)t] = (T)x1;
             }
         }
         __syncthreads();
     }
-    if (j < n) {
-        const double d0 = fac[((long long)kPcrSteps * 8 + 0) * n + j], d1 = fac[((long long)kPcrSteps * 8 + 1) * n + j];
-        const double d2 = fac[((long long)kPcrSteps * 8 + 2) * n + j], d3 = fac[((long long)kPcrSteps * 8 + 3) * n + j];
-        base[L.dU + j] = (T)(d0 * b0 + d1 * b1);
-        base[L.dU + n + (long long)j] = (T)(d2 * b0 + d3 * b1);
+
+    // ---- up: prolongation and post-smoothing ------------------------------------------------
+    while (li > lb) {
+        li -= 1;
+        const Level1D L = mg.levs[li];
+        const int n = L.n;
+        // rhs offset of this level: walk the offsets again (levels above lb only)
+        int qo = 0;
+        for (int x = lb + 1; x < li; x++) qo += mg.levs[x].n;
+        double par[2][2];
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int c = t + k * NT;
+            par[k][0] = par[k][1] = 0.0;
+            if (c < n) { par[k][0] = u0[(c >> 1) + 1]; par[k][1] = u1[(c >> 1) + 1]; }
+        }
+        __syncthreads();
+        double Jr[2][12], D[2][4], r[2][2], du[2][2];
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int c = t + k * NT;
+            du[k][0] = du[k][1] = 0.0;
+            r[k][0] = r[k][1] = 0.0;
+            if (c < n) {
+                bottom_load(base, L, c, Jr[k], D[k]);
+                if (li == lb) {
+                    r[k][0] = ld(base + L.rhs, c);
+                    r[k][1] = ld(base + L.rhs, n + (long long)c);
+                } else {
+                    r[k][0] = q0[qo + c];
+                    r[k][1] = q1[qo + c];
+                }
+                du[k][0] = ld(base + L.dU, c) + par[k][0];
+                du[k][1] = ld(base + L.dU, n + (long long)c) + par[k][1];
+                u0[c + 1] = du[k][0];
+                u1[c + 1] = du[k][1];
+            }
+        }
+        if (t == 0) { u0[n + 1] = 0.0; u1[n + 1] = 0.0; }
+        __syncthreads();
+        for (int s = 0; s < I.nu2; s++)
+            for (int hs = 0; hs < 4; hs++) {
+                const int col = hs < 2 ? hs : 3 - hs;
+#pragma unroll
+                for (int k = 0; k < 2; k++) {
+                    const int c = t + k * NT;
+                    if (c < n && (c & 1) == col) {
+                        const double x0 = u0[c], x1 = u1[c], y0 = u0[c + 2], y1 = u1[c + 2];
+                        double a0 = r[k][0], a1 = r[k][1];
+                        a0 = a0 + (Jr[k][0] * x0 + Jr[k][1] * x1);
+                        a1 = a1 + (Jr[k][2] * x0 + Jr[k][3] * x1);
+                        a0 = a0 + (Jr[k][8] * y0 + Jr[k][9] * y1);
+                        a1 = a1 + (Jr[k][10] * y0 + Jr[k][11] * y1);
+                        const double t0 = D[k][0] * a0 + D[k][1] * a1;
+                        const double t1 = D[k][2] * a0 + D[k][3] * a1;
+                        du[k][0] = (1.0 - w) * du[k][0] - w * t0;
+                        du[k][1] = (1.0 - w) * du[k][1] - w * t1;
+                        u0[c + 1] = du[k][0];
+                        u1[c + 1] = du[k][1];
+                    }
+                }
+                __syncthreads();
+            }
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int c = t + k * NT;
+            if (c >= n) continue;
+            if (li == I.lev0 && final_update) {
+                I.U[c] = I.U[c] + I.tau * du[k][0];
+                I.U[I.N + c] = I.U[I.N + c] + I.tau * du[k][1];
+            } else if (li == lb) {
+                base[L.dU + c] = (T)du[k][0];
+                base[L.dU + n + (long long)c] = (T)du[k][1];
+            }
+        }
     }
 }
 
@@ -424,23 +582,14 @@ hipError_t launch_coarsen1d(const MGArgs &mg, const Tile *tiles, int ntiles, int
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_factor(const MGArgs &mg, const int *inst_list, int n, int prec, hipStream_t s)
+hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero_init0, int final_update,
+                         int prec, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     if (prec == NMG_FP32_MG)
-        hipLaunchKernelGGL(k_coarse_factor<float>, dim3(n), dim3(kMaxCoarse), 0, s, mg, inst_list);
+        hipLaunchKernelGGL(k_bottom<float>, dim3(n), dim3(kBottomThreads), 0, s, mg, inst_list, zero_init0, final_update);
     else
-        hipLaunchKernelGGL(k_coarse_factor<double>, dim3(n), dim3(kMaxCoarse), 0, s, mg, inst_list);
-    return hipGetLastError();
-}
-
-hipError_t launch_coarse_solve(const MGArgs &mg, const int *inst_list, int n, int prec, hipStream_t s)
-{
-    if (n == 0) return hipSuccess;
-    if (prec == NMG_FP32_MG)
-        hipLaunchKernelGGL(k_coarse_solve<float>, dim3(n), dim3(kMaxCoarse), 0, s, mg, inst_list);
-    else
-        hipLaunchKernelGGL(k_coarse_solve<double>, dim3(n), dim3(kMaxCoarse), 0, s, mg, inst_list);
+        hipLaunchKernelGGL(k_bottom<double>, dim3(n), dim3(kBottomThreads), 0, s, mg, inst_list, zero_init0, final_update);
     return hipGetLastError();
 }
 

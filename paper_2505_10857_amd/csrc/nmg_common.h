@@ -13,7 +13,8 @@ constexpr int kTile = 256;        // threads (= cells) per 1D tile
 constexpr int kCoarsenCells = 4;  // level-l0 cells per thread in the coarsening kernel
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 256;   // cells on the coarsest 1D level (one thread per cell)
-constexpr int kPcrSteps = 8;      // cyclic-reduction steps for up to kMaxCoarse cells
+constexpr int kBottomThreads = 1024;          // threads of the bottom-of-cycle kernel
+constexpr int kBottomCells = 2 * kBottomThreads;  // largest level it handles
 constexpr double kZeta = 1e-6;    // WENO epsilon of eq. (8)
 
 // One 1D instance as the kernels see it.
@@ -31,8 +32,8 @@ struct Inst1D {
     int lev0;          // index of level 0 in the level table
     int levc;          // index of the coarsest level
     int res_tile0, res_tiles;  // residual tiles of this instance (contiguous)
-    long long lu;      // element offset (doubles) of the coarsest-level factor in the factor region
-    int max_hist, pad;
+    int max_hist;
+    int lbot;          // first level handled by the bottom-of-cycle kernel
     double *hist;      // device history of res, [max_hist] (may be null)
 };
 
@@ -59,12 +60,7 @@ struct MGArgs {
     const Level1D *levs;
     NewtonState *state;   // may be null: every instance active
     void *mg;             // base of the multigrid value arrays (double or float)
-    double *lu;           // base of the coarsest-level factor region (doubles)
 };
-
-// doubles per coarsest cell in the factor region: two 2x2 multipliers per reduction step and
-// the final inverse
-constexpr int kFactorPerCell = 8 * kPcrSteps + 4;
 
 __host__ __device__ inline int halo_cells(int nb, int nu)
 {
@@ -88,8 +84,8 @@ hipError_t launch_jacobian1d(const Inst1D *insts_dev, const Tile *tiles, int nti
                              const Inst1D *single, double *J_single, const MGArgs &mg, int prec,
                              int nb_mask, hipStream_t s);
 hipError_t launch_coarsen1d(const MGArgs &mg, const Tile *tiles, int ntiles, int prec, hipStream_t s);
-hipError_t launch_coarse_factor(const MGArgs &mg, const int *inst_list, int n, int prec, hipStream_t s);
-hipError_t launch_coarse_solve(const MGArgs &mg, const int *inst_list, int n, int prec, hipStream_t s);
+hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero_init0, int final_update,
+                         int prec, hipStream_t s);
 hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_max, int mode,
                            int zero_init, int final_update, int prec, hipStream_t s);
 hipError_t launch_convert(const void *src, int src_prec, void *dst, int dst_prec, long long n,
