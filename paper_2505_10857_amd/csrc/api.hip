@@ -119,6 +119,8 @@ struct nmg_plan {
     void *g_ws = nullptr;
     hipStream_t own_stream = nullptr;
     NewtonState *host_state = nullptr;        // pinned
+    char *host_tables = nullptr;              // pinned staging of the instance table
+    void *tables_ws = nullptr;                // workspace whose static tables are current
     // kernel timing
     int prof_kernel = NMG_K_NONE;
     std::vector<hipEvent_t> ev_pool;          // created lazily, reused
@@ -134,6 +136,7 @@ struct nmg_plan {
         if (graph) (void)hipGraphDestroy(graph);
         if (own_stream) (void)hipStreamDestroy(own_stream);
         if (host_state) (void)hipHostFree(host_state);
+        if (host_tables) (void)hipHostFree(host_tables);
     }
 };
 
@@ -309,25 +312,37 @@ MGArgs mg_args(const nmg_plan *P, char *ws, bool with_state)
     return a;
 }
 
-// Upload the tables with the device pointers of this workspace and these states.
+// Upload the tables with the device pointers of this workspace and these states.  The level
+// and tile tables depend only on the plan and the workspace and are uploaded once per
+// workspace; the instance table (which holds the state pointers) is uploaded on every call,
+// from pinned memory.
 nmg_status upload_tables(nmg_plan *P, char *ws, double *const *U, hipStream_t s)
 {
-    std::vector<char> h(P->off_state, 0);
+    if (P->tables_ws != ws) {
+        std::vector<char> h(P->off_state - P->off_levs, 0);
+        const size_t b = P->off_levs;
+        memcpy(h.data() + P->off_levs - b, P->levs.data(), sizeof(Level1D) * P->levs.size());
+        if (!P->tiles.empty())
+            memcpy(h.data() + P->off_tiles - b, P->tiles.data(), sizeof(Tile) * P->tiles.size());
+        std::vector<int> list(P->n);
+        for (int k = 0; k < P->n; k++) list[k] = k;
+        memcpy(h.data() + P->off_list - b, list.data(), sizeof(int) * P->n);
+        HIP_TRY(hipMemcpyAsync(ws + b, h.data(), h.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        P->tables_ws = ws;
+    }
+    const size_t isz = sizeof(Inst1D) * P->n;
+    if (!P->host_tables) HIP_TRY(hipHostMalloc((void **)&P->host_tables, isz));
+    else HIP_TRY(hipStreamSynchronize(s));   // the previous upload from this buffer has landed
     for (int k = 0; k < P->n; k++) {
         Inst1D I = P->insts[k];
         I.U = U ? U[k] : nullptr;
         I.R = reinterpret_cast<double *>(ws + P->R_off[k]);
         I.rn = I.R + 2 * (size_t)I.N;
         I.hist = reinterpret_cast<double *>(ws + P->off_hist) + (size_t)k * std::max(1, P->max_hist);
-        memcpy(h.data() + P->off_insts + sizeof(Inst1D) * k, &I, sizeof(Inst1D));
+        memcpy(P->host_tables + sizeof(Inst1D) * k, &I, sizeof(Inst1D));
     }
-    memcpy(h.data() + P->off_levs, P->levs.data(), sizeof(Level1D) * P->levs.size());
-    if (!P->tiles.empty()) memcpy(h.data() + P->off_tiles, P->tiles.data(), sizeof(Tile) * P->tiles.size());
-    std::vector<int> list(P->n);
-    for (int k = 0; k < P->n; k++) list[k] = k;
-    memcpy(h.data() + P->off_list, list.data(), sizeof(int) * P->n);
-    HIP_TRY(hipMemcpyAsync(ws, h.data(), h.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpyAsync(ws + P->off_insts, P->host_tables, isz, hipMemcpyHostToDevice, s));
     return NMG_OK;
 }
 
@@ -645,7 +660,7 @@ nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *w
     st = enqueue_vcycle(&P, w, mg, false, false, s);
     if (st != NMG_OK) return st;
     HIP_TRY(launch_convert(mgb + vsz * L0.dU, P.prec, dU, P.prec, 2 * n0, s));
-    HIP_TRY(hipStreamSynchronize(s));   // the tables above live in this call's plan
+    HIP_TRY(hipStreamSynchronize(s));   // the pinned table staging belongs to this call's plan
     return NMG_OK;
 }
 
