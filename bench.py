@@ -33,16 +33,18 @@ FLOPS_LOCAL_RESIDUAL = 10 * 22 + 2 * 46 + 36 + 3
 # Algorithmic HBM bytes per cell and launch (FP64, J3):
 #   Jacobian: read U 16, R 16, rn 8, geometry 7*8 = 56; write J 96 and rhs 16
 BYTES_JACOBIAN_J3 = 16 + 16 + 8 + 56 + 96 + 16
-#   finest pre-smoothing: read J 96, Dinv 32, rhs 16, (dU 16 unless zero-initial);
-#   write dU 16 and the restricted rhs 8 per fine cell
-BYTES_SMOOTH_PRE_J3 = 96 + 32 + 16 + 16 + 16 + 8
+#   finest pre-smoothing: read J 96, Dinv 32, rhs 16; write dU 16 and the restricted rhs 8 per
+#   fine cell; plus a read of dU 16 in the second of the two cycles (average 8)
+BYTES_SMOOTH_PRE_J3 = 96 + 32 + 16 + 16 + 8 + 8
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    # the GPU needs a few hundred milliseconds of load to reach its steady clock; 30 batch
+    # solves (~0.5 s) of warmup keep the clock ramp out of the timed region
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--n", type=int, default=12800)
     ap.add_argument("--levels", type=int, default=8)
@@ -140,8 +142,8 @@ def main():
     }
 
     # ---- roofline of the dominant kernel: HIP events around its launches on the launch stream --
-    el2, _, jms, jcnt, _ = timed_solves(solver, U0s, 1, 0, False, A.NMG_K_JACOBIAN)
-    _, _, pms, pcnt, _ = timed_solves(solver, U0s, 1, 0, False, A.NMG_K_SMOOTH_PRE)
+    el2, _, jms, jcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_JACOBIAN)
+    _, _, pms, pcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_SMOOTH_PRE)
     cells = args.batch * args.n
     jac_ms = jms / max(jcnt, 1)
     pre_ms = pms / max(pcnt, 1)
@@ -155,7 +157,7 @@ def main():
         "avg_launch_ms": jac_ms, "launches_timed": jcnt,
         "algorithmic_flops_per_launch": jac_flops,
         "hbm_gbs": cells * BYTES_JACOBIAN_J3 / (jac_ms * 1e-3) / 1e9,
-        "share_of_step_time": jms / (el2 * 1e3),
+        "share_of_solve_time": jms / (el2 * 1e3),
     }
     out["smoother_roofline"] = {
         "kernel": "k_smooth<double,3> mode 0, finest level (pre-smoothing + restriction)",
@@ -172,18 +174,18 @@ def main():
         # single instance, one solve at a time
         single = BatchSolver1D(probs[:1], device="cuda:0", jac=3, precision=NMG_FP64)
         u1 = single.states()
-        e1, st1, _, _, _ = timed_solves(single, u1, 5, 1, use_graph)
-        forms["fp64_single_instance"] = {"solves_per_s": 5 / e1, "latency_ms": 1e3 * e1 / 5,
+        e1, st1, _, _, _ = timed_solves(single, u1, 20, 10, use_graph)
+        forms["fp64_single_instance"] = {"solves_per_s": 20 / e1, "latency_ms": 1e3 * e1 / 20,
                                          "newton_steps": st1[-1][0][0]}
         # full Jacobian J5, batched
         s5 = BatchSolver1D(probs, device="cuda:0", jac=5, precision=NMG_FP64)
-        e5, st5, _, _, _ = timed_solves(s5, s5.states(), max(1, args.steps // 2), 1, use_graph)
-        forms["fp64_batch_J5"] = {"solves_per_s": args.batch * max(1, args.steps // 2) / e5,
+        e5, st5, _, _, _ = timed_solves(s5, s5.states(), args.steps, 5, use_graph)
+        forms["fp64_batch_J5"] = {"solves_per_s": args.batch * args.steps / e5,
                                   "newton_steps": [min(s[0] for s in st5[-1]), max(s[0] for s in st5[-1])]}
         forms["fp64_batch_J3"] = {"solves_per_s": value, "newton_steps": out["newton_steps_per_solve"]}
         # FP32 multigrid, FP64 residual / update / test
         s32 = BatchSolver1D(probs, device="cuda:0", jac=3, precision=NMG_FP32_MG)
-        e32, st32, _, _, U32 = timed_solves(s32, s32.states(), args.steps, 1, use_graph)
+        e32, st32, _, _, U32 = timed_solves(s32, s32.states(), args.steps, 5, use_graph)
         err = max(float((a - b).abs().max()) for a, b in zip(U32, Ulast))
         forms["fp32mg_batch_J3"] = {"solves_per_s": args.batch * args.steps / e32,
                                     "newton_steps": [min(s[0] for s in st32[-1]), max(s[0] for s in st32[-1])],

@@ -163,10 +163,11 @@ __global__ void __launch_bounds__(kTile) k_coarsen(MGArgs mg, const Tile *tiles)
 
 // mode 0: (zero or loaded) dU -> nu1 symmetric steps -> write dU, restrict rhs to the child.
 // mode 1: dU + prolongated child dU -> nu2 symmetric steps -> write dU (or update U).
-template <typename T, int NB>
-__global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, int mode,
-                                                  int zero_init, int final_update)
+template <typename T, int NB, int MODE>
+__global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, int zero_init,
+                                                  int final_update)
 {
+    constexpr int mode = MODE;
     constexpr int HW = NB / 2;
     constexpr int C = NB == 5 ? 3 : 2;
     __shared__ double s0[kTile + 2 * HW], s1[kTile + 2 * HW];
@@ -593,20 +594,26 @@ hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero
     return hipGetLastError();
 }
 
+template <typename T, int NB>
+static void launch_smooth_t(const MGArgs &mg, const Tile *tiles, int ntiles, int mode, int zero_init,
+                            int final_update, hipStream_t s)
+{
+    if (mode == 0)
+        hipLaunchKernelGGL((k_smooth<T, NB, 0>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, final_update);
+    else
+        hipLaunchKernelGGL((k_smooth<T, NB, 1>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, final_update);
+}
+
 hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_mask, int mode,
                            int zero_init, int final_update, int prec, hipStream_t s)
 {
     if (ntiles == 0) return hipSuccess;
     if (prec == NMG_FP32_MG) {
-        if (nb_mask & 1)
-            hipLaunchKernelGGL((k_smooth<float, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, mode, zero_init, final_update);
-        if (nb_mask & 2)
-            hipLaunchKernelGGL((k_smooth<float, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, mode, zero_init, final_update);
+        if (nb_mask & 1) launch_smooth_t<float, 3>(mg, tiles, ntiles, mode, zero_init, final_update, s);
+        if (nb_mask & 2) launch_smooth_t<float, 5>(mg, tiles, ntiles, mode, zero_init, final_update, s);
     } else {
-        if (nb_mask & 1)
-            hipLaunchKernelGGL((k_smooth<double, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, mode, zero_init, final_update);
-        if (nb_mask & 2)
-            hipLaunchKernelGGL((k_smooth<double, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, mode, zero_init, final_update);
+        if (nb_mask & 1) launch_smooth_t<double, 3>(mg, tiles, ntiles, mode, zero_init, final_update, s);
+        if (nb_mask & 2) launch_smooth_t<double, 5>(mg, tiles, ntiles, mode, zero_init, final_update, s);
     }
     return hipGetLastError();
 }
