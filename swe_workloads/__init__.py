@@ -305,12 +305,15 @@ def config4_instance(i: int, n_min: int = 256, n_max: int = 16384):
 
 
 def wedge_problem(nx: int = 1024, ny: int = 512, levels: Optional[int] = None, seed: int = 0,
-                  n_bumps: int = 16, amp: float = 1e-3, nu: int = 20) -> Problem2D:
+                  n_bumps: int = 16, amp: float = 1e-3, nu: Optional[int] = None,
+                  omega: float = 0.05) -> Problem2D:
     """Hydraulic jump over a wedge-like wall (section 5.2.2 rescaled): channel [0,40]x[0,30],
     inflow h = 1, (u, v) = 8.57 (cos t, -sin t), t = 8.95 deg on the left and top; extrapolation
     on the right; bottom side: extrapolation for x < 10, reflective wall beyond.  Flat bottom
     plus ``n_bumps`` seeded Gaussians of amplitude ``amp`` (centres ~ U over the box, unit
-    variance).  Coarsest grid 8x4."""
+    variance).  Coarsest grid 8x4.  Smoothing steps 10 / 15 / 20 on 16x8 / 32x16 / larger grids
+    (section 5.2); omega = 0.05: the multicolour ordering needs half the paper's 0.1 (which is
+    for its four directional sweeps) to stay stable once the jump forms."""
     th = math.radians(8.95)
     u, v = 8.57 * math.cos(th), -8.57 * math.sin(th)
     rng = np.random.default_rng([3, seed])
@@ -335,9 +338,11 @@ def wedge_problem(nx: int = 1024, ny: int = 512, levels: Optional[int] = None, s
         while (nx >> levels) >= 8 and (ny >> levels) >= 4 and (nx >> (levels - 1)) > 8:
             levels += 1
     inflow = BC(BC_STATE, h=1.0, u=u, v=v)
-    p = Params(eps=1e-6, omega=0.1, nu1=nu, nu2=nu, nu3=3)
+    if nu is None:
+        nu = 10 if nx <= 16 else (15 if nx <= 32 else 20)
+    p = Params(eps=1e-6, omega=omega, nu1=nu, nu2=nu, nu3=3)
     return Problem2D("wedge", 0.0, 40.0, 0.0, 30.0, nx, ny, levels, bottom,
-                     [inflow, BC(BC_EXTRAP), BC(BC_EXTRAP), inflow], p, wall_x=10.0,
+                     [inflow, BC(BC_EXTRAP), BC(BC_WALL), inflow], p, wall_x=10.0,
                      init_state=(1.0, u, v), meta=dict(theta=th, seed=seed))
 
 
