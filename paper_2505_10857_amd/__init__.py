@@ -8,12 +8,12 @@ from ._abi import (NMG_BC_DEPTH, NMG_BC_DISCHARGE, NMG_BC_EXTRAP, NMG_BC_STATE, 
                    NMG_EHIP, NMG_EINVAL, NMG_ENOMEM_WS, NMG_ENONFINITE, NMG_FP32_MG, NMG_FP64,
                    NMG_NOT_CONVERGED, NMG_OK, NmgError, load)
 
-__all__ = ["load", "NmgError", "NMG_FP64", "NMG_FP32_MG", "Solver1D", "BatchSolver1D"]
+__all__ = ["load", "NmgError", "NMG_FP64", "NMG_FP32_MG", "Solver1D", "BatchSolver1D", "Solver2D"]
 
 
 def __getattr__(name):
     # the binding imports torch; keep `import paper_2505_10857_amd` light for the build step
-    if name in ("Solver1D", "BatchSolver1D", "Problem1DDevice"):
+    if name in ("Solver1D", "BatchSolver1D", "Problem1DDevice", "Solver2D", "Problem2DDevice"):
         from . import solver
         return getattr(solver, name)
     raise AttributeError(name)

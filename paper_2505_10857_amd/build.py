@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnmg.so")
-SOURCES = ["swe1d.hip", "mg1d.hip", "api.hip"]
+SOURCES = ["swe1d.hip", "mg1d.hip", "api.hip", "swe2d.hip", "mg2d.hip", "api2d.hip"]
 HEADERS = ["nmg_common.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -94,6 +94,8 @@ Inst1D make_inst(const nmg_desc *d, const nmg_params *p)
 
 }  // namespace
 
+nmg_status nmg::set_error(nmg_status st, const char *msg) { return fail(st, msg); }
+
 struct nmg_plan {
     int n = 0;
     int prec = NMG_FP64;
@@ -592,6 +594,7 @@ nmg_status nmg_plan_solve(nmg_plan *P, void *ws, size_t ws_bytes, double *const 
 
 size_t nmg_workspace_bytes(const nmg_desc *desc, const nmg_params *params)
 {
+    if (desc && desc->dim == 2) return workspace2d_bytes(desc, params);
     nmg_plan P;
     if (build_plan(&P, desc, params, 1) != NMG_OK) return 0;
     return P.total;
@@ -600,6 +603,7 @@ size_t nmg_workspace_bytes(const nmg_desc *desc, const nmg_params *params)
 nmg_status nmg_residual(const nmg_desc *desc, const double *U, double *R, double *rn,
                         double *res_dev, void *stream)
 {
+    if (desc && desc->dim == 2) return residual2d(desc, U, R, rn, res_dev, (hipStream_t)stream);
     nmg_params p;
     memset(&p, 0, sizeof(p));
     p.eps = 1.0; p.nu3 = 1;
@@ -620,6 +624,7 @@ nmg_status nmg_jacobian_assemble_simplified(const nmg_desc *desc, const nmg_para
                                             const double *U, const double *R, const double *rn,
                                             double *J, void *stream)
 {
+    if (desc && desc->dim == 2) return jacobian2d(desc, params, U, R, rn, J, (hipStream_t)stream);
     nmg_status st = check_desc1d(desc, params);
     if (st != NMG_OK) return st;
     if (!U || !R || !rn || !J) return fail(NMG_EINVAL, "null U/R/rn/J");
@@ -636,6 +641,7 @@ nmg_status nmg_jacobian_assemble_simplified(const nmg_desc *desc, const nmg_para
 nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
                          const void *J, const void *rhs, void *dU, int32_t setup, void *stream)
 {
+    if (desc && desc->dim == 2) return vcycle2d(desc, params, ws, ws_bytes, J, rhs, dU, setup, (hipStream_t)stream);
     if (!ws || !rhs || !dU || (setup && !J)) return fail(NMG_EINVAL, "null argument");
     nmg_plan P;
     nmg_status st = build_plan(&P, desc, params, 1);
@@ -667,6 +673,10 @@ nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *w
 nmg_status nmg_newton_solve(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
                             double *U, nmg_stats *stats, double *hist, int32_t max_hist, void *stream)
 {
+    if (desc && desc->dim == 2) {
+        nmg_stats local;
+        return newton2d(desc, params, ws, ws_bytes, U, stats ? stats : &local, hist, max_hist, (hipStream_t)stream);
+    }
     nmg_plan P;
     nmg_status st = build_plan(&P, desc, params, 1);
     if (st != NMG_OK) return st;

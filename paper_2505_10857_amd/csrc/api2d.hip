@@ -1,0 +1,324 @@
+// libnmg host side for 2D problems (section 4): argument checks, workspace layout and the
+// Newton driver of Algorithm 1 with the V-cycle of Algorithm 2 on the 2D hierarchy.
+//
+// Workspace layout (byte offsets, each 256-byte aligned):
+//   state    : NewtonState
+//   partial  : double[residual tiles]      (per-tile sums of ||R_ij||_1)
+//   hist     : double[max_hist]
+//   R, rn    : double [3][ny][nx], [ny][nx]
+//   mg       : per level: J [nb*9][n_l], Dinv [9][n_l], rhs [3][n_l], dU [3][n_l]
+//              in double (NMG_FP64) or float (NMG_FP32_MG)
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nmg_common.h"
+
+namespace nmg {
+
+namespace {
+
+#define HIP_TRY2(expr)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return set_error(NMG_EHIP, (std::string(#expr) + ": " + hipGetErrorString(e_)).c_str()); \
+    } while (0)
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Plan2D {
+    Inst2D I;
+    int levels = 0, prec = NMG_FP64, nu1 = 0, nu2 = 0, nu3 = 1, n_max = 0, max_hist = 0, ntiles = 0;
+    int check_every = 1;
+    double tau = 0.0, omega = 1.0, tol = 0.0;
+    std::vector<Level2D> L;
+    size_t off_state = 0, off_partial = 0, off_hist = 0, off_R = 0, off_rn = 0, off_mg = 0, total = 0;
+};
+
+nmg_status check2d(const nmg_desc *d, const nmg_params *p)
+{
+    if (!d || !p) return set_error(NMG_EINVAL, "null desc or params");
+    if (d->dim != 2) return set_error(NMG_EINVAL, "dim must be 2");
+    if (d->nx < 1 || d->ny < 1) return set_error(NMG_EINVAL, "nx and ny must be positive");
+    if (d->levels < 1 || d->levels > kMaxLevels) return set_error(NMG_EINVAL, "levels must be in [1, 16]");
+    const int f = 1 << (d->levels - 1);
+    if (d->nx % f != 0 || d->ny % f != 0)
+        return set_error(NMG_EINVAL, "nx and ny must be divisible by 2^(levels-1)");
+    if ((long long)(d->nx / f) * (d->ny / f) > kMaxCoarse2D)
+        return set_error(NMG_EINVAL, "coarsest 2D level has more than 40 cells; add levels");
+    if ((long long)d->nx * d->ny > (1LL << 28)) return set_error(NMG_EINVAL, "grid too large");
+    if (d->jac != 9) return set_error(NMG_EINVAL, "2D jac must be 9");
+    if (!d->bx_gp || !d->by_gp) return set_error(NMG_EINVAL, "null geometry pointer");
+    if (!(d->x1 > d->x0) || !(d->y1 > d->y0)) return set_error(NMG_EINVAL, "empty domain");
+    for (int k = 0; k < 4; k++)
+        if (d->bc[k].kind < NMG_BC_DISCHARGE || d->bc[k].kind > NMG_BC_STATE)
+            return set_error(NMG_EINVAL, "bad boundary kind");
+    if (!(p->eps > 0.0)) return set_error(NMG_EINVAL, "eps must be positive");
+    if (p->nu1 < 0 || p->nu2 < 0 || p->nu3 < 1 || p->n_max < 0)
+        return set_error(NMG_EINVAL, "bad nu1/nu2/nu3/n_max");
+    if (p->nu1 > 1000 || p->nu2 > 1000 || p->nu3 > 1000) return set_error(NMG_EINVAL, "nu above 1000");
+    if (p->precision != NMG_FP64 && p->precision != NMG_FP32_MG) return set_error(NMG_EINVAL, "bad precision");
+    return NMG_OK;
+}
+
+Inst2D make_inst2d(const nmg_desc *d, const nmg_params *p)
+{
+    Inst2D I;
+    memset(&I, 0, sizeof(I));
+    I.Nx = d->nx;
+    I.Ny = d->ny;
+    I.dx = (d->x1 - d->x0) / d->nx;
+    I.dy = (d->y1 - d->y0) / d->ny;
+    I.g = d->g;
+    I.x0 = d->x0;
+    I.y0 = d->y0;
+    for (int k = 0; k < 4; k++) {
+        I.bc_kind[k] = d->bc[k].kind;
+        I.bc_q[k] = d->bc[k].q;
+        I.bc_h[k] = d->bc[k].h;
+        I.bc_u[k] = d->bc[k].u;
+        I.bc_v[k] = d->bc[k].v;
+    }
+    I.wall_x = d->wall_x;
+    I.bx = d->bx_gp;
+    I.by = d->by_gp;
+    I.alpha = p ? p->alpha : 0.0;
+    I.eps = p ? p->eps : 1.0;
+    return I;
+}
+
+nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p)
+{
+    nmg_status st = check2d(d, p);
+    if (st != NMG_OK) return st;
+    P.I = make_inst2d(d, p);
+    P.levels = d->levels;
+    P.prec = p->precision;
+    P.nu1 = p->nu1;
+    P.nu2 = p->nu2;
+    P.nu3 = p->nu3;
+    P.n_max = p->n_max;
+    P.max_hist = std::min(std::max(p->n_max, 1), 100000);
+    P.check_every = std::max(1, p->check_every);
+    P.tau = p->tau;
+    P.omega = p->omega;
+    P.tol = p->tol;
+    P.ntiles = residual2d_tiles(d->nx, d->ny);
+    const size_t vsz = P.prec == NMG_FP32_MG ? 4 : 8;
+    long long e = 0;
+    P.L.clear();
+    for (int l = 0; l < P.levels; l++) {
+        Level2D L;
+        memset(&L, 0, sizeof(L));
+        L.nx = d->nx >> l;
+        L.ny = d->ny >> l;
+        L.nb = l == 0 ? 9 : 5;
+        const long long n = (long long)L.nx * L.ny;
+        L.J = e; e += (long long)L.nb * 9 * n;
+        L.Dinv = e; e += 9 * n;
+        L.rhs = e; e += 3 * n;
+        L.dU = e; e += 3 * n;
+        e = (e + 63) & ~63LL;
+        P.L.push_back(L);
+    }
+    const long long n0 = (long long)d->nx * d->ny;
+    size_t o = 0;
+    P.off_state = o; o = al256(o + sizeof(NewtonState));
+    P.off_partial = o; o = al256(o + sizeof(double) * P.ntiles);
+    P.off_hist = o; o = al256(o + sizeof(double) * P.max_hist);
+    P.off_R = o; o = al256(o + sizeof(double) * 3 * n0);
+    P.off_rn = o; o = al256(o + sizeof(double) * n0);
+    P.off_mg = o; o = al256(o + vsz * (size_t)e);
+    P.total = o;
+    return NMG_OK;
+}
+
+// one smoothing iteration: two symmetric multicolour steps (colours 0..C-1, then C-1..0)
+nmg_status smooth_iter(const Plan2D &P, char *mgb, int l, hipStream_t s)
+{
+    const Level2D &L = P.L[l];
+    const int C = L.nb == 5 ? 2 : 3;
+    for (int rep = 0; rep < 2; rep++) {
+        for (int c = 0; c < C; c++) HIP_TRY2(launch_smooth2d_pass(mgb, L, c, P.omega, P.prec, s));
+        for (int c = C - 1; c >= 0; c--) HIP_TRY2(launch_smooth2d_pass(mgb, L, c, P.omega, P.prec, s));
+    }
+    return NMG_OK;
+}
+
+// Algorithm 2 from level l (recursive)
+nmg_status vcycle_from(const Plan2D &P, char *mgb, int l, hipStream_t s)
+{
+    if (l == P.levels - 1) {
+        HIP_TRY2(launch_coarse_solve2d(mgb, P.L[l], P.prec, s));
+        return NMG_OK;
+    }
+    nmg_status st;
+    for (int k = 0; k < P.nu1; k++)
+        if ((st = smooth_iter(P, mgb, l, s)) != NMG_OK) return st;
+    HIP_TRY2(launch_restrict2d(mgb, P.L[l], P.L[l + 1], P.prec, s));
+    if ((st = vcycle_from(P, mgb, l + 1, s)) != NMG_OK) return st;
+    HIP_TRY2(launch_prolong2d(mgb, P.L[l], P.L[l + 1], P.prec, s));
+    for (int k = 0; k < P.nu2; k++)
+        if ((st = smooth_iter(P, mgb, l, s)) != NMG_OK) return st;
+    return NMG_OK;
+}
+
+nmg_status coarsen_all(const Plan2D &P, char *mgb, hipStream_t s)
+{
+    for (int l = 1; l < P.levels; l++) HIP_TRY2(launch_coarsen2d(mgb, P.L[l - 1], P.L[l], P.prec, s));
+    return NMG_OK;
+}
+
+Inst2D bound_inst(const Plan2D &P, char *w, double *U)
+{
+    Inst2D I = P.I;
+    I.U = U;
+    I.R = (double *)(w + P.off_R);
+    I.rn = (double *)(w + P.off_rn);
+    return I;
+}
+
+// one Newton step of Algorithm 1 (all device work, no host synchronisation)
+nmg_status newton_step(const Plan2D &P, char *w, double *U, hipStream_t s)
+{
+    const Inst2D I = bound_inst(P, w, U);
+    char *mgb = w + P.off_mg;
+    const size_t vsz = P.prec == NMG_FP32_MG ? 4 : 8;
+    const Level2D &L0 = P.L[0];
+    const long long n0 = (long long)L0.nx * L0.ny;
+    NewtonState *S = (NewtonState *)(w + P.off_state);
+    HIP_TRY2(launch_jacobian2d(I, mgb + vsz * L0.J, mgb + vsz * L0.rhs, mgb + vsz * L0.Dinv, P.prec, s));
+    nmg_status st = coarsen_all(P, mgb, s);
+    if (st != NMG_OK) return st;
+    HIP_TRY2(launch_fill(mgb + vsz * L0.dU, P.prec, 3 * n0, s));
+    for (int m = 0; m < P.nu3; m++)
+        if ((st = vcycle_from(P, mgb, 0, s)) != NMG_OK) return st;
+    HIP_TRY2(launch_update2d(U, mgb, L0, P.tau, S, P.prec, s));
+    HIP_TRY2(launch_residual2d(I, (double *)(w + P.off_partial), s));
+    HIP_TRY2(launch_state2d((double *)(w + P.off_partial), P.ntiles, n0, P.tol, P.n_max, S,
+                            (double *)(w + P.off_hist), P.max_hist, 0, s));
+    return NMG_OK;
+}
+
+// The residual/Jacobian kernels of swe2d.hip are switched off: their first gfx950 run stopped
+// with a memory aperture violation whose cause has not been identified (a CPU build of the same
+// device functions, with bounds checks on every staged access, matches the oracle bit for bit).
+// The multigrid entry point (nmg_mg_vcycle) does not use them and stays enabled.
+constexpr bool kResidual2DEnabled = false;
+
+nmg_status residual2d_disabled()
+{
+    return set_error(NMG_EINVAL, "2D residual/Jacobian kernels are disabled: their first gfx950 run faulted "
+                                 "and the cause is not yet identified");
+}
+
+}  // namespace
+
+size_t workspace2d_bytes(const nmg_desc *d, const nmg_params *p)
+{
+    Plan2D P;
+    if (build2d(P, d, p) != NMG_OK) return 0;
+    return P.total;
+}
+
+nmg_status residual2d(const nmg_desc *d, const double *U, double *R, double *rn, double *res, hipStream_t s)
+{
+    if (!kResidual2DEnabled) return residual2d_disabled();
+    nmg_params p;
+    memset(&p, 0, sizeof(p));
+    p.eps = 1.0;
+    p.nu3 = 1;
+    nmg_status st = check2d(d, &p);
+    if (st != NMG_OK) return st;
+    if (!U || !R || !rn) return set_error(NMG_EINVAL, "null U/R/rn");
+    Inst2D I = make_inst2d(d, &p);
+    I.U = const_cast<double *>(U);
+    I.R = R;
+    I.rn = rn;
+    HIP_TRY2(launch_residual2d(I, nullptr, s));
+    if (res) HIP_TRY2(launch_sum_res(rn, d->nx * d->ny, res, s));
+    return NMG_OK;
+}
+
+nmg_status jacobian2d(const nmg_desc *d, const nmg_params *p, const double *U, const double *R,
+                      const double *rn, double *J, hipStream_t s)
+{
+    if (!kResidual2DEnabled) return residual2d_disabled();
+    nmg_status st = check2d(d, p);
+    if (st != NMG_OK) return st;
+    if (!U || !R || !rn || !J) return set_error(NMG_EINVAL, "null U/R/rn/J");
+    Inst2D I = make_inst2d(d, p);
+    I.U = const_cast<double *>(U);
+    I.R = const_cast<double *>(R);
+    I.rn = const_cast<double *>(rn);
+    HIP_TRY2(launch_jacobian2d(I, J, nullptr, nullptr, NMG_FP64, s));
+    return NMG_OK;
+}
+
+nmg_status vcycle2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, const void *J,
+                    const void *rhs, void *dU, int setup, hipStream_t s)
+{
+    if (!ws || !rhs || !dU || (setup && !J)) return set_error(NMG_EINVAL, "null argument");
+    Plan2D P;
+    nmg_status st = build2d(P, d, p);
+    if (st != NMG_OK) return st;
+    if (ws_bytes < P.total) return set_error(NMG_ENOMEM_WS, "workspace too small");
+    char *mgb = (char *)ws + P.off_mg;
+    const size_t vsz = P.prec == NMG_FP32_MG ? 4 : 8;
+    const Level2D &L0 = P.L[0];
+    const long long n0 = (long long)L0.nx * L0.ny;
+    if (setup) {
+        HIP_TRY2(launch_convert(J, NMG_FP64, mgb + vsz * L0.J, P.prec, 81 * n0, s));
+        HIP_TRY2(launch_dinv2d((const double *)J, mgb + vsz * L0.Dinv, n0, P.prec, s));
+        if ((st = coarsen_all(P, mgb, s)) != NMG_OK) return st;
+    }
+    HIP_TRY2(launch_convert(rhs, P.prec, mgb + vsz * L0.rhs, P.prec, 3 * n0, s));
+    HIP_TRY2(launch_convert(dU, P.prec, mgb + vsz * L0.dU, P.prec, 3 * n0, s));
+    if ((st = vcycle_from(P, mgb, 0, s)) != NMG_OK) return st;
+    HIP_TRY2(launch_convert(mgb + vsz * L0.dU, P.prec, dU, P.prec, 3 * n0, s));
+    return NMG_OK;
+}
+
+nmg_status newton2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, double *U,
+                    nmg_stats *stats, double *hist, int max_hist, hipStream_t s)
+{
+    if (!kResidual2DEnabled) return residual2d_disabled();
+    if (!ws || !U || !stats) return set_error(NMG_EINVAL, "null argument");
+    Plan2D P;
+    nmg_status st = build2d(P, d, p);
+    if (st != NMG_OK) return st;
+    if (ws_bytes < P.total) return set_error(NMG_ENOMEM_WS, "workspace too small");
+    char *w = (char *)ws;
+    const Inst2D I = bound_inst(P, w, U);
+    const long long n0 = (long long)P.L[0].nx * P.L[0].ny;
+    NewtonState *S = (NewtonState *)(w + P.off_state);
+    HIP_TRY2(launch_residual2d(I, (double *)(w + P.off_partial), s));
+    HIP_TRY2(launch_state2d((double *)(w + P.off_partial), P.ntiles, n0, P.tol, P.n_max, S, nullptr, 0, 1, s));
+    NewtonState hs;
+    memset(&hs, 0, sizeof(hs));
+    HIP_TRY2(hipMemcpyAsync(&hs, S, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIP_TRY2(hipStreamSynchronize(s));
+    // Steps are enqueued check_every at a time; once the device state stops, the remaining
+    // enqueued steps leave U unchanged (the update kernel reads the state).
+    while (hs.active) {
+        for (int k = 0; k < P.check_every; k++)
+            if ((st = newton_step(P, w, U, s)) != NMG_OK) return st;
+        HIP_TRY2(hipMemcpyAsync(&hs, S, sizeof(hs), hipMemcpyDeviceToHost, s));
+        HIP_TRY2(hipStreamSynchronize(s));
+    }
+    stats->iters = hs.n;
+    stats->status = hs.status;
+    stats->res = hs.res;
+    if (hist && max_hist > 0) {
+        const int cnt = std::min(std::min(max_hist, hs.n), P.max_hist);
+        if (cnt > 0) {
+            HIP_TRY2(hipMemcpyAsync(hist, w + P.off_hist, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+            HIP_TRY2(hipStreamSynchronize(s));
+        }
+    }
+    return (nmg_status)hs.status;
+}
+
+}  // namespace nmg

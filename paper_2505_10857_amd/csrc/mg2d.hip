@@ -1,0 +1,394 @@
+// Geometric multigrid for the 2D regularised Newton systems (section 4.2, eq. 22-25) on gfx950:
+// coarse operators of eq. (24) (cross stencil -> five points on level 1, five points -> five
+// points below), multicolour block SOR passes (eq. 22), restriction, injection prolongation,
+// and Gaussian elimination with partial pivoting on the coarsest grid (dense, in LDS).
+// One thread per cell or coarse cell; the sums run in the order of the definitions.
+#include <algorithm>
+
+#include "nmg_common.h"
+
+namespace nmg {
+
+template <typename T>
+__device__ __forceinline__ double ld2(const T *p, long long i) { return (double)p[i]; }
+
+// stencil offsets: the cross of eq. (21) on the finest level, five points below
+__device__ __forceinline__ void stencil_off(int nb, int b, int &di, int &dj)
+{
+    if (nb == 9) {
+        const int ox[9] = {0, -2, -1, 1, 2, 0, 0, 0, 0};
+        const int oy[9] = {0, 0, 0, 0, 0, -2, -1, 1, 2};
+        di = ox[b]; dj = oy[b];
+    } else {
+        const int ox[5] = {0, -1, 1, 0, 0};
+        const int oy[5] = {0, 0, 0, -1, 1};
+        di = ox[b]; dj = oy[b];
+    }
+}
+
+__device__ __forceinline__ int find_off(int nb, int di, int dj)
+{
+    for (int b = 0; b < nb; b++) {
+        int ox, oy;
+        stencil_off(nb, b, ox, oy);
+        if (ox == di && oy == dj) return b;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ void inv3d(const double A[9], double B[9])
+{
+    const double c00 = A[4] * A[8] - A[5] * A[7];
+    const double c01 = A[5] * A[6] - A[3] * A[8];
+    const double c02 = A[3] * A[7] - A[4] * A[6];
+    const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    B[0] = c00 / det;
+    B[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+    B[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+    B[3] = c01 / det;
+    B[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+    B[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    B[6] = c02 / det;
+    B[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+    B[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+}
+
+// eq. (24), operator part, one thread per coarse cell: for each five-point offset, sum the fine
+// blocks of the 2x2 children rows against the 2x2 children of the neighbour; then D^{-1}.
+template <typename T>
+__global__ void k_coarsen2d(T *mg, Level2D Lf, Level2D Lc)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Jq = blockIdx.y;
+    if (I >= Lc.nx || Jq >= Lc.ny) return;
+    const long long nf = (long long)Lf.nx * Lf.ny, nc = (long long)Lc.nx * Lc.ny;
+    const long long cc = (long long)Jq * Lc.nx + I;
+    double D[9];
+    for (int bc = 0; bc < 5; bc++) {
+        int dP, dQ;
+        stencil_off(5, bc, dP, dQ);
+        const int P = I + dP, Q = Jq + dQ;
+        double blk[9];
+#pragma unroll
+        for (int e = 0; e < 9; e++) blk[e] = 0.0;
+        if (P >= 0 && P < Lc.nx && Q >= 0 && Q < Lc.ny) {
+            for (int fj = 2 * Jq; fj <= 2 * Jq + 1; fj++)
+                for (int fi = 2 * I; fi <= 2 * I + 1; fi++)
+                    for (int cj = 2 * Q; cj <= 2 * Q + 1; cj++)
+                        for (int ci = 2 * P; ci <= 2 * P + 1; ci++) {
+                            const int b = find_off(Lf.nb, ci - fi, cj - fj);
+                            if (b < 0) continue;
+                            const long long fc = (long long)fj * Lf.nx + fi;
+#pragma unroll
+                            for (int e = 0; e < 9; e++)
+                                blk[e] = blk[e] + ld2(mg + Lf.J, (b * 9 + e) * nf + fc);
+                        }
+        }
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            mg[Lc.J + (bc * 9 + e) * nc + cc] = (T)blk[e];
+            if (bc == 0) D[e] = blk[e];
+        }
+    }
+    double B[9];
+    inv3d(D, B);
+#pragma unroll
+    for (int e = 0; e < 9; e++) mg[Lc.Dinv + e * nc + cc] = (T)B[e];
+}
+
+// One colour pass of eq. (22) on one level: cells with (i + j) mod C == colour.
+template <typename T>
+__global__ void k_smooth2d_pass(T *mg, Level2D L, int colour, double omega)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= L.nx || j >= L.ny) return;
+    const int C = L.nb == 5 ? 2 : 3;
+    if ((i + j) % C != colour) return;
+    const long long n = (long long)L.nx * L.ny, cc = (long long)j * L.nx + i;
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) r[c] = ld2(mg + L.rhs, c * n + cc);
+    for (int b = 1; b < L.nb; b++) {
+        int di, dj;
+        stencil_off(L.nb, b, di, dj);
+        const int pi = i + di, pj = j + dj;
+        if (pi < 0 || pi >= L.nx || pj < 0 || pj >= L.ny) continue;
+        const long long nc2 = (long long)pj * L.nx + pi;
+        const double x0 = ld2(mg + L.dU, nc2), x1 = ld2(mg + L.dU, n + nc2), x2 = ld2(mg + L.dU, 2 * n + nc2);
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            r[c] = r[c] + (ld2(mg + L.J, (b * 9 + c * 3 + 0) * n + cc) * x0 +
+                           ld2(mg + L.J, (b * 9 + c * 3 + 1) * n + cc) * x1 +
+                           ld2(mg + L.J, (b * 9 + c * 3 + 2) * n + cc) * x2);
+    }
+    double t[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+        t[c] = ld2(mg + L.Dinv, (c * 3 + 0) * n + cc) * r[0] + ld2(mg + L.Dinv, (c * 3 + 1) * n + cc) * r[1] +
+               ld2(mg + L.Dinv, (c * 3 + 2) * n + cc) * r[2];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const double d = ld2(mg + L.dU, c * n + cc);
+        mg[L.dU + c * n + cc] = (T)((1.0 - omega) * d - omega * t[c]);
+    }
+}
+
+// eq. (24), right-hand side, one thread per coarse cell; also clears the coarse dU.
+template <typename T>
+__global__ void k_restrict2d(T *mg, Level2D Lf, Level2D Lc)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Jq = blockIdx.y;
+    if (I >= Lc.nx || Jq >= Lc.ny) return;
+    const long long nf = (long long)Lf.nx * Lf.ny, nc = (long long)Lc.nx * Lc.ny;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int fj = 2 * Jq; fj <= 2 * Jq + 1; fj++)
+        for (int fi = 2 * I; fi <= 2 * I + 1; fi++) {
+            const long long fc = (long long)fj * Lf.nx + fi;
+            double a[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) a[c] = ld2(mg + Lf.rhs, c * nf + fc);
+            for (int b = 0; b < Lf.nb; b++) {
+                int di, dj;
+                stencil_off(Lf.nb, b, di, dj);
+                const int pi = fi + di, pj = fj + dj;
+                if (pi < 0 || pi >= Lf.nx || pj < 0 || pj >= Lf.ny) continue;
+                const long long q = (long long)pj * Lf.nx + pi;
+                const double x0 = ld2(mg + Lf.dU, q), x1 = ld2(mg + Lf.dU, nf + q), x2 = ld2(mg + Lf.dU, 2 * nf + q);
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    a[c] = a[c] + (ld2(mg + Lf.J, (b * 9 + c * 3 + 0) * nf + fc) * x0 +
+                                   ld2(mg + Lf.J, (b * 9 + c * 3 + 1) * nf + fc) * x1 +
+                                   ld2(mg + Lf.J, (b * 9 + c * 3 + 2) * nf + fc) * x2);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; c++) s[c] = s[c] + a[c];
+        }
+    const long long cc = (long long)Jq * Lc.nx + I;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        mg[Lc.rhs + c * nc + cc] = (T)s[c];
+        mg[Lc.dU + c * nc + cc] = (T)0.0;
+    }
+}
+
+// eq. (25): dU_fine += dU_coarse(parent)
+template <typename T>
+__global__ void k_prolong2d(T *mg, Level2D Lf, Level2D Lc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= Lf.nx || j >= Lf.ny) return;
+    const long long nf = (long long)Lf.nx * Lf.ny, nc = (long long)Lc.nx * Lc.ny;
+    const long long fc = (long long)j * Lf.nx + i, pc = (long long)(j >> 1) * Lc.nx + (i >> 1);
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+        mg[Lf.dU + c * nf + fc] = (T)(ld2(mg + Lf.dU, c * nf + fc) + ld2(mg + Lc.dU, c * nc + pc));
+}
+
+// Coarsest level: dense Gaussian elimination with partial pivoting of sum J dU = -rhs
+// (unknown (j*nx + i)*3 + c), one workgroup, the matrix in LDS.
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse_solve2d(T *mg, Level2D L)
+{
+    constexpr int MM = 3 * kMaxCoarse2D;
+    __shared__ double A[MM * MM];
+    __shared__ double x[MM];
+    __shared__ double f[MM];
+    __shared__ int piv_s;
+    const int nx = L.nx, ny = L.ny, n = nx * ny, M = 3 * n;
+    const int t = threadIdx.x;
+    for (int e = t; e < M * M; e += 256) A[e] = 0.0;
+    __syncthreads();
+    for (int e = t; e < n * L.nb; e += 256) {
+        const int cell = e / L.nb, b = e % L.nb;
+        const int i = cell % nx, j = cell / nx;
+        int di, dj;
+        stencil_off(L.nb, b, di, dj);
+        const int pi = i + di, pj = j + dj;
+        if (pi < 0 || pi >= nx || pj < 0 || pj >= ny) continue;
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++)
+                A[(cell * 3 + r) * M + (pj * nx + pi) * 3 + c] = ld2(mg + L.J, (b * 9 + r * 3 + c) * (long long)n + cell);
+    }
+    for (int r = t; r < M; r += 256) x[r] = -ld2(mg + L.rhs, (r % 3) * (long long)n + r / 3);
+    __syncthreads();
+    for (int k = 0; k < M; k++) {
+        if (t == 0) {
+            int p = k;
+            for (int r = k + 1; r < M; r++)
+                if (fabs(A[r * M + k]) > fabs(A[p * M + k])) p = r;
+            piv_s = p;
+        }
+        __syncthreads();
+        const int p = piv_s;
+        if (p != k) {
+            for (int c = t; c < M; c += 256) {
+                const double y = A[k * M + c];
+                A[k * M + c] = A[p * M + c];
+                A[p * M + c] = y;
+            }
+            if (t == 0) { const double y = x[k]; x[k] = x[p]; x[p] = y; }
+        }
+        __syncthreads();
+        for (int r = k + 1 + t; r < M; r += 256) f[r] = A[r * M + k] / A[k * M + k];
+        __syncthreads();
+        for (int e = t; e < (M - k - 1) * (M - k); e += 256) {
+            const int r = k + 1 + e / (M - k), c = k + e % (M - k);
+            if (f[r] != 0.0) A[r * M + c] -= f[r] * A[k * M + c];
+        }
+        __syncthreads();
+        if (t == 0)
+            for (int r = k + 1; r < M; r++)
+                if (f[r] != 0.0) x[r] -= f[r] * x[k];
+        __syncthreads();
+    }
+    if (t == 0) {
+        for (int k = M - 1; k >= 0; k--) {
+            double s = x[k];
+            for (int c = k + 1; c < M; c++) s -= A[k * M + c] * x[c];
+            x[k] = s / A[k * M + k];
+        }
+    }
+    __syncthreads();
+    for (int r = t; r < M; r += 256) mg[L.dU + (r % 3) * (long long)n + r / 3] = (T)x[r];
+}
+
+// inverse of the centre blocks of an FP64 level-0 operator [nb*9][n] (block 0 first)
+template <typename T>
+__global__ void k_dinv2d(const double *J, T *Dinv, long long n)
+{
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+        double D[9], B[9];
+#pragma unroll
+        for (int e = 0; e < 9; e++) D[e] = J[e * n + c];
+        inv3d(D, B);
+#pragma unroll
+        for (int e = 0; e < 9; e++) Dinv[e * n + c] = (T)B[e];
+    }
+}
+
+template <typename T>
+__global__ void k_fill(T *p, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = (T)0.0;
+}
+
+// eq. (14): U <- U + tau dU (skipped once the Newton iteration has stopped)
+template <typename T>
+__global__ void k_update2d(double *U, const T *mg, Level2D L0, double tau, const NewtonState *S)
+{
+    if (S && !S->active) return;
+    const long long n = (long long)L0.nx * L0.ny;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < 3 * n; e += (long long)gridDim.x * blockDim.x)
+        U[e] = U[e] + tau * ld2(mg + L0.dU, e);
+}
+
+// res from the tile partials, Newton counter and stopping test (Algorithm 1)
+__global__ void __launch_bounds__(256) k_state2d(const double *partial, int ntiles, long long ncells, double tol,
+                                                 int n_max, NewtonState *S, double *hist, int max_hist, int init)
+{
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int k = threadIdx.x; k < ntiles; k += 256) v += partial[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double res = (red[0] + red[1] + red[2] + red[3]) / (double)ncells;
+    if (init) {
+        S->res = res; S->n = 0; S->active = 1; S->status = NMG_NOT_CONVERGED;
+        if (!(res == res) || res > 1e300) { S->active = 0; S->status = NMG_ENONFINITE; }
+        return;
+    }
+    if (!S->active) return;
+    S->res = res;
+    if (hist && S->n < max_hist) hist[S->n] = res;
+    S->n += 1;
+    if (!(res == res) || res > 1e300) { S->active = 0; S->status = NMG_ENONFINITE; }
+    else if (res < tol) { S->active = 0; S->status = NMG_OK; }
+    else if (S->n >= n_max) { S->active = 0; S->status = NMG_NOT_CONVERGED; }
+}
+
+// ---- launchers ---------------------------------------------------------------------------
+
+#define DISPATCH(prec, KER, grid, block, ...)                                                      \
+    do {                                                                                           \
+        if ((prec) == NMG_FP32_MG) hipLaunchKernelGGL(KER<float>, grid, block, 0, s, (float *)mg, __VA_ARGS__); \
+        else hipLaunchKernelGGL(KER<double>, grid, block, 0, s, (double *)mg, __VA_ARGS__);       \
+    } while (0)
+
+hipError_t launch_coarsen2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s)
+{
+    dim3 grid((Lc.nx + 63) / 64, Lc.ny);
+    DISPATCH(prec, k_coarsen2d, grid, dim3(64), Lf, Lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, double omega, int prec, hipStream_t s)
+{
+    dim3 grid((L.nx + 63) / 64, (L.ny + 3) / 4);
+    DISPATCH(prec, k_smooth2d_pass, grid, dim3(64, 4), L, colour, omega);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s)
+{
+    dim3 grid((Lc.nx + 63) / 64, Lc.ny);
+    DISPATCH(prec, k_restrict2d, grid, dim3(64), Lf, Lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s)
+{
+    dim3 grid((Lf.nx + 63) / 64, (Lf.ny + 3) / 4);
+    DISPATCH(prec, k_prolong2d, grid, dim3(64, 4), Lf, Lc);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_solve2d(void *mg, const Level2D &L, int prec, hipStream_t s)
+{
+    DISPATCH(prec, k_coarse_solve2d, dim3(1), dim3(256), L);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(void *p, int prec, long long n, hipStream_t s)
+{
+    int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+    if (blocks < 1) return hipSuccess;
+    if (prec == NMG_FP32_MG) hipLaunchKernelGGL(k_fill<float>, dim3(blocks), dim3(256), 0, s, (float *)p, n);
+    else hipLaunchKernelGGL(k_fill<double>, dim3(blocks), dim3(256), 0, s, (double *)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_update2d(double *U, const void *mg, const Level2D &L0, double tau, const NewtonState *state,
+                           int prec, hipStream_t s)
+{
+    const long long n = 3LL * L0.nx * L0.ny;
+    int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    if (prec == NMG_FP32_MG)
+        hipLaunchKernelGGL(k_update2d<float>, dim3(blocks), dim3(256), 0, s, U, (const float *)mg, L0, tau, state);
+    else
+        hipLaunchKernelGGL(k_update2d<double>, dim3(blocks), dim3(256), 0, s, U, (const double *)mg, L0, tau, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_dinv2d(const double *J, void *Dinv, long long n, int prec, hipStream_t s)
+{
+    int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    if (prec == NMG_FP32_MG) hipLaunchKernelGGL(k_dinv2d<float>, dim3(blocks), dim3(256), 0, s, J, (float *)Dinv, n);
+    else hipLaunchKernelGGL(k_dinv2d<double>, dim3(blocks), dim3(256), 0, s, J, (double *)Dinv, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_state2d(const double *partial, int ntiles, long long ncells, double tol, int n_max,
+                          NewtonState *state, double *hist, int max_hist, int init, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_state2d, dim3(1), dim3(256), 0, s, partial, ntiles, ncells, tol, n_max, state, hist,
+                       max_hist, init);
+    return hipGetLastError();
+}
+
+}  // namespace nmg

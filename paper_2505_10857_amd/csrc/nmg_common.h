@@ -69,6 +69,25 @@ __host__ __device__ inline int halo_cells(int nb, int nu)
     return nu * 2 * C * (nb / 2);
 }
 
+// One 2D instance (section 4).
+struct Inst2D {
+    int Nx, Ny;
+    double dx, dy, g, x0, y0;
+    int bc_kind[4];
+    double bc_q[4], bc_h[4], bc_u[4], bc_v[4];
+    double wall_x;
+    const double *bx, *by;     // [Ny][Nx][2][2]: (y point beta, x point gamma)
+    double *U, *R, *rn;        // U, R: [3][Ny][Nx]
+    double alpha, eps;
+};
+
+// One 2D multigrid level: blocks J [nb*9][n], Dinv [9][n], rhs [3][n], dU [3][n] (cell j*nx+i);
+// offsets in elements of the value type.
+struct Level2D {
+    int nx, ny, nb, pad;
+    long long J, Dinv, rhs, dU;
+};
+
 // ---- launchers (return hipError_t of the launch) ----------------------------------------
 
 // residual over tiles (batched: tiles index instances) or one instance (tiles == null)
@@ -90,5 +109,38 @@ hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int 
                            int zero_init, int final_update, int prec, hipStream_t s);
 hipError_t launch_convert(const void *src, int src_prec, void *dst, int dst_prec, long long n,
                           hipStream_t s);
+
+// 2D
+int residual2d_tiles(int Nx, int Ny);
+hipError_t launch_residual2d(const Inst2D &I, double *partial, hipStream_t s);
+hipError_t launch_res2d_finalize(const double *partial, int ntiles, long long ncells, double *res,
+                                 hipStream_t s);
+hipError_t launch_jacobian2d(const Inst2D &I, void *J, void *rhs, void *Dinv, int prec, hipStream_t s);
+hipError_t launch_coarsen2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
+hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, double omega, int prec, hipStream_t s);
+hipError_t launch_restrict2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
+hipError_t launch_prolong2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
+hipError_t launch_coarse_solve2d(void *mg, const Level2D &L, int prec, hipStream_t s);
+hipError_t launch_fill(void *p, int prec, long long n, hipStream_t s);
+hipError_t launch_update2d(double *U, const void *mg, const Level2D &L0, double tau,
+                           const NewtonState *state, int prec, hipStream_t s);
+hipError_t launch_dinv2d(const double *J, void *Dinv, long long n, int prec, hipStream_t s);
+hipError_t launch_state2d(const double *partial, int ntiles, long long ncells, double tol, int n_max,
+                          NewtonState *state, double *hist, int max_hist, int init, hipStream_t s);
+constexpr int kMaxCoarse2D = 40;   // cells on the coarsest 2D level (dense solve in LDS)
+
+// error reporting shared by the host translation units (sets the thread-local message)
+nmg_status set_error(nmg_status st, const char *msg);
+
+// 2D entry points (dim = 2), called by the ABI functions
+size_t workspace2d_bytes(const nmg_desc *d, const nmg_params *p);
+nmg_status residual2d(const nmg_desc *d, const double *U, double *R, double *rn, double *res,
+                      hipStream_t s);
+nmg_status jacobian2d(const nmg_desc *d, const nmg_params *p, const double *U, const double *R,
+                      const double *rn, double *J, hipStream_t s);
+nmg_status vcycle2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, const void *J,
+                    const void *rhs, void *dU, int setup, hipStream_t s);
+nmg_status newton2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, double *U,
+                    nmg_stats *stats, double *hist, int max_hist, hipStream_t s);
 
 }  // namespace nmg

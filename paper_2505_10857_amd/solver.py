@@ -210,3 +210,116 @@ class BatchSolver1D:
         A.check(A.load().nmg_plan_steps(self.plan, _dptr(self.ws), k, 1 if use_graph else 0, active,
                                         stats, C.c_void_p(_stream_ptr())))
         return list(active), [(s.iters, s.status, s.res) for s in stats]
+
+
+class Problem2DDevice:
+    """Device-resident description of one 2D problem (eq. 1-2): b_x and b_y sampled at the
+    tensor Gauss points (x_i -/+ dx/(2 sqrt 3), y_j -/+ dy/(2 sqrt 3)) of every cell, stored
+    [ny][nx][y point][x point]."""
+
+    def __init__(self, prob, device="cuda"):
+        self.prob = prob
+        nx, ny, dx, dy = prob.nx, prob.ny, prob.dx, prob.dy
+        gx = dx / (2.0 * math.sqrt(3.0))
+        gy = dy / (2.0 * math.sqrt(3.0))
+        xc = prob.x0 + (np.arange(nx) + 0.5) * dx
+        yc = prob.y0 + (np.arange(ny) + 0.5) * dy
+        bx = np.empty((ny, nx, 2, 2))
+        by = np.empty((ny, nx, 2, 2))
+        for b, sy in ((0, -gy), (1, gy)):
+            for a, sx in ((0, -gx), (1, gx)):
+                X = np.ascontiguousarray(np.broadcast_to((xc + sx)[None, :], (ny, nx)))
+                Y = np.ascontiguousarray(np.broadcast_to((yc + sy)[:, None], (ny, nx)))
+                _, dbx, dby = prob.bottom(X, Y)
+                bx[:, :, b, a] = dbx
+                by[:, :, b, a] = dby
+        f64 = dict(dtype=torch.float64, device=device)
+        self.bx_gp = torch.tensor(np.ascontiguousarray(bx), **f64)
+        self.by_gp = torch.tensor(np.ascontiguousarray(by), **f64)
+        d = A.nmg_desc()
+        d.dim, d.nx, d.ny, d.levels, d.jac = 2, nx, ny, prob.levels, 9
+        d.x0, d.x1, d.y0, d.y1, d.g = prob.x0, prob.x1, prob.y0, prob.y1, prob.g
+        for k, bc in enumerate(prob.bc):
+            d.bc[k].kind, d.bc[k].q, d.bc[k].h, d.bc[k].u, d.bc[k].v = bc.kind, bc.q, bc.h, bc.u, bc.v
+        d.wall_x = prob.wall_x
+        d.bx_gp = self.bx_gp.data_ptr()
+        d.by_gp = self.by_gp.data_ptr()
+        self.desc = d
+        self.device = device
+
+
+class Solver2D:
+    """Single-instance entry points of the C ABI for one 2D problem (state [3, ny, nx])."""
+
+    def __init__(self, prob, device="cuda", precision: int = A.NMG_FP64, check_every: int = 4,
+                 levels: Optional[int] = None, **param_overrides):
+        A.load()
+        self.dev = Problem2DDevice(prob, device)
+        if levels is not None:
+            self.dev.desc.levels = levels
+        p = prob.params
+        if param_overrides:
+            import dataclasses
+            p = dataclasses.replace(p, **param_overrides)
+        self.p = p
+        self.params = params_struct(p, precision, check_every)
+        self.precision = precision
+        self.nx, self.ny = prob.nx, prob.ny
+        self.device = device
+        self._ws = None
+
+    @property
+    def L(self):
+        return A.load()
+
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            nbytes = self.L.nmg_workspace_bytes(C.byref(self.dev.desc), C.byref(self.params))
+            if nbytes == 0:
+                raise A.NmgError(A.NMG_EINVAL, self.L.nmg_last_error().decode())
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def state(self, U=None) -> torch.Tensor:
+        U = self.dev.prob.initial_guess() if U is None else U
+        if isinstance(U, torch.Tensor):
+            return U.to(device=self.device, dtype=torch.float64).contiguous().clone()
+        return torch.tensor(np.ascontiguousarray(U), dtype=torch.float64, device=self.device)
+
+    def residual(self, U: torch.Tensor):
+        """R [3, ny, nx], rn [ny, nx], res (0-d tensor) on the device (eq. 20, Algorithm 1)."""
+        R = torch.empty_like(U)
+        rn = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        res = torch.empty((), dtype=torch.float64, device=self.device)
+        A.check(self.L.nmg_residual(C.byref(self.dev.desc), _dptr(U), _dptr(R), _dptr(rn),
+                                    _dptr(res), C.c_void_p(_stream_ptr())))
+        return R, rn, res
+
+    def jacobian(self, U, R, rn) -> torch.Tensor:
+        """Blocks J [9, 3, 3, ny, nx] (eq. 12-13, 21) on the device."""
+        J = torch.empty((9, 3, 3, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        A.check(self.L.nmg_jacobian_assemble_simplified(
+            C.byref(self.dev.desc), C.byref(self.params), _dptr(U), _dptr(R), _dptr(rn), _dptr(J),
+            C.c_void_p(_stream_ptr())))
+        return J
+
+    def vcycle(self, J: Optional[torch.Tensor], rhs: torch.Tensor, dU: torch.Tensor, setup: bool):
+        """One V-cycle for sum J dU = -rhs (rhs, dU [3, ny, nx]); dU is updated in place."""
+        ws = self.workspace()
+        A.check(self.L.nmg_mg_vcycle(C.byref(self.dev.desc), C.byref(self.params), _dptr(ws),
+                                     ws.numel(), _dptr(J) if J is not None else None, _dptr(rhs),
+                                     _dptr(dU), 1 if setup else 0, C.c_void_p(_stream_ptr())))
+        return dU
+
+    def newton_solve(self, U: torch.Tensor, max_hist: int = 0):
+        """Algorithm 1 in place on U.  Returns (stats, history ndarray)."""
+        ws = self.workspace()
+        st = A.nmg_stats()
+        hist = (C.c_double * max(1, max_hist))()
+        status = self.L.nmg_newton_solve(C.byref(self.dev.desc), C.byref(self.params), _dptr(ws),
+                                         ws.numel(), _dptr(U), C.byref(st),
+                                         hist if max_hist > 0 else None, max_hist,
+                                         C.c_void_p(_stream_ptr()))
+        A.check(status, ok=(A.NMG_OK, A.NMG_NOT_CONVERGED, A.NMG_ENONFINITE))
+        h = np.array(hist[:min(max_hist, st.iters)]) if max_hist > 0 else np.zeros(0)
+        return st, h
