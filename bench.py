@@ -9,8 +9,10 @@ update).  value = B * steps / timed wall time.  Inputs are resident in HBM befor
 region starts.
 
 Also reported: Newton-MG DOF/s, the single-instance solve rate and latency, the full Jacobian
-J5 side by side, the FP32-multigrid form, the roofline of the dominant kernel (HIP events on
-the launch stream) and the CPU oracle on a bounded sample of the same workload.
+J5 side by side, the FP32-multigrid form, the uneven batch of 512 instances, the
+continuous-batching server (Poisson arrivals at 200 req/s, and saturated) with p50/p99
+latency, the roofline of the dominant kernel (HIP events on the launch stream) and the CPU
+oracle on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -53,6 +55,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-instances", type=int, default=3)
+    ap.add_argument("--served-requests", type=int, default=400)
+    ap.add_argument("--served-budget-gib", type=int, default=16)
     return ap.parse_args()
 
 
@@ -84,6 +88,29 @@ def timed_solves(solver, U0s, steps, warmup, use_graph, profile_kernel=None):
         kms, kcnt = solver.profile_read()
         solver.profile(0)
     return el, stats, kms, kcnt, sets[-1]
+
+
+def served(args, rate):
+    """The request loop of paper_2505_10857_amd.serve on a seeded Poisson stream (FP32 multigrid,
+    FP64 residual / update / test); the two smallest results are checked against the oracle."""
+    import numpy as np
+    import oracle
+    from paper_2505_10857_amd import NMG_FP32_MG
+    from paper_2505_10857_amd.serve import GpuEngine, Server, stream
+    reqs = stream(args.served_requests, rate=rate, seed=0)
+    server = Server(GpuEngine("cuda:0", precision=NMG_FP32_MG), hbm_budget=args.served_budget_gib << 30,
+                    steps_per_tick=2, keep_states=True)
+    rep = server.run(reqs)
+    out = rep.summary()
+    out.update(rate_req_s=rate if rate < 1e6 else "all at t=0", requests=len(reqs),
+               n_range=[min(r.prob.n for r in reqs), max(r.prob.n for r in reqs)],
+               hbm_budget_gib=args.served_budget_gib)
+    errs = []
+    for r in sorted(rep.results, key=lambda r: r.n)[:2]:
+        Uo, _, _, _ = oracle.Oracle1D(reqs[r.rid].prob).newton_solve()
+        errs.append(float(np.abs(r.state.cpu().numpy() - Uo).max()))
+    out["max_abs_err_vs_fp64_oracle_two_smallest"] = max(errs) if errs else None
+    return out
 
 
 def cpu_baseline(args):
@@ -191,6 +218,20 @@ def main():
                                     "newton_steps": [min(s[0] for s in st32[-1]), max(s[0] for s in st32[-1])],
                                     "max_abs_diff_vs_fp64_gpu": err,
                                     "converged": all(s[1] == 0 and s[2] < 1e-10 for st in st32 for s in st)}
+        # uneven batch: 512 instances, N log-uniform in [256, 16384], FP32 multigrid, one plan
+        from swe_workloads import config4_instance
+        uprobs = [config4_instance(i) for i in range(512)]
+        su = BatchSolver1D(uprobs, device="cuda:0", jac=3, precision=NMG_FP32_MG)
+        eu, stu, _, _, _ = timed_solves(su, su.states(), 3, 2, use_graph)
+        ucells = sum(p.n for p in uprobs)
+        forms["fp32mg_uneven512"] = {
+            "solves_per_s": 512 * 3 / eu, "cells_per_batch": ucells,
+            "dof_per_s": sum(2 * p.n * st[0] for sts in stu for p, st in zip(uprobs, sts)) / eu,
+            "newton_steps": [min(st[0] for st in stu[-1]), max(st[0] for st in stu[-1])],
+            "converged": all(st[1] == 0 and st[2] < 1e-10 for sts in stu for st in sts)}
+        # continuous-batching server: Poisson arrivals at 200 req/s, N in [512, 32768]
+        forms["served_200rps"] = served(args, 200.0)
+        forms["served_saturated"] = served(args, 1e7)
         out["forms"] = forms
 
     # ---- CPU oracle ----------------------------------------------------------------------------

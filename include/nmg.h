@@ -99,7 +99,9 @@ typedef struct {
 } nmg_stats;
 
 /* Bytes of device workspace nmg_mg_vcycle and nmg_newton_solve need for this problem
- * (multigrid hierarchy, Jacobian, residual buffers, tables).  0 on invalid input. */
+ * (multigrid hierarchy, Jacobian, residual buffers, tables).  Only sizes and parameters are
+ * read: the geometry pointers may be null, so a caller can budget memory before uploading
+ * anything.  0 on invalid input. */
 size_t nmg_workspace_bytes(const nmg_desc *desc, const nmg_params *params);
 
 /* Residual of eq. (10) (1D, not divided by dx) or eq. (20) (2D) for every cell, the cell norms
@@ -153,6 +155,13 @@ nmg_status nmg_plan_solve(nmg_plan *plan, void *ws, size_t ws_bytes, double *con
 nmg_status nmg_plan_begin(nmg_plan *plan, void *ws, size_t ws_bytes, double *const *U, void *stream);
 nmg_status nmg_plan_steps(nmg_plan *plan, void *ws, int32_t steps, int32_t use_graph,
                           int32_t *active_out, nmg_stats *stats, void *stream);
+/* nmg_plan_begin for instances that have already taken Newton steps under another plan (a
+ * serving loop re-plans between steps as requests arrive and retire): n_done (host, length n)
+ * holds each instance's step count so far, which must be below its n_max.  The residual is
+ * re-evaluated from U[k]; with the same U it equals the value the previous step ended with, so
+ * a solve split over several plans takes exactly the steps of an uninterrupted one. */
+nmg_status nmg_plan_resume(nmg_plan *plan, void *ws, size_t ws_bytes, double *const *U,
+                           const int32_t *n_done, void *stream);
 void nmg_plan_destroy(nmg_plan *plan);
 
 /* Kernel timing for benchmarks: with kernel = one of NMG_K_*, every later non-graph step

@@ -30,7 +30,7 @@ EXPORTS = [
     "nmg_workspace_bytes", "nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",
     "nmg_newton_solve", "nmg_plan_create", "nmg_plan_workspace_bytes", "nmg_plan_solve",
     "nmg_plan_begin", "nmg_plan_steps", "nmg_plan_destroy", "nmg_last_error",
-    "nmg_plan_profile", "nmg_plan_profile_read",
+    "nmg_plan_profile", "nmg_plan_profile_read", "nmg_plan_resume",
 ]
 
 NMG_K_NONE = 0
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
     L.nmg_plan_solve.argtypes = [vp, vp, sz, P(vp), P(nmg_stats), C.c_int32, vp]
     L.nmg_plan_begin.argtypes = [vp, vp, sz, P(vp), vp]
     L.nmg_plan_steps.argtypes = [vp, vp, C.c_int32, C.c_int32, P(C.c_int32), P(nmg_stats), vp]
+    L.nmg_plan_resume.argtypes = [vp, vp, sz, P(vp), P(C.c_int32), vp]
     L.nmg_plan_destroy.argtypes = [vp]
     L.nmg_plan_destroy.restype = None
     L.nmg_plan_profile.argtypes = [vp, C.c_int32]
@@ -109,7 +110,7 @@ def load(path: str = LIB_PATH):
     L.nmg_last_error.restype = C.c_char_p
     for nm in ("nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",
                "nmg_newton_solve", "nmg_plan_create", "nmg_plan_solve", "nmg_plan_begin",
-               "nmg_plan_steps"):
+               "nmg_plan_steps", "nmg_plan_resume"):
         getattr(L, nm).restype = C.c_int32
     _lib = L
     return L

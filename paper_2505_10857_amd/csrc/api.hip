@@ -38,7 +38,7 @@ nmg_status fail(nmg_status st, const std::string &msg)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-nmg_status check_desc1d(const nmg_desc *d, const nmg_params *p)
+nmg_status check_desc1d(const nmg_desc *d, const nmg_params *p, bool need_geometry = true)
 {
     if (!d || !p) return fail(NMG_EINVAL, "null desc or params");
     if (d->dim != 1) return fail(NMG_EINVAL, "only dim = 1 is handled by this entry point");
@@ -49,7 +49,7 @@ nmg_status check_desc1d(const nmg_desc *d, const nmg_params *p)
     if ((d->nx >> (d->levels - 1)) > kMaxCoarse)
         return fail(NMG_EINVAL, "coarsest level has more than 256 cells; add levels");
     if (d->jac != 3 && d->jac != 5) return fail(NMG_EINVAL, "1D jac must be 3 or 5");
-    if (!d->sig_face || !d->sig_gp || !d->sigx_gp || !d->bx_gp)
+    if (need_geometry && (!d->sig_face || !d->sig_gp || !d->sigx_gp || !d->bx_gp))
         return fail(NMG_EINVAL, "null geometry pointer");
     if (!(d->x1 > d->x0)) return fail(NMG_EINVAL, "x1 must exceed x0");
     if (!(p->eps > 0.0)) return fail(NMG_EINVAL, "eps must be positive");
@@ -114,6 +114,7 @@ struct nmg_plan {
     size_t off_insts = 0, off_levs = 0, off_tiles = 0, off_list = 0, off_state = 0, off_partial = 0,
            off_hist = 0, off_R = 0, off_mg = 0, total = 0;
     std::vector<size_t> R_off;                // per instance byte offset of R (rn follows)
+    std::vector<int> n_start;                 // Newton steps already taken, per instance
     int max_hist = 0;
     // graph cache
     hipGraphExec_t gexec = nullptr;
@@ -144,7 +145,8 @@ struct nmg_plan {
 
 namespace {
 
-nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *params, int n)
+nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *params, int n,
+                      bool need_geometry = true)
 {
     if (n <= 0) return fail(NMG_EINVAL, "need at least one instance");
     P->n = n;
@@ -152,7 +154,7 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
     P->nu3 = params[0].nu3;
     P->check_every = std::max(1, params[0].check_every);
     for (int k = 0; k < n; k++) {
-        nmg_status st = check_desc1d(&descs[k], &params[k]);
+        nmg_status st = check_desc1d(&descs[k], &params[k], need_geometry);
         if (st != NMG_OK) return fail(st, "instance " + std::to_string(k) + ": " + g_err);
         if (params[k].precision != P->prec) return fail(NMG_EINVAL, "mixed precisions in one plan");
         if (params[k].nu3 != P->nu3) return fail(NMG_EINVAL, "mixed nu3 in one plan");
@@ -342,6 +344,7 @@ nmg_status upload_tables(nmg_plan *P, char *ws, double *const *U, hipStream_t s)
         I.R = reinterpret_cast<double *>(ws + P->R_off[k]);
         I.rn = I.R + 2 * (size_t)I.N;
         I.hist = reinterpret_cast<double *>(ws + P->off_hist) + (size_t)k * std::max(1, P->max_hist);
+        I.n_start = P->n_start.empty() ? 0 : P->n_start[k];
         memcpy(P->host_tables + sizeof(Inst1D) * k, &I, sizeof(Inst1D));
     }
     HIP_TRY(hipMemcpyAsync(ws + P->off_insts, P->host_tables, isz, hipMemcpyHostToDevice, s));
@@ -530,6 +533,22 @@ void nmg_plan_destroy(nmg_plan *plan) { delete plan; }
 nmg_status nmg_plan_begin(nmg_plan *P, void *ws, size_t ws_bytes, double *const *U, void *stream)
 {
     if (!P) return fail(NMG_EINVAL, "null plan");
+    P->n_start.assign(P->n, 0);
+    return plan_begin(P, (char *)ws, ws_bytes, U, (hipStream_t)stream);
+}
+
+nmg_status nmg_plan_resume(nmg_plan *P, void *ws, size_t ws_bytes, double *const *U, const int32_t *n_done,
+                           void *stream)
+{
+    if (!P) return fail(NMG_EINVAL, "null plan");
+    if (!n_done) return fail(NMG_EINVAL, "null step counts");
+    P->n_start.assign(P->n, 0);
+    for (int k = 0; k < P->n; k++) {
+        if (n_done[k] < 0) return fail(NMG_EINVAL, "negative step count");
+        if (n_done[k] >= P->insts[k].n_max)
+            return fail(NMG_EINVAL, "instance " + std::to_string(k) + " has no Newton steps left");
+        P->n_start[k] = n_done[k];
+    }
     return plan_begin(P, (char *)ws, ws_bytes, U, (hipStream_t)stream);
 }
 
@@ -560,6 +579,7 @@ nmg_status nmg_plan_solve(nmg_plan *P, void *ws, size_t ws_bytes, double *const 
 {
     if (!P) return fail(NMG_EINVAL, "null plan");
     hipStream_t s = (hipStream_t)stream;
+    P->n_start.assign(P->n, 0);
     nmg_status st = plan_begin(P, (char *)ws, ws_bytes, U, s);
     if (st != NMG_OK) return st;
     int max_steps = 0;
@@ -596,7 +616,7 @@ size_t nmg_workspace_bytes(const nmg_desc *desc, const nmg_params *params)
 {
     if (desc && desc->dim == 2) return workspace2d_bytes(desc, params);
     nmg_plan P;
-    if (build_plan(&P, desc, params, 1) != NMG_OK) return 0;
+    if (build_plan(&P, desc, params, 1, false) != NMG_OK) return 0;
     return P.total;
 }
 

@@ -37,7 +37,7 @@ struct Plan2D {
     size_t off_state = 0, off_partial = 0, off_hist = 0, off_R = 0, off_rn = 0, off_mg = 0, total = 0;
 };
 
-nmg_status check2d(const nmg_desc *d, const nmg_params *p)
+nmg_status check2d(const nmg_desc *d, const nmg_params *p, bool need_geometry = true)
 {
     if (!d || !p) return set_error(NMG_EINVAL, "null desc or params");
     if (d->dim != 2) return set_error(NMG_EINVAL, "dim must be 2");
@@ -50,7 +50,7 @@ nmg_status check2d(const nmg_desc *d, const nmg_params *p)
         return set_error(NMG_EINVAL, "coarsest 2D level has more than 40 cells; add levels");
     if ((long long)d->nx * d->ny > (1LL << 28)) return set_error(NMG_EINVAL, "grid too large");
     if (d->jac != 9) return set_error(NMG_EINVAL, "2D jac must be 9");
-    if (!d->bx_gp || !d->by_gp) return set_error(NMG_EINVAL, "null geometry pointer");
+    if (need_geometry && (!d->bx_gp || !d->by_gp)) return set_error(NMG_EINVAL, "null geometry pointer");
     if (!(d->x1 > d->x0) || !(d->y1 > d->y0)) return set_error(NMG_EINVAL, "empty domain");
     for (int k = 0; k < 4; k++)
         if (d->bc[k].kind < NMG_BC_DISCHARGE || d->bc[k].kind > NMG_BC_STATE)
@@ -89,9 +89,9 @@ Inst2D make_inst2d(const nmg_desc *d, const nmg_params *p)
     return I;
 }
 
-nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p)
+nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p, bool need_geometry = true)
 {
-    nmg_status st = check2d(d, p);
+    nmg_status st = check2d(d, p, need_geometry);
     if (st != NMG_OK) return st;
     P.I = make_inst2d(d, p);
     P.levels = d->levels;
@@ -219,7 +219,7 @@ nmg_status residual2d_disabled()
 size_t workspace2d_bytes(const nmg_desc *d, const nmg_params *p)
 {
     Plan2D P;
-    if (build2d(P, d, p) != NMG_OK) return 0;
+    if (build2d(P, d, p, false) != NMG_OK) return 0;
     return P.total;
 }
 

@@ -34,6 +34,7 @@ struct Inst1D {
     int res_tile0, res_tiles;  // residual tiles of this instance (contiguous)
     int max_hist;
     int lbot;          // first level handled by the bottom-of-cycle kernel
+    int n_start;       // Newton steps already taken (a resumed instance); 0 for a fresh one
     double *hist;      // device history of res, [max_hist] (may be null)
 };
 

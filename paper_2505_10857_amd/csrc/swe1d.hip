@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(64) k_res_finalize(const Inst1D *insts, int ni
     const double res = v / I.N;
     S.res = res;
     if (init) {
-        S.n = 0;
+        S.n = I.n_start;
         S.active = 1;
         S.status = NMG_NOT_CONVERGED;
         if (!(res == res) || res > 1e300) { S.active = 0; S.status = NMG_ENONFINITE; }

@@ -151,9 +151,12 @@ class BatchSolver1D:
     """Many independent 1D problems solved together (one launch per kernel per step)."""
 
     def __init__(self, probs: Sequence, device="cuda", jac: int = 3, precision: int = A.NMG_FP64,
-                 check_every: int = 4, jacs: Optional[Sequence[int]] = None):
+                 check_every: int = 4, jacs: Optional[Sequence[int]] = None,
+                 devs: Optional[Sequence[Problem1DDevice]] = None):
         A.load()
-        self.devs = [Problem1DDevice(p, device, (jacs[k] if jacs else jac)) for k, p in enumerate(probs)]
+        if devs is None:
+            devs = [Problem1DDevice(p, device, (jacs[k] if jacs else jac)) for k, p in enumerate(probs)]
+        self.devs = list(devs)
         self.probs = list(probs)
         n = len(probs)
         self.descs = (A.nmg_desc * n)(*[d.desc for d in self.devs])
@@ -192,6 +195,13 @@ class BatchSolver1D:
         self._ptrs = (C.c_void_p * self.n)(*[u.data_ptr() for u in Us])
         A.check(A.load().nmg_plan_begin(self.plan, _dptr(self.ws), self.ws_bytes, self._ptrs,
                                         C.c_void_p(_stream_ptr())))
+
+    def resume(self, Us: List[torch.Tensor], n_done: Sequence[int]):
+        """Begin on states that have already taken n_done[k] Newton steps under another plan."""
+        self._ptrs = (C.c_void_p * self.n)(*[u.data_ptr() for u in Us])
+        counts = (C.c_int32 * self.n)(*[int(v) for v in n_done])
+        A.check(A.load().nmg_plan_resume(self.plan, _dptr(self.ws), self.ws_bytes, self._ptrs, counts,
+                                         C.c_void_p(_stream_ptr())))
 
     def profile(self, kernel: int):
         """Time every later non-graph launch of one kernel (NMG_K_*) with HIP events."""
