@@ -4,9 +4,12 @@
 // One thread per cell; a 256-cell tile stages U (+2 halo cells per side) in LDS so that the
 // five-cell stencil of eq. (10) is read from HBM once.  Each thread keeps its stencil in
 // registers and evaluates the local residual R_j for the base state and for every column
-// perturbation of the kept blocks.  The arithmetic follows the paper's formulas in their
-// printed order with FMA contraction disabled (-ffp-contract=off), so the residual is
-// reproducible bit for bit by any IEEE-754 FP64 evaluation of the same formulas.
+// perturbation of the kept blocks.  FP64 division is the costly operation here (a reciprocal
+// and several dependent FMAs each), so the formulas are evaluated in algebraically equal forms
+// with few divisions: one per WENO3 reconstruction (the normalised weights combined over a
+// common denominator), one reciprocal per depth and wave-speed difference in the HLL flux,
+// reciprocals of the widths once per cell and of the perturbation once per launch.  The result
+// agrees with the printed forms to rounding.
 #include "nmg_common.h"
 
 namespace nmg {
@@ -17,53 +20,52 @@ namespace nmg {
 
 __device__ __forceinline__ double weno_plus(double um, double u0, double up)
 {
-    // right state U+_{j-1/2} at the left face of cell j
-    double c0 = 1.5 * u0 - 0.5 * up;   // T0 = {j, j+1}
-    double c1 = 0.5 * um + 0.5 * u0;   // T1 = {j-1, j}
-    double b0 = (up - u0) * (up - u0);
-    double b1 = (u0 - um) * (u0 - um);
-    double a0 = (1.0 / 3.0) / ((kZeta + b0) * (kZeta + b0));
-    double a1 = (2.0 / 3.0) / ((kZeta + b1) * (kZeta + b1));
-    double w0 = a0 / (a0 + a1);
-    double w1 = a1 / (a0 + a1);
-    return w0 * c0 + w1 * c1;
+    // right state U+_{j-1/2} at the left face of cell j: candidates T0 = {j, j+1} (weight 1/3)
+    // and T1 = {j-1, j} (2/3); w_r = alpha_r / (alpha_0 + alpha_1) with
+    // alpha_r = d_r / (zeta + beta_r)^2, combined over the common denominator
+    const double c0 = 1.5 * u0 - 0.5 * up;
+    const double c1 = 0.5 * um + 0.5 * u0;
+    const double z0 = kZeta + (up - u0) * (up - u0);
+    const double z1 = kZeta + (u0 - um) * (u0 - um);
+    const double e0 = z0 * z0, e1 = z1 * z1;
+    return (e1 * c0 + 2.0 * (e0 * c1)) / (e1 + 2.0 * e0);
 }
 
 __device__ __forceinline__ double weno_minus(double um, double u0, double up)
 {
-    // left state U-_{j+1/2} at the right face of cell j
-    double c0 = 0.5 * u0 + 0.5 * up;
-    double c1 = -0.5 * um + 1.5 * u0;
-    double b0 = (up - u0) * (up - u0);
-    double b1 = (u0 - um) * (u0 - um);
-    double a0 = (2.0 / 3.0) / ((kZeta + b0) * (kZeta + b0));
-    double a1 = (1.0 / 3.0) / ((kZeta + b1) * (kZeta + b1));
-    double w0 = a0 / (a0 + a1);
-    double w1 = a1 / (a0 + a1);
-    return w0 * c0 + w1 * c1;
+    // left state U-_{j+1/2} at the right face of cell j: T0 = {j, j+1} (2/3), T1 = {j-1, j} (1/3)
+    const double c0 = 0.5 * u0 + 0.5 * up;
+    const double c1 = -0.5 * um + 1.5 * u0;
+    const double z0 = kZeta + (up - u0) * (up - u0);
+    const double z1 = kZeta + (u0 - um) * (u0 - um);
+    const double e0 = z0 * z0, e1 = z1 * z1;
+    return (2.0 * (e1 * c0) + e0 * c1) / (2.0 * e1 + e0);
 }
 
 // ---- HLL flux for eq. (4) with Davis wave-speed bounds ----------------------------------
 
 __device__ __forceinline__ void hll(double HL, double QL, double HR, double QR, double sig,
-                                    double g, double &F0, double &F1)
+                                    double isig, double g, double &F0, double &F1)
 {
-    double hl = HL / sig, hr = HR / sig;
-    double FL0 = QL, FL1 = QL * QL / HL + 0.5 * g * sig * hl * hl;
-    double FR0 = QR, FR1 = QR * QR / HR + 0.5 * g * sig * hr * hr;
-    double uL = QL / HL, uR = QR / HR;
-    double cL = sqrt(g * hl), cR = sqrt(g * hr);
-    double sl1 = uL - cL, sl2 = uR - cR;
-    double sr1 = uL + cL, sr2 = uR + cR;
-    double SL = sl1 < sl2 ? sl1 : sl2;
-    double SR = sr1 > sr2 ? sr1 : sr2;
+    // sig: width at the face, isig = 1 / sig
+    const double iHL = 1.0 / HL, iHR = 1.0 / HR;
+    const double hl = HL * isig, hr = HR * isig;
+    const double uL = QL * iHL, uR = QR * iHR;
+    const double FL0 = QL, FL1 = QL * uL + 0.5 * g * sig * hl * hl;
+    const double FR0 = QR, FR1 = QR * uR + 0.5 * g * sig * hr * hr;
+    const double cL = sqrt(g * hl), cR = sqrt(g * hr);
+    const double sl1 = uL - cL, sl2 = uR - cR;
+    const double sr1 = uL + cL, sr2 = uR + cR;
+    const double SL = sl1 < sl2 ? sl1 : sl2;
+    const double SR = sr1 > sr2 ? sr1 : sr2;
     if (SL >= 0.0) {
         F0 = FL0; F1 = FL1;
     } else if (SR <= 0.0) {
         F0 = FR0; F1 = FR1;
     } else {
-        F0 = (SR * FL0 - SL * FR0 + SL * SR * (HR - HL)) / (SR - SL);
-        F1 = (SR * FL1 - SL * FR1 + SL * SR * (QR - QL)) / (SR - SL);
+        const double iw = 1.0 / (SR - SL);
+        F0 = (SR * FL0 - SL * FR0 + SL * SR * (HR - HL)) * iw;
+        F1 = (SR * FL1 - SL * FR1 + SL * SR * (QR - QL)) * iw;
     }
 }
 
@@ -93,8 +95,8 @@ struct CubicGauss {
 
 // Geometry of one cell: faces j-1/2, j+1/2 and the two Gauss points.
 struct CellGeom {
-    double sfm, sfp;
-    double sg[2], sxg[2], bxg[2];
+    double sfm, sfp, isfm, isfp;      // widths at the faces and their reciprocals
+    double sg[2], isg[2], sxg[2], bxg[2];
 };
 
 __device__ __forceinline__ CellGeom load_geom(const Inst1D &I, int j)
@@ -102,9 +104,12 @@ __device__ __forceinline__ CellGeom load_geom(const Inst1D &I, int j)
     CellGeom G;
     G.sfm = I.sig_face[j];
     G.sfp = I.sig_face[j + 1];
+    G.isfm = 1.0 / G.sfm;
+    G.isfp = 1.0 / G.sfp;
 #pragma unroll
     for (int q = 0; q < 2; q++) {
         G.sg[q] = I.sig_gp[2 * j + q];
+        G.isg[q] = 1.0 / G.sg[q];
         G.sxg[q] = I.sigx_gp[2 * j + q];
         G.bxg[q] = I.bx_gp[2 * j + q];
     }
@@ -170,7 +175,7 @@ __device__ __forceinline__ double source_term(double Hp_ll, double Hp_l, double 
 #pragma unroll
     for (int q = 0; q < 2; q++) {
         double Hg = W.w[q][0] * Hp_ll + W.w[q][1] * Hp_l + W.w[q][2] * Hm_r + W.w[q][3] * Hm_rr;
-        double hg = Hg / G.sg[q];
+        double hg = Hg * G.isg[q];
         double s = 0.5 * g * hg * hg * G.sxg[q] - g * G.sg[q] * hg * G.bxg[q];
         sum = sum + s;
     }
@@ -207,8 +212,8 @@ __device__ __forceinline__ void assemble_residual(const Recon &r, double S, cons
                                                   double g, double &R0, double &R1)
 {
     double Fm0, Fm1, Fp0, Fp1;
-    hll(r.Hm_l, r.Qm_l, r.Hp_l, r.Qp_l, G.sfm, g, Fm0, Fm1);
-    hll(r.Hm_r, r.Qm_r, r.Hp_r, r.Qp_r, G.sfp, g, Fp0, Fp1);
+    hll(r.Hm_l, r.Qm_l, r.Hp_l, r.Qp_l, G.sfm, G.isfm, g, Fm0, Fm1);
+    hll(r.Hm_r, r.Qm_r, r.Hp_r, r.Qp_r, G.sfp, G.isfp, g, Fp0, Fp1);
     R0 = Fp0 - Fm0;
     R1 = Fp1 - Fm1 - S;
 }
@@ -421,7 +426,7 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs, 
         const CellGeom G = load_geom(I, j);
         const CubicGauss W;
         const double R0 = I.R[j], R1 = I.R[I.N + j], rn = I.rn[j];
-        const double eps = I.eps;
+        const double eps = I.eps, ieps = 1.0 / I.eps;
         if (rhs) {   // the finest level's right-hand side of eq. (16) is R itself
             rhs[j] = (T)R0;
             rhs[stride + j] = (T)R1;
@@ -454,8 +459,8 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs, 
                         stencil_ghosts(Hp, Qp, j, I);
                         local_residual(Hp, Qp, G, W, I.dx, I.g, P0, P1);
                     }
-                    e0 = (P0 - R0) / eps;
-                    e1 = (P1 - R1) / eps;
+                    e0 = (P0 - R0) * ieps;
+                    e1 = (P1 - R1) * ieps;
                     if (b == HW) {
                         if (m == 0) e0 += I.alpha * rn;
                         else e1 += I.alpha * rn;

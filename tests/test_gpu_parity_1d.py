@@ -1,8 +1,9 @@
 """GPU parity of the 1D hot path against the CPU oracle, through the C ABI.
 
-Bar (FP64): residual and Jacobian within 1e-12 relative (the arithmetic is written to be
-bit-identical, which these tests also report), one V-cycle within 1e-12 relative, Newton
-trajectories within 1e-10 at the same step count.  FP32 multigrid: converged state within
+Bar (FP64): residual and Jacobian within 1e-12 relative (the kernels evaluate the formulas in
+algebraically equal forms with fewer divisions, so agreement is to rounding; the tests report
+whether it is also bitwise), one V-cycle within 1e-12 relative, Newton trajectories within
+1e-10 at the same step count.  FP32 multigrid: converged state within
 1e-9 of the FP64 oracle's.
 """
 import math
@@ -70,7 +71,8 @@ def test_residual_parity(name, prob):
         print(f"{name}: residual max|dR| = {err:.3e} (bitwise equal: {np.array_equal(Rg, Ro)})")
         assert err <= 1e-12 * scale
         assert np.abs(rn.cpu().numpy() - rno).max() <= 1e-12 * scale
-        assert abs(res.item() - reso) <= 1e-13 * max(reso, 1e-300)
+        # res is the mean of |R0| + |R1|, so its error is at most twice the largest R error
+        assert abs(res.item() - reso) <= 2e-12 * scale
 
 
 @pytest.mark.parametrize("nb", [3, 5])
@@ -154,7 +156,9 @@ def test_config2_full_size_residual_jacobian_and_solve():
     U = s.state(U0)
     R, rn, _ = s.residual(U)
     Ro, rno, _ = o.residual(U0)
-    assert np.abs(R.cpu().numpy() - Ro).max() <= 1e-12 * np.abs(Ro).max()
+    # R is a difference of fluxes of size O(10): near a steady state its own magnitude is no
+    # yardstick for rounding, so the bar is relative to max(|R|, 1) as in the other R tests
+    assert np.abs(R.cpu().numpy() - Ro).max() <= 1e-12 * max(np.abs(Ro).max(), 1.0)
     J = np.transpose(s.jacobian(U, R, rn).cpu().numpy(), (3, 0, 1, 2))
     Jo = o.jacobian(U0, nb=3)
     assert np.abs(J - Jo).max() <= 1e-12 * np.abs(Jo).max()
