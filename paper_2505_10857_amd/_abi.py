@@ -30,7 +30,8 @@ EXPORTS = [
     "nmg_workspace_bytes", "nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",
     "nmg_newton_solve", "nmg_plan_create", "nmg_plan_workspace_bytes", "nmg_plan_solve",
     "nmg_plan_begin", "nmg_plan_steps", "nmg_plan_destroy", "nmg_last_error",
-    "nmg_plan_profile", "nmg_plan_profile_read", "nmg_plan_resume",
+    "nmg_plan_profile", "nmg_plan_profile_read", "nmg_plan_resume", "nmg_plan_set_options",
+    "nmg_plan_get_options", "nmg_plan_autotune",
 ]
 
 NMG_K_NONE = 0
@@ -64,6 +65,13 @@ class nmg_params(C.Structure):
 
 class nmg_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("res", C.c_double)]
+
+
+class nmg_plan_options(C.Structure):
+    _fields_ = [("bottom_cells", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+NMG_TUNE_CANDIDATES = 4
 
 
 class NmgError(RuntimeError):
@@ -100,6 +108,10 @@ def load(path: str = LIB_PATH):
     L.nmg_plan_begin.argtypes = [vp, vp, sz, P(vp), vp]
     L.nmg_plan_steps.argtypes = [vp, vp, C.c_int32, C.c_int32, P(C.c_int32), P(nmg_stats), vp]
     L.nmg_plan_resume.argtypes = [vp, vp, sz, P(vp), P(C.c_int32), vp]
+    L.nmg_plan_set_options.argtypes = [vp, P(nmg_plan_options)]
+    L.nmg_plan_get_options.argtypes = [vp, P(nmg_plan_options)]
+    L.nmg_plan_autotune.argtypes = [vp, vp, sz, P(vp), C.c_int32, C.c_int32, P(nmg_plan_options),
+                                    P(C.c_double), vp]
     L.nmg_plan_destroy.argtypes = [vp]
     L.nmg_plan_destroy.restype = None
     L.nmg_plan_profile.argtypes = [vp, C.c_int32]
@@ -110,7 +122,8 @@ def load(path: str = LIB_PATH):
     L.nmg_last_error.restype = C.c_char_p
     for nm in ("nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",
                "nmg_newton_solve", "nmg_plan_create", "nmg_plan_solve", "nmg_plan_begin",
-               "nmg_plan_steps", "nmg_plan_resume"):
+               "nmg_plan_steps", "nmg_plan_resume", "nmg_plan_set_options", "nmg_plan_get_options",
+               "nmg_plan_autotune"):
         getattr(L, nm).restype = C.c_int32
     _lib = L
     return L

@@ -115,6 +115,12 @@ struct nmg_plan {
            off_hist = 0, off_R = 0, off_mg = 0, total = 0;
     std::vector<size_t> R_off;                // per instance byte offset of R (rn follows)
     std::vector<int> n_start;                 // Newton steps already taken, per instance
+    // tunables (nmg_plan_options) and what is needed to rebuild the tables for them
+    int bottom_cells = 2048;                  // levels up to this size run in k_bottom
+    int bottom_nt = 1024;                     // its workgroup size
+    size_t tile_cap = 0;                      // tile-table entries reserved (any option fits)
+    std::vector<nmg_desc> descs;
+    std::vector<nmg_params> params;
     int max_hist = 0;
     // graph cache
     hipGraphExec_t gexec = nullptr;
@@ -198,10 +204,10 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
             P->levs.push_back(L);
         }
         I.levc = (int)P->levs.size() - 1;
-        // bottom kernel: from the first three-block level with at most kBottomCells cells
+        // bottom kernel: from the first three-block level with at most bottom_cells cells
         I.lbot = I.levels - 1;
         for (int l = 0; l < I.levels; l++)
-            if ((I.N >> l) <= kBottomCells && (l > 0 || I.nb == 3)) { I.lbot = l; break; }
+            if ((I.N >> l) <= P->bottom_cells && (l > 0 || I.nb == 3)) { I.lbot = l; break; }
         I.max_hist = std::min(params[k].n_max, 100000);
         P->insts.push_back(I);
     }
@@ -258,7 +264,8 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
     size_t o = 0;
     P->off_insts = o; o = align256(o + sizeof(Inst1D) * n);
     P->off_levs = o; o = align256(o + sizeof(Level1D) * P->levs.size());
-    P->off_tiles = o; o = align256(o + sizeof(Tile) * std::max<size_t>(1, P->tiles.size()));
+    P->off_tiles = o;
+    o = align256(o + sizeof(Tile) * std::max<size_t>(1, std::max(P->tiles.size(), P->tile_cap)));
     P->off_list = o; o = align256(o + sizeof(int) * n);
     P->off_state = o; o = align256(o + sizeof(NewtonState) * n);
     P->off_partial = o; o = align256(o + sizeof(double) * std::max(1, P->res_nt));
@@ -378,7 +385,7 @@ nmg_status enqueue_vcycle(nmg_plan *P, char *ws, const MGArgs &mg, bool zero_ini
         HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
                                 P->smooth_mask[d], 0, (d > 0 || zero_init0) ? 1 : 0, 0, P->prec, s));
     }
-    HIP_TRY(launch_bottom(mg, list, P->n, zero_init0 ? 1 : 0, final_update ? 1 : 0, P->prec, s));
+    HIP_TRY(launch_bottom(mg, list, P->n, zero_init0 ? 1 : 0, final_update ? 1 : 0, P->prec, P->bottom_nt, s));
     for (int d = P->depth - 1; d >= 0; d--) {
         if (P->smooth[d].second == 0) continue;
         ProfScope ps(P, d == 0 ? NMG_K_SMOOTH_POST : -1, s, cap);
@@ -481,6 +488,80 @@ nmg_status plan_steps(nmg_plan *P, char *ws, int steps, int use_graph, hipStream
     return NMG_OK;
 }
 
+constexpr int kTuneCandidates[NMG_TUNE_CANDIDATES] = {256, 512, 1024, 2048};
+
+// Rebuild the plan's tables for another bottom-kernel threshold.  The byte layout does not move
+// (the tile table is reserved for the largest tile count), so a workspace sized for the plan
+// fits every option; device tables and any captured graph are refreshed on the next use.
+nmg_status apply_bottom_cells(nmg_plan *P, int cells)
+{
+    bool ok = false;
+    for (int c : kTuneCandidates) ok = ok || c == cells;
+    if (!ok) return fail(NMG_EINVAL, "bottom_cells must be 256, 512, 1024 or 2048");
+    const size_t total = P->total;
+    P->bottom_cells = cells;
+    P->bottom_nt = std::min(1024, std::max(256, cells / 2));
+    nmg_status st = build_plan(P, P->descs.data(), P->params.data(), P->n);
+    if (st != NMG_OK) return st;
+    P->total = std::max(P->total, total);
+    P->tables_ws = nullptr;
+    if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+    if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
+    return NMG_OK;
+}
+
+nmg_status plan_autotune(nmg_plan *P, char *ws, size_t ws_bytes, double *const *U, int trial_steps,
+                         int use_graph, nmg_plan_options *best, double *times_ms, hipStream_t s)
+{
+    if (trial_steps < 1 || trial_steps > 100) return fail(NMG_EINVAL, "trial_steps must be in [1, 100]");
+    if (!U) return fail(NMG_EINVAL, "null state array");
+    if (ws_bytes < P->total) return fail(NMG_ENOMEM_WS, "workspace too small");
+    // the trials move U: keep a device copy of every state
+    std::vector<size_t> off(P->n + 1, 0);
+    for (int k = 0; k < P->n; k++) {
+        if (!U[k]) return fail(NMG_EINVAL, "null state pointer");
+        off[k + 1] = off[k] + 2 * (size_t)P->insts[k].N;
+    }
+    double *save = nullptr;
+    HIP_TRY(hipMalloc((void **)&save, sizeof(double) * off[P->n]));
+    struct Free { double *p; ~Free() { if (p) (void)hipFree(p); } } guard{save};
+    for (int k = 0; k < P->n; k++)
+        HIP_TRY(hipMemcpyAsync(save + off[k], U[k], sizeof(double) * (off[k + 1] - off[k]),
+                               hipMemcpyDeviceToDevice, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    struct FreeEv { hipEvent_t a, b; ~FreeEv() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } evg{e0, e1};
+    const int initial = P->bottom_cells;
+    int best_cells = initial;
+    double best_ms = 1e300;
+    for (int ci = 0; ci < NMG_TUNE_CANDIDATES; ci++) {
+        const int cells = kTuneCandidates[ci];
+        nmg_status st = apply_bottom_cells(P, cells);
+        if (st != NMG_OK) return st;
+        P->n_start.assign(P->n, 0);
+        if ((st = plan_begin(P, ws, ws_bytes, U, s)) != NMG_OK) return st;
+        if ((st = plan_steps(P, ws, 1, use_graph, s)) != NMG_OK) return st;   // warm, capture
+        HIP_TRY(hipEventRecord(e0, s));
+        if ((st = plan_steps(P, ws, trial_steps, use_graph, s)) != NMG_OK) return st;
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        const double per = ms / trial_steps;
+        if (times_ms) times_ms[ci] = per;
+        if (per < best_ms) { best_ms = per; best_cells = cells; }
+        for (int k = 0; k < P->n; k++)
+            HIP_TRY(hipMemcpyAsync(U[k], save + off[k], sizeof(double) * (off[k + 1] - off[k]),
+                                   hipMemcpyDeviceToDevice, s));
+    }
+    nmg_status st = apply_bottom_cells(P, best_cells);
+    if (st != NMG_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    if (best) { memset(best, 0, sizeof(*best)); best->bottom_cells = best_cells; }
+    return NMG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -490,9 +571,19 @@ const char *nmg_last_error(void) { return g_err.c_str(); }
 nmg_status nmg_plan_create(const nmg_desc *descs, const nmg_params *params, int32_t n, nmg_plan **out)
 {
     if (!descs || !params || !out) return fail(NMG_EINVAL, "null argument");
+    if (n <= 0) return fail(NMG_EINVAL, "need at least one instance");
     nmg_plan *P = new (std::nothrow) nmg_plan();
     if (!P) return fail(NMG_EINVAL, "out of host memory");
+    P->descs.assign(descs, descs + n);
+    P->params.assign(params, params + n);
+    // the smallest bottom threshold has the most smoothing tiles: reserve for it
+    P->bottom_cells = 256;
     nmg_status st = build_plan(P, descs, params, n);
+    if (st != NMG_OK) { delete P; return st; }
+    P->tile_cap = P->tiles.size();
+    P->bottom_cells = 2048;
+    P->bottom_nt = 1024;
+    st = build_plan(P, descs, params, n);
     if (st != NMG_OK) { delete P; return st; }
     *out = P;
     return NMG_OK;
@@ -529,6 +620,28 @@ nmg_status nmg_plan_profile_read(nmg_plan *P, double *ms, int32_t *launches)
 }
 
 void nmg_plan_destroy(nmg_plan *plan) { delete plan; }
+
+nmg_status nmg_plan_set_options(nmg_plan *P, const nmg_plan_options *opt)
+{
+    if (!P || !opt) return fail(NMG_EINVAL, "null argument");
+    return apply_bottom_cells(P, opt->bottom_cells);
+}
+
+nmg_status nmg_plan_get_options(const nmg_plan *P, nmg_plan_options *opt)
+{
+    if (!P || !opt) return fail(NMG_EINVAL, "null argument");
+    memset(opt, 0, sizeof(*opt));
+    opt->bottom_cells = P->bottom_cells;
+    return NMG_OK;
+}
+
+nmg_status nmg_plan_autotune(nmg_plan *P, void *ws, size_t ws_bytes, double *const *U, int32_t trial_steps,
+                             int32_t use_graph, nmg_plan_options *best, double *times_ms, void *stream)
+{
+    if (!P || !ws) return fail(NMG_EINVAL, "null plan or workspace");
+    return plan_autotune(P, (char *)ws, ws_bytes, U, trial_steps, use_graph, best, times_ms,
+                         (hipStream_t)stream);
+}
 
 nmg_status nmg_plan_begin(nmg_plan *P, void *ws, size_t ws_bytes, double *const *U, void *stream)
 {

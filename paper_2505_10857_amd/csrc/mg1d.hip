@@ -286,10 +286,11 @@ __device__ __forceinline__ void mul2(const double A[4], const double B[4], doubl
 }
 
 // ---- bottom of the V-cycle -----------------------------------------------------------------
-// Every level with at most kBottomCells cells (always including the coarsest) is handled by one
-// 1024-thread workgroup per instance in a single launch: pre-smoothing and restriction down to
-// the coarsest level, the cyclic-reduction solve there, prolongation and post-smoothing back
-// up.  Thread t owns cells t and t + 1024 of every level; dU of the current level lives in LDS,
+// Every level with at most 2 NT cells (always including the coarsest; the plan picks the first
+// such level) is handled by one NT-thread workgroup per instance in a single launch:
+// pre-smoothing and restriction down to the coarsest level, the cyclic-reduction solve there,
+// prolongation and post-smoothing back up.  Thread t owns cells t and t + NT of every level;
+// dU of the current level lives in LDS,
 // the restricted right-hand sides of all levels below the first stay in LDS, and the
 // pre-smoothed dU of each level goes to HBM and comes back to the thread that wrote it.
 // Same arithmetic, in the same order, as the per-level kernels.
@@ -303,13 +304,13 @@ __device__ __forceinline__ void bottom_load(const T *base, const Level1D &L, int
     for (int e = 0; e < 4; e++) D[e] = ld(base + L.Dinv, e * (long long)L.n + c);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBottomThreads) k_bottom(MGArgs mg, const int *inst_list, int zero_init0,
-                                                           int final_update)
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_bottom(MGArgs mg, const int *inst_list, int zero_init0,
+                                               int final_update)
 {
-    constexpr int NT = kBottomThreads;
-    __shared__ double u0[kBottomCells + 2], u1[kBottomCells + 2];   // dU of the current level, index c+1
-    __shared__ double q0[kBottomCells], q1[kBottomCells];           // rhs of the levels below the first
+    static_assert(2 * NT >= kMaxCoarse, "the coarsest level needs one thread per cell");
+    __shared__ double u0[2 * NT + 2], u1[2 * NT + 2];   // dU of the current level, index c+1
+    __shared__ double q0[2 * NT], q1[2 * NT];           // rhs of the levels below the first
     __shared__ double sW[kMaxCoarse][4], sD[kMaxCoarse][4], sE[kMaxCoarse][4], sDi[kMaxCoarse][4];
     const int inst = inst_list[blockIdx.x];
     if (!active_of(mg, inst)) return;
@@ -402,7 +403,12 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(MGArgs mg, const int 
             }
             const double p0 = __shfl_xor(a0, 1, 64), p1 = __shfl_xor(a1, 1, 64);
             if (c < n) {
-                if ((c & 1) == 0) { q0[qn + (c >> 1)] = a0 + p0; q1[qn + (c >> 1)] = a1 + p1; }
+                // rounded to the value type as the tiled kernels round it in HBM, so the result
+                // does not depend on which levels run here
+                if ((c & 1) == 0) {
+                    q0[qn + (c >> 1)] = (double)(T)(a0 + p0);
+                    q1[qn + (c >> 1)] = (double)(T)(a1 + p1);
+                }
                 base[L.dU + c] = (T)du[k][0];
                 base[L.dU + n + (long long)c] = (T)du[k][1];
             }
@@ -499,7 +505,7 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(MGArgs mg, const int 
         for (int k = 0; k < 2; k++) {
             const int c = t + k * NT;
             par[k][0] = par[k][1] = 0.0;
-            if (c < n) { par[k][0] = u0[(c >> 1) + 1]; par[k][1] = u1[(c >> 1) + 1]; }
+            if (c < n) { par[k][0] = (double)(T)u0[(c >> 1) + 1]; par[k][1] = (double)(T)u1[(c >> 1) + 1]; }
         }
         __syncthreads();
         double Jr[2][12], D[2][4], r[2][2], du[2][2];
@@ -583,14 +589,25 @@ hipError_t launch_coarsen1d(const MGArgs &mg, const Tile *tiles, int ntiles, int
     return hipGetLastError();
 }
 
+template <typename T>
+static void launch_bottom_t(const MGArgs &mg, const int *inst_list, int n, int zero_init0, int final_update,
+                            int nt, hipStream_t s)
+{
+    if (nt <= 256)
+        hipLaunchKernelGGL((k_bottom<T, 256>), dim3(n), dim3(256), 0, s, mg, inst_list, zero_init0, final_update);
+    else if (nt <= 512)
+        hipLaunchKernelGGL((k_bottom<T, 512>), dim3(n), dim3(512), 0, s, mg, inst_list, zero_init0, final_update);
+    else
+        hipLaunchKernelGGL((k_bottom<T, 1024>), dim3(n), dim3(1024), 0, s, mg, inst_list, zero_init0, final_update);
+}
+
 hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero_init0, int final_update,
-                         int prec, hipStream_t s)
+                         int prec, int nt, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    if (prec == NMG_FP32_MG)
-        hipLaunchKernelGGL(k_bottom<float>, dim3(n), dim3(kBottomThreads), 0, s, mg, inst_list, zero_init0, final_update);
-    else
-        hipLaunchKernelGGL(k_bottom<double>, dim3(n), dim3(kBottomThreads), 0, s, mg, inst_list, zero_init0, final_update);
+    if (nt != 256 && nt != 512 && nt != 1024) return hipErrorInvalidValue;
+    if (prec == NMG_FP32_MG) launch_bottom_t<float>(mg, inst_list, n, zero_init0, final_update, nt, s);
+    else launch_bottom_t<double>(mg, inst_list, n, zero_init0, final_update, nt, s);
     return hipGetLastError();
 }
 

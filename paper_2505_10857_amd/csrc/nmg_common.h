@@ -13,8 +13,7 @@ constexpr int kTile = 256;        // threads (= cells) per 1D tile
 constexpr int kCoarsenCells = 4;  // level-l0 cells per thread in the coarsening kernel
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 256;   // cells on the coarsest 1D level (one thread per cell)
-constexpr int kBottomThreads = 1024;          // threads of the bottom-of-cycle kernel
-constexpr int kBottomCells = 2 * kBottomThreads;  // largest level it handles
+constexpr int kBottomCellsMax = 2048;  // largest level the bottom-of-cycle kernel handles
 constexpr double kZeta = 1e-6;    // WENO epsilon of eq. (8)
 
 // One 1D instance as the kernels see it.
@@ -104,8 +103,9 @@ hipError_t launch_jacobian1d(const Inst1D *insts_dev, const Tile *tiles, int nti
                              const Inst1D *single, double *J_single, const MGArgs &mg, int prec,
                              int nb_mask, hipStream_t s);
 hipError_t launch_coarsen1d(const MGArgs &mg, const Tile *tiles, int ntiles, int prec, hipStream_t s);
+// nt: threads of the bottom workgroup (256, 512 or 1024); it handles levels of up to 2 nt cells
 hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero_init0, int final_update,
-                         int prec, hipStream_t s);
+                         int prec, int nt, hipStream_t s);
 hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_max, int mode,
                            int zero_init, int final_update, int prec, hipStream_t s);
 hipError_t launch_convert(const void *src, int src_prec, void *dst, int dst_prec, long long n,

@@ -439,10 +439,12 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs, 
             recon_Q(Q, base);
             S0 = source_term(base.Hp_ll, base.Hp_l, base.Hm_r, base.Hm_rr, G, W, I.dx, I.g);
         }
+#pragma unroll 1
         for (int b = 0; b < NB; b++) {
             const int i = j + b - HW;
             const bool col_ok = i >= 0 && i < I.N;
             const int pp = 2 + b - HW;  // stencil position of the perturbed cell
+#pragma unroll 1
             for (int m = 0; m < 2; m++) {
                 double e0 = 0.0, e1 = 0.0;
                 if (col_ok) {
