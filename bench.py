@@ -33,8 +33,14 @@ FP64_VECTOR_TFLOPS = 78.6
 # two-point Gauss source (36) and the final differences (3).
 FLOPS_LOCAL_RESIDUAL = 10 * 22 + 2 * 46 + 36 + 3
 # Algorithmic HBM bytes per cell and launch (FP64, J3):
-#   Jacobian: read U 16, R 16, rn 8, geometry 7*8 = 56; write J 96 and rhs 16
-BYTES_JACOBIAN_J3 = 16 + 16 + 8 + 56 + 96 + 16
+#   Jacobian: read U 16, R 16, rn 8, geometry 7*8 = 56; write J 96, rhs 16, D^-1 32 and the
+#   coarse operators (J 96 + D^-1 32 per coarse cell) of the eight levels built inside its tile
+#   (sum over l = 1..8 of 2^-l coarse cells per fine cell)
+BYTES_JACOBIAN_J3 = 16 + 16 + 8 + 56 + 96 + 16 + 32 + 128 * (1.0 - 2.0 ** -8)
+# HBM traffic of the Jacobian kernel measured with rocprofv3 counters (profiles/), valid while
+# the kernel source is the one it was measured on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobian_j3_fp64_hump12800_batch256_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2505_10857_amd", "csrc", "swe1d.hip")
 #   finest pre-smoothing: read J 96, Dinv 32, rhs 16; write dU 16 and the restricted rhs 8 per
 #   fine cell; plus a read of dU 16 in the second of the two cycles (average 8)
 BYTES_SMOOTH_PRE_J3 = 96 + 32 + 16 + 16 + 8 + 8
@@ -56,9 +62,40 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-instances", type=int, default=3)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device copy first (counter calibration under rocprofv3)")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-budget-gib", type=int, default=16)
     return ap.parse_args()
+
+
+def measured_traffic(batch, n):
+    """HBM bytes per launch of the Jacobian kernel from the committed counter summary, or None
+    if there is none for this workload or the kernel source changed since it was taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != sha or kv.get("cells") != str(batch * n):
+        return None
+    return float(kv["bytes_per_launch"])
+
+
+def calibration_copy():
+    """One device-to-device copy of 256 MiB (the reference dispatch for scaling the FETCH_SIZE
+    and WRITE_SIZE counters to bytes)."""
+    import torch
+    src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def make_batch(B, n, levels, variant):
@@ -142,6 +179,8 @@ def main():
     from paper_2505_10857_amd import _abi as A
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibration_copy()
     use_graph = not args.no_graph
     probs = make_batch(args.batch, args.n, args.levels, args.variant)
     solver = BatchSolver1D(probs, device="cuda:0", jac=3, precision=NMG_FP64)
@@ -184,7 +223,7 @@ def main():
         "bound": "alu", "achieved": jac_flops / (jac_ms * 1e-3) / 1e12,
         "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": jac_flops / (jac_ms * 1e-3) / 1e12 / FP64_VECTOR_TFLOPS,
-        "traffic": None,
+        "traffic": measured_traffic(args.batch, args.n),
         "avg_launch_ms": jac_ms, "launches_timed": jcnt,
         "algorithmic_flops_per_launch": jac_flops,
         "hbm_gbs": cells * BYTES_JACOBIAN_J3 / (jac_ms * 1e-3) / 1e9,
