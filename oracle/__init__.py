@@ -100,6 +100,7 @@ def _declare(L):
     L.or1d_restrict.argtypes = [vp, C.c_int]
     L.or1d_prolong.argtypes = [vp, C.c_int]
     L.or1d_coarse_solve.argtypes = [vp, C.c_int]
+    L.or1d_interp_a2.argtypes = [C.c_int, _dp, _dp]
     L.or1d_vcycle.argtypes = [vp, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int]
     if hasattr(L, "or2d_residual"):
         from . import swe2d as _s2
@@ -249,3 +250,34 @@ def blocks_to_dense(J: np.ndarray) -> np.ndarray:
             if 0 <= i < n:
                 A[2 * j:2 * j + 2, 2 * i:2 * i + 2] = J[j, b]
     return A
+
+
+def interp_a2(Uc: np.ndarray) -> np.ndarray:
+    """Fine-grid cell averages from a coarse solution [2, nc] (Appendix A, eq. A.1-A.2)."""
+    Uc = np.ascontiguousarray(Uc, dtype=np.float64)
+    nc = Uc.shape[1]
+    if nc < 3:
+        raise ValueError("the interpolation needs at least three coarse cells")
+    Uf = np.empty((2, 2 * nc))
+    lib().or1d_interp_a2(nc, ptr(Uc), ptr(Uf))
+    return Uf
+
+
+def nested_solve(prob, ngrids=None, U0=None, nb=3, **over):
+    """Algorithm 3: Newton with a direct linear solve on the coarsest grid (N / 2^(ngrids-1)
+    cells) from the problem's initial guess there, then on each finer grid l the Newton
+    multigrid iteration with ngrids - l levels from the Appendix A interpolation of the coarser
+    solution.  Returns (U on the finest grid, [(cells, Newton steps, res) per grid, coarsest
+    first])."""
+    from swe_workloads import nested_grids
+    grids = nested_grids(prob, ngrids)
+    ng = len(grids)
+    U = grids[-1].initial_guess() if U0 is None else np.ascontiguousarray(U0, dtype=np.float64)
+    report = []
+    for g in range(ng - 1, -1, -1):
+        if g < ng - 1:
+            U = interp_a2(U)
+        Ug, it, res, _ = Oracle1D(grids[g]).newton_solve(U0=U, nb=nb, levels=ng - g, **over)
+        report.append((grids[g].n, it, res))
+        U = Ug
+    return U, report

@@ -615,3 +615,35 @@ void or1d_smooth_only(int N, int nb, const double *J, const double *rhs, double 
     memcpy(dU, mg->dU[0], sizeof(double) * 2 * N);
     or1d_mg_free(mg);
 }
+
+/* Appendix A, eq. (A.1)-(A.2): initial cell averages of the level-l grid from the coarser
+ * level-(l+1) solution (Algorithm 3, step 9).  Uc is [2][nc], Uf is [2][2 nc]; children 2j and
+ * 2j+1 (0-based) of coarse cell j.  Interior cells take eq. (A.2) as printed.  Reading (the
+ * appendix is silent at the ends): the first and last coarse cells take the quadratic (A.1)
+ * centred one cell inward, averaged over their two halves (still conservative and exact for
+ * quadratics).  Needs nc >= 3. */
+void or1d_interp_a2(int nc, const double *Uc, double *Uf)
+{
+    const int nf = 2 * nc;
+    for (int c = 0; c < 2; c++) {
+        const double *u = Uc + (size_t)c * nc;
+        double *v = Uf + (size_t)c * nf;
+        for (int j = 0; j < nc; j++) {
+            if (j >= 1 && j <= nc - 2) {
+                v[2 * j] = u[j - 1] / 8.0 + u[j] - u[j + 1] / 8.0;
+                v[2 * j + 1] = -u[j - 1] / 8.0 + u[j] + u[j + 1] / 8.0;
+            } else {
+                const int k = j == 0 ? 1 : nc - 2;
+                /* P(xi) = u_k + a xi + b (xi^2 - 1/12), xi = (x - x_k) / dx_coarse */
+                const double a = (u[k + 1] - u[k - 1]) / 2.0;
+                const double b = (u[k - 1] - 2.0 * u[k] + u[k + 1]) / 2.0;
+                for (int half = 0; half < 2; half++) {
+                    const double lo = (double)(j - k) - 0.5 + 0.5 * half, hi = lo + 0.5;
+                    const double m1 = (lo + hi) / 2.0;                      /* mean of xi   */
+                    const double m2 = (lo * lo + lo * hi + hi * hi) / 3.0;  /* mean of xi^2 */
+                    v[2 * j + half] = u[k] + a * m1 + b * (m2 - 1.0 / 12.0);
+                }
+            }
+        }
+    }
+}

@@ -284,6 +284,24 @@ def config4_instance(i: int, n_min: int = 256, n_max: int = 16384):
     return _uneven_instance(np.random.default_rng([4, i]), f"cfg4[{i}]", n_min, n_max)
 
 
+def nested_grids(prob, ngrids: Optional[int] = None):
+    """The grids of the nested iteration (Algorithm 3) for a 1D problem: grid g (g = 0 the
+    problem itself) has N / 2^g cells and levels - g multigrid levels, the same channel,
+    boundary data and solver parameters, and the perturbation of the grid-size table for its
+    own size (eps_for_n, except that the finest grid keeps the problem's).  ngrids defaults to
+    the problem's number of levels."""
+    ng = prob.levels if ngrids is None else ngrids
+    if ng < 1 or ng > prob.levels or prob.n % (1 << (ng - 1)):
+        raise ValueError("ngrids must be in [1, levels] and divide the grid")
+    out = []
+    for g in range(ng):
+        n = prob.n >> g
+        p = prob.params if g == 0 else dataclasses.replace(prob.params, eps=eps_for_n(n))
+        out.append(dataclasses.replace(prob, name=f"{prob.name}/{n}", n=n, levels=prob.levels - g,
+                                       params=p))
+    return out
+
+
 def served_request(i: int, seed: int = 0, n_min: int = 512, n_max: int = 32768):
     """Request i of a served stream: a 1D channel drawn like the uneven-batch instances (size
     log-uniform in [n_min, n_max], bump amplitude, discharge, outflow depth, width) from
