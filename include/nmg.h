@@ -66,7 +66,8 @@ typedef struct {
  *   the bottom side is EXTRAP for x < wall_x and WALL beyond when bc[2].kind == NMG_BC_WALL
  *   and wall_x > x0.  bx_gp, by_gp [ny][nx][2][2]: b_x, b_y at the tensor Gauss points
  *   (y point beta, x point gamma) of each cell.
- * levels = L + 1 grid levels (eq. 15 / 23): nx (and ny) must be divisible by 2^(levels-1).
+ * levels = L + 1 grid levels (eq. 15 / 23): nx (and ny) must be divisible by 2^(levels-1);
+ *   levels = 1 (1D, jac = 3) solves the regularised system directly (Algorithm 3, step 4).
  * jac = 3 or 5 (1D), 9 (2D): which Jacobian blocks are assembled (section 3.3 / 4.1). */
 typedef struct {
     int32_t dim, nx, ny, levels, jac, pad;
@@ -134,6 +135,24 @@ nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *w
 nmg_status nmg_newton_solve(const nmg_desc *desc, const nmg_params *params, void *ws,
                             size_t ws_bytes, double *U, nmg_stats *stats, double *hist,
                             int32_t max_hist, void *stream);
+
+/* ---- nested iteration (Algorithm 3, Appendix A) -----------------------------------------
+ * nmg_interp_coarse_to_fine: the initial cell averages of a 1D grid from the solution on the
+ * grid with half as many cells, eq. (A.1)-(A.2): Uc [2][nc] -> Uf [2][2 nc] (device).  The
+ * first and last coarse cells (the appendix is silent there) average over their halves the
+ * quadratic (A.1) of the neighbouring interior cell.  nc >= 3.
+ * nmg_nested_solve: Algorithm 3 on a 1D problem given on ngrids nested grids: descs[g] and
+ * params[g] describe grid g (g = 0 the finest; grid g has half the cells of grid g-1 and
+ * ngrids - g levels, so the coarsest grid is solved by Newton with the direct coarsest solve).
+ * U[g] (device, [2][nx_g]) is grid g's state: U[ngrids-1] holds the initial guess on entry;
+ * every other grid starts from the interpolation of the next coarser solution.  stats[g]
+ * (host) receives each grid's Newton statistics.  Returns the finest grid's status
+ * (NMG_ENONFINITE as soon as a grid breaks down).  The workspace must hold
+ * nmg_nested_workspace_bytes() (the largest grid's).  Synchronises `stream`. */
+nmg_status nmg_interp_coarse_to_fine(const double *Uc, int32_t nc, double *Uf, void *stream);
+size_t nmg_nested_workspace_bytes(const nmg_desc *descs, int32_t ngrids, const nmg_params *params);
+nmg_status nmg_nested_solve(const nmg_desc *descs, int32_t ngrids, const nmg_params *params, void *ws,
+                            size_t ws_bytes, double *const *U, nmg_stats *stats, void *stream);
 
 /* ---- batched form: many independent 1D instances (any sizes) per launch ----------------
  * A plan fixes n instances (descs/params host arrays of length n) and the workspace layout.

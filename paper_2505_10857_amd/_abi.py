@@ -31,7 +31,8 @@ EXPORTS = [
     "nmg_newton_solve", "nmg_plan_create", "nmg_plan_workspace_bytes", "nmg_plan_solve",
     "nmg_plan_begin", "nmg_plan_steps", "nmg_plan_destroy", "nmg_last_error",
     "nmg_plan_profile", "nmg_plan_profile_read", "nmg_plan_resume", "nmg_plan_set_options",
-    "nmg_plan_get_options", "nmg_plan_autotune",
+    "nmg_plan_get_options", "nmg_plan_autotune", "nmg_interp_coarse_to_fine",
+    "nmg_nested_workspace_bytes", "nmg_nested_solve",
 ]
 
 NMG_K_NONE = 0
@@ -108,6 +109,10 @@ def load(path: str = LIB_PATH):
     L.nmg_plan_begin.argtypes = [vp, vp, sz, P(vp), vp]
     L.nmg_plan_steps.argtypes = [vp, vp, C.c_int32, C.c_int32, P(C.c_int32), P(nmg_stats), vp]
     L.nmg_plan_resume.argtypes = [vp, vp, sz, P(vp), P(C.c_int32), vp]
+    L.nmg_interp_coarse_to_fine.argtypes = [vp, C.c_int32, vp, vp]
+    L.nmg_nested_workspace_bytes.argtypes = [P(nmg_desc), C.c_int32, P(nmg_params)]
+    L.nmg_nested_workspace_bytes.restype = sz
+    L.nmg_nested_solve.argtypes = [P(nmg_desc), C.c_int32, P(nmg_params), vp, sz, P(vp), P(nmg_stats), vp]
     L.nmg_plan_set_options.argtypes = [vp, P(nmg_plan_options)]
     L.nmg_plan_get_options.argtypes = [vp, P(nmg_plan_options)]
     L.nmg_plan_autotune.argtypes = [vp, vp, sz, P(vp), C.c_int32, C.c_int32, P(nmg_plan_options),
@@ -123,7 +128,7 @@ def load(path: str = LIB_PATH):
     for nm in ("nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",
                "nmg_newton_solve", "nmg_plan_create", "nmg_plan_solve", "nmg_plan_begin",
                "nmg_plan_steps", "nmg_plan_resume", "nmg_plan_set_options", "nmg_plan_get_options",
-               "nmg_plan_autotune"):
+               "nmg_plan_autotune", "nmg_interp_coarse_to_fine", "nmg_nested_solve"):
         getattr(L, nm).restype = C.c_int32
     _lib = L
     return L

@@ -43,7 +43,9 @@ nmg_status check_desc1d(const nmg_desc *d, const nmg_params *p, bool need_geomet
     if (!d || !p) return fail(NMG_EINVAL, "null desc or params");
     if (d->dim != 1) return fail(NMG_EINVAL, "only dim = 1 is handled by this entry point");
     if (d->nx < 4) return fail(NMG_EINVAL, "nx must be >= 4");
-    if (d->levels < 2 || d->levels > kMaxLevels) return fail(NMG_EINVAL, "levels must be in [2, 16]");
+    if (d->levels < 1 || d->levels > kMaxLevels) return fail(NMG_EINVAL, "levels must be in [1, 16]");
+    if (d->levels == 1 && d->jac != 3)
+        return fail(NMG_EINVAL, "a one-level hierarchy (direct solve) needs the three-block Jacobian");
     if (d->nx % (1 << (d->levels - 1)) != 0)
         return fail(NMG_EINVAL, "nx must be divisible by 2^(levels-1)");
     if ((d->nx >> (d->levels - 1)) > kMaxCoarse)
@@ -801,6 +803,51 @@ nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *w
     HIP_TRY(launch_convert(mgb + vsz * L0.dU, P.prec, dU, P.prec, 2 * n0, s));
     HIP_TRY(hipStreamSynchronize(s));   // the pinned table staging belongs to this call's plan
     return NMG_OK;
+}
+
+nmg_status nmg_interp_coarse_to_fine(const double *Uc, int32_t nc, double *Uf, void *stream)
+{
+    if (!Uc || !Uf) return fail(NMG_EINVAL, "null argument");
+    if (nc < 3) return fail(NMG_EINVAL, "the interpolation needs at least three coarse cells");
+    HIP_TRY(launch_interp_a2(Uc, nc, Uf, (hipStream_t)stream));
+    return NMG_OK;
+}
+
+size_t nmg_nested_workspace_bytes(const nmg_desc *descs, int32_t ngrids, const nmg_params *params)
+{
+    if (!descs || !params || ngrids < 1 || ngrids > kMaxLevels) return 0;
+    size_t m = 0;
+    for (int g = 0; g < ngrids; g++) {
+        const size_t b = nmg_workspace_bytes(&descs[g], &params[g]);
+        if (b == 0) return 0;
+        m = std::max(m, b);
+    }
+    return m;
+}
+
+nmg_status nmg_nested_solve(const nmg_desc *descs, int32_t ngrids, const nmg_params *params, void *ws,
+                            size_t ws_bytes, double *const *U, nmg_stats *stats, void *stream)
+{
+    if (!descs || !params || !ws || !U || !stats) return fail(NMG_EINVAL, "null argument");
+    if (ngrids < 1 || ngrids > kMaxLevels) return fail(NMG_EINVAL, "ngrids must be in [1, 16]");
+    for (int g = 0; g < ngrids; g++) {
+        if (descs[g].dim != 1) return fail(NMG_EINVAL, "nested iteration is one-dimensional");
+        if (!U[g]) return fail(NMG_EINVAL, "null state pointer");
+        if (g > 0 && descs[g].nx * 2 != descs[g - 1].nx)
+            return fail(NMG_EINVAL, "grid g must have half the cells of grid g-1");
+        if (descs[g].levels != ngrids - g) return fail(NMG_EINVAL, "grid g must have ngrids - g levels");
+    }
+    if (ws_bytes < nmg_nested_workspace_bytes(descs, ngrids, params))
+        return fail(NMG_ENOMEM_WS, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    for (int g = ngrids - 1; g >= 0; g--) {
+        if (g < ngrids - 1) HIP_TRY(launch_interp_a2(U[g + 1], descs[g + 1].nx, U[g], s));
+        const nmg_status st = nmg_newton_solve(&descs[g], &params[g], ws, ws_bytes, U[g], &stats[g],
+                                               nullptr, 0, stream);
+        if (st < 0 && st != NMG_ENONFINITE) return st;
+        if (stats[g].status == NMG_ENONFINITE) return fail(NMG_ENONFINITE, "grid " + std::to_string(g) + " diverged");
+    }
+    return stats[0].status;
 }
 
 nmg_status nmg_newton_solve(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,

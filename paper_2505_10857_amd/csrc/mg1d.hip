@@ -484,7 +484,10 @@ __global__ void __launch_bounds__(NT) k_bottom(MGArgs mg, const int *inst_list, 
             const double x1 = Di[2] * b0 + Di[3] * b1;
             u0[t + 1] = x0;
             u1[t + 1] = x1;
-            if (li == lb) {   // a one-level bottom (the whole hierarchy is the coarsest level)
+            if (li == I.lev0 && final_update) {   // one-level hierarchy: the Newton update, eq. (14)
+                I.U[t] = I.U[t] + I.tau * x0;
+                I.U[I.N + t] = I.U[I.N + t] + I.tau * x1;
+            } else if (li == lb) {   // the bottom is the coarsest level only
                 base[L.dU + t] = (T)x0;
                 base[L.dU + n + (long long)t] = (T)x1;
             }
@@ -567,6 +570,41 @@ __global__ void __launch_bounds__(NT) k_bottom(MGArgs mg, const int *inst_list, 
             }
         }
     }
+}
+
+// Initial cell averages of a grid from the solution on the grid with half as many cells
+// (Appendix A, eq. A.1-A.2), both components; one thread per coarse cell.  Interior cells use
+// eq. (A.2); the first and last coarse cells average, over their two halves, the quadratic
+// (A.1) of the neighbouring interior cell.
+__global__ void k_interp_a2(const double *Uc, int nc, double *Uf)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j >= nc) return;
+    const double *u = Uc + (long long)c * nc;
+    double *v = Uf + (long long)c * 2 * nc;
+    if (j >= 1 && j <= nc - 2) {
+        v[2 * j] = u[j - 1] / 8.0 + u[j] - u[j + 1] / 8.0;
+        v[2 * j + 1] = -u[j - 1] / 8.0 + u[j] + u[j + 1] / 8.0;
+        return;
+    }
+    const int k = j == 0 ? 1 : nc - 2;          // centre of the quadratic used
+    const double a = (u[k + 1] - u[k - 1]) / 2.0;
+    const double b = (u[k - 1] - 2.0 * u[k] + u[k + 1]) / 2.0;
+#pragma unroll
+    for (int half = 0; half < 2; half++) {
+        // this half of cell j spans xi in [lo, hi], xi = (x - x_k) / dx of the coarse grid
+        const double lo = (double)(j - k) - 0.5 + 0.5 * half, hi = lo + 0.5;
+        const double m1 = (lo + hi) / 2.0;
+        const double m2 = (lo * lo + lo * hi + hi * hi) / 3.0;
+        v[2 * j + half] = u[k] + a * m1 + b * (m2 - 1.0 / 12.0);
+    }
+}
+
+hipError_t launch_interp_a2(const double *Uc, int nc, double *Uf, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_interp_a2, dim3((nc + 255) / 256, 2), dim3(256), 0, s, Uc, nc, Uf);
+    return hipGetLastError();
 }
 
 template <typename S, typename D>

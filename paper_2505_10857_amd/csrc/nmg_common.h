@@ -110,6 +110,8 @@ hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int 
                            int zero_init, int final_update, int prec, hipStream_t s);
 hipError_t launch_convert(const void *src, int src_prec, void *dst, int dst_prec, long long n,
                           hipStream_t s);
+// Appendix A interpolation of a 1D state [2][nc] to [2][2 nc]
+hipError_t launch_interp_a2(const double *Uc, int nc, double *Uf, hipStream_t s);
 
 // 2D
 int residual2d_tiles(int Nx, int Ny);

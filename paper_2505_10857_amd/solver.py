@@ -354,3 +354,37 @@ class Solver2D:
         A.check(status, ok=(A.NMG_OK, A.NMG_NOT_CONVERGED, A.NMG_ENONFINITE))
         h = np.array(hist[:min(max_hist, st.iters)]) if max_hist > 0 else np.zeros(0)
         return st, h
+
+
+def interp_coarse_to_fine(Uc: torch.Tensor) -> torch.Tensor:
+    """Appendix A interpolation of a device state [2, nc] to [2, 2 nc]."""
+    Uc = Uc.contiguous()
+    Uf = torch.empty((2, 2 * Uc.shape[1]), dtype=torch.float64, device=Uc.device)
+    A.check(A.load().nmg_interp_coarse_to_fine(_dptr(Uc), Uc.shape[1], _dptr(Uf), C.c_void_p(_stream_ptr())))
+    return Uf
+
+
+def nested_solve(prob, ngrids: Optional[int] = None, device="cuda", precision: int = A.NMG_FP64,
+                 check_every: int = 4):
+    """Algorithm 3 on the GPU for a 1D problem: Newton with the direct solve on the coarsest of
+    the nested grids (from the problem's initial guess there), then the Newton multigrid
+    iteration on every finer grid from the interpolated coarser solution.  Returns (finest
+    state [2, N] on the device, [(cells, Newton steps, status, res) per grid, finest first])."""
+    from swe_workloads import nested_grids
+    grids = nested_grids(prob, ngrids)
+    ng = len(grids)
+    devs = [Problem1DDevice(g, device, 3) for g in grids]
+    descs = (A.nmg_desc * ng)(*[d.desc for d in devs])
+    params = (A.nmg_params * ng)(*[params_struct(g.params, precision, check_every) for g in grids])
+    Us = [torch.empty((2, g.n), dtype=torch.float64, device=device) for g in grids]
+    Us[-1].copy_(torch.tensor(np.ascontiguousarray(grids[-1].initial_guess()), dtype=torch.float64))
+    L = A.load()
+    nbytes = L.nmg_nested_workspace_bytes(descs, ng, params)
+    if nbytes == 0:
+        raise A.NmgError(A.NMG_EINVAL, L.nmg_last_error().decode())
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    ptrs = (C.c_void_p * ng)(*[u.data_ptr() for u in Us])
+    stats = (A.nmg_stats * ng)()
+    st = L.nmg_nested_solve(descs, ng, params, _dptr(ws), nbytes, ptrs, stats, C.c_void_p(_stream_ptr()))
+    A.check(st, ok=(A.NMG_OK, A.NMG_NOT_CONVERGED, A.NMG_ENONFINITE))
+    return Us[0], [(g.n, s.iters, s.status, s.res) for g, s in zip(grids, stats)]

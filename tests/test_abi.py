@@ -62,11 +62,14 @@ def test_workspace_query_and_argument_checks():
     assert L.nmg_workspace_bytes(ctypes.byref(d), ctypes.byref(p)) > 0
     bad = [dict(nx=60, levels=4),      # not divisible by 2^(levels-1)
            dict(nx=4096, levels=2),    # coarsest level too large
-           dict(jac=4), dict(levels=1)]
+           dict(jac=4), dict(levels=0),
+           dict(levels=1, jac=5)]      # the direct one-level solve is block-tridiagonal
     for kw in bad:
         d2, p2 = _desc(abi, **kw)
         assert L.nmg_workspace_bytes(ctypes.byref(d2), ctypes.byref(p2)) == 0
         assert L.nmg_last_error()
+    d1, p1 = _desc(abi, nx=128, levels=1)   # one level: Newton with the direct solve
+    assert L.nmg_workspace_bytes(ctypes.byref(d1), ctypes.byref(p1)) > 0
     d3, p3 = _desc(abi)
     p3.eps = 0.0
     assert L.nmg_workspace_bytes(ctypes.byref(d3), ctypes.byref(p3)) == 0
@@ -91,3 +94,24 @@ def test_plan_rejects_mixed_precision():
     assert L.nmg_plan_create(descs, params, 2, ctypes.byref(plan)) == abi.NMG_OK
     assert L.nmg_plan_workspace_bytes(plan) > L.nmg_workspace_bytes(ctypes.byref(d1), ctypes.byref(p1))
     L.nmg_plan_destroy(plan)
+
+
+def test_nested_solve_argument_checks():
+    """Grid g of the nested iteration must have half the cells of grid g-1 and ngrids - g levels;
+    the checks run on the host before any launch."""
+    abi, L = _lib()
+    grids = [_desc(abi, nx=256 >> g, levels=3 - g) for g in range(3)]
+    descs = (abi.nmg_desc * 3)(*[g[0] for g in grids])
+    params = (abi.nmg_params * 3)(*[g[1] for g in grids])
+    ws = L.nmg_nested_workspace_bytes(descs, 3, params)
+    assert ws == max(L.nmg_workspace_bytes(ctypes.byref(d), ctypes.byref(p)) for d, p in grids)
+    U = (ctypes.c_void_p * 3)(256, 512, 768)
+    st = (abi.nmg_stats * 3)()
+    descs[1].levels = 3
+    assert L.nmg_nested_solve(descs, 3, params, ctypes.c_void_p(1024), ws, U, st, None) == abi.NMG_EINVAL
+    descs[1].levels = 2
+    descs[2].nx = 48
+    assert L.nmg_nested_solve(descs, 3, params, ctypes.c_void_p(1024), ws, U, st, None) == abi.NMG_EINVAL
+    descs[2].nx = 64
+    assert L.nmg_nested_solve(descs, 3, params, ctypes.c_void_p(1024), 16, U, st, None) == abi.NMG_ENOMEM_WS
+    assert L.nmg_interp_coarse_to_fine(ctypes.c_void_p(256), 2, ctypes.c_void_p(512), None) == abi.NMG_EINVAL

@@ -1,0 +1,60 @@
+"""Nested iteration (Algorithm 3) on the GPU against the oracle: the Appendix A interpolation,
+Newton with the direct coarsest solve (one-level hierarchy), and the whole nested solve on the
+subcritical and transcritical humps (the latter is out of reach of plain Newton from the flat
+surface)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from swe_workloads import config2  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_interpolation_parity():
+    from paper_2505_10857_amd.solver import interp_coarse_to_fine
+    rng = np.random.default_rng(17)
+    for nc in (3, 4, 100, 1603):
+        Uc = rng.uniform(0.3, 3.0, (2, nc))
+        Uf = interp_coarse_to_fine(torch.tensor(Uc, device=DEV)).cpu().numpy()
+        ref = oracle.interp_a2(Uc)
+        print(nc, np.abs(Uf - ref).max(), np.array_equal(Uf, ref))
+        assert np.abs(Uf - ref).max() <= 1e-15 * np.abs(ref).max()
+
+
+def test_one_level_newton_is_the_direct_solve():
+    from paper_2505_10857_amd import Solver1D
+    for variant in ("sub", "trans"):
+        prob = config2(0, variant, n=100, levels=1)
+        s = Solver1D(prob, device=DEV)
+        U = s.state()
+        st, _ = s.newton_solve(U)
+        Uo, ito, reso, _ = oracle.Oracle1D(prob).newton_solve()
+        err = np.abs(U.cpu().numpy() - Uo).max()
+        print(variant, st.iters, ito, st.res, err)
+        assert st.status == 0 and abs(st.iters - ito) <= 1
+        assert err <= 1e-10
+
+
+@pytest.mark.parametrize("variant,n,levels", [("sub", 800, 4), ("trans", 3200, 6), ("trans", 12800, 8)])
+def test_nested_solve_matches_the_oracle(variant, n, levels):
+    from paper_2505_10857_amd.solver import nested_solve
+    prob = config2(0, variant, n=n, levels=levels)
+    U, rep = nested_solve(prob, device=DEV)
+    Uo, rep_o = oracle.nested_solve(prob)
+    err = np.abs(U.cpu().numpy() - Uo).max()
+    print(variant, n, "gpu", [(r[0], r[1]) for r in rep], "oracle", [(r[0], r[1]) for r in rep_o[::-1]],
+          f"|dU| {err:.2e}")
+    assert all(r[2] == 0 for r in rep)
+    for (ng, it, _, _), (no, ito, _) in zip(rep, rep_o[::-1]):
+        assert ng == no and abs(it - ito) <= 1
+    assert err <= 1e-10
