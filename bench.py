@@ -98,6 +98,11 @@ def calibration_copy():
     del src, dst
 
 
+def config2(i, variant, n, levels):
+    from swe_workloads import config2 as c2
+    return c2(i, variant, n=n, levels=levels)
+
+
 def make_batch(B, n, levels, variant):
     from swe_workloads import config2
     return [config2(i, variant, n=n, levels=levels) for i in range(B)]
@@ -261,6 +266,25 @@ def main():
                                     "newton_steps": [min(s[0] for s in st32[-1]), max(s[0] for s in st32[-1])],
                                     "max_abs_diff_vs_fp64_gpu": err,
                                     "converged": all(s[1] == 0 and s[2] < 1e-10 for st in st32 for s in st)}
+        # transcritical hump (q = 1.53, h_out = 0.66): out of reach of plain Newton from the flat
+        # surface; nested iteration (Algorithm 3) over the 8 grids 100 .. 12800, batched per grid
+        from paper_2505_10857_amd.solver import NestedBatch
+        tprobs = [config2(i, "trans", n=args.n, levels=args.levels) for i in range(args.batch)]
+        nb_ = NestedBatch(tprobs, device="cuda:0", precision=NMG_FP64)
+        sets = [nb_.states() for _ in range(3)]
+        torch.cuda.synchronize()
+        nb_.solve(sets[0], use_graph)                 # warmup (captures the graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = [nb_.solve(sets[k], use_graph) for k in (1, 2)]
+        torch.cuda.synchronize()
+        et = time.perf_counter() - t0
+        fin = rep[-1][-1]
+        forms["fp64_batch_trans_nested"] = {
+            "solves_per_s": 2 * args.batch / et, "batch": args.batch,
+            "newton_steps_finest": [min(x[0] for x in fin), max(x[0] for x in fin)],
+            "newton_steps_per_grid_instance0": [r[0][0] for r in rep[-1]],
+            "converged": all(x[1] == 0 and x[2] < 1e-10 for x in fin)}
         # uneven batch: 512 instances, N log-uniform in [256, 16384], FP32 multigrid, one plan
         from swe_workloads import config4_instance
         uprobs = [config4_instance(i) for i in range(512)]

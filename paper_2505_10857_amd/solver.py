@@ -388,3 +388,43 @@ def nested_solve(prob, ngrids: Optional[int] = None, device="cuda", precision: i
     st = L.nmg_nested_solve(descs, ng, params, _dptr(ws), nbytes, ptrs, stats, C.c_void_p(_stream_ptr()))
     A.check(st, ok=(A.NMG_OK, A.NMG_NOT_CONVERGED, A.NMG_ENONFINITE))
     return Us[0], [(g.n, s.iters, s.status, s.res) for g, s in zip(grids, stats)]
+
+
+class NestedBatch:
+    """Algorithm 3 for a batch of 1D problems on the same nested grids: one batched plan per
+    grid (every launch covers every instance), the Appendix A interpolation between grids.
+    Each instance's result equals its own nested solve (no cross-instance arithmetic)."""
+
+    def __init__(self, probs: Sequence, ngrids: Optional[int] = None, device="cuda",
+                 precision: int = A.NMG_FP64, check_every: int = 4):
+        from swe_workloads import nested_grids
+        A.load()
+        self.grids = [nested_grids(p, ngrids) for p in probs]      # [instance][grid]
+        ng = len(self.grids[0])
+        if any(len(g) != ng or g[0].n != self.grids[0][0].n for g in self.grids):
+            raise ValueError("all problems of a nested batch need the same grids")
+        self.ng = ng
+        self.n = len(probs)
+        self.device = device
+        self.plans = [BatchSolver1D([g[k] for g in self.grids], device=device, precision=precision,
+                                    check_every=check_every) for k in range(ng)]
+
+    def states(self):
+        """Fresh per-grid state buffers with the coarsest initial guesses filled in."""
+        Us = [[torch.empty((2, g[k].n), dtype=torch.float64, device=self.device) for g in self.grids]
+              for k in range(self.ng)]
+        for i, g in enumerate(self.grids):
+            Us[-1][i].copy_(torch.tensor(np.ascontiguousarray(g[-1].initial_guess()), dtype=torch.float64))
+        return Us
+
+    def solve(self, Us, use_graph: bool = True):
+        """Returns per grid (coarsest first) the list of (iters, status, res) per instance;
+        Us[0] holds the finest solutions afterwards."""
+        out = []
+        for k in range(self.ng - 1, -1, -1):
+            if k < self.ng - 1:
+                for i in range(self.n):
+                    A.check(A.load().nmg_interp_coarse_to_fine(
+                        _dptr(Us[k + 1][i]), Us[k + 1][i].shape[1], _dptr(Us[k][i]), C.c_void_p(_stream_ptr())))
+            out.append(self.plans[k].solve(Us[k], use_graph=use_graph))
+        return out

@@ -195,8 +195,8 @@ def sine_width(kw: int, length: float = 25.0, amp: float = 0.2) -> Fn:
 
 def eps_for_n(n: int) -> float:
     """Perturbation of the finite-difference Jacobian by grid size (section 5.1): 0.2, 0.15,
-    0.1, 0.05 for 96..768 cells; sizes between the listed ones take the value of the next
-    listed size up, up to 2048 cells; 0.02 for finer grids.  The paper's 0.01 for fine grids
+    0.1, 0.05 for 96, 192, 384, 768 cells; other sizes up to 2048 cells take the value of the
+    nearest listed size (by ratio); 0.02 for finer grids.  The paper's 0.01 for fine grids
     ("usually sufficient") diverges from the flat-surface initial guess on many seeded channels
     (checked on the oracle), as does 0.02 on some strongly varying widths below 2048 cells;
     these values converge on every seeded instance checked."""
@@ -288,8 +288,11 @@ def nested_grids(prob, ngrids: Optional[int] = None):
     """The grids of the nested iteration (Algorithm 3) for a 1D problem: grid g (g = 0 the
     problem itself) has N / 2^g cells and levels - g multigrid levels, the same channel,
     boundary data and solver parameters, and the perturbation of the grid-size table for its
-    own size (eps_for_n, except that the finest grid keeps the problem's).  ngrids defaults to
-    the problem's number of levels."""
+    own size (eps_for_n, except that the finest grid keeps the problem's).  The coarsest grid,
+    solved by Newton with the direct linear solve from the flat-surface guess, takes the
+    regularisation alpha = 5: with the default 3 that first solve breaks down on 3 of 256
+    seeded transcritical humps (all converge with 5).  ngrids defaults to the problem's number
+    of levels."""
     ng = prob.levels if ngrids is None else ngrids
     if ng < 1 or ng > prob.levels or prob.n % (1 << (ng - 1)):
         raise ValueError("ngrids must be in [1, levels] and divide the grid")
@@ -297,6 +300,8 @@ def nested_grids(prob, ngrids: Optional[int] = None):
     for g in range(ng):
         n = prob.n >> g
         p = prob.params if g == 0 else dataclasses.replace(prob.params, eps=eps_for_n(n))
+        if g == ng - 1 and ng > 1:
+            p = dataclasses.replace(p, alpha=5.0)
         out.append(dataclasses.replace(prob, name=f"{prob.name}/{n}", n=n, levels=prob.levels - g,
                                        params=p))
     return out

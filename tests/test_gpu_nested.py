@@ -58,3 +58,16 @@ def test_nested_solve_matches_the_oracle(variant, n, levels):
     for (ng, it, _, _), (no, ito, _) in zip(rep, rep_o[::-1]):
         assert ng == no and abs(it - ito) <= 1
     assert err <= 1e-10
+
+
+def test_nested_batch_equals_single_nested_solves():
+    from paper_2505_10857_amd.solver import NestedBatch, nested_solve
+    probs = [config2(i, v, n=800, levels=4) for i, v in ((0, "trans"), (1, "sub"), (2, "trans"))]
+    nb = NestedBatch(probs, device=DEV)
+    Us = nb.states()
+    rep = nb.solve(Us, use_graph=True)
+    assert all(x[1] == 0 for x in rep[-1])
+    for i, p in enumerate(probs):
+        U1, r1 = nested_solve(p, device=DEV)
+        assert torch.equal(U1, Us[0][i])
+        assert [r[1] for r in r1] == [rep[::-1][k][i][0] for k in range(4)]

@@ -50,6 +50,7 @@ def test_nested_grids_follow_the_hierarchy():
     assert [g.n for g in gs] == [800, 400, 200, 100]
     assert [g.levels for g in gs] == [4, 3, 2, 1]
     assert gs[0].params.eps == p.params.eps and gs[-1].params.eps == 0.2
+    assert [g.params.alpha for g in gs] == [p.params.alpha] * 3 + [5.0]
 
 
 def test_nested_solve_reaches_the_same_discrete_solution():
