@@ -33,17 +33,17 @@ FP64_VECTOR_TFLOPS = 78.6
 # two-point Gauss source (36) and the final differences (3).
 FLOPS_LOCAL_RESIDUAL = 10 * 22 + 2 * 46 + 36 + 3
 # Algorithmic HBM bytes per cell and launch (FP64, J3):
-#   Jacobian: read U 16, R 16, rn 8, geometry 7*8 = 56; write J 96, rhs 16, D^-1 32 and the
-#   coarse operators (J 96 + D^-1 32 per coarse cell) of the eight levels built inside its tile
-#   (sum over l = 1..8 of 2^-l coarse cells per fine cell)
-BYTES_JACOBIAN_J3 = 16 + 16 + 8 + 56 + 96 + 16 + 32 + 128 * (1.0 - 2.0 ** -8)
+#   Jacobian: read U 16, R 16, rn 8, geometry 7*8 = 56; write J 96, rhs 16 and the coarse
+#   operators (J 96 per coarse cell) of the eight levels built inside its tile (sum over
+#   l = 1..8 of 2^-l coarse cells per fine cell)
+BYTES_JACOBIAN_J3 = 16 + 16 + 8 + 56 + 96 + 16 + 96 * (1.0 - 2.0 ** -8)
 # HBM traffic of the Jacobian kernel measured with rocprofv3 counters (profiles/), valid while
 # the kernel source is the one it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobian_j3_fp64_hump12800_batch256_traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2505_10857_amd", "csrc", "swe1d.hip")
-#   finest pre-smoothing: read J 96, Dinv 32, rhs 16; write dU 16 and the restricted rhs 8 per
-#   fine cell; plus a read of dU 16 in the second of the two cycles (average 8)
-BYTES_SMOOTH_PRE_J3 = 96 + 32 + 16 + 16 + 8 + 8
+#   finest pre-smoothing: read J 96 and rhs 16; write dU 16 and the restricted rhs 8 per fine
+#   cell; plus a read of dU 16 in the second of the two cycles (average 8)
+BYTES_SMOOTH_PRE_J3 = 96 + 16 + 16 + 8 + 8
 
 
 def parse():

@@ -7,7 +7,7 @@
 //   partial  : double[res tiles]            (per-tile sums of ||R_j||_1)
 //   hist     : double[n][max_hist]
 //   R, rn    : double, per instance [2N] and [N]
-//   mg       : per instance and level: J [nb*4][n_l], Dinv [4][n_l], rhs [2][n_l], dU [2][n_l]
+//   mg       : per instance and level: J [nb*4][n_l], rhs [2][n_l], dU [2][n_l]
 //              in double (NMG_FP64) or float (NMG_FP32_MG)
 #include <algorithm>
 #include <cstdio>
@@ -198,7 +198,6 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
             L.V = kTile - 2 * L.halo;
             L.child = L.coarsest ? -1 : (int)P->levs.size() + 1;
             L.J = mg_elems; mg_elems += (long long)L.nb * 4 * L.n;
-            L.Dinv = mg_elems; mg_elems += 4LL * L.n;
             L.rhs = mg_elems; mg_elems += 2LL * L.n;
             L.dU = mg_elems; mg_elems += 2LL * L.n;
             mg_elems = (mg_elems + 63) & ~63LL;

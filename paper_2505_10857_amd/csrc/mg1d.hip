@@ -3,10 +3,11 @@
 //
 //  * k_coarsen: coarse operators of eq. (17) for up to ten levels in one launch.  A workgroup
 //    owns an aligned run of 1024 cells of the starting level and reduces them level by level
-//    in LDS (each coarse cell aggregates two children, eq. 15), writing every level's blocks
-//    and the closed-form 2x2 inverses of the diagonal blocks used by eq. (19).
+//    in LDS (each coarse cell aggregates two children, eq. 15), writing every level's blocks.
+//    The smoothers form the closed-form 2x2 inverses of the diagonal blocks of eq. (19)
+//    themselves, so no inverse is stored.
 //  * k_smooth: all nu multicolour block-SOR half-sweeps of one smoothing phase fused in one
-//    launch.  Each workgroup loads its cells' block rows, inverse and right-hand side into
+//    launch.  Each workgroup loads its cells' block rows and right-hand side into
 //    registers once, keeps dU in LDS, and runs the half-sweeps with a halo wide enough that
 //    the cells it writes are exact; the pre-smoothing kernel then forms the restricted
 //    right-hand side of eq. (17), the post-smoothing kernel first adds the prolongation of
@@ -74,16 +75,14 @@ __device__ __forceinline__ void first_coarse(const Level1D &L0, const Level1D &L
                 f0[b][e] = ld(base + L0.J, (b * 4 + e) * (long long)L0.n + 2 * jc);
                 f1[b][e] = ld(base + L0.J, (b * 4 + e) * (long long)L0.n + 2 * jc + 1);
             }
-        double W[4], D[4], E[4], B[4];
+        double W[4], D[4], E[4];
         coarse_row(NB, f0, f1, W, D, E);
-        inv2(D, B);
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             blk[jl][e] = W[e]; blk[jl][4 + e] = D[e]; blk[jl][8 + e] = E[e];
             base[Lc.J + (0 * 4 + e) * (long long)Lc.n + jc] = (T)W[e];
             base[Lc.J + (1 * 4 + e) * (long long)Lc.n + jc] = (T)D[e];
             base[Lc.J + (2 * 4 + e) * (long long)Lc.n + jc] = (T)E[e];
-            base[Lc.Dinv + e * (long long)Lc.n + jc] = (T)B[e];
         }
     }
 }
@@ -101,16 +100,6 @@ __global__ void __launch_bounds__(kTile) k_coarsen(MGArgs mg, const Tile *tiles)
     const int t = threadIdx.x;
     const int nb = L0.nb;
 
-    // diagonal inverses of the starting level
-    for (int k = 0; k < CPT; k++) {
-        const int j = tl.a + t * CPT + k;
-        if (j >= L0.n) break;
-        double A[4], B[4];
-#pragma unroll
-        for (int e = 0; e < 4; e++) A[e] = ld(base + L0.J, ((nb / 2) * 4 + e) * (long long)L0.n + j);
-        inv2(A, B);
-        for (int e = 0; e < 4; e++) base[L0.Dinv + e * (long long)L0.n + j] = (T)B[e];
-    }
     if (L0.coarsest) return;
 
     // first coarse level from the starting level (global reads)
@@ -129,7 +118,7 @@ __global__ void __launch_bounds__(kTile) k_coarsen(MGArgs mg, const Tile *tiles)
         const Level1D Ln = mg.levs[nlev];
         const int nstart = cstart / 2;
         const int ncnt = cnt / 2;
-        double W[4], D[4], E[4], B[4];
+        double W[4], D[4], E[4];
         const int jc = nstart + t;
         const bool mine = t < ncnt && jc < Ln.n;
         if (mine) {
@@ -140,7 +129,6 @@ __global__ void __launch_bounds__(kTile) k_coarsen(MGArgs mg, const Tile *tiles)
                 f1[0][e] = blk[2 * t + 1][e]; f1[1][e] = blk[2 * t + 1][4 + e]; f1[2][e] = blk[2 * t + 1][8 + e];
             }
             coarse_row(3, f0, f1, W, D, E);
-            inv2(D, B);
         }
         __syncthreads();
         if (mine) {
@@ -149,7 +137,6 @@ __global__ void __launch_bounds__(kTile) k_coarsen(MGArgs mg, const Tile *tiles)
                 base[Ln.J + (0 * 4 + e) * (long long)Ln.n + jc] = (T)W[e];
                 base[Ln.J + (1 * 4 + e) * (long long)Ln.n + jc] = (T)D[e];
                 base[Ln.J + (2 * 4 + e) * (long long)Ln.n + jc] = (T)E[e];
-                base[Ln.Dinv + e * (long long)Ln.n + jc] = (T)B[e];
             }
         }
         __syncthreads();
@@ -187,8 +174,10 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
     for (int b = 0; b < NB; b++)
 #pragma unroll
         for (int e = 0; e < 4; e++) Jr[b][e] = in ? ld(base + L.J, (b * 4 + e) * (long long)n + j) : 0.0;
-#pragma unroll
-    for (int e = 0; e < 4; e++) D[e] = in ? ld(base + L.Dinv, e * (long long)n + j) : 0.0;
+    // the inverse of the diagonal block, formed here instead of read (one division per cell
+    // and launch against 4 values of HBM traffic per cell and half-sweep phase)
+    if (in) inv2(Jr[HW], D);
+    else D[0] = D[1] = D[2] = D[3] = 0.0;
     if (in) {
         r0 = ld(base + L.rhs, j);
         r1 = ld(base + L.rhs, n + (long long)j);
@@ -300,8 +289,7 @@ __device__ __forceinline__ void bottom_load(const T *base, const Level1D &L, int
 {
 #pragma unroll
     for (int e = 0; e < 12; e++) Jr[e] = ld(base + L.J, e * (long long)L.n + c);
-#pragma unroll
-    for (int e = 0; e < 4; e++) D[e] = ld(base + L.Dinv, e * (long long)L.n + c);
+    inv2(&Jr[4], D);   // the inverse of the diagonal block, as in the tiled smoother
 }
 
 template <typename T, int NT>

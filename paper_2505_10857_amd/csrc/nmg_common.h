@@ -41,7 +41,7 @@ struct Inst1D {
 struct Level1D {
     int inst, l, n, nb;
     int coarsest, halo, V, child;    // child: level index of l+1 (-1 at the coarsest)
-    long long J, Dinv, rhs, dU;
+    long long J, rhs, dU;
 };
 
 struct Tile {

@@ -403,10 +403,10 @@ __device__ __forceinline__ void coarse_from_children(const double *f0, const dou
 }
 
 // Jacobian rows of one tile.  With `mg` levels (batched path) the tile also writes the finest
-// right-hand side, every level's diagonal inverse and the coarse operators of all levels that
-// lie inside the tile (up to eight: 256 -> 1 cells).
+// right-hand side and the coarse operators of all levels that lie inside the tile (up to
+// eight: 256 -> 1 cells).
 template <typename T, int NB>
-__device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs, T *Dinv,
+__device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
                               const MGArgs *mg, const Level1D *L0)
 {
     __shared__ double sH[kTile + 4], sQ[kTile + 4];
@@ -474,14 +474,6 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs, 
         }
 #pragma unroll
         for (int e = 0; e < NB * 4; e++) J[e * (long long)stride + j] = (T)myrow[e];
-        if (Dinv) {
-            double D[4], Di[4];
-#pragma unroll
-            for (int e = 0; e < 4; e++) D[e] = myrow[HW * 4 + e];
-            inv2d(D, Di);
-#pragma unroll
-            for (int e = 0; e < 4; e++) Dinv[e * (long long)stride + j] = (T)Di[e];
-        }
     }
     if (!mg || L0->coarsest) return;
 
@@ -493,11 +485,9 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs, 
     {
         const int jc = cstart + t;
         const bool mine = t < cnt && jc < Lc.n;
-        double Wc[4], Dc[4], Ec[4], Bi[4];
-        if (mine) {
+        double Wc[4], Dc[4], Ec[4];
+        if (mine)
             coarse_from_children<NB>(&rows[(2 * t) * NB * 4], &rows[(2 * t + 1) * NB * 4], Wc, Dc, Ec);
-            inv2d(Dc, Bi);
-        }
         __syncthreads();
         if (mine) {
 #pragma unroll
@@ -506,7 +496,6 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs, 
                 base_mg[Lc.J + (0 * 4 + e) * (long long)Lc.n + jc] = (T)Wc[e];
                 base_mg[Lc.J + (1 * 4 + e) * (long long)Lc.n + jc] = (T)Dc[e];
                 base_mg[Lc.J + (2 * 4 + e) * (long long)Lc.n + jc] = (T)Ec[e];
-                base_mg[Lc.Dinv + e * (long long)Lc.n + jc] = (T)Bi[e];
             }
         }
         __syncthreads();
@@ -516,11 +505,8 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs, 
         const int nstart = cstart / 2, ncnt = cnt / 2;
         const int jc = nstart + t;
         const bool mine = t < ncnt && jc < Ln.n;
-        double Wc[4], Dc[4], Ec[4], Bi[4];
-        if (mine) {
-            coarse_from_children<3>(&rows[(2 * t) * 12], &rows[(2 * t + 1) * 12], Wc, Dc, Ec);
-            inv2d(Dc, Bi);
-        }
+        double Wc[4], Dc[4], Ec[4];
+        if (mine) coarse_from_children<3>(&rows[(2 * t) * 12], &rows[(2 * t + 1) * 12], Wc, Dc, Ec);
         __syncthreads();
         if (mine) {
 #pragma unroll
@@ -529,7 +515,6 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs, 
                 base_mg[Ln.J + (0 * 4 + e) * (long long)Ln.n + jc] = (T)Wc[e];
                 base_mg[Ln.J + (1 * 4 + e) * (long long)Ln.n + jc] = (T)Dc[e];
                 base_mg[Ln.J + (2 * 4 + e) * (long long)Ln.n + jc] = (T)Ec[e];
-                base_mg[Ln.Dinv + e * (long long)Ln.n + jc] = (T)Bi[e];
             }
         }
         __syncthreads();
@@ -548,14 +533,14 @@ __global__ void __launch_bounds__(kTile) k_jacobian_batch(MGArgs mg, const Tile 
     const Level1D L = mg.levs[I.lev0];
     if (L.nb != NB) return;
     T *base = reinterpret_cast<T *>(mg.mg);
-    jacobian_tile<T, NB>(I, t.a, base + L.J, L.n, base + L.rhs, base + L.Dinv, &mg, &L);
+    jacobian_tile<T, NB>(I, t.a, base + L.J, L.n, base + L.rhs, &mg, &L);
 }
 
 template <int NB>
 __global__ void __launch_bounds__(kTile) k_jacobian_single(Inst1D I, double *J)
 {
-    jacobian_tile<double, NB>(I, blockIdx.x * kTile, J, I.N, (double *)nullptr, (double *)nullptr,
-                              (const MGArgs *)nullptr, (const Level1D *)nullptr);
+    jacobian_tile<double, NB>(I, blockIdx.x * kTile, J, I.N, (double *)nullptr, (const MGArgs *)nullptr,
+                              (const Level1D *)nullptr);
 }
 
 // ---- launchers ---------------------------------------------------------------------------
