@@ -85,12 +85,25 @@ typedef struct {
  * (eq. 14), eps FD perturbation (eq. 12), omega SOR relaxation (eq. 19/22), nu1/nu2 symmetric
  * smoothing steps, nu3 V-cycles per Newton step, tol on res = mean ||R_j||_1, n_max Newton
  * steps.  check_every: Newton steps between host reads of the convergence state in
- * nmg_newton_solve / nmg_plan_solve (>= 1). */
+ * nmg_newton_solve / nmg_plan_solve (>= 1).
+ * linear (1D): how each Newton step solves the regularised system.  NMG_LINEAR_MG: nu3 V-cycles
+ * (Algorithm 2).  NMG_LINEAR_SOR / NMG_LINEAR_SOR_LEX: the Newton-SOR reference solver of
+ * section 5.1.1 -- symmetric block SOR steps on the grid itself (multicolour, or the
+ * lexicographic forward + backward sweep, which runs one thread per instance and is meant for
+ * iteration-count comparisons), stopped once the l1 norm of the change of dU between two
+ * successive steps (summed over cells and components) falls below sor_tol, or after sor_max
+ * steps; levels is then ignored. */
+#define NMG_LINEAR_MG 0
+#define NMG_LINEAR_SOR 1
+#define NMG_LINEAR_SOR_LEX 2
 typedef struct {
     double alpha, tau, eps, omega, tol;
     int32_t nu1, nu2, nu3, n_max;
     int32_t precision;
     int32_t check_every;
+    int32_t linear;
+    int32_t sor_max;
+    double sor_tol;
 } nmg_params;
 
 typedef struct {

@@ -63,7 +63,8 @@ class OrParams1D(C.Structure):
     _fields_ = [("alpha", C.c_double), ("tau", C.c_double), ("eps", C.c_double),
                 ("omega", C.c_double), ("tol", C.c_double),
                 ("nu1", C.c_int), ("nu2", C.c_int), ("nu3", C.c_int), ("n_max", C.c_int),
-                ("levels", C.c_int), ("nb", C.c_int), ("smoother", C.c_int)]
+                ("levels", C.c_int), ("nb", C.c_int), ("smoother", C.c_int),
+                ("linear", C.c_int), ("sor_max", C.c_int), ("sor_tol", C.c_double)]
 
 
 def _declare(L):

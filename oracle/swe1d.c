@@ -63,6 +63,9 @@ typedef struct {
     int levels;     /* L + 1 */
     int nb;         /* 3 (simplified J3) or 5 (full J5) */
     int smoother;   /* 0 multicolour, 1 lexicographic forward+backward */
+    int linear;     /* 0: nu3 V-cycles (Algorithm 1 with Algorithm 2); 1: Newton-SOR */
+    int sor_max;    /* Newton-SOR: at most this many symmetric SOR steps per Newton step */
+    double sor_tol; /* ... stopping once the l1 norm of the change of dU falls below this */
 } or1d_params;
 
 static const double ZETA = 1e-6; /* WENO epsilon of eq. (8) */
@@ -557,7 +560,7 @@ int or1d_newton_solve(const or1d_prob *p, const or1d_params *pp, double *U, doub
     double *R = malloc(sizeof(double) * 2 * N);
     double *rn = malloc(sizeof(double) * N);
     double *J = malloc(sizeof(double) * (size_t)N * nb * 4);
-    or1d_mg *mg = or1d_mg_create(N, pp->levels, nb);
+    or1d_mg *mg = or1d_mg_create(N, pp->linear == 1 ? 1 : pp->levels, nb);
     double res = or1d_residual(p, U, R, rn);
     int n = 0;
     do {
@@ -568,8 +571,25 @@ int or1d_newton_solve(const or1d_prob *p, const or1d_params *pp, double *U, doub
             mg->rhs[0][2 * j + 1] = R[N + j];
         }
         memset(mg->dU[0], 0, sizeof(double) * 2 * N);
-        for (int m = 0; m < pp->nu3; m++)
-            or1d_vcycle(mg, 0, pp->omega, pp->nu1, pp->nu2, pp->smoother);
+        if (pp->linear == 1) {
+            /* Newton-SOR (section 5.1.1, the reference solver of Table 2): the multigrid
+             * iteration replaced by symmetric block SOR steps on the grid itself, stopped when
+             * the l1 norm of the change between two successive iterates falls below sor_tol or
+             * after sor_max steps (reading: the l1 norm sums |change| over all cells and both
+             * components) */
+            double *old = malloc(sizeof(double) * 2 * N);
+            for (int k = 0; k < pp->sor_max; k++) {
+                memcpy(old, mg->dU[0], sizeof(double) * 2 * N);
+                or1d_smooth(mg, 0, pp->omega, pp->smoother);
+                double var = 0.0;
+                for (int e = 0; e < 2 * N; e++) var += fabs(mg->dU[0][e] - old[e]);
+                if (var < pp->sor_tol) break;
+            }
+            free(old);
+        } else {
+            for (int m = 0; m < pp->nu3; m++)
+                or1d_vcycle(mg, 0, pp->omega, pp->nu1, pp->nu2, pp->smoother);
+        }
         for (int j = 0; j < N; j++) {
             U[j] = U[j] + pp->tau * mg->dU[0][2 * j];
             U[N + j] = U[N + j] + pp->tau * mg->dU[0][2 * j + 1];

@@ -26,6 +26,10 @@ NMG_BC_STATE = 4
 NMG_FP64 = 0
 NMG_FP32_MG = 1
 
+NMG_LINEAR_MG = 0
+NMG_LINEAR_SOR = 1
+NMG_LINEAR_SOR_LEX = 2
+
 EXPORTS = [
     "nmg_workspace_bytes", "nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",
     "nmg_newton_solve", "nmg_plan_create", "nmg_plan_workspace_bytes", "nmg_plan_solve",
@@ -61,7 +65,8 @@ class nmg_params(C.Structure):
     _fields_ = [("alpha", C.c_double), ("tau", C.c_double), ("eps", C.c_double),
                 ("omega", C.c_double), ("tol", C.c_double),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("nu3", C.c_int32), ("n_max", C.c_int32),
-                ("precision", C.c_int32), ("check_every", C.c_int32)]
+                ("precision", C.c_int32), ("check_every", C.c_int32),
+                ("linear", C.c_int32), ("sor_max", C.c_int32), ("sor_tol", C.c_double)]
 
 
 class nmg_stats(C.Structure):

@@ -43,13 +43,20 @@ nmg_status check_desc1d(const nmg_desc *d, const nmg_params *p, bool need_geomet
     if (!d || !p) return fail(NMG_EINVAL, "null desc or params");
     if (d->dim != 1) return fail(NMG_EINVAL, "only dim = 1 is handled by this entry point");
     if (d->nx < 4) return fail(NMG_EINVAL, "nx must be >= 4");
-    if (d->levels < 1 || d->levels > kMaxLevels) return fail(NMG_EINVAL, "levels must be in [1, 16]");
-    if (d->levels == 1 && d->jac != 3)
-        return fail(NMG_EINVAL, "a one-level hierarchy (direct solve) needs the three-block Jacobian");
-    if (d->nx % (1 << (d->levels - 1)) != 0)
-        return fail(NMG_EINVAL, "nx must be divisible by 2^(levels-1)");
-    if ((d->nx >> (d->levels - 1)) > kMaxCoarse)
-        return fail(NMG_EINVAL, "coarsest level has more than 256 cells; add levels");
+    if (p->linear != NMG_LINEAR_MG && p->linear != NMG_LINEAR_SOR && p->linear != NMG_LINEAR_SOR_LEX)
+        return fail(NMG_EINVAL, "bad linear solver");
+    if (p->linear != NMG_LINEAR_MG) {   // Newton-SOR: no hierarchy
+        if (p->sor_max < 1 || p->sor_max > 1000) return fail(NMG_EINVAL, "sor_max must be in [1, 1000]");
+        if (!(p->sor_tol >= 0.0)) return fail(NMG_EINVAL, "sor_tol must be >= 0");
+    } else {
+        if (d->levels < 1 || d->levels > kMaxLevels) return fail(NMG_EINVAL, "levels must be in [1, 16]");
+        if (d->levels == 1 && d->jac != 3)
+            return fail(NMG_EINVAL, "a one-level hierarchy (direct solve) needs the three-block Jacobian");
+        if (d->nx % (1 << (d->levels - 1)) != 0)
+            return fail(NMG_EINVAL, "nx must be divisible by 2^(levels-1)");
+        if ((d->nx >> (d->levels - 1)) > kMaxCoarse)
+            return fail(NMG_EINVAL, "coarsest level has more than 256 cells; add levels");
+    }
     if (d->jac != 3 && d->jac != 5) return fail(NMG_EINVAL, "1D jac must be 3 or 5");
     if (need_geometry && (!d->sig_face || !d->sig_gp || !d->sigx_gp || !d->bx_gp))
         return fail(NMG_EINVAL, "null geometry pointer");
@@ -69,7 +76,7 @@ Inst1D make_inst(const nmg_desc *d, const nmg_params *p)
     Inst1D I;
     memset(&I, 0, sizeof(I));
     I.N = d->nx;
-    I.levels = d->levels;
+    I.levels = p->linear == NMG_LINEAR_MG ? d->levels : 1;   // Newton-SOR works on the grid alone
     I.nb = d->jac;
     I.dx = (d->x1 - d->x0) / d->nx;
     I.g = d->g;
@@ -118,6 +125,10 @@ struct nmg_plan {
     std::vector<size_t> R_off;                // per instance byte offset of R (rn follows)
     std::vector<int> n_start;                 // Newton steps already taken, per instance
     // tunables (nmg_plan_options) and what is needed to rebuild the tables for them
+    int linear = NMG_LINEAR_MG;               // inner solver (nmg_params.linear)
+    int sor_max = 0;
+    double sor_tol = 0.0;
+    int sor_t0 = 0, sor_nt = 0;               // Newton-SOR tiles (level 0, one-step halo)
     int bottom_cells = 2048;                  // levels up to this size run in k_bottom
     int bottom_nt = 1024;                     // its workgroup size
     size_t tile_cap = 0;                      // tile-table entries reserved (any option fits)
@@ -161,11 +172,16 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
     P->prec = params[0].precision;
     P->nu3 = params[0].nu3;
     P->check_every = std::max(1, params[0].check_every);
+    P->linear = params[0].linear;
+    P->sor_max = params[0].sor_max;
+    P->sor_tol = params[0].sor_tol;
     for (int k = 0; k < n; k++) {
         nmg_status st = check_desc1d(&descs[k], &params[k], need_geometry);
         if (st != NMG_OK) return fail(st, "instance " + std::to_string(k) + ": " + g_err);
         if (params[k].precision != P->prec) return fail(NMG_EINVAL, "mixed precisions in one plan");
         if (params[k].nu3 != P->nu3) return fail(NMG_EINVAL, "mixed nu3 in one plan");
+        if (params[k].linear != P->linear || params[k].sor_max != P->sor_max || !(params[k].sor_tol == P->sor_tol))
+            return fail(NMG_EINVAL, "mixed linear solvers in one plan");
     }
     const size_t vsz = P->prec == NMG_FP32_MG ? sizeof(float) : sizeof(double);
     P->insts.clear();
@@ -174,7 +190,7 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
     int max_levels = 0;
     P->max_hist = 0;
     for (int k = 0; k < n; k++) {
-        max_levels = std::max(max_levels, descs[k].levels);
+        max_levels = std::max(max_levels, P->linear == NMG_LINEAR_MG ? descs[k].levels : 1);
         P->max_hist = std::max(P->max_hist, std::min(params[k].n_max, 100000));
     }
     P->depth = max_levels - 1;
@@ -194,12 +210,14 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
             L.n = I.N >> l;
             L.nb = l == 0 ? I.nb : 3;
             L.coarsest = l == I.levels - 1;
-            L.halo = halo_cells(L.nb, std::max(I.nu1, I.nu2));
+            L.halo = halo_cells(L.nb, P->linear == NMG_LINEAR_MG ? std::max(I.nu1, I.nu2) : 1);
             L.V = kTile - 2 * L.halo;
             L.child = L.coarsest ? -1 : (int)P->levs.size() + 1;
             L.J = mg_elems; mg_elems += (long long)L.nb * 4 * L.n;
             L.rhs = mg_elems; mg_elems += 2LL * L.n;
             L.dU = mg_elems; mg_elems += 2LL * L.n;
+            L.aux = -1;
+            if (P->linear == NMG_LINEAR_SOR_LEX && l == 0) { L.aux = mg_elems; mg_elems += 2LL * L.n; }
             mg_elems = (mg_elems + 63) & ~63LL;
             lev_index[k].push_back((int)P->levs.size());
             P->levs.push_back(L);
@@ -223,6 +241,17 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
         P->jac_mask |= P->insts[k].nb == 5 ? 2 : 1;
     }
     P->res_nt = (int)P->tiles.size();
+    // Newton-SOR tiles: level 0 with the halo of one symmetric step
+    P->sor_t0 = (int)P->tiles.size();
+    if (P->linear == NMG_LINEAR_SOR) {
+        for (int k = 0; k < n; k++) {
+            const Level1D &L = P->levs[lev_index[k][0]];
+            P->insts[k].sor_tile0 = (int)P->tiles.size() - P->sor_t0;
+            for (int a = 0; a < L.n; a += L.V) P->tiles.push_back({lev_index[k][0], a});
+            P->insts[k].sor_tiles = (int)P->tiles.size() - P->sor_t0 - P->insts[k].sor_tile0;
+        }
+    }
+    P->sor_nt = (int)P->tiles.size() - P->sor_t0;
     // coarsening passes: each pass starts at level 10*p and builds up to ten more levels
     P->coarsen.clear();
     const int span = kTile * kCoarsenCells;
@@ -269,7 +298,7 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
     o = align256(o + sizeof(Tile) * std::max<size_t>(1, std::max(P->tiles.size(), P->tile_cap)));
     P->off_list = o; o = align256(o + sizeof(int) * n);
     P->off_state = o; o = align256(o + sizeof(NewtonState) * n);
-    P->off_partial = o; o = align256(o + sizeof(double) * std::max(1, P->res_nt));
+    P->off_partial = o; o = align256(o + sizeof(double) * std::max(1, std::max(P->res_nt, P->sor_nt)));
     P->off_hist = o; o = align256(o + sizeof(double) * (size_t)n * std::max(1, P->max_hist));
     P->R_off.resize(n);
     for (int k = 0; k < n; k++) {
@@ -410,9 +439,25 @@ nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s, bool cap = false)
     }
     nmg_status st = enqueue_setup(P, ws, mg, s, cap, true);
     if (st != NMG_OK) return st;
-    for (int v = 0; v < P->nu3; v++) {
-        st = enqueue_vcycle(P, ws, mg, v == 0, v == P->nu3 - 1, s, cap);
-        if (st != NMG_OK) return st;
+    if (P->linear == NMG_LINEAR_MG) {
+        for (int v = 0; v < P->nu3; v++) {
+            st = enqueue_vcycle(P, ws, mg, v == 0, v == P->nu3 - 1, s, cap);
+            if (st != NMG_OK) return st;
+        }
+    } else {
+        // Newton-SOR: up to sor_max symmetric steps; an instance whose step changed dU by less
+        // than sor_tol (l1) is skipped by the remaining ones
+        const int nb_max = (P->jac_mask & 2) ? 5 : 3;
+        for (int k = 0; k < P->sor_max; k++) {
+            if (P->linear == NMG_LINEAR_SOR) {
+                HIP_TRY(launch_sor_mc(mg, tiles_at(P, ws, P->sor_t0), P->sor_nt, nb_max, k == 0 ? 1 : 0, partial,
+                                      P->prec, s));
+                HIP_TRY(launch_sor_finalize(insts, P->n, state, partial, P->sor_tol, s));
+            } else {
+                HIP_TRY(launch_sor_lex(mg, P->n, nb_max, k == 0 ? 1 : 0, P->sor_tol, P->prec, s));
+            }
+        }
+        HIP_TRY(launch_update1d(mg, rt, P->res_nt, P->prec, s));
     }
     {
         ProfScope ps(P, NMG_K_RESIDUAL, s, cap);
@@ -777,6 +822,7 @@ nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *w
 {
     if (desc && desc->dim == 2) return vcycle2d(desc, params, ws, ws_bytes, J, rhs, dU, setup, (hipStream_t)stream);
     if (!ws || !rhs || !dU || (setup && !J)) return fail(NMG_EINVAL, "null argument");
+    if (params && params->linear != NMG_LINEAR_MG) return fail(NMG_EINVAL, "a V-cycle needs linear = NMG_LINEAR_MG");
     nmg_plan P;
     nmg_status st = build_plan(&P, desc, params, 1);
     if (st != NMG_OK) return st;

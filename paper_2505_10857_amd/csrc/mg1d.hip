@@ -560,6 +560,189 @@ __global__ void __launch_bounds__(NT) k_bottom(MGArgs mg, const int *inst_list, 
     }
 }
 
+// ---- Newton-SOR (section 5.1.1) ----------------------------------------------------------
+// The reference solver of the paper's Table 2: each Newton step solves the regularised system on
+// the grid itself by symmetric block SOR steps (eq. 19) until the l1 norm of the change of dU
+// between two successive steps falls below a tolerance or a step limit is reached.  The
+// multicolour step reuses the tiled smoother's structure (one symmetric step per launch, halo
+// for one step) and reports the change per tile; a finalisation launch per Newton-SOR step sums
+// it per instance (fixed order) and marks the instance done, after which the later steps of the
+// same Newton step skip it.
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(kTile) k_sor_mc(MGArgs mg, const Tile *tiles, int zero_init, double *partial)
+{
+    constexpr int HW = NB / 2;
+    constexpr int C = NB == 5 ? 3 : 2;
+    __shared__ double s0[kTile + 2 * HW], s1[kTile + 2 * HW];
+    __shared__ double red[kTile / 64];
+    const Tile tl = tiles[blockIdx.x];
+    const Level1D L = mg.levs[tl.lev];
+    const int t = threadIdx.x;
+    if (L.nb != NB) return;
+    const Inst1D &I = mg.insts[L.inst];
+    const NewtonState *S = mg.state ? &mg.state[I.active_idx] : nullptr;
+    if (S && (!S->active || S->sor_done)) {
+        if (t == 0) partial[blockIdx.x] = 0.0;
+        return;
+    }
+    T *base = reinterpret_cast<T *>(mg.mg);
+    const int n = L.n, h = L.halo;
+    const int j = tl.a - h + t;
+    const bool in = j >= 0 && j < n;
+    double Jr[NB][4], D[4], r0 = 0.0, r1 = 0.0, du0 = 0.0, du1 = 0.0;
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) Jr[b][e] = in ? ld(base + L.J, (b * 4 + e) * (long long)n + j) : 0.0;
+    if (in) inv2(Jr[HW], D);
+    else D[0] = D[1] = D[2] = D[3] = 0.0;
+    if (in) {
+        r0 = ld(base + L.rhs, j);
+        r1 = ld(base + L.rhs, n + (long long)j);
+        if (!zero_init) {
+            du0 = ld(base + L.dU, j);
+            du1 = ld(base + L.dU, n + (long long)j);
+        }
+    }
+    const double old0 = du0, old1 = du1;
+    s0[t + HW] = du0;
+    s1[t + HW] = du1;
+    if (t < HW) { s0[t] = 0.0; s1[t] = 0.0; s0[kTile + HW + t] = 0.0; s1[kTile + HW + t] = 0.0; }
+    __syncthreads();
+    const double w = I.omega;
+    const int col = ((j % C) + C) % C;
+    for (int hs = 0; hs < 2 * C; hs++) {
+        const int c = hs < C ? hs : 2 * C - 1 - hs;
+        if (in && col == c) {
+            double a0 = r0, a1 = r1;
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                if (b == HW) continue;
+                const double x0 = s0[t + b], x1 = s1[t + b];
+                a0 = a0 + (Jr[b][0] * x0 + Jr[b][1] * x1);
+                a1 = a1 + (Jr[b][2] * x0 + Jr[b][3] * x1);
+            }
+            const double t0 = D[0] * a0 + D[1] * a1;
+            const double t1 = D[2] * a0 + D[3] * a1;
+            du0 = (1.0 - w) * du0 - w * t0;
+            du1 = (1.0 - w) * du1 - w * t1;
+            s0[t + HW] = du0;
+            s1[t + HW] = du1;
+        }
+        __syncthreads();
+    }
+    const bool valid = in && t >= h && t < h + L.V;
+    double v = 0.0;
+    if (valid) {
+        base[L.dU + j] = (T)du0;
+        base[L.dU + n + (long long)j] = (T)du1;
+        v = fabs((double)(T)du0 - old0) + fabs((double)(T)du1 - old1);
+    }
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+        double sum = 0.0;
+        for (int k = 0; k < kTile / 64; k++) sum += red[k];
+        partial[blockIdx.x] = sum;
+    }
+}
+
+// per instance: the change of this Newton-SOR step from its tiles' partial sums
+__global__ void __launch_bounds__(64) k_sor_finalize(const Inst1D *insts, int ninst, NewtonState *state,
+                                                     const double *partial, double tol)
+{
+    const int b = blockIdx.x;
+    if (b >= ninst) return;
+    const Inst1D &I = insts[b];
+    NewtonState &S = state[I.active_idx];
+    if (!S.active || S.sor_done) return;
+    double v = 0.0;
+    for (int k = threadIdx.x; k < I.sor_tiles; k += 64) v += partial[I.sor_tile0 + k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (threadIdx.x == 0 && v < tol) S.sor_done = 1;
+}
+
+// the lexicographic symmetric step (forward then backward sweep) of one instance per thread,
+// with its own stopping test
+template <typename T, int NB>
+__global__ void __launch_bounds__(64) k_sor_lex(MGArgs mg, int ninst, int zero_init, double tol)
+{
+    constexpr int HW = NB / 2;
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= ninst) return;
+    const Inst1D &I = mg.insts[k];
+    NewtonState *S = mg.state ? &mg.state[I.active_idx] : nullptr;
+    if (S && (!S->active || S->sor_done)) return;
+    const Level1D L = mg.levs[I.lev0];
+    if (L.nb != NB) return;
+    T *base = reinterpret_cast<T *>(mg.mg);
+    const int n = L.n;
+    const double w = I.omega;
+    // keep the iterate before this step in aux (zero at the first step of a Newton step)
+    for (int j = 0; j < n; j++) {
+        const double d0 = zero_init ? 0.0 : ld(base + L.dU, j);
+        const double d1 = zero_init ? 0.0 : ld(base + L.dU, n + (long long)j);
+        base[L.aux + j] = (T)d0;
+        base[L.aux + n + (long long)j] = (T)d1;
+        if (zero_init) { base[L.dU + j] = (T)0.0; base[L.dU + n + (long long)j] = (T)0.0; }
+    }
+    for (int pass = 0; pass < 2; pass++) {
+        for (int q = 0; q < n; q++) {
+            const int j = pass == 0 ? q : n - 1 - q;
+            double a0 = ld(base + L.rhs, j), a1 = ld(base + L.rhs, n + (long long)j);
+            double Jd[4];
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                const int i = j + b - HW;
+                if (b == HW) {
+#pragma unroll
+                    for (int e = 0; e < 4; e++) Jd[e] = ld(base + L.J, (b * 4 + e) * (long long)n + j);
+                    continue;
+                }
+                if (i < 0 || i >= n) continue;
+                const double x0 = ld(base + L.dU, i), x1 = ld(base + L.dU, n + (long long)i);
+                a0 = a0 + (ld(base + L.J, (b * 4 + 0) * (long long)n + j) * x0 +
+                           ld(base + L.J, (b * 4 + 1) * (long long)n + j) * x1);
+                a1 = a1 + (ld(base + L.J, (b * 4 + 2) * (long long)n + j) * x0 +
+                           ld(base + L.J, (b * 4 + 3) * (long long)n + j) * x1);
+            }
+            double D[4];
+            inv2(Jd, D);
+            const double t0 = D[0] * a0 + D[1] * a1;
+            const double t1 = D[2] * a0 + D[3] * a1;
+            const double d0 = ld(base + L.dU, j), d1 = ld(base + L.dU, n + (long long)j);
+            const double n0 = (1.0 - w) * d0 - w * t0;
+            const double n1 = (1.0 - w) * d1 - w * t1;
+            base[L.dU + j] = (T)n0;
+            base[L.dU + n + (long long)j] = (T)n1;
+        }
+    }
+    // l1 norm of the change over the whole step, cells in order, components interleaved
+    double v = 0.0;
+    for (int j = 0; j < n; j++) {
+        v += fabs(ld(base + L.dU, j) - ld(base + L.aux, j));
+        v += fabs(ld(base + L.dU, n + (long long)j) - ld(base + L.aux, n + (long long)j));
+    }
+    if (S && v < tol) S->sor_done = 1;
+}
+
+// eq. (14) after the Newton-SOR steps: U <- U + tau dU on level 0 of every active instance
+template <typename T>
+__global__ void __launch_bounds__(kTile) k_update1d(MGArgs mg, const Tile *tiles)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const Inst1D &I = mg.insts[tl.lev];
+    if (mg.state && !mg.state[I.active_idx].active) return;
+    const Level1D L = mg.levs[I.lev0];
+    const T *base = reinterpret_cast<const T *>(mg.mg);
+    const int j = tl.a + threadIdx.x;
+    if (j >= I.N) return;
+    I.U[j] = I.U[j] + I.tau * ld(base + L.dU, j);
+    I.U[I.N + j] = I.U[I.N + j] + I.tau * ld(base + L.dU, L.n + (long long)j);
+}
+
 // Initial cell averages of a grid from the solution on the grid with half as many cells
 // (Appendix A, eq. A.1-A.2), both components; one thread per coarse cell.  Interior cells use
 // eq. (A.2); the first and last coarse cells average, over their two halves, the quadratic
@@ -587,6 +770,51 @@ __global__ void k_interp_a2(const double *Uc, int nc, double *Uf)
         const double m2 = (lo * lo + lo * hi + hi * hi) / 3.0;
         v[2 * j + half] = u[k] + a * m1 + b * (m2 - 1.0 / 12.0);
     }
+}
+
+hipError_t launch_sor_mc(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_max, int zero_init,
+                         double *partial, int prec, hipStream_t s)
+{
+    if (ntiles == 0) return hipSuccess;
+    if (prec == NMG_FP32_MG) {
+        hipLaunchKernelGGL((k_sor_mc<float, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, partial);
+        if (nb_max == 5)
+            hipLaunchKernelGGL((k_sor_mc<float, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, partial);
+    } else {
+        hipLaunchKernelGGL((k_sor_mc<double, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, partial);
+        if (nb_max == 5)
+            hipLaunchKernelGGL((k_sor_mc<double, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, partial);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sor_finalize(const Inst1D *insts, int ninst, NewtonState *state, const double *partial,
+                               double tol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sor_finalize, dim3(ninst), dim3(64), 0, s, insts, ninst, state, partial, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_sor_lex(const MGArgs &mg, int ninst, int nb_max, int zero_init, double tol, int prec,
+                          hipStream_t s)
+{
+    const dim3 grid((ninst + 63) / 64);
+    if (prec == NMG_FP32_MG) {
+        hipLaunchKernelGGL((k_sor_lex<float, 3>), grid, dim3(64), 0, s, mg, ninst, zero_init, tol);
+        if (nb_max == 5) hipLaunchKernelGGL((k_sor_lex<float, 5>), grid, dim3(64), 0, s, mg, ninst, zero_init, tol);
+    } else {
+        hipLaunchKernelGGL((k_sor_lex<double, 3>), grid, dim3(64), 0, s, mg, ninst, zero_init, tol);
+        if (nb_max == 5) hipLaunchKernelGGL((k_sor_lex<double, 5>), grid, dim3(64), 0, s, mg, ninst, zero_init, tol);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update1d(const MGArgs &mg, const Tile *tiles, int ntiles, int prec, hipStream_t s)
+{
+    if (ntiles == 0) return hipSuccess;
+    if (prec == NMG_FP32_MG) hipLaunchKernelGGL(k_update1d<float>, dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+    else hipLaunchKernelGGL(k_update1d<double>, dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+    return hipGetLastError();
 }
 
 hipError_t launch_interp_a2(const double *Uc, int nc, double *Uf, hipStream_t s)

@@ -34,6 +34,7 @@ struct Inst1D {
     int max_hist;
     int lbot;          // first level handled by the bottom-of-cycle kernel
     int n_start;       // Newton steps already taken (a resumed instance); 0 for a fresh one
+    int sor_tile0, sor_tiles;  // Newton-SOR tiles of this instance (contiguous)
     double *hist;      // device history of res, [max_hist] (may be null)
 };
 
@@ -42,6 +43,7 @@ struct Level1D {
     int inst, l, n, nb;
     int coarsest, halo, V, child;    // child: level index of l+1 (-1 at the coarsest)
     long long J, rhs, dU;
+    long long aux;                   // Newton-SOR, level 0: dU before the current step [2][n]
 };
 
 struct Tile {
@@ -51,7 +53,8 @@ struct Tile {
 
 struct NewtonState {
     double res;
-    int n, active, status, pad;
+    int n, active, status;
+    int sor_done;   // Newton-SOR: the inner SOR iteration of the current step has stopped
 };
 
 // Kernel arguments common to the multigrid kernels.
@@ -110,6 +113,16 @@ hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int 
                            int zero_init, int final_update, int prec, hipStream_t s);
 hipError_t launch_convert(const void *src, int src_prec, void *dst, int dst_prec, long long n,
                           hipStream_t s);
+// Newton-SOR (section 5.1.1) on level 0: one symmetric multicolour block-SOR step per launch
+// with the per-tile l1 change of dU in partial[], the per-instance stopping test, the
+// lexicographic variant (one thread per instance, test included) and the update U += tau dU
+hipError_t launch_sor_mc(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_max, int zero_init,
+                         double *partial, int prec, hipStream_t s);
+hipError_t launch_sor_finalize(const Inst1D *insts, int ninst, NewtonState *state, const double *partial,
+                               double tol, hipStream_t s);
+hipError_t launch_sor_lex(const MGArgs &mg, int ninst, int nb_max, int zero_init, double tol, int prec,
+                          hipStream_t s);
+hipError_t launch_update1d(const MGArgs &mg, const Tile *tiles, int ntiles, int prec, hipStream_t s);
 // Appendix A interpolation of a 1D state [2][nc] to [2][2 nc]
 hipError_t launch_interp_a2(const double *Uc, int nc, double *Uf, hipStream_t s);
 

@@ -326,6 +326,7 @@ __global__ void __launch_bounds__(64) k_res_finalize(const Inst1D *insts, int ni
     if (threadIdx.x != 0) return;
     const double res = v / I.N;
     S.res = res;
+    S.sor_done = 0;   // the next Newton step starts a fresh inner iteration
     if (init) {
         S.n = I.n_start;
         S.active = 1;

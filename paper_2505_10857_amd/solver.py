@@ -30,6 +30,9 @@ def params_struct(p, precision: int = A.NMG_FP64, check_every: int = 4) -> A.nmg
     s.nu1, s.nu2, s.nu3, s.n_max = p.nu1, p.nu2, p.nu3, p.n_max
     s.precision = precision
     s.check_every = check_every
+    s.linear = getattr(p, "linear", A.NMG_LINEAR_MG)
+    s.sor_max = getattr(p, "sor_max", 10)
+    s.sor_tol = getattr(p, "sor_tol", 1e-7)
     return s
 
 

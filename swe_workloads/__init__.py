@@ -42,7 +42,9 @@ class BC:
 
 @dataclasses.dataclass
 class Params:
-    """Solver constants of section 5 (alpha, tau, nu1..nu3, omega) plus eps and tol."""
+    """Solver constants of section 5 (alpha, tau, nu1..nu3, omega) plus eps and tol; linear
+    selects the inner solver (0: multigrid, 1: Newton-SOR multicolour, 2: Newton-SOR
+    lexicographic) with the Newton-SOR stopping rule of section 5.1.1 (sor_max, sor_tol)."""
     alpha: float = 3.0
     tau: float = 0.6
     eps: float = 0.01
@@ -52,6 +54,9 @@ class Params:
     nu3: int = 2
     tol: float = 1e-10
     n_max: int = 2000
+    linear: int = 0
+    sor_max: int = 10
+    sor_tol: float = 1e-7
 
 
 @dataclasses.dataclass

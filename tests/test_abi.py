@@ -40,7 +40,7 @@ def test_struct_sizes_match_header_layout():
     abi, _ = _lib()
     assert ctypes.sizeof(abi.nmg_bc) == 40
     assert ctypes.sizeof(abi.nmg_desc) == 24 + 40 + 4 * 40 + 8 + 5 * 8
-    assert ctypes.sizeof(abi.nmg_params) == 5 * 8 + 6 * 4
+    assert ctypes.sizeof(abi.nmg_params) == 5 * 8 + 8 * 4 + 8
 
 
 def _desc(abi, nx=64, levels=3, jac=3):

@@ -1,0 +1,75 @@
+"""Newton-SOR (the reference solver of section 5.1.1 / Table 2) on the GPU against the oracle:
+the lexicographic symmetric sweep reproduces the oracle's Newton-SOR to the bit budget of the
+parity bar, the multicolour variant its trajectory; both inner iterations stop by the l1 change
+of dU or the step limit."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from swe_workloads import config1, config4_instance, e1_problem  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _sor_problem(prob, linear):
+    return dataclasses.replace(prob, params=dataclasses.replace(prob.params, linear=linear, sor_max=10,
+                                                                sor_tol=1e-7))
+
+
+def test_lexicographic_newton_sor_matches_the_oracle():
+    """E1 on 96 cells (Table 2's smallest grid): full solve, same step count, same state."""
+    from paper_2505_10857_amd import Solver1D
+    prob = _sor_problem(e1_problem(96), 2)
+    s = Solver1D(prob, device=DEV, check_every=1)
+    U = s.state()
+    st, _ = s.newton_solve(U)
+    Uo, ito, reso, _ = oracle.Oracle1D(prob).newton_solve(linear=1, smoother=1, sor_max=10, sor_tol=1e-7)
+    err = np.abs(U.cpu().numpy() - Uo).max()
+    print("lex Newton-SOR:", st.iters, ito, st.res, reso, err)
+    assert st.status == 0 and reso < prob.params.tol
+    assert abs(st.iters - ito) <= 1
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("name,prob", [("cfg1", config1(0)), ("cfg4", config4_instance(5))])
+def test_multicolour_newton_sor_trajectory(name, prob):
+    """Five Newton-SOR steps with the multicolour symmetric step: state within 1e-10."""
+    from paper_2505_10857_amd import Solver1D
+    p = _sor_problem(prob, 1)
+    s = Solver1D(p, device=DEV, check_every=1, n_max=5)
+    U = s.state()
+    st, hist = s.newton_solve(U, max_hist=5)
+    Uo, ito, reso, hist_o = oracle.Oracle1D(p).newton_solve(linear=1, smoother=0, sor_max=10, sor_tol=1e-7,
+                                                            n_max=5)
+    err = np.abs(U.cpu().numpy() - Uo).max() / np.abs(Uo).max()
+    print(name, "mc Newton-SOR 5 steps:", hist, hist_o, err)
+    assert st.iters == ito == 5
+    assert err <= 1e-10
+
+
+def test_newton_sor_batch_equals_single():
+    from paper_2505_10857_amd import BatchSolver1D
+    probs = [_sor_problem(p, 1) for p in (config1(1), config4_instance(9), config1(3))]
+    alone = []
+    for p in probs:
+        b = BatchSolver1D([p], device=DEV)
+        Us = b.states()
+        r = b.solve(Us, use_graph=False)
+        alone.append((Us[0].clone(), r[0]))
+    mix = BatchSolver1D(probs, device=DEV)
+    Us = mix.states()
+    rs = mix.solve(Us, use_graph=True)
+    for k in range(len(probs)):
+        assert rs[k][0] == alone[k][1][0]
+        assert torch.equal(Us[k], alone[k][0])
