@@ -6,8 +6,9 @@
 //   partial  : double[residual tiles]      (per-tile sums of ||R_ij||_1)
 //   hist     : double[max_hist]
 //   R, rn    : double [3][ny][nx], [ny][nx]
-//   mg       : per level: J [nb*9][n_l], Dinv [9][n_l], rhs [3][n_l], dU [3][n_l]
-//              in double (NMG_FP64) or float (NMG_FP32_MG)
+//   mg       : per level: J [nb*9][M_l], Dinv [9][M_l], rhs [3][M_l], dU [3][M_l]
+//              in double (NMG_FP64) or float (NMG_FP32_MG), cells in the level's colour-blocked
+//              order (M_l slots, Perm2D); the caller's arrays stay in the natural order
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -115,7 +116,8 @@ nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p, bool need_
         L.nx = d->nx >> l;
         L.ny = d->ny >> l;
         L.nb = l == 0 ? 9 : 5;
-        const long long n = (long long)L.nx * L.ny;
+        L.P = make_perm2d(L.nx, L.ny, l == 0 ? 3 : 2);   // colours of the cross / five-point stencil
+        const long long n = L.P.M;
         L.J = e; e += (long long)L.nb * 9 * n;
         L.Dinv = e; e += 9 * n;
         L.rhs = e; e += 3 * n;
@@ -139,7 +141,7 @@ nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p, bool need_
 nmg_status smooth_iter(const Plan2D &P, char *mgb, int l, hipStream_t s)
 {
     const Level2D &L = P.L[l];
-    const int C = L.nb == 5 ? 2 : 3;
+    const int C = L.P.C;
     for (int rep = 0; rep < 2; rep++) {
         for (int c = 0; c < C; c++) HIP_TRY2(launch_smooth2d_pass(mgb, L, c, P.omega, P.prec, s));
         for (int c = C - 1; c >= 0; c--) HIP_TRY2(launch_smooth2d_pass(mgb, L, c, P.omega, P.prec, s));
@@ -189,10 +191,10 @@ nmg_status newton_step(const Plan2D &P, char *w, double *U, hipStream_t s)
     const Level2D &L0 = P.L[0];
     const long long n0 = (long long)L0.nx * L0.ny;
     NewtonState *S = (NewtonState *)(w + P.off_state);
-    HIP_TRY2(launch_jacobian2d(I, mgb + vsz * L0.J, mgb + vsz * L0.rhs, mgb + vsz * L0.Dinv, P.prec, s));
+    HIP_TRY2(launch_jacobian2d(I, L0.P, mgb + vsz * L0.J, mgb + vsz * L0.rhs, mgb + vsz * L0.Dinv, P.prec, s));
     nmg_status st = coarsen_all(P, mgb, s);
     if (st != NMG_OK) return st;
-    HIP_TRY2(launch_fill(mgb + vsz * L0.dU, P.prec, 3 * n0, s));
+    HIP_TRY2(launch_fill(mgb + vsz * L0.dU, P.prec, 3 * L0.P.M, s));
     for (int m = 0; m < P.nu3; m++)
         if ((st = vcycle_from(P, mgb, 0, s)) != NMG_OK) return st;
     HIP_TRY2(launch_update2d(U, mgb, L0, P.tau, S, P.prec, s));
@@ -253,7 +255,7 @@ nmg_status jacobian2d(const nmg_desc *d, const nmg_params *p, const double *U, c
     I.U = const_cast<double *>(U);
     I.R = const_cast<double *>(R);
     I.rn = const_cast<double *>(rn);
-    HIP_TRY2(launch_jacobian2d(I, J, nullptr, nullptr, NMG_FP64, s));
+    HIP_TRY2(launch_jacobian2d(I, make_perm2d(d->nx, d->ny, 1), J, nullptr, nullptr, NMG_FP64, s));
     return NMG_OK;
 }
 
@@ -268,16 +270,15 @@ nmg_status vcycle2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_
     char *mgb = (char *)ws + P.off_mg;
     const size_t vsz = P.prec == NMG_FP32_MG ? 4 : 8;
     const Level2D &L0 = P.L[0];
-    const long long n0 = (long long)L0.nx * L0.ny;
     if (setup) {
-        HIP_TRY2(launch_convert(J, NMG_FP64, mgb + vsz * L0.J, P.prec, 81 * n0, s));
-        HIP_TRY2(launch_dinv2d((const double *)J, mgb + vsz * L0.Dinv, n0, P.prec, s));
+        HIP_TRY2(launch_permute2d(J, NMG_FP64, mgb + vsz * L0.J, P.prec, L0, 81, 1, s));
+        HIP_TRY2(launch_dinv2d((const double *)J, mgb + vsz * L0.Dinv, L0, P.prec, s));
         if ((st = coarsen_all(P, mgb, s)) != NMG_OK) return st;
     }
-    HIP_TRY2(launch_convert(rhs, P.prec, mgb + vsz * L0.rhs, P.prec, 3 * n0, s));
-    HIP_TRY2(launch_convert(dU, P.prec, mgb + vsz * L0.dU, P.prec, 3 * n0, s));
+    HIP_TRY2(launch_permute2d(rhs, P.prec, mgb + vsz * L0.rhs, P.prec, L0, 3, 1, s));
+    HIP_TRY2(launch_permute2d(dU, P.prec, mgb + vsz * L0.dU, P.prec, L0, 3, 1, s));
     if ((st = vcycle_from(P, mgb, 0, s)) != NMG_OK) return st;
-    HIP_TRY2(launch_convert(mgb + vsz * L0.dU, P.prec, dU, P.prec, 3 * n0, s));
+    HIP_TRY2(launch_permute2d(mgb + vsz * L0.dU, P.prec, dU, P.prec, L0, 3, 0, s));
     return NMG_OK;
 }
 

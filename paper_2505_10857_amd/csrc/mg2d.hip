@@ -2,7 +2,12 @@
 // coarse operators of eq. (24) (cross stencil -> five points on level 1, five points -> five
 // points below), multicolour block SOR passes (eq. 22), restriction, injection prolongation,
 // and Gaussian elimination with partial pivoting on the coarsest grid (dense, in LDS).
-// One thread per cell or coarse cell; the sums run in the order of the definitions.
+//
+// Every level keeps its per-cell arrays in colour-blocked order (Perm2D): a colour pass of the
+// smoother touches only the cells of one colour, and with the colours stored apart it reads them
+// contiguously instead of pulling whole cache lines of interleaved colours.  One thread per cell
+// or coarse cell; the sums run in the order of the definitions, so no result depends on the
+// layout.
 #include <algorithm>
 
 #include "nmg_common.h"
@@ -61,8 +66,8 @@ __global__ void k_coarsen2d(T *mg, Level2D Lf, Level2D Lc)
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int Jq = blockIdx.y;
     if (I >= Lc.nx || Jq >= Lc.ny) return;
-    const long long nf = (long long)Lf.nx * Lf.ny, nc = (long long)Lc.nx * Lc.ny;
-    const long long cc = (long long)Jq * Lc.nx + I;
+    const long long nf = Lf.P.M, nc = Lc.P.M;
+    const long long cc = perm2d(Lc.P, I, Jq);
     double D[9];
     for (int bc = 0; bc < 5; bc++) {
         int dP, dQ;
@@ -73,16 +78,17 @@ __global__ void k_coarsen2d(T *mg, Level2D Lf, Level2D Lc)
         for (int e = 0; e < 9; e++) blk[e] = 0.0;
         if (P >= 0 && P < Lc.nx && Q >= 0 && Q < Lc.ny) {
             for (int fj = 2 * Jq; fj <= 2 * Jq + 1; fj++)
-                for (int fi = 2 * I; fi <= 2 * I + 1; fi++)
+                for (int fi = 2 * I; fi <= 2 * I + 1; fi++) {
+                    const long long fc = perm2d(Lf.P, fi, fj);
                     for (int cj = 2 * Q; cj <= 2 * Q + 1; cj++)
                         for (int ci = 2 * P; ci <= 2 * P + 1; ci++) {
                             const int b = find_off(Lf.nb, ci - fi, cj - fj);
                             if (b < 0) continue;
-                            const long long fc = (long long)fj * Lf.nx + fi;
 #pragma unroll
                             for (int e = 0; e < 9; e++)
                                 blk[e] = blk[e] + ld2(mg + Lf.J, (b * 9 + e) * nf + fc);
                         }
+                }
         }
 #pragma unroll
         for (int e = 0; e < 9; e++) {
@@ -96,16 +102,18 @@ __global__ void k_coarsen2d(T *mg, Level2D Lf, Level2D Lc)
     for (int e = 0; e < 9; e++) mg[Lc.Dinv + e * nc + cc] = (T)B[e];
 }
 
-// One colour pass of eq. (22) on one level: cells with (i + j) mod C == colour.
+// One colour pass of eq. (22) on one level: the cells with (i + j) mod C == colour, thread
+// (k, j) taking the k-th cell of that colour in row j (contiguous slots of the colour block).
 template <typename T>
 __global__ void k_smooth2d_pass(T *mg, Level2D L, int colour, double omega)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= L.nx || j >= L.ny) return;
-    const int C = L.nb == 5 ? 2 : 3;
-    if ((i + j) % C != colour) return;
-    const long long n = (long long)L.nx * L.ny, cc = (long long)j * L.nx + i;
+    if (k >= L.P.W || j >= L.ny) return;
+    const int C = L.P.C;
+    const int i = ((colour - j) % C + C) % C + C * k;
+    if (i >= L.nx) return;
+    const long long n = L.P.M, cc = (long long)colour * L.ny * L.P.W + (long long)j * L.P.W + k;
     double r[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) r[c] = ld2(mg + L.rhs, c * n + cc);
@@ -114,7 +122,7 @@ __global__ void k_smooth2d_pass(T *mg, Level2D L, int colour, double omega)
         stencil_off(L.nb, b, di, dj);
         const int pi = i + di, pj = j + dj;
         if (pi < 0 || pi >= L.nx || pj < 0 || pj >= L.ny) continue;
-        const long long nc2 = (long long)pj * L.nx + pi;
+        const long long nc2 = perm2d(L.P, pi, pj);
         const double x0 = ld2(mg + L.dU, nc2), x1 = ld2(mg + L.dU, n + nc2), x2 = ld2(mg + L.dU, 2 * n + nc2);
 #pragma unroll
         for (int c = 0; c < 3; c++)
@@ -141,11 +149,11 @@ __global__ void k_restrict2d(T *mg, Level2D Lf, Level2D Lc)
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int Jq = blockIdx.y;
     if (I >= Lc.nx || Jq >= Lc.ny) return;
-    const long long nf = (long long)Lf.nx * Lf.ny, nc = (long long)Lc.nx * Lc.ny;
+    const long long nf = Lf.P.M, nc = Lc.P.M;
     double s[3] = {0.0, 0.0, 0.0};
     for (int fj = 2 * Jq; fj <= 2 * Jq + 1; fj++)
         for (int fi = 2 * I; fi <= 2 * I + 1; fi++) {
-            const long long fc = (long long)fj * Lf.nx + fi;
+            const long long fc = perm2d(Lf.P, fi, fj);
             double a[3];
 #pragma unroll
             for (int c = 0; c < 3; c++) a[c] = ld2(mg + Lf.rhs, c * nf + fc);
@@ -154,7 +162,7 @@ __global__ void k_restrict2d(T *mg, Level2D Lf, Level2D Lc)
                 stencil_off(Lf.nb, b, di, dj);
                 const int pi = fi + di, pj = fj + dj;
                 if (pi < 0 || pi >= Lf.nx || pj < 0 || pj >= Lf.ny) continue;
-                const long long q = (long long)pj * Lf.nx + pi;
+                const long long q = perm2d(Lf.P, pi, pj);
                 const double x0 = ld2(mg + Lf.dU, q), x1 = ld2(mg + Lf.dU, nf + q), x2 = ld2(mg + Lf.dU, 2 * nf + q);
 #pragma unroll
                 for (int c = 0; c < 3; c++)
@@ -165,7 +173,7 @@ __global__ void k_restrict2d(T *mg, Level2D Lf, Level2D Lc)
 #pragma unroll
             for (int c = 0; c < 3; c++) s[c] = s[c] + a[c];
         }
-    const long long cc = (long long)Jq * Lc.nx + I;
+    const long long cc = perm2d(Lc.P, I, Jq);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         mg[Lc.rhs + c * nc + cc] = (T)s[c];
@@ -180,8 +188,8 @@ __global__ void k_prolong2d(T *mg, Level2D Lf, Level2D Lc)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= Lf.nx || j >= Lf.ny) return;
-    const long long nf = (long long)Lf.nx * Lf.ny, nc = (long long)Lc.nx * Lc.ny;
-    const long long fc = (long long)j * Lf.nx + i, pc = (long long)(j >> 1) * Lc.nx + (i >> 1);
+    const long long nf = Lf.P.M, nc = Lc.P.M;
+    const long long fc = perm2d(Lf.P, i, j), pc = perm2d(Lc.P, i >> 1, j >> 1);
 #pragma unroll
     for (int c = 0; c < 3; c++)
         mg[Lf.dU + c * nf + fc] = (T)(ld2(mg + Lf.dU, c * nf + fc) + ld2(mg + Lc.dU, c * nc + pc));
@@ -198,6 +206,7 @@ __global__ void __launch_bounds__(256) k_coarse_solve2d(T *mg, Level2D L)
     __shared__ double f[MM];
     __shared__ int piv_s;
     const int nx = L.nx, ny = L.ny, n = nx * ny, M = 3 * n;
+    const long long Ms = L.P.M;
     const int t = threadIdx.x;
     for (int e = t; e < M * M; e += 256) A[e] = 0.0;
     __syncthreads();
@@ -208,11 +217,15 @@ __global__ void __launch_bounds__(256) k_coarse_solve2d(T *mg, Level2D L)
         stencil_off(L.nb, b, di, dj);
         const int pi = i + di, pj = j + dj;
         if (pi < 0 || pi >= nx || pj < 0 || pj >= ny) continue;
+        const long long q = perm2d(L.P, i, j);
         for (int r = 0; r < 3; r++)
             for (int c = 0; c < 3; c++)
-                A[(cell * 3 + r) * M + (pj * nx + pi) * 3 + c] = ld2(mg + L.J, (b * 9 + r * 3 + c) * (long long)n + cell);
+                A[(cell * 3 + r) * M + (pj * nx + pi) * 3 + c] = ld2(mg + L.J, (b * 9 + r * 3 + c) * Ms + q);
     }
-    for (int r = t; r < M; r += 256) x[r] = -ld2(mg + L.rhs, (r % 3) * (long long)n + r / 3);
+    for (int r = t; r < M; r += 256) {
+        const int cell = r / 3;
+        x[r] = -ld2(mg + L.rhs, (r % 3) * Ms + perm2d(L.P, cell % nx, cell / nx));
+    }
     __syncthreads();
     for (int k = 0; k < M; k++) {
         if (t == 0) {
@@ -252,20 +265,39 @@ __global__ void __launch_bounds__(256) k_coarse_solve2d(T *mg, Level2D L)
         }
     }
     __syncthreads();
-    for (int r = t; r < M; r += 256) mg[L.dU + (r % 3) * (long long)n + r / 3] = (T)x[r];
+    for (int r = t; r < M; r += 256) {
+        const int cell = r / 3;
+        mg[L.dU + (r % 3) * Ms + perm2d(L.P, cell % nx, cell / nx)] = (T)x[r];
+    }
 }
 
-// inverse of the centre blocks of an FP64 level-0 operator [nb*9][n] (block 0 first)
+// inverse of the centre blocks of an FP64 level-0 operator in the natural order ([nb*9][n],
+// block 0 first), written in the level's order
 template <typename T>
-__global__ void k_dinv2d(const double *J, T *Dinv, long long n)
+__global__ void k_dinv2d(const double *J, T *Dinv, Level2D L0)
 {
+    const long long n = (long long)L0.nx * L0.ny;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
         double D[9], B[9];
 #pragma unroll
         for (int e = 0; e < 9; e++) D[e] = J[e * n + c];
         inv3d(D, B);
+        const long long q = perm2d(L0.P, (int)(c % L0.nx), (int)(c / L0.nx));
 #pragma unroll
-        for (int e = 0; e < 9; e++) Dinv[e * n + c] = (T)B[e];
+        for (int e = 0; e < 9; e++) Dinv[e * L0.P.M + q] = (T)B[e];
+    }
+}
+
+// per-cell entries between the natural order [nent][n] and a level's order [nent][M]
+template <typename S, typename D>
+__global__ void k_permute2d(const S *src, D *dst, Level2D L, int nent, int to_level)
+{
+    const long long n = (long long)L.nx * L.ny, total = n * nent;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+        const long long c = e % n, a = e / n;
+        const long long q = perm2d(L.P, (int)(c % L.nx), (int)(c / L.nx));
+        if (to_level) dst[a * L.P.M + q] = (D)src[e];
+        else dst[e] = (D)src[a * L.P.M + q];
     }
 }
 
@@ -276,14 +308,18 @@ __global__ void k_fill(T *p, long long n)
         p[i] = (T)0.0;
 }
 
-// eq. (14): U <- U + tau dU (skipped once the Newton iteration has stopped)
+// eq. (14): U <- U + tau dU (skipped once the Newton iteration has stopped); U in the natural
+// order [3][ny][nx]
 template <typename T>
 __global__ void k_update2d(double *U, const T *mg, Level2D L0, double tau, const NewtonState *S)
 {
     if (S && !S->active) return;
     const long long n = (long long)L0.nx * L0.ny;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < 3 * n; e += (long long)gridDim.x * blockDim.x)
-        U[e] = U[e] + tau * ld2(mg + L0.dU, e);
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < 3 * n; e += (long long)gridDim.x * blockDim.x) {
+        const long long c = e % n, comp = e / n;
+        const long long q = perm2d(L0.P, (int)(c % L0.nx), (int)(c / L0.nx));
+        U[e] = U[e] + tau * ld2(mg + L0.dU, comp * L0.P.M + q);
+    }
 }
 
 // res from the tile partials, Newton counter and stopping test (Algorithm 1)
@@ -329,7 +365,7 @@ hipError_t launch_coarsen2d(void *mg, const Level2D &Lf, const Level2D &Lc, int 
 
 hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, double omega, int prec, hipStream_t s)
 {
-    dim3 grid((L.nx + 63) / 64, (L.ny + 3) / 4);
+    dim3 grid((L.P.W + 63) / 64, (L.ny + 3) / 4);
     DISPATCH(prec, k_smooth2d_pass, grid, dim3(64, 4), L, colour, omega);
     return hipGetLastError();
 }
@@ -375,11 +411,34 @@ hipError_t launch_update2d(double *U, const void *mg, const Level2D &L0, double 
     return hipGetLastError();
 }
 
-hipError_t launch_dinv2d(const double *J, void *Dinv, long long n, int prec, hipStream_t s)
+hipError_t launch_dinv2d(const double *J, void *Dinv, const Level2D &L0, int prec, hipStream_t s)
 {
+    const long long n = (long long)L0.nx * L0.ny;
     int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
-    if (prec == NMG_FP32_MG) hipLaunchKernelGGL(k_dinv2d<float>, dim3(blocks), dim3(256), 0, s, J, (float *)Dinv, n);
-    else hipLaunchKernelGGL(k_dinv2d<double>, dim3(blocks), dim3(256), 0, s, J, (double *)Dinv, n);
+    if (prec == NMG_FP32_MG) hipLaunchKernelGGL(k_dinv2d<float>, dim3(blocks), dim3(256), 0, s, J, (float *)Dinv, L0);
+    else hipLaunchKernelGGL(k_dinv2d<double>, dim3(blocks), dim3(256), 0, s, J, (double *)Dinv, L0);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute2d(const void *src, int src_prec, void *dst, int dst_prec, const Level2D &L, int nent,
+                            int to_level, hipStream_t s)
+{
+    const long long total = (long long)L.nx * L.ny * nent;
+    int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
+    if (blocks < 1) return hipSuccess;
+    const bool s32 = src_prec == NMG_FP32_MG, d32 = dst_prec == NMG_FP32_MG;
+    if (!s32 && !d32)
+        hipLaunchKernelGGL((k_permute2d<double, double>), dim3(blocks), dim3(256), 0, s, (const double *)src,
+                           (double *)dst, L, nent, to_level);
+    else if (!s32)
+        hipLaunchKernelGGL((k_permute2d<double, float>), dim3(blocks), dim3(256), 0, s, (const double *)src,
+                           (float *)dst, L, nent, to_level);
+    else if (!d32)
+        hipLaunchKernelGGL((k_permute2d<float, double>), dim3(blocks), dim3(256), 0, s, (const float *)src,
+                           (double *)dst, L, nent, to_level);
+    else
+        hipLaunchKernelGGL((k_permute2d<float, float>), dim3(blocks), dim3(256), 0, s, (const float *)src,
+                           (float *)dst, L, nent, to_level);
     return hipGetLastError();
 }
 

@@ -84,10 +84,39 @@ struct Inst2D {
     double alpha, eps;
 };
 
-// One 2D multigrid level: blocks J [nb*9][n], Dinv [9][n], rhs [3][n], dU [3][n] (cell j*nx+i);
-// offsets in elements of the value type.
+// Colour-blocked cell order of a 2D level: the cells of colour c = (i + j) mod C are stored
+// together, row by row, so that a colour pass of the smoother reads contiguous data.  Cell
+// (i, j) sits at c*ny*W + j*W + (i - i_c(j)) / C, i_c(j) the first column of colour c in row j and
+// W = ceil(nx / C) slots per row and colour; C = 1 is the natural order j*nx + i.
+struct Perm2D {
+    int C, W, ny, pad;
+    long long M;       // slots per array: C * ny * W
+};
+
+__host__ __device__ inline long long perm2d(const Perm2D &P, int i, int j)
+{
+    const int c = (i + j) % P.C;
+    const int ic = ((c - j) % P.C + P.C) % P.C;
+    return (long long)c * P.ny * P.W + (long long)j * P.W + (i - ic) / P.C;
+}
+
+inline Perm2D make_perm2d(int nx, int ny, int C)
+{
+    Perm2D P;
+    P.C = C;
+    P.W = (nx + C - 1) / C;
+    P.ny = ny;
+    P.pad = 0;
+    P.M = (long long)C * ny * P.W;
+    return P;
+}
+
+// One 2D multigrid level: blocks J [nb*9][M], Dinv [9][M], rhs [3][M], dU [3][M] in the level's
+// colour-blocked order (C = 3 on the nine-block finest level, 2 on five-point levels); offsets
+// in elements of the value type.
 struct Level2D {
     int nx, ny, nb, pad;
+    Perm2D P;
     long long J, Dinv, rhs, dU;
 };
 
@@ -131,7 +160,9 @@ int residual2d_tiles(int Nx, int Ny);
 hipError_t launch_residual2d(const Inst2D &I, double *partial, hipStream_t s);
 hipError_t launch_res2d_finalize(const double *partial, int ntiles, long long ncells, double *res,
                                  hipStream_t s);
-hipError_t launch_jacobian2d(const Inst2D &I, void *J, void *rhs, void *Dinv, int prec, hipStream_t s);
+// J, rhs, Dinv written in the cell order P (make_perm2d(Nx, Ny, 1) for the natural order)
+hipError_t launch_jacobian2d(const Inst2D &I, const Perm2D &P, void *J, void *rhs, void *Dinv, int prec,
+                             hipStream_t s);
 hipError_t launch_coarsen2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
 hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, double omega, int prec, hipStream_t s);
 hipError_t launch_restrict2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
@@ -140,7 +171,10 @@ hipError_t launch_coarse_solve2d(void *mg, const Level2D &L, int prec, hipStream
 hipError_t launch_fill(void *p, int prec, long long n, hipStream_t s);
 hipError_t launch_update2d(double *U, const void *mg, const Level2D &L0, double tau,
                            const NewtonState *state, int prec, hipStream_t s);
-hipError_t launch_dinv2d(const double *J, void *Dinv, long long n, int prec, hipStream_t s);
+hipError_t launch_dinv2d(const double *J, void *Dinv, const Level2D &L0, int prec, hipStream_t s);
+// nent per-cell entries between the natural order (src or dst, per `to_level`) and a level's order
+hipError_t launch_permute2d(const void *src, int src_prec, void *dst, int dst_prec, const Level2D &L, int nent,
+                            int to_level, hipStream_t s);
 hipError_t launch_state2d(const double *partial, int ntiles, long long ncells, double tol, int n_max,
                           NewtonState *state, double *hist, int max_hist, int init, hipStream_t s);
 constexpr int kMaxCoarse2D = 40;   // cells on the coarsest 2D level (dense solve in LDS)

@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(256) k_res2d_finalize(const double *partial, i
 // J[(b*9 + l*3 + m) * n + cell] for the blocks b of (centre, x-2, x-1, x+1, x+2, y-2, y-1, y+1,
 // y+2).  Optionally the finest right-hand side (= R) and the inverse of the diagonal block.
 template <typename T>
-__global__ void __launch_bounds__(kTX * kTY) k_jacobian2d(Inst2D I, T *J, T *rhs, T *Dinv)
+__global__ void __launch_bounds__(kTX * kTY) k_jacobian2d(Inst2D I, Perm2D Pm, T *J, T *rhs, T *Dinv)
 {
     __shared__ double s[3 * kSY * kSX];
     const int i0 = blockIdx.x * kTX, j0 = blockIdx.y * kTY;
@@ -372,12 +372,13 @@ __global__ void __launch_bounds__(kTX * kTY) k_jacobian2d(Inst2D I, T *J, T *rhs
     const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
     if (i >= I.Nx || j >= I.Ny) return;
     const long long n = (long long)I.Nx * I.Ny, cidx = (long long)j * I.Nx + i;
+    const long long M = Pm.M, pidx = perm2d(Pm, i, j);   // output slot of this cell
     const double R0[3] = {I.R[cidx], I.R[n + cidx], I.R[2 * n + cidx]};
     const double rn = I.rn[cidx];
     if (rhs) {
-        rhs[cidx] = (T)R0[0];
-        rhs[n + cidx] = (T)R0[1];
-        rhs[2 * n + cidx] = (T)R0[2];
+        rhs[pidx] = (T)R0[0];
+        rhs[M + pidx] = (T)R0[1];
+        rhs[2 * M + pidx] = (T)R0[2];
     }
     const Stage S{s, i0, j0};
     const int offx[9] = {0, -2, -1, 1, 2, 0, 0, 0, 0};
@@ -398,7 +399,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_jacobian2d(Inst2D I, T *J, T *rhs
             }
 #pragma unroll
             for (int l = 0; l < 3; l++) {
-                J[(b * 9 + l * 3 + m) * n + cidx] = (T)col[l];
+                J[(b * 9 + l * 3 + m) * M + pidx] = (T)col[l];
                 if (b == 0) D[l * 3 + m] = col[l];
             }
         }
@@ -420,7 +421,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_jacobian2d(Inst2D I, T *J, T *rhs
         B[7] = (D[1] * D[6] - D[0] * D[7]) / det;
         B[8] = (D[0] * D[4] - D[1] * D[3]) / det;
 #pragma unroll
-        for (int e = 0; e < 9; e++) Dinv[e * n + cidx] = (T)B[e];
+        for (int e = 0; e < 9; e++) Dinv[e * M + pidx] = (T)B[e];
     }
 }
 
@@ -442,13 +443,16 @@ hipError_t launch_res2d_finalize(const double *partial, int ntiles, long long nc
     return hipGetLastError();
 }
 
-hipError_t launch_jacobian2d(const Inst2D &I, void *J, void *rhs, void *Dinv, int prec, hipStream_t s)
+hipError_t launch_jacobian2d(const Inst2D &I, const Perm2D &P, void *J, void *rhs, void *Dinv, int prec,
+                             hipStream_t s)
 {
     dim3 grid((I.Nx + kTX - 1) / kTX, (I.Ny + kTY - 1) / kTY);
     if (prec == NMG_FP32_MG)
-        hipLaunchKernelGGL(k_jacobian2d<float>, grid, dim3(kTX, kTY), 0, s, I, (float *)J, (float *)rhs, (float *)Dinv);
+        hipLaunchKernelGGL(k_jacobian2d<float>, grid, dim3(kTX, kTY), 0, s, I, P, (float *)J, (float *)rhs,
+                           (float *)Dinv);
     else
-        hipLaunchKernelGGL(k_jacobian2d<double>, grid, dim3(kTX, kTY), 0, s, I, (double *)J, (double *)rhs, (double *)Dinv);
+        hipLaunchKernelGGL(k_jacobian2d<double>, grid, dim3(kTX, kTY), 0, s, I, P, (double *)J, (double *)rhs,
+                           (double *)Dinv);
     return hipGetLastError();
 }
 

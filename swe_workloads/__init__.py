@@ -423,3 +423,22 @@ def parabolic_bump_2d(nx: int = 16, ny: int = 8, levels: Optional[int] = None,
     return Problem2D("bump2d", -4.0, 4.0, 0.0, 4.0, nx, ny, levels, bottom,
                      [BC(BC_DISCHARGE, q=1.0), BC(BC_DEPTH, h=1.0), BC(BC_WALL), BC(BC_WALL)], p,
                      init_state=(1.0, 1.0, 0.0))
+
+
+def synthetic_operator_2d(nx: int, ny: int, seed: int = 0, dominance: float = 3.0, spread: float = 0.1):
+    """A seeded block operator with the shape of the 2D simplified Jacobian J9 (eq. 21): blocks
+    [ny][nx][9][3][3] in the cross order (centre, x-2, x-1, x+1, x+2, y-2, y-1, y+1, y+2), entries
+    U(-spread, spread) plus dominance * I on the centre block, and a right-hand side [ny][nx][3]
+    with entries U(-1, 1), from default_rng([7, seed]).  Blocks that would couple to cells
+    outside the grid are zero.  It stands in for the Jacobian of the 1024 x 512 wedge when only
+    the multigrid is exercised."""
+    rng = np.random.default_rng([7, seed])
+    J = rng.uniform(-spread, spread, (ny, nx, 9, 3, 3))
+    J[:, :, 0] += dominance * np.eye(3)
+    offs = [(0, 0), (-2, 0), (-1, 0), (1, 0), (2, 0), (0, -2), (0, -1), (0, 1), (0, 2)]
+    ii, jj = np.meshgrid(np.arange(nx), np.arange(ny))
+    for b, (di, dj) in enumerate(offs):
+        out = (ii + di < 0) | (ii + di >= nx) | (jj + dj < 0) | (jj + dj >= ny)
+        J[out, b] = 0.0
+    rhs = rng.uniform(-1.0, 1.0, (ny, nx, 3))
+    return J, rhs

@@ -267,3 +267,21 @@ def test_rejects_bad_2d_descriptors():
         _solver(prob, levels=2).workspace()            # coarsest 16 x 8 > 40 cells
     with pytest.raises(A.NmgError):
         _solver(prob, levels=7).workspace()            # 32 not divisible by 64
+
+
+def test_full_size_vcycle_on_the_wedge_grid():
+    """1024 x 512, 8 levels, nu = 20, omega = 0.05 (the wedge's launch configuration): one
+    V-cycle on a seeded J9-shaped operator equals the oracle's."""
+    from swe_workloads import synthetic_operator_2d
+    prob = wedge_problem(1024, 512)
+    Jo, rhs_o = synthetic_operator_2d(1024, 512, seed=1)
+    p = prob.params
+    s = _solver(prob)
+    J = torch.tensor(np.ascontiguousarray(Jo.transpose(2, 3, 4, 0, 1)), dtype=torch.float64, device=DEV)
+    rhs = torch.tensor(np.ascontiguousarray(rhs_o.transpose(2, 0, 1)), dtype=torch.float64, device=DEV)
+    dU = torch.zeros((3, 512, 1024), dtype=torch.float64, device=DEV)
+    s.vcycle(J, rhs, dU, setup=True)
+    d1 = vcycles2d(Jo, rhs_o, levels=prob.levels, ncycles=1, omega=p.omega, nu1=p.nu1, nu2=p.nu2)
+    e = _rel(dU.cpu().numpy().transpose(1, 2, 0), d1)
+    print(f"1024x512 V-cycle rel err {e:.3e}")
+    assert e <= 1e-12
