@@ -9,6 +9,7 @@
 //   mg       : per level: J [nb*9][M_l], Dinv [9][M_l], rhs [3][M_l], dU [3][M_l]
 //              in double (NMG_FP64) or float (NMG_FP32_MG), cells in the level's colour-blocked
 //              order (M_l slots, Perm2D); the caller's arrays stay in the natural order
+//   lu       : LU factors and row permutation of the coarsest operator (double [M][M], int [M])
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -35,7 +36,7 @@ struct Plan2D {
     int check_every = 1;
     double tau = 0.0, omega = 1.0, tol = 0.0;
     std::vector<Level2D> L;
-    size_t off_state = 0, off_partial = 0, off_hist = 0, off_R = 0, off_rn = 0, off_mg = 0, total = 0;
+    size_t off_state = 0, off_partial = 0, off_hist = 0, off_R = 0, off_rn = 0, off_mg = 0, off_lu = 0, total = 0;
 };
 
 nmg_status check2d(const nmg_desc *d, const nmg_params *p, bool need_geometry = true)
@@ -133,19 +134,30 @@ nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p, bool need_
     P.off_R = o; o = al256(o + sizeof(double) * 3 * n0);
     P.off_rn = o; o = al256(o + sizeof(double) * n0);
     P.off_mg = o; o = al256(o + vsz * (size_t)e);
+    const Level2D &Lc = P.L.back();
+    P.off_lu = o; o = al256(o + coarse_lu_bytes(3 * Lc.nx * Lc.ny));
     P.total = o;
     return NMG_OK;
 }
 
-// one smoothing iteration: two symmetric multicolour steps (colours 0..C-1, then C-1..0)
-nmg_status smooth_iter(const Plan2D &P, char *mgb, int l, hipStream_t s)
+// nu smoothing iterations on level l, each two symmetric multicolour steps (colours 0..C-1, then
+// C-1..0).  Consecutive passes of one colour (C-1 C-1 at a turn, 0 0 between steps) see the same
+// neighbour values and run as one launch that relaxes twice.
+nmg_status smooth(const Plan2D &P, char *mgb, int l, int nu, hipStream_t s)
 {
     const Level2D &L = P.L[l];
     const int C = L.P.C;
-    for (int rep = 0; rep < 2; rep++) {
-        for (int c = 0; c < C; c++) HIP_TRY2(launch_smooth2d_pass(mgb, L, c, P.omega, P.prec, s));
-        for (int c = C - 1; c >= 0; c--) HIP_TRY2(launch_smooth2d_pass(mgb, L, c, P.omega, P.prec, s));
-    }
+    int cur = -1, run = 0;
+    for (int it = 0; it < nu; it++)
+        for (int half = 0; half < 4; half++)
+            for (int q = 0; q < C; q++) {
+                const int c = (half & 1) ? C - 1 - q : q;
+                if (c == cur) { run++; continue; }
+                if (run > 0) HIP_TRY2(launch_smooth2d_pass(mgb, L, cur, run, P.omega, P.prec, s));
+                cur = c;
+                run = 1;
+            }
+    if (run > 0) HIP_TRY2(launch_smooth2d_pass(mgb, L, cur, run, P.omega, P.prec, s));
     return NMG_OK;
 }
 
@@ -153,23 +165,22 @@ nmg_status smooth_iter(const Plan2D &P, char *mgb, int l, hipStream_t s)
 nmg_status vcycle_from(const Plan2D &P, char *mgb, int l, hipStream_t s)
 {
     if (l == P.levels - 1) {
-        HIP_TRY2(launch_coarse_solve2d(mgb, P.L[l], P.prec, s));
+        HIP_TRY2(launch_coarse_apply2d(mgb, P.L[l], (const double *)(mgb - P.off_mg + P.off_lu), P.prec, s));
         return NMG_OK;
     }
     nmg_status st;
-    for (int k = 0; k < P.nu1; k++)
-        if ((st = smooth_iter(P, mgb, l, s)) != NMG_OK) return st;
+    if ((st = smooth(P, mgb, l, P.nu1, s)) != NMG_OK) return st;
     HIP_TRY2(launch_restrict2d(mgb, P.L[l], P.L[l + 1], P.prec, s));
     if ((st = vcycle_from(P, mgb, l + 1, s)) != NMG_OK) return st;
     HIP_TRY2(launch_prolong2d(mgb, P.L[l], P.L[l + 1], P.prec, s));
-    for (int k = 0; k < P.nu2; k++)
-        if ((st = smooth_iter(P, mgb, l, s)) != NMG_OK) return st;
-    return NMG_OK;
+    return smooth(P, mgb, l, P.nu2, s);
 }
 
+// coarse operators of every level below the finest, then the factors of the coarsest
 nmg_status coarsen_all(const Plan2D &P, char *mgb, hipStream_t s)
 {
     for (int l = 1; l < P.levels; l++) HIP_TRY2(launch_coarsen2d(mgb, P.L[l - 1], P.L[l], P.prec, s));
+    HIP_TRY2(launch_coarse_factor2d(mgb, P.L.back(), (double *)(mgb - P.off_mg + P.off_lu), P.prec, s));
     return NMG_OK;
 }
 

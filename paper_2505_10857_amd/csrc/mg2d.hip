@@ -102,18 +102,21 @@ __global__ void k_coarsen2d(T *mg, Level2D Lf, Level2D Lc)
     for (int e = 0; e < 9; e++) mg[Lc.Dinv + e * nc + cc] = (T)B[e];
 }
 
-// One colour pass of eq. (22) on one level: the cells with (i + j) mod C == colour, thread
-// (k, j) taking the k-th cell of that colour in row j (contiguous slots of the colour block).
+// `reps` consecutive passes of eq. (22) over the cells with (i + j) mod C == colour on one level,
+// thread p taking slot p of that colour's block (row p / W, k-th cell of the colour in the row).
+// Passes of one colour in a row see the same neighbour values, so the off-diagonal sum and
+// D^{-1} r are formed once and the relaxation is applied `reps` times, each result rounded to the
+// storage type as if it had been stored between the passes.
 template <typename T>
-__global__ void k_smooth2d_pass(T *mg, Level2D L, int colour, double omega)
+__global__ void __launch_bounds__(256) k_smooth2d_pass(T *mg, Level2D L, int colour, double omega, int reps)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (k >= L.P.W || j >= L.ny) return;
-    const int C = L.P.C;
+    const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const int W = L.P.W, C = L.P.C;
+    if (p >= (long long)L.ny * W) return;
+    const int j = (int)(p / W), k = (int)(p - (long long)j * W);
     const int i = ((colour - j) % C + C) % C + C * k;
     if (i >= L.nx) return;
-    const long long n = L.P.M, cc = (long long)colour * L.ny * L.P.W + (long long)j * L.P.W + k;
+    const long long n = L.P.M, cc = (long long)colour * L.ny * W + p;
     double r[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) r[c] = ld2(mg + L.rhs, c * n + cc);
@@ -137,8 +140,9 @@ __global__ void k_smooth2d_pass(T *mg, Level2D L, int colour, double omega)
                ld2(mg + L.Dinv, (c * 3 + 2) * n + cc) * r[2];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        const double d = ld2(mg + L.dU, c * n + cc);
-        mg[L.dU + c * n + cc] = (T)((1.0 - omega) * d - omega * t[c]);
+        T d = mg[L.dU + c * n + cc];
+        for (int q = 0; q < reps; q++) d = (T)((1.0 - omega) * (double)d - omega * t[c]);
+        mg[L.dU + c * n + cc] = d;
     }
 }
 
@@ -195,20 +199,33 @@ __global__ void k_prolong2d(T *mg, Level2D Lf, Level2D Lc)
         mg[Lf.dU + c * nf + fc] = (T)(ld2(mg + Lf.dU, c * nf + fc) + ld2(mg + Lc.dU, c * nc + pc));
 }
 
-// Coarsest level: dense Gaussian elimination with partial pivoting of sum J dU = -rhs
-// (unknown (j*nx + i)*3 + c), one workgroup, the matrix in LDS.
+// Coarsest level: Gaussian elimination with partial pivoting of the dense system sum J dU = -rhs
+// (unknown (j*nx + i)*3 + c), split into a factorisation done once per operator and a solve per
+// V-cycle.  The factorisation takes the pivots and eliminates exactly as the plain algorithm does
+// (largest magnitude, first on ties; rows with a zero multiplier untouched) and keeps, in the
+// workspace, the eliminated matrix with each multiplier in the place it eliminates (rows
+// interchanged whole, multipliers included) and the row permutation.  The solve then applies the
+// permutation to the right-hand side, the multipliers column by column (the same operations on
+// the same values as eliminating the right-hand side alongside), and back substitution.
+struct CoarseLU {
+    double *A;    // [M][M]
+    int *perm;    // [M]
+};
+
+__device__ __forceinline__ CoarseLU coarse_lu(double *base, int M) { return CoarseLU{base, (int *)(base + (long long)M * M)}; }
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_coarse_solve2d(T *mg, Level2D L)
+__global__ void __launch_bounds__(256) k_coarse_factor2d(T *mg, Level2D L, double *lu_base)
 {
     constexpr int MM = 3 * kMaxCoarse2D;
     __shared__ double A[MM * MM];
-    __shared__ double x[MM];
-    __shared__ double f[MM];
+    __shared__ int perm[MM];
     __shared__ int piv_s;
     const int nx = L.nx, ny = L.ny, n = nx * ny, M = 3 * n;
     const long long Ms = L.P.M;
     const int t = threadIdx.x;
     for (int e = t; e < M * M; e += 256) A[e] = 0.0;
+    for (int r = t; r < M; r += 256) perm[r] = r;
     __syncthreads();
     for (int e = t; e < n * L.nb; e += 256) {
         const int cell = e / L.nb, b = e % L.nb;
@@ -222,17 +239,21 @@ __global__ void __launch_bounds__(256) k_coarse_solve2d(T *mg, Level2D L)
             for (int c = 0; c < 3; c++)
                 A[(cell * 3 + r) * M + (pj * nx + pi) * 3 + c] = ld2(mg + L.J, (b * 9 + r * 3 + c) * Ms + q);
     }
-    for (int r = t; r < M; r += 256) {
-        const int cell = r / 3;
-        x[r] = -ld2(mg + L.rhs, (r % 3) * Ms + perm2d(L.P, cell % nx, cell / nx));
-    }
     __syncthreads();
     for (int k = 0; k < M; k++) {
-        if (t == 0) {
-            int p = k;
-            for (int r = k + 1; r < M; r++)
-                if (fabs(A[r * M + k]) > fabs(A[p * M + k])) p = r;
-            piv_s = p;
+        if (t < 64) {            // pivot: largest |A[r][k]|, r >= k, the first one on ties
+            int p = -1;
+            double v = -1.0;
+            for (int r = k + t; r < M; r += 64) {
+                const double a = fabs(A[r * M + k]);
+                if (a > v) { v = a; p = r; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double v2 = __shfl_xor(v, off, 64);
+                const int p2 = __shfl_xor(p, off, 64);
+                if (v2 > v || (v2 == v && p2 >= 0 && (p < 0 || p2 < p))) { v = v2; p = p2; }
+            }
+            if (t == 0) piv_s = p < 0 ? k : p;      // no comparable entry: keep the row
         }
         __syncthreads();
         const int p = piv_s;
@@ -242,29 +263,68 @@ __global__ void __launch_bounds__(256) k_coarse_solve2d(T *mg, Level2D L)
                 A[k * M + c] = A[p * M + c];
                 A[p * M + c] = y;
             }
-            if (t == 0) { const double y = x[k]; x[k] = x[p]; x[p] = y; }
+            if (t == 0) { const int y = perm[k]; perm[k] = perm[p]; perm[p] = y; }
         }
         __syncthreads();
-        for (int r = k + 1 + t; r < M; r += 256) f[r] = A[r * M + k] / A[k * M + k];
-        __syncthreads();
-        for (int e = t; e < (M - k - 1) * (M - k); e += 256) {
-            const int r = k + 1 + e / (M - k), c = k + e % (M - k);
-            if (f[r] != 0.0) A[r * M + c] -= f[r] * A[k * M + c];
+        const double akk = A[k * M + k];
+        // every thread reads column k before any row is updated
+        double fr[(MM + 255) / 256];
+#pragma unroll
+        for (int q = 0; q < (MM + 255) / 256; q++) {
+            const int r = k + 1 + t + 256 * q;
+            fr[q] = r < M ? A[r * M + k] / akk : 0.0;
         }
         __syncthreads();
-        if (t == 0)
-            for (int r = k + 1; r < M; r++)
-                if (f[r] != 0.0) x[r] -= f[r] * x[k];
+#pragma unroll
+        for (int q = 0; q < (MM + 255) / 256; q++) {
+            const int r = k + 1 + t + 256 * q;
+            if (r < M) A[r * M + k] = fr[q];
+        }
+        __syncthreads();
+        const int w = M - k - 1;
+        for (int e = t; e < w * w; e += 256) {
+            const int r = k + 1 + e / w, c = k + 1 + e % w;
+            const double f = A[r * M + k];
+            if (f != 0.0) A[r * M + c] -= f * A[k * M + c];
+        }
         __syncthreads();
     }
-    if (t == 0) {
-        for (int k = M - 1; k >= 0; k--) {
-            double s = x[k];
-            for (int c = k + 1; c < M; c++) s -= A[k * M + c] * x[c];
-            x[k] = s / A[k * M + k];
-        }
+    const CoarseLU lu = coarse_lu(lu_base, M);
+    for (int e = t; e < M * M; e += 256) lu.A[e] = A[e];
+    for (int r = t; r < M; r += 256) lu.perm[r] = perm[r];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse_apply2d(T *mg, Level2D L, const double *lu_base)
+{
+    constexpr int MM = 3 * kMaxCoarse2D;
+    __shared__ double A[MM * MM];
+    __shared__ double x[MM];
+    const int nx = L.nx, n = nx * L.ny, M = 3 * n;
+    const long long Ms = L.P.M;
+    const int t = threadIdx.x;
+    const CoarseLU lu = coarse_lu(const_cast<double *>(lu_base), M);
+    for (int e = t; e < M * M; e += 256) A[e] = lu.A[e];
+    for (int r = t; r < M; r += 256) {
+        const int src = lu.perm[r], cell = src / 3;
+        x[r] = -ld2(mg + L.rhs, (src % 3) * Ms + perm2d(L.P, cell % nx, cell / nx));
     }
     __syncthreads();
+    for (int k = 0; k < M - 1; k++) {
+        const double xk = x[k];
+        for (int r = k + 1 + t; r < M; r += 256) {
+            const double f = A[r * M + k];
+            if (f != 0.0) x[r] -= f * xk;
+        }
+        __syncthreads();
+    }
+    for (int k = M - 1; k >= 0; k--) {
+        if (t == 0) x[k] = x[k] / A[k * M + k];
+        __syncthreads();
+        const double xk = x[k];
+        for (int r = t; r < k; r += 256) x[r] -= A[r * M + k] * xk;
+        __syncthreads();
+    }
     for (int r = t; r < M; r += 256) {
         const int cell = r / 3;
         mg[L.dU + (r % 3) * Ms + perm2d(L.P, cell % nx, cell / nx)] = (T)x[r];
@@ -363,10 +423,12 @@ hipError_t launch_coarsen2d(void *mg, const Level2D &Lf, const Level2D &Lc, int 
     return hipGetLastError();
 }
 
-hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, double omega, int prec, hipStream_t s)
+hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, int reps, double omega, int prec,
+                               hipStream_t s)
 {
-    dim3 grid((L.P.W + 63) / 64, (L.ny + 3) / 4);
-    DISPATCH(prec, k_smooth2d_pass, grid, dim3(64, 4), L, colour, omega);
+    const long long slots = (long long)L.ny * L.P.W;
+    dim3 grid((unsigned)((slots + 255) / 256));
+    DISPATCH(prec, k_smooth2d_pass, grid, dim3(256), L, colour, omega, reps);
     return hipGetLastError();
 }
 
@@ -384,9 +446,15 @@ hipError_t launch_prolong2d(void *mg, const Level2D &Lf, const Level2D &Lc, int 
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_solve2d(void *mg, const Level2D &L, int prec, hipStream_t s)
+hipError_t launch_coarse_factor2d(void *mg, const Level2D &L, double *lu, int prec, hipStream_t s)
 {
-    DISPATCH(prec, k_coarse_solve2d, dim3(1), dim3(256), L);
+    DISPATCH(prec, k_coarse_factor2d, dim3(1), dim3(256), L, lu);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_apply2d(void *mg, const Level2D &L, const double *lu, int prec, hipStream_t s)
+{
+    DISPATCH(prec, k_coarse_apply2d, dim3(1), dim3(256), L, lu);
     return hipGetLastError();
 }
 

@@ -164,10 +164,16 @@ hipError_t launch_res2d_finalize(const double *partial, int ntiles, long long nc
 hipError_t launch_jacobian2d(const Inst2D &I, const Perm2D &P, void *J, void *rhs, void *Dinv, int prec,
                              hipStream_t s);
 hipError_t launch_coarsen2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
-hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, double omega, int prec, hipStream_t s);
+// `reps` consecutive passes of one colour (the same neighbour values), one launch
+hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, int reps, double omega, int prec,
+                               hipStream_t s);
 hipError_t launch_restrict2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
 hipError_t launch_prolong2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
-hipError_t launch_coarse_solve2d(void *mg, const Level2D &L, int prec, hipStream_t s);
+// coarsest level: LU factors with row permutation (M*M doubles then M ints, M = 3 cells) once
+// per operator, and the solve per V-cycle
+hipError_t launch_coarse_factor2d(void *mg, const Level2D &L, double *lu, int prec, hipStream_t s);
+hipError_t launch_coarse_apply2d(void *mg, const Level2D &L, const double *lu, int prec, hipStream_t s);
+inline size_t coarse_lu_bytes(int M) { return sizeof(double) * (size_t)M * M + sizeof(int) * (size_t)M; }
 hipError_t launch_fill(void *p, int prec, long long n, hipStream_t s);
 hipError_t launch_update2d(double *U, const void *mg, const Level2D &L0, double tau,
                            const NewtonState *state, int prec, hipStream_t s);
