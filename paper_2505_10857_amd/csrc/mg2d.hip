@@ -102,36 +102,55 @@ __global__ void k_coarsen2d(T *mg, Level2D Lf, Level2D Lc)
     for (int e = 0; e < 9; e++) mg[Lc.Dinv + e * nc + cc] = (T)B[e];
 }
 
-// `reps` consecutive passes of eq. (22) over the cells with (i + j) mod C == colour on one level,
-// thread p taking slot p of that colour's block (row p / W, k-th cell of the colour in the row).
-// Passes of one colour in a row see the same neighbour values, so the off-diagonal sum and
-// D^{-1} r are formed once and the relaxation is applied `reps` times, each result rounded to the
-// storage type as if it had been stored between the passes.
-template <typename T>
+// `reps` consecutive passes of eq. (22) over the cells with (i + j) mod C == colour on one level
+// with the NB-block stencil (C = 3 colours for the nine-block cross, 2 for five points), thread p
+// taking slot p of that colour's block (row p / W, k-th cell of the colour in the row).  Passes
+// of one colour in a row see the same neighbour values, so the off-diagonal sum and D^{-1} r are
+// formed once and the relaxation is applied `reps` times, each result rounded to the storage
+// type as if it had been stored between the passes.  The stencil is unrolled so that every load
+// of the cell's row is issued up front; neighbours outside the grid read the cell's own slot and
+// are left out of the sum.
+template <typename T, int NB>
 __global__ void __launch_bounds__(256) k_smooth2d_pass(T *mg, Level2D L, int colour, double omega, int reps)
 {
+    constexpr int C = NB == 9 ? 3 : 2;
     const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const int W = L.P.W, C = L.P.C;
+    const int W = L.P.W;
     if (p >= (long long)L.ny * W) return;
     const int j = (int)(p / W), k = (int)(p - (long long)j * W);
     const int i = ((colour - j) % C + C) % C + C * k;
     if (i >= L.nx) return;
     const long long n = L.P.M, cc = (long long)colour * L.ny * W + p;
-    double r[3];
+    const T *Jr = mg + L.J + cc;
+    const T *Ur = mg + L.dU;
+    double x[NB][3];
+    bool ok[NB];
 #pragma unroll
-    for (int c = 0; c < 3; c++) r[c] = ld2(mg + L.rhs, c * n + cc);
-    for (int b = 1; b < L.nb; b++) {
+    for (int b = 1; b < NB; b++) {
         int di, dj;
-        stencil_off(L.nb, b, di, dj);
+        stencil_off(NB, b, di, dj);
         const int pi = i + di, pj = j + dj;
-        if (pi < 0 || pi >= L.nx || pj < 0 || pj >= L.ny) continue;
-        const long long nc2 = perm2d(L.P, pi, pj);
-        const double x0 = ld2(mg + L.dU, nc2), x1 = ld2(mg + L.dU, n + nc2), x2 = ld2(mg + L.dU, 2 * n + nc2);
+        ok[b] = pi >= 0 && pi < L.nx && pj >= 0 && pj < L.ny;
+        const int c2 = ((pi + pj) % C + C) % C;
+        const int ic = ((c2 - pj) % C + C) % C;
+        const long long q = ok[b] ? (long long)c2 * L.ny * W + (long long)pj * W + (pi - ic) / C : cc;
+#pragma unroll
+        for (int c = 0; c < 3; c++) x[b][c] = (double)Ur[c * n + q];
+    }
+    double a[NB][3];
+#pragma unroll
+    for (int b = 1; b < NB; b++)
 #pragma unroll
         for (int c = 0; c < 3; c++)
-            r[c] = r[c] + (ld2(mg + L.J, (b * 9 + c * 3 + 0) * n + cc) * x0 +
-                           ld2(mg + L.J, (b * 9 + c * 3 + 1) * n + cc) * x1 +
-                           ld2(mg + L.J, (b * 9 + c * 3 + 2) * n + cc) * x2);
+            a[b][c] = (double)Jr[(b * 9 + c * 3 + 0) * n] * x[b][0] + (double)Jr[(b * 9 + c * 3 + 1) * n] * x[b][1] +
+                      (double)Jr[(b * 9 + c * 3 + 2) * n] * x[b][2];
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        r[c] = ld2(mg + L.rhs, c * n + cc);
+#pragma unroll
+        for (int b = 1; b < NB; b++)
+            if (ok[b]) r[c] = r[c] + a[b][c];
     }
     double t[3];
 #pragma unroll
@@ -428,7 +447,18 @@ hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, int reps
 {
     const long long slots = (long long)L.ny * L.P.W;
     dim3 grid((unsigned)((slots + 255) / 256));
-    DISPATCH(prec, k_smooth2d_pass, grid, dim3(256), L, colour, omega, reps);
+    if (L.P.C != (L.nb == 9 ? 3 : 2)) return hipErrorInvalidValue;
+    if (L.nb == 9) {
+        if (prec == NMG_FP32_MG)
+            hipLaunchKernelGGL((k_smooth2d_pass<float, 9>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
+        else
+            hipLaunchKernelGGL((k_smooth2d_pass<double, 9>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
+    } else {
+        if (prec == NMG_FP32_MG)
+            hipLaunchKernelGGL((k_smooth2d_pass<float, 5>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
+        else
+            hipLaunchKernelGGL((k_smooth2d_pass<double, 5>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
+    }
     return hipGetLastError();
 }
 

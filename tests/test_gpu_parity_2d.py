@@ -285,3 +285,27 @@ def test_full_size_vcycle_on_the_wedge_grid():
     e = _rel(dU.cpu().numpy().transpose(1, 2, 0), d1)
     print(f"1024x512 V-cycle rel err {e:.3e}")
     assert e <= 1e-12
+
+
+def test_repeated_vcycles_match_oracle():
+    """Four V-cycle calls in a row on one workspace, with other device work and host
+    synchronisation between them, each equal to the oracle's k-th V-cycle; then the same on a
+    fresh workspace."""
+    prob = wedge_problem(32, 16)
+    Jo, R = _operator(prob, seed=9)
+    p = prob.params
+    rhs_o = np.ascontiguousarray(R.transpose(1, 2, 0))
+    J = torch.tensor(np.ascontiguousarray(Jo.transpose(2, 3, 4, 0, 1)), dtype=torch.float64, device=DEV)
+    rhs = torch.tensor(R, dtype=torch.float64, device=DEV)
+    for trial in range(2):
+        s = _solver(prob, nu1=2, nu2=2)
+        dU = torch.zeros((3, prob.ny, prob.nx), dtype=torch.float64, device=DEV)
+        for k in range(1, 5):
+            s.vcycle(J if k == 1 else None, rhs, dU, setup=(k == 1))
+            junk = (dU * 2.0).sum()                        # other work on the stream in between
+            torch.cuda.synchronize()
+            assert torch.isfinite(junk)
+            dk = vcycles2d(Jo, rhs_o, levels=prob.levels, ncycles=k, omega=p.omega, nu1=2, nu2=2)
+            e = _rel(dU.cpu().numpy().transpose(1, 2, 0), dk)
+            print(f"workspace {trial}, V-cycle {k}: rel err {e:.3e}")
+            assert e <= 1e-12
