@@ -34,6 +34,7 @@ struct Plan2D {
     Inst2D I;
     int levels = 0, prec = NMG_FP64, nu1 = 0, nu2 = 0, nu3 = 1, n_max = 0, max_hist = 0, ntiles = 0;
     int check_every = 1;
+    int bottom_first = 0;      // first level of the one-workgroup bottom (launch_bottom2d)
     double tau = 0.0, omega = 1.0, tol = 0.0;
     std::vector<Level2D> L;
     size_t off_state = 0, off_partial = 0, off_hist = 0, off_R = 0, off_rn = 0, off_mg = 0, off_lu = 0, total = 0;
@@ -135,6 +136,10 @@ nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p, bool need_
     P.off_rn = o; o = al256(o + sizeof(double) * n0);
     P.off_mg = o; o = al256(o + vsz * (size_t)e);
     const Level2D &Lc = P.L.back();
+    P.bottom_first = P.levels - 1;
+    while (P.bottom_first > 0 &&
+           (long long)P.L[P.bottom_first - 1].nx * P.L[P.bottom_first - 1].ny <= kBottom2DCells)
+        P.bottom_first--;
     P.off_lu = o; o = al256(o + coarse_lu_bytes(3 * Lc.nx * Lc.ny));
     P.total = o;
     return NMG_OK;
@@ -164,8 +169,9 @@ nmg_status smooth(const Plan2D &P, char *mgb, int l, int nu, hipStream_t s)
 // Algorithm 2 from level l (recursive)
 nmg_status vcycle_from(const Plan2D &P, char *mgb, int l, hipStream_t s)
 {
-    if (l == P.levels - 1) {
-        HIP_TRY2(launch_coarse_apply2d(mgb, P.L[l], (const double *)(mgb - P.off_mg + P.off_lu), P.prec, s));
+    if (l >= P.bottom_first) {
+        HIP_TRY2(launch_bottom2d(mgb, P.L.data(), l, P.levels, P.nu1, P.nu2, P.omega,
+                                 (const double *)(mgb - P.off_mg + P.off_lu), P.prec, s));
         return NMG_OK;
     }
     nmg_status st;

@@ -9,6 +9,7 @@
 // or coarse cell; the sums run in the order of the definitions, so no result depends on the
 // layout.
 #include <algorithm>
+#include <cstring>
 
 #include "nmg_common.h"
 
@@ -111,12 +112,10 @@ __global__ void k_coarsen2d(T *mg, Level2D Lf, Level2D Lc)
 // of the cell's row is issued up front; neighbours outside the grid read the cell's own slot and
 // are left out of the sum.
 template <typename T, int NB>
-__global__ void __launch_bounds__(256) k_smooth2d_pass(T *mg, Level2D L, int colour, double omega, int reps)
+__device__ __forceinline__ void smooth_slot(T *mg, const Level2D &L, int colour, double omega, int reps, long long p)
 {
     constexpr int C = NB == 9 ? 3 : 2;
-    const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int W = L.P.W;
-    if (p >= (long long)L.ny * W) return;
     const int j = (int)(p / W), k = (int)(p - (long long)j * W);
     const int i = ((colour - j) % C + C) % C + C * k;
     if (i >= L.nx) return;
@@ -165,13 +164,18 @@ __global__ void __launch_bounds__(256) k_smooth2d_pass(T *mg, Level2D L, int col
     }
 }
 
-// eq. (24), right-hand side, one thread per coarse cell; also clears the coarse dU.
-template <typename T>
-__global__ void k_restrict2d(T *mg, Level2D Lf, Level2D Lc)
+template <typename T, int NB>
+__global__ void __launch_bounds__(256) k_smooth2d_pass(T *mg, Level2D L, int colour, double omega, int reps)
 {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    const int Jq = blockIdx.y;
-    if (I >= Lc.nx || Jq >= Lc.ny) return;
+    const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (p >= (long long)L.ny * L.P.W) return;
+    smooth_slot<T, NB>(mg, L, colour, omega, reps, p);
+}
+
+// eq. (24), right-hand side of coarse cell (I, Jq); also clears its dU.
+template <typename T>
+__device__ __forceinline__ void restrict_cell(T *mg, const Level2D &Lf, const Level2D &Lc, int I, int Jq)
+{
     const long long nf = Lf.P.M, nc = Lc.P.M;
     double s[3] = {0.0, 0.0, 0.0};
     for (int fj = 2 * Jq; fj <= 2 * Jq + 1; fj++)
@@ -204,18 +208,33 @@ __global__ void k_restrict2d(T *mg, Level2D Lf, Level2D Lc)
     }
 }
 
+template <typename T>
+__global__ void k_restrict2d(T *mg, Level2D Lf, Level2D Lc)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Jq = blockIdx.y;
+    if (I >= Lc.nx || Jq >= Lc.ny) return;
+    restrict_cell(mg, Lf, Lc, I, Jq);
+}
+
 // eq. (25): dU_fine += dU_coarse(parent)
+template <typename T>
+__device__ __forceinline__ void prolong_cell(T *mg, const Level2D &Lf, const Level2D &Lc, int i, int j)
+{
+    const long long nf = Lf.P.M, nc = Lc.P.M;
+    const long long fc = perm2d(Lf.P, i, j), pc = perm2d(Lc.P, i >> 1, j >> 1);
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+        mg[Lf.dU + c * nf + fc] = (T)(ld2(mg + Lf.dU, c * nf + fc) + ld2(mg + Lc.dU, c * nc + pc));
+}
+
 template <typename T>
 __global__ void k_prolong2d(T *mg, Level2D Lf, Level2D Lc)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= Lf.nx || j >= Lf.ny) return;
-    const long long nf = Lf.P.M, nc = Lc.P.M;
-    const long long fc = perm2d(Lf.P, i, j), pc = perm2d(Lc.P, i >> 1, j >> 1);
-#pragma unroll
-    for (int c = 0; c < 3; c++)
-        mg[Lf.dU + c * nf + fc] = (T)(ld2(mg + Lf.dU, c * nf + fc) + ld2(mg + Lc.dU, c * nc + pc));
+    prolong_cell(mg, Lf, Lc, i, j);
 }
 
 // Coarsest level: Gaussian elimination with partial pivoting of the dense system sum J dU = -rhs
@@ -313,25 +332,23 @@ __global__ void __launch_bounds__(256) k_coarse_factor2d(T *mg, Level2D L, doubl
     for (int r = t; r < M; r += 256) lu.perm[r] = perm[r];
 }
 
+// solve with the factors of k_coarse_factor2d; A and x are LDS arrays of the calling workgroup
 template <typename T>
-__global__ void __launch_bounds__(256) k_coarse_apply2d(T *mg, Level2D L, const double *lu_base)
+__device__ __forceinline__ void coarse_apply(T *mg, const Level2D &L, const double *lu_base, double *A, double *x)
 {
-    constexpr int MM = 3 * kMaxCoarse2D;
-    __shared__ double A[MM * MM];
-    __shared__ double x[MM];
     const int nx = L.nx, n = nx * L.ny, M = 3 * n;
     const long long Ms = L.P.M;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, nt = blockDim.x;
     const CoarseLU lu = coarse_lu(const_cast<double *>(lu_base), M);
-    for (int e = t; e < M * M; e += 256) A[e] = lu.A[e];
-    for (int r = t; r < M; r += 256) {
+    for (int e = t; e < M * M; e += nt) A[e] = lu.A[e];
+    for (int r = t; r < M; r += nt) {
         const int src = lu.perm[r], cell = src / 3;
         x[r] = -ld2(mg + L.rhs, (src % 3) * Ms + perm2d(L.P, cell % nx, cell / nx));
     }
     __syncthreads();
     for (int k = 0; k < M - 1; k++) {
         const double xk = x[k];
-        for (int r = k + 1 + t; r < M; r += 256) {
+        for (int r = k + 1 + t; r < M; r += nt) {
             const double f = A[r * M + k];
             if (f != 0.0) x[r] -= f * xk;
         }
@@ -341,12 +358,73 @@ __global__ void __launch_bounds__(256) k_coarse_apply2d(T *mg, Level2D L, const 
         if (t == 0) x[k] = x[k] / A[k * M + k];
         __syncthreads();
         const double xk = x[k];
-        for (int r = t; r < k; r += 256) x[r] -= A[r * M + k] * xk;
+        for (int r = t; r < k; r += nt) x[r] -= A[r * M + k] * xk;
         __syncthreads();
     }
-    for (int r = t; r < M; r += 256) {
+    for (int r = t; r < M; r += nt) {
         const int cell = r / 3;
         mg[L.dU + (r % 3) * Ms + perm2d(L.P, cell % nx, cell / nx)] = (T)x[r];
+    }
+}
+
+// The bottom of a V-cycle in one workgroup: from level `first` (a small level) down to the
+// coarsest and back, with every pass of Algorithm 2 on those levels (the same schedule of merged
+// colour passes as the launches on the finer levels) separated by workgroup barriers instead of
+// kernel boundaries.  Used for levels of at most kBottom2DCells cells, where a launch costs more
+// than the pass itself.
+struct Bottom2DArgs {
+    Level2D L[kMaxLevels];
+    int first, levels, nu1, nu2;
+    double omega;
+    const double *lu;
+};
+
+template <typename T>
+__device__ void bottom_smooth(T *mg, const Level2D &L, int nu, double omega)
+{
+    const int C = L.P.C;
+    const long long slots = (long long)L.ny * L.P.W;
+    int cur = -1, run = 0;
+    for (int it = 0; it <= nu; it++) {
+        for (int half = 0; half < 4; half++)
+            for (int q = 0; q < C; q++) {
+                const bool last = it == nu;
+                const int c = (half & 1) ? C - 1 - q : q;
+                if (!last && c == cur) { run++; continue; }
+                if (run > 0) {
+                    for (long long p = threadIdx.x; p < slots; p += blockDim.x) {
+                        if (L.nb == 9) smooth_slot<T, 9>(mg, L, cur, omega, run, p);
+                        else smooth_slot<T, 5>(mg, L, cur, omega, run, p);
+                    }
+                    __syncthreads();
+                }
+                if (last) return;
+                cur = c;
+                run = 1;
+            }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_bottom2d(T *mg, Bottom2DArgs B)
+{
+    constexpr int MM = 3 * kMaxCoarse2D;
+    __shared__ double A[MM * MM];
+    __shared__ double x[MM];
+    const int last = B.levels - 1;
+    for (int l = B.first; l < last; l++) {
+        bottom_smooth(mg, B.L[l], B.nu1, B.omega);
+        const Level2D &Lc = B.L[l + 1];
+        for (int e = threadIdx.x; e < Lc.nx * Lc.ny; e += blockDim.x) restrict_cell(mg, B.L[l], Lc, e % Lc.nx, e / Lc.nx);
+        __syncthreads();
+    }
+    coarse_apply(mg, B.L[last], B.lu, A, x);
+    __syncthreads();
+    for (int l = last - 1; l >= B.first; l--) {
+        const Level2D &Lf = B.L[l];
+        for (int e = threadIdx.x; e < Lf.nx * Lf.ny; e += blockDim.x) prolong_cell(mg, Lf, B.L[l + 1], e % Lf.nx, e / Lf.nx);
+        __syncthreads();
+        bottom_smooth(mg, Lf, B.nu2, B.omega);
     }
 }
 
@@ -482,9 +560,20 @@ hipError_t launch_coarse_factor2d(void *mg, const Level2D &L, double *lu, int pr
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_apply2d(void *mg, const Level2D &L, const double *lu, int prec, hipStream_t s)
+hipError_t launch_bottom2d(void *mg, const Level2D *levels, int first, int nlev, int nu1, int nu2, double omega,
+                           const double *lu, int prec, hipStream_t s)
 {
-    DISPATCH(prec, k_coarse_apply2d, dim3(1), dim3(256), L, lu);
+    if (first < 0 || first >= nlev || nlev > kMaxLevels) return hipErrorInvalidValue;
+    Bottom2DArgs B;
+    memset(&B, 0, sizeof(B));
+    for (int l = 0; l < nlev; l++) B.L[l] = levels[l];
+    B.first = first;
+    B.levels = nlev;
+    B.nu1 = nu1;
+    B.nu2 = nu2;
+    B.omega = omega;
+    B.lu = lu;
+    DISPATCH(prec, k_bottom2d, dim3(1), dim3(512), B);
     return hipGetLastError();
 }
 

@@ -170,9 +170,12 @@ hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, int reps
 hipError_t launch_restrict2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
 hipError_t launch_prolong2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
 // coarsest level: LU factors with row permutation (M*M doubles then M ints, M = 3 cells) once
-// per operator, and the solve per V-cycle
+// per operator; the solve with them runs in launch_bottom2d
 hipError_t launch_coarse_factor2d(void *mg, const Level2D &L, double *lu, int prec, hipStream_t s);
-hipError_t launch_coarse_apply2d(void *mg, const Level2D &L, const double *lu, int prec, hipStream_t s);
+// the levels first..nlev-1 of a V-cycle (down to the coarsest solve and back) in one workgroup
+hipError_t launch_bottom2d(void *mg, const Level2D *levels, int first, int nlev, int nu1, int nu2, double omega,
+                           const double *lu, int prec, hipStream_t s);
+constexpr long long kBottom2DCells = 512;    // levels at most this size go to launch_bottom2d
 inline size_t coarse_lu_bytes(int M) { return sizeof(double) * (size_t)M * M + sizeof(int) * (size_t)M; }
 hipError_t launch_fill(void *p, int prec, long long n, hipStream_t s);
 hipError_t launch_update2d(double *U, const void *mg, const Level2D &L0, double tau,
