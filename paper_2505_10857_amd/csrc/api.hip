@@ -216,6 +216,7 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
             L.J = mg_elems; mg_elems += (long long)L.nb * 4 * L.n;
             L.rhs = mg_elems; mg_elems += 2LL * L.n;
             L.dU = mg_elems; mg_elems += 2LL * L.n;
+            L.dUo = mg_elems; mg_elems += 2LL * L.n;
             L.aux = -1;
             if (P->linear == NMG_LINEAR_SOR_LEX && l == 0) { L.aux = mg_elems; mg_elems += 2LL * L.n; }
             mg_elems = (mg_elems + 63) & ~63LL;
@@ -450,14 +451,17 @@ nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s, bool cap = false)
         const int nb_max = (P->jac_mask & 2) ? 5 : 3;
         for (int k = 0; k < P->sor_max; k++) {
             if (P->linear == NMG_LINEAR_SOR) {
-                HIP_TRY(launch_sor_mc(mg, tiles_at(P, ws, P->sor_t0), P->sor_nt, nb_max, k == 0 ? 1 : 0, partial,
+                HIP_TRY(launch_sor_mc(mg, tiles_at(P, ws, P->sor_t0), P->sor_nt, nb_max, k, partial,
                                       P->prec, s));
                 HIP_TRY(launch_sor_finalize(insts, P->n, state, partial, P->sor_tol, s));
             } else {
                 HIP_TRY(launch_sor_lex(mg, P->n, nb_max, k == 0 ? 1 : 0, P->sor_tol, P->prec, s));
             }
         }
-        HIP_TRY(launch_update1d(mg, rt, P->res_nt, P->prec, s));
+        // the multicolour steps alternate between the two dU buffers (the last one written is
+        // dUo when the step count is odd); the lexicographic sweep works in dU
+        const int from_out = P->linear == NMG_LINEAR_SOR && (P->sor_max & 1) ? 1 : 0;
+        HIP_TRY(launch_update1d(mg, rt, P->res_nt, from_out, P->prec, s));
     }
     {
         ProfScope ps(P, NMG_K_RESIDUAL, s, cap);

@@ -181,9 +181,12 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
     if (in) {
         r0 = ld(base + L.rhs, j);
         r1 = ld(base + L.rhs, n + (long long)j);
+        // pre-smoothing reads dU and writes dUo, post-smoothing reads dUo and writes dU (the
+        // halo of a tile must hold the values from before the launch)
+        const long long src = mode == 0 ? L.dU : L.dUo;
         if (!(mode == 0 && zero_init)) {
-            du0 = ld(base + L.dU, j);
-            du1 = ld(base + L.dU, n + (long long)j);
+            du0 = ld(base + src, j);
+            du1 = ld(base + src, n + (long long)j);
         }
         if (mode == 1) {
             const Level1D &Lc = mg.levs[L.child];
@@ -199,10 +202,16 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
     const int steps = mode == 0 ? I.nu1 : I.nu2;
     const double w = I.omega;
     const int col = ((j % C) + C) % C;
-    for (int s = 0; s < steps; s++) {
-        for (int hs = 0; hs < 2 * C; hs++) {
-            const int c = hs < C ? hs : 2 * C - 1 - hs;
-            if (in && col == c) {
+    // half-sweep colours 0..C-1, C-1..0 per step; a run of equal colours (at every turn) sees
+    // the same neighbour values, so its relaxations share one off-diagonal sum
+    const int total = steps * 2 * C;
+    int cur = -1, reps = 0;
+    for (int q = 0; q <= total; q++) {
+        const int hs = q % (2 * C);
+        const int c = q == total ? -1 : (hs < C ? hs : 2 * C - 1 - hs);
+        if (c == cur) { reps++; continue; }
+        if (reps > 0) {
+            if (in && col == cur) {
                 // eq. (19): dU_j <- (1-w) dU_j - w J_jj^{-1} (rhs_j + sum_{i != j} J_ji dU_i)
                 double a0 = r0, a1 = r1;
 #pragma unroll
@@ -214,13 +223,17 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
                 }
                 const double t0 = D[0] * a0 + D[1] * a1;
                 const double t1 = D[2] * a0 + D[3] * a1;
-                du0 = (1.0 - w) * du0 - w * t0;
-                du1 = (1.0 - w) * du1 - w * t1;
+                for (int k = 0; k < reps; k++) {
+                    du0 = (1.0 - w) * du0 - w * t0;
+                    du1 = (1.0 - w) * du1 - w * t1;
+                }
                 s0[t + HW] = du0;
                 s1[t + HW] = du1;
             }
             __syncthreads();
         }
+        cur = c;
+        reps = 1;
     }
 
     const bool valid = in && t >= h && t < h + L.V;
@@ -236,8 +249,8 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
         const double p0 = __shfl_xor(a0, 1, 64);
         const double p1 = __shfl_xor(a1, 1, 64);
         if (valid) {
-            base[L.dU + j] = (T)du0;
-            base[L.dU + n + (long long)j] = (T)du1;
+            base[L.dUo + j] = (T)du0;
+            base[L.dUo + n + (long long)j] = (T)du1;
             if ((j & 1) == 0 && !L.coarsest) {
                 const Level1D &Lc = mg.levs[L.child];
                 base[Lc.rhs + (j >> 1)] = (T)(a0 + p0);
@@ -351,29 +364,32 @@ __global__ void __launch_bounds__(NT) k_bottom(MGArgs mg, const int *inst_list, 
         }
         if (t == 0) { u0[n + 1] = 0.0; u1[n + 1] = 0.0; }
         __syncthreads();
-        for (int s = 0; s < I.nu1; s++)
-            for (int hs = 0; hs < 4; hs++) {
-                const int col = hs < 2 ? hs : 3 - hs;
+        // half-sweeps 0 1 1 0 per step: runs 0, (1 1), (0 0), ..., (1 1), 0 of one colour
+        // share the neighbour values and so one off-diagonal sum
+        for (int run = 0; I.nu1 > 0 && run <= 2 * I.nu1; run++) {
+            const int col = run & 1, reps = (run == 0 || run == 2 * I.nu1) ? 1 : 2;
 #pragma unroll
-                for (int k = 0; k < 2; k++) {
-                    const int c = t + k * NT;
-                    if (c < n && (c & 1) == col) {
-                        const double x0 = u0[c], x1 = u1[c], y0 = u0[c + 2], y1 = u1[c + 2];
-                        double a0 = r[k][0], a1 = r[k][1];
-                        a0 = a0 + (Jr[k][0] * x0 + Jr[k][1] * x1);
-                        a1 = a1 + (Jr[k][2] * x0 + Jr[k][3] * x1);
-                        a0 = a0 + (Jr[k][8] * y0 + Jr[k][9] * y1);
-                        a1 = a1 + (Jr[k][10] * y0 + Jr[k][11] * y1);
-                        const double t0 = D[k][0] * a0 + D[k][1] * a1;
-                        const double t1 = D[k][2] * a0 + D[k][3] * a1;
+            for (int k = 0; k < 2; k++) {
+                const int c = t + k * NT;
+                if (c < n && (c & 1) == col) {
+                    const double x0 = u0[c], x1 = u1[c], y0 = u0[c + 2], y1 = u1[c + 2];
+                    double a0 = r[k][0], a1 = r[k][1];
+                    a0 = a0 + (Jr[k][0] * x0 + Jr[k][1] * x1);
+                    a1 = a1 + (Jr[k][2] * x0 + Jr[k][3] * x1);
+                    a0 = a0 + (Jr[k][8] * y0 + Jr[k][9] * y1);
+                    a1 = a1 + (Jr[k][10] * y0 + Jr[k][11] * y1);
+                    const double t0 = D[k][0] * a0 + D[k][1] * a1;
+                    const double t1 = D[k][2] * a0 + D[k][3] * a1;
+                    for (int q = 0; q < reps; q++) {
                         du[k][0] = (1.0 - w) * du[k][0] - w * t0;
                         du[k][1] = (1.0 - w) * du[k][1] - w * t1;
-                        u0[c + 1] = du[k][0];
-                        u1[c + 1] = du[k][1];
                     }
+                    u0[c + 1] = du[k][0];
+                    u1[c + 1] = du[k][1];
                 }
-                __syncthreads();
             }
+            __syncthreads();
+        }
         // restriction to the child (eq. 17) into LDS; pre-smoothed dU to HBM
         const int qn = li == lb ? 0 : qoff + n;
 #pragma unroll
@@ -522,29 +538,32 @@ __global__ void __launch_bounds__(NT) k_bottom(MGArgs mg, const int *inst_list, 
         }
         if (t == 0) { u0[n + 1] = 0.0; u1[n + 1] = 0.0; }
         __syncthreads();
-        for (int s = 0; s < I.nu2; s++)
-            for (int hs = 0; hs < 4; hs++) {
-                const int col = hs < 2 ? hs : 3 - hs;
+        // half-sweeps 0 1 1 0 per step: runs 0, (1 1), (0 0), ..., (1 1), 0 of one colour
+        // share the neighbour values and so one off-diagonal sum
+        for (int run = 0; I.nu2 > 0 && run <= 2 * I.nu2; run++) {
+            const int col = run & 1, reps = (run == 0 || run == 2 * I.nu2) ? 1 : 2;
 #pragma unroll
-                for (int k = 0; k < 2; k++) {
-                    const int c = t + k * NT;
-                    if (c < n && (c & 1) == col) {
-                        const double x0 = u0[c], x1 = u1[c], y0 = u0[c + 2], y1 = u1[c + 2];
-                        double a0 = r[k][0], a1 = r[k][1];
-                        a0 = a0 + (Jr[k][0] * x0 + Jr[k][1] * x1);
-                        a1 = a1 + (Jr[k][2] * x0 + Jr[k][3] * x1);
-                        a0 = a0 + (Jr[k][8] * y0 + Jr[k][9] * y1);
-                        a1 = a1 + (Jr[k][10] * y0 + Jr[k][11] * y1);
-                        const double t0 = D[k][0] * a0 + D[k][1] * a1;
-                        const double t1 = D[k][2] * a0 + D[k][3] * a1;
+            for (int k = 0; k < 2; k++) {
+                const int c = t + k * NT;
+                if (c < n && (c & 1) == col) {
+                    const double x0 = u0[c], x1 = u1[c], y0 = u0[c + 2], y1 = u1[c + 2];
+                    double a0 = r[k][0], a1 = r[k][1];
+                    a0 = a0 + (Jr[k][0] * x0 + Jr[k][1] * x1);
+                    a1 = a1 + (Jr[k][2] * x0 + Jr[k][3] * x1);
+                    a0 = a0 + (Jr[k][8] * y0 + Jr[k][9] * y1);
+                    a1 = a1 + (Jr[k][10] * y0 + Jr[k][11] * y1);
+                    const double t0 = D[k][0] * a0 + D[k][1] * a1;
+                    const double t1 = D[k][2] * a0 + D[k][3] * a1;
+                    for (int q = 0; q < reps; q++) {
                         du[k][0] = (1.0 - w) * du[k][0] - w * t0;
                         du[k][1] = (1.0 - w) * du[k][1] - w * t1;
-                        u0[c + 1] = du[k][0];
-                        u1[c + 1] = du[k][1];
                     }
+                    u0[c + 1] = du[k][0];
+                    u1[c + 1] = du[k][1];
                 }
-                __syncthreads();
             }
+            __syncthreads();
+        }
 #pragma unroll
         for (int k = 0; k < 2; k++) {
             const int c = t + k * NT;
@@ -570,8 +589,9 @@ __global__ void __launch_bounds__(NT) k_bottom(MGArgs mg, const int *inst_list, 
 // same Newton step skip it.
 
 template <typename T, int NB>
-__global__ void __launch_bounds__(kTile) k_sor_mc(MGArgs mg, const Tile *tiles, int zero_init, double *partial)
+__global__ void __launch_bounds__(kTile) k_sor_mc(MGArgs mg, const Tile *tiles, int step, double *partial)
 {
+    const bool zero_init = step == 0;
     constexpr int HW = NB / 2;
     constexpr int C = NB == 5 ? 3 : 2;
     __shared__ double s0[kTile + 2 * HW], s1[kTile + 2 * HW];
@@ -582,14 +602,21 @@ __global__ void __launch_bounds__(kTile) k_sor_mc(MGArgs mg, const Tile *tiles, 
     if (L.nb != NB) return;
     const Inst1D &I = mg.insts[L.inst];
     const NewtonState *S = mg.state ? &mg.state[I.active_idx] : nullptr;
-    if (S && (!S->active || S->sor_done)) {
-        if (t == 0) partial[blockIdx.x] = 0.0;
-        return;
-    }
     T *base = reinterpret_cast<T *>(mg.mg);
     const int n = L.n, h = L.halo;
     const int j = tl.a - h + t;
     const bool in = j >= 0 && j < n;
+    // step k reads dU (k even) or dUo (k odd) and writes the other buffer
+    const long long src = (step & 1) ? L.dUo : L.dU, dst = (step & 1) ? L.dU : L.dUo;
+    if (S && (!S->active || S->sor_done)) {
+        // stopped: carry the iterate over to the buffer the next step reads
+        if (S->active && !zero_init && in && t >= h && t < h + L.V) {
+            base[dst + j] = base[src + j];
+            base[dst + n + (long long)j] = base[src + n + (long long)j];
+        }
+        if (t == 0) partial[blockIdx.x] = 0.0;
+        return;
+    }
     double Jr[NB][4], D[4], r0 = 0.0, r1 = 0.0, du0 = 0.0, du1 = 0.0;
 #pragma unroll
     for (int b = 0; b < NB; b++)
@@ -601,8 +628,8 @@ __global__ void __launch_bounds__(kTile) k_sor_mc(MGArgs mg, const Tile *tiles, 
         r0 = ld(base + L.rhs, j);
         r1 = ld(base + L.rhs, n + (long long)j);
         if (!zero_init) {
-            du0 = ld(base + L.dU, j);
-            du1 = ld(base + L.dU, n + (long long)j);
+            du0 = ld(base + src, j);
+            du1 = ld(base + src, n + (long long)j);
         }
     }
     const double old0 = du0, old1 = du1;
@@ -635,8 +662,8 @@ __global__ void __launch_bounds__(kTile) k_sor_mc(MGArgs mg, const Tile *tiles, 
     const bool valid = in && t >= h && t < h + L.V;
     double v = 0.0;
     if (valid) {
-        base[L.dU + j] = (T)du0;
-        base[L.dU + n + (long long)j] = (T)du1;
+        base[dst + j] = (T)du0;
+        base[dst + n + (long long)j] = (T)du1;
         v = fabs((double)(T)du0 - old0) + fabs((double)(T)du1 - old1);
     }
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -730,7 +757,7 @@ __global__ void __launch_bounds__(64) k_sor_lex(MGArgs mg, int ninst, int zero_i
 
 // eq. (14) after the Newton-SOR steps: U <- U + tau dU on level 0 of every active instance
 template <typename T>
-__global__ void __launch_bounds__(kTile) k_update1d(MGArgs mg, const Tile *tiles)
+__global__ void __launch_bounds__(kTile) k_update1d(MGArgs mg, const Tile *tiles, int from_out)
 {
     const Tile tl = tiles[blockIdx.x];
     const Inst1D &I = mg.insts[tl.lev];
@@ -739,8 +766,9 @@ __global__ void __launch_bounds__(kTile) k_update1d(MGArgs mg, const Tile *tiles
     const T *base = reinterpret_cast<const T *>(mg.mg);
     const int j = tl.a + threadIdx.x;
     if (j >= I.N) return;
-    I.U[j] = I.U[j] + I.tau * ld(base + L.dU, j);
-    I.U[I.N + j] = I.U[I.N + j] + I.tau * ld(base + L.dU, L.n + (long long)j);
+    const long long d = from_out ? L.dUo : L.dU;
+    I.U[j] = I.U[j] + I.tau * ld(base + d, j);
+    I.U[I.N + j] = I.U[I.N + j] + I.tau * ld(base + d, L.n + (long long)j);
 }
 
 // Initial cell averages of a grid from the solution on the grid with half as many cells
@@ -772,18 +800,18 @@ __global__ void k_interp_a2(const double *Uc, int nc, double *Uf)
     }
 }
 
-hipError_t launch_sor_mc(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_max, int zero_init,
+hipError_t launch_sor_mc(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_max, int step,
                          double *partial, int prec, hipStream_t s)
 {
     if (ntiles == 0) return hipSuccess;
     if (prec == NMG_FP32_MG) {
-        hipLaunchKernelGGL((k_sor_mc<float, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, partial);
+        hipLaunchKernelGGL((k_sor_mc<float, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, step, partial);
         if (nb_max == 5)
-            hipLaunchKernelGGL((k_sor_mc<float, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, partial);
+            hipLaunchKernelGGL((k_sor_mc<float, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, step, partial);
     } else {
-        hipLaunchKernelGGL((k_sor_mc<double, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, partial);
+        hipLaunchKernelGGL((k_sor_mc<double, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, step, partial);
         if (nb_max == 5)
-            hipLaunchKernelGGL((k_sor_mc<double, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, partial);
+            hipLaunchKernelGGL((k_sor_mc<double, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, step, partial);
     }
     return hipGetLastError();
 }
@@ -809,11 +837,12 @@ hipError_t launch_sor_lex(const MGArgs &mg, int ninst, int nb_max, int zero_init
     return hipGetLastError();
 }
 
-hipError_t launch_update1d(const MGArgs &mg, const Tile *tiles, int ntiles, int prec, hipStream_t s)
+hipError_t launch_update1d(const MGArgs &mg, const Tile *tiles, int ntiles, int from_out, int prec, hipStream_t s)
 {
     if (ntiles == 0) return hipSuccess;
-    if (prec == NMG_FP32_MG) hipLaunchKernelGGL(k_update1d<float>, dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
-    else hipLaunchKernelGGL(k_update1d<double>, dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+    if (prec == NMG_FP32_MG)
+        hipLaunchKernelGGL(k_update1d<float>, dim3(ntiles), dim3(kTile), 0, s, mg, tiles, from_out);
+    else hipLaunchKernelGGL(k_update1d<double>, dim3(ntiles), dim3(kTile), 0, s, mg, tiles, from_out);
     return hipGetLastError();
 }
 

@@ -43,6 +43,10 @@ struct Level1D {
     int inst, l, n, nb;
     int coarsest, halo, V, child;    // child: level index of l+1 (-1 at the coarsest)
     long long J, rhs, dU;
+    // second dU buffer [2][n]: a tiled kernel reads its tile and halo from one buffer and writes
+    // its cells to the other, so that no workgroup reads a halo cell that a neighbouring tile of
+    // the same launch has already overwritten
+    long long dUo;
     long long aux;                   // Newton-SOR, level 0: dU before the current step [2][n]
 };
 
@@ -145,13 +149,15 @@ hipError_t launch_convert(const void *src, int src_prec, void *dst, int dst_prec
 // Newton-SOR (section 5.1.1) on level 0: one symmetric multicolour block-SOR step per launch
 // with the per-tile l1 change of dU in partial[], the per-instance stopping test, the
 // lexicographic variant (one thread per instance, test included) and the update U += tau dU
-hipError_t launch_sor_mc(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_max, int zero_init,
+// Newton-SOR step `step` of a Newton step: reads dU (even steps) or dUo (odd), writes the other
+hipError_t launch_sor_mc(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_max, int step,
                          double *partial, int prec, hipStream_t s);
 hipError_t launch_sor_finalize(const Inst1D *insts, int ninst, NewtonState *state, const double *partial,
                                double tol, hipStream_t s);
 hipError_t launch_sor_lex(const MGArgs &mg, int ninst, int nb_max, int zero_init, double tol, int prec,
                           hipStream_t s);
-hipError_t launch_update1d(const MGArgs &mg, const Tile *tiles, int ntiles, int prec, hipStream_t s);
+// U += tau dU on level 0, dU taken from dUo when from_out
+hipError_t launch_update1d(const MGArgs &mg, const Tile *tiles, int ntiles, int from_out, int prec, hipStream_t s);
 // Appendix A interpolation of a 1D state [2][nc] to [2][2 nc]
 hipError_t launch_interp_a2(const double *Uc, int nc, double *Uf, hipStream_t s);
 

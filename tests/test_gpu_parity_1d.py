@@ -218,3 +218,31 @@ def test_nonfinite_state_is_reported():
     U[0, 50] = -1.0          # negative depth: sqrt of a negative number in the flux
     st, _ = s.newton_solve(U)
     assert st.status == NMG_ENONFINITE
+
+
+def test_full_batch_newton_steps_equal_solo_and_repeat():
+    """The benchmark batch (256 instances of the N = 12800 hump, 8 levels): far more tiles than
+    the GPU holds at once, so neighbouring tiles of one launch run at different times.  Two
+    Newton steps of the batch, with and without the graph, equal those of each sampled instance
+    solved alone, bit for bit, and repeat bit for bit."""
+    from paper_2505_10857_amd import BatchSolver1D
+    from swe_workloads import config2
+    probs = [config2(i, "sub", n=12800, levels=8) for i in range(256)]
+
+    def two_steps(ps, use_graph):
+        b = BatchSolver1D(ps, device=DEV)
+        Us = b.states()
+        b.begin(Us)
+        b.steps(2, use_graph=use_graph)
+        torch.cuda.synchronize()
+        return [u.cpu().numpy() for u in Us]
+
+    a = two_steps(probs, False)
+    g = two_steps(probs, True)
+    a2 = two_steps(probs, False)
+    for k in range(256):
+        assert np.array_equal(a[k], a2[k]), f"instance {k}: batch not repeatable"
+        assert np.array_equal(a[k], g[k]), f"instance {k}: graph differs from launches"
+    for k in (0, 1, 157, 255):
+        solo = two_steps([probs[k]], False)[0]
+        assert np.array_equal(a[k], solo), f"instance {k}: batch differs from solo"
