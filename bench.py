@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--cpu-instances", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration under rocprofv3)")
+    ap.add_argument("--vcycle2d-only", action="store_true",
+                    help="time only the 2D V-cycle form (1024 x 512 wedge configuration) and print it")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-budget-gib", type=int, default=16)
     return ap.parse_args()
@@ -248,6 +250,9 @@ def main():
     from paper_2505_10857_amd import _abi as A
 
     torch.cuda.set_device(0)
+    if args.vcycle2d_only:
+        print(json.dumps({"mg2d_vcycle_wedge1024x512": vcycle2d_form()}))
+        return
     if args.calibrate_copy:
         calibration_copy()
     use_graph = not args.no_graph
@@ -281,11 +286,17 @@ def main():
     }
 
     # ---- roofline of the dominant kernel: HIP events around its launches on the launch stream --
-    el2, _, jms, jcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_JACOBIAN)
-    _, _, pms, pcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_SMOOTH_PRE)
+    el2, stj, jms, jcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_JACOBIAN)
+    _, stp, pms, pcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_SMOOTH_PRE)
     cells = args.batch * args.n
-    jac_ms = jms / max(jcnt, 1)
-    pre_ms = pms / max(pcnt, 1)
+    # instances drop out of every launch once converged, so the work of the timed launches is
+    # counted per active instance: the Jacobian runs once per Newton step of an instance, the
+    # finest pre-smoothing once per V-cycle (nu3 = 2 per step); "full launches" = that work in
+    # units of one launch over the whole batch
+    jac_full = sum(s[0] for st in stj for s in st) / args.batch
+    pre_full = 2 * sum(s[0] for st in stp for s in st) / args.batch
+    jac_ms = jms / jac_full       # time of one launch over the whole batch
+    pre_ms = pms / pre_full
     jac_flops = cells * 6 * FLOPS_LOCAL_RESIDUAL
     out["roofline"] = {
         "kernel": "k_jacobian_batch<double,3> (FD Jacobian J3, eq. 12-13)",
@@ -293,14 +304,16 @@ def main():
         "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": jac_flops / (jac_ms * 1e-3) / 1e12 / FP64_VECTOR_TFLOPS,
         "traffic": measured_traffic(args.batch, args.n),
-        "avg_launch_ms": jac_ms, "launches_timed": jcnt,
+        "avg_launch_ms": jms / max(jcnt, 1), "launches_timed": jcnt, "full_launch_ms": jac_ms,
+        "full_launch_equivalents": jac_full,
         "algorithmic_flops_per_launch": jac_flops,
         "hbm_gbs": cells * BYTES_JACOBIAN_J3 / (jac_ms * 1e-3) / 1e9,
         "share_of_solve_time": jms / (el2 * 1e3),
     }
     out["smoother_roofline"] = {
         "kernel": "k_smooth<double,3> mode 0, finest level (pre-smoothing + restriction)",
-        "bound": "hbm", "avg_launch_ms": pre_ms, "launches_timed": pcnt,
+        "bound": "hbm", "avg_launch_ms": pms / max(pcnt, 1), "launches_timed": pcnt, "full_launch_ms": pre_ms,
+        "full_launch_equivalents": pre_full,
         "achieved": cells * BYTES_SMOOTH_PRE_J3 / (pre_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": cells * BYTES_SMOOTH_PRE_J3 / (pre_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
