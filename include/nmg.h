@@ -68,9 +68,21 @@ typedef struct {
  *   (y point beta, x point gamma) of each cell.
  * levels = L + 1 grid levels (eq. 15 / 23): nx (and ny) must be divisible by 2^(levels-1);
  *   levels = 1 (1D, jac = 3) solves the regularised system directly (Algorithm 3, step 4).
- * jac = 3 or 5 (1D), 9 (2D): which Jacobian blocks are assembled (section 3.3 / 4.1). */
+ * jac = 3 or 5 (1D), 9 (2D): which Jacobian blocks are assembled (section 3.3 / 4.1).
+ * recon (1D): NMG_RECON_CONSERVED reconstructs H as in section 3.1 (the paper's scheme, not
+ *   well balanced).  NMG_RECON_SURFACE, for channels of constant width (the width arrays are
+ *   then not read; width 1): WENO3 reconstructs the surface eta = H + zbar, the depths at a face
+ *   are eta-/+ minus b at the face, and the source of eq. (9) is evaluated in the exactly equal
+ *   split form -g [int (eta_h - eta_j) b_x + eta_j (b_{j+1/2} - b_{j-1/2}) - (b_{j+1/2}^2 -
+ *   b_{j-1/2}^2) / 2] (eta_h the cubic through the four face values of eta, the integral by the
+ *   same Gauss rule, eta_j = H_j + zbar_j), so a still surface is steady to rounding on any
+ *   bottom.  Ghosts copy the surface where the conserved variant copies H (H_g = H_src +
+ *   zbar_src - zbar_g).  It needs z_face [nx+1] (b at the faces) and z_avg [nx+4] (cell
+ *   averages of b over cells -2..nx+1, ghosts included).  2D problems take recon = 0. */
+#define NMG_RECON_CONSERVED 0
+#define NMG_RECON_SURFACE 1
 typedef struct {
-    int32_t dim, nx, ny, levels, jac, pad;
+    int32_t dim, nx, ny, levels, jac, recon;
     double x0, x1, y0, y1, g;
     nmg_bc bc[4];
     double wall_x;
@@ -79,6 +91,8 @@ typedef struct {
     const double *sigx_gp;
     const double *bx_gp;
     const double *by_gp;
+    const double *z_face;
+    const double *z_avg;
 } nmg_desc;
 
 /* Solver parameters (section 3.2, 3.4, 5): alpha regularisation (eq. 13), tau damping

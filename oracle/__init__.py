@@ -56,7 +56,8 @@ _dp = C.POINTER(C.c_double)
 class OrProb1D(C.Structure):
     _fields_ = [("N", C.c_int), ("dx", C.c_double), ("g", C.c_double),
                 ("sig_face", _dp), ("sig_gp", _dp), ("sigx_gp", _dp), ("bx_gp", _dp),
-                ("bc_kind", C.c_int * 2), ("bc_q", C.c_double * 2), ("bc_h", C.c_double * 2)]
+                ("bc_kind", C.c_int * 2), ("bc_q", C.c_double * 2), ("bc_h", C.c_double * 2),
+                ("recon", C.c_int), ("z_face", _dp), ("z_avg", _dp)]
 
 
 class OrParams1D(C.Structure):
@@ -149,6 +150,12 @@ class Oracle1D:
         c.bc_kind[0], c.bc_kind[1] = prob.bc_left.kind, prob.bc_right.kind
         c.bc_q[0], c.bc_q[1] = prob.bc_left.q, prob.bc_right.q
         c.bc_h[0], c.bc_h[1] = prob.bc_left.h, prob.bc_right.h
+        c.recon = getattr(prob, "recon", 0)
+        if c.recon:
+            from swe_workloads import bottom_faces_and_averages
+            self.z_face, self.z_avg = bottom_faces_and_averages(prob)
+            c.z_face = ptr(self.z_face)
+            c.z_avg = ptr(self.z_avg)
         self.c = c
         lib()
 

@@ -34,6 +34,15 @@
  *      rows); one symmetric step sweeps colours 0..C-1 then C-1..0.  The paper's
  *      lexicographic forward+backward sweep (eq. 19) is kept as an option.
  *  R6  The coarsest system is solved by dense Gaussian elimination with partial pivoting.
+ *  R7  Optional surface reconstruction (recon = 1, constant width only; not the paper's scheme,
+ *      which is not well balanced): WENO3 runs on the surface eta = H + zbar (zbar the cell
+ *      average of the bottom), face depths are eta -/+ minus the bottom at the face, and the
+ *      source integral -g int h b_x over the cell is split exactly as
+ *        -g [ int (eta_h - eta_j) b_x  +  eta_j (b_{j+1/2} - b_{j-1/2})  -  (b_{j+1/2}^2 - b_{j-1/2}^2) / 2 ],
+ *      eta_h the cubic through the four face values of eta (two-point Gauss rule for the first
+ *      integral), eta_j = H_j + zbar_j.  A still surface (eta constant, Q = 0) then has R = 0 up
+ *      to rounding on any bottom.  Ghosts copy eta where R3 copies H (H_g = H_src + zbar_src -
+ *      zbar_g); imposed depths stay H = h.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -55,6 +64,9 @@ typedef struct {
     int bc_kind[2];         /* left, right */
     double bc_q[2];
     double bc_h[2];
+    int recon;              /* 0: reconstruct H (the paper); 1: reconstruct the surface (R7) */
+    const double *z_face;   /* [N+1] bottom at face x_{j-1/2} (recon = 1) */
+    const double *z_avg;    /* [N+4] cell averages of the bottom, cells -2..N+1 (recon = 1) */
 } or1d_prob;
 
 typedef struct {
@@ -97,7 +109,14 @@ void or1d_fill_ghosts(const or1d_prob *p, const double *U, double *Ug)
         double sig = p->sig_face[side == 0 ? 0 : N];
         double H0 = U[b0], Q0 = U[N + b0];
         double H1 = U[b1], Q1 = U[N + b1];
-        double Hg0 = H0, Qg0 = Q0, Hg1 = H0, Qg1 = Q0;
+        /* copies carry H, or with the surface reconstruction (R7) the surface H + zbar */
+        double c00 = 0.0, c01 = 0.0, c11 = 0.0;   /* zbar_src - zbar_ghost for the copies */
+        if (p->recon == 1) {
+            c00 = p->z_avg[b0 + 2] - p->z_avg[g0 + 2];
+            c01 = p->z_avg[b0 + 2] - p->z_avg[g1 + 2];
+            c11 = p->z_avg[b1 + 2] - p->z_avg[g1 + 2];
+        }
+        double Hg0 = H0 + c00, Qg0 = Q0, Hg1 = H0 + c01, Qg1 = Q0;
         switch (p->bc_kind[side]) {
         case OR_BC_DISCHARGE:
             Qg0 = Qg1 = p->bc_q[side];
@@ -109,8 +128,8 @@ void or1d_fill_ghosts(const or1d_prob *p, const double *U, double *Ug)
                 Hg0 = Hg1 = sig * p->bc_h[side];
             break;
         case OR_BC_WALL:
-            Hg0 = H0; Qg0 = -Q0;
-            Hg1 = H1; Qg1 = -Q1;
+            Hg0 = H0 + c00; Qg0 = -Q0;
+            Hg1 = H1 + c11; Qg1 = -Q1;
             break;
         default: /* EXTRAP */
             break;
@@ -232,8 +251,45 @@ double or1d_source(const or1d_prob *p, int j, const double Hf[4])
 
 #define UG(k, c) Ug[((k) + 2) * 2 + (c)]
 
+/* R7: the local residual with the surface reconstructed (constant width, sigma = 1) */
+static void local_residual_surface(const or1d_prob *p, const double *Ug, int j, double R[2])
+{
+    double E[5];   /* surface eta = H + zbar on cells j-2..j+2 */
+    for (int k = 0; k < 5; k++) E[k] = UG(j - 2 + k, 0) + p->z_avg[j + k];
+    double Em_jm = or1d_weno_minus(E[0], E[1], E[2]);   /* eta-_{j-1/2}, from cell j-1 */
+    double Ep_jm = or1d_weno_plus(E[1], E[2], E[3]);    /* eta+_{j-1/2}, from cell j */
+    double Em_jp = or1d_weno_minus(E[1], E[2], E[3]);   /* eta-_{j+1/2}, from cell j */
+    double Ep_jp = or1d_weno_plus(E[2], E[3], E[4]);    /* eta+_{j+1/2}, from cell j+1 */
+    double Ep_jmm = or1d_weno_plus(E[0], E[1], E[2]);   /* eta+_{j-3/2}, from cell j-1 */
+    double Em_jpp = or1d_weno_minus(E[2], E[3], E[4]);  /* eta-_{j+3/2}, from cell j+1 */
+    double zl = p->z_face[j], zr = p->z_face[j + 1];
+    double Um_jm[2] = {Em_jm - zl, or1d_weno_minus(UG(j - 2, 1), UG(j - 1, 1), UG(j, 1))};
+    double Up_jm[2] = {Ep_jm - zl, or1d_weno_plus(UG(j - 1, 1), UG(j, 1), UG(j + 1, 1))};
+    double Um_jp[2] = {Em_jp - zr, or1d_weno_minus(UG(j - 1, 1), UG(j, 1), UG(j + 1, 1))};
+    double Up_jp[2] = {Ep_jp - zr, or1d_weno_plus(UG(j, 1), UG(j + 1, 1), UG(j + 2, 1))};
+    double Fm[2], Fp[2];
+    or1d_hll(Um_jm, Up_jm, 1.0, p->g, Fm);
+    or1d_hll(Um_jp, Up_jp, 1.0, p->g, Fp);
+    /* the split source of R7 */
+    double Wt[2][4];
+    or1d_cubic_gauss_weights(Wt);
+    double eta_j = E[2];
+    double quad = 0.0;
+    for (int q = 0; q < 2; q++) {
+        double eg = Wt[q][0] * Ep_jmm + Wt[q][1] * Ep_jm + Wt[q][2] * Em_jp + Wt[q][3] * Em_jpp;
+        quad = quad + (eg - eta_j) * p->bx_gp[2 * j + q];
+    }
+    double S = -p->g * (0.5 * p->dx * quad + eta_j * (zr - zl) - 0.5 * (zr * zr - zl * zl));
+    R[0] = Fp[0] - Fm[0];
+    R[1] = Fp[1] - Fm[1] - S;
+}
+
 void or1d_local_residual(const or1d_prob *p, const double *Ug, int j, double R[2])
 {
+    if (p->recon == 1) {
+        local_residual_surface(p, Ug, j, R);
+        return;
+    }
     double Um_jm[2], Up_jm[2], Um_jp[2], Up_jp[2];  /* U-_{j-1/2}, U+_{j-1/2}, U-_{j+1/2}, U+_{j+1/2} */
     double Hp_jmm, Hm_jpp;                          /* H+_{j-3/2}, H-_{j+3/2} */
     for (int c = 0; c < 2; c++) {

@@ -25,6 +25,8 @@ NMG_BC_STATE = 4
 
 NMG_FP64 = 0
 NMG_FP32_MG = 1
+NMG_RECON_CONSERVED = 0
+NMG_RECON_SURFACE = 1
 
 NMG_LINEAR_MG = 0
 NMG_LINEAR_SOR = 1
@@ -54,11 +56,12 @@ class nmg_bc(C.Structure):
 
 class nmg_desc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("levels", C.c_int32),
-                ("jac", C.c_int32), ("pad", C.c_int32),
+                ("jac", C.c_int32), ("recon", C.c_int32),
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("g", C.c_double), ("bc", nmg_bc * 4), ("wall_x", C.c_double),
                 ("sig_face", C.c_void_p), ("sig_gp", C.c_void_p), ("sigx_gp", C.c_void_p),
-                ("bx_gp", C.c_void_p), ("by_gp", C.c_void_p)]
+                ("bx_gp", C.c_void_p), ("by_gp", C.c_void_p), ("z_face", C.c_void_p),
+                ("z_avg", C.c_void_p)]
 
 
 class nmg_params(C.Structure):

@@ -58,8 +58,12 @@ nmg_status check_desc1d(const nmg_desc *d, const nmg_params *p, bool need_geomet
             return fail(NMG_EINVAL, "coarsest level has more than 256 cells; add levels");
     }
     if (d->jac != 3 && d->jac != 5) return fail(NMG_EINVAL, "1D jac must be 3 or 5");
+    if (d->recon != NMG_RECON_CONSERVED && d->recon != NMG_RECON_SURFACE)
+        return fail(NMG_EINVAL, "bad recon");
     if (need_geometry && (!d->sig_face || !d->sig_gp || !d->sigx_gp || !d->bx_gp))
         return fail(NMG_EINVAL, "null geometry pointer");
+    if (need_geometry && d->recon == NMG_RECON_SURFACE && (!d->z_face || !d->z_avg))
+        return fail(NMG_EINVAL, "the surface reconstruction needs z_face and z_avg");
     if (!(d->x1 > d->x0)) return fail(NMG_EINVAL, "x1 must exceed x0");
     if (!(p->eps > 0.0)) return fail(NMG_EINVAL, "eps must be positive");
     if (p->nu1 < 0 || p->nu2 < 0 || p->nu3 < 1 || p->n_max < 0)
@@ -89,6 +93,9 @@ Inst1D make_inst(const nmg_desc *d, const nmg_params *p)
     I.sig_gp = d->sig_gp;
     I.sigx_gp = d->sigx_gp;
     I.bx_gp = d->bx_gp;
+    I.recon = d->recon;
+    I.z_face = d->z_face;
+    I.z_avg = d->z_avg;
     I.alpha = p->alpha;
     I.tau = p->tau;
     I.eps = p->eps;
@@ -130,6 +137,7 @@ struct nmg_plan {
     double sor_tol = 0.0;
     int sor_t0 = 0, sor_nt = 0;               // Newton-SOR tiles (level 0, one-step halo)
     int bottom_cells = 2048;                  // levels up to this size run in k_bottom
+    int recon = NMG_RECON_CONSERVED;          // reconstruction of every instance
     int bottom_nt = 1024;                     // its workgroup size
     size_t tile_cap = 0;                      // tile-table entries reserved (any option fits)
     std::vector<nmg_desc> descs;
@@ -175,6 +183,7 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
     P->linear = params[0].linear;
     P->sor_max = params[0].sor_max;
     P->sor_tol = params[0].sor_tol;
+    P->recon = descs[0].recon;
     for (int k = 0; k < n; k++) {
         nmg_status st = check_desc1d(&descs[k], &params[k], need_geometry);
         if (st != NMG_OK) return fail(st, "instance " + std::to_string(k) + ": " + g_err);
@@ -182,6 +191,7 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
         if (params[k].nu3 != P->nu3) return fail(NMG_EINVAL, "mixed nu3 in one plan");
         if (params[k].linear != P->linear || params[k].sor_max != P->sor_max || !(params[k].sor_tol == P->sor_tol))
             return fail(NMG_EINVAL, "mixed linear solvers in one plan");
+        if (descs[k].recon != P->recon) return fail(NMG_EINVAL, "mixed reconstructions in one plan");
     }
     const size_t vsz = P->prec == NMG_FP32_MG ? sizeof(float) : sizeof(double);
     P->insts.clear();
@@ -436,7 +446,7 @@ nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s, bool cap = false)
     double *partial = reinterpret_cast<double *>(ws + P->off_partial);
     {
         ProfScope ps(P, NMG_K_JACOBIAN, s, cap);
-        HIP_TRY(launch_jacobian1d(insts, rt, P->res_nt, nullptr, nullptr, mg, P->prec, P->jac_mask, s));
+        HIP_TRY(launch_jacobian1d(insts, rt, P->res_nt, nullptr, nullptr, mg, P->prec, P->jac_mask, P->recon, s));
     }
     nmg_status st = enqueue_setup(P, ws, mg, s, cap, true);
     if (st != NMG_OK) return st;
@@ -465,7 +475,7 @@ nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s, bool cap = false)
     }
     {
         ProfScope ps(P, NMG_K_RESIDUAL, s, cap);
-        HIP_TRY(launch_residual1d(insts, rt, P->res_nt, nullptr, state, partial, s));
+        HIP_TRY(launch_residual1d(insts, rt, P->res_nt, nullptr, state, partial, P->recon, s));
     }
     HIP_TRY(launch_res_finalize(insts, P->n, state, partial, 0, s));
     return NMG_OK;
@@ -489,7 +499,7 @@ nmg_status plan_begin(nmg_plan *P, char *ws, size_t ws_bytes, double *const *U, 
     MGArgs mg = mg_args(P, ws, true);
     const Tile *rt = tiles_at(P, ws, P->res_t0);
     double *partial = reinterpret_cast<double *>(ws + P->off_partial);
-    HIP_TRY(launch_residual1d(mg.insts, rt, P->res_nt, nullptr, nullptr, partial, s));
+    HIP_TRY(launch_residual1d(mg.insts, rt, P->res_nt, nullptr, nullptr, partial, P->recon, s));
     HIP_TRY(launch_res_finalize(mg.insts, P->n, mg.state, partial, 1, s));
     return NMG_OK;
 }
@@ -798,7 +808,7 @@ nmg_status nmg_residual(const nmg_desc *desc, const double *U, double *R, double
     I.R = R;
     I.rn = rn;
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(launch_residual1d(nullptr, nullptr, 0, &I, nullptr, nullptr, s));
+    HIP_TRY(launch_residual1d(nullptr, nullptr, 0, &I, nullptr, nullptr, I.recon, s));
     if (res_dev) HIP_TRY(launch_sum_res(rn, I.N, res_dev, s));
     return NMG_OK;
 }
@@ -817,7 +827,7 @@ nmg_status nmg_jacobian_assemble_simplified(const nmg_desc *desc, const nmg_para
     I.rn = const_cast<double *>(rn);
     MGArgs none;
     memset(&none, 0, sizeof(none));
-    HIP_TRY(launch_jacobian1d(nullptr, nullptr, 0, &I, J, none, NMG_FP64, 0, (hipStream_t)stream));
+    HIP_TRY(launch_jacobian1d(nullptr, nullptr, 0, &I, J, none, NMG_FP64, 0, I.recon, (hipStream_t)stream));
     return NMG_OK;
 }
 

@@ -53,6 +53,7 @@ nmg_status check2d(const nmg_desc *d, const nmg_params *p, bool need_geometry = 
         return set_error(NMG_EINVAL, "coarsest 2D level has more than 40 cells; add levels");
     if ((long long)d->nx * d->ny > (1LL << 28)) return set_error(NMG_EINVAL, "grid too large");
     if (d->jac != 9) return set_error(NMG_EINVAL, "2D jac must be 9");
+    if (d->recon != NMG_RECON_CONSERVED) return set_error(NMG_EINVAL, "2D problems take recon = 0");
     if (need_geometry && (!d->bx_gp || !d->by_gp)) return set_error(NMG_EINVAL, "null geometry pointer");
     if (!(d->x1 > d->x0) || !(d->y1 > d->y0)) return set_error(NMG_EINVAL, "empty domain");
     for (int k = 0; k < 4; k++)

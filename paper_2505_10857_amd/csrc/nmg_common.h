@@ -36,6 +36,8 @@ struct Inst1D {
     int n_start;       // Newton steps already taken (a resumed instance); 0 for a fresh one
     int sor_tile0, sor_tiles;  // Newton-SOR tiles of this instance (contiguous)
     double *hist;      // device history of res, [max_hist] (may be null)
+    int recon;         // NMG_RECON_CONSERVED or NMG_RECON_SURFACE (then the width is taken as 1)
+    const double *z_face, *z_avg;   // surface reconstruction: bottom at faces [N+1], cell averages [N+4]
 };
 
 // One multigrid level of one instance.  Offsets are in elements of the MG value type.
@@ -127,8 +129,9 @@ struct Level2D {
 // ---- launchers (return hipError_t of the launch) ----------------------------------------
 
 // residual over tiles (batched: tiles index instances) or one instance (tiles == null)
+// recon: the reconstruction of every instance in the launch (NMG_RECON_*)
 hipError_t launch_residual1d(const Inst1D *insts_dev, const Tile *tiles, int ntiles,
-                             const Inst1D *single, NewtonState *state, double *partial,
+                             const Inst1D *single, NewtonState *state, double *partial, int recon,
                              hipStream_t s);
 hipError_t launch_res_finalize(const Inst1D *insts_dev, int ninst, NewtonState *state,
                                const double *partial, int init, hipStream_t s);
@@ -137,7 +140,7 @@ hipError_t launch_sum_res(const double *rn, int N, double *res, hipStream_t s);
 // at each instance's level-0 J (batched, via the level table)
 hipError_t launch_jacobian1d(const Inst1D *insts_dev, const Tile *tiles, int ntiles,
                              const Inst1D *single, double *J_single, const MGArgs &mg, int prec,
-                             int nb_mask, hipStream_t s);
+                             int nb_mask, int recon, hipStream_t s);
 hipError_t launch_coarsen1d(const MGArgs &mg, const Tile *tiles, int ntiles, int prec, hipStream_t s);
 // nt: threads of the bottom workgroup (256, 512 or 1024); it handles levels of up to 2 nt cells
 hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero_init0, int final_update,

@@ -97,11 +97,28 @@ struct CubicGauss {
 struct CellGeom {
     double sfm, sfp, isfm, isfp;      // widths at the faces and their reciprocals
     double sg[2], isg[2], sxg[2], bxg[2];
+    double zfm, zfp;                  // bottom at the faces (surface reconstruction)
 };
 
+// SURF: the surface reconstruction (constant width 1): the widths are not read, the bottom at
+// the faces is
+template <bool SURF>
 __device__ __forceinline__ CellGeom load_geom(const Inst1D &I, int j)
 {
     CellGeom G;
+    if (SURF) {
+        G.sfm = G.sfp = G.isfm = G.isfp = 1.0;
+        G.zfm = I.z_face[j];
+        G.zfp = I.z_face[j + 1];
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            G.sg[q] = G.isg[q] = 1.0;
+            G.sxg[q] = 0.0;
+            G.bxg[q] = I.bx_gp[2 * j + q];
+        }
+        return G;
+    }
+    G.zfm = G.zfp = 0.0;
     G.sfm = I.sig_face[j];
     G.sfp = I.sig_face[j + 1];
     G.isfm = 1.0 / G.sfm;
@@ -124,23 +141,28 @@ __device__ __forceinline__ bool subcrit(double H, double Q, double sig, double g
 }
 
 // Boundary ghosts from the boundary cell (c0) and its neighbour (c1): first and second ghost.
+// SURF: a copy carries the surface H + zbar, so the copied H gains c00, c01 or c11 (zbar of
+// the source cell minus zbar of the ghost)
+template <bool SURF>
 __device__ __forceinline__ void ghost_pair(int kind, double q, double hb, double sig, double g,
                                            double H0, double Q0, double H1, double Q1,
+                                           double c00, double c01, double c11,
                                            double &Hg0, double &Qg0, double &Hg1, double &Qg1)
 {
-    Hg0 = H0; Qg0 = Q0; Hg1 = H0; Qg1 = Q0;
+    Hg0 = SURF ? H0 + c00 : H0; Qg0 = Q0; Hg1 = SURF ? H0 + c01 : H0; Qg1 = Q0;
     if (kind == NMG_BC_DISCHARGE) {
         Qg0 = q; Qg1 = q;
         if (!subcrit(H0, Q0, sig, g) && hb > 0.0) { Hg0 = sig * hb; Hg1 = sig * hb; }
     } else if (kind == NMG_BC_DEPTH) {
         if (subcrit(H0, Q0, sig, g)) { Hg0 = sig * hb; Hg1 = sig * hb; }
     } else if (kind == NMG_BC_WALL) {
-        Hg0 = H0; Qg0 = -Q0; Hg1 = H1; Qg1 = -Q1;
+        Hg0 = SURF ? H0 + c00 : H0; Qg0 = -Q0; Hg1 = SURF ? H1 + c11 : H1; Qg1 = -Q1;
     }
 }
 
 // Fill the ghost entries of a stencil (cells j-2..j+2 at positions 0..4) from its own interior
 // entries, so that ghosts follow any perturbation of the boundary cells.
+template <bool SURF>
 __device__ __forceinline__ void stencil_ghosts(double H[5], double Q[5], int j, const Inst1D &I)
 {
     const int N = I.N;
@@ -149,8 +171,12 @@ __device__ __forceinline__ void stencil_ghosts(double H[5], double Q[5], int j, 
         double Hg0, Qg0, Hg1, Qg1;
         double H0 = p0 == 1 ? H[1] : H[2], Q0 = p0 == 1 ? Q[1] : Q[2];
         double H1 = p0 == 1 ? H[2] : H[3], Q1 = p0 == 1 ? Q[2] : Q[3];
-        ghost_pair(I.bc_kind[0], I.bc_q[0], I.bc_h[0], I.sig_face[0], I.g, H0, Q0, H1, Q1,
-                   Hg0, Qg0, Hg1, Qg1);
+        // z_avg holds cells -2..N+1: cell k at k + 2
+        const double c00 = SURF ? I.z_avg[2] - I.z_avg[1] : 0.0;
+        const double c01 = SURF ? I.z_avg[2] - I.z_avg[0] : 0.0;
+        const double c11 = SURF ? I.z_avg[3] - I.z_avg[0] : 0.0;
+        ghost_pair<SURF>(I.bc_kind[0], I.bc_q[0], I.bc_h[0], SURF ? 1.0 : I.sig_face[0], I.g, H0, Q0, H1,
+                         Q1, c00, c01, c11, Hg0, Qg0, Hg1, Qg1);
         if (p0 == 1) { H[0] = Hg0; Q[0] = Qg0; }
         else { H[1] = Hg0; Q[1] = Qg0; H[0] = Hg1; Q[0] = Qg1; }
     }
@@ -159,18 +185,35 @@ __device__ __forceinline__ void stencil_ghosts(double H[5], double Q[5], int j, 
         double Hg0, Qg0, Hg1, Qg1;
         double H0 = pb == 3 ? H[3] : H[2], Q0 = pb == 3 ? Q[3] : Q[2];
         double H1 = pb == 3 ? H[2] : H[1], Q1 = pb == 3 ? Q[2] : Q[1];
-        ghost_pair(I.bc_kind[1], I.bc_q[1], I.bc_h[1], I.sig_face[N], I.g, H0, Q0, H1, Q1,
-                   Hg0, Qg0, Hg1, Qg1);
+        const double c00 = SURF ? I.z_avg[N + 1] - I.z_avg[N + 2] : 0.0;
+        const double c01 = SURF ? I.z_avg[N + 1] - I.z_avg[N + 3] : 0.0;
+        const double c11 = SURF ? I.z_avg[N] - I.z_avg[N + 3] : 0.0;
+        ghost_pair<SURF>(I.bc_kind[1], I.bc_q[1], I.bc_h[1], SURF ? 1.0 : I.sig_face[N], I.g, H0, Q0, H1,
+                         Q1, c00, c01, c11, Hg0, Qg0, Hg1, Qg1);
         if (pb == 3) { H[4] = Hg0; Q[4] = Qg0; }
         else { H[3] = Hg0; Q[3] = Qg0; H[4] = Hg1; Q[4] = Qg1; }
     }
 }
 
-// Source of eq. (9) from the four face values of H feeding the cubic U_h.
+// Source of eq. (9) from the four face values of H feeding the cubic U_h.  SURF: the four face
+// values are of the surface eta, eta_j = H_j + zbar_j, and -g int h b_x over the cell is split
+// exactly into -g [int (eta_h - eta_j) b_x + eta_j (b_{j+1/2} - b_{j-1/2}) - (b_{j+1/2}^2 -
+// b_{j-1/2}^2) / 2], the integral by the same two-point Gauss rule; a still surface then gives
+// R = 0 to rounding on any bottom.
+template <bool SURF>
 __device__ __forceinline__ double source_term(double Hp_ll, double Hp_l, double Hm_r, double Hm_rr,
                                               const CellGeom &G, const CubicGauss &W, double dx,
-                                              double g)
+                                              double g, double eta_j)
 {
+    if (SURF) {
+        double quad = 0.0;
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            const double eg = W.w[q][0] * Hp_ll + W.w[q][1] * Hp_l + W.w[q][2] * Hm_r + W.w[q][3] * Hm_rr;
+            quad = quad + (eg - eta_j) * G.bxg[q];
+        }
+        return -g * (0.5 * dx * quad + eta_j * (G.zfp - G.zfm) - 0.5 * (G.zfp * G.zfp - G.zfm * G.zfm));
+    }
     double sum = 0.0;
 #pragma unroll
     for (int q = 0; q < 2; q++) {
@@ -208,17 +251,26 @@ __device__ __forceinline__ void recon_Q(const double Q[5], Recon &r)
 }
 
 // R_j = F(U-_{j+1/2}, U+_{j+1/2}) - F(U-_{j-1/2}, U+_{j-1/2}) - S_j  (eq. 10)
+// SURF: the reconstructed H values are surface values; the depths are eta - b at the face
+template <bool SURF>
 __device__ __forceinline__ void assemble_residual(const Recon &r, double S, const CellGeom &G,
                                                   double g, double &R0, double &R1)
 {
     double Fm0, Fm1, Fp0, Fp1;
-    hll(r.Hm_l, r.Qm_l, r.Hp_l, r.Qp_l, G.sfm, G.isfm, g, Fm0, Fm1);
-    hll(r.Hm_r, r.Qm_r, r.Hp_r, r.Qp_r, G.sfp, G.isfp, g, Fp0, Fp1);
+    if (SURF) {
+        hll(r.Hm_l - G.zfm, r.Qm_l, r.Hp_l - G.zfm, r.Qp_l, 1.0, 1.0, g, Fm0, Fm1);
+        hll(r.Hm_r - G.zfp, r.Qm_r, r.Hp_r - G.zfp, r.Qp_r, 1.0, 1.0, g, Fp0, Fp1);
+    } else {
+        hll(r.Hm_l, r.Qm_l, r.Hp_l, r.Qp_l, G.sfm, G.isfm, g, Fm0, Fm1);
+        hll(r.Hm_r, r.Qm_r, r.Hp_r, r.Qp_r, G.sfp, G.isfp, g, Fp0, Fp1);
+    }
     R0 = Fp0 - Fm0;
     R1 = Fp1 - Fm1 - S;
 }
 
 // Local residual of eq. (10) from a ghost-complete stencil.
+// SURF: H holds the surface H + zbar of the five cells
+template <bool SURF>
 __device__ __forceinline__ void local_residual(const double H[5], const double Q[5],
                                                const CellGeom &G, const CubicGauss &W,
                                                double dx, double g, double &R0, double &R1)
@@ -226,8 +278,8 @@ __device__ __forceinline__ void local_residual(const double H[5], const double Q
     Recon r;
     recon_H(H, r);
     recon_Q(Q, r);
-    const double S = source_term(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, dx, g);
-    assemble_residual(r, S, G, g, R0, R1);
+    const double S = source_term<SURF>(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, dx, g, H[2]);
+    assemble_residual<SURF>(r, S, G, g, R0, R1);
 }
 
 // Stage U[a-2 .. a+kTile+1] of one instance into LDS (zeros outside the grid).
@@ -259,6 +311,14 @@ __device__ double block_sum(double v, double *scratch)
     return s;
 }
 
+// the surface H + zbar of the five cells of a ghost-complete stencil
+__device__ __forceinline__ void to_surface(double H[5], const Inst1D &I, int j)
+{
+#pragma unroll
+    for (int p = 0; p < 5; p++) H[p] = H[p] + I.z_avg[j + p];
+}
+
+template <bool SURF>
 __device__ void residual_tile(const Inst1D &I, int a, double *partial_out)
 {
     __shared__ double sH[kTile + 4], sQ[kTile + 4];
@@ -271,11 +331,12 @@ __device__ void residual_tile(const Inst1D &I, int a, double *partial_out)
         double H[5], Q[5];
 #pragma unroll
         for (int p = 0; p < 5; p++) { H[p] = sH[threadIdx.x + p]; Q[p] = sQ[threadIdx.x + p]; }
-        stencil_ghosts(H, Q, j, I);
-        CellGeom G = load_geom(I, j);
+        stencil_ghosts<SURF>(H, Q, j, I);
+        if (SURF) to_surface(H, I, j);
+        CellGeom G = load_geom<SURF>(I, j);
         CubicGauss W;
         double R0, R1;
-        local_residual(H, Q, G, W, I.dx, I.g, R0, R1);
+        local_residual<SURF>(H, Q, G, W, I.dx, I.g, R0, R1);
         I.R[j] = R0;
         I.R[I.N + j] = R1;
         n1 = fabs(R0) + fabs(R1);
@@ -285,18 +346,20 @@ __device__ void residual_tile(const Inst1D &I, int a, double *partial_out)
     if (threadIdx.x == 0 && partial_out) *partial_out = s;
 }
 
+template <bool SURF>
 __global__ void __launch_bounds__(kTile) k_residual_batch(const Inst1D *insts, const Tile *tiles,
                                                           NewtonState *state, double *partial)
 {
     const Tile t = tiles[blockIdx.x];
     const Inst1D &I = insts[t.lev];
     if (!inst_active(state, I)) return;
-    residual_tile(I, t.a, partial + blockIdx.x);
+    residual_tile<SURF>(I, t.a, partial + blockIdx.x);
 }
 
+template <bool SURF>
 __global__ void __launch_bounds__(kTile) k_residual_single(Inst1D I)
 {
-    residual_tile(I, blockIdx.x * kTile, nullptr);
+    residual_tile<SURF>(I, blockIdx.x * kTile, nullptr);
 }
 
 // res = (1/N) sum_j rn_j for a single instance: one workgroup, fixed order.
@@ -349,6 +412,7 @@ __global__ void __launch_bounds__(64) k_res_finalize(const Inst1D *insts, int ni
 // the same inputs the full evaluation would use, so the result is identical to re-evaluating
 // the whole local residual (which the boundary cells still do).
 
+template <bool SURF>
 __device__ __forceinline__ void perturbed_residual(const double H[5], const double Q[5], int pp, int m,
                                                    double eps, const Recon &base, double S0,
                                                    const CellGeom &G, const CubicGauss &W, double dx,
@@ -365,13 +429,13 @@ __device__ __forceinline__ void perturbed_residual(const double H[5], const doub
         if (left) { r.Hm_l = weno_minus(X[0], X[1], X[2]); r.Hp_ll = weno_plus(X[0], X[1], X[2]); }
         if (mid) { r.Hp_l = weno_plus(X[1], X[2], X[3]); r.Hm_r = weno_minus(X[1], X[2], X[3]); }
         if (right) { r.Hp_r = weno_plus(X[2], X[3], X[4]); r.Hm_rr = weno_minus(X[2], X[3], X[4]); }
-        S = source_term(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, dx, g);
+        S = source_term<SURF>(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, dx, g, X[2]);
     } else {
         if (left) r.Qm_l = weno_minus(X[0], X[1], X[2]);
         if (mid) { r.Qp_l = weno_plus(X[1], X[2], X[3]); r.Qm_r = weno_minus(X[1], X[2], X[3]); }
         if (right) r.Qp_r = weno_plus(X[2], X[3], X[4]);
     }
-    assemble_residual(r, S, G, g, R0, R1);
+    assemble_residual<SURF>(r, S, G, g, R0, R1);
 }
 
 __device__ __forceinline__ void inv2d(const double A[4], double B[4])
@@ -406,7 +470,7 @@ __device__ __forceinline__ void coarse_from_children(const double *f0, const dou
 // Jacobian rows of one tile.  With `mg` levels (batched path) the tile also writes the finest
 // right-hand side and the coarse operators of all levels that lie inside the tile (up to
 // eight: 256 -> 1 cells).
-template <typename T, int NB>
+template <typename T, int NB, bool SURF>
 __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
                               const MGArgs *mg, const Level1D *L0)
 {
@@ -424,7 +488,7 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
         double H[5], Q[5];
 #pragma unroll
         for (int p = 0; p < 5; p++) { H[p] = sH[t + p]; Q[p] = sQ[t + p]; }
-        const CellGeom G = load_geom(I, j);
+        const CellGeom G = load_geom<SURF>(I, j);
         const CubicGauss W;
         const double R0 = I.R[j], R1 = I.R[I.N + j], rn = I.rn[j];
         const double eps = I.eps, ieps = 1.0 / I.eps;
@@ -436,9 +500,11 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
         Recon base;
         double S0 = 0.0;
         if (interior) {
+            // SURF: perturbing H perturbs the surface H + zbar by the same amount
+            if (SURF) to_surface(H, I, j);
             recon_H(H, base);
             recon_Q(Q, base);
-            S0 = source_term(base.Hp_ll, base.Hp_l, base.Hm_r, base.Hm_rr, G, W, I.dx, I.g);
+            S0 = source_term<SURF>(base.Hp_ll, base.Hp_l, base.Hm_r, base.Hm_rr, G, W, I.dx, I.g, H[2]);
         }
 #pragma unroll 1
         for (int b = 0; b < NB; b++) {
@@ -451,7 +517,7 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
                 if (col_ok) {
                     double P0, P1;
                     if (interior) {
-                        perturbed_residual(H, Q, pp, m, eps, base, S0, G, W, I.dx, I.g, P0, P1);
+                        perturbed_residual<SURF>(H, Q, pp, m, eps, base, S0, G, W, I.dx, I.g, P0, P1);
                     } else {
                         double Hp[5], Qp[5];
 #pragma unroll
@@ -459,8 +525,9 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
                             Hp[p] = (p == pp && m == 0) ? H[p] + eps : H[p];
                             Qp[p] = (p == pp && m == 1) ? Q[p] + eps : Q[p];
                         }
-                        stencil_ghosts(Hp, Qp, j, I);
-                        local_residual(Hp, Qp, G, W, I.dx, I.g, P0, P1);
+                        stencil_ghosts<SURF>(Hp, Qp, j, I);
+                        if (SURF) to_surface(Hp, I, j);
+                        local_residual<SURF>(Hp, Qp, G, W, I.dx, I.g, P0, P1);
                     }
                     e0 = (P0 - R0) * ieps;
                     e1 = (P1 - R1) * ieps;
@@ -525,7 +592,7 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
     }
 }
 
-template <typename T, int NB>
+template <typename T, int NB, bool SURF>
 __global__ void __launch_bounds__(kTile) k_jacobian_batch(MGArgs mg, const Tile *tiles)
 {
     const Tile t = tiles[blockIdx.x];
@@ -534,29 +601,35 @@ __global__ void __launch_bounds__(kTile) k_jacobian_batch(MGArgs mg, const Tile 
     const Level1D L = mg.levs[I.lev0];
     if (L.nb != NB) return;
     T *base = reinterpret_cast<T *>(mg.mg);
-    jacobian_tile<T, NB>(I, t.a, base + L.J, L.n, base + L.rhs, &mg, &L);
+    jacobian_tile<T, NB, SURF>(I, t.a, base + L.J, L.n, base + L.rhs, &mg, &L);
 }
 
-template <int NB>
+template <int NB, bool SURF>
 __global__ void __launch_bounds__(kTile) k_jacobian_single(Inst1D I, double *J)
 {
-    jacobian_tile<double, NB>(I, blockIdx.x * kTile, J, I.N, (double *)nullptr, (const MGArgs *)nullptr,
+    jacobian_tile<double, NB, SURF>(I, blockIdx.x * kTile, J, I.N, (double *)nullptr, (const MGArgs *)nullptr,
                               (const Level1D *)nullptr);
 }
 
 // ---- launchers ---------------------------------------------------------------------------
 
 hipError_t launch_residual1d(const Inst1D *insts_dev, const Tile *tiles, int ntiles,
-                             const Inst1D *single, NewtonState *state, double *partial,
+                             const Inst1D *single, NewtonState *state, double *partial, int recon,
                              hipStream_t s)
 {
+    const bool surf = recon == NMG_RECON_SURFACE;
     if (single) {
         int nt = (single->N + kTile - 1) / kTile;
-        hipLaunchKernelGGL(k_residual_single, dim3(nt), dim3(kTile), 0, s, *single);
+        if (surf) hipLaunchKernelGGL(k_residual_single<true>, dim3(nt), dim3(kTile), 0, s, *single);
+        else hipLaunchKernelGGL(k_residual_single<false>, dim3(nt), dim3(kTile), 0, s, *single);
     } else {
         if (ntiles == 0) return hipSuccess;
-        hipLaunchKernelGGL(k_residual_batch, dim3(ntiles), dim3(kTile), 0, s, insts_dev, tiles,
-                           state, partial);
+        if (surf)
+            hipLaunchKernelGGL(k_residual_batch<true>, dim3(ntiles), dim3(kTile), 0, s, insts_dev, tiles, state,
+                               partial);
+        else
+            hipLaunchKernelGGL(k_residual_batch<false>, dim3(ntiles), dim3(kTile), 0, s, insts_dev, tiles, state,
+                               partial);
     }
     return hipGetLastError();
 }
@@ -575,28 +648,36 @@ hipError_t launch_sum_res(const double *rn, int N, double *res, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_jacobian1d(const Inst1D *insts_dev, const Tile *tiles, int ntiles,
-                             const Inst1D *single, double *J_single, const MGArgs &mg, int prec,
-                             int nb_mask, hipStream_t s)
+template <bool SURF>
+static void jacobian_launches(const Tile *tiles, int ntiles, const Inst1D *single, double *J_single,
+                              const MGArgs &mg, int prec, int nb_mask, hipStream_t s)
 {
     if (single) {
         int nt = (single->N + kTile - 1) / kTile;
         if (single->nb == 5)
-            hipLaunchKernelGGL(k_jacobian_single<5>, dim3(nt), dim3(kTile), 0, s, *single, J_single);
+            hipLaunchKernelGGL((k_jacobian_single<5, SURF>), dim3(nt), dim3(kTile), 0, s, *single, J_single);
         else
-            hipLaunchKernelGGL(k_jacobian_single<3>, dim3(nt), dim3(kTile), 0, s, *single, J_single);
-        return hipGetLastError();
+            hipLaunchKernelGGL((k_jacobian_single<3, SURF>), dim3(nt), dim3(kTile), 0, s, *single, J_single);
+        return;
     }
-    if (ntiles == 0) return hipSuccess;
-    (void)insts_dev;
     // one launch per stencil width present; each tile runs only the one its instance uses
     if (prec == NMG_FP32_MG) {
-        if (nb_mask & 1) hipLaunchKernelGGL((k_jacobian_batch<float, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
-        if (nb_mask & 2) hipLaunchKernelGGL((k_jacobian_batch<float, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+        if (nb_mask & 1) hipLaunchKernelGGL((k_jacobian_batch<float, 3, SURF>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+        if (nb_mask & 2) hipLaunchKernelGGL((k_jacobian_batch<float, 5, SURF>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
     } else {
-        if (nb_mask & 1) hipLaunchKernelGGL((k_jacobian_batch<double, 3>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
-        if (nb_mask & 2) hipLaunchKernelGGL((k_jacobian_batch<double, 5>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+        if (nb_mask & 1) hipLaunchKernelGGL((k_jacobian_batch<double, 3, SURF>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+        if (nb_mask & 2) hipLaunchKernelGGL((k_jacobian_batch<double, 5, SURF>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
     }
+}
+
+hipError_t launch_jacobian1d(const Inst1D *insts_dev, const Tile *tiles, int ntiles,
+                             const Inst1D *single, double *J_single, const MGArgs &mg, int prec,
+                             int nb_mask, int recon, hipStream_t s)
+{
+    (void)insts_dev;
+    if (!single && ntiles == 0) return hipSuccess;
+    if (recon == NMG_RECON_SURFACE) jacobian_launches<true>(tiles, ntiles, single, J_single, mg, prec, nb_mask, s);
+    else jacobian_launches<false>(tiles, ntiles, single, J_single, mg, prec, nb_mask, s);
     return hipGetLastError();
 }
 

@@ -65,6 +65,14 @@ class Problem1DDevice:
         d.sig_gp = self.sig_gp.data_ptr()
         d.sigx_gp = self.sigx_gp.data_ptr()
         d.bx_gp = self.bx_gp.data_ptr()
+        d.recon = getattr(prob, "recon", A.NMG_RECON_CONSERVED)
+        if d.recon == A.NMG_RECON_SURFACE:
+            from swe_workloads import bottom_faces_and_averages
+            zf, za = bottom_faces_and_averages(prob)
+            self.z_face = torch.tensor(zf, **f64)
+            self.z_avg = torch.tensor(za, **f64)
+            d.z_face = self.z_face.data_ptr()
+            d.z_avg = self.z_avg.data_ptr()
         self.desc = d
         self.n = n
         self.device = device

@@ -76,6 +76,7 @@ class Problem1D:
     q0: float = 1.0             # initial guess: Q = q0
     g: float = G
     meta: dict = dataclasses.field(default_factory=dict)
+    recon: int = 0              # 0: reconstruct H (the paper); 1: reconstruct the surface h + b
 
     @property
     def dx(self) -> float:
@@ -442,3 +443,36 @@ def synthetic_operator_2d(nx: int, ny: int, seed: int = 0, dominance: float = 3.
         J[out, b] = 0.0
     rhs = rng.uniform(-1.0, 1.0, (ny, nx, 3))
     return J, rhs
+
+
+def bottom_faces_and_averages(prob: Problem1D):
+    """Bottom samples for the surface reconstruction: b at the faces x_{j-1/2}, j = 0..N
+    ([N+1]), and the cell averages of b over cells -2..N+1 ([N+4]: two cells beyond each end
+    of the grid, for the ghosts), each by the three-point Gauss-Legendre rule."""
+    n, dx = prob.n, prob.dx
+    zf, _ = prob.bottom(prob.x0 + np.arange(n + 1) * dx)
+    xc = prob.x0 + (np.arange(-2, n + 2) + 0.5) * dx
+    r = 0.5 * dx * np.sqrt(0.6)
+    zl, _ = prob.bottom(xc - r)
+    zc, _ = prob.bottom(xc)
+    zr, _ = prob.bottom(xc + r)
+    za = (5.0 * zl + 8.0 * zc + 5.0 * zr) / 18.0
+    return np.ascontiguousarray(zf, dtype=np.float64), np.ascontiguousarray(za, dtype=np.float64)
+
+
+def lake_at_rest(n: int = 64, surface: float = 1.0, amp: float = 0.3, levels: int = 3,
+                 recon: int = 1, right: str = "wall", centre: float = 10.0) -> Problem1D:
+    """Still water (surface h + b = ``surface``, Q = 0) over a smooth bump of height ``amp``
+    centred at ``centre`` in a channel of constant width on [0, 25], walls at both ends
+    (``right = "depth"`` imposes the still depth at the right end instead); the initial guess is
+    the still surface sampled at the cell centres."""
+    def bottom(x):
+        e = np.exp(-0.5 * (x - centre) ** 2)
+        return amp * e, -amp * (x - centre) * e
+
+    def width(x):
+        return np.ones_like(x), np.zeros_like(x)
+
+    rb = BC(BC_WALL) if right == "wall" else BC(BC_DEPTH, h=surface)
+    return Problem1D("lake", 0.0, 25.0, n, levels, bottom, width, BC(BC_WALL), rb,
+                     Params(eps=eps_for_n(n)), surface0=surface, q0=0.0, recon=recon)

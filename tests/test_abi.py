@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header_layout():
     abi, _ = _lib()
     assert ctypes.sizeof(abi.nmg_bc) == 40
-    assert ctypes.sizeof(abi.nmg_desc) == 24 + 40 + 4 * 40 + 8 + 5 * 8
+    assert ctypes.sizeof(abi.nmg_desc) == 24 + 40 + 4 * 40 + 8 + 7 * 8
     assert ctypes.sizeof(abi.nmg_params) == 5 * 8 + 8 * 4 + 8
 
 
@@ -115,3 +115,14 @@ def test_nested_solve_argument_checks():
     descs[2].nx = 64
     assert L.nmg_nested_solve(descs, 3, params, ctypes.c_void_p(1024), 16, U, st, None) == abi.NMG_ENOMEM_WS
     assert L.nmg_interp_coarse_to_fine(ctypes.c_void_p(256), 2, ctypes.c_void_p(512), None) == abi.NMG_EINVAL
+
+
+def test_reconstruction_field_is_checked():
+    """recon must be NMG_RECON_CONSERVED or NMG_RECON_SURFACE (1D); 2D takes only the first."""
+    abi, L = _lib()
+    d, p = _desc(abi)
+    d.recon = abi.NMG_RECON_SURFACE
+    assert L.nmg_workspace_bytes(ctypes.byref(d), ctypes.byref(p)) > 0
+    d.recon = 2
+    assert L.nmg_workspace_bytes(ctypes.byref(d), ctypes.byref(p)) == 0
+    assert b"recon" in L.nmg_last_error()
