@@ -41,9 +41,13 @@ BYTES_JACOBIAN_J3 = 16 + 16 + 8 + 56 + 96 + 16 + 96 * (1.0 - 2.0 ** -8)
 # the kernel source is the one it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobian_j3_fp64_hump12800_batch256_traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2505_10857_amd", "csrc", "swe1d.hip")
-#   finest pre-smoothing: read J 96 and rhs 16; write dU 16 and the restricted rhs 8 per fine
-#   cell; plus a read of dU 16 in the second of the two cycles (average 8)
-BYTES_SMOOTH_PRE_J3 = 96 + 16 + 16 + 8 + 8
+#   finest pre-smoothing of the first V-cycle of a Newton step (dU starts at zero): read J 96
+#   and rhs 16; write dU 16 and the restricted rhs 8 per fine cell (the later cycles' finest
+#   pre-smoothing runs in the launch of the previous post-smoothing)
+BYTES_SMOOTH_PRE_J3 = 96 + 16 + 16 + 8
+#   finest fused post- + pre-smoothing: read J 96, rhs 16, dU 16 and the coarse correction 8;
+#   write dU 16 and the restricted rhs 8 per fine cell
+BYTES_SMOOTH_FUSED_J3 = 96 + 16 + 16 + 8 + 16 + 8
 
 
 def parse():
@@ -288,13 +292,20 @@ def main():
     # ---- roofline of the dominant kernel: HIP events around its launches on the launch stream --
     el2, stj, jms, jcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_JACOBIAN)
     _, stp, pms, pcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_SMOOTH_PRE)
+    fused = solver.options()["fused_finest"]
+    if fused:
+        _, stf, fms, fcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_SMOOTH_FUSED)
     cells = args.batch * args.n
     # instances drop out of every launch once converged, so the work of the timed launches is
     # counted per active instance: the Jacobian runs once per Newton step of an instance, the
     # finest pre-smoothing once per V-cycle (nu3 = 2 per step); "full launches" = that work in
     # units of one launch over the whole batch
     jac_full = sum(s[0] for st in stj for s in st) / args.batch
-    pre_full = 2 * sum(s[0] for st in stp for s in st) / args.batch
+    # finest pre-smoothing launches per Newton step: one per V-cycle, or only the first one
+    # when the plan runs each later one together with the previous post-smoothing
+    pre_per_step = 1 if fused else 2
+    pre_full = pre_per_step * sum(s[0] for st in stp for s in st) / args.batch
+    pre_bytes = BYTES_SMOOTH_PRE_J3 + (0 if fused else 8)   # unfused: dU read in the 2nd cycle
     jac_ms = jms / jac_full       # time of one launch over the whole batch
     pre_ms = pms / pre_full
     jac_flops = cells * 6 * FLOPS_LOCAL_RESIDUAL
@@ -314,11 +325,23 @@ def main():
         "kernel": "k_smooth<double,3> mode 0, finest level (pre-smoothing + restriction)",
         "bound": "hbm", "avg_launch_ms": pms / max(pcnt, 1), "launches_timed": pcnt, "full_launch_ms": pre_ms,
         "full_launch_equivalents": pre_full,
-        "achieved": cells * BYTES_SMOOTH_PRE_J3 / (pre_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+        "achieved": cells * pre_bytes / (pre_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": cells * BYTES_SMOOTH_PRE_J3 / (pre_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "frac": cells * pre_bytes / (pre_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "note": "working set below the 256 MB Infinity Cache: effective GB/s",
     }
+    if fused:
+        # one launch per Newton step (nu3 = 2): post-smoothing of the first V-cycle and
+        # pre-smoothing of the second on the finest level
+        f_full = sum(s[0] for st in stf for s in st) / args.batch
+        f_ms = fms / f_full
+        out["smoother_fused_roofline"] = {
+            "kernel": "k_smooth<double,3> mode 2, finest level (prolongation + post- and pre-smoothing + restriction)",
+            "bound": "hbm", "avg_launch_ms": fms / max(fcnt, 1), "launches_timed": fcnt, "full_launch_ms": f_ms,
+            "full_launch_equivalents": f_full,
+            "achieved": cells * BYTES_SMOOTH_FUSED_J3 / (f_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": cells * BYTES_SMOOTH_FUSED_J3 / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        }
 
     # ---- extra forms --------------------------------------------------------------------------
     if not args.no_extras:

@@ -221,6 +221,7 @@ void nmg_plan_destroy(nmg_plan *plan);
 #define NMG_K_SMOOTH_POST 3   /* finest-level prolongation + post-smoothing (eq. 18, 19) */
 #define NMG_K_RESIDUAL 4      /* residual (eq. 10) */
 #define NMG_K_COARSEN 5       /* coarse operators of all levels (eq. 17) */
+#define NMG_K_SMOOTH_FUSED 6  /* finest level: post-smoothing of one V-cycle + pre-smoothing of the next */
 nmg_status nmg_plan_profile(nmg_plan *plan, int32_t kernel);
 nmg_status nmg_plan_profile_read(nmg_plan *plan, double *ms, int32_t *launches);
 
@@ -231,10 +232,14 @@ nmg_status nmg_plan_profile_read(nmg_plan *plan, double *ms, int32_t *launches);
  * a small value spreads more levels over the whole GPU, a large one saves launches and
  * synchronisation.  Default 2048.  Setting options refreshes the plan's device tables (and any
  * captured graph) on its next use; the workspace size does not change.  Set them before
- * nmg_plan_begin / nmg_plan_solve. */
+ * nmg_plan_begin / nmg_plan_solve.  fused_finest (reported by nmg_plan_get_options, ignored by
+ * nmg_plan_set_options): 1 when the finest level's post-smoothing of one V-cycle and the
+ * pre-smoothing of the next run in one launch (multigrid plans with nu3 >= 2 whose instances all
+ * use the three-block Jacobian); the arithmetic is the same either way. */
 typedef struct {
     int32_t bottom_cells;
-    int32_t reserved[7];
+    int32_t fused_finest;
+    int32_t reserved[6];
 } nmg_plan_options;
 nmg_status nmg_plan_set_options(nmg_plan *plan, const nmg_plan_options *opt);
 nmg_status nmg_plan_get_options(const nmg_plan *plan, nmg_plan_options *opt);

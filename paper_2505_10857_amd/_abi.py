@@ -47,6 +47,7 @@ NMG_K_SMOOTH_PRE = 2
 NMG_K_SMOOTH_POST = 3
 NMG_K_RESIDUAL = 4
 NMG_K_COARSEN = 5
+NMG_K_SMOOTH_FUSED = 6
 
 
 class nmg_bc(C.Structure):
@@ -77,7 +78,7 @@ class nmg_stats(C.Structure):
 
 
 class nmg_plan_options(C.Structure):
-    _fields_ = [("bottom_cells", C.c_int32), ("reserved", C.c_int32 * 7)]
+    _fields_ = [("bottom_cells", C.c_int32), ("fused_finest", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 NMG_TUNE_CANDIDATES = 4

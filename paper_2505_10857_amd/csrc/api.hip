@@ -125,6 +125,9 @@ struct nmg_plan {
     std::vector<std::pair<int, int>> coarsen8;// (t0, nt) per pass from level 8 (Newton path)
     std::vector<std::pair<int, int>> smooth;  // (t0, nt) per depth
     std::vector<int> smooth_mask;             // stencil widths present per depth (bit0: 3, bit1: 5)
+    // finest-level tiles of the launch that runs one V-cycle's post-smoothing and the next one's
+    // pre-smoothing (nu3 >= 2, every instance on three-block rows); count 0 when not used
+    std::pair<int, int> fused0 = {0, 0};
     int jac_mask = 0;
     int depth = 0;
     size_t off_insts = 0, off_levs = 0, off_tiles = 0, off_list = 0, off_state = 0, off_partial = 0,
@@ -222,6 +225,8 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
             L.coarsest = l == I.levels - 1;
             L.halo = halo_cells(L.nb, P->linear == NMG_LINEAR_MG ? std::max(I.nu1, I.nu2) : 1);
             L.V = kTile - 2 * L.halo;
+            L.halo2 = halo_cells(L.nb, I.nu1 + I.nu2);
+            L.V2 = kTile - 2 * L.halo2;
             L.child = L.coarsest ? -1 : (int)P->levs.size() + 1;
             L.J = mg_elems; mg_elems += (long long)L.nb * 4 * L.n;
             L.rhs = mg_elems; mg_elems += 2LL * L.n;
@@ -300,6 +305,21 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
         }
         P->smooth.push_back({t0, (int)P->tiles.size() - t0});
         P->smooth_mask.push_back(mask);
+    }
+    P->fused0 = {0, 0};
+    if (P->linear == NMG_LINEAR_MG && P->nu3 >= 2 && P->jac_mask == 1 && P->depth > 0) {
+        bool ok = true;
+        for (int k = 0; k < n && ok; k++)
+            ok = P->levs[lev_index[k][0]].V2 >= kTile / 2;   // at most twice the tiles
+        if (ok) {
+            int t0 = (int)P->tiles.size();
+            for (int k = 0; k < n; k++) {
+                if (P->insts[k].lbot == 0) continue;
+                const Level1D &L = P->levs[lev_index[k][0]];
+                for (int a = 0; a < L.n; a += L.V2) P->tiles.push_back({lev_index[k][0], a});
+            }
+            P->fused0 = {t0, (int)P->tiles.size() - t0};
+        }
     }
     // byte layout
     size_t o = 0;
@@ -416,23 +436,43 @@ nmg_status enqueue_setup(nmg_plan *P, char *ws, const MGArgs &mg, hipStream_t s,
 }
 
 // One V-cycle (Algorithm 2) over every instance.
+// One V-cycle (Algorithm 2) over every instance.  Each tiled launch reads a level's dU from one
+// of its two buffers and writes the other: below the finest level pre-smoothing writes dUo and
+// post-smoothing reads it back into dU.  On the finest level `src0` names the buffer holding
+// its current dU (0: dU, 1: dUo); `skip_pre0` leaves out its pre-smoothing (already done by the
+// fused launch of the previous cycle) and `fuse_up0` replaces its post-smoothing by the fused
+// launch that also pre-smooths for the next cycle.  Returns the finest level's buffer after the
+// cycle in *src0_out.
 nmg_status enqueue_vcycle(nmg_plan *P, char *ws, const MGArgs &mg, bool zero_init0, bool final_update,
-                          hipStream_t s, bool cap = true)
+                          hipStream_t s, bool cap = true, int src0 = 0, bool skip_pre0 = false,
+                          bool fuse_up0 = false, int *src0_out = nullptr)
 {
     const int *list = reinterpret_cast<const int *>(ws + P->off_list);
     for (int d = 0; d < P->depth; d++) {
-        if (P->smooth[d].second == 0) continue;
+        if (P->smooth[d].second == 0 || (d == 0 && skip_pre0)) continue;
         ProfScope ps(P, d == 0 ? NMG_K_SMOOTH_PRE : -1, s, cap);
+        const int src = d == 0 ? src0 : 0;
         HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
-                                P->smooth_mask[d], 0, (d > 0 || zero_init0) ? 1 : 0, 0, P->prec, s));
+                                P->smooth_mask[d], 0, (d > 0 || zero_init0) ? 1 : 0, 0, src, P->prec, s));
+        if (d == 0) src0 = 1 - src;
     }
     HIP_TRY(launch_bottom(mg, list, P->n, zero_init0 ? 1 : 0, final_update ? 1 : 0, P->prec, P->bottom_nt, s));
     for (int d = P->depth - 1; d >= 0; d--) {
         if (P->smooth[d].second == 0) continue;
+        if (d == 0 && fuse_up0) {
+            ProfScope ps(P, NMG_K_SMOOTH_FUSED, s, cap);
+            HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->fused0.first), P->fused0.second, P->smooth_mask[0], 2,
+                                    0, 0, src0, P->prec, s));
+            src0 = 1 - src0;
+            continue;
+        }
         ProfScope ps(P, d == 0 ? NMG_K_SMOOTH_POST : -1, s, cap);
+        const int src = d == 0 ? src0 : 1;
         HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
-                                P->smooth_mask[d], 1, 0, (d == 0 && final_update) ? 1 : 0, P->prec, s));
+                                P->smooth_mask[d], 1, 0, (d == 0 && final_update) ? 1 : 0, src, P->prec, s));
+        if (d == 0) src0 = 1 - src;
     }
+    if (src0_out) *src0_out = src0;
     return NMG_OK;
 }
 
@@ -451,8 +491,13 @@ nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s, bool cap = false)
     nmg_status st = enqueue_setup(P, ws, mg, s, cap, true);
     if (st != NMG_OK) return st;
     if (P->linear == NMG_LINEAR_MG) {
+        // with fused finest-level tiles, the post-smoothing of a cycle and the pre-smoothing of
+        // the next run in one launch (nothing else touches the finest level between them)
+        const bool fuse = P->fused0.second > 0;
+        int src0 = 0;
         for (int v = 0; v < P->nu3; v++) {
-            st = enqueue_vcycle(P, ws, mg, v == 0, v == P->nu3 - 1, s, cap);
+            st = enqueue_vcycle(P, ws, mg, v == 0, v == P->nu3 - 1, s, cap, src0, fuse && v > 0,
+                                fuse && v < P->nu3 - 1, &src0);
             if (st != NMG_OK) return st;
         }
     } else {
@@ -654,7 +699,7 @@ size_t nmg_plan_workspace_bytes(const nmg_plan *plan) { return plan ? plan->tota
 nmg_status nmg_plan_profile(nmg_plan *P, int32_t kernel)
 {
     if (!P) return fail(NMG_EINVAL, "null plan");
-    if (kernel < NMG_K_NONE || kernel > NMG_K_COARSEN) return fail(NMG_EINVAL, "unknown kernel id");
+    if (kernel < NMG_K_NONE || kernel > NMG_K_SMOOTH_FUSED) return fail(NMG_EINVAL, "unknown kernel id");
     P->prof_kernel = kernel;
     return NMG_OK;
 }
@@ -692,6 +737,7 @@ nmg_status nmg_plan_get_options(const nmg_plan *P, nmg_plan_options *opt)
     if (!P || !opt) return fail(NMG_EINVAL, "null argument");
     memset(opt, 0, sizeof(*opt));
     opt->bottom_cells = P->bottom_cells;
+    opt->fused_finest = P->fused0.second > 0 ? 1 : 0;
     return NMG_OK;
 }
 

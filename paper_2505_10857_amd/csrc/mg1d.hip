@@ -150,9 +150,13 @@ __global__ void __launch_bounds__(kTile) k_coarsen(MGArgs mg, const Tile *tiles)
 
 // mode 0: (zero or loaded) dU -> nu1 symmetric steps -> write dU, restrict rhs to the child.
 // mode 1: dU + prolongated child dU -> nu2 symmetric steps -> write dU (or update U).
+// mode 2: dU + prolongated child dU -> nu2 + nu1 symmetric steps (the post-smoothing of one
+//         V-cycle and the pre-smoothing of the next, with nothing between them on this level)
+//         -> write dU, restrict rhs to the child; its tiles have the wider halo halo2.
+// src_out: the tile reads dU from dUo (1) or dU (0) and writes its cells to the other buffer.
 template <typename T, int NB, int MODE>
 __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, int zero_init,
-                                                  int final_update)
+                                                  int final_update, int src_out)
 {
     constexpr int mode = MODE;
     constexpr int HW = NB / 2;
@@ -164,10 +168,13 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
     if (!active_of(mg, L.inst)) return;
     const Inst1D &I = mg.insts[L.inst];
     T *base = reinterpret_cast<T *>(mg.mg);
-    const int n = L.n, h = L.halo;
+    const int n = L.n, h = mode == 2 ? L.halo2 : L.halo, V = mode == 2 ? L.V2 : L.V;
     const int t = threadIdx.x;
     const int j = tl.a - h + t;
     const bool in = j >= 0 && j < n;
+    // the halo of a tile must hold the values from before the launch, so the cells are written
+    // to the other buffer
+    const long long src = src_out ? L.dUo : L.dU, dst = src_out ? L.dU : L.dUo;
 
     double Jr[NB][4], D[4], r0 = 0.0, r1 = 0.0, du0 = 0.0, du1 = 0.0;
 #pragma unroll
@@ -181,14 +188,11 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
     if (in) {
         r0 = ld(base + L.rhs, j);
         r1 = ld(base + L.rhs, n + (long long)j);
-        // pre-smoothing reads dU and writes dUo, post-smoothing reads dUo and writes dU (the
-        // halo of a tile must hold the values from before the launch)
-        const long long src = mode == 0 ? L.dU : L.dUo;
         if (!(mode == 0 && zero_init)) {
             du0 = ld(base + src, j);
             du1 = ld(base + src, n + (long long)j);
         }
-        if (mode == 1) {
+        if (mode != 0) {
             const Level1D &Lc = mg.levs[L.child];
             du0 = du0 + ld(base + Lc.dU, j >> 1);
             du1 = du1 + ld(base + Lc.dU, Lc.n + (long long)(j >> 1));
@@ -199,45 +203,56 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
     if (t < HW) { s0[t] = 0.0; s1[t] = 0.0; s0[kTile + HW + t] = 0.0; s1[kTile + HW + t] = 0.0; }
     __syncthreads();
 
-    const int steps = mode == 0 ? I.nu1 : I.nu2;
     const double w = I.omega;
     const int col = ((j % C) + C) % C;
-    // half-sweep colours 0..C-1, C-1..0 per step; a run of equal colours (at every turn) sees
-    // the same neighbour values, so its relaxations share one off-diagonal sum
-    const int total = steps * 2 * C;
-    int cur = -1, reps = 0;
-    for (int q = 0; q <= total; q++) {
-        const int hs = q % (2 * C);
-        const int c = q == total ? -1 : (hs < C ? hs : 2 * C - 1 - hs);
-        if (c == cur) { reps++; continue; }
-        if (reps > 0) {
-            if (in && col == cur) {
-                // eq. (19): dU_j <- (1-w) dU_j - w J_jj^{-1} (rhs_j + sum_{i != j} J_ji dU_i)
-                double a0 = r0, a1 = r1;
-#pragma unroll
-                for (int b = 0; b < NB; b++) {
-                    if (b == HW) continue;
-                    const double x0 = s0[t + b], x1 = s1[t + b];
-                    a0 = a0 + (Jr[b][0] * x0 + Jr[b][1] * x1);
-                    a1 = a1 + (Jr[b][2] * x0 + Jr[b][3] * x1);
-                }
-                const double t0 = D[0] * a0 + D[1] * a1;
-                const double t1 = D[2] * a0 + D[3] * a1;
-                for (int k = 0; k < reps; k++) {
-                    du0 = (1.0 - w) * du0 - w * t0;
-                    du1 = (1.0 - w) * du1 - w * t1;
-                }
-                s0[t + HW] = du0;
-                s1[t + HW] = du1;
-            }
+    // mode 2 runs the post-smoothing steps, rounds dU to the storage type as the separate
+    // launches would when storing it, then the pre-smoothing steps
+    for (int phase = 0; phase < (mode == 2 ? 2 : 1); phase++) {
+        const int steps = mode == 0 ? I.nu1 : mode == 1 ? I.nu2 : phase == 0 ? I.nu2 : I.nu1;
+        if (phase == 1) {
+            du0 = (double)(T)du0;
+            du1 = (double)(T)du1;
+            s0[t + HW] = du0;
+            s1[t + HW] = du1;
             __syncthreads();
         }
-        cur = c;
-        reps = 1;
+        // half-sweep colours 0..C-1, C-1..0 per step; a run of equal colours (at every turn)
+        // sees the same neighbour values, so its relaxations share one off-diagonal sum
+        const int total = steps * 2 * C;
+        int cur = -1, reps = 0;
+        for (int q = 0; q <= total; q++) {
+            const int hs = q % (2 * C);
+            const int c = q == total ? -1 : (hs < C ? hs : 2 * C - 1 - hs);
+            if (c == cur) { reps++; continue; }
+            if (reps > 0) {
+                if (in && col == cur) {
+                    // eq. (19): dU_j <- (1-w) dU_j - w J_jj^{-1} (rhs_j + sum_{i != j} J_ji dU_i)
+                    double a0 = r0, a1 = r1;
+#pragma unroll
+                    for (int b = 0; b < NB; b++) {
+                        if (b == HW) continue;
+                        const double x0 = s0[t + b], x1 = s1[t + b];
+                        a0 = a0 + (Jr[b][0] * x0 + Jr[b][1] * x1);
+                        a1 = a1 + (Jr[b][2] * x0 + Jr[b][3] * x1);
+                    }
+                    const double t0 = D[0] * a0 + D[1] * a1;
+                    const double t1 = D[2] * a0 + D[3] * a1;
+                    for (int k = 0; k < reps; k++) {
+                        du0 = (1.0 - w) * du0 - w * t0;
+                        du1 = (1.0 - w) * du1 - w * t1;
+                    }
+                    s0[t + HW] = du0;
+                    s1[t + HW] = du1;
+                }
+                __syncthreads();
+            }
+            cur = c;
+            reps = 1;
+        }
     }
 
-    const bool valid = in && t >= h && t < h + L.V;
-    if (mode == 0) {
+    const bool valid = in && t >= h && t < h + V;
+    if (mode != 1) {
         // restriction, eq. (17): rhs_c = sum over the two children of (rhs + sum_i J dU_i)
         double a0 = r0, a1 = r1;
 #pragma unroll
@@ -249,8 +264,8 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
         const double p0 = __shfl_xor(a0, 1, 64);
         const double p1 = __shfl_xor(a1, 1, 64);
         if (valid) {
-            base[L.dUo + j] = (T)du0;
-            base[L.dUo + n + (long long)j] = (T)du1;
+            base[dst + j] = (T)du0;
+            base[dst + n + (long long)j] = (T)du1;
             if ((j & 1) == 0 && !L.coarsest) {
                 const Level1D &Lc = mg.levs[L.child];
                 base[Lc.rhs + (j >> 1)] = (T)(a0 + p0);
@@ -263,8 +278,8 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
             I.U[j] = I.U[j] + I.tau * du0;
             I.U[I.N + j] = I.U[I.N + j] + I.tau * du1;
         } else {
-            base[L.dU + j] = (T)du0;
-            base[L.dU + n + (long long)j] = (T)du1;
+            base[dst + j] = (T)du0;
+            base[dst + n + (long long)j] = (T)du1;
         }
     }
 }
@@ -896,24 +911,29 @@ hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero
 
 template <typename T, int NB>
 static void launch_smooth_t(const MGArgs &mg, const Tile *tiles, int ntiles, int mode, int zero_init,
-                            int final_update, hipStream_t s)
+                            int final_update, int src_out, hipStream_t s)
 {
     if (mode == 0)
-        hipLaunchKernelGGL((k_smooth<T, NB, 0>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, final_update);
+        hipLaunchKernelGGL((k_smooth<T, NB, 0>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, final_update,
+                           src_out);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_smooth<T, NB, 1>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, final_update,
+                           src_out);
     else
-        hipLaunchKernelGGL((k_smooth<T, NB, 1>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, final_update);
+        hipLaunchKernelGGL((k_smooth<T, NB, 2>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, final_update,
+                           src_out);
 }
 
 hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_mask, int mode,
-                           int zero_init, int final_update, int prec, hipStream_t s)
+                           int zero_init, int final_update, int src_out, int prec, hipStream_t s)
 {
     if (ntiles == 0) return hipSuccess;
     if (prec == NMG_FP32_MG) {
-        if (nb_mask & 1) launch_smooth_t<float, 3>(mg, tiles, ntiles, mode, zero_init, final_update, s);
-        if (nb_mask & 2) launch_smooth_t<float, 5>(mg, tiles, ntiles, mode, zero_init, final_update, s);
+        if (nb_mask & 1) launch_smooth_t<float, 3>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
+        if (nb_mask & 2) launch_smooth_t<float, 5>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
     } else {
-        if (nb_mask & 1) launch_smooth_t<double, 3>(mg, tiles, ntiles, mode, zero_init, final_update, s);
-        if (nb_mask & 2) launch_smooth_t<double, 5>(mg, tiles, ntiles, mode, zero_init, final_update, s);
+        if (nb_mask & 1) launch_smooth_t<double, 3>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
+        if (nb_mask & 2) launch_smooth_t<double, 5>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
     }
     return hipGetLastError();
 }

@@ -44,6 +44,7 @@ struct Inst1D {
 struct Level1D {
     int inst, l, n, nb;
     int coarsest, halo, V, child;    // child: level index of l+1 (-1 at the coarsest)
+    int halo2, V2;                   // halo and valid width of a launch running nu2 + nu1 steps
     long long J, rhs, dU;
     // second dU buffer [2][n]: a tiled kernel reads its tile and halo from one buffer and writes
     // its cells to the other, so that no workgroup reads a halo cell that a neighbouring tile of
@@ -145,8 +146,11 @@ hipError_t launch_coarsen1d(const MGArgs &mg, const Tile *tiles, int ntiles, int
 // nt: threads of the bottom workgroup (256, 512 or 1024); it handles levels of up to 2 nt cells
 hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero_init0, int final_update,
                          int prec, int nt, hipStream_t s);
-hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_max, int mode,
-                           int zero_init, int final_update, int prec, hipStream_t s);
+// mode 0: pre-smoothing + restriction; 1: prolongation + post-smoothing (+ update); 2: both,
+// the post-smoothing of one V-cycle and the pre-smoothing of the next on one level.  src_out:
+// read dU from dUo (1) or dU (0) and write the other buffer.
+hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_mask, int mode,
+                           int zero_init, int final_update, int src_out, int prec, hipStream_t s);
 hipError_t launch_convert(const void *src, int src_prec, void *dst, int dst_prec, long long n,
                           hipStream_t s);
 // Newton-SOR (section 5.1.1) on level 0: one symmetric multicolour block-SOR step per launch

@@ -222,7 +222,7 @@ class BatchSolver1D:
     def options(self) -> dict:
         opt = A.nmg_plan_options()
         A.check(A.load().nmg_plan_get_options(self.plan, C.byref(opt)))
-        return {"bottom_cells": opt.bottom_cells}
+        return {"bottom_cells": opt.bottom_cells, "fused_finest": bool(opt.fused_finest)}
 
     def autotune(self, Us: List[torch.Tensor], trial_steps: int = 3, use_graph: bool = True):
         """Time every candidate option set on these states (restored afterwards), keep the
