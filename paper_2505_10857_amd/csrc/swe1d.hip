@@ -405,38 +405,8 @@ __global__ void __launch_bounds__(64) k_res_finalize(const Inst1D *insts, int ni
 }
 
 // ---- Jacobian --------------------------------------------------------------------------
-// Column (i, m) of eq. (12) perturbs component m of cell i.  Away from the boundaries the
-// ghosts do not move, so a perturbation of H leaves every Q reconstruction unchanged, a
-// perturbation of Q leaves every H reconstruction and the source unchanged, and only the
-// reconstructions whose three-cell stencil contains cell i change.  Those are recomputed from
-// the same inputs the full evaluation would use, so the result is identical to re-evaluating
-// the whole local residual (which the boundary cells still do).
-
-template <bool SURF>
-__device__ __forceinline__ void perturbed_residual(const double H[5], const double Q[5], int pp, int m,
-                                                   double eps, const Recon &base, double S0,
-                                                   const CellGeom &G, const CubicGauss &W, double dx,
-                                                   double g, double &R0, double &R1)
-{
-    Recon r = base;
-    double S = S0;
-    double X[5];
-    const double *src = m == 0 ? H : Q;
-#pragma unroll
-    for (int p = 0; p < 5; p++) X[p] = p == pp ? src[p] + eps : src[p];
-    const bool left = pp <= 2, mid = pp >= 1 && pp <= 3, right = pp >= 2;
-    if (m == 0) {
-        if (left) { r.Hm_l = weno_minus(X[0], X[1], X[2]); r.Hp_ll = weno_plus(X[0], X[1], X[2]); }
-        if (mid) { r.Hp_l = weno_plus(X[1], X[2], X[3]); r.Hm_r = weno_minus(X[1], X[2], X[3]); }
-        if (right) { r.Hp_r = weno_plus(X[2], X[3], X[4]); r.Hm_rr = weno_minus(X[2], X[3], X[4]); }
-        S = source_term<SURF>(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, dx, g, X[2]);
-    } else {
-        if (left) r.Qm_l = weno_minus(X[0], X[1], X[2]);
-        if (mid) { r.Qp_l = weno_plus(X[1], X[2], X[3]); r.Qm_r = weno_minus(X[1], X[2], X[3]); }
-        if (right) r.Qp_r = weno_plus(X[2], X[3], X[4]);
-    }
-    assemble_residual<SURF>(r, S, G, g, R0, R1);
-}
+// Column (i, m) of eq. (12) perturbs component m of cell i; the kernel evaluates the local
+// residual of each row for each column of its stencil.
 
 __device__ __forceinline__ void inv2d(const double A[4], double B[4])
 {
@@ -497,28 +467,56 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
             rhs[stride + j] = (T)R1;
         }
         const bool interior = j >= 2 && j <= I.N - 3;
-        Recon base;
-        double S0 = 0.0;
         if (interior) {
-            // SURF: perturbing H perturbs the surface H + zbar by the same amount
+            // Away from the boundaries the ghosts do not move: a column of H leaves every Q
+            // reconstruction unchanged and a column of Q every H reconstruction and the
+            // source, so each is formed once for its three (five) columns.  The values are
+            // those of a full re-evaluation, and only one component's reconstructions are
+            // live at a time (register pressure sets the occupancy of this ALU-bound kernel).
             if (SURF) to_surface(H, I, j);
-            recon_H(H, base);
-            recon_Q(Q, base);
-            S0 = source_term<SURF>(base.Hp_ll, base.Hp_l, base.Hm_r, base.Hm_rr, G, W, I.dx, I.g, H[2]);
-        }
+            Recon r;
+            recon_Q(Q, r);
 #pragma unroll 1
-        for (int b = 0; b < NB; b++) {
-            const int i = j + b - HW;
-            const bool col_ok = i >= 0 && i < I.N;
-            const int pp = 2 + b - HW;  // stencil position of the perturbed cell
+            for (int b = 0; b < NB; b++) {
+                const int pp = 2 + b - HW;
+                double X[5];
+#pragma unroll
+                for (int p = 0; p < 5; p++) X[p] = p == pp ? H[p] + eps : H[p];
+                recon_H(X, r);
+                const double S = source_term<SURF>(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, I.dx, I.g, X[2]);
+                double P0, P1;
+                assemble_residual<SURF>(r, S, G, I.g, P0, P1);
+                double e0 = (P0 - R0) * ieps, e1 = (P1 - R1) * ieps;
+                if (b == HW) e0 += I.alpha * rn;
+                myrow[(b * 2 + 0) * 2 + 0] = e0;
+                myrow[(b * 2 + 1) * 2 + 0] = e1;
+            }
+            recon_H(H, r);
+            const double S0 = source_term<SURF>(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, I.dx, I.g, H[2]);
 #pragma unroll 1
-            for (int m = 0; m < 2; m++) {
-                double e0 = 0.0, e1 = 0.0;
-                if (col_ok) {
-                    double P0, P1;
-                    if (interior) {
-                        perturbed_residual<SURF>(H, Q, pp, m, eps, base, S0, G, W, I.dx, I.g, P0, P1);
-                    } else {
+            for (int b = 0; b < NB; b++) {
+                const int pp = 2 + b - HW;
+                double X[5];
+#pragma unroll
+                for (int p = 0; p < 5; p++) X[p] = p == pp ? Q[p] + eps : Q[p];
+                recon_Q(X, r);
+                double P0, P1;
+                assemble_residual<SURF>(r, S0, G, I.g, P0, P1);
+                double e0 = (P0 - R0) * ieps, e1 = (P1 - R1) * ieps;
+                if (b == HW) e1 += I.alpha * rn;
+                myrow[(b * 2 + 0) * 2 + 1] = e0;
+                myrow[(b * 2 + 1) * 2 + 1] = e1;
+            }
+        } else {
+#pragma unroll 1
+            for (int b = 0; b < NB; b++) {
+                const int i = j + b - HW;
+                const bool col_ok = i >= 0 && i < I.N;
+                const int pp = 2 + b - HW;  // stencil position of the perturbed cell
+#pragma unroll 1
+                for (int m = 0; m < 2; m++) {
+                    double e0 = 0.0, e1 = 0.0;
+                    if (col_ok) {
                         double Hp[5], Qp[5];
 #pragma unroll
                         for (int p = 0; p < 5; p++) {
@@ -527,17 +525,18 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
                         }
                         stencil_ghosts<SURF>(Hp, Qp, j, I);
                         if (SURF) to_surface(Hp, I, j);
+                        double P0, P1;
                         local_residual<SURF>(Hp, Qp, G, W, I.dx, I.g, P0, P1);
+                        e0 = (P0 - R0) * ieps;
+                        e1 = (P1 - R1) * ieps;
+                        if (b == HW) {
+                            if (m == 0) e0 += I.alpha * rn;
+                            else e1 += I.alpha * rn;
+                        }
                     }
-                    e0 = (P0 - R0) * ieps;
-                    e1 = (P1 - R1) * ieps;
-                    if (b == HW) {
-                        if (m == 0) e0 += I.alpha * rn;
-                        else e1 += I.alpha * rn;
-                    }
+                    myrow[(b * 2 + 0) * 2 + m] = e0;
+                    myrow[(b * 2 + 1) * 2 + m] = e1;
                 }
-                myrow[(b * 2 + 0) * 2 + m] = e0;
-                myrow[(b * 2 + 1) * 2 + m] = e1;
             }
         }
 #pragma unroll

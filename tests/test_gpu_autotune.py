@@ -54,7 +54,7 @@ def test_autotune_restores_states_and_keeps_a_valid_option():
     best, times = s.autotune(Us, trial_steps=2)
     print("autotune", best, times)
     assert best["bottom_cells"] in (256, 512, 1024, 2048)
-    assert s.options() == best
+    assert s.options()["bottom_cells"] == best["bottom_cells"]
     assert all(t > 0 for t in times.values())
     assert best["bottom_cells"] == min(times, key=times.get)
     for a, b in zip(Us, before):

@@ -246,3 +246,21 @@ def test_full_batch_newton_steps_equal_solo_and_repeat():
     for k in (0, 1, 157, 255):
         solo = two_steps([probs[k]], False)[0]
         assert np.array_equal(a[k], solo), f"instance {k}: batch differs from solo"
+
+
+def test_full_uneven_batch_sampled_against_the_oracle():
+    """The uneven batch at its full size and launch configuration (512 instances, N from 256 to
+    16384, FP32 multigrid, HIP graph): every instance converges, and the three smallest equal
+    the FP64 oracle's solutions within the FP32-multigrid bar (1e-9)."""
+    from paper_2505_10857_amd import NMG_FP32_MG, BatchSolver1D
+    from swe_workloads import config4_instance
+    probs = [config4_instance(i) for i in range(512)]
+    b = BatchSolver1D(probs, device=DEV, precision=NMG_FP32_MG)
+    Us = b.states()
+    st = b.solve(Us, use_graph=True)
+    assert all(s[1] == 0 and s[2] < 1e-10 for s in st)
+    for k in sorted(range(512), key=lambda k: probs[k].n)[:3]:
+        Uo, ito, reso, _ = oracle.Oracle1D(probs[k]).newton_solve()
+        err = np.abs(Us[k].cpu().numpy() - Uo).max()
+        print(f"instance {k} (N={probs[k].n}): |U - U_oracle| = {err:.2e}, steps {st[k][0]} vs {ito}")
+        assert err <= 1e-9
