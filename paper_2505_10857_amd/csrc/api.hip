@@ -223,10 +223,11 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
             L.n = I.N >> l;
             L.nb = l == 0 ? I.nb : 3;
             L.coarsest = l == I.levels - 1;
-            L.halo = halo_cells(L.nb, P->linear == NMG_LINEAR_MG ? std::max(I.nu1, I.nu2) : 1);
-            L.V = kTile - 2 * L.halo;
-            L.halo2 = halo_cells(L.nb, I.nu1 + I.nu2);
-            L.V2 = kTile - 2 * L.halo2;
+            L.halo = P->linear == NMG_LINEAR_MG ? smooth_halo(L.nb, std::max(I.nu1, I.nu2), 0)
+                                                : halo_cells(L.nb, 1);
+            L.V = (P->linear == NMG_LINEAR_MG ? kSmoothTile : kTile) - 2 * L.halo;
+            L.halo2 = smooth_halo(L.nb, I.nu2, I.nu1);
+            L.V2 = kSmoothTile - 2 * L.halo2;
             L.child = L.coarsest ? -1 : (int)P->levs.size() + 1;
             L.J = mg_elems; mg_elems += (long long)L.nb * 4 * L.n;
             L.rhs = mg_elems; mg_elems += 2LL * L.n;
@@ -310,7 +311,7 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
     if (P->linear == NMG_LINEAR_MG && P->nu3 >= 2 && P->jac_mask == 1 && P->depth > 0) {
         bool ok = true;
         for (int k = 0; k < n && ok; k++)
-            ok = P->levs[lev_index[k][0]].V2 >= kTile / 2;   // at most twice the tiles
+            ok = P->levs[lev_index[k][0]].V2 >= kSmoothTile / 2;   // at most twice the tiles
         if (ok) {
             int t0 = (int)P->tiles.size();
             for (int k = 0; k < n; k++) {

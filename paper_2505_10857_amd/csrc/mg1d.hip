@@ -155,13 +155,13 @@ __global__ void __launch_bounds__(kTile) k_coarsen(MGArgs mg, const Tile *tiles)
 //         -> write dU, restrict rhs to the child; its tiles have the wider halo halo2.
 // src_out: the tile reads dU from dUo (1) or dU (0) and writes its cells to the other buffer.
 template <typename T, int NB, int MODE>
-__global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, int zero_init,
+__global__ void __launch_bounds__(kSmoothTile) k_smooth(MGArgs mg, const Tile *tiles, int zero_init,
                                                   int final_update, int src_out)
 {
     constexpr int mode = MODE;
     constexpr int HW = NB / 2;
     constexpr int C = NB == 5 ? 3 : 2;
-    __shared__ double s0[kTile + 2 * HW], s1[kTile + 2 * HW];
+    __shared__ double s0[kSmoothTile + 2 * HW], s1[kSmoothTile + 2 * HW];
     const Tile tl = tiles[blockIdx.x];
     const Level1D L = mg.levs[tl.lev];
     if (L.nb != NB) return;
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(kTile) k_smooth(MGArgs mg, const Tile *tiles, 
     }
     s0[t + HW] = du0;
     s1[t + HW] = du1;
-    if (t < HW) { s0[t] = 0.0; s1[t] = 0.0; s0[kTile + HW + t] = 0.0; s1[kTile + HW + t] = 0.0; }
+    if (t < HW) { s0[t] = 0.0; s1[t] = 0.0; s0[kSmoothTile + HW + t] = 0.0; s1[kSmoothTile + HW + t] = 0.0; }
     __syncthreads();
 
     const double w = I.omega;
@@ -914,13 +914,13 @@ static void launch_smooth_t(const MGArgs &mg, const Tile *tiles, int ntiles, int
                             int final_update, int src_out, hipStream_t s)
 {
     if (mode == 0)
-        hipLaunchKernelGGL((k_smooth<T, NB, 0>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, final_update,
+        hipLaunchKernelGGL((k_smooth<T, NB, 0>), dim3(ntiles), dim3(kSmoothTile), 0, s, mg, tiles, zero_init, final_update,
                            src_out);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_smooth<T, NB, 1>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, final_update,
+        hipLaunchKernelGGL((k_smooth<T, NB, 1>), dim3(ntiles), dim3(kSmoothTile), 0, s, mg, tiles, zero_init, final_update,
                            src_out);
     else
-        hipLaunchKernelGGL((k_smooth<T, NB, 2>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, zero_init, final_update,
+        hipLaunchKernelGGL((k_smooth<T, NB, 2>), dim3(ntiles), dim3(kSmoothTile), 0, s, mg, tiles, zero_init, final_update,
                            src_out);
 }
 

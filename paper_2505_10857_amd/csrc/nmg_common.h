@@ -10,6 +10,7 @@
 namespace nmg {
 
 constexpr int kTile = 256;        // threads (= cells) per 1D tile
+constexpr int kSmoothTile = 256;  // threads (= cells) per tile of the tiled multigrid smoother
 constexpr int kCoarsenCells = 4;  // level-l0 cells per thread in the coarsening kernel
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 256;   // cells on the coarsest 1D level (one thread per cell)
@@ -71,6 +72,21 @@ struct MGArgs {
     NewtonState *state;   // may be null: every instance active
     void *mg;             // base of the multigrid value arrays (double or float)
 };
+
+// Halo of a tiled multigrid smoothing launch running nu_a then nu_b symmetric steps (k_smooth):
+// the steps' runs of one colour (consecutive half-sweeps of a colour merged, nu (2C - 2) + 1
+// runs for nu steps) each move information nb/2 cells, and the restriction reads the neighbours
+// of every cell written once more.  A tile cell whose distance to the tile edge is at least
+// this many cells holds the exact value of the untiled sweep.  The width is rounded up to even:
+// a tile then starts at an even cell, which pairs the two children of a coarse cell in adjacent
+// lanes (t, t ^ 1) for the restriction.
+__host__ __device__ inline int smooth_halo(int nb, int nu_a, int nu_b)
+{
+    const int C = nb == 5 ? 3 : 2;
+    auto runs = [C](int nu) { return nu > 0 ? nu * (2 * C - 2) + 1 : 0; };
+    const int h = (runs(nu_a) + runs(nu_b) + 1) * (nb / 2);
+    return (h + 1) & ~1;
+}
 
 __host__ __device__ inline int halo_cells(int nb, int nu)
 {
