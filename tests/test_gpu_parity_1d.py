@@ -115,6 +115,53 @@ def test_vcycle_parity(name, prob):
         assert err <= 1e-12
 
 
+def _with_params(prob, **kw):
+    import dataclasses
+    return dataclasses.replace(prob, params=dataclasses.replace(prob.params, **kw))
+
+
+@pytest.mark.parametrize("nb,nu1,nu2", [(3, 1, 3), (3, 3, 1), (5, 2, 2), (5, 1, 2)])
+def test_vcycle_parity_tiled_levels(nb, nu1, nu2):
+    """Levels above the bottom-of-cycle threshold (2048 cells) are smoothed in tiles whose halo
+    is the reach of the merged colour schedule; N = 8192 puts the two finest levels in 34 and
+    17 tiles.  Unequal pre/post counts and the three-colour J5 smoother, two V-cycles, 1e-12."""
+    prob = _with_params(config2(0, "sub", n=8192, levels=6), nu1=nu1, nu2=nu2)
+    s = _solver(prob, jac=nb)
+    o = oracle.Oracle1D(prob)
+    U0 = _mid_state(prob, steps=3)
+    Jo = o.jacobian(U0, nb=nb)
+    rng = np.random.default_rng(1)
+    rhs = rng.standard_normal((prob.n, 2))
+    J = torch.tensor(np.ascontiguousarray(np.transpose(Jo, (1, 2, 3, 0))), dtype=torch.float64, device=DEV)
+    rhs_d = torch.tensor(np.ascontiguousarray(rhs.T), dtype=torch.float64, device=DEV)
+    dU = torch.zeros(2, prob.n, dtype=torch.float64, device=DEV)
+    ref = np.zeros((prob.n, 2))
+    for cyc in range(2):
+        s.vcycle(J, rhs_d, dU, setup=(cyc == 0))
+        ref = oracle.vcycles(Jo, rhs, ref, levels=prob.levels, ncycles=1, omega=prob.params.omega,
+                             nu1=nu1, nu2=nu2)
+        err = _rel(dU.cpu().numpy().T, ref)
+        print(f"J{nb} nu=({nu1},{nu2}): V-cycle {cyc + 1} rel.err {err:.3e}")
+        assert err <= 1e-12
+
+
+@pytest.mark.parametrize("nu1,nu2", [(1, 3), (2, 2)])
+def test_newton_trajectory_fused_smoothing(nu1, nu2):
+    """N = 8192, nu3 = 2: the finest level's post-smoothing of the first cycle and the
+    pre-smoothing of the second run in one tiled launch (halo for nu2 + nu1 steps).  Three
+    Newton steps against the oracle's, within 1e-10."""
+    prob = _with_params(config2(1, "sub", n=8192, levels=6), nu1=nu1, nu2=nu2)
+    o = oracle.Oracle1D(prob)
+    s = _solver(prob, check_every=1, n_max=3)
+    U = s.state()
+    st, _ = s.newton_solve(U)
+    Uo, ito, reso, _ = o.newton_solve(n_max=3)
+    assert st.iters == ito == 3
+    err = np.abs(U.cpu().numpy() - Uo).max()
+    print(f"nu=({nu1},{nu2}): after 3 steps |U_gpu - U_oracle| = {err:.3e}")
+    assert err <= 1e-10
+
+
 @pytest.mark.parametrize("name,prob", list(_cases())[:3], ids=[c[0] for c in _cases()][:3])
 def test_newton_trajectory_parity(name, prob):
     """Same number of Newton steps, states within 1e-10 after each checked prefix."""
