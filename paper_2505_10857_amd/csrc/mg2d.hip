@@ -173,48 +173,89 @@ __global__ void __launch_bounds__(256) k_smooth2d_pass(T *mg, Level2D L, int col
 }
 
 // eq. (24), right-hand side of coarse cell (I, Jq); also clears its dU.
+// rhs + J dU of fine cell (fi, fj), the summand of eq. (24)'s restriction
 template <typename T>
-__device__ __forceinline__ void restrict_cell(T *mg, const Level2D &Lf, const Level2D &Lc, int I, int Jq)
+__device__ __forceinline__ void restrict_child(const T *mg, const Level2D &Lf, int fi, int fj, double a[3])
 {
-    const long long nf = Lf.P.M, nc = Lc.P.M;
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int fj = 2 * Jq; fj <= 2 * Jq + 1; fj++)
-        for (int fi = 2 * I; fi <= 2 * I + 1; fi++) {
-            const long long fc = perm2d(Lf.P, fi, fj);
-            double a[3];
+    const long long nf = Lf.P.M;
+    const long long fc = perm2d(Lf.P, fi, fj);
 #pragma unroll
-            for (int c = 0; c < 3; c++) a[c] = ld2(mg + Lf.rhs, c * nf + fc);
-            for (int b = 0; b < Lf.nb; b++) {
-                int di, dj;
-                stencil_off(Lf.nb, b, di, dj);
-                const int pi = fi + di, pj = fj + dj;
-                if (pi < 0 || pi >= Lf.nx || pj < 0 || pj >= Lf.ny) continue;
-                const long long q = perm2d(Lf.P, pi, pj);
-                const double x0 = ld2(mg + Lf.dU, q), x1 = ld2(mg + Lf.dU, nf + q), x2 = ld2(mg + Lf.dU, 2 * nf + q);
+    for (int c = 0; c < 3; c++) a[c] = ld2(mg + Lf.rhs, c * nf + fc);
+    for (int b = 0; b < Lf.nb; b++) {
+        int di, dj;
+        stencil_off(Lf.nb, b, di, dj);
+        const int pi = fi + di, pj = fj + dj;
+        if (pi < 0 || pi >= Lf.nx || pj < 0 || pj >= Lf.ny) continue;
+        const long long q = perm2d(Lf.P, pi, pj);
+        const double x0 = ld2(mg + Lf.dU, q), x1 = ld2(mg + Lf.dU, nf + q), x2 = ld2(mg + Lf.dU, 2 * nf + q);
 #pragma unroll
-                for (int c = 0; c < 3; c++)
-                    a[c] = a[c] + (ld2(mg + Lf.J, (b * 9 + c * 3 + 0) * nf + fc) * x0 +
-                                   ld2(mg + Lf.J, (b * 9 + c * 3 + 1) * nf + fc) * x1 +
-                                   ld2(mg + Lf.J, (b * 9 + c * 3 + 2) * nf + fc) * x2);
-            }
-#pragma unroll
-            for (int c = 0; c < 3; c++) s[c] = s[c] + a[c];
-        }
-    const long long cc = perm2d(Lc.P, I, Jq);
+        for (int c = 0; c < 3; c++)
+            a[c] = a[c] + (ld2(mg + Lf.J, (b * 9 + c * 3 + 0) * nf + fc) * x0 +
+                           ld2(mg + Lf.J, (b * 9 + c * 3 + 1) * nf + fc) * x1 +
+                           ld2(mg + Lf.J, (b * 9 + c * 3 + 2) * nf + fc) * x2);
+    }
+}
+
+// coarse rhs = the four children's summands added in the order (2I, 2J), (2I+1, 2J), (2I, 2J+1),
+// (2I+1, 2J+1); coarse dU = 0
+template <typename T>
+__device__ __forceinline__ void restrict_store(T *mg, const Level2D &Lc, int I, int Jq, const double a00[3],
+                                               const double a10[3], const double a01[3], const double a11[3])
+{
+    const long long nc = Lc.P.M, cc = perm2d(Lc.P, I, Jq);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        mg[Lc.rhs + c * nc + cc] = (T)s[c];
+        double sum = 0.0;
+        sum = sum + a00[c];
+        sum = sum + a10[c];
+        sum = sum + a01[c];
+        sum = sum + a11[c];
+        mg[Lc.rhs + c * nc + cc] = (T)sum;
         mg[Lc.dU + c * nc + cc] = (T)0.0;
     }
 }
 
 template <typename T>
-__global__ void k_restrict2d(T *mg, Level2D Lf, Level2D Lc)
+__device__ __forceinline__ void restrict_cell(T *mg, const Level2D &Lf, const Level2D &Lc, int I, int Jq)
 {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    const int Jq = blockIdx.y;
-    if (I >= Lc.nx || Jq >= Lc.ny) return;
-    restrict_cell(mg, Lf, Lc, I, Jq);
+    double a00[3], a10[3], a01[3], a11[3];
+    restrict_child(mg, Lf, 2 * I, 2 * Jq, a00);
+    restrict_child(mg, Lf, 2 * I + 1, 2 * Jq, a10);
+    restrict_child(mg, Lf, 2 * I, 2 * Jq + 1, a01);
+    restrict_child(mg, Lf, 2 * I + 1, 2 * Jq + 1, a11);
+    restrict_store(mg, Lc, I, Jq, a00, a10, a01, a11);
+}
+
+// One workgroup per strip of two fine rows and kRX fine columns: a thread per fine cell forms its
+// summand (consecutive lanes read consecutive slots of the colour-blocked arrays), then a thread
+// per coarse cell adds its four children from LDS.
+constexpr int kRX = 128;
+
+template <typename T>
+__global__ void __launch_bounds__(2 * kRX) k_restrict2d(T *mg, Level2D Lf, Level2D Lc)
+{
+    __shared__ double sa[3][2][kRX];
+    const int t = threadIdx.x, r = t / kRX, x = t % kRX;
+    const int fi = blockIdx.x * kRX + x, fj = 2 * blockIdx.y + r;
+    if (fi < Lf.nx && fj < Lf.ny) {
+        double a[3];
+        restrict_child(mg, Lf, fi, fj, a);
+#pragma unroll
+        for (int c = 0; c < 3; c++) sa[c][r][x] = a[c];
+    }
+    __syncthreads();
+    const int I = blockIdx.x * (kRX / 2) + t, Jq = blockIdx.y;
+    if (t < kRX / 2 && I < Lc.nx && Jq < Lc.ny) {
+        double a00[3], a10[3], a01[3], a11[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            a00[c] = sa[c][0][2 * t];
+            a10[c] = sa[c][0][2 * t + 1];
+            a01[c] = sa[c][1][2 * t];
+            a11[c] = sa[c][1][2 * t + 1];
+        }
+        restrict_store(mg, Lc, I, Jq, a00, a10, a01, a11);
+    }
 }
 
 // eq. (25): dU_fine += dU_coarse(parent)
@@ -542,8 +583,8 @@ hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, int reps
 
 hipError_t launch_restrict2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s)
 {
-    dim3 grid((Lc.nx + 63) / 64, Lc.ny);
-    DISPATCH(prec, k_restrict2d, grid, dim3(64), Lf, Lc);
+    dim3 grid((Lf.nx + kRX - 1) / kRX, Lc.ny);
+    DISPATCH(prec, k_restrict2d, grid, dim3(2 * kRX), Lf, Lc);
     return hipGetLastError();
 }
 
