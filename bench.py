@@ -282,8 +282,12 @@ def main():
                                f"{args.variant}critical, J3, FP64, batch of {args.batch} seeded instances "
                                f"per step solved to res<1e-10",
                    "n": args.n, "levels": args.levels, "batch": args.batch, "variant": args.variant,
-                   "hip_graph": use_graph, "autotuned": {"bottom_cells": tune_best["bottom_cells"],
-                                                         "ms_per_newton_step": tune_times}},
+                   "hip_graph": use_graph,
+                   "autotuned": {"bottom_cells": tune_best["bottom_cells"],
+                                 "smooth_tile": tune_best["smooth_tile"],
+                                 "split_finest": tune_best["split_finest"],
+                                 "ms_per_newton_step": {f"bottom{b}_split{sp}_tile{t}": ms
+                                                        for (b, sp, t), ms in tune_times.items()}}},
         "dof_per_s": dofs,
         "newton_steps_per_solve": [min(newton), max(newton)],
         "converged": ok,

@@ -226,32 +226,41 @@ nmg_status nmg_plan_profile(nmg_plan *plan, int32_t kernel);
 nmg_status nmg_plan_profile_read(nmg_plan *plan, double *ms, int32_t *launches);
 
 /* Tunables of a plan.  They choose between kernels that do the same arithmetic in the same
- * order, so results do not depend on them.  bottom_cells: the levels of each instance with at
- * most this many cells (256, 512, 1024 or 2048; the coarsest level always) run in the
- * one-workgroup-per-instance bottom-of-cycle kernel, the larger ones in the tiled smoothers:
- * a small value spreads more levels over the whole GPU, a large one saves launches and
- * synchronisation.  Default 2048.  Setting options refreshes the plan's device tables (and any
- * captured graph) on its next use; the workspace size does not change.  Set them before
- * nmg_plan_begin / nmg_plan_solve.  fused_finest (reported by nmg_plan_get_options, ignored by
- * nmg_plan_set_options): 1 when the finest level's post-smoothing of one V-cycle and the
- * pre-smoothing of the next run in one launch (multigrid plans with nu3 >= 2 whose instances all
- * use the three-block Jacobian); the arithmetic is the same either way. */
+ * order, so results do not depend on them; a zero-initialised struct (with bottom_cells set)
+ * selects the defaults.
+ *   bottom_cells: the levels of each instance with at most this many cells (256, 512, 1024 or
+ *     2048; the coarsest level always) run in the one-workgroup-per-instance bottom-of-cycle
+ *     kernel, whose workgroup size follows (bottom_cells / 2, at least 256, at most 1024); the
+ *     larger levels run in the tiled smoothers.  A small value spreads more levels over the
+ *     whole GPU, a large one saves launches and synchronisation.  Default 2048.
+ *   smooth_tile: cells (= threads) per tile of the tiled smoother, 256 or 512 (0: 256).
+ *   split_finest: 0 (default) runs the finest level's post-smoothing of one V-cycle and the
+ *     pre-smoothing of the next in one launch where the plan allows it (multigrid plans with
+ *     nu3 >= 2 whose instances all use the three-block Jacobian); 1 keeps them apart.
+ *   fused_finest: reported by nmg_plan_get_options (1 when that fused launch is in use),
+ *     ignored by nmg_plan_set_options.
+ * Setting options refreshes the plan's device tables (and any captured graph) on its next use;
+ * the workspace size does not change.  Set them before nmg_plan_begin / nmg_plan_solve.  An
+ * invalid set is rejected with NMG_EINVAL and leaves the plan as it was. */
 typedef struct {
     int32_t bottom_cells;
     int32_t fused_finest;
-    int32_t reserved[6];
+    int32_t smooth_tile;
+    int32_t split_finest;
+    int32_t reserved[4];
 } nmg_plan_options;
 nmg_status nmg_plan_set_options(nmg_plan *plan, const nmg_plan_options *opt);
 nmg_status nmg_plan_get_options(const nmg_plan *plan, nmg_plan_options *opt);
 
-/* Autotuner for the batched form: for every candidate option set (NMG_TUNE_CANDIDATES of them:
- * bottom_cells = 256, 512, 1024, 2048) it begins the plan's instances from the states U, runs
- * one untimed Newton step (with use_graph = 1 it also captures the step graph) and times
- * trial_steps more with HIP events; it keeps the fastest set in the plan and returns it in
- * best (host, may be NULL) and the per-step milliseconds of every candidate in times_ms (host,
- * length NMG_TUNE_CANDIDATES, may be NULL).  The states are restored before it returns (it
- * allocates a device copy of them for the duration of the call).  Synchronises `stream`. */
-#define NMG_TUNE_CANDIDATES 4
+/* Autotuner for the batched form: for every candidate option set (NMG_TUNE_CANDIDATES of them,
+ * candidate c: bottom_cells = 256 << (c % 4), split_finest = (c / 4) % 2, smooth_tile =
+ * 256 << (c / 8)) it begins the plan's instances from the states U, runs one untimed Newton step
+ * (with use_graph = 1 it also captures the step graph) and times trial_steps more with HIP
+ * events; it keeps the fastest set in the plan and returns it in best (host, may be NULL) and
+ * the per-step milliseconds of every candidate in times_ms (host, length NMG_TUNE_CANDIDATES,
+ * may be NULL).  The states are restored before it returns (it allocates a device copy of them
+ * for the duration of the call).  Synchronises `stream`. */
+#define NMG_TUNE_CANDIDATES 16
 nmg_status nmg_plan_autotune(nmg_plan *plan, void *ws, size_t ws_bytes, double *const *U,
                              int32_t trial_steps, int32_t use_graph, nmg_plan_options *best,
                              double *times_ms, void *stream);

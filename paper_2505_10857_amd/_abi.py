@@ -78,10 +78,11 @@ class nmg_stats(C.Structure):
 
 
 class nmg_plan_options(C.Structure):
-    _fields_ = [("bottom_cells", C.c_int32), ("fused_finest", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("bottom_cells", C.c_int32), ("fused_finest", C.c_int32), ("smooth_tile", C.c_int32),
+                ("split_finest", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
-NMG_TUNE_CANDIDATES = 4
+NMG_TUNE_CANDIDATES = 16
 
 
 class NmgError(RuntimeError):

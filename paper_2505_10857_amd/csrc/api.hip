@@ -142,6 +142,8 @@ struct nmg_plan {
     int bottom_cells = 2048;                  // levels up to this size run in k_bottom
     int recon = NMG_RECON_CONSERVED;          // reconstruction of every instance
     int bottom_nt = 1024;                     // its workgroup size
+    int smooth_tile = kSmoothTile;            // cells per tile of the tiled multigrid smoother
+    int split_finest = 0;                     // 1: no fused finest-level launch between cycles
     size_t tile_cap = 0;                      // tile-table entries reserved (any option fits)
     std::vector<nmg_desc> descs;
     std::vector<nmg_params> params;
@@ -225,9 +227,9 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
             L.coarsest = l == I.levels - 1;
             L.halo = P->linear == NMG_LINEAR_MG ? smooth_halo(L.nb, std::max(I.nu1, I.nu2), 0)
                                                 : halo_cells(L.nb, 1);
-            L.V = (P->linear == NMG_LINEAR_MG ? kSmoothTile : kTile) - 2 * L.halo;
+            L.V = (P->linear == NMG_LINEAR_MG ? P->smooth_tile : kTile) - 2 * L.halo;
             L.halo2 = smooth_halo(L.nb, I.nu2, I.nu1);
-            L.V2 = kSmoothTile - 2 * L.halo2;
+            L.V2 = P->smooth_tile - 2 * L.halo2;
             L.child = L.coarsest ? -1 : (int)P->levs.size() + 1;
             L.J = mg_elems; mg_elems += (long long)L.nb * 4 * L.n;
             L.rhs = mg_elems; mg_elems += 2LL * L.n;
@@ -308,10 +310,10 @@ nmg_status build_plan(nmg_plan *P, const nmg_desc *descs, const nmg_params *para
         P->smooth_mask.push_back(mask);
     }
     P->fused0 = {0, 0};
-    if (P->linear == NMG_LINEAR_MG && P->nu3 >= 2 && P->jac_mask == 1 && P->depth > 0) {
+    if (P->linear == NMG_LINEAR_MG && P->nu3 >= 2 && P->jac_mask == 1 && P->depth > 0 && !P->split_finest) {
         bool ok = true;
         for (int k = 0; k < n && ok; k++)
-            ok = P->levs[lev_index[k][0]].V2 >= kSmoothTile / 2;   // at most twice the tiles
+            ok = P->levs[lev_index[k][0]].V2 >= P->smooth_tile / 2;   // at most twice the tiles
         if (ok) {
             int t0 = (int)P->tiles.size();
             for (int k = 0; k < n; k++) {
@@ -454,7 +456,7 @@ nmg_status enqueue_vcycle(nmg_plan *P, char *ws, const MGArgs &mg, bool zero_ini
         ProfScope ps(P, d == 0 ? NMG_K_SMOOTH_PRE : -1, s, cap);
         const int src = d == 0 ? src0 : 0;
         HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
-                                P->smooth_mask[d], 0, (d > 0 || zero_init0) ? 1 : 0, 0, src, P->prec, s));
+                                P->smooth_mask[d], 0, (d > 0 || zero_init0) ? 1 : 0, 0, src, P->prec, P->smooth_tile, s));
         if (d == 0) src0 = 1 - src;
     }
     HIP_TRY(launch_bottom(mg, list, P->n, zero_init0 ? 1 : 0, final_update ? 1 : 0, P->prec, P->bottom_nt, s));
@@ -463,14 +465,14 @@ nmg_status enqueue_vcycle(nmg_plan *P, char *ws, const MGArgs &mg, bool zero_ini
         if (d == 0 && fuse_up0) {
             ProfScope ps(P, NMG_K_SMOOTH_FUSED, s, cap);
             HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->fused0.first), P->fused0.second, P->smooth_mask[0], 2,
-                                    0, 0, src0, P->prec, s));
+                                    0, 0, src0, P->prec, P->smooth_tile, s));
             src0 = 1 - src0;
             continue;
         }
         ProfScope ps(P, d == 0 ? NMG_K_SMOOTH_POST : -1, s, cap);
         const int src = d == 0 ? src0 : 1;
         HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
-                                P->smooth_mask[d], 1, 0, (d == 0 && final_update) ? 1 : 0, src, P->prec, s));
+                                P->smooth_mask[d], 1, 0, (d == 0 && final_update) ? 1 : 0, src, P->prec, P->smooth_tile, s));
         if (d == 0) src0 = 1 - src;
     }
     if (src0_out) *src0_out = src0;
@@ -594,21 +596,39 @@ nmg_status plan_steps(nmg_plan *P, char *ws, int steps, int use_graph, hipStream
     return NMG_OK;
 }
 
-constexpr int kTuneCandidates[NMG_TUNE_CANDIDATES] = {256, 512, 1024, 2048};
+constexpr int kBottomCandidates[4] = {256, 512, 1024, 2048};
+constexpr int kTileCandidates[2] = {kSmoothTile, kSmoothTileMax};
+static_assert(NMG_TUNE_CANDIDATES == 4 * 2 * 2, "tuner grid: bottom_cells x split_finest x smooth_tile");
 
-// Rebuild the plan's tables for another bottom-kernel threshold.  The byte layout does not move
-// (the tile table is reserved for the largest tile count), so a workspace sized for the plan
-// fits every option; device tables and any captured graph are refreshed on the next use.
-nmg_status apply_bottom_cells(nmg_plan *P, int cells)
+// Rebuild the plan's tables for another option set.  The byte layout does not move (the tile
+// table is reserved for the largest tile count), so a workspace sized for the plan fits every
+// option; device tables and any captured graph are refreshed on the next use.
+nmg_status apply_options(nmg_plan *P, int cells, int split, int tile)
 {
     bool ok = false;
-    for (int c : kTuneCandidates) ok = ok || c == cells;
+    for (int c : kBottomCandidates) ok = ok || c == cells;
     if (!ok) return fail(NMG_EINVAL, "bottom_cells must be 256, 512, 1024 or 2048");
+    if (tile == 0) tile = kSmoothTile;
+    if (tile != kSmoothTile && tile != kSmoothTileMax) return fail(NMG_EINVAL, "smooth_tile must be 0, 256 or 512");
+    if (split != 0 && split != 1) return fail(NMG_EINVAL, "split_finest must be 0 or 1");
     const size_t total = P->total;
+    const int old_cells = P->bottom_cells, old_nt = P->bottom_nt, old_tile = P->smooth_tile, old_split = P->split_finest;
     P->bottom_cells = cells;
     P->bottom_nt = std::min(1024, std::max(256, cells / 2));
+    P->smooth_tile = tile;
+    P->split_finest = split;
     nmg_status st = build_plan(P, P->descs.data(), P->params.data(), P->n);
-    if (st != NMG_OK) return st;
+    if (st == NMG_OK && P->tiles.size() > P->tile_cap)
+        st = fail(NMG_EINVAL, "option set needs more tiles than the plan reserved");
+    if (st != NMG_OK) {   // keep the previous, valid tables
+        const std::string err = g_err;
+        P->bottom_cells = old_cells;
+        P->bottom_nt = old_nt;
+        P->smooth_tile = old_tile;
+        P->split_finest = old_split;
+        (void)build_plan(P, P->descs.data(), P->params.data(), P->n);
+        return fail(st, err);
+    }
     P->total = std::max(P->total, total);
     P->tables_ws = nullptr;
     if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
@@ -638,12 +658,13 @@ nmg_status plan_autotune(nmg_plan *P, char *ws, size_t ws_bytes, double *const *
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     struct FreeEv { hipEvent_t a, b; ~FreeEv() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } evg{e0, e1};
-    const int initial = P->bottom_cells;
-    int best_cells = initial;
+    int best_cells = P->bottom_cells, best_split = P->split_finest, best_tile = P->smooth_tile;
     double best_ms = 1e300;
+    // candidate ci: bottom_cells = kBottomCandidates[ci % 4], split_finest = (ci / 4) % 2,
+    // smooth_tile = kTileCandidates[ci / 8]
     for (int ci = 0; ci < NMG_TUNE_CANDIDATES; ci++) {
-        const int cells = kTuneCandidates[ci];
-        nmg_status st = apply_bottom_cells(P, cells);
+        const int cells = kBottomCandidates[ci % 4], split = (ci / 4) % 2, tile = kTileCandidates[ci / 8];
+        nmg_status st = apply_options(P, cells, split, tile);
         if (st != NMG_OK) return st;
         P->n_start.assign(P->n, 0);
         if ((st = plan_begin(P, ws, ws_bytes, U, s)) != NMG_OK) return st;
@@ -656,15 +677,21 @@ nmg_status plan_autotune(nmg_plan *P, char *ws, size_t ws_bytes, double *const *
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
         const double per = ms / trial_steps;
         if (times_ms) times_ms[ci] = per;
-        if (per < best_ms) { best_ms = per; best_cells = cells; }
+        if (per < best_ms) { best_ms = per; best_cells = cells; best_split = split; best_tile = tile; }
         for (int k = 0; k < P->n; k++)
             HIP_TRY(hipMemcpyAsync(U[k], save + off[k], sizeof(double) * (off[k + 1] - off[k]),
                                    hipMemcpyDeviceToDevice, s));
     }
-    nmg_status st = apply_bottom_cells(P, best_cells);
+    nmg_status st = apply_options(P, best_cells, best_split, best_tile);
     if (st != NMG_OK) return st;
     HIP_TRY(hipStreamSynchronize(s));
-    if (best) { memset(best, 0, sizeof(*best)); best->bottom_cells = best_cells; }
+    if (best) {
+        memset(best, 0, sizeof(*best));
+        best->bottom_cells = best_cells;
+        best->fused_finest = P->fused0.second > 0 ? 1 : 0;
+        best->smooth_tile = best_tile;
+        best->split_finest = best_split;
+    }
     return NMG_OK;
 }
 
@@ -730,7 +757,7 @@ void nmg_plan_destroy(nmg_plan *plan) { delete plan; }
 nmg_status nmg_plan_set_options(nmg_plan *P, const nmg_plan_options *opt)
 {
     if (!P || !opt) return fail(NMG_EINVAL, "null argument");
-    return apply_bottom_cells(P, opt->bottom_cells);
+    return apply_options(P, opt->bottom_cells, opt->split_finest, opt->smooth_tile);
 }
 
 nmg_status nmg_plan_get_options(const nmg_plan *P, nmg_plan_options *opt)
@@ -739,6 +766,8 @@ nmg_status nmg_plan_get_options(const nmg_plan *P, nmg_plan_options *opt)
     memset(opt, 0, sizeof(*opt));
     opt->bottom_cells = P->bottom_cells;
     opt->fused_finest = P->fused0.second > 0 ? 1 : 0;
+    opt->smooth_tile = P->smooth_tile;
+    opt->split_finest = P->split_finest;
     return NMG_OK;
 }
 

@@ -154,14 +154,14 @@ __global__ void __launch_bounds__(kTile) k_coarsen(MGArgs mg, const Tile *tiles)
 //         V-cycle and the pre-smoothing of the next, with nothing between them on this level)
 //         -> write dU, restrict rhs to the child; its tiles have the wider halo halo2.
 // src_out: the tile reads dU from dUo (1) or dU (0) and writes its cells to the other buffer.
-template <typename T, int NB, int MODE>
-__global__ void __launch_bounds__(kSmoothTile) k_smooth(MGArgs mg, const Tile *tiles, int zero_init,
+template <typename T, int NB, int MODE, int TW>
+__global__ void __launch_bounds__(TW) k_smooth(MGArgs mg, const Tile *tiles, int zero_init,
                                                   int final_update, int src_out)
 {
     constexpr int mode = MODE;
     constexpr int HW = NB / 2;
     constexpr int C = NB == 5 ? 3 : 2;
-    __shared__ double s0[kSmoothTile + 2 * HW], s1[kSmoothTile + 2 * HW];
+    __shared__ double s0[TW + 2 * HW], s1[TW + 2 * HW];
     const Tile tl = tiles[blockIdx.x];
     const Level1D L = mg.levs[tl.lev];
     if (L.nb != NB) return;
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(kSmoothTile) k_smooth(MGArgs mg, const Tile *t
     }
     s0[t + HW] = du0;
     s1[t + HW] = du1;
-    if (t < HW) { s0[t] = 0.0; s1[t] = 0.0; s0[kSmoothTile + HW + t] = 0.0; s1[kSmoothTile + HW + t] = 0.0; }
+    if (t < HW) { s0[t] = 0.0; s1[t] = 0.0; s0[TW + HW + t] = 0.0; s1[TW + HW + t] = 0.0; }
     __syncthreads();
 
     const double w = I.omega;
@@ -909,31 +909,42 @@ hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero
     return hipGetLastError();
 }
 
-template <typename T, int NB>
-static void launch_smooth_t(const MGArgs &mg, const Tile *tiles, int ntiles, int mode, int zero_init,
+template <typename T, int NB, int TW>
+static void launch_smooth_w(const MGArgs &mg, const Tile *tiles, int ntiles, int mode, int zero_init,
                             int final_update, int src_out, hipStream_t s)
 {
     if (mode == 0)
-        hipLaunchKernelGGL((k_smooth<T, NB, 0>), dim3(ntiles), dim3(kSmoothTile), 0, s, mg, tiles, zero_init, final_update,
-                           src_out);
+        hipLaunchKernelGGL((k_smooth<T, NB, 0, TW>), dim3(ntiles), dim3(TW), 0, s, mg, tiles, zero_init,
+                           final_update, src_out);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_smooth<T, NB, 1>), dim3(ntiles), dim3(kSmoothTile), 0, s, mg, tiles, zero_init, final_update,
-                           src_out);
+        hipLaunchKernelGGL((k_smooth<T, NB, 1, TW>), dim3(ntiles), dim3(TW), 0, s, mg, tiles, zero_init,
+                           final_update, src_out);
     else
-        hipLaunchKernelGGL((k_smooth<T, NB, 2>), dim3(ntiles), dim3(kSmoothTile), 0, s, mg, tiles, zero_init, final_update,
-                           src_out);
+        hipLaunchKernelGGL((k_smooth<T, NB, 2, TW>), dim3(ntiles), dim3(TW), 0, s, mg, tiles, zero_init,
+                           final_update, src_out);
+}
+
+template <typename T, int NB>
+static void launch_smooth_t(const MGArgs &mg, const Tile *tiles, int ntiles, int mode, int zero_init,
+                            int final_update, int src_out, int tile, hipStream_t s)
+{
+    if (tile == kSmoothTileMax)
+        launch_smooth_w<T, NB, kSmoothTileMax>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
+    else
+        launch_smooth_w<T, NB, kSmoothTile>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
 }
 
 hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_mask, int mode,
-                           int zero_init, int final_update, int src_out, int prec, hipStream_t s)
+                           int zero_init, int final_update, int src_out, int prec, int tile, hipStream_t s)
 {
     if (ntiles == 0) return hipSuccess;
+    if (tile != kSmoothTile && tile != kSmoothTileMax) return hipErrorInvalidValue;
     if (prec == NMG_FP32_MG) {
-        if (nb_mask & 1) launch_smooth_t<float, 3>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
-        if (nb_mask & 2) launch_smooth_t<float, 5>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
+        if (nb_mask & 1) launch_smooth_t<float, 3>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, s);
+        if (nb_mask & 2) launch_smooth_t<float, 5>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, s);
     } else {
-        if (nb_mask & 1) launch_smooth_t<double, 3>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
-        if (nb_mask & 2) launch_smooth_t<double, 5>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
+        if (nb_mask & 1) launch_smooth_t<double, 3>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, s);
+        if (nb_mask & 2) launch_smooth_t<double, 5>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, s);
     }
     return hipGetLastError();
 }

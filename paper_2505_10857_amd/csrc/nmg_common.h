@@ -10,7 +10,8 @@
 namespace nmg {
 
 constexpr int kTile = 256;        // threads (= cells) per 1D tile
-constexpr int kSmoothTile = 256;  // threads (= cells) per tile of the tiled multigrid smoother
+constexpr int kSmoothTile = 256;  // default threads (= cells) per tile of the tiled multigrid smoother
+constexpr int kSmoothTileMax = 512;  // the other width the plan options offer
 constexpr int kCoarsenCells = 4;  // level-l0 cells per thread in the coarsening kernel
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 256;   // cells on the coarsest 1D level (one thread per cell)
@@ -166,7 +167,7 @@ hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero
 // the post-smoothing of one V-cycle and the pre-smoothing of the next on one level.  src_out:
 // read dU from dUo (1) or dU (0) and write the other buffer.
 hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_mask, int mode,
-                           int zero_init, int final_update, int src_out, int prec, hipStream_t s);
+                           int zero_init, int final_update, int src_out, int prec, int tile, hipStream_t s);
 hipError_t launch_convert(const void *src, int src_prec, void *dst, int dst_prec, long long n,
                           hipStream_t s);
 // Newton-SOR (section 5.1.1) on level 0: one symmetric multicolour block-SOR step per launch

@@ -214,26 +214,40 @@ class BatchSolver1D:
         A.check(A.load().nmg_plan_resume(self.plan, _dptr(self.ws), self.ws_bytes, self._ptrs, counts,
                                          C.c_void_p(_stream_ptr())))
 
-    def set_options(self, bottom_cells: int):
+    def set_options(self, bottom_cells: int, smooth_tile: int = 0, split_finest: int = 0):
         opt = A.nmg_plan_options()
         opt.bottom_cells = bottom_cells
+        opt.smooth_tile = smooth_tile
+        opt.split_finest = split_finest
         A.check(A.load().nmg_plan_set_options(self.plan, C.byref(opt)))
+
+    @staticmethod
+    def _opt_dict(opt) -> dict:
+        return {"bottom_cells": opt.bottom_cells, "smooth_tile": opt.smooth_tile,
+                "split_finest": opt.split_finest, "fused_finest": bool(opt.fused_finest)}
 
     def options(self) -> dict:
         opt = A.nmg_plan_options()
         A.check(A.load().nmg_plan_get_options(self.plan, C.byref(opt)))
-        return {"bottom_cells": opt.bottom_cells, "fused_finest": bool(opt.fused_finest)}
+        return self._opt_dict(opt)
+
+    @staticmethod
+    def tune_candidate(c: int) -> tuple:
+        """(bottom_cells, split_finest, smooth_tile) of autotuner candidate c."""
+        return 256 << (c % 4), (c // 4) % 2, 256 << (c // 8)
 
     def autotune(self, Us: List[torch.Tensor], trial_steps: int = 3, use_graph: bool = True):
         """Time every candidate option set on these states (restored afterwards), keep the
-        fastest.  Returns (best options, {bottom_cells: ms per Newton step})."""
+        fastest.  Returns (best options, {(bottom_cells, split_finest, smooth_tile): ms per
+        Newton step})."""
         ptrs = (C.c_void_p * self.n)(*[u.data_ptr() for u in Us])
         best = A.nmg_plan_options()
         times = (C.c_double * A.NMG_TUNE_CANDIDATES)()
         A.check(A.load().nmg_plan_autotune(self.plan, _dptr(self.ws), self.ws_bytes, ptrs, trial_steps,
                                            1 if use_graph else 0, C.byref(best), times,
                                            C.c_void_p(_stream_ptr())))
-        return {"bottom_cells": best.bottom_cells}, dict(zip((256, 512, 1024, 2048), list(times)))
+        return (self._opt_dict(best),
+                {self.tune_candidate(c): times[c] for c in range(A.NMG_TUNE_CANDIDATES)})
 
     def profile(self, kernel: int):
         """Time every later non-graph launch of one kernel (NMG_K_*) with HIP events."""

@@ -41,6 +41,8 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(abi.nmg_bc) == 40
     assert ctypes.sizeof(abi.nmg_desc) == 24 + 40 + 4 * 40 + 8 + 7 * 8
     assert ctypes.sizeof(abi.nmg_params) == 5 * 8 + 8 * 4 + 8
+    assert ctypes.sizeof(abi.nmg_plan_options) == 8 * 4
+    assert abi.NMG_TUNE_CANDIDATES == 16
 
 
 def _desc(abi, nx=64, levels=3, jac=3):
