@@ -8,11 +8,33 @@
 // and several dependent FMAs each), so the formulas are evaluated in algebraically equal forms
 // with few divisions: one per WENO3 reconstruction (the normalised weights combined over a
 // common denominator), one reciprocal per depth and wave-speed difference in the HLL flux,
-// reciprocals of the widths once per cell and of the perturbation once per launch.  The result
-// agrees with the printed forms to rounding.
+// reciprocals of the widths once per cell and of the perturbation once per launch.  Those
+// divisions and reciprocals use the hardware reciprocal refined by Newton-Raphson steps instead
+// of the fully IEEE-rounded sequence (their operands are well scaled), so a quotient may differ
+// from the correctly rounded one in its last bit.  The result agrees with the printed forms to
+// rounding.
 #include "nmg_common.h"
 
 namespace nmg {
+
+// a / b within about an ulp for the well-scaled operands of this file: the hardware's approximate
+// reciprocal refined by two Newton-Raphson steps x <- x + x (1 - b x), then the quotient a x
+// corrected once by its residual a - b q (no range scaling: |b| stays far from the overflow
+// and denormal limits here)
+__device__ __forceinline__ double qrcp(double b)
+{
+    double x = __builtin_amdgcn_rcp(b);
+    x = fma(fma(-b, x, 1.0), x, x);
+    x = fma(fma(-b, x, 1.0), x, x);
+    return x;
+}
+
+__device__ __forceinline__ double qdiv(double a, double b)
+{
+    const double x = qrcp(b);
+    const double q = a * x;
+    return fma(fma(-b, q, a), x, q);
+}
 
 // ---- WENO3 reconstruction (eq. 7-8) ----------------------------------------------------
 // Linear weights paired for third order: the central two-cell candidate takes 2/3 (the
@@ -28,7 +50,7 @@ __device__ __forceinline__ double weno_plus(double um, double u0, double up)
     const double z0 = kZeta + (up - u0) * (up - u0);
     const double z1 = kZeta + (u0 - um) * (u0 - um);
     const double e0 = z0 * z0, e1 = z1 * z1;
-    return (e1 * c0 + 2.0 * (e0 * c1)) / (e1 + 2.0 * e0);
+    return qdiv(e1 * c0 + 2.0 * (e0 * c1), e1 + 2.0 * e0);
 }
 
 __device__ __forceinline__ double weno_minus(double um, double u0, double up)
@@ -39,7 +61,7 @@ __device__ __forceinline__ double weno_minus(double um, double u0, double up)
     const double z0 = kZeta + (up - u0) * (up - u0);
     const double z1 = kZeta + (u0 - um) * (u0 - um);
     const double e0 = z0 * z0, e1 = z1 * z1;
-    return (2.0 * (e1 * c0) + e0 * c1) / (2.0 * e1 + e0);
+    return qdiv(2.0 * (e1 * c0) + e0 * c1, 2.0 * e1 + e0);
 }
 
 // ---- HLL flux for eq. (4) with Davis wave-speed bounds ----------------------------------
@@ -48,7 +70,7 @@ __device__ __forceinline__ void hll(double HL, double QL, double HR, double QR, 
                                     double isig, double g, double &F0, double &F1)
 {
     // sig: width at the face, isig = 1 / sig
-    const double iHL = 1.0 / HL, iHR = 1.0 / HR;
+    const double iHL = qrcp(HL), iHR = qrcp(HR);
     const double hl = HL * isig, hr = HR * isig;
     const double uL = QL * iHL, uR = QR * iHR;
     const double FL0 = QL, FL1 = QL * uL + 0.5 * g * sig * hl * hl;
@@ -63,7 +85,7 @@ __device__ __forceinline__ void hll(double HL, double QL, double HR, double QR, 
     } else if (SR <= 0.0) {
         F0 = FR0; F1 = FR1;
     } else {
-        const double iw = 1.0 / (SR - SL);
+        const double iw = qrcp(SR - SL);
         F0 = (SR * FL0 - SL * FR0 + SL * SR * (HR - HL)) * iw;
         F1 = (SR * FL1 - SL * FR1 + SL * SR * (QR - QL)) * iw;
     }
@@ -121,12 +143,12 @@ __device__ __forceinline__ CellGeom load_geom(const Inst1D &I, int j)
     G.zfm = G.zfp = 0.0;
     G.sfm = I.sig_face[j];
     G.sfp = I.sig_face[j + 1];
-    G.isfm = 1.0 / G.sfm;
-    G.isfp = 1.0 / G.sfp;
+    G.isfm = qrcp(G.sfm);
+    G.isfp = qrcp(G.sfp);
 #pragma unroll
     for (int q = 0; q < 2; q++) {
         G.sg[q] = I.sig_gp[2 * j + q];
-        G.isg[q] = 1.0 / G.sg[q];
+        G.isg[q] = qrcp(G.sg[q]);
         G.sxg[q] = I.sigx_gp[2 * j + q];
         G.bxg[q] = I.bx_gp[2 * j + q];
     }
