@@ -36,6 +36,23 @@ __device__ __forceinline__ double qdiv(double a, double b)
     return fma(fma(-b, q, a), x, q);
 }
 
+// sqrt(a) for a positive normal a (here g h at a face, h > 0): the hardware's reciprocal square
+// root r refined by the coupled Goldschmidt iteration on g ~ a r and h ~ r / 2, then two residual
+// corrections g += (a - g^2) h.  These are the operations of the IEEE-rounded square root without
+// its scaling of tiny arguments and its handling of zero and infinity, which such an a never needs.
+__device__ __forceinline__ double qsqrt(double a)
+{
+    const double r = __builtin_amdgcn_rsq(a);
+    double g = a * r, h = r * 0.5;
+    const double e = fma(-h, g, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    double d = fma(-g, g, a);
+    g = fma(d, h, g);
+    d = fma(-g, g, a);
+    return fma(d, h, g);
+}
+
 // ---- WENO3 reconstruction (eq. 7-8) ----------------------------------------------------
 // Linear weights paired for third order: the central two-cell candidate takes 2/3 (the
 // printed d_r labels of eq. 8 are swapped; with them the scheme is second order).
@@ -75,7 +92,7 @@ __device__ __forceinline__ void hll(double HL, double QL, double HR, double QR, 
     const double uL = QL * iHL, uR = QR * iHR;
     const double FL0 = QL, FL1 = QL * uL + 0.5 * g * sig * hl * hl;
     const double FR0 = QR, FR1 = QR * uR + 0.5 * g * sig * hr * hr;
-    const double cL = sqrt(g * hl), cR = sqrt(g * hr);
+    const double cL = qsqrt(g * hl), cR = qsqrt(g * hr);
     const double sl1 = uL - cL, sl2 = uR - cR;
     const double sr1 = uL + cL, sr2 = uR + cR;
     const double SL = sl1 < sl2 ? sl1 : sl2;
