@@ -134,7 +134,10 @@ size_t nmg_workspace_bytes(const nmg_desc *desc, const nmg_params *params);
 
 /* Residual of eq. (10) (1D, not divided by dx) or eq. (20) (2D) for every cell, the cell norms
  * rn[j] = ||R_j||_1 and res_dev[0] = (1/N) sum_j rn[j] (Algorithm 1).  U, R, rn, res_dev are
- * device pointers. */
+ * device pointers.  The 1D kernels divide by depths, widths and wave-speed differences with a
+ * refined hardware reciprocal that assumes normal-range operands (a physical state: depths and
+ * widths well above 1e-150); a zero or negative depth gives a non-finite residual, which the
+ * Newton drivers report as NMG_ENONFINITE. */
 nmg_status nmg_residual(const nmg_desc *desc, const double *U, double *R, double *rn,
                         double *res_dev, void *stream);
 
