@@ -370,6 +370,32 @@ def main():
                                     "newton_steps": [min(s[0] for s in st32[-1]), max(s[0] for s in st32[-1])],
                                     "max_abs_diff_vs_fp64_gpu": err,
                                     "converged": all(s[1] == 0 and s[2] < 1e-10 for st in st32 for s in st)}
+        # the well-balanced surface reconstruction (WENO3 on H + zbar) on the same batch
+        import dataclasses
+        sprobs = [dataclasses.replace(p, recon=1) for p in probs]
+        ssurf = BatchSolver1D(sprobs, device="cuda:0", jac=3, precision=NMG_FP64)
+        esf, stsf, _, _, Usf = timed_solves(ssurf, ssurf.states(), args.steps, 5, use_graph)
+        forms["fp64_batch_J3_surface"] = {
+            "solves_per_s": args.batch * args.steps / esf,
+            "newton_steps": [min(s[0] for s in stsf[-1]), max(s[0] for s in stsf[-1])],
+            "converged": all(s[1] == 0 and s[2] < 1e-10 for st in stsf for s in st),
+            "max_abs_diff_vs_conserved_reconstruction": max(float((a - b).abs().max()) for a, b in zip(Usf, Ulast))}
+        del ssurf
+        # Newton-SOR (the paper's reference solver: <= 10 multicolour block-SOR steps per Newton
+        # step) against NMGM-3 on 256 config-1 instances (N = 200)
+        from swe_workloads import config1
+        c1 = [config1(i) for i in range(args.batch)]
+        cmp1 = {}
+        for name, lin in (("nmgm3", A.NMG_LINEAR_MG), ("newton_sor", A.NMG_LINEAR_SOR)):
+            pp = [dataclasses.replace(p, params=dataclasses.replace(p.params, linear=lin)) for p in c1]
+            sb = BatchSolver1D(pp, device="cuda:0", jac=3, precision=NMG_FP64)
+            eb, stb, _, _, _ = timed_solves(sb, sb.states(), 1, 1, use_graph)
+            last = stb[-1]
+            cmp1[name] = {"solves_per_s": args.batch / eb,
+                          "newton_steps": [min(x[0] for x in last), max(x[0] for x in last)],
+                          "converged": sum(1 for x in last if x[1] == 0 and x[2] < 1e-10)}
+            del sb
+        forms["fp64_cfg1_nmgm3_vs_newton_sor"] = cmp1
         # transcritical hump (q = 1.53, h_out = 0.66): out of reach of plain Newton from the flat
         # surface; nested iteration (Algorithm 3) over the 8 grids 100 .. 12800, batched per grid
         from paper_2505_10857_amd.solver import NestedBatch
