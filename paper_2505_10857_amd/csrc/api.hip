@@ -456,23 +456,29 @@ nmg_status enqueue_vcycle(nmg_plan *P, char *ws, const MGArgs &mg, bool zero_ini
         ProfScope ps(P, d == 0 ? NMG_K_SMOOTH_PRE : -1, s, cap);
         const int src = d == 0 ? src0 : 0;
         HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
-                                P->smooth_mask[d], 0, (d > 0 || zero_init0) ? 1 : 0, 0, src, P->prec, P->smooth_tile, s));
+                                P->smooth_mask[d], 0, (d > 0 || zero_init0) ? 1 : 0, 0, src, P->prec, P->smooth_tile,
+                                0, s));
         if (d == 0) src0 = 1 - src;
     }
     HIP_TRY(launch_bottom(mg, list, P->n, zero_init0 ? 1 : 0, final_update ? 1 : 0, P->prec, P->bottom_nt, s));
+    // Passes alternate direction over data that a recent pass streamed, so that each begins in
+    // the memory-side cache: the residual runs in tile order and the Jacobian after it in
+    // reverse (k_jacobian_batch), so the finest pre-smoothing after that runs in order; a coarse
+    // level's post-smoothing, with only smaller levels since its pre-smoothing, runs in reverse.
     for (int d = P->depth - 1; d >= 0; d--) {
         if (P->smooth[d].second == 0) continue;
         if (d == 0 && fuse_up0) {
             ProfScope ps(P, NMG_K_SMOOTH_FUSED, s, cap);
             HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->fused0.first), P->fused0.second, P->smooth_mask[0], 2,
-                                    0, 0, src0, P->prec, P->smooth_tile, s));
+                                    0, 0, src0, P->prec, P->smooth_tile, 0, s));
             src0 = 1 - src0;
             continue;
         }
         ProfScope ps(P, d == 0 ? NMG_K_SMOOTH_POST : -1, s, cap);
         const int src = d == 0 ? src0 : 1;
         HIP_TRY(launch_smooth1d(mg, tiles_at(P, ws, P->smooth[d].first), P->smooth[d].second,
-                                P->smooth_mask[d], 1, 0, (d == 0 && final_update) ? 1 : 0, src, P->prec, P->smooth_tile, s));
+                                P->smooth_mask[d], 1, 0, (d == 0 && final_update) ? 1 : 0, src, P->prec, P->smooth_tile,
+                                d > 0 ? 1 : 0, s));
         if (d == 0) src0 = 1 - src;
     }
     if (src0_out) *src0_out = src0;

@@ -156,13 +156,16 @@ __global__ void __launch_bounds__(kTile) k_coarsen(MGArgs mg, const Tile *tiles)
 // src_out: the tile reads dU from dUo (1) or dU (0) and writes its cells to the other buffer.
 template <typename T, int NB, int MODE, int TW>
 __global__ void __launch_bounds__(TW) k_smooth(MGArgs mg, const Tile *tiles, int zero_init,
-                                                  int final_update, int src_out)
+                                                  int final_update, int src_out, int reverse)
 {
     constexpr int mode = MODE;
     constexpr int HW = NB / 2;
     constexpr int C = NB == 5 ? 3 : 2;
     __shared__ double s0[TW + 2 * HW], s1[TW + 2 * HW];
-    const Tile tl = tiles[blockIdx.x];
+    // reverse: the last tiles first (workgroups start roughly in index order), so that a pass
+    // that follows another pass over the same data begins with what that pass touched last,
+    // which is still in the memory-side cache
+    const Tile tl = tiles[reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x];
     const Level1D L = mg.levs[tl.lev];
     if (L.nb != NB) return;
     if (!active_of(mg, L.inst)) return;
@@ -911,40 +914,40 @@ hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero
 
 template <typename T, int NB, int TW>
 static void launch_smooth_w(const MGArgs &mg, const Tile *tiles, int ntiles, int mode, int zero_init,
-                            int final_update, int src_out, hipStream_t s)
+                            int final_update, int src_out, int reverse, hipStream_t s)
 {
     if (mode == 0)
         hipLaunchKernelGGL((k_smooth<T, NB, 0, TW>), dim3(ntiles), dim3(TW), 0, s, mg, tiles, zero_init,
-                           final_update, src_out);
+                           final_update, src_out, reverse);
     else if (mode == 1)
         hipLaunchKernelGGL((k_smooth<T, NB, 1, TW>), dim3(ntiles), dim3(TW), 0, s, mg, tiles, zero_init,
-                           final_update, src_out);
+                           final_update, src_out, reverse);
     else
         hipLaunchKernelGGL((k_smooth<T, NB, 2, TW>), dim3(ntiles), dim3(TW), 0, s, mg, tiles, zero_init,
-                           final_update, src_out);
+                           final_update, src_out, reverse);
 }
 
 template <typename T, int NB>
 static void launch_smooth_t(const MGArgs &mg, const Tile *tiles, int ntiles, int mode, int zero_init,
-                            int final_update, int src_out, int tile, hipStream_t s)
+                            int final_update, int src_out, int tile, int reverse, hipStream_t s)
 {
     if (tile == kSmoothTileMax)
-        launch_smooth_w<T, NB, kSmoothTileMax>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
+        launch_smooth_w<T, NB, kSmoothTileMax>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, reverse, s);
     else
-        launch_smooth_w<T, NB, kSmoothTile>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, s);
+        launch_smooth_w<T, NB, kSmoothTile>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, reverse, s);
 }
 
 hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_mask, int mode,
-                           int zero_init, int final_update, int src_out, int prec, int tile, hipStream_t s)
+                           int zero_init, int final_update, int src_out, int prec, int tile, int reverse, hipStream_t s)
 {
     if (ntiles == 0) return hipSuccess;
     if (tile != kSmoothTile && tile != kSmoothTileMax) return hipErrorInvalidValue;
     if (prec == NMG_FP32_MG) {
-        if (nb_mask & 1) launch_smooth_t<float, 3>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, s);
-        if (nb_mask & 2) launch_smooth_t<float, 5>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, s);
+        if (nb_mask & 1) launch_smooth_t<float, 3>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, reverse, s);
+        if (nb_mask & 2) launch_smooth_t<float, 5>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, reverse, s);
     } else {
-        if (nb_mask & 1) launch_smooth_t<double, 3>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, s);
-        if (nb_mask & 2) launch_smooth_t<double, 5>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, s);
+        if (nb_mask & 1) launch_smooth_t<double, 3>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, reverse, s);
+        if (nb_mask & 2) launch_smooth_t<double, 5>(mg, tiles, ntiles, mode, zero_init, final_update, src_out, tile, reverse, s);
     }
     return hipGetLastError();
 }

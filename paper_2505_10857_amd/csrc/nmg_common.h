@@ -167,7 +167,7 @@ hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero
 // the post-smoothing of one V-cycle and the pre-smoothing of the next on one level.  src_out:
 // read dU from dUo (1) or dU (0) and write the other buffer.
 hipError_t launch_smooth1d(const MGArgs &mg, const Tile *tiles, int ntiles, int nb_mask, int mode,
-                           int zero_init, int final_update, int src_out, int prec, int tile, hipStream_t s);
+                           int zero_init, int final_update, int src_out, int prec, int tile, int reverse, hipStream_t s);
 hipError_t launch_convert(const void *src, int src_prec, void *dst, int dst_prec, long long n,
                           hipStream_t s);
 // Newton-SOR (section 5.1.1) on level 0: one symmetric multicolour block-SOR step per launch

@@ -633,7 +633,9 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
 template <typename T, int NB, bool SURF>
 __global__ void __launch_bounds__(kTile) k_jacobian_batch(MGArgs mg, const Tile *tiles)
 {
-    const Tile t = tiles[blockIdx.x];
+    // the last tiles first: the residual launch before this one streamed the same state and
+    // geometry in tile order, so its last tiles' data are still in the memory-side cache
+    const Tile t = tiles[gridDim.x - 1 - blockIdx.x];
     const Inst1D &I = mg.insts[t.lev];
     if (!inst_active(mg.state, I)) return;
     const Level1D L = mg.levs[I.lev0];
