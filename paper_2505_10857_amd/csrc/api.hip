@@ -633,6 +633,7 @@ nmg_status apply_options(nmg_plan *P, int cells, int split, int tile)
         P->smooth_tile = old_tile;
         P->split_finest = old_split;
         (void)build_plan(P, P->descs.data(), P->params.data(), P->n);
+        P->total = std::max(P->total, total);
         return fail(st, err);
     }
     P->total = std::max(P->total, total);
