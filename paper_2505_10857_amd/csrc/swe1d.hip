@@ -583,7 +583,9 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
     }
     if (!mg || L0->coarsest) return;
 
-    // coarse operators of the levels inside this tile (eq. 17), reduced in LDS
+    // coarse operators of the levels inside this tile (eq. 17), reduced in LDS; stored with
+    // non-temporal hints: they are read only after the finest level's first smoothing pass,
+    // which should find this tile's fine rows, not these, in the memory-side cache
     __syncthreads();
     T *base_mg = reinterpret_cast<T *>(mg->mg);
     Level1D Lc = mg->levs[L0->child];
@@ -599,9 +601,9 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 rows[t * 12 + e] = Wc[e]; rows[t * 12 + 4 + e] = Dc[e]; rows[t * 12 + 8 + e] = Ec[e];
-                base_mg[Lc.J + (0 * 4 + e) * (long long)Lc.n + jc] = (T)Wc[e];
-                base_mg[Lc.J + (1 * 4 + e) * (long long)Lc.n + jc] = (T)Dc[e];
-                base_mg[Lc.J + (2 * 4 + e) * (long long)Lc.n + jc] = (T)Ec[e];
+                __builtin_nontemporal_store((T)Wc[e], &base_mg[Lc.J + (0 * 4 + e) * (long long)Lc.n + jc]);
+                __builtin_nontemporal_store((T)Dc[e], &base_mg[Lc.J + (1 * 4 + e) * (long long)Lc.n + jc]);
+                __builtin_nontemporal_store((T)Ec[e], &base_mg[Lc.J + (2 * 4 + e) * (long long)Lc.n + jc]);
             }
         }
         __syncthreads();
@@ -618,9 +620,9 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 rows[t * 12 + e] = Wc[e]; rows[t * 12 + 4 + e] = Dc[e]; rows[t * 12 + 8 + e] = Ec[e];
-                base_mg[Ln.J + (0 * 4 + e) * (long long)Ln.n + jc] = (T)Wc[e];
-                base_mg[Ln.J + (1 * 4 + e) * (long long)Ln.n + jc] = (T)Dc[e];
-                base_mg[Ln.J + (2 * 4 + e) * (long long)Ln.n + jc] = (T)Ec[e];
+                __builtin_nontemporal_store((T)Wc[e], &base_mg[Ln.J + (0 * 4 + e) * (long long)Ln.n + jc]);
+                __builtin_nontemporal_store((T)Dc[e], &base_mg[Ln.J + (1 * 4 + e) * (long long)Ln.n + jc]);
+                __builtin_nontemporal_store((T)Ec[e], &base_mg[Ln.J + (2 * 4 + e) * (long long)Ln.n + jc]);
             }
         }
         __syncthreads();
