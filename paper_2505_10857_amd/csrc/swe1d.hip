@@ -139,35 +139,44 @@ struct CellGeom {
     double zfm, zfp;                  // bottom at the faces (surface reconstruction)
 };
 
+// a load that is this data's last use in the step (STREAM): the non-temporal hint leaves the
+// memory-side cache to what the next launch re-reads
+template <bool STREAM>
+__device__ __forceinline__ double ldg(const double *p)
+{
+    if (STREAM) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
 // SURF: the surface reconstruction (constant width 1): the widths are not read, the bottom at
 // the faces is
-template <bool SURF>
+template <bool SURF, bool STREAM = false>
 __device__ __forceinline__ CellGeom load_geom(const Inst1D &I, int j)
 {
     CellGeom G;
     if (SURF) {
         G.sfm = G.sfp = G.isfm = G.isfp = 1.0;
-        G.zfm = I.z_face[j];
-        G.zfp = I.z_face[j + 1];
+        G.zfm = ldg<STREAM>(&I.z_face[j]);
+        G.zfp = ldg<STREAM>(&I.z_face[j + 1]);
 #pragma unroll
         for (int q = 0; q < 2; q++) {
             G.sg[q] = G.isg[q] = 1.0;
             G.sxg[q] = 0.0;
-            G.bxg[q] = I.bx_gp[2 * j + q];
+            G.bxg[q] = ldg<STREAM>(&I.bx_gp[2 * j + q]);
         }
         return G;
     }
     G.zfm = G.zfp = 0.0;
-    G.sfm = I.sig_face[j];
-    G.sfp = I.sig_face[j + 1];
+    G.sfm = ldg<STREAM>(&I.sig_face[j]);
+    G.sfp = ldg<STREAM>(&I.sig_face[j + 1]);
     G.isfm = qrcp(G.sfm);
     G.isfp = qrcp(G.sfp);
 #pragma unroll
     for (int q = 0; q < 2; q++) {
-        G.sg[q] = I.sig_gp[2 * j + q];
+        G.sg[q] = ldg<STREAM>(&I.sig_gp[2 * j + q]);
         G.isg[q] = qrcp(G.sg[q]);
-        G.sxg[q] = I.sigx_gp[2 * j + q];
-        G.bxg[q] = I.bx_gp[2 * j + q];
+        G.sxg[q] = ldg<STREAM>(&I.sigx_gp[2 * j + q]);
+        G.bxg[q] = ldg<STREAM>(&I.bx_gp[2 * j + q]);
     }
     return G;
 }
@@ -322,13 +331,14 @@ __device__ __forceinline__ void local_residual(const double H[5], const double Q
 }
 
 // Stage U[a-2 .. a+kTile+1] of one instance into LDS (zeros outside the grid).
+template <bool STREAM = false>
 __device__ __forceinline__ void stage_state(const Inst1D &I, int a, double (*sH), double (*sQ))
 {
     for (int k = threadIdx.x; k < kTile + 4; k += kTile) {
         int c = a - 2 + k;
         bool ok = c >= 0 && c < I.N;
-        sH[k] = ok ? I.U[c] : 0.0;
-        sQ[k] = ok ? I.U[I.N + c] : 0.0;
+        sH[k] = ok ? ldg<STREAM>(&I.U[c]) : 0.0;
+        sQ[k] = ok ? ldg<STREAM>(&I.U[I.N + c]) : 0.0;
     }
 }
 
@@ -485,7 +495,7 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
 {
     __shared__ double sH[kTile + 4], sQ[kTile + 4];
     __shared__ double rows[kTile * NB * 4];
-    stage_state(I, a, sH, sQ);
+    stage_state<true>(I, a, sH, sQ);   // the state, geometry and residual: last use this step
     __syncthreads();
     const int t = threadIdx.x;
     const int j = a + t;
@@ -497,9 +507,9 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
         double H[5], Q[5];
 #pragma unroll
         for (int p = 0; p < 5; p++) { H[p] = sH[t + p]; Q[p] = sQ[t + p]; }
-        const CellGeom G = load_geom<SURF>(I, j);
+        const CellGeom G = load_geom<SURF, true>(I, j);
         const CubicGauss W;
-        const double R0 = I.R[j], R1 = I.R[I.N + j], rn = I.rn[j];
+        const double R0 = ldg<true>(&I.R[j]), R1 = ldg<true>(&I.R[I.N + j]), rn = ldg<true>(&I.rn[j]);
         const double eps = I.eps, ieps = 1.0 / I.eps;
         if (rhs) {   // the finest level's right-hand side of eq. (16) is R itself
             rhs[j] = (T)R0;
