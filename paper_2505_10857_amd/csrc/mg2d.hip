@@ -18,6 +18,15 @@ namespace nmg {
 template <typename T>
 __device__ __forceinline__ double ld2(const T *p, long long i) { return (double)p[i]; }
 
+// a load whose data will be evicted before it is read again (STREAM): the non-temporal hint
+// keeps it out of the memory-side cache
+template <bool STREAM, typename T>
+__device__ __forceinline__ double lds2(const T *p)
+{
+    if (STREAM) return (double)__builtin_nontemporal_load(p);
+    return (double)*p;
+}
+
 // stencil offsets: the cross of eq. (21) on the finest level, five points below
 __device__ __forceinline__ void stencil_off(int nb, int b, int &di, int &dj)
 {
@@ -111,7 +120,7 @@ __global__ void k_coarsen2d(T *mg, Level2D Lf, Level2D Lc)
 // type as if it had been stored between the passes.  The stencil is unrolled so that every load
 // of the cell's row is issued up front; neighbours outside the grid read the cell's own slot and
 // are left out of the sum.
-template <typename T, int NB>
+template <typename T, int NB, bool STREAM = false>
 __device__ __forceinline__ void smooth_slot(T *mg, const Level2D &L, int colour, double omega, int reps, long long p)
 {
     constexpr int C = NB == 9 ? 3 : 2;
@@ -141,8 +150,8 @@ __device__ __forceinline__ void smooth_slot(T *mg, const Level2D &L, int colour,
     for (int b = 1; b < NB; b++)
 #pragma unroll
         for (int c = 0; c < 3; c++)
-            a[b][c] = (double)Jr[(b * 9 + c * 3 + 0) * n] * x[b][0] + (double)Jr[(b * 9 + c * 3 + 1) * n] * x[b][1] +
-                      (double)Jr[(b * 9 + c * 3 + 2) * n] * x[b][2];
+            a[b][c] = lds2<STREAM>(Jr + (b * 9 + c * 3 + 0) * n) * x[b][0] + lds2<STREAM>(Jr + (b * 9 + c * 3 + 1) * n) * x[b][1] +
+                      lds2<STREAM>(Jr + (b * 9 + c * 3 + 2) * n) * x[b][2];
     double r[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -154,8 +163,8 @@ __device__ __forceinline__ void smooth_slot(T *mg, const Level2D &L, int colour,
     double t[3];
 #pragma unroll
     for (int c = 0; c < 3; c++)
-        t[c] = ld2(mg + L.Dinv, (c * 3 + 0) * n + cc) * r[0] + ld2(mg + L.Dinv, (c * 3 + 1) * n + cc) * r[1] +
-               ld2(mg + L.Dinv, (c * 3 + 2) * n + cc) * r[2];
+        t[c] = lds2<STREAM>(mg + L.Dinv + (c * 3 + 0) * n + cc) * r[0] + lds2<STREAM>(mg + L.Dinv + (c * 3 + 1) * n + cc) * r[1] +
+               lds2<STREAM>(mg + L.Dinv + (c * 3 + 2) * n + cc) * r[2];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         T d = mg[L.dU + c * n + cc];
@@ -164,12 +173,12 @@ __device__ __forceinline__ void smooth_slot(T *mg, const Level2D &L, int colour,
     }
 }
 
-template <typename T, int NB>
+template <typename T, int NB, bool STREAM>
 __global__ void __launch_bounds__(256) k_smooth2d_pass(T *mg, Level2D L, int colour, double omega, int reps)
 {
     const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (p >= (long long)L.ny * L.P.W) return;
-    smooth_slot<T, NB>(mg, L, colour, omega, reps, p);
+    smooth_slot<T, NB, STREAM>(mg, L, colour, omega, reps, p);
 }
 
 // eq. (24), right-hand side of coarse cell (I, Jq); also clears its dU.
@@ -568,15 +577,24 @@ hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, int reps
     dim3 grid((unsigned)((slots + 255) / 256));
     if (L.P.C != (L.nb == 9 ? 3 : 2)) return hipErrorInvalidValue;
     if (L.nb == 9) {
-        if (prec == NMG_FP32_MG)
-            hipLaunchKernelGGL((k_smooth2d_pass<float, 9>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
-        else
-            hipLaunchKernelGGL((k_smooth2d_pass<double, 9>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
+        // finest level: the symmetric schedule returns to colour 1 every other run and to colours
+        // 0 and 2 every fourth.  When the level's operator is larger than the memory-side cache,
+        // colours 0 and 2 are evicted before they come back, so their passes stream their rows
+        // and leave the cache to colour 1's
+        const size_t vsz = prec == NMG_FP32_MG ? 4 : 8;
+        const bool stream = colour != 1 && (size_t)L.nb * 9 * (size_t)L.P.M * vsz > kMemCacheBytes;
+        if (prec == NMG_FP32_MG) {
+            if (stream) hipLaunchKernelGGL((k_smooth2d_pass<float, 9, true>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
+            else hipLaunchKernelGGL((k_smooth2d_pass<float, 9, false>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
+        } else {
+            if (stream) hipLaunchKernelGGL((k_smooth2d_pass<double, 9, true>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
+            else hipLaunchKernelGGL((k_smooth2d_pass<double, 9, false>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
+        }
     } else {
         if (prec == NMG_FP32_MG)
-            hipLaunchKernelGGL((k_smooth2d_pass<float, 5>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
+            hipLaunchKernelGGL((k_smooth2d_pass<float, 5, false>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
         else
-            hipLaunchKernelGGL((k_smooth2d_pass<double, 5>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
+            hipLaunchKernelGGL((k_smooth2d_pass<double, 5, false>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
     }
     return hipGetLastError();
 }

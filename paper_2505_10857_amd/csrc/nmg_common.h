@@ -12,6 +12,7 @@ namespace nmg {
 constexpr int kTile = 256;        // threads (= cells) per 1D tile
 constexpr int kSmoothTile = 256;  // default threads (= cells) per tile of the tiled multigrid smoother
 constexpr int kSmoothTileMax = 512;  // the other width the plan options offer
+constexpr size_t kMemCacheBytes = size_t(256) << 20;   // MI355X memory-side (Infinity) cache
 constexpr int kCoarsenCells = 4;  // level-l0 cells per thread in the coarsening kernel
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 256;   // cells on the coarsest 1D level (one thread per cell)
