@@ -194,6 +194,35 @@ class Oracle1D:
                             ptr(np.ascontiguousarray(rn)), eps, alpha, nb, ptr(J))
         return J
 
+    def jacobian_rows(self, U, rows, eps=None, alpha=None, nb=3, R=None, rn=None):
+        """Blocks J[len(rows), nb, 2, 2] of the rows `rows` only (eq. 12-13): each column
+        (i, m) of a row is the forward difference of that row's local residual under the
+        perturbation of component m of cell i, with the ghosts refilled from the perturbed
+        state, plus alpha ||R_j||_1 on the diagonal block.  The same arithmetic as
+        ``jacobian`` (which differences every column of the grid), for grids too large for it."""
+        p = self.prob.params
+        eps = p.eps if eps is None else eps
+        alpha = p.alpha if alpha is None else alpha
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        if R is None:
+            R, rn, _ = self.residual(U)
+        hw = nb // 2
+        out = np.zeros((len(rows), nb, 2, 2))
+        for k, j in enumerate(rows):
+            for b in range(nb):
+                i = j + b - hw
+                if i < 0 or i >= self.n:
+                    continue
+                for m in range(2):
+                    Up = U.copy()
+                    Up[m, i] = Up[m, i] + eps
+                    Rp = self.local_residual(self.ghosts(Up), j)
+                    for l in range(2):
+                        out[k, b, l, m] = (Rp[l] - R[l, j]) / eps
+            for l in range(2):
+                out[k, hw, l, l] += alpha * rn[j]
+        return out
+
     # -- Newton ---------------------------------------------------------------------------
     def newton_solve(self, U0=None, nb=3, smoother=0, levels=None, max_hist=100000, **over):
         """Algorithm 1 with nu3 V-cycles per step.  Returns (U, iterations, res, history)."""

@@ -445,6 +445,25 @@ def synthetic_operator_2d(nx: int, ny: int, seed: int = 0, dominance: float = 3.
     return J, rhs
 
 
+def synthetic_operator_1d(n: int, nb: int = 3, seed: int = 0, dominance: float = 3.0,
+                          spread: float = 0.1):
+    """A seeded block operator with the shape of the 1D simplified Jacobian (eq. 12-13): blocks
+    [n][nb][2][2], block b coupling cell j to cell j + b - nb // 2, entries U(-spread, spread)
+    plus dominance * I on the diagonal block, and a right-hand side [n][2] with entries U(-1, 1),
+    from default_rng([8, seed, n]).  Blocks that would couple to cells outside the grid are zero.
+    It stands in for a Jacobian at sizes where the oracle's column-by-column differencing (whose
+    cost grows with the square of the cell count) is out of reach."""
+    rng = np.random.default_rng([8, seed, n])
+    J = rng.uniform(-spread, spread, (n, nb, 2, 2))
+    hw = nb // 2
+    J[:, hw] += dominance * np.eye(2)
+    j = np.arange(n)
+    for b in range(nb):
+        J[(j + b - hw < 0) | (j + b - hw >= n), b] = 0.0
+    rhs = rng.uniform(-1.0, 1.0, (n, 2))
+    return J, rhs
+
+
 def bottom_faces_and_averages(prob: Problem1D):
     """Bottom samples for the surface reconstruction: b at the faces x_{j-1/2}, j = 0..N
     ([N+1]), and the cell averages of b over cells -2..N+1 ([N+4]: two cells beyond each end

@@ -292,6 +292,35 @@ def test_jacobian_entries_equal_brute_force_global_fd(bcl, bcr):
             assert np.all(dense[~band] == 0)
 
 
+def test_jacobian_rows_equal_brute_force_global_fd():
+    # The sampled-row form (for grids too large to difference every column) against the same
+    # brute force through the public global residual, boundary rows included, and with the
+    # regularisation bit for bit equal to the full form.
+    n, eps = 12, 0.02
+    pr = _prob(n=n, bottom=gaussian_bump(0.1, 0.5, 0.02), width=sine_width(1, 1.0, 0.1),
+               bcl=BC(BC_DISCHARGE, q=1.0), bcr=BC(BC_WALL))
+    o = Oracle1D(pr)
+    rng = np.random.default_rng(12)
+    U = np.stack([1.0 + 0.2 * rng.random(n), 0.6 + 0.2 * rng.random(n)])
+    R0, _, _ = o.residual(U)
+    rows = [0, 1, 2, 5, n - 3, n - 2, n - 1]
+    for nb in (3, 5):
+        Jr = o.jacobian_rows(U, rows, eps=eps, alpha=0.0, nb=nb)
+        for k, j in enumerate(rows):
+            for b in range(nb):
+                i = j + b - nb // 2
+                for m in range(2):
+                    if not 0 <= i < n:
+                        assert np.all(Jr[k, b, :, m] == 0)
+                        continue
+                    Up = U.copy()
+                    Up[m, i] = U[m, i] + eps
+                    col = (o.residual(Up)[0][:, j] - R0[:, j]) / eps
+                    assert np.array_equal(Jr[k, b, :, m], col)
+        Jfull = o.jacobian(U, eps=eps, alpha=0.7, nb=nb)
+        assert np.array_equal(o.jacobian_rows(U, rows, eps=eps, alpha=0.7, nb=nb), Jfull[rows])
+
+
 def test_block_magnitudes_on_e1_96():
     # Section 3.3: on the 96-cell smooth subcritical test, central tridiagonal blocks exceed 1,
     # outermost blocks are below 1, and about 69% of the outermost ones are below 1e-4.
