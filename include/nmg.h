@@ -68,7 +68,10 @@ typedef struct {
  *   (y point beta, x point gamma) of each cell.
  * levels = L + 1 grid levels (eq. 15 / 23): nx (and ny) must be divisible by 2^(levels-1);
  *   levels = 1 (1D, jac = 3) solves the regularised system directly (Algorithm 3, step 4).
- * jac = 3 or 5 (1D), 9 (2D): which Jacobian blocks are assembled (section 3.3 / 4.1).
+ * jac = 3 or 5 (1D), 9 (2D): which Jacobian blocks are assembled (section 3.3 / 4.1).  On very
+ *   fine 1D grids the three-block Newton iteration itself can fail where J5 converges: on a
+ *   smooth hump flow it converged up to 2^19 cells and ended non-finite from 2^21 cells, where
+ *   J5 took 14-16 steps; such a solve reports NMG_ENONFINITE.
  * recon (1D): NMG_RECON_CONSERVED reconstructs H as in section 3.1 (the paper's scheme, not
  *   well balanced).  NMG_RECON_SURFACE, for channels of constant width (the width arrays are
  *   then not read; width 1): WENO3 reconstructs the surface eta = H + zbar, the depths at a face
