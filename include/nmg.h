@@ -66,8 +66,12 @@ typedef struct {
  *   the bottom side is EXTRAP for x < wall_x and WALL beyond when bc[2].kind == NMG_BC_WALL
  *   and wall_x > x0.  bx_gp, by_gp [ny][nx][2][2]: b_x, b_y at the tensor Gauss points
  *   (y point beta, x point gamma) of each cell.
- * levels = L + 1 grid levels (eq. 15 / 23): nx (and ny) must be divisible by 2^(levels-1);
+ * levels = L + 1 grid levels (eq. 15 / 23), at most 16: nx (and ny) must be divisible by
+ *   2^(levels-1), and the coarsest level may hold at most 256 cells in 1D (so 1D grids have
+ *   4 <= nx <= 256 * 2^15 cells) and at most 40 in 2D (2D grids hold at most 2^28 cells);
  *   levels = 1 (1D, jac = 3) solves the regularised system directly (Algorithm 3, step 4).
+ *   Newton-SOR plans (params->linear != NMG_LINEAR_MG) build no hierarchy and skip these
+ *   level checks.
  * jac = 3 or 5 (1D), 9 (2D): which Jacobian blocks are assembled (section 3.3 / 4.1).  On very
  *   fine 1D grids the three-block Newton iteration itself can fail where J5 converges: on a
  *   smooth hump flow it converged up to 2^19 cells and ended non-finite from 2^21 cells, where
