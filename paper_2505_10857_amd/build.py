@@ -16,7 +16,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # bit-reproducible FP64 residual: no contraction of a*b+c into fma
+    # no contraction of a*b+c into fma by default (the multigrid kernels then round as the
+    # plain C oracle does); the residual and Jacobian file enables it for its own expressions
     "-ffp-contract=off",
     # packed-FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -13,7 +13,14 @@
 // of the fully IEEE-rounded sequence (their operands are well scaled), so a quotient may differ
 // from the correctly rounded one in its last bit.  The result agrees with the printed forms to
 // rounding.
+//
+// This file's kernels are bound by FP64 arithmetic, so a product added to another term within
+// one expression is contracted into a single fused multiply-add (the library's other files keep
+// contraction off).  Contraction follows the source expressions alone, so every kernel that
+// evaluates a residual here rounds it the same way.
 #include "nmg_common.h"
+
+#pragma clang fp contract(on)
 
 namespace nmg {
 
