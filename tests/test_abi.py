@@ -128,3 +128,28 @@ def test_reconstruction_field_is_checked():
     d.recon = 2
     assert L.nmg_workspace_bytes(ctypes.byref(d), ctypes.byref(p)) == 0
     assert b"recon" in L.nmg_last_error()
+
+
+def test_size_limits_and_empty_batch():
+    """The accepted 1D sizes end exactly where the header says, and an empty batch is refused."""
+    abi, L = _lib()
+    ok = [dict(nx=4, levels=1), dict(nx=256 << 15, levels=16), dict(nx=256, levels=1)]
+    bad = [dict(nx=3, levels=1),               # fewer than four cells
+           dict(nx=256 << 16, levels=16),      # coarsest level of 512 cells
+           dict(nx=257 << 15, levels=16),      # not divisible by 2^15
+           dict(nx=512, levels=1),             # one level of more than 256 cells
+           dict(nx=256 << 16, levels=17)]      # more than 16 levels
+    for kw in ok:
+        d, p = _desc(abi, **kw)
+        assert L.nmg_workspace_bytes(ctypes.byref(d), ctypes.byref(p)) > 0, kw
+    for kw in bad:
+        d, p = _desc(abi, **kw)
+        assert L.nmg_workspace_bytes(ctypes.byref(d), ctypes.byref(p)) == 0, kw
+        assert L.nmg_last_error()
+    d, p = _desc(abi)
+    descs = (abi.nmg_desc * 1)(d)
+    params = (abi.nmg_params * 1)(p)
+    plan = ctypes.c_void_p()
+    for n in (0, -1):
+        assert L.nmg_plan_create(descs, params, n, ctypes.byref(plan)) == abi.NMG_EINVAL
+        assert L.nmg_last_error()
