@@ -222,18 +222,6 @@ nmg_status newton_step(const Plan2D &P, char *w, double *U, hipStream_t s)
     return NMG_OK;
 }
 
-// The residual/Jacobian kernels of swe2d.hip are switched off: their first gfx950 run stopped
-// with a memory aperture violation whose cause has not been identified (a CPU build of the same
-// device functions, with bounds checks on every staged access, matches the oracle bit for bit).
-// The multigrid entry point (nmg_mg_vcycle) does not use them and stays enabled.
-constexpr bool kResidual2DEnabled = false;
-
-nmg_status residual2d_disabled()
-{
-    return set_error(NMG_EINVAL, "2D residual/Jacobian kernels are disabled: their first gfx950 run faulted "
-                                 "and the cause is not yet identified");
-}
-
 }  // namespace
 
 size_t workspace2d_bytes(const nmg_desc *d, const nmg_params *p)
@@ -245,7 +233,6 @@ size_t workspace2d_bytes(const nmg_desc *d, const nmg_params *p)
 
 nmg_status residual2d(const nmg_desc *d, const double *U, double *R, double *rn, double *res, hipStream_t s)
 {
-    if (!kResidual2DEnabled) return residual2d_disabled();
     nmg_params p;
     memset(&p, 0, sizeof(p));
     p.eps = 1.0;
@@ -265,7 +252,6 @@ nmg_status residual2d(const nmg_desc *d, const double *U, double *R, double *rn,
 nmg_status jacobian2d(const nmg_desc *d, const nmg_params *p, const double *U, const double *R,
                       const double *rn, double *J, hipStream_t s)
 {
-    if (!kResidual2DEnabled) return residual2d_disabled();
     nmg_status st = check2d(d, p);
     if (st != NMG_OK) return st;
     if (!U || !R || !rn || !J) return set_error(NMG_EINVAL, "null U/R/rn/J");
@@ -303,7 +289,6 @@ nmg_status vcycle2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_
 nmg_status newton2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, double *U,
                     nmg_stats *stats, double *hist, int max_hist, hipStream_t s)
 {
-    if (!kResidual2DEnabled) return residual2d_disabled();
     if (!ws || !U || !stats) return set_error(NMG_EINVAL, "null argument");
     Plan2D P;
     nmg_status st = build2d(P, d, p);

@@ -404,13 +404,17 @@ __device__ __forceinline__ void coarse_apply(T *mg, const Level2D &L, const doub
         }
         __syncthreads();
     }
-    for (int k = M - 1; k >= 0; k--) {
-        if (t == 0) x[k] = x[k] / A[k * M + k];
-        __syncthreads();
-        const double xk = x[k];
-        for (int r = t; r < k; r += nt) x[r] -= A[r * M + k] * xk;
-        __syncthreads();
+    // back substitution row by row, each row's sum over the later unknowns in ascending column
+    // order (the order of a plain dense solve, so the result rounds like one); the rows depend on
+    // each other in sequence, so one lane does it (at most 120 unknowns)
+    if (t == 0) {
+        for (int k = M - 1; k >= 0; k--) {
+            double s = x[k];
+            for (int c = k + 1; c < M; c++) s -= A[k * M + c] * x[c];
+            x[k] = s / A[k * M + k];
+        }
     }
+    __syncthreads();
     for (int r = t; r < M; r += nt) {
         const int cell = r / 3;
         mg[L.dU + (r % 3) * Ms + perm2d(L.P, cell % nx, cell / nx)] = (T)x[r];

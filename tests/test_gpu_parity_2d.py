@@ -16,14 +16,6 @@ from swe_workloads import (BC, BC_DEPTH, BC_DISCHARGE, BC_WALL, Params, Problem2
 
 DEV = "cuda:0"
 
-# The 2D residual/Jacobian kernels stopped with a memory aperture violation on their first gfx950
-# run (test_residual_parity[wedge32x16]); no out-of-range access was found by reading them or in a
-# bounds-checked CPU build of the same device functions, so their entry points are disabled and
-# every test that needs them is skipped until the cause is identified.
-needs_residual2d = pytest.mark.skip(reason="2D residual/Jacobian kernels disabled: first gfx950 run "
-                                    "faulted (memory aperture violation), cause not yet identified")
-
-
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
     if not torch.cuda.is_available():
@@ -72,7 +64,6 @@ CASES = list(_cases())
 IDS = [c[0] for c in CASES]
 
 
-@needs_residual2d
 @pytest.mark.parametrize("name,prob", CASES, ids=IDS)
 def test_residual_parity(name, prob):
     s = _solver(prob)
@@ -90,7 +81,6 @@ def test_residual_parity(name, prob):
         assert abs(res.item() - reso) <= 1e-12 * max(reso, 1e-300)
 
 
-@needs_residual2d
 @pytest.mark.parametrize("name,prob", CASES, ids=IDS)
 def test_jacobian_parity(name, prob):
     s = _solver(prob)
@@ -175,7 +165,6 @@ def test_vcycle_fp32_mg_tracks_fp64():
     assert e <= 1e-4
 
 
-@needs_residual2d
 @pytest.mark.parametrize("name,prob", [CASES[0], CASES[3]], ids=[IDS[0], IDS[3]])
 def test_newton_trajectory(name, prob):
     """Five Newton steps (Algorithm 1): state and res history within 1e-10."""
@@ -191,7 +180,6 @@ def test_newton_trajectory(name, prob):
     assert np.all(np.abs(hist - hist_o) <= 1e-10 * np.maximum(np.abs(hist_o), 1e-300) + 1e-14)
 
 
-@needs_residual2d
 def test_newton_converges_like_oracle_wedge():
     """Jump over a wedge, 32 x 16, to res < 1e-10: same step count (+-1), state within 1e-10."""
     prob = wedge_problem(32, 16)
@@ -207,7 +195,6 @@ def test_newton_converges_like_oracle_wedge():
     assert e <= 1e-10
 
 
-@needs_residual2d
 def test_fp32_mg_converges_to_fp64_solution():
     """FP32 Jacobian and multigrid, FP64 residual/update/test: converged state within 1e-9."""
     from paper_2505_10857_amd import _abi as A
@@ -222,7 +209,6 @@ def test_fp32_mg_converges_to_fp64_solution():
     assert e <= 1e-9
 
 
-@needs_residual2d
 def test_full_size_sampled_rows():
     """1024 x 512 wedge at a generic state: the whole residual against the oracle's, and J9 rows
     of sampled grid lines (first, last, interior) against the oracle's rows."""
@@ -243,7 +229,6 @@ def test_full_size_sampled_rows():
         assert np.abs(Jg - Jt).max() <= 1e-12 * np.abs(Jt).max(), j0
 
 
-@needs_residual2d
 def test_full_size_newton_step_reduces_res():
     """1024 x 512 wedge, the launch configuration of the benchmark: three Newton steps in FP64
     and in FP32-MG lower res below its value at the uniform inflow guess and stay finite."""
