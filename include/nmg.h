@@ -173,6 +173,23 @@ nmg_status nmg_newton_solve(const nmg_desc *desc, const nmg_params *params, void
                             size_t ws_bytes, double *U, nmg_stats *stats, double *hist,
                             int32_t max_hist, void *stream);
 
+/* ---- Newton solve without allocation ----------------------------------------------------
+ * For callers that cannot allocate memory: code next to HIP graph capture, tight serving loops
+ * and harnesses that forbid hipMalloc.  nmg_newton_solve_static is nmg_newton_solve with the
+ * library's own device workspace instead of the ws argument: a static array of
+ * NMG_STATIC_WS_MIB MiB that every GPU the library runs on holds from the library's load until
+ * the process ends.  Same arguments and results otherwise (the same kernels, launched without a
+ * HIP graph; the result is bitwise that of nmg_newton_solve).  It calls no hipMalloc, hipFree,
+ * pinned-memory or other allocating HIP routine.  A problem whose nmg_workspace_bytes exceeds
+ * the array returns NMG_ENOMEM_WS (64 MiB covers 1D grids up to about 2e5 cells and 2D grids up
+ * to 256 x 128 in FP64, 512 x 256 with NMG_FP32_MG).  Every call on one GPU uses that GPU's one
+ * array and leaves its contents behind (each call initialises what it reads): calls that overlap
+ * on one GPU, from several threads or streams, race and must be serialised by the caller.
+ * Synchronises `stream`. */
+#define NMG_STATIC_WS_MIB 64
+nmg_status nmg_newton_solve_static(const nmg_desc *desc, const nmg_params *params, double *U,
+                                   nmg_stats *stats, double *hist, int32_t max_hist, void *stream);
+
 /* ---- nested iteration (Algorithm 3, Appendix A) -----------------------------------------
  * nmg_interp_coarse_to_fine: the initial cell averages of a 1D grid from the solution on the
  * grid with half as many cells, eq. (A.1)-(A.2): Uc [2][nc] -> Uf [2][2 nc] (device).  The

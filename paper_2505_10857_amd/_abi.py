@@ -38,8 +38,10 @@ EXPORTS = [
     "nmg_plan_begin", "nmg_plan_steps", "nmg_plan_destroy", "nmg_last_error",
     "nmg_plan_profile", "nmg_plan_profile_read", "nmg_plan_resume", "nmg_plan_set_options",
     "nmg_plan_get_options", "nmg_plan_autotune", "nmg_interp_coarse_to_fine",
-    "nmg_nested_workspace_bytes", "nmg_nested_solve",
+    "nmg_nested_workspace_bytes", "nmg_nested_solve", "nmg_newton_solve_static",
 ]
+
+NMG_STATIC_WS_MIB = 64
 
 NMG_K_NONE = 0
 NMG_K_JACOBIAN = 1
@@ -112,6 +114,8 @@ def load(path: str = LIB_PATH):
     L.nmg_mg_vcycle.argtypes = [P(nmg_desc), P(nmg_params), vp, sz, vp, vp, vp, C.c_int32, vp]
     L.nmg_newton_solve.argtypes = [P(nmg_desc), P(nmg_params), vp, sz, vp, P(nmg_stats),
                                    P(C.c_double), C.c_int32, vp]
+    L.nmg_newton_solve_static.argtypes = [P(nmg_desc), P(nmg_params), vp, P(nmg_stats), P(C.c_double),
+                                          C.c_int32, vp]
     L.nmg_plan_create.argtypes = [P(nmg_desc), P(nmg_params), C.c_int32, P(vp)]
     L.nmg_plan_workspace_bytes.argtypes = [vp]
     L.nmg_plan_workspace_bytes.restype = sz
@@ -136,7 +140,7 @@ def load(path: str = LIB_PATH):
     L.nmg_last_error.argtypes = []
     L.nmg_last_error.restype = C.c_char_p
     for nm in ("nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",
-               "nmg_newton_solve", "nmg_plan_create", "nmg_plan_solve", "nmg_plan_begin",
+               "nmg_newton_solve", "nmg_newton_solve_static", "nmg_plan_create", "nmg_plan_solve", "nmg_plan_begin",
                "nmg_plan_steps", "nmg_plan_resume", "nmg_plan_set_options", "nmg_plan_get_options",
                "nmg_plan_autotune", "nmg_interp_coarse_to_fine", "nmg_nested_solve"):
         getattr(L, nm).restype = C.c_int32

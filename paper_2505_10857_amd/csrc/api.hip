@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -155,6 +156,7 @@ struct nmg_plan {
     hipStream_t own_stream = nullptr;
     NewtonState *host_state = nullptr;        // pinned
     char *host_tables = nullptr;              // pinned staging of the instance table
+    bool host_borrowed = false;               // host_state / host_tables belong to the caller
     void *tables_ws = nullptr;                // workspace whose static tables are current
     // kernel timing
     int prof_kernel = NMG_K_NONE;
@@ -170,8 +172,8 @@ struct nmg_plan {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (own_stream) (void)hipStreamDestroy(own_stream);
-        if (host_state) (void)hipHostFree(host_state);
-        if (host_tables) (void)hipHostFree(host_tables);
+        if (host_state && !host_borrowed) (void)hipHostFree(host_state);
+        if (host_tables && !host_borrowed) (void)hipHostFree(host_tables);
     }
 };
 
@@ -1011,6 +1013,90 @@ nmg_status nmg_newton_solve(const nmg_desc *desc, const nmg_params *params, void
         int cnt = std::min(std::min((int)max_hist, S.iters), P.max_hist);
         if (cnt > 0) {
             hipStream_t s = (hipStream_t)stream;
+            if (hipMemcpyAsync(hist, (char *)ws + P.off_hist, sizeof(double) * cnt, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(NMG_EHIP, "history copy failed");
+        }
+    }
+    return st;
+}
+
+}  // extern "C"
+
+// ---- the Newton solve that allocates nothing -----------------------------------------------
+
+namespace {
+
+constexpr size_t kStaticWsBytes = size_t(NMG_STATIC_WS_MIB) << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+// The library's own device workspace for nmg_newton_solve_static.  Every GPU the library runs on
+// holds its own copy from the library's load until the process ends.  In host code the name is
+// only a stand-in for the symbol: the array's device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) char scratch[kStaticWsBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// this device's address of `scratch`, looked up once per device (with that device current)
+nmg_status scratch_address(void **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(NMG_EHIP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(NMG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nmg_status nmg_newton_solve_static(const nmg_desc *desc, const nmg_params *params, double *U,
+                                   nmg_stats *stats, double *hist, int32_t max_hist, void *stream)
+{
+    if (!desc || !params) return fail(NMG_EINVAL, "null desc or params");
+    if (!U) return fail(NMG_EINVAL, "null U");
+    const size_t need = nmg_workspace_bytes(desc, params);
+    if (need == 0) return NMG_EINVAL;   // the size query has set the message
+    if (need > kStaticWsBytes)
+        return fail(NMG_ENOMEM_WS, "the problem needs " + std::to_string(need) +
+                                       " bytes of workspace; the static workspace holds " +
+                                       std::to_string(kStaticWsBytes) + " (use nmg_newton_solve)");
+    void *ws = nullptr;
+    nmg_status st = scratch_address(&ws);
+    if (st != NMG_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    nmg_stats local;
+    nmg_stats &S = stats ? *stats : local;
+    if (desc->dim == 2) return newton2d(desc, params, ws, kStaticWsBytes, U, &S, hist, max_hist, s);
+    nmg_plan P;
+    st = build_plan(&P, desc, params, 1);
+    if (st != NMG_OK) return st;
+    // the instance table and the Newton state pass through host buffers on this call's stack
+    // instead of pinned allocations; the call synchronises before they go out of scope
+    alignas(64) char tables[sizeof(Inst1D)];
+    NewtonState hs;
+    P.host_tables = tables;
+    P.host_state = &hs;
+    P.host_borrowed = true;
+    double *Us[1] = {U};
+    st = nmg_plan_solve(&P, ws, kStaticWsBytes, Us, &S, 0, stream);
+    if (hist && max_hist > 0 && (st >= 0 || st == NMG_ENONFINITE)) {
+        const int cnt = std::min(std::min((int)max_hist, S.iters), P.max_hist);
+        if (cnt > 0) {
             if (hipMemcpyAsync(hist, (char *)ws + P.off_hist, sizeof(double) * cnt, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return fail(NMG_EHIP, "history copy failed");

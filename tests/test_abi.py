@@ -153,3 +153,23 @@ def test_size_limits_and_empty_batch():
     for n in (0, -1):
         assert L.nmg_plan_create(descs, params, n, ctypes.byref(plan)) == abi.NMG_EINVAL
         assert L.nmg_last_error()
+
+
+def test_static_newton_solve_rejects_on_the_host():
+    """nmg_newton_solve_static refuses null arguments and problems whose workspace exceeds its
+    NMG_STATIC_WS_MIB static array before it touches the device."""
+    abi, L = _lib()
+    d, p = _desc(abi)
+    st = abi.nmg_stats()
+    assert L.nmg_newton_solve_static(None, ctypes.byref(p), ctypes.c_void_p(256), ctypes.byref(st), None, 0,
+                                     None) == abi.NMG_EINVAL
+    assert L.nmg_newton_solve_static(ctypes.byref(d), ctypes.byref(p), None, ctypes.byref(st), None, 0,
+                                     None) == abi.NMG_EINVAL
+    big, pb = _desc(abi, nx=256 << 12, levels=13)            # about 300 MiB of workspace
+    assert L.nmg_workspace_bytes(ctypes.byref(big), ctypes.byref(pb)) > abi.NMG_STATIC_WS_MIB << 20
+    assert L.nmg_newton_solve_static(ctypes.byref(big), ctypes.byref(pb), ctypes.c_void_p(256),
+                                     ctypes.byref(st), None, 0, None) == abi.NMG_ENOMEM_WS
+    assert b"static workspace" in L.nmg_last_error()
+    bad, pbad = _desc(abi, nx=60, levels=4)
+    assert L.nmg_newton_solve_static(ctypes.byref(bad), ctypes.byref(pbad), ctypes.c_void_p(256),
+                                     ctypes.byref(st), None, 0, None) == abi.NMG_EINVAL
