@@ -427,8 +427,12 @@ def test_coarsest_solve_matches_lapack():
 # ---------------------------------------------------------------------------------------
 
 def test_e1_orders_and_magnitudes_against_table1():
-    """Table 1: third order under refinement; magnitudes within a factor 3 of the printed
-    errors (ghost cells and HLL speeds are not specified in the paper)."""
+    """Table 1: third order under refinement.  Magnitudes: the h errors are 2.0-2.5 times the
+    printed ones and the hu errors 1.4-1.8 times, at every grid; 70% of the h error sits at the
+    bumps (|x| < 5), and prescribing the full state h = 1, hu = 1 in the ghosts of both ends
+    instead changes the h errors by less than 6%, so the excess comes from the interior scheme
+    the paper leaves open (HLL wave speeds), not the boundary reading.  The bands below hold the
+    measured factors with a small margin."""
     rows = _table("e1_table1.txt")
     eh, eq = [], []
     for r in rows:
@@ -439,8 +443,8 @@ def test_e1_orders_and_magnitudes_against_table1():
         hbar = _cell_avg(lambda x: 1.0 / _exact_e1_u(x), pr.x0, pr.dx, n)
         eh.append(np.mean(np.abs(U[0] - hbar)))
         eq.append(np.mean(np.abs(U[1] - 1.0)))
-        assert float(r[1]) / 3 < eh[-1] < float(r[1]) * 3, (n, eh[-1], r[1])
-        assert float(r[3]) / 3 < eq[-1] < float(r[3]) * 3, (n, eq[-1], r[3])
+        assert float(r[1]) / 1.5 < eh[-1] < float(r[1]) * 2.7, (n, eh[-1], r[1])
+        assert float(r[3]) / 1.5 < eq[-1] < float(r[3]) * 2.0, (n, eq[-1], r[3])
     oh = [math.log2(eh[k] / eh[k + 1]) for k in range(3)]
     oq = [math.log2(eq[k] / eq[k + 1]) for k in range(3)]
     assert 2.7 < oh[-1] < 3.4 and 2.7 < oq[-1] < 3.6, (oh, oq)
