@@ -9,10 +9,11 @@ update).  value = B * steps / timed wall time.  Inputs are resident in HBM befor
 region starts.
 
 Also reported: Newton-MG DOF/s, the single-instance solve rate and latency, the full Jacobian
-J5 side by side, the FP32-multigrid form, the uneven batch of 512 instances, the
+J5 side by side, the FP32-multigrid form, the uneven batch of 512 instances, the 2D jump over
+a wedge (1024 x 512 cells, FP64 and FP32 multigrid) solved end to end, the
 continuous-batching server (Poisson arrivals at 200 req/s, and saturated) with p50/p99
 latency, the roofline of the dominant kernel (HIP events on the launch stream) and the CPU
-oracle on a bounded sample of the same workload.
+oracle on a bounded sample of the same workload, run on the host's cores.
 """
 import argparse
 import json
@@ -27,11 +28,22 @@ if ROOT not in sys.path:
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
+# ridge point of the FP64 roofline: a kernel doing fewer FP64 operations per algorithmic HBM
+# byte than this is bound by HBM, more by the FP64 vector units
+RIDGE_FLOP_PER_BYTE = FP64_VECTOR_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
 
 # Algorithmic FP64 operations of one local residual evaluation of eq. (10) (each add, mul, div
 # and sqrt counts one): ten WENO3 reconstructions (22 each), two HLL fluxes (46 each), the
 # two-point Gauss source (36) and the final differences (3).
 FLOPS_LOCAL_RESIDUAL = 10 * 22 + 2 * 46 + 36 + 3
+# FP64 operations the J3 Jacobian kernel performs per interior cell: the H columns (three) each
+# reconstruct H six times, form the source and two HLL fluxes, the Q reconstructions being formed
+# once (4 x 22); the H reconstructions and the source then once more (6 x 22 + 36) for the Q
+# columns, which each reconstruct Q four times and form two fluxes; four operations per column
+# form the difference quotients.  Boundary cells (four per instance) re-evaluate everything.
+FLOPS_JACOBIAN_J3 = (4 * 22) + 3 * (6 * 22 + 36 + 2 * 46 + 3 + 4) + (6 * 22 + 36) + 3 * (4 * 22 + 2 * 46 + 3 + 4)
+# residual kernel: read U 16 and the geometry 56, write R 16 and rn 8 per cell
+BYTES_RESIDUAL = 16 + 56 + 16 + 8
 # Algorithmic HBM bytes per cell and launch (FP64, J3):
 #   Jacobian: read U 16, R 16, rn 8, geometry 7*8 = 56; write J 96, rhs 16 and the coarse
 #   operators (J 96 per coarse cell) of the eight levels built inside its tile (sum over
@@ -50,6 +62,11 @@ BYTES_SMOOTH_PRE_J3 = 96 + 16 + 16 + 8
 BYTES_SMOOTH_FUSED_J3 = 96 + 16 + 16 + 8 + 16 + 8
 
 
+def log(msg):
+    """Progress on stderr (stdout carries the one JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,14 +82,34 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--cpu-instances", type=int, default=3)
+    ap.add_argument("--cpu-instances", type=int, default=2, help="oracle instances per host thread")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration under rocprofv3)")
     ap.add_argument("--vcycle2d-only", action="store_true",
                     help="time only the 2D V-cycle form (1024 x 512 wedge configuration) and print it")
+    ap.add_argument("--wedge2d-only", action="store_true",
+                    help="run only the end-to-end 2D wedge form and print it")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-budget-gib", type=int, default=16)
     return ap.parse_args()
+
+
+def roofline_entry(kernel, bytes_per_launch, flops_per_launch, ms):
+    """Roofline of one kernel from its algorithmic bytes and FP64 operations per launch and its
+    launch time: bound by HBM when its arithmetic intensity is below the FP64 ridge, else by
+    the FP64 vector units; the other resource's use is reported beside it."""
+    gbs = bytes_per_launch / (ms * 1e-3) / 1e9
+    tflops = flops_per_launch / (ms * 1e-3) / 1e12
+    ai = flops_per_launch / bytes_per_launch
+    e = {"kernel": kernel, "flop_per_byte": ai, "ridge_flop_per_byte": RIDGE_FLOP_PER_BYTE,
+         "algorithmic_bytes_per_launch": bytes_per_launch, "algorithmic_flops_per_launch": flops_per_launch}
+    if ai < RIDGE_FLOP_PER_BYTE:
+        e.update(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
+                 fp64_tflops=tflops, fp64_frac=tflops / FP64_VECTOR_TFLOPS)
+    else:
+        e.update(bound="fp64", achieved=tflops, peak=FP64_VECTOR_TFLOPS, unit="TFLOP/s",
+                 frac=tflops / FP64_VECTOR_TFLOPS, hbm_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS)
+    return e
 
 
 def measured_traffic(batch, n):
@@ -226,20 +263,98 @@ def served(args, rate):
     return out
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args):
-    """The oracle as it stands, single-threaded, on a bounded sample of the workload."""
+    """The oracle as it stands on a bounded sample of the workload, its instances spread over
+    the host's cores (one instance per thread at a time; the oracle's C code runs without the
+    interpreter lock), median of three runs."""
+    import statistics
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
-    probs = make_batch(args.cpu_instances, args.n, args.levels, args.variant)
-    t0 = time.perf_counter()
-    its = 0
-    for p in probs:
-        U, it, res, _ = oracle.Oracle1D(p).newton_solve()
-        its += it
-    el = time.perf_counter() - t0
-    return {"value": len(probs) / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(probs)} instances of the benchmark workload (seeds 0..{len(probs) - 1}), "
-                      f"single-threaded FP64 C oracle, {its} Newton steps in {el:.1f} s",
-            "dof_per_s": 2 * args.n * its / el}
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    probs = make_batch(args.cpu_instances * threads, args.n, args.levels, args.variant)
+    oracle.lib()
+
+    def one(p):
+        return oracle.Oracle1D(p).newton_solve()[1]
+
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            its = sum(ex.map(one, probs))
+        runs.append((time.perf_counter() - t0, its))
+    el, its = sorted(runs)[1]
+    return {"value": len(probs) / el, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(probs)} instances of the benchmark workload (seeds 0..{len(probs) - 1}), FP64 C "
+                      f"oracle, {threads} threads across instances, {its} Newton steps in {el:.1f} s "
+                      f"(median of 3 runs: {', '.join(f'{r[0]:.2f}' for r in runs)} s)",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "dof_per_s": 2 * args.n * its / el,
+            "runs_s": [r[0] for r in runs]}
+
+
+def wedge2d_form():
+    """The 2D jump over a wedge (section 5.2.2 rescaled), 1024 x 512 cells, 8 levels, solved
+    from the uniform inflow state to res < 1e-10 in FP64 and with FP32 multigrid; per-kernel
+    launch times; and the error against the oracle's converged state on the 64 x 32 wedge."""
+    import numpy as np
+    import torch
+    import oracle.swe2d
+    from paper_2505_10857_amd import NMG_FP32_MG, NMG_FP64, Solver2D
+    from swe_workloads import wedge_problem
+    prob = wedge_problem(1024, 512)
+    cells = prob.nx * prob.ny
+    out = {"workload": "2D SWE jump over a wedge on [0,40]x[0,30], 1024 x 512 cells, 8 levels, J9, LLF, "
+                       "nu = 20, nu3 = 3, omega = 0.05, eps = 1e-6, from the uniform inflow state to res < 1e-10"}
+    states = {}
+    for name, prec in (("fp64", NMG_FP64), ("fp32mg", NMG_FP32_MG)):
+        s = Solver2D(prob, device="cuda:0", precision=prec, check_every=8, n_max=2000)
+        U = s.state()
+        R, rn, _ = s.residual(U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, hist = s.newton_solve(U, max_hist=2000)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        states[name] = U
+        e = {"solves_per_s": 1.0 / el, "seconds_per_solve": el, "newton_steps": st.iters,
+             "status": st.status, "res": st.res, "ms_per_newton_step": 1e3 * el / max(st.iters, 1),
+             "dof_per_s": 3 * cells * st.iters / el}
+        if name == "fp64":
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(5):
+                s.residual(U)
+            ev[1].record()
+            for _ in range(5):
+                s.jacobian(U, R, rn)
+            ev[2].record()
+            torch.cuda.synchronize()
+            e["residual_ms"] = ev[0].elapsed_time(ev[1]) / 5
+            e["jacobian_j9_ms"] = ev[1].elapsed_time(ev[2]) / 5
+        out[name] = e
+    out["fp32mg"]["max_abs_diff_vs_fp64_gpu"] = float((states["fp32mg"] - states["fp64"]).abs().max())
+    small = wedge_problem(64, 32)
+    Uo, ito, reso, _ = oracle.swe2d.Oracle2D(small).newton_solve()
+    errs = {}
+    for name, prec in (("fp64", NMG_FP64), ("fp32mg", NMG_FP32_MG)):
+        s = Solver2D(small, device="cuda:0", precision=prec, check_every=8)
+        U = s.state()
+        st, _ = s.newton_solve(U)
+        errs[name] = {"max_abs_err_vs_oracle": float(np.abs(U.cpu().numpy() - Uo).max()),
+                      "newton_steps": st.iters, "oracle_newton_steps": ito}
+    out["oracle_check_wedge64x32"] = errs
+    return out
 
 
 def main():
@@ -254,17 +369,22 @@ def main():
     from paper_2505_10857_amd import _abi as A
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibration_copy()
     if args.vcycle2d_only:
         print(json.dumps({"mg2d_vcycle_wedge1024x512": vcycle2d_form()}))
         return
-    if args.calibrate_copy:
-        calibration_copy()
+    if args.wedge2d_only:
+        print(json.dumps({"wedge2d_1024x512": wedge2d_form()}))
+        return
     use_graph = not args.no_graph
     probs = make_batch(args.batch, args.n, args.levels, args.variant)
     solver = BatchSolver1D(probs, device="cuda:0", jac=3, precision=NMG_FP64)
     U0s = solver.states()
     # the plan's schedule is picked by the autotuner on this workload (outside the timed region)
+    log("autotuning the plan options")
     tune_best, tune_times = solver.autotune([u.clone() for u in U0s], trial_steps=3, use_graph=use_graph)
+    log(f"timed region: {args.warmup} warmup + {args.steps} batch solves")
 
     # ---- main timed region -------------------------------------------------------------------
     el, stats, _, _, Ulast = timed_solves(solver, U0s, args.steps, args.warmup, use_graph)
@@ -293,6 +413,7 @@ def main():
         "converged": ok,
     }
 
+    log(f"headline {value:.1f} solves/s; kernel timings")
     # ---- roofline of the dominant kernel: HIP events around its launches on the launch stream --
     el2, stj, jms, jcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_JACOBIAN)
     _, stp, pms, pcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_SMOOTH_PRE)
@@ -312,19 +433,25 @@ def main():
     pre_bytes = BYTES_SMOOTH_PRE_J3 + (0 if fused else 8)   # unfused: dU read in the 2nd cycle
     jac_ms = jms / jac_full       # time of one launch over the whole batch
     pre_ms = pms / pre_full
-    jac_flops = cells * 6 * FLOPS_LOCAL_RESIDUAL
-    out["roofline"] = {
-        "kernel": "k_jacobian_batch<double,3> (FD Jacobian J3, eq. 12-13)",
-        "bound": "alu", "achieved": jac_flops / (jac_ms * 1e-3) / 1e12,
-        "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-        "frac": jac_flops / (jac_ms * 1e-3) / 1e12 / FP64_VECTOR_TFLOPS,
+    jac_flops = cells * FLOPS_JACOBIAN_J3
+    jac_bytes = cells * BYTES_JACOBIAN_J3
+    out["roofline"] = roofline_entry(
+        "k_jacobian_batch<double,3> (FD Jacobian J3, eq. 12-13, with the coarse operators of eq. 17)",
+        jac_bytes, jac_flops, jac_ms)
+    out["roofline"].update({
         "traffic": measured_traffic(args.batch, args.n),
         "avg_launch_ms": jms / max(jcnt, 1), "launches_timed": jcnt, "full_launch_ms": jac_ms,
-        "full_launch_equivalents": jac_full,
-        "algorithmic_flops_per_launch": jac_flops,
-        "hbm_gbs": cells * BYTES_JACOBIAN_J3 / (jac_ms * 1e-3) / 1e9,
-        "share_of_solve_time": jms / (el2 * 1e3),
-    }
+        "full_launch_equivalents": jac_full, "share_of_solve_time": jms / (el2 * 1e3),
+    })
+    _, str_, rms, rcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_RESIDUAL)
+    # the residual runs once at the start of a solve and once per Newton step of every active
+    # instance
+    res_full = sum(s[0] + 1 for st in str_ for s in st) / args.batch
+    res_ms = rms / res_full
+    out["residual_roofline"] = roofline_entry("k_residual_batch (eq. 10 and ||R_j||_1)", cells * BYTES_RESIDUAL,
+                                              cells * FLOPS_LOCAL_RESIDUAL, res_ms)
+    out["residual_roofline"].update({"avg_launch_ms": rms / max(rcnt, 1), "launches_timed": rcnt,
+                                     "full_launch_ms": res_ms})
     out["smoother_roofline"] = {
         "kernel": "k_smooth<double,3> mode 0, finest level (pre-smoothing + restriction)",
         "bound": "hbm", "avg_launch_ms": pms / max(pcnt, 1), "launches_timed": pcnt, "full_launch_ms": pre_ms,
@@ -354,11 +481,13 @@ def main():
         single = BatchSolver1D(probs[:1], device="cuda:0", jac=3, precision=NMG_FP64)
         u1 = single.states()
         e1, st1, _, _, _ = timed_solves(single, u1, 20, 10, use_graph)
+        log("form fp64_single_instance")
         forms["fp64_single_instance"] = {"solves_per_s": 20 / e1, "latency_ms": 1e3 * e1 / 20,
                                          "newton_steps": st1[-1][0][0]}
         # full Jacobian J5, batched
         s5 = BatchSolver1D(probs, device="cuda:0", jac=5, precision=NMG_FP64)
         e5, st5, _, _, _ = timed_solves(s5, s5.states(), args.steps, 5, use_graph)
+        log("form fp64_batch_J5")
         forms["fp64_batch_J5"] = {"solves_per_s": args.batch * args.steps / e5,
                                   "newton_steps": [min(s[0] for s in st5[-1]), max(s[0] for s in st5[-1])]}
         forms["fp64_batch_J3"] = {"solves_per_s": value, "newton_steps": out["newton_steps_per_solve"]}
@@ -366,6 +495,7 @@ def main():
         s32 = BatchSolver1D(probs, device="cuda:0", jac=3, precision=NMG_FP32_MG)
         e32, st32, _, _, U32 = timed_solves(s32, s32.states(), args.steps, 5, use_graph)
         err = max(float((a - b).abs().max()) for a, b in zip(U32, Ulast))
+        log("form fp32mg_batch_J3")
         forms["fp32mg_batch_J3"] = {"solves_per_s": args.batch * args.steps / e32,
                                     "newton_steps": [min(s[0] for s in st32[-1]), max(s[0] for s in st32[-1])],
                                     "max_abs_diff_vs_fp64_gpu": err,
@@ -375,6 +505,7 @@ def main():
         sprobs = [dataclasses.replace(p, recon=1) for p in probs]
         ssurf = BatchSolver1D(sprobs, device="cuda:0", jac=3, precision=NMG_FP64)
         esf, stsf, _, _, Usf = timed_solves(ssurf, ssurf.states(), args.steps, 5, use_graph)
+        log("form fp64_batch_J3_surface")
         forms["fp64_batch_J3_surface"] = {
             "solves_per_s": args.batch * args.steps / esf,
             "newton_steps": [min(s[0] for s in stsf[-1]), max(s[0] for s in stsf[-1])],
@@ -395,6 +526,7 @@ def main():
                           "newton_steps": [min(x[0] for x in last), max(x[0] for x in last)],
                           "converged": sum(1 for x in last if x[1] == 0 and x[2] < 1e-10)}
             del sb
+        log("form fp64_cfg1_nmgm3_vs_newton_sor")
         forms["fp64_cfg1_nmgm3_vs_newton_sor"] = cmp1
         # transcritical hump (q = 1.53, h_out = 0.66): out of reach of plain Newton from the flat
         # surface; nested iteration (Algorithm 3) over the 8 grids 100 .. 12800, batched per grid
@@ -410,6 +542,7 @@ def main():
         torch.cuda.synchronize()
         et = time.perf_counter() - t0
         fin = rep[-1][-1]
+        log("form fp64_batch_trans_nested")
         forms["fp64_batch_trans_nested"] = {
             "solves_per_s": 2 * args.batch / et, "batch": args.batch,
             "newton_steps_finest": [min(x[0] for x in fin), max(x[0] for x in fin)],
@@ -421,6 +554,7 @@ def main():
         su = BatchSolver1D(uprobs, device="cuda:0", jac=3, precision=NMG_FP32_MG)
         eu, stu, _, _, _ = timed_solves(su, su.states(), 3, 2, use_graph)
         ucells = sum(p.n for p in uprobs)
+        log("form fp32mg_uneven512")
         forms["fp32mg_uneven512"] = {
             "solves_per_s": 512 * 3 / eu, "cells_per_batch": ucells,
             "dof_per_s": sum(2 * p.n * st[0] for sts in stu for p, st in zip(uprobs, sts)) / eu,
@@ -428,14 +562,21 @@ def main():
             "converged": all(st[1] == 0 and st[2] < 1e-10 for sts in stu for st in sts)}
         # 2D multigrid at the wedge's size and launch configuration (1024 x 512, 8 levels,
         # nu = 20, omega = 0.05) on a seeded J9-shaped operator
+        log("form mg2d_vcycle_wedge1024x512")
         forms["mg2d_vcycle_wedge1024x512"] = vcycle2d_form()
+        # the same wedge solved end to end (Newton with the 2D residual, J9 and V-cycles)
+        log("form wedge2d_1024x512")
+        forms["wedge2d_1024x512"] = wedge2d_form()
         # continuous-batching server: Poisson arrivals at 200 req/s, N in [512, 32768]
+        log("form served_200rps")
         forms["served_200rps"] = served(args, 200.0)
+        log("form served_saturated")
         forms["served_saturated"] = served(args, 1e7)
         out["forms"] = forms
 
     # ---- CPU oracle ----------------------------------------------------------------------------
     if not args.no_cpu:
+        log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)
 
