@@ -49,6 +49,11 @@ BYTES_RESIDUAL = 16 + 56 + 16 + 8
 #   operators (J 96 per coarse cell) of the eight levels built inside its tile (sum over
 #   l = 1..8 of 2^-l coarse cells per fine cell)
 BYTES_JACOBIAN_J3 = 16 + 16 + 8 + 56 + 96 + 16 + 96 * (1.0 - 2.0 ** -8)
+# the Jacobian launch that also evaluates the residual (the plan's default order): R and rn are
+# not read, and the unperturbed reconstructions and source give R with one more pair of HLL
+# fluxes and the norm
+BYTES_JACOBIAN_J3_FUSED = BYTES_JACOBIAN_J3 - 16 - 8
+FLOPS_JACOBIAN_J3_FUSED = FLOPS_JACOBIAN_J3 + (2 * 46 + 3) + 2
 # HBM traffic of the Jacobian kernel measured with rocprofv3 counters (profiles/), valid while
 # the kernel source is the one it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobian_j3_fp64_hump12800_batch256_traffic.txt")
@@ -112,9 +117,10 @@ def roofline_entry(kernel, bytes_per_launch, flops_per_launch, ms):
     return e
 
 
-def measured_traffic(batch, n):
+def measured_traffic(batch, n, fused=False):
     """HBM bytes per launch of the Jacobian kernel from the committed counter summary, or None
-    if there is none for this workload or the kernel source changed since it was taken."""
+    if there is none for this workload and launch form or the kernel source changed since it
+    was taken."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -125,6 +131,8 @@ def measured_traffic(batch, n):
             kv[k.strip()] = v.strip()
     sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     if kv.get("source_sha256") != sha or kv.get("cells") != str(batch * n):
+        return None
+    if kv.get("fused_residual", "0") != ("1" if fused else "0"):
         return None
     return float(kv["bytes_per_launch"])
 
@@ -406,8 +414,9 @@ def main():
                    "autotuned": {"bottom_cells": tune_best["bottom_cells"],
                                  "smooth_tile": tune_best["smooth_tile"],
                                  "split_finest": tune_best["split_finest"],
-                                 "ms_per_newton_step": {f"bottom{b}_split{sp}_tile{t}": ms
-                                                        for (b, sp, t), ms in tune_times.items()}}},
+                                 "split_residual": tune_best["split_residual"],
+                                 "ms_per_newton_step": {f"bottom{b}_split{sp}_tile{t}_res{r}": ms
+                                                        for (b, sp, t, r), ms in tune_times.items()}}},
         "dof_per_s": dofs,
         "newton_steps_per_solve": [min(newton), max(newton)],
         "converged": ok,
@@ -425,7 +434,9 @@ def main():
     # counted per active instance: the Jacobian runs once per Newton step of an instance, the
     # finest pre-smoothing once per V-cycle (nu3 = 2 per step); "full launches" = that work in
     # units of one launch over the whole batch
-    jac_full = sum(s[0] for st in stj for s in st) / args.batch
+    fused_res = tune_best["split_residual"] == 0
+    # fused order: one Jacobian launch per Newton step plus the one that begins the solve
+    jac_full = sum(s[0] + (1 if fused_res else 0) for st in stj for s in st) / args.batch
     # finest pre-smoothing launches per Newton step: one per V-cycle, or only the first one
     # when the plan runs each later one together with the previous post-smoothing
     pre_per_step = 1 if fused else 2
@@ -433,25 +444,29 @@ def main():
     pre_bytes = BYTES_SMOOTH_PRE_J3 + (0 if fused else 8)   # unfused: dU read in the 2nd cycle
     jac_ms = jms / jac_full       # time of one launch over the whole batch
     pre_ms = pms / pre_full
-    jac_flops = cells * FLOPS_JACOBIAN_J3
-    jac_bytes = cells * BYTES_JACOBIAN_J3
-    out["roofline"] = roofline_entry(
-        "k_jacobian_batch<double,3> (FD Jacobian J3, eq. 12-13, with the coarse operators of eq. 17)",
-        jac_bytes, jac_flops, jac_ms)
+    if fused_res:
+        jac_flops, jac_bytes = cells * FLOPS_JACOBIAN_J3_FUSED, cells * BYTES_JACOBIAN_J3_FUSED
+        jac_name = ("k_jacobian_batch<double,3,false,true> (residual eq. 10 + FD Jacobian J3 eq. 12-13 "
+                    "+ coarse operators eq. 17, one launch)")
+    else:
+        jac_flops, jac_bytes = cells * FLOPS_JACOBIAN_J3, cells * BYTES_JACOBIAN_J3
+        jac_name = "k_jacobian_batch<double,3,false,false> (FD Jacobian J3, eq. 12-13, with the coarse operators of eq. 17)"
+    out["roofline"] = roofline_entry(jac_name, jac_bytes, jac_flops, jac_ms)
     out["roofline"].update({
-        "traffic": measured_traffic(args.batch, args.n),
+        "traffic": measured_traffic(args.batch, args.n, fused_res),
         "avg_launch_ms": jms / max(jcnt, 1), "launches_timed": jcnt, "full_launch_ms": jac_ms,
         "full_launch_equivalents": jac_full, "share_of_solve_time": jms / (el2 * 1e3),
     })
-    _, str_, rms, rcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_RESIDUAL)
-    # the residual runs once at the start of a solve and once per Newton step of every active
-    # instance
-    res_full = sum(s[0] + 1 for st in str_ for s in st) / args.batch
-    res_ms = rms / res_full
-    out["residual_roofline"] = roofline_entry("k_residual_batch (eq. 10 and ||R_j||_1)", cells * BYTES_RESIDUAL,
-                                              cells * FLOPS_LOCAL_RESIDUAL, res_ms)
-    out["residual_roofline"].update({"avg_launch_ms": rms / max(rcnt, 1), "launches_timed": rcnt,
-                                     "full_launch_ms": res_ms})
+    if not fused_res:
+        _, str_, rms, rcnt, _ = timed_solves(solver, U0s, 2, 0, False, A.NMG_K_RESIDUAL)
+        # the residual runs once at the start of a solve and once per Newton step of every
+        # active instance
+        res_full = sum(s[0] + 1 for st in str_ for s in st) / args.batch
+        res_ms = rms / res_full
+        out["residual_roofline"] = roofline_entry("k_residual_batch (eq. 10 and ||R_j||_1)", cells * BYTES_RESIDUAL,
+                                                  cells * FLOPS_LOCAL_RESIDUAL, res_ms)
+        out["residual_roofline"].update({"avg_launch_ms": rms / max(rcnt, 1), "launches_timed": rcnt,
+                                         "full_launch_ms": res_ms})
     out["smoother_roofline"] = {
         "kernel": "k_smooth<double,3> mode 0, finest level (pre-smoothing + restriction)",
         "bound": "hbm", "avg_launch_ms": pms / max(pcnt, 1), "launches_timed": pcnt, "full_launch_ms": pre_ms,
@@ -496,9 +511,25 @@ def main():
         e32, st32, _, _, U32 = timed_solves(s32, s32.states(), args.steps, 5, use_graph)
         err = max(float((a - b).abs().max()) for a, b in zip(U32, Ulast))
         log("form fp32mg_batch_J3")
+        # both forms iterated on to the round-off floor (res < 1e-13), where the 1e-9 bar of the
+        # FP32-multigrid form is defined (at the res < 1e-10 stop the two stop at different
+        # iterates)
+        import dataclasses
+        fl = {}
+        for nm, prc in (("fp64", NMG_FP64), ("fp32mg", NMG_FP32_MG)):
+            fprobs = [dataclasses.replace(p, params=dataclasses.replace(p.params, tol=1e-13, n_max=5000))
+                      for p in probs]
+            sf = BatchSolver1D(fprobs, device="cuda:0", jac=3, precision=prc)
+            Uf = sf.states()
+            stf = sf.solve(Uf, use_graph=use_graph)
+            fl[nm] = (Uf, stf)
+            del sf
+        err_floor = max(float((a - b).abs().max()) for a, b in zip(fl["fp32mg"][0], fl["fp64"][0]))
         forms["fp32mg_batch_J3"] = {"solves_per_s": args.batch * args.steps / e32,
                                     "newton_steps": [min(s[0] for s in st32[-1]), max(s[0] for s in st32[-1])],
                                     "max_abs_diff_vs_fp64_gpu": err,
+                                    "max_abs_diff_vs_fp64_gpu_at_roundoff_floor": err_floor,
+                                    "roundoff_floor_res": max(s[2] for s in fl["fp32mg"][1]),
                                     "converged": all(s[1] == 0 and s[2] < 1e-10 for st in st32 for s in st)}
         # the well-balanced surface reconstruction (WENO3 on H + zbar) on the same batch
         import dataclasses

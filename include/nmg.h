@@ -266,6 +266,10 @@ nmg_status nmg_plan_profile_read(nmg_plan *plan, double *ms, int32_t *launches);
  *     nu3 >= 2 whose instances all use the three-block Jacobian); 1 keeps them apart.
  *   fused_finest: reported by nmg_plan_get_options (1 when that fused launch is in use),
  *     ignored by nmg_plan_set_options.
+ *   split_residual: 0 (default) evaluates the residual of eq. (10) and its cell norms inside the
+ *     Jacobian launch that ends each Newton step (the Jacobian the next step needs; an instance
+ *     that then meets the stopping test leaves it unused); 1 ends each step with a separate
+ *     residual launch and starts the next with the Jacobian, which reads it.
  * Setting options refreshes the plan's device tables (and any captured graph) on its next use;
  * the workspace size does not change.  Set them before nmg_plan_begin / nmg_plan_solve.  An
  * invalid set is rejected with NMG_EINVAL and leaves the plan as it was. */
@@ -274,20 +278,21 @@ typedef struct {
     int32_t fused_finest;
     int32_t smooth_tile;
     int32_t split_finest;
-    int32_t reserved[4];
+    int32_t split_residual;
+    int32_t reserved[3];
 } nmg_plan_options;
 nmg_status nmg_plan_set_options(nmg_plan *plan, const nmg_plan_options *opt);
 nmg_status nmg_plan_get_options(const nmg_plan *plan, nmg_plan_options *opt);
 
 /* Autotuner for the batched form: for every candidate option set (NMG_TUNE_CANDIDATES of them,
  * candidate c: bottom_cells = 256 << (c % 4), split_finest = (c / 4) % 2, smooth_tile =
- * 256 << (c / 8)) it begins the plan's instances from the states U, runs one untimed Newton step
+ * 256 << ((c / 8) % 2), split_residual = c / 16) it begins the plan's instances from the states U, runs one untimed Newton step
  * (with use_graph = 1 it also captures the step graph) and times trial_steps more with HIP
  * events; it keeps the fastest set in the plan and returns it in best (host, may be NULL) and
  * the per-step milliseconds of every candidate in times_ms (host, length NMG_TUNE_CANDIDATES,
  * may be NULL).  The states are restored before it returns (it allocates a device copy of them
  * for the duration of the call).  Synchronises `stream`. */
-#define NMG_TUNE_CANDIDATES 16
+#define NMG_TUNE_CANDIDATES 32
 nmg_status nmg_plan_autotune(nmg_plan *plan, void *ws, size_t ws_bytes, double *const *U,
                              int32_t trial_steps, int32_t use_graph, nmg_plan_options *best,
                              double *times_ms, void *stream);

@@ -81,10 +81,10 @@ class nmg_stats(C.Structure):
 
 class nmg_plan_options(C.Structure):
     _fields_ = [("bottom_cells", C.c_int32), ("fused_finest", C.c_int32), ("smooth_tile", C.c_int32),
-                ("split_finest", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("split_finest", C.c_int32), ("split_residual", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
-NMG_TUNE_CANDIDATES = 16
+NMG_TUNE_CANDIDATES = 32
 
 
 class NmgError(RuntimeError):

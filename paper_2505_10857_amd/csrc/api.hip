@@ -145,6 +145,10 @@ struct nmg_plan {
     int bottom_nt = 1024;                     // its workgroup size
     int smooth_tile = kSmoothTile;            // cells per tile of the tiled multigrid smoother
     int split_finest = 0;                     // 1: no fused finest-level launch between cycles
+    // 0: the residual is evaluated inside the Jacobian launch at the end of each Newton step
+    // (the next step's Jacobian), 1: a separate residual launch ends each step and the Jacobian
+    // starts the next
+    int split_residual = 0;
     size_t tile_cap = 0;                      // tile-table entries reserved (any option fits)
     std::vector<nmg_desc> descs;
     std::vector<nmg_params> params;
@@ -488,6 +492,39 @@ nmg_status enqueue_vcycle(nmg_plan *P, char *ws, const MGArgs &mg, bool zero_ini
 }
 
 // One Newton step of Algorithm 1 for every active instance.  `cap`: being captured into a graph.
+// The Jacobian of the current state and the residual norms behind the stopping test.  Fused
+// (the default): one launch evaluates both (state: null while the Newton states are not yet
+// initialised); split: the residual launch, then the Jacobian reads it.
+nmg_status enqueue_residual_jacobian(nmg_plan *P, char *ws, const MGArgs &mg, hipStream_t s, bool cap)
+{
+    const Tile *rt = tiles_at(P, ws, P->res_t0);
+    double *partial = reinterpret_cast<double *>(ws + P->off_partial);
+    if (!P->split_residual) {
+        ProfScope ps(P, NMG_K_JACOBIAN, s, cap);
+        HIP_TRY(launch_jacobian1d(mg.insts, rt, P->res_nt, nullptr, nullptr, mg, P->prec, P->jac_mask, P->recon, s,
+                                  partial));
+        return NMG_OK;
+    }
+    {
+        ProfScope ps(P, NMG_K_RESIDUAL, s, cap);
+        HIP_TRY(launch_residual1d(mg.insts, rt, P->res_nt, nullptr, mg.state, partial, P->recon, s));
+    }
+    return NMG_OK;
+}
+
+nmg_status enqueue_split_jacobian(nmg_plan *P, char *ws, const MGArgs &mg, hipStream_t s, bool cap)
+{
+    ProfScope ps(P, NMG_K_JACOBIAN, s, cap);
+    HIP_TRY(launch_jacobian1d(mg.insts, tiles_at(P, ws, P->res_t0), P->res_nt, nullptr, nullptr, mg, P->prec,
+                              P->jac_mask, P->recon, s));
+    return NMG_OK;
+}
+
+// One Newton step of Algorithm 1 for every active instance.  Fused order: the coarse operators
+// beyond the Jacobian tile (the finest levels' were built with the Jacobian that ended the
+// previous step), the linear solve and the damped update, then the next state's residual and
+// Jacobian in one launch and the stopping test.  Split order: Jacobian, coarse operators, linear
+// solve and update, residual, stopping test.  Both do the same arithmetic on the same values.
 nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s, bool cap = false)
 {
     MGArgs mg = mg_args(P, ws, true);
@@ -495,11 +532,9 @@ nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s, bool cap = false)
     const Tile *rt = tiles_at(P, ws, P->res_t0);
     NewtonState *state = mg.state;
     double *partial = reinterpret_cast<double *>(ws + P->off_partial);
-    {
-        ProfScope ps(P, NMG_K_JACOBIAN, s, cap);
-        HIP_TRY(launch_jacobian1d(insts, rt, P->res_nt, nullptr, nullptr, mg, P->prec, P->jac_mask, P->recon, s));
-    }
-    nmg_status st = enqueue_setup(P, ws, mg, s, cap, true);
+    nmg_status st;
+    if (P->split_residual && (st = enqueue_split_jacobian(P, ws, mg, s, cap)) != NMG_OK) return st;
+    st = enqueue_setup(P, ws, mg, s, cap, true);
     if (st != NMG_OK) return st;
     if (P->linear == NMG_LINEAR_MG) {
         // with fused finest-level tiles, the post-smoothing of a cycle and the pre-smoothing of
@@ -529,10 +564,7 @@ nmg_status enqueue_step(nmg_plan *P, char *ws, hipStream_t s, bool cap = false)
         const int from_out = P->linear == NMG_LINEAR_SOR && (P->sor_max & 1) ? 1 : 0;
         HIP_TRY(launch_update1d(mg, rt, P->res_nt, from_out, P->prec, s));
     }
-    {
-        ProfScope ps(P, NMG_K_RESIDUAL, s, cap);
-        HIP_TRY(launch_residual1d(insts, rt, P->res_nt, nullptr, state, partial, P->recon, s));
-    }
+    if ((st = enqueue_residual_jacobian(P, ws, mg, s, cap)) != NMG_OK) return st;
     HIP_TRY(launch_res_finalize(insts, P->n, state, partial, 0, s));
     return NMG_OK;
 }
@@ -553,9 +585,13 @@ nmg_status plan_begin(nmg_plan *P, char *ws, size_t ws_bytes, double *const *U, 
         P->graph = nullptr;
     }
     MGArgs mg = mg_args(P, ws, true);
-    const Tile *rt = tiles_at(P, ws, P->res_t0);
     double *partial = reinterpret_cast<double *>(ws + P->off_partial);
-    HIP_TRY(launch_residual1d(mg.insts, rt, P->res_nt, nullptr, nullptr, partial, P->recon, s));
+    // the initial state's residual (and, fused, its Jacobian) for every instance: the Newton
+    // states are initialised only by the stopping test that follows
+    MGArgs all = mg;
+    all.state = nullptr;
+    nmg_status st2 = enqueue_residual_jacobian(P, ws, all, s, false);
+    if (st2 != NMG_OK) return st2;
     HIP_TRY(launch_res_finalize(mg.insts, P->n, mg.state, partial, 1, s));
     return NMG_OK;
 }
@@ -606,13 +642,15 @@ nmg_status plan_steps(nmg_plan *P, char *ws, int steps, int use_graph, hipStream
 
 constexpr int kBottomCandidates[4] = {256, 512, 1024, 2048};
 constexpr int kTileCandidates[2] = {kSmoothTile, kSmoothTileMax};
-static_assert(NMG_TUNE_CANDIDATES == 4 * 2 * 2, "tuner grid: bottom_cells x split_finest x smooth_tile");
+static_assert(NMG_TUNE_CANDIDATES == 4 * 2 * 2 * 2,
+              "tuner grid: bottom_cells x split_finest x smooth_tile x split_residual");
 
 // Rebuild the plan's tables for another option set.  The byte layout does not move (the tile
 // table is reserved for the largest tile count), so a workspace sized for the plan fits every
 // option; device tables and any captured graph are refreshed on the next use.
-nmg_status apply_options(nmg_plan *P, int cells, int split, int tile)
+nmg_status apply_options(nmg_plan *P, int cells, int split, int tile, int split_res)
 {
+    if (split_res != 0 && split_res != 1) return fail(NMG_EINVAL, "split_residual must be 0 or 1");
     bool ok = false;
     for (int c : kBottomCandidates) ok = ok || c == cells;
     if (!ok) return fail(NMG_EINVAL, "bottom_cells must be 256, 512, 1024 or 2048");
@@ -639,6 +677,7 @@ nmg_status apply_options(nmg_plan *P, int cells, int split, int tile)
         return fail(st, err);
     }
     P->total = std::max(P->total, total);
+    P->split_residual = split_res;
     P->tables_ws = nullptr;
     if (P->gexec) { (void)hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
     if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
@@ -668,12 +707,14 @@ nmg_status plan_autotune(nmg_plan *P, char *ws, size_t ws_bytes, double *const *
     HIP_TRY(hipEventCreate(&e1));
     struct FreeEv { hipEvent_t a, b; ~FreeEv() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } evg{e0, e1};
     int best_cells = P->bottom_cells, best_split = P->split_finest, best_tile = P->smooth_tile;
+    int best_res = P->split_residual;
     double best_ms = 1e300;
     // candidate ci: bottom_cells = kBottomCandidates[ci % 4], split_finest = (ci / 4) % 2,
-    // smooth_tile = kTileCandidates[ci / 8]
+    // smooth_tile = kTileCandidates[(ci / 8) % 2], split_residual = ci / 16
     for (int ci = 0; ci < NMG_TUNE_CANDIDATES; ci++) {
-        const int cells = kBottomCandidates[ci % 4], split = (ci / 4) % 2, tile = kTileCandidates[ci / 8];
-        nmg_status st = apply_options(P, cells, split, tile);
+        const int cells = kBottomCandidates[ci % 4], split = (ci / 4) % 2, tile = kTileCandidates[(ci / 8) % 2];
+        const int sres = ci / 16;
+        nmg_status st = apply_options(P, cells, split, tile, sres);
         if (st != NMG_OK) return st;
         P->n_start.assign(P->n, 0);
         if ((st = plan_begin(P, ws, ws_bytes, U, s)) != NMG_OK) return st;
@@ -686,12 +727,12 @@ nmg_status plan_autotune(nmg_plan *P, char *ws, size_t ws_bytes, double *const *
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
         const double per = ms / trial_steps;
         if (times_ms) times_ms[ci] = per;
-        if (per < best_ms) { best_ms = per; best_cells = cells; best_split = split; best_tile = tile; }
+        if (per < best_ms) { best_ms = per; best_cells = cells; best_split = split; best_tile = tile; best_res = sres; }
         for (int k = 0; k < P->n; k++)
             HIP_TRY(hipMemcpyAsync(U[k], save + off[k], sizeof(double) * (off[k + 1] - off[k]),
                                    hipMemcpyDeviceToDevice, s));
     }
-    nmg_status st = apply_options(P, best_cells, best_split, best_tile);
+    nmg_status st = apply_options(P, best_cells, best_split, best_tile, best_res);
     if (st != NMG_OK) return st;
     HIP_TRY(hipStreamSynchronize(s));
     if (best) {
@@ -700,6 +741,7 @@ nmg_status plan_autotune(nmg_plan *P, char *ws, size_t ws_bytes, double *const *
         best->fused_finest = P->fused0.second > 0 ? 1 : 0;
         best->smooth_tile = best_tile;
         best->split_finest = best_split;
+        best->split_residual = best_res;
     }
     return NMG_OK;
 }
@@ -766,7 +808,7 @@ void nmg_plan_destroy(nmg_plan *plan) { delete plan; }
 nmg_status nmg_plan_set_options(nmg_plan *P, const nmg_plan_options *opt)
 {
     if (!P || !opt) return fail(NMG_EINVAL, "null argument");
-    return apply_options(P, opt->bottom_cells, opt->split_finest, opt->smooth_tile);
+    return apply_options(P, opt->bottom_cells, opt->split_finest, opt->smooth_tile, opt->split_residual);
 }
 
 nmg_status nmg_plan_get_options(const nmg_plan *P, nmg_plan_options *opt)
@@ -777,6 +819,7 @@ nmg_status nmg_plan_get_options(const nmg_plan *P, nmg_plan_options *opt)
     opt->fused_finest = P->fused0.second > 0 ? 1 : 0;
     opt->smooth_tile = P->smooth_tile;
     opt->split_finest = P->split_finest;
+    opt->split_residual = P->split_residual;
     return NMG_OK;
 }
 

@@ -156,10 +156,12 @@ hipError_t launch_res_finalize(const Inst1D *insts_dev, int ninst, NewtonState *
                                const double *partial, int init, hipStream_t s);
 hipError_t launch_sum_res(const double *rn, int N, double *res, hipStream_t s);
 // Jacobian: writes FP64 (prec 0) or FP32 (prec 1) blocks with row stride N at J_out (single) or
-// at each instance's level-0 J (batched, via the level table)
+// at each instance's level-0 J (batched, via the level table).  fused_partial (batched only):
+// evaluate the residual in the same launch (the tiles' sums of ||R_j||_1 go to fused_partial,
+// in the order of the tile list) instead of reading R and ||R_j||_1
 hipError_t launch_jacobian1d(const Inst1D *insts_dev, const Tile *tiles, int ntiles,
                              const Inst1D *single, double *J_single, const MGArgs &mg, int prec,
-                             int nb_mask, int recon, hipStream_t s);
+                             int nb_mask, int recon, hipStream_t s, double *fused_partial = nullptr);
 hipError_t launch_coarsen1d(const MGArgs &mg, const Tile *tiles, int ntiles, int prec, hipStream_t s);
 // nt: threads of the bottom workgroup (256, 512 or 1024); it handles levels of up to 2 nt cells
 hipError_t launch_bottom(const MGArgs &mg, const int *inst_list, int n, int zero_init0, int final_update,

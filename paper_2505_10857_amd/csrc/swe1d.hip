@@ -495,13 +495,17 @@ __device__ __forceinline__ void coarse_from_children(const double *f0, const dou
 
 // Jacobian rows of one tile.  With `mg` levels (batched path) the tile also writes the finest
 // right-hand side and the coarse operators of all levels that lie inside the tile (up to
-// eight: 256 -> 1 cells).
-template <typename T, int NB, bool SURF>
+// eight: 256 -> 1 cells).  FUSED: the tile evaluates the residual R_j of its rows itself (the
+// base of every difference quotient, and the finest right-hand side), with the same operations
+// as the residual kernel, instead of reading R and ||R_j||_1; it writes the tile's sum of
+// ||R_j||_1 to *partial_out for the stopping test (every thread of the workgroup calls this).
+template <typename T, int NB, bool SURF, bool FUSED = false>
 __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
-                              const MGArgs *mg, const Level1D *L0)
+                              const MGArgs *mg, const Level1D *L0, double *partial_out = nullptr)
 {
     __shared__ double sH[kTile + 4], sQ[kTile + 4];
     __shared__ double rows[kTile * NB * 4];
+    __shared__ double red[kTile / 64];
     stage_state<true>(I, a, sH, sQ);   // the state, geometry and residual: last use this step
     __syncthreads();
     const int t = threadIdx.x;
@@ -510,18 +514,20 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
     double *myrow = &rows[t * NB * 4];   // this cell's block row, in LDS
 #pragma unroll
     for (int e = 0; e < NB * 4; e++) myrow[e] = 0.0;
+    double n1 = 0.0;   // ||R_j||_1 of this row (FUSED)
     if (j < I.N) {
         double H[5], Q[5];
 #pragma unroll
         for (int p = 0; p < 5; p++) { H[p] = sH[t + p]; Q[p] = sQ[t + p]; }
         const CellGeom G = load_geom<SURF, true>(I, j);
         const CubicGauss W;
-        const double R0 = ldg<true>(&I.R[j]), R1 = ldg<true>(&I.R[I.N + j]), rn = ldg<true>(&I.rn[j]);
-        const double eps = I.eps, ieps = 1.0 / I.eps;
-        if (rhs) {   // the finest level's right-hand side of eq. (16) is R itself
-            rhs[j] = (T)R0;
-            rhs[stride + j] = (T)R1;
+        double R0 = 0.0, R1 = 0.0, rn = 0.0;
+        if (!FUSED) {
+            R0 = ldg<true>(&I.R[j]);
+            R1 = ldg<true>(&I.R[I.N + j]);
+            rn = ldg<true>(&I.rn[j]);
         }
+        const double eps = I.eps, ieps = 1.0 / I.eps;
         const bool interior = j >= 2 && j <= I.N - 3;
         if (interior) {
             // Away from the boundaries the ghosts do not move: a column of H leaves every Q
@@ -532,6 +538,7 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
             if (SURF) to_surface(H, I, j);
             Recon r;
             recon_Q(Q, r);
+            // the H columns' perturbed residuals, kept in the row until R is known
 #pragma unroll 1
             for (int b = 0; b < NB; b++) {
                 const int pp = 2 + b - HW;
@@ -542,13 +549,23 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
                 const double S = source_term<SURF>(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, I.dx, I.g, X[2]);
                 double P0, P1;
                 assemble_residual<SURF>(r, S, G, I.g, P0, P1);
-                double e0 = (P0 - R0) * ieps, e1 = (P1 - R1) * ieps;
+                myrow[(b * 2 + 0) * 2 + 0] = P0;
+                myrow[(b * 2 + 1) * 2 + 0] = P1;
+            }
+            recon_H(H, r);
+            const double S0 = source_term<SURF>(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, I.dx, I.g, H[2]);
+            if (FUSED) {   // the unperturbed reconstructions and source give R itself
+                assemble_residual<SURF>(r, S0, G, I.g, R0, R1);
+                n1 = fabs(R0) + fabs(R1);
+                rn = n1;
+            }
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                double e0 = (myrow[(b * 2 + 0) * 2 + 0] - R0) * ieps, e1 = (myrow[(b * 2 + 1) * 2 + 0] - R1) * ieps;
                 if (b == HW) e0 += I.alpha * rn;
                 myrow[(b * 2 + 0) * 2 + 0] = e0;
                 myrow[(b * 2 + 1) * 2 + 0] = e1;
             }
-            recon_H(H, r);
-            const double S0 = source_term<SURF>(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, I.dx, I.g, H[2]);
 #pragma unroll 1
             for (int b = 0; b < NB; b++) {
                 const int pp = 2 + b - HW;
@@ -564,6 +581,16 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
                 myrow[(b * 2 + 1) * 2 + 1] = e1;
             }
         } else {
+            if (FUSED) {   // R from the ghost-complete unperturbed stencil
+                double Hb[5], Qb[5];
+#pragma unroll
+                for (int p = 0; p < 5; p++) { Hb[p] = H[p]; Qb[p] = Q[p]; }
+                stencil_ghosts<SURF>(Hb, Qb, j, I);
+                if (SURF) to_surface(Hb, I, j);
+                local_residual<SURF>(Hb, Qb, G, W, I.dx, I.g, R0, R1);
+                n1 = fabs(R0) + fabs(R1);
+                rn = n1;
+            }
 #pragma unroll 1
             for (int b = 0; b < NB; b++) {
                 const int i = j + b - HW;
@@ -595,8 +622,16 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
                 }
             }
         }
+        if (rhs) {   // the finest level's right-hand side of eq. (16) is R itself
+            rhs[j] = (T)R0;
+            rhs[stride + j] = (T)R1;
+        }
 #pragma unroll
         for (int e = 0; e < NB * 4; e++) J[e * (long long)stride + j] = (T)myrow[e];
+    }
+    if (FUSED) {
+        const double sum = block_sum(n1, red);
+        if (t == 0 && partial_out) *partial_out = sum;
     }
     if (!mg || L0->coarsest) return;
 
@@ -649,18 +684,21 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
     }
 }
 
-template <typename T, int NB, bool SURF>
-__global__ void __launch_bounds__(kTile) k_jacobian_batch(MGArgs mg, const Tile *tiles)
+// FUSED: the residual is evaluated in the same launch (partial: per-tile sums of ||R_j||_1 in
+// the tile order of the residual's tile list); otherwise R and ||R_j||_1 are read.
+template <typename T, int NB, bool SURF, bool FUSED>
+__global__ void __launch_bounds__(kTile) k_jacobian_batch(MGArgs mg, const Tile *tiles, double *partial)
 {
-    // the last tiles first: the residual launch before this one streamed the same state and
-    // geometry in tile order, so its last tiles' data are still in the memory-side cache
-    const Tile t = tiles[gridDim.x - 1 - blockIdx.x];
+    // the last tiles first: the pass before this one streamed the same state and geometry in
+    // tile order, so its last tiles' data are still in the memory-side cache
+    const int ti = gridDim.x - 1 - blockIdx.x;
+    const Tile t = tiles[ti];
     const Inst1D &I = mg.insts[t.lev];
     if (!inst_active(mg.state, I)) return;
     const Level1D L = mg.levs[I.lev0];
     if (L.nb != NB) return;
     T *base = reinterpret_cast<T *>(mg.mg);
-    jacobian_tile<T, NB, SURF>(I, t.a, base + L.J, L.n, base + L.rhs, &mg, &L);
+    jacobian_tile<T, NB, SURF, FUSED>(I, t.a, base + L.J, L.n, base + L.rhs, &mg, &L, partial + ti);
 }
 
 template <int NB, bool SURF>
@@ -707,36 +745,53 @@ hipError_t launch_sum_res(const double *rn, int N, double *res, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool SURF>
-static void jacobian_launches(const Tile *tiles, int ntiles, const Inst1D *single, double *J_single,
-                              const MGArgs &mg, int prec, int nb_mask, hipStream_t s)
+template <bool SURF, bool FUSED>
+static void jacobian_batch_launches(const Tile *tiles, int ntiles, const MGArgs &mg, int prec, int nb_mask,
+                                    double *partial, hipStream_t s)
 {
-    if (single) {
-        int nt = (single->N + kTile - 1) / kTile;
-        if (single->nb == 5)
-            hipLaunchKernelGGL((k_jacobian_single<5, SURF>), dim3(nt), dim3(kTile), 0, s, *single, J_single);
-        else
-            hipLaunchKernelGGL((k_jacobian_single<3, SURF>), dim3(nt), dim3(kTile), 0, s, *single, J_single);
-        return;
-    }
     // one launch per stencil width present; each tile runs only the one its instance uses
     if (prec == NMG_FP32_MG) {
-        if (nb_mask & 1) hipLaunchKernelGGL((k_jacobian_batch<float, 3, SURF>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
-        if (nb_mask & 2) hipLaunchKernelGGL((k_jacobian_batch<float, 5, SURF>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+        if (nb_mask & 1)
+            hipLaunchKernelGGL((k_jacobian_batch<float, 3, SURF, FUSED>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, partial);
+        if (nb_mask & 2)
+            hipLaunchKernelGGL((k_jacobian_batch<float, 5, SURF, FUSED>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, partial);
     } else {
-        if (nb_mask & 1) hipLaunchKernelGGL((k_jacobian_batch<double, 3, SURF>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
-        if (nb_mask & 2) hipLaunchKernelGGL((k_jacobian_batch<double, 5, SURF>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles);
+        if (nb_mask & 1)
+            hipLaunchKernelGGL((k_jacobian_batch<double, 3, SURF, FUSED>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, partial);
+        if (nb_mask & 2)
+            hipLaunchKernelGGL((k_jacobian_batch<double, 5, SURF, FUSED>), dim3(ntiles), dim3(kTile), 0, s, mg, tiles, partial);
     }
+}
+
+template <bool SURF>
+static void jacobian_single_launch(const Inst1D *single, double *J_single, hipStream_t s)
+{
+    const int nt = (single->N + kTile - 1) / kTile;
+    if (single->nb == 5)
+        hipLaunchKernelGGL((k_jacobian_single<5, SURF>), dim3(nt), dim3(kTile), 0, s, *single, J_single);
+    else
+        hipLaunchKernelGGL((k_jacobian_single<3, SURF>), dim3(nt), dim3(kTile), 0, s, *single, J_single);
 }
 
 hipError_t launch_jacobian1d(const Inst1D *insts_dev, const Tile *tiles, int ntiles,
                              const Inst1D *single, double *J_single, const MGArgs &mg, int prec,
-                             int nb_mask, int recon, hipStream_t s)
+                             int nb_mask, int recon, hipStream_t s, double *fused_partial)
 {
     (void)insts_dev;
-    if (!single && ntiles == 0) return hipSuccess;
-    if (recon == NMG_RECON_SURFACE) jacobian_launches<true>(tiles, ntiles, single, J_single, mg, prec, nb_mask, s);
-    else jacobian_launches<false>(tiles, ntiles, single, J_single, mg, prec, nb_mask, s);
+    const bool surf = recon == NMG_RECON_SURFACE;
+    if (single) {
+        if (surf) jacobian_single_launch<true>(single, J_single, s);
+        else jacobian_single_launch<false>(single, J_single, s);
+        return hipGetLastError();
+    }
+    if (ntiles == 0) return hipSuccess;
+    if (fused_partial) {
+        if (surf) jacobian_batch_launches<true, true>(tiles, ntiles, mg, prec, nb_mask, fused_partial, s);
+        else jacobian_batch_launches<false, true>(tiles, ntiles, mg, prec, nb_mask, fused_partial, s);
+    } else {
+        if (surf) jacobian_batch_launches<true, false>(tiles, ntiles, mg, prec, nb_mask, nullptr, s);
+        else jacobian_batch_launches<false, false>(tiles, ntiles, mg, prec, nb_mask, nullptr, s);
+    }
     return hipGetLastError();
 }
 

@@ -214,17 +214,20 @@ class BatchSolver1D:
         A.check(A.load().nmg_plan_resume(self.plan, _dptr(self.ws), self.ws_bytes, self._ptrs, counts,
                                          C.c_void_p(_stream_ptr())))
 
-    def set_options(self, bottom_cells: int, smooth_tile: int = 0, split_finest: int = 0):
+    def set_options(self, bottom_cells: int, smooth_tile: int = 0, split_finest: int = 0,
+                    split_residual: int = 0):
         opt = A.nmg_plan_options()
         opt.bottom_cells = bottom_cells
         opt.smooth_tile = smooth_tile
         opt.split_finest = split_finest
+        opt.split_residual = split_residual
         A.check(A.load().nmg_plan_set_options(self.plan, C.byref(opt)))
 
     @staticmethod
     def _opt_dict(opt) -> dict:
         return {"bottom_cells": opt.bottom_cells, "smooth_tile": opt.smooth_tile,
-                "split_finest": opt.split_finest, "fused_finest": bool(opt.fused_finest)}
+                "split_finest": opt.split_finest, "fused_finest": bool(opt.fused_finest),
+                "split_residual": opt.split_residual}
 
     def options(self) -> dict:
         opt = A.nmg_plan_options()
@@ -233,12 +236,12 @@ class BatchSolver1D:
 
     @staticmethod
     def tune_candidate(c: int) -> tuple:
-        """(bottom_cells, split_finest, smooth_tile) of autotuner candidate c."""
-        return 256 << (c % 4), (c // 4) % 2, 256 << (c // 8)
+        """(bottom_cells, split_finest, smooth_tile, split_residual) of autotuner candidate c."""
+        return 256 << (c % 4), (c // 4) % 2, 256 << ((c // 8) % 2), c // 16
 
     def autotune(self, Us: List[torch.Tensor], trial_steps: int = 3, use_graph: bool = True):
         """Time every candidate option set on these states (restored afterwards), keep the
-        fastest.  Returns (best options, {(bottom_cells, split_finest, smooth_tile): ms per
+        fastest.  Returns (best options, {(bottom_cells, split_finest, smooth_tile, split_residual): ms per
         Newton step})."""
         ptrs = (C.c_void_p * self.n)(*[u.data_ptr() for u in Us])
         best = A.nmg_plan_options()

@@ -42,7 +42,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(abi.nmg_desc) == 24 + 40 + 4 * 40 + 8 + 7 * 8
     assert ctypes.sizeof(abi.nmg_params) == 5 * 8 + 8 * 4 + 8
     assert ctypes.sizeof(abi.nmg_plan_options) == 8 * 4
-    assert abi.NMG_TUNE_CANDIDATES == 16
+    assert abi.NMG_TUNE_CANDIDATES == 32
 
 
 def _desc(abi, nx=64, levels=3, jac=3):

@@ -1,6 +1,6 @@
 """Plan options and the autotuner of the batched form: every option set (bottom-kernel threshold
 and workgroup size, smoother tile width, fused or separate finest-level launches between
-cycles) gives the same result bit for bit (the kernels do the same arithmetic in the same
+cycles, residual inside the Jacobian launch or separate) gives the same result bit for bit (the kernels do the same arithmetic in the same
 order), and the autotuner restores the states it trials on and keeps the fastest set."""
 import numpy as np
 import pytest
@@ -29,17 +29,18 @@ def test_every_option_set_gives_the_same_solution(prec_name):
     prec = NMG_FP64 if prec_name == "fp64" else NMG_FP32_MG
     probs = _probs()
     ref = None
-    for c in range(16):
-        cells, split, tile = BatchSolver1D.tune_candidate(c)
+    for c in range(32):
+        cells, split, tile, sres = BatchSolver1D.tune_candidate(c)
         s = BatchSolver1D(probs, device=DEV, precision=prec)
-        s.set_options(cells, smooth_tile=tile, split_finest=split)
+        s.set_options(cells, smooth_tile=tile, split_finest=split, split_residual=sres)
         opt = s.options()
-        assert (opt["bottom_cells"], opt["split_finest"], opt["smooth_tile"]) == (cells, split, tile)
+        assert (opt["bottom_cells"], opt["split_finest"], opt["smooth_tile"], opt["split_residual"]) == \
+            (cells, split, tile, sres)
         assert opt["fused_finest"] == (split == 0)
         Us = s.states()
         st = s.solve(Us, use_graph=True)
         out = [u.cpu().numpy() for u in Us]
-        print(prec_name, cells, split, tile, [x[0] for x in st])
+        print(prec_name, cells, split, tile, sres, [x[0] for x in st])
         assert all(x[1] == 0 for x in st)
         if ref is None:
             ref = (out, st)
@@ -59,11 +60,11 @@ def test_autotune_restores_states_and_keeps_a_valid_option():
     print("autotune", best, times)
     assert best["bottom_cells"] in (256, 512, 1024, 2048)
     assert best["smooth_tile"] in (256, 512) and best["split_finest"] in (0, 1)
-    assert len(times) == 16 and all(t > 0 for t in times.values())
-    key = (best["bottom_cells"], best["split_finest"], best["smooth_tile"])
+    assert len(times) == 32 and all(t > 0 for t in times.values())
+    key = (best["bottom_cells"], best["split_finest"], best["smooth_tile"], best["split_residual"])
     assert key == min(times, key=times.get)
     opt = s.options()
-    assert (opt["bottom_cells"], opt["split_finest"], opt["smooth_tile"]) == key
+    assert (opt["bottom_cells"], opt["split_finest"], opt["smooth_tile"], opt["split_residual"]) == key
     for a, b in zip(Us, before):
         assert torch.equal(a, b)
     st = s.solve(Us, use_graph=True)
@@ -75,7 +76,7 @@ def test_bad_option_is_rejected():
     s = BatchSolver1D([config1(0)], device=DEV)
     s.set_options(1024, smooth_tile=512)
     for bad in (dict(bottom_cells=300), dict(bottom_cells=512, smooth_tile=300),
-                dict(bottom_cells=512, split_finest=2)):
+                dict(bottom_cells=512, split_finest=2), dict(bottom_cells=512, split_residual=3)):
         with pytest.raises(NmgError):
             s.set_options(**bad)
         opt = s.options()   # a rejected set leaves the plan as it was

@@ -295,10 +295,48 @@ def test_full_batch_newton_steps_equal_solo_and_repeat():
         assert np.array_equal(a[k], solo), f"instance {k}: batch differs from solo"
 
 
+def _oracle_floor(probs, tol=1e-13):
+    """FP64 oracle solutions iterated to the round-off floor, on host threads (the oracle's C
+    code runs without the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.lib()
+    with ThreadPoolExecutor(max_workers=min(len(probs), 16)) as ex:
+        return list(ex.map(lambda p: oracle.Oracle1D(p).newton_solve(tol=tol, n_max=5000), probs))
+
+
+@pytest.mark.parametrize("seed", [0, 7])
+def test_headline_size_at_roundoff_floor(seed):
+    """The benchmark workload (hump, N = 12800, 8 levels) in FP64 and with FP32 multigrid,
+    iterated to the round-off floor (res < 1e-13), against the FP64 oracle iterated the same
+    way: within 1e-10 (FP64) and 1e-9 (FP32 multigrid).  The difference at the res < 1e-10
+    termination of the benchmark is printed beside it."""
+    from paper_2505_10857_amd import NMG_FP32_MG, NMG_FP64
+    from swe_workloads import config2
+    prob = config2(seed, "sub", n=12800, levels=8)
+    (Uo, ito, reso, _), = _oracle_floor([prob])
+    Ut, _, _, _ = oracle.Oracle1D(prob).newton_solve()
+    for name, prec, bar in (("fp64", NMG_FP64, 1e-10), ("fp32mg", NMG_FP32_MG, 1e-9)):
+        s = _solver(prob, precision=prec, tol=1e-13, n_max=5000)
+        U = s.state()
+        st, _ = s.newton_solve(U)
+        err = np.abs(U.cpu().numpy() - Uo).max()
+        s10 = _solver(prob, precision=prec)
+        U10 = s10.state()
+        s10.newton_solve(U10)
+        err10 = np.abs(U10.cpu().numpy() - Ut).max()
+        print(f"seed {seed} {name}: floor {st.iters} it res {st.res:.2e} (oracle {ito} it {reso:.2e}) "
+              f"|dU| {err:.2e}; at res < 1e-10 termination |dU| {err10:.2e}")
+        assert st.status == 0 and reso < 1e-13
+        assert err <= bar
+
+
 def test_full_uneven_batch_sampled_against_the_oracle():
     """The uneven batch at its full size and launch configuration (512 instances, N from 256 to
-    16384, FP32 multigrid, HIP graph): every instance converges, and the three smallest equal
-    the FP64 oracle's solutions within the FP32-multigrid bar (1e-9)."""
+    16384, FP32 multigrid, HIP graph): every instance converges; then the same batch iterated to
+    the round-off floor (res < 1e-13) agrees with the FP64 oracle's floor within the FP32-multigrid
+    bar (1e-9) on a sample spanning the sizes: the two smallest (256 cells), two of the three
+    largest (16384 cells) and two seeded picks in between."""
+    import dataclasses
     from paper_2505_10857_amd import NMG_FP32_MG, BatchSolver1D
     from swe_workloads import config4_instance
     probs = [config4_instance(i) for i in range(512)]
@@ -306,8 +344,18 @@ def test_full_uneven_batch_sampled_against_the_oracle():
     Us = b.states()
     st = b.solve(Us, use_graph=True)
     assert all(s[1] == 0 and s[2] < 1e-10 for s in st)
-    for k in sorted(range(512), key=lambda k: probs[k].n)[:3]:
-        Uo, ito, reso, _ = oracle.Oracle1D(probs[k]).newton_solve()
-        err = np.abs(Us[k].cpu().numpy() - Uo).max()
-        print(f"instance {k} (N={probs[k].n}): |U - U_oracle| = {err:.2e}, steps {st[k][0]} vs {ito}")
+    by_n = sorted(range(512), key=lambda k: probs[k].n)
+    rng = np.random.default_rng(12)
+    sample = by_n[:2] + [k for k in by_n if probs[k].n == 16384][:2] + [int(k) for k in rng.choice(by_n[2:-3], 2, replace=False)]
+    assert sum(probs[k].n == 16384 for k in sample) == 2
+    fprobs = [dataclasses.replace(p, params=dataclasses.replace(p.params, tol=1e-13, n_max=5000)) for p in probs]
+    bf = BatchSolver1D(fprobs, device=DEV, precision=NMG_FP32_MG)
+    Uf = bf.states()
+    stf = bf.solve(Uf, use_graph=True)
+    ref = _oracle_floor([probs[k] for k in sample])
+    for k, (Uo, ito, reso, _) in zip(sample, ref):
+        err = np.abs(Uf[k].cpu().numpy() - Uo).max()
+        print(f"instance {k} (N={probs[k].n}): floor |U - U_oracle| = {err:.2e}, steps {stf[k][0]} vs {ito}; "
+              f"res {stf[k][2]:.1e} vs {reso:.1e}")
+        assert stf[k][1] == 0 and reso < 1e-13
         assert err <= 1e-9
