@@ -195,15 +195,22 @@ nmg_status nmg_newton_solve_static(const nmg_desc *desc, const nmg_params *param
  * grid with half as many cells, eq. (A.1)-(A.2): Uc [2][nc] -> Uf [2][2 nc] (device).  The
  * first and last coarse cells (the appendix is silent there) average over their halves the
  * quadratic (A.1) of the neighbouring interior cell.  nc >= 3.
- * nmg_nested_solve: Algorithm 3 on a 1D problem given on ngrids nested grids: descs[g] and
- * params[g] describe grid g (g = 0 the finest; grid g has half the cells of grid g-1 and
- * ngrids - g levels, so the coarsest grid is solved by Newton with the direct coarsest solve).
- * U[g] (device, [2][nx_g]) is grid g's state: U[ngrids-1] holds the initial guess on entry;
+ * nmg_interp2d_coarse_to_fine: the same in two dimensions, eq. (A.3), whose formula the text
+ * leaves unfinished: the tensor product of (A.1), so the fine averages are (A.2) along x in each
+ * coarse row and then (A.2) along y, the end cells of both directions as in 1D:
+ * Uc [3][nyc][nxc] -> Uf [3][2 nyc][2 nxc] (device); nxc, nyc >= 3, nyc <= 32767, nxc nyc <= 2^26;
+ * other sizes or null pointers return NMG_EINVAL before any launch.
+ * nmg_nested_solve: Algorithm 3 on a 1D or 2D problem given on ngrids nested grids: descs[g]
+ * and params[g] describe grid g (g = 0 the finest; grid g has half the cells of grid g-1 in
+ * each direction and ngrids - g levels, so the coarsest grid is solved by Newton with the direct
+ * coarsest solve).  U[g] (device, [2][nx_g] or [3][ny_g][nx_g]) is grid g's state: U[ngrids-1]
+ * holds the initial guess on entry;
  * every other grid starts from the interpolation of the next coarser solution.  stats[g]
  * (host) receives each grid's Newton statistics.  Returns the finest grid's status
  * (NMG_ENONFINITE as soon as a grid breaks down).  The workspace must hold
  * nmg_nested_workspace_bytes() (the largest grid's).  Synchronises `stream`. */
 nmg_status nmg_interp_coarse_to_fine(const double *Uc, int32_t nc, double *Uf, void *stream);
+nmg_status nmg_interp2d_coarse_to_fine(const double *Uc, int32_t nxc, int32_t nyc, double *Uf, void *stream);
 size_t nmg_nested_workspace_bytes(const nmg_desc *descs, int32_t ngrids, const nmg_params *params);
 nmg_status nmg_nested_solve(const nmg_desc *descs, int32_t ngrids, const nmg_params *params, void *ws,
                             size_t ws_bytes, double *const *U, nmg_stats *stats, void *stream);

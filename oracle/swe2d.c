@@ -704,3 +704,47 @@ int or2d_newton_solve(const or2d_prob *p, const or2d_params *pp, double *U, doub
     free(R); free(rn); free(J);
     return it;
 }
+
+/* ---- nested iteration: Appendix A in two dimensions (eq. A.3) ------------------------------ */
+
+/* One line of eq. (A.2): the averages over the two halves of each of n coarse cells of the
+ * quadratic (A.1) through the cell and its two neighbours (reading: the first and last cell use
+ * the quadratic centred one cell inward), read with stride `is` and written with stride `os`. */
+static void a2_line(int n, const double *u, int is, double *v, int os)
+{
+    for (int j = 0; j < n; j++) {
+        if (j >= 1 && j <= n - 2) {
+            v[(2 * j) * os] = u[(j - 1) * is] / 8.0 + u[j * is] - u[(j + 1) * is] / 8.0;
+            v[(2 * j + 1) * os] = -u[(j - 1) * is] / 8.0 + u[j * is] + u[(j + 1) * is] / 8.0;
+        } else {
+            const int k = j == 0 ? 1 : n - 2;
+            /* P(xi) = u_k + a xi + b (xi^2 - 1/12), xi in coarse cell widths from the centre of k */
+            const double a = (u[(k + 1) * is] - u[(k - 1) * is]) / 2.0;
+            const double b = (u[(k - 1) * is] - 2.0 * u[k * is] + u[(k + 1) * is]) / 2.0;
+            for (int half = 0; half < 2; half++) {
+                const double lo = (double)(j - k) - 0.5 + 0.5 * half, hi = lo + 0.5;
+                const double m1 = (lo + hi) / 2.0;                      /* mean of xi   */
+                const double m2 = (lo * lo + lo * hi + hi * hi) / 3.0;  /* mean of xi^2 */
+                v[(2 * j + half) * os] = u[k * is] + a * m1 + b * (m2 - 1.0 / 12.0);
+            }
+        }
+    }
+}
+
+/* Fine cell averages of the polynomial of eq. (A.3) from a coarse state [3][nyc][nxc] to
+ * [3][2 nyc][2 nxc].  P is the tensor product of the one-dimensional quadratics (A.1), so its
+ * average over a quarter of a coarse cell is the x average of (A.2) taken in each of the three
+ * coarse rows and then combined along y with the same weights: first every coarse row is
+ * refined in x, then every fine column in y.  nxc, nyc >= 3. */
+void or2d_interp_a3(int nxc, int nyc, const double *Uc, double *Uf)
+{
+    const int nxf = 2 * nxc, nyf = 2 * nyc;
+    double *t = malloc(sizeof(double) * (size_t)nyc * nxf);
+    for (int c = 0; c < 3; c++) {
+        const double *u = Uc + (size_t)c * nyc * nxc;
+        double *v = Uf + (size_t)c * nyf * nxf;
+        for (int j = 0; j < nyc; j++) a2_line(nxc, u + (size_t)j * nxc, 1, t + (size_t)j * nxf, 1);
+        for (int i = 0; i < nxf; i++) a2_line(nyc, t + i, nxf, v + i, nxf);
+    }
+    free(t);
+}

@@ -43,6 +43,7 @@ def _declare(L):
     L.or2d_flux.argtypes = [_dp, C.c_int, C.c_double, _dp]
     L.or2d_eigen.argtypes = [_dp, C.c_int, C.c_double, _dp, _dp]
     L.or2d_newton_solve.argtypes = [P, C.POINTER(OrParams2D), _dp, _dp, C.c_int, _dp]
+    L.or2d_interp_a3.argtypes = [C.c_int, C.c_int, _dp, _dp]
     L.or2d_newton_solve.restype = C.c_int
     L.or2d_vcycles.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, C.c_int,
                                C.c_double, C.c_int, C.c_int, C.c_int]
@@ -220,3 +221,35 @@ def coarse_operators(J, levels):
         out.append(a.reshape(ny >> l, nx >> l, 5, 3, 3).copy())
     L.or2d_mg_free(mg)
     return out
+
+
+def interp_a3(Uc: np.ndarray) -> np.ndarray:
+    """Fine-grid cell averages [3, 2 ny, 2 nx] from a coarse state [3, ny, nx] (Appendix A,
+    eq. A.3: the tensor product of eq. A.2, first along x, then along y)."""
+    from . import lib
+    Uc = np.ascontiguousarray(Uc, dtype=np.float64)
+    _, ny, nx = Uc.shape
+    if nx < 3 or ny < 3:
+        raise ValueError("the interpolation needs at least three coarse cells in each direction")
+    Uf = np.empty((3, 2 * ny, 2 * nx))
+    lib().or2d_interp_a3(nx, ny, _ptr(Uc), _ptr(Uf))
+    return Uf
+
+
+def nested_solve2d(prob, ngrids=None, which=9, smoother=0, **over):
+    """Algorithm 3 in two dimensions: Newton with the dense direct solve on the coarsest of the
+    nested grids (a one-level hierarchy) from the problem's initial state there, then on each
+    finer grid the Newton multigrid iteration with one more level, started from the eq. (A.3)
+    interpolation of the coarser solution.  Returns (U on the finest grid, [(nx, ny, Newton
+    steps, res) per grid, coarsest first])."""
+    from swe_workloads import nested_grids_2d
+    grids = nested_grids_2d(prob, ngrids)
+    U = None
+    report = []
+    for g in range(len(grids) - 1, -1, -1):
+        pg = grids[g]
+        U0 = pg.initial_guess() if U is None else interp_a3(U)
+        Ug, it, res, _ = Oracle2D(pg).newton_solve(U0=U0, which=which, smoother=smoother, **over)
+        report.append((pg.nx, pg.ny, it, res))
+        U = Ug
+    return U, report

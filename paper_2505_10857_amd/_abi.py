@@ -39,6 +39,7 @@ EXPORTS = [
     "nmg_plan_profile", "nmg_plan_profile_read", "nmg_plan_resume", "nmg_plan_set_options",
     "nmg_plan_get_options", "nmg_plan_autotune", "nmg_interp_coarse_to_fine",
     "nmg_nested_workspace_bytes", "nmg_nested_solve", "nmg_newton_solve_static",
+    "nmg_interp2d_coarse_to_fine",
 ]
 
 NMG_STATIC_WS_MIB = 64
@@ -124,6 +125,7 @@ def load(path: str = LIB_PATH):
     L.nmg_plan_steps.argtypes = [vp, vp, C.c_int32, C.c_int32, P(C.c_int32), P(nmg_stats), vp]
     L.nmg_plan_resume.argtypes = [vp, vp, sz, P(vp), P(C.c_int32), vp]
     L.nmg_interp_coarse_to_fine.argtypes = [vp, C.c_int32, vp, vp]
+    L.nmg_interp2d_coarse_to_fine.argtypes = [vp, C.c_int32, C.c_int32, vp, vp]
     L.nmg_nested_workspace_bytes.argtypes = [P(nmg_desc), C.c_int32, P(nmg_params)]
     L.nmg_nested_workspace_bytes.restype = sz
     L.nmg_nested_solve.argtypes = [P(nmg_desc), C.c_int32, P(nmg_params), vp, sz, P(vp), P(nmg_stats), vp]
@@ -142,7 +144,8 @@ def load(path: str = LIB_PATH):
     for nm in ("nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",
                "nmg_newton_solve", "nmg_newton_solve_static", "nmg_plan_create", "nmg_plan_solve", "nmg_plan_begin",
                "nmg_plan_steps", "nmg_plan_resume", "nmg_plan_set_options", "nmg_plan_get_options",
-               "nmg_plan_autotune", "nmg_interp_coarse_to_fine", "nmg_nested_solve"):
+               "nmg_plan_autotune", "nmg_interp_coarse_to_fine", "nmg_interp2d_coarse_to_fine",
+               "nmg_nested_solve"):
         getattr(L, nm).restype = C.c_int32
     _lib = L
     return L

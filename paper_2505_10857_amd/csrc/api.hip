@@ -992,6 +992,15 @@ nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *w
     return NMG_OK;
 }
 
+nmg_status nmg_interp2d_coarse_to_fine(const double *Uc, int32_t nxc, int32_t nyc, double *Uf, void *stream)
+{
+    if (!Uc || !Uf) return fail(NMG_EINVAL, "null argument");
+    if (nxc < 3 || nyc < 3) return fail(NMG_EINVAL, "the interpolation needs at least three coarse cells in each direction");
+    if ((long long)nxc * nyc > (1LL << 26) || nyc > 32767) return fail(NMG_EINVAL, "grid too large");
+    HIP_TRY(launch_interp_a3(Uc, nxc, nyc, Uf, (hipStream_t)stream));
+    return NMG_OK;
+}
+
 nmg_status nmg_interp_coarse_to_fine(const double *Uc, int32_t nc, double *Uf, void *stream)
 {
     if (!Uc || !Uf) return fail(NMG_EINVAL, "null argument");
@@ -1017,18 +1026,25 @@ nmg_status nmg_nested_solve(const nmg_desc *descs, int32_t ngrids, const nmg_par
 {
     if (!descs || !params || !ws || !U || !stats) return fail(NMG_EINVAL, "null argument");
     if (ngrids < 1 || ngrids > kMaxLevels) return fail(NMG_EINVAL, "ngrids must be in [1, 16]");
+    const int dim = descs[0].dim;
+    if (dim != 1 && dim != 2) return fail(NMG_EINVAL, "dim must be 1 or 2");
     for (int g = 0; g < ngrids; g++) {
-        if (descs[g].dim != 1) return fail(NMG_EINVAL, "nested iteration is one-dimensional");
+        if (descs[g].dim != dim) return fail(NMG_EINVAL, "every grid of a nested iteration has the same dim");
         if (!U[g]) return fail(NMG_EINVAL, "null state pointer");
-        if (g > 0 && descs[g].nx * 2 != descs[g - 1].nx)
-            return fail(NMG_EINVAL, "grid g must have half the cells of grid g-1");
+        if (g > 0 && (descs[g].nx * 2 != descs[g - 1].nx || (dim == 2 && descs[g].ny * 2 != descs[g - 1].ny)))
+            return fail(NMG_EINVAL, "grid g must have half the cells of grid g-1 in each direction");
+        if (g > 0 && (descs[g].nx < 3 || (dim == 2 && descs[g].ny < 3)))
+            return fail(NMG_EINVAL, "the interpolation needs at least three coarse cells in each direction");
         if (descs[g].levels != ngrids - g) return fail(NMG_EINVAL, "grid g must have ngrids - g levels");
     }
     if (ws_bytes < nmg_nested_workspace_bytes(descs, ngrids, params))
         return fail(NMG_ENOMEM_WS, "workspace too small");
     hipStream_t s = (hipStream_t)stream;
     for (int g = ngrids - 1; g >= 0; g--) {
-        if (g < ngrids - 1) HIP_TRY(launch_interp_a2(U[g + 1], descs[g + 1].nx, U[g], s));
+        if (g < ngrids - 1) {
+            if (dim == 1) HIP_TRY(launch_interp_a2(U[g + 1], descs[g + 1].nx, U[g], s));
+            else HIP_TRY(launch_interp_a3(U[g + 1], descs[g + 1].nx, descs[g + 1].ny, U[g], s));
+        }
         const nmg_status st = nmg_newton_solve(&descs[g], &params[g], ws, ws_bytes, U[g], &stats[g],
                                                nullptr, 0, stream);
         if (st < 0 && st != NMG_ENONFINITE) return st;

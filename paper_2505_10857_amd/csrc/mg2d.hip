@@ -559,6 +559,58 @@ __global__ void __launch_bounds__(256) k_state2d(const double *partial, int ntil
     else if (S->n >= n_max) { S->active = 0; S->status = NMG_NOT_CONVERGED; }
 }
 
+// ---- nested iteration: Appendix A in two dimensions (eq. A.3) ------------------------------
+
+// Eq. (A.2) from three consecutive coarse values um, u0, up of a line centred at cell k, for
+// half h (0 or 1) of coarse cell j: in the interior j = k and the half's average of the quadratic
+// (A.1) has the weights (1/8, 1, -1/8) or (-1/8, 1, 1/8); the first and last cell of the line
+// (j = 0, k = 1 or j = n-1, k = n-2) average the quadratic centred one cell inward over their
+// half.
+__device__ __forceinline__ double a2_from3(double um, double u0, double up, int j, int k, int h)
+{
+    if (j == k) {
+        if (h == 0) return um / 8.0 + u0 - up / 8.0;
+        return -um / 8.0 + u0 + up / 8.0;
+    }
+    const double a = (up - um) / 2.0;
+    const double b = (um - 2.0 * u0 + up) / 2.0;
+    const double lo = (double)(j - k) - 0.5 + 0.5 * h, hi = lo + 0.5;
+    const double m1 = (lo + hi) / 2.0;                      // mean of xi over the half
+    const double m2 = (lo * lo + lo * hi + hi * hi) / 3.0;  // mean of xi^2
+    return u0 + a * m1 + b * (m2 - 1.0 / 12.0);
+}
+
+__device__ __forceinline__ int a2_centre(int j, int n) { return j >= 1 && j <= n - 2 ? j : (j == 0 ? 1 : n - 2); }
+
+// Fine cell (fi, fj) of component c: the polynomial of eq. (A.3) is the tensor product of the
+// quadratics (A.1), so its average over a quarter of a coarse cell is eq. (A.2) along x in the
+// three coarse rows it needs, then eq. (A.2) along y of those three values (the same operations
+// in the same order as refining every coarse row in x first and every fine column in y after).
+__global__ void __launch_bounds__(256) k_interp_a3(const double *Uc, int nxc, int nyc, double *Uf)
+{
+    const int fi = blockIdx.x * blockDim.x + threadIdx.x, fj = blockIdx.y, c = blockIdx.z;
+    const int nxf = 2 * nxc;
+    if (fi >= nxf) return;
+    const double *u = Uc + (long long)c * nyc * nxc;
+    const int ic = fi >> 1, hx = fi & 1, jc = fj >> 1, hy = fj & 1;
+    const int kx = a2_centre(ic, nxc), ky = a2_centre(jc, nyc);
+    double t[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const double *row = u + (long long)(ky - 1 + q) * nxc;
+        t[q] = a2_from3(row[kx - 1], row[kx], row[kx + 1], ic, kx, hx);
+    }
+    Uf[((long long)c * 2 * nyc + fj) * nxf + fi] = a2_from3(t[0], t[1], t[2], jc, ky, hy);
+}
+
+hipError_t launch_interp_a3(const double *Uc, int nxc, int nyc, double *Uf, hipStream_t s)
+{
+    if (nxc < 3 || nyc < 3 || 2 * (long long)nyc > 65535) return hipErrorInvalidValue;   // grid.y holds the fine rows
+    dim3 grid((2 * nxc + 255) / 256, 2 * nyc, 3);
+    hipLaunchKernelGGL(k_interp_a3, grid, dim3(256), 0, s, Uc, nxc, nyc, Uf);
+    return hipGetLastError();
+}
+
 // ---- launchers ---------------------------------------------------------------------------
 
 #define DISPATCH(prec, KER, grid, block, ...)                                                      \

@@ -187,6 +187,8 @@ hipError_t launch_sor_lex(const MGArgs &mg, int ninst, int nb_max, int zero_init
 hipError_t launch_update1d(const MGArgs &mg, const Tile *tiles, int ntiles, int from_out, int prec, hipStream_t s);
 // Appendix A interpolation of a 1D state [2][nc] to [2][2 nc]
 hipError_t launch_interp_a2(const double *Uc, int nc, double *Uf, hipStream_t s);
+// Appendix A interpolation of a 2D state [3][nyc][nxc] to [3][2 nyc][2 nxc] (eq. A.3)
+hipError_t launch_interp_a3(const double *Uc, int nxc, int nyc, double *Uf, hipStream_t s);
 
 // 2D
 int residual2d_tiles(int Nx, int Ny);

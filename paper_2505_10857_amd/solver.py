@@ -418,6 +418,45 @@ def nested_solve(prob, ngrids: Optional[int] = None, device="cuda", precision: i
     return Us[0], [(g.n, s.iters, s.status, s.res) for g, s in zip(grids, stats)]
 
 
+def interp2d_coarse_to_fine(Uc: torch.Tensor) -> torch.Tensor:
+    """Eq. (A.3) interpolation of a device state [3, nyc, nxc] to [3, 2 nyc, 2 nxc]."""
+    Uc = Uc.contiguous()
+    _, nyc, nxc = Uc.shape
+    Uf = torch.empty((3, 2 * nyc, 2 * nxc), dtype=torch.float64, device=Uc.device)
+    A.check(A.load().nmg_interp2d_coarse_to_fine(_dptr(Uc), nxc, nyc, _dptr(Uf), C.c_void_p(_stream_ptr())))
+    return Uf
+
+
+def nested_solve2d(prob, ngrids: Optional[int] = None, device="cuda", precision: int = A.NMG_FP64,
+                   check_every: int = 1, **param_overrides):
+    """Algorithm 3 on the GPU for a 2D problem: Newton with the dense direct solve on the
+    coarsest grid (one level) from the problem's initial state there, then the Newton multigrid
+    iteration on every finer grid from the eq. (A.3) interpolation of the coarser solution.
+    param_overrides apply to every grid.  Returns (finest state [3, ny, nx] on the device,
+    [(nx, ny, Newton steps, status, res) per grid, finest first])."""
+    import dataclasses
+    from swe_workloads import nested_grids_2d
+    grids = nested_grids_2d(prob, ngrids)
+    ng = len(grids)
+    A.load()
+    devs = [Problem2DDevice(g, device) for g in grids]
+    descs = (A.nmg_desc * ng)(*[d.desc for d in devs])
+    params = (A.nmg_params * ng)(*[params_struct(dataclasses.replace(g.params, **param_overrides),
+                                                 precision, check_every) for g in grids])
+    Us = [torch.empty((3, g.ny, g.nx), dtype=torch.float64, device=device) for g in grids]
+    Us[-1].copy_(torch.tensor(np.ascontiguousarray(grids[-1].initial_guess()), dtype=torch.float64))
+    L = A.load()
+    nbytes = L.nmg_nested_workspace_bytes(descs, ng, params)
+    if nbytes == 0:
+        raise A.NmgError(A.NMG_EINVAL, L.nmg_last_error().decode())
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    ptrs = (C.c_void_p * ng)(*[u.data_ptr() for u in Us])
+    stats = (A.nmg_stats * ng)()
+    st = L.nmg_nested_solve(descs, ng, params, _dptr(ws), nbytes, ptrs, stats, C.c_void_p(_stream_ptr()))
+    A.check(st, ok=(A.NMG_OK, A.NMG_NOT_CONVERGED, A.NMG_ENONFINITE))
+    return Us[0], [(g.nx, g.ny, s.iters, s.status, s.res) for g, s in zip(grids, stats)]
+
+
 class NestedBatch:
     """Algorithm 3 for a batch of 1D problems on the same nested grids: one batched plan per
     grid (every launch covers every instance), the Appendix A interpolation between grids.

@@ -313,6 +313,27 @@ def nested_grids(prob, ngrids: Optional[int] = None):
     return out
 
 
+def nested_grids_2d(prob, ngrids: Optional[int] = None):
+    """The grids of the nested iteration (Algorithm 3) for a 2D problem: grid g (g = 0 the
+    problem itself) has nx / 2^g x ny / 2^g cells and levels - g multigrid levels, the same
+    domain, bottom, boundary data and solver parameters except the smoothing steps, which follow
+    the grid size as in section 5.2 (10 up to 16 cells across, 15 up to 32, 20 beyond, never more
+    than the problem's).  The coarsest grid is solved with the dense direct solve (one level).
+    ngrids defaults to the problem's number of levels."""
+    ng = prob.levels if ngrids is None else ngrids
+    f = 1 << (ng - 1)
+    if ng < 1 or ng > prob.levels or prob.nx % f or prob.ny % f:
+        raise ValueError("ngrids must be in [1, levels] and divide the grid")
+    out = []
+    for g in range(ng):
+        nx, ny = prob.nx >> g, prob.ny >> g
+        nu = min(prob.params.nu1, 10 if nx <= 16 else (15 if nx <= 32 else 20))
+        p = prob.params if g == 0 else dataclasses.replace(prob.params, nu1=nu, nu2=nu)
+        out.append(dataclasses.replace(prob, name=f"{prob.name}/{nx}x{ny}", nx=nx, ny=ny,
+                                       levels=prob.levels - g, params=p))
+    return out
+
+
 def served_request(i: int, seed: int = 0, n_min: int = 512, n_max: int = 32768):
     """Request i of a served stream: a 1D channel drawn like the uneven-batch instances (size
     log-uniform in [n_min, n_max], bump amplitude, discharge, outflow depth, width) from

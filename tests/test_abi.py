@@ -117,6 +117,11 @@ def test_nested_solve_argument_checks():
     descs[2].nx = 64
     assert L.nmg_nested_solve(descs, 3, params, ctypes.c_void_p(1024), 16, U, st, None) == abi.NMG_ENOMEM_WS
     assert L.nmg_interp_coarse_to_fine(ctypes.c_void_p(256), 2, ctypes.c_void_p(512), None) == abi.NMG_EINVAL
+    assert L.nmg_interp2d_coarse_to_fine(ctypes.c_void_p(256), 4, 2, ctypes.c_void_p(512), None) == abi.NMG_EINVAL
+    assert L.nmg_interp2d_coarse_to_fine(None, 4, 4, ctypes.c_void_p(512), None) == abi.NMG_EINVAL
+    descs[1].dim = 2                 # grids of one nested iteration share their dimension
+    assert L.nmg_nested_solve(descs, 3, params, ctypes.c_void_p(1024), ws, U, st, None) == abi.NMG_EINVAL
+    assert b"same dim" in L.nmg_last_error()
 
 
 def test_reconstruction_field_is_checked():
