@@ -31,7 +31,10 @@
  *      normal discharge, DEPTH sets h and copies the momenta.  The bottom side may be EXTRAP for
  *      cell centres x < wall_x and WALL beyond.
  *  Q5  Multicolour smoothing: colour (i + j) mod C, C = 3 on the cross stencil (offsets up to 2),
- *      2 on five-point levels; one smoothing iteration = four colour sweeps (forward, backward,
+ *      2 on five-point levels; on the full 21-cell stencil, whose diagonal neighbours (1, -1)
+ *      share (i + j) mod 3, nine colours (i mod 3) + 3 (j mod 3).  With these colourings no
+ *      two cells of one colour are coupled, so a colour sweep is a simultaneous block-Jacobi
+ *      update of its cells.  One smoothing iteration = four colour sweeps (forward, backward,
  *      forward, backward), the analogue of the four directional sweeps D1-D4.
  */
 #include <math.h>
@@ -537,6 +540,12 @@ static void sor2(or2d_mg *mg, int l, int i, int j, double omega)
     for (int c = 0; c < 3; c++) dU[(j * nx + i) * 3 + c] = (1.0 - omega) * dU[(j * nx + i) * 3 + c] - omega * t[c];
 }
 
+/* colour of cell (i, j) among C (reading Q5) */
+static int colour_of(int i, int j, int C)
+{
+    return C == 9 ? i % 3 + 3 * (j % 3) : (i + j) % C;
+}
+
 /* one smoothing iteration (reading Q5; smoother 1: the sweeps D1-D4 of section 4.2) */
 void or2d_smooth(or2d_mg *mg, int l, double omega, int smoother)
 {
@@ -548,12 +557,12 @@ void or2d_smooth(or2d_mg *mg, int l, double omega, int smoother)
         for (int i = 0; i < nx; i++) for (int j = ny - 1; j >= 0; j--) sor2(mg, l, i, j, omega);       /* D4 */
         return;
     }
-    int C = mg->nb[l] == 5 ? 2 : 3;
+    int C = mg->nb[l] == 5 ? 2 : (mg->nb[l] == 21 ? 9 : 3);
     for (int rep = 0; rep < 2; rep++) {
         for (int c = 0; c < C; c++)
-            for (int j = 0; j < ny; j++) for (int i = 0; i < nx; i++) if ((i + j) % C == c) sor2(mg, l, i, j, omega);
+            for (int j = 0; j < ny; j++) for (int i = 0; i < nx; i++) if (colour_of(i, j, C) == c) sor2(mg, l, i, j, omega);
         for (int c = C - 1; c >= 0; c--)
-            for (int j = 0; j < ny; j++) for (int i = 0; i < nx; i++) if ((i + j) % C == c) sor2(mg, l, i, j, omega);
+            for (int j = 0; j < ny; j++) for (int i = 0; i < nx; i++) if (colour_of(i, j, C) == c) sor2(mg, l, i, j, omega);
     }
 }
 

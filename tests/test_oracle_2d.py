@@ -302,6 +302,85 @@ def test_vcycles_converge_to_dense_solve_on_wedge_operator(smoother):
     assert np.abs(y - x).max() < 1e-7 * np.abs(x).max()
 
 
+def _colour(i, j, nb):
+    return i % 3 + 3 * (j % 3) if nb == 21 else (i + j) % (2 if nb == 5 else 3)
+
+
+@pytest.mark.parametrize("which", [9, 21])
+def test_colourings_leave_no_coupling_within_a_colour(which):
+    """The cross stencil under (i + j) mod 3 and the full stencil under (i mod 3) + 3 (j mod 3):
+    no offset of the stencil joins two cells of one colour; (i + j) mod 3 would not do for the
+    full stencil, whose diagonal (1, -1) keeps i + j."""
+    for di, dj in stencil_offsets(which)[1:]:
+        for i in range(3):
+            for j in range(3):
+                assert _colour(i, j, which) != _colour(i + di, j + dj, which), (di, dj)
+    assert any((di + dj) % 3 == 0 for di, dj in stencil_offsets(21)[1:])
+
+
+@pytest.mark.parametrize("which", [9, 21])
+def test_colour_sweeps_are_block_jacobi_updates_of_the_dense_system(which):
+    """One smoothing iteration of the oracle equals, on the dense matrix of the operator, the
+    schedule of colour updates (colours forward, backward, forward, backward), each a
+    simultaneous block-Jacobi relaxation of the cells of that colour: x_c <- (1 - w) x_c -
+    w D_c^-1 (rhs_c + sum of the off-diagonal blocks times x)."""
+    p, J9, R = _wedge_operator(12, 9)
+    o = Oracle2D(p)
+    U = p.initial_guess()
+    Rr, rn, _ = o.residual(U)
+    J = o.jacobian(U, R=Rr, rn=rn, which=which)
+    A = blocks_to_dense2d(J)
+    nx, ny = p.nx, p.ny
+    rng = np.random.default_rng(4)
+    rhs = rng.standard_normal(3 * nx * ny)
+    x0 = rng.standard_normal(3 * nx * ny) * 0.1
+    omega = 0.7
+    C = 9 if which == 21 else 3
+    col = np.array([_colour(i, j, which) for j in range(ny) for i in range(nx)])
+    D = np.zeros_like(A)
+    for k in range(nx * ny):
+        D[3 * k:3 * k + 3, 3 * k:3 * k + 3] = A[3 * k:3 * k + 3, 3 * k:3 * k + 3]
+    Dinv = np.zeros_like(A)
+    for k in range(nx * ny):
+        Dinv[3 * k:3 * k + 3, 3 * k:3 * k + 3] = np.linalg.inv(A[3 * k:3 * k + 3, 3 * k:3 * k + 3])
+    off = A - D
+    x = x0.copy()
+    order = (list(range(C)) + list(range(C - 1, -1, -1))) * 2
+    for c in order:
+        sel = np.repeat(col == c, 3)
+        t = Dinv @ (rhs + off @ x)
+        x[sel] = (1 - omega) * x[sel] - omega * t[sel]
+    y = smooth2d(J, rhs, x0, iters=1, omega=omega, smoother=0).reshape(-1)
+    assert np.abs(y - x).max() < 1e-12 * np.abs(x).max()
+
+
+def test_nmgm21_and_nmgm9_take_the_same_newton_steps():
+    """Section 5.2: the full and the simplified Jacobian converge almost alike (the linear solver
+    changes, not the discrete equations).  Wedge 16 x 8, 32 x 16: the same Newton step counts,
+    and the two solutions agree to the level the stopping test leaves."""
+    for nx, ny in ((16, 8), (32, 16)):
+        p = wedge_problem(nx, ny)
+        o = Oracle2D(p)
+        U9, it9, r9, _ = o.newton_solve(which=9)
+        U21, it21, r21, _ = o.newton_solve(which=21)
+        assert r9 < 1e-10 and r21 < 1e-10
+        assert abs(it9 - it21) <= max(1, it9 // 10), (nx, it9, it21)
+        assert np.abs(U9 - U21).max() < 1e-8
+
+
+def test_j21_vcycles_converge_to_dense_solve():
+    p = wedge_problem(32, 16)
+    o = Oracle2D(p)
+    U = p.initial_guess()
+    R, rn, _ = o.residual(U)
+    J = o.jacobian(U, R=R, rn=rn, which=21)
+    A = blocks_to_dense2d(J)
+    rhs = np.transpose(R, (1, 2, 0)).reshape(-1)
+    x = np.linalg.solve(A, -rhs)
+    y = vcycles2d(J, rhs, None, levels=3, ncycles=12, omega=0.05, nu1=10, nu2=10).reshape(-1)
+    assert np.abs(y - x).max() < 1e-7 * np.abs(x).max()
+
+
 def test_coarsest_dense_solve_matches_lapack():
     p, J, R = _wedge_operator(8, 4)
     A = blocks_to_dense2d(J)
