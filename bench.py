@@ -92,6 +92,8 @@ def parse():
                     help="run one 256 MiB device copy first (counter calibration under rocprofv3)")
     ap.add_argument("--vcycle2d-only", action="store_true",
                     help="time only the 2D V-cycle form (1024 x 512 wedge configuration) and print it")
+    ap.add_argument("--nmgm21-only", action="store_true",
+                    help="run only the NMGM-21 against NMGM-9 form (Table 5 assembly times, wedge solves)")
     ap.add_argument("--wedge2d-only", action="store_true",
                     help="run only the end-to-end 2D wedge form and print it")
     ap.add_argument("--served-requests", type=int, default=400)
@@ -365,6 +367,53 @@ def wedge2d_form():
     return out
 
 
+def nmgm21_form():
+    """NMGM-21 against NMGM-9 (section 4.1, Table 5's comparison): the time of one Jacobian
+    assembly, full J21 against simplified J9, on the parabolic bump at Table 5's three grids and on
+    the 1024 x 512 wedge (mean over 20 launches after 3 warm-up launches, HIP events on the
+    launching stream, FP64 blocks, residual and norms given); and the 1024 x 512 wedge solved to
+    res < 1e-10 by both (Newton steps, seconds, the largest state difference)."""
+    import torch
+    from paper_2505_10857_amd import NMG_FP64, Solver2D
+    from swe_workloads import parabolic_bump_2d, wedge_problem
+    out = {"assembly_ms": {}}
+    for name, prob in (("bump16x8", parabolic_bump_2d(16, 8)), ("bump32x16", parabolic_bump_2d(32, 16)),
+                       ("bump64x32", parabolic_bump_2d(64, 32)), ("wedge1024x512", wedge_problem(1024, 512))):
+        row = {}
+        for jac in (9, 21):
+            s = Solver2D(prob, device="cuda:0", jac=jac)
+            U = s.state()
+            R, rn, _ = s.residual(U)
+            for _ in range(3):
+                s.jacobian(U, R, rn)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(20):
+                s.jacobian(U, R, rn)
+            ev[1].record()
+            torch.cuda.synchronize()
+            row[f"J{jac}"] = ev[0].elapsed_time(ev[1]) / 20
+        row["ratio_J21_over_J9"] = row["J21"] / row["J9"]
+        out["assembly_ms"][name] = row
+    prob = wedge_problem(1024, 512)
+    states = {}
+    for jac in (9, 21):
+        log(f"form nmgm21_vs_nmgm9: wedge 1024 x 512 solve with J{jac}")
+        s = Solver2D(prob, device="cuda:0", precision=NMG_FP64, check_every=8, n_max=2000, jac=jac)
+        U = s.state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, _ = s.newton_solve(U)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        states[jac] = U
+        out[f"wedge1024x512_nmgm{jac}"] = {"seconds_per_solve": el, "newton_steps": st.iters, "status": st.status,
+                                           "res": st.res, "ms_per_newton_step": 1e3 * el / max(st.iters, 1)}
+    out["wedge1024x512_max_abs_diff_nmgm21_vs_nmgm9"] = float((states[21] - states[9]).abs().max())
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -384,6 +433,9 @@ def main():
         return
     if args.wedge2d_only:
         print(json.dumps({"wedge2d_1024x512": wedge2d_form()}))
+        return
+    if args.nmgm21_only:
+        print(json.dumps({"nmgm21_vs_nmgm9": nmgm21_form()}))
         return
     use_graph = not args.no_graph
     probs = make_batch(args.batch, args.n, args.levels, args.variant)
@@ -598,6 +650,8 @@ def main():
         # the same wedge solved end to end (Newton with the 2D residual, J9 and V-cycles)
         log("form wedge2d_1024x512")
         forms["wedge2d_1024x512"] = wedge2d_form()
+        log("form nmgm21_vs_nmgm9")
+        forms["nmgm21_vs_nmgm9"] = nmgm21_form()
         # continuous-batching server: Poisson arrivals at 200 req/s, N in [512, 32768]
         log("form served_200rps")
         forms["served_200rps"] = served(args, 200.0)

@@ -20,7 +20,9 @@
  *    dR_j^l / dU_i^m with i = j + b - nb/2; nb = 3 (simplified J3) or 5 (full J5).
  *    Blocks whose column cell lies outside the grid are zero.
  *  - 2D Jacobian J9: [9][3][3][ny][nx], blocks ordered (centre, x-2, x-1, x+1, x+2, y-2, y-1,
- *    y+1, y+2) following eq. (21).
+ *    y+1, y+2) following eq. (21).  J21 (the full stencil): [21][3][3][ny][nx], the nine cross
+ *    blocks first, then (x-2, x-1, x+1, x+2) on row y-1, the same on row y+1, then (x-1, y-2),
+ *    (x-1, y+2), (x+1, y-2), (x+1, y+2).  Blocks whose column cell lies outside the grid are zero.
  */
 #ifndef NMG_H
 #define NMG_H
@@ -72,7 +74,10 @@ typedef struct {
  *   levels = 1 (1D, jac = 3) solves the regularised system directly (Algorithm 3, step 4).
  *   Newton-SOR plans (params->linear != NMG_LINEAR_MG) build no hierarchy and skip these
  *   level checks.
- * jac = 3 or 5 (1D), 9 (2D): which Jacobian blocks are assembled (section 3.3 / 4.1).  On very
+ * jac = 3 or 5 (1D), 9 or 21 (2D): which Jacobian blocks are assembled (section 3.3 / 4.1; 21
+ *   is the full 2D stencil of NMGM-21, whose block SOR on the finest level uses nine colours
+ *   (i mod 3) + 3 (j mod 3) since its diagonal neighbours share (i + j) mod 3; the coarse
+ *   levels keep the five-point operators of eq. (24) either way).  On very
  *   fine 1D grids the three-block Newton iteration itself can fail where J5 converges: on a
  *   smooth hump flow it converged up to 2^19 cells and ended non-finite from 2^21 cells, where
  *   J5 took 14-16 steps; such a solve reports NMG_ENONFINITE.
@@ -150,7 +155,7 @@ nmg_status nmg_residual(const nmg_desc *desc, const double *U, double *R, double
 
 /* Finite-difference Jacobian of eq. (12) with the regularisation alpha*||R_j||_1*I of eq. (13),
  * assembled on the reduced stencil of section 3.3 (J3; desc->jac = 5 gives J5) or section 4.1
- * (J9).  R and rn must be nmg_residual's output for the same U.  J (device, FP64) receives the
+ * (J9; desc->jac = 21 gives the full J21).  R and rn must be nmg_residual's output for the same U.  J (device, FP64) receives the
  * blocks in the layout above. */
 nmg_status nmg_jacobian_assemble_simplified(const nmg_desc *desc, const nmg_params *params,
                                             const double *U, const double *R, const double *rn,

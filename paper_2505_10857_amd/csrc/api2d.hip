@@ -6,7 +6,8 @@
 //   partial  : double[residual tiles]      (per-tile sums of ||R_ij||_1)
 //   hist     : double[max_hist]
 //   R, rn    : double [3][ny][nx], [ny][nx]
-//   mg       : per level: J [nb*9][M_l], Dinv [9][M_l], rhs [3][M_l], dU [3][M_l]
+//   mg       : per level: J [nb*9][M_l], Dinv [9][M_l], rhs [3][M_l], dU [3][M_l] (nb = 9 or 21 on
+//              the finest level, 5 below)
 //              in double (NMG_FP64) or float (NMG_FP32_MG), cells in the level's colour-blocked
 //              order (M_l slots, Perm2D); the caller's arrays stay in the natural order
 //   lu       : LU factors and row permutation of the coarsest operator (double [M][M], int [M])
@@ -52,7 +53,7 @@ nmg_status check2d(const nmg_desc *d, const nmg_params *p, bool need_geometry = 
     if ((long long)(d->nx / f) * (d->ny / f) > kMaxCoarse2D)
         return set_error(NMG_EINVAL, "coarsest 2D level has more than 40 cells; add levels");
     if ((long long)d->nx * d->ny > (1LL << 28)) return set_error(NMG_EINVAL, "grid too large");
-    if (d->jac != 9) return set_error(NMG_EINVAL, "2D jac must be 9");
+    if (d->jac != 9 && d->jac != 21) return set_error(NMG_EINVAL, "2D jac must be 9 or 21");
     if (d->recon != NMG_RECON_CONSERVED) return set_error(NMG_EINVAL, "2D problems take recon = 0");
     if (need_geometry && (!d->bx_gp || !d->by_gp)) return set_error(NMG_EINVAL, "null geometry pointer");
     if (!(d->x1 > d->x0) || !(d->y1 > d->y0)) return set_error(NMG_EINVAL, "empty domain");
@@ -118,8 +119,9 @@ nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p, bool need_
         memset(&L, 0, sizeof(L));
         L.nx = d->nx >> l;
         L.ny = d->ny >> l;
-        L.nb = l == 0 ? 9 : 5;
-        L.P = make_perm2d(L.nx, L.ny, l == 0 ? 3 : 2);   // colours of the cross / five-point stencil
+        L.nb = l == 0 ? d->jac : 5;
+        // colours of the cross (3), the full stencil (9) or the five-point stencil (2)
+        L.P = make_perm2d(L.nx, L.ny, l == 0 ? (d->jac == 21 ? 9 : 3) : 2);
         const long long n = L.P.M;
         L.J = e; e += (long long)L.nb * 9 * n;
         L.Dinv = e; e += 9 * n;
@@ -209,7 +211,7 @@ nmg_status newton_step(const Plan2D &P, char *w, double *U, hipStream_t s)
     const Level2D &L0 = P.L[0];
     const long long n0 = (long long)L0.nx * L0.ny;
     NewtonState *S = (NewtonState *)(w + P.off_state);
-    HIP_TRY2(launch_jacobian2d(I, L0.P, mgb + vsz * L0.J, mgb + vsz * L0.rhs, mgb + vsz * L0.Dinv, P.prec, s));
+    HIP_TRY2(launch_jacobian2d(I, L0.P, mgb + vsz * L0.J, mgb + vsz * L0.rhs, mgb + vsz * L0.Dinv, P.prec, s, L0.nb));
     nmg_status st = coarsen_all(P, mgb, s);
     if (st != NMG_OK) return st;
     HIP_TRY2(launch_fill(mgb + vsz * L0.dU, P.prec, 3 * L0.P.M, s));
@@ -259,7 +261,7 @@ nmg_status jacobian2d(const nmg_desc *d, const nmg_params *p, const double *U, c
     I.U = const_cast<double *>(U);
     I.R = const_cast<double *>(R);
     I.rn = const_cast<double *>(rn);
-    HIP_TRY2(launch_jacobian2d(I, make_perm2d(d->nx, d->ny, 1), J, nullptr, nullptr, NMG_FP64, s));
+    HIP_TRY2(launch_jacobian2d(I, make_perm2d(d->nx, d->ny, 1), J, nullptr, nullptr, NMG_FP64, s, d->jac));
     return NMG_OK;
 }
 
@@ -275,7 +277,7 @@ nmg_status vcycle2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_
     const size_t vsz = P.prec == NMG_FP32_MG ? 4 : 8;
     const Level2D &L0 = P.L[0];
     if (setup) {
-        HIP_TRY2(launch_permute2d(J, NMG_FP64, mgb + vsz * L0.J, P.prec, L0, 81, 1, s));
+        HIP_TRY2(launch_permute2d(J, NMG_FP64, mgb + vsz * L0.J, P.prec, L0, 9 * L0.nb, 1, s));
         HIP_TRY2(launch_dinv2d((const double *)J, mgb + vsz * L0.Dinv, L0, P.prec, s));
         if ((st = coarsen_all(P, mgb, s)) != NMG_OK) return st;
     }

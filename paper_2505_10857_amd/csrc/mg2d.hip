@@ -27,18 +27,12 @@ __device__ __forceinline__ double lds2(const T *p)
     return (double)*p;
 }
 
-// stencil offsets: the cross of eq. (21) on the finest level, five points below
+// stencil offsets: the cross of eq. (21) or the full 21 cells on the finest level, five points
+// below (stencil_dx / stencil_dy)
 __device__ __forceinline__ void stencil_off(int nb, int b, int &di, int &dj)
 {
-    if (nb == 9) {
-        const int ox[9] = {0, -2, -1, 1, 2, 0, 0, 0, 0};
-        const int oy[9] = {0, 0, 0, 0, 0, -2, -1, 1, 2};
-        di = ox[b]; dj = oy[b];
-    } else {
-        const int ox[5] = {0, -1, 1, 0, 0};
-        const int oy[5] = {0, 0, 0, -1, 1};
-        di = ox[b]; dj = oy[b];
-    }
+    di = stencil_dx(nb, b);
+    dj = stencil_dy(nb, b);
 }
 
 __device__ __forceinline__ int find_off(int nb, int di, int dj)
@@ -112,23 +106,31 @@ __global__ void k_coarsen2d(T *mg, Level2D Lf, Level2D Lc)
     for (int e = 0; e < 9; e++) mg[Lc.Dinv + e * nc + cc] = (T)B[e];
 }
 
-// `reps` consecutive passes of eq. (22) over the cells with (i + j) mod C == colour on one level
-// with the NB-block stencil (C = 3 colours for the nine-block cross, 2 for five points), thread p
-// taking slot p of that colour's block (row p / W, k-th cell of the colour in the row).  Passes
+// `reps` consecutive passes of eq. (22) over the cells of one colour on one level with the
+// NB-block stencil (C = 3 colours (i + j) mod 3 for the nine-block cross, 2 for five points, 9
+// colours (i mod 3) + 3 (j mod 3) for the full 21 cells), thread p taking slot p of that colour's
+// block (row p / W, k-th cell of the colour in the row).  Passes
 // of one colour in a row see the same neighbour values, so the off-diagonal sum and D^{-1} r are
 // formed once and the relaxation is applied `reps` times, each result rounded to the storage
 // type as if it had been stored between the passes.  The stencil is unrolled so that every load
 // of the cell's row is issued up front; neighbours outside the grid read the cell's own slot and
 // are left out of the sum.
 template <typename T, int NB, bool STREAM = false>
+__device__ __forceinline__ void smooth_slot21(T *mg, const Level2D &L, int colour, double omega, int reps, long long p);
+
+template <typename T, int NB, bool STREAM = false>
 __device__ __forceinline__ void smooth_slot(T *mg, const Level2D &L, int colour, double omega, int reps, long long p)
 {
+    if constexpr (NB == 21) {
+        smooth_slot21<T, NB, STREAM>(mg, L, colour, omega, reps, p);
+        return;
+    } else {
     constexpr int C = NB == 9 ? 3 : 2;
     const int W = L.P.W;
     const int j = (int)(p / W), k = (int)(p - (long long)j * W);
     const int i = ((colour - j) % C + C) % C + C * k;
     if (i >= L.nx) return;
-    const long long n = L.P.M, cc = (long long)colour * L.ny * W + p;
+    const long long n = L.P.M, cc = (long long)colour * L.P.ny * W + p;
     const T *Jr = mg + L.J + cc;
     const T *Ur = mg + L.dU;
     double x[NB][3];
@@ -171,13 +173,60 @@ __device__ __forceinline__ void smooth_slot(T *mg, const Level2D &L, int colour,
         for (int q = 0; q < reps; q++) d = (T)((1.0 - omega) * (double)d - omega * t[c]);
         mg[L.dU + c * n + cc] = d;
     }
+    }
+}
+
+// The same pass on the full 21-cell stencil with nine colours: thread p is cell
+// (3 (p mod W) + colour mod 3, 3 (p / W) + colour / 3).  The off-diagonal sum runs block by block
+// in stencil order (the order of eq. 22's sum as the oracle forms it), each block's three
+// products added before the block joins the sum; the blocks' loads are independent of the sum,
+// so they issue ahead of it.
+template <typename T, int NB, bool STREAM>
+__device__ __forceinline__ void smooth_slot21(T *mg, const Level2D &L, int colour, double omega, int reps, long long p)
+{
+    const int W = L.P.W;
+    const int jr = (int)(p / W), k = (int)(p - (long long)jr * W);
+    const int i = 3 * k + colour % 3, j = 3 * jr + colour / 3;
+    if (i >= L.nx || j >= L.ny) return;
+    const long long n = L.P.M, cc = (long long)colour * L.P.ny * W + p;
+    const T *Jr = mg + L.J + cc;
+    const T *Ur = mg + L.dU;
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) r[c] = ld2(mg + L.rhs, c * n + cc);
+#pragma unroll
+    for (int b = 1; b < 21; b++) {
+        int di, dj;
+        stencil_off(21, b, di, dj);
+        const int pi = i + di, pj = j + dj;
+        const bool ok = pi >= 0 && pi < L.nx && pj >= 0 && pj < L.ny;
+        const long long q = ok ? perm2d(L.P, pi, pj) : cc;
+        const double x0 = (double)Ur[q], x1 = (double)Ur[n + q], x2 = (double)Ur[2 * n + q];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const double a = lds2<STREAM>(Jr + (b * 9 + c * 3 + 0) * n) * x0 + lds2<STREAM>(Jr + (b * 9 + c * 3 + 1) * n) * x1 +
+                             lds2<STREAM>(Jr + (b * 9 + c * 3 + 2) * n) * x2;
+            if (ok) r[c] = r[c] + a;
+        }
+    }
+    double t[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+        t[c] = lds2<STREAM>(mg + L.Dinv + (c * 3 + 0) * n + cc) * r[0] + lds2<STREAM>(mg + L.Dinv + (c * 3 + 1) * n + cc) * r[1] +
+               lds2<STREAM>(mg + L.Dinv + (c * 3 + 2) * n + cc) * r[2];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        T d = mg[L.dU + c * n + cc];
+        for (int q = 0; q < reps; q++) d = (T)((1.0 - omega) * (double)d - omega * t[c]);
+        mg[L.dU + c * n + cc] = d;
+    }
 }
 
 template <typename T, int NB, bool STREAM>
 __global__ void __launch_bounds__(256) k_smooth2d_pass(T *mg, Level2D L, int colour, double omega, int reps)
 {
     const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (p >= (long long)L.ny * L.P.W) return;
+    if (p >= (long long)L.P.ny * L.P.W) return;
     smooth_slot<T, NB, STREAM>(mg, L, colour, omega, reps, p);
 }
 
@@ -437,7 +486,7 @@ template <typename T>
 __device__ void bottom_smooth(T *mg, const Level2D &L, int nu, double omega)
 {
     const int C = L.P.C;
-    const long long slots = (long long)L.ny * L.P.W;
+    const long long slots = (long long)L.P.ny * L.P.W;
     int cur = -1, run = 0;
     for (int it = 0; it <= nu; it++) {
         for (int half = 0; half < 4; half++)
@@ -448,6 +497,7 @@ __device__ void bottom_smooth(T *mg, const Level2D &L, int nu, double omega)
                 if (run > 0) {
                     for (long long p = threadIdx.x; p < slots; p += blockDim.x) {
                         if (L.nb == 9) smooth_slot<T, 9>(mg, L, cur, omega, run, p);
+                        else if (L.nb == 21) smooth_slot<T, 21>(mg, L, cur, omega, run, p);
                         else smooth_slot<T, 5>(mg, L, cur, omega, run, p);
                     }
                     __syncthreads();
@@ -629,10 +679,22 @@ hipError_t launch_coarsen2d(void *mg, const Level2D &Lf, const Level2D &Lc, int 
 hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, int reps, double omega, int prec,
                                hipStream_t s)
 {
-    const long long slots = (long long)L.ny * L.P.W;
+    const long long slots = (long long)L.P.ny * L.P.W;
     dim3 grid((unsigned)((slots + 255) / 256));
-    if (L.P.C != (L.nb == 9 ? 3 : 2)) return hipErrorInvalidValue;
-    if (L.nb == 9) {
+    if (L.P.C != (L.nb == 9 ? 3 : (L.nb == 21 ? 9 : 2))) return hipErrorInvalidValue;
+    if (L.nb == 21) {
+        // nine colours: a colour's rows come back only after the eight others have streamed
+        // theirs, so when the operator exceeds the memory-side cache every pass streams
+        const size_t vsz = prec == NMG_FP32_MG ? 4 : 8;
+        const bool stream = (size_t)L.nb * 9 * (size_t)L.P.M * vsz > kMemCacheBytes;
+        if (prec == NMG_FP32_MG) {
+            if (stream) hipLaunchKernelGGL((k_smooth2d_pass<float, 21, true>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
+            else hipLaunchKernelGGL((k_smooth2d_pass<float, 21, false>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
+        } else {
+            if (stream) hipLaunchKernelGGL((k_smooth2d_pass<double, 21, true>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
+            else hipLaunchKernelGGL((k_smooth2d_pass<double, 21, false>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
+        }
+    } else if (L.nb == 9) {
         // finest level: the symmetric schedule returns to colour 1 every other run and to colours
         // 0 and 2 every fourth.  When the level's operator is larger than the memory-side cache,
         // colours 0 and 2 are evicted before they come back, so their passes stream their rows

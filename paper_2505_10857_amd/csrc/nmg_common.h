@@ -109,17 +109,20 @@ struct Inst2D {
     double alpha, eps;
 };
 
-// Colour-blocked cell order of a 2D level: the cells of colour c = (i + j) mod C are stored
-// together, row by row, so that a colour pass of the smoother reads contiguous data.  Cell
-// (i, j) sits at c*ny*W + j*W + (i - i_c(j)) / C, i_c(j) the first column of colour c in row j and
-// W = ceil(nx / C) slots per row and colour; C = 1 is the natural order j*nx + i.
+// Colour-blocked cell order of a 2D level: the cells of one colour are stored together, row by
+// row, so that a colour pass of the smoother reads contiguous data.  C = 2 or 3: colour
+// c = (i + j) mod C, cell (i, j) at c*ny*W + j*W + (i - i_c(j)) / C, i_c(j) the first column of
+// colour c in row j and W = ceil(nx / C) slots per row and colour.  C = 9 (the full 21-cell
+// stencil): colour c = (i mod 3) + 3 (j mod 3), cell (i, j) at c*ceil(ny/3)*W + (j/3)*W + i/3 with
+// W = ceil(nx / 3).  C = 1 is the natural order j*nx + i.
 struct Perm2D {
-    int C, W, ny, pad;
+    int C, W, ny, pad;  // ny: rows per colour (ny of the level, ceil(ny / 3) when C = 9)
     long long M;       // slots per array: C * ny * W
 };
 
 __host__ __device__ inline long long perm2d(const Perm2D &P, int i, int j)
 {
+    if (P.C == 9) return (long long)(i % 3 + 3 * (j % 3)) * P.ny * P.W + (long long)(j / 3) * P.W + i / 3;
     const int c = (i + j) % P.C;
     const int ic = ((c - j) % P.C + P.C) % P.C;
     return (long long)c * P.ny * P.W + (long long)j * P.W + (i - ic) / P.C;
@@ -129,16 +132,35 @@ inline Perm2D make_perm2d(int nx, int ny, int C)
 {
     Perm2D P;
     P.C = C;
-    P.W = (nx + C - 1) / C;
-    P.ny = ny;
+    P.W = C == 9 ? (nx + 2) / 3 : (nx + C - 1) / C;
+    P.ny = C == 9 ? (ny + 2) / 3 : ny;
     P.pad = 0;
-    P.M = (long long)C * ny * P.W;
+    P.M = (long long)C * P.ny * P.W;
     return P;
 }
 
+// Block b of a 2D stencil of nb blocks (closed forms, no tables): nb = 9, the cross of eq. (21)
+// (centre, x-2, x-1, x+1, x+2, y-2, y-1, y+1, y+2); nb = 21, the full stencil (the cross, then
+// x-2, x-1, x+1, x+2 on row y-1 and on row y+1, then x-1 and x+1 on rows y-2 and y+2, the row
+// first); nb = 5, the five points of the coarse levels (centre, x-1, x+1, y-1, y+1).
+__host__ __device__ constexpr int stencil_dx(int nb, int b)
+{
+    if (nb == 5) return b == 1 ? -1 : (b == 2 ? 1 : 0);
+    if (b < 9) return (b >= 1 && b <= 4) ? (b <= 2 ? b - 3 : b - 2) : 0;
+    if (b < 17) return ((b - 9) & 3) < 2 ? ((b - 9) & 3) - 2 : ((b - 9) & 3) - 1;
+    return b - 17 < 2 ? -1 : 1;
+}
+__host__ __device__ constexpr int stencil_dy(int nb, int b)
+{
+    if (nb == 5) return b == 3 ? -1 : (b == 4 ? 1 : 0);
+    if (b < 9) return b >= 5 ? (b <= 6 ? b - 7 : b - 6) : 0;
+    if (b < 17) return b - 9 < 4 ? -1 : 1;
+    return ((b - 17) & 1) ? 2 : -2;
+}
+
 // One 2D multigrid level: blocks J [nb*9][M], Dinv [9][M], rhs [3][M], dU [3][M] in the level's
-// colour-blocked order (C = 3 on the nine-block finest level, 2 on five-point levels); offsets
-// in elements of the value type.
+// colour-blocked order (C = 3 on a nine-block finest level, 9 on a 21-block one, 2 on five-point
+// levels); offsets in elements of the value type.
 struct Level2D {
     int nx, ny, nb, pad;
     Perm2D P;
@@ -197,7 +219,7 @@ hipError_t launch_res2d_finalize(const double *partial, int ntiles, long long nc
                                  hipStream_t s);
 // J, rhs, Dinv written in the cell order P (make_perm2d(Nx, Ny, 1) for the natural order)
 hipError_t launch_jacobian2d(const Inst2D &I, const Perm2D &P, void *J, void *rhs, void *Dinv, int prec,
-                             hipStream_t s);
+                             hipStream_t s, int nb = 9);
 hipError_t launch_coarsen2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
 // `reps` consecutive passes of one colour (the same neighbour values), one launch
 hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, int reps, double omega, int prec,

@@ -1,6 +1,6 @@
 // 2D finite-volume residual (section 4.1, eq. 20) with characteristic WENO3, Gauss quadrature
 // along faces and the tensor Gauss source, and its finite-difference Jacobian on the cross
-// stencil of eq. (21), for gfx950.
+// stencil of eq. (21) (J9) or the full 21-cell stencil (J21), for gfx950.
 //
 // The arithmetic is that of the formulas in their printed order, without FMA contraction and
 // with correctly rounded division and square root, so every face state, flux and residual is
@@ -14,7 +14,7 @@
 // its cells use once, into LDS tables, and each cell assembles its residual from them.  For the
 // Jacobian a perturbation of cell p changes only the face states whose three cells include p;
 // for a row at least two cells inside the grid (no ghost in its residual) and a column at a fixed
-// offset of the cross stencil, which of the row's 36 states those are is known at compile time,
+// offset of the stencil, which of the row's 36 states those are is known at compile time,
 // so the interior kernel recomputes just those (at most 12) and reads the rest from the tables.
 // The values equal a full re-evaluation of the perturbed local residual bit for bit.  Rows within
 // two cells of a side, whose ghosts also follow the perturbed cell, take a separate kernel that
@@ -602,22 +602,18 @@ NMG2D_INL bool border_row(const Inst2D &I, int i, int j)
     return i < 2 || j < 2 || i >= I.Nx - 2 || j >= I.Ny - 2;
 }
 
-template <int B>
-NMG2D_INL constexpr int cross_dx() { return (B >= 1 && B <= 4) ? (B <= 2 ? B - 3 : B - 2) : 0; }
-template <int B>
-NMG2D_INL constexpr int cross_dy() { return B >= 5 ? (B <= 6 ? B - 7 : B - 6) : 0; }
-
 template <int B, typename T>
 NMG2D_INL void interior_column(T *J, const JacOut &o, const TableFS &tab, const LdsState &st, const Inst2D &I,
                                int i, int j, int m, const double bx[4], const double by[4], double d[3])
 {
-    const PerturbedFS<cross_dx<B>(), cross_dy<B>()> fs{tab, st, i, j, m, I.eps, I.g};
+    const PerturbedFS<stencil_dx(21, B), stencil_dy(21, B)> fs{tab, st, i, j, m, I.eps, I.g};
     const V3 Rp = assemble_residual(fs, I, bx, by);
     store_column(J, o, B, m, Rp, d);
 }
 
-// the 27 columns of the interior row (i, j) of a tile whose state and face tables are staged
-template <typename T>
+// the 3 NB columns of the interior row (i, j) of a tile whose state and face tables are staged
+// (the first nine blocks of the full stencil are the cross, so one offset table serves both)
+template <typename T, int NB>
 NMG2D_INL void jacobian_interior_row(const Inst2D &I, const Perm2D &Pm, T *J, T *rhs, T *Dinv, const double *xs,
                                      const double *ys, const LdsState &st, int i, int j)
 {
@@ -643,10 +639,10 @@ NMG2D_INL void jacobian_interior_row(const Inst2D &I, const Perm2D &Pm, T *J, T 
     double D[9];
 #pragma unroll
     for (int e = 0; e < 9; e++) D[e] = 0.0;
-    // one column at a time (a rolled loop over the 27 columns, the stencil offset dispatched to
+    // one column at a time (a rolled loop over the columns, the stencil offset dispatched to
     // its compile-time form), so that only one column's values are live
 #pragma unroll 1
-    for (int col = 0; col < 27; col++) {
+    for (int col = 0; col < 3 * NB; col++) {
         const int b = col / 3, m = col - 3 * b;
         double d[3];
         switch (b) {
@@ -658,7 +654,25 @@ NMG2D_INL void jacobian_interior_row(const Inst2D &I, const Perm2D &Pm, T *J, T 
         case 5: interior_column<5>(J, o, tab, st, I, i, j, m, bx, by, d); break;
         case 6: interior_column<6>(J, o, tab, st, I, i, j, m, bx, by, d); break;
         case 7: interior_column<7>(J, o, tab, st, I, i, j, m, bx, by, d); break;
-        default: interior_column<8>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+        case 8: interior_column<8>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+        default:
+            if constexpr (NB == 21) {
+                switch (b) {
+                case 9: interior_column<9>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                case 10: interior_column<10>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                case 11: interior_column<11>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                case 12: interior_column<12>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                case 13: interior_column<13>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                case 14: interior_column<14>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                case 15: interior_column<15>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                case 16: interior_column<16>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                case 17: interior_column<17>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                case 18: interior_column<18>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                case 19: interior_column<19>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                default: interior_column<20>(J, o, tab, st, I, i, j, m, bx, by, d); break;
+                }
+            }
+            break;
         }
         if (b == 0) {
             if (m == 0) { D[0] = d[0]; D[3] = d[1]; D[6] = d[2]; }
@@ -670,9 +684,9 @@ NMG2D_INL void jacobian_interior_row(const Inst2D &I, const Perm2D &Pm, T *J, T 
 }
 
 // Finite-difference Jacobian (eq. 12, 13) of the rows at least two cells inside the grid, one
-// thread per row: for each component m, the nine columns of the cross stencil.  Optionally the
-// finest right-hand side (= R) and the inverse of the diagonal block.
-template <typename T>
+// thread per row: for each component m, the NB columns of the stencil.  Optionally the finest
+// right-hand side (= R) and the inverse of the diagonal block.
+template <typename T, int NB>
 __global__ void __launch_bounds__(kTX * kTY) k_jacobian2d(Inst2D I, Perm2D Pm, T *J, T *rhs, T *Dinv)
 {
     __shared__ double s[3 * kSY * kSX];
@@ -686,7 +700,7 @@ __global__ void __launch_bounds__(kTX * kTY) k_jacobian2d(Inst2D I, Perm2D Pm, T
     __syncthreads();
     const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
     if (i >= I.Nx || j >= I.Ny || border_row(I, i, j)) return;
-    jacobian_interior_row(I, Pm, J, rhs, Dinv, xs, ys, st, i, j);
+    jacobian_interior_row<T, NB>(I, Pm, J, rhs, Dinv, xs, ys, st, i, j);
 }
 
 // Face states of a border row, full re-evaluation: the 36 states sit in per-thread LDS slots,
@@ -779,9 +793,7 @@ NMG2D_INL long long jacobian_border_column(const Inst2D &I, const Perm2D &Pm, T 
         rhs[o.M + o.slot] = (T)o.R1;
         rhs[2 * o.M + o.slot] = (T)o.R2;
     }
-    const int dxb = (b >= 1 && b <= 4) ? (b <= 2 ? b - 3 : b - 2) : 0;
-    const int dyb = b >= 5 ? (b <= 6 ? b - 7 : b - 6) : 0;
-    const int pi = i + dxb, pj = j + dyb;
+    const int pi = i + stencil_dx(21, b), pj = j + stencil_dy(21, b);
     if (pi < 0 || pi >= I.Nx || pj < 0 || pj >= I.Ny) {
         store_zero_column(J, o, b, m);
         return o.slot;
@@ -801,25 +813,28 @@ NMG2D_INL long long jacobian_border_column(const Inst2D &I, const Perm2D &Pm, T 
     return o.slot;
 }
 
-// Jacobian of the border rows: one thread per (row, column of the cross stencil), each a full
+// Jacobian of the border rows: one thread per (row, column of the stencil), each a full
 // re-evaluation of the perturbed local residual from the state in global memory.  A row takes
-// 32 lanes of a wavefront (27 in use), so the lanes of its three diagonal-block columns can hand
-// their FP64 values to the row's first lane, which writes the inverse of the diagonal block.
-template <typename T>
+// LPR lanes of a wavefront (32 for the 27 columns of J9, 64 for the 63 of J21), so the lanes of
+// its three diagonal-block columns can hand their FP64 values to the row's first lane, which
+// writes the inverse of the diagonal block.
+template <typename T, int NB>
 __global__ void __launch_bounds__(kBorderNT) k_jacobian2d_border(Inst2D I, Perm2D Pm, T *J, T *rhs, T *Dinv,
                                                                  long long nrows)
 {
+    constexpr int LPR = NB == 9 ? 32 : 64, LOG = NB == 9 ? 5 : 6;
+    static_assert(kBorderNT % LPR == 0, "a workgroup holds whole rows");
     __shared__ double slots[kSlots * 3 * kBorderNT];
     const long long gid = blockIdx.x * (long long)kBorderNT + threadIdx.x;
-    const long long r = gid >> 5;
-    const int col = (int)(gid & 31), b = col / 3, m = col - 3 * b;
-    const bool active = r < nrows && col < 27;
+    const long long r = gid >> LOG;
+    const int col = (int)(gid & (LPR - 1)), b = col / 3, m = col - 3 * b;
+    const bool active = r < nrows && col < 3 * NB;
     double d[3] = {0.0, 0.0, 0.0};
     long long slot = 0;
     if (active) slot = jacobian_border_column(I, Pm, J, rhs, slots, threadIdx.x, r, col, d);
     if (!Dinv) return;   // uniform over the launch
-    // the diagonal block's columns m = 0, 1, 2 sit in lanes 0, 1, 2 of the row's 32
-    const int base = threadIdx.x & ~31;
+    // the diagonal block's columns m = 0, 1, 2 sit in lanes 0, 1, 2 of the row's LPR
+    const int base = threadIdx.x & ~(LPR - 1);
     double D[9];
 #pragma unroll
     for (int mm = 0; mm < 3; mm++)
@@ -846,25 +861,31 @@ hipError_t launch_res2d_finalize(const double *partial, int ntiles, long long nc
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int NB>
 static hipError_t jacobian2d_t(const Inst2D &I, const Perm2D &P, T *J, T *rhs, T *Dinv, hipStream_t s)
 {
+    constexpr int LPR = NB == 9 ? 32 : 64;
     dim3 grid((I.Nx + kTX - 1) / kTX, (I.Ny + kTY - 1) / kTY);
-    hipLaunchKernelGGL(k_jacobian2d<T>, grid, dim3(kTX, kTY), 0, s, I, P, J, rhs, Dinv);
+    hipLaunchKernelGGL((k_jacobian2d<T, NB>), grid, dim3(kTX, kTY), 0, s, I, P, J, rhs, Dinv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long nb = border_rows2d(I.Nx, I.Ny);
-    const long long blocks = (nb * 32 + kBorderNT - 1) / kBorderNT;
-    hipLaunchKernelGGL(k_jacobian2d_border<T>, dim3((unsigned)blocks), dim3(kBorderNT), 0, s, I, P, J, rhs, Dinv,
-                       nb);
+    const long long blocks = (nb * LPR + kBorderNT - 1) / kBorderNT;
+    hipLaunchKernelGGL((k_jacobian2d_border<T, NB>), dim3((unsigned)blocks), dim3(kBorderNT), 0, s, I, P, J, rhs,
+                       Dinv, nb);
     return hipGetLastError();
 }
 
 hipError_t launch_jacobian2d(const Inst2D &I, const Perm2D &P, void *J, void *rhs, void *Dinv, int prec,
-                             hipStream_t s)
+                             hipStream_t s, int nb)
 {
-    if (prec == NMG_FP32_MG) return jacobian2d_t(I, P, (float *)J, (float *)rhs, (float *)Dinv, s);
-    return jacobian2d_t(I, P, (double *)J, (double *)rhs, (double *)Dinv, s);
+    if (nb != 9 && nb != 21) return hipErrorInvalidValue;
+    if (prec == NMG_FP32_MG) {
+        if (nb == 21) return jacobian2d_t<float, 21>(I, P, (float *)J, (float *)rhs, (float *)Dinv, s);
+        return jacobian2d_t<float, 9>(I, P, (float *)J, (float *)rhs, (float *)Dinv, s);
+    }
+    if (nb == 21) return jacobian2d_t<double, 21>(I, P, (double *)J, (double *)rhs, (double *)Dinv, s);
+    return jacobian2d_t<double, 9>(I, P, (double *)J, (double *)rhs, (double *)Dinv, s);
 }
 
 }  // namespace nmg

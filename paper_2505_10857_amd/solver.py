@@ -276,7 +276,7 @@ class Problem2DDevice:
     tensor Gauss points (x_i -/+ dx/(2 sqrt 3), y_j -/+ dy/(2 sqrt 3)) of every cell, stored
     [ny][nx][y point][x point]."""
 
-    def __init__(self, prob, device="cuda"):
+    def __init__(self, prob, device="cuda", jac: int = 9):
         self.prob = prob
         nx, ny, dx, dy = prob.nx, prob.ny, prob.dx, prob.dy
         gx = dx / (2.0 * math.sqrt(3.0))
@@ -296,7 +296,7 @@ class Problem2DDevice:
         self.bx_gp = torch.tensor(np.ascontiguousarray(bx), **f64)
         self.by_gp = torch.tensor(np.ascontiguousarray(by), **f64)
         d = A.nmg_desc()
-        d.dim, d.nx, d.ny, d.levels, d.jac = 2, nx, ny, prob.levels, 9
+        d.dim, d.nx, d.ny, d.levels, d.jac = 2, nx, ny, prob.levels, jac
         d.x0, d.x1, d.y0, d.y1, d.g = prob.x0, prob.x1, prob.y0, prob.y1, prob.g
         for k, bc in enumerate(prob.bc):
             d.bc[k].kind, d.bc[k].q, d.bc[k].h, d.bc[k].u, d.bc[k].v = bc.kind, bc.q, bc.h, bc.u, bc.v
@@ -311,9 +311,10 @@ class Solver2D:
     """Single-instance entry points of the C ABI for one 2D problem (state [3, ny, nx])."""
 
     def __init__(self, prob, device="cuda", precision: int = A.NMG_FP64, check_every: int = 4,
-                 levels: Optional[int] = None, **param_overrides):
+                 levels: Optional[int] = None, jac: int = 9, **param_overrides):
         A.load()
-        self.dev = Problem2DDevice(prob, device)
+        self.dev = Problem2DDevice(prob, device, jac)
+        self.nb = jac
         if levels is not None:
             self.dev.desc.levels = levels
         p = prob.params
@@ -355,8 +356,8 @@ class Solver2D:
         return R, rn, res
 
     def jacobian(self, U, R, rn) -> torch.Tensor:
-        """Blocks J [9, 3, 3, ny, nx] (eq. 12-13, 21) on the device."""
-        J = torch.empty((9, 3, 3, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        """Blocks J [nb, 3, 3, ny, nx] (eq. 12-13, 21; nb = 9 or 21) on the device."""
+        J = torch.empty((self.nb, 3, 3, self.ny, self.nx), dtype=torch.float64, device=self.device)
         A.check(self.L.nmg_jacobian_assemble_simplified(
             C.byref(self.dev.desc), C.byref(self.params), _dptr(U), _dptr(R), _dptr(rn), _dptr(J),
             C.c_void_p(_stream_ptr())))
@@ -428,7 +429,7 @@ def interp2d_coarse_to_fine(Uc: torch.Tensor) -> torch.Tensor:
 
 
 def nested_solve2d(prob, ngrids: Optional[int] = None, device="cuda", precision: int = A.NMG_FP64,
-                   check_every: int = 1, **param_overrides):
+                   check_every: int = 1, jac: int = 9, **param_overrides):
     """Algorithm 3 on the GPU for a 2D problem: Newton with the dense direct solve on the
     coarsest grid (one level) from the problem's initial state there, then the Newton multigrid
     iteration on every finer grid from the eq. (A.3) interpolation of the coarser solution.
@@ -439,7 +440,7 @@ def nested_solve2d(prob, ngrids: Optional[int] = None, device="cuda", precision:
     grids = nested_grids_2d(prob, ngrids)
     ng = len(grids)
     A.load()
-    devs = [Problem2DDevice(g, device) for g in grids]
+    devs = [Problem2DDevice(g, device, jac) for g in grids]
     descs = (A.nmg_desc * ng)(*[d.desc for d in devs])
     params = (A.nmg_params * ng)(*[params_struct(dataclasses.replace(g.params, **param_overrides),
                                                  precision, check_every) for g in grids])
