@@ -230,6 +230,61 @@ __global__ void __launch_bounds__(256) k_smooth2d_pass(T *mg, Level2D L, int col
     smooth_slot<T, NB, STREAM>(mg, L, colour, omega, reps, p);
 }
 
+// The same passes with each cell's three rows of eq. (22) on three lanes: wavefront c of a
+// 192-thread workgroup forms row c (the off-diagonal sum in stencil order, as the per-cell form
+// does) for 64 consecutive slots of the colour, so every wavefront reads one row of the blocks
+// at consecutive addresses; the three sums meet in LDS, and lane c applies row c of D^{-1} and
+// relaxes component c.  The same operations in the same order as smooth_slot, so the results
+// are identical; three times the threads of the per-cell form, and a third of its loads per
+// thread, keep more of a colour's cells in flight.
+constexpr int kSplitCells = 64;
+
+template <typename T, int NB, bool STREAM>
+__global__ void __launch_bounds__(3 * kSplitCells) k_smooth2d_split(T *mg, Level2D L, int colour, double omega, int reps)
+{
+    __shared__ double sr[3][kSplitCells];
+    constexpr int C = NB == 9 ? 3 : (NB == 21 ? 9 : 2);
+    const int c = threadIdx.x / kSplitCells, lane = threadIdx.x % kSplitCells;
+    const long long p = blockIdx.x * (long long)kSplitCells + lane;
+    const int W = L.P.W;
+    bool valid = p < (long long)L.P.ny * W;
+    int i = 0, j = 0;
+    if (valid) {
+        const int jr = (int)(p / W), k = (int)(p - (long long)jr * W);
+        if (C == 9) { i = 3 * k + colour % 3; j = 3 * jr + colour / 3; }
+        else { j = jr; i = ((colour - j) % C + C) % C + C * k; }
+        valid = i < L.nx && j < L.ny;
+    }
+    const long long n = L.P.M, cc = (long long)colour * L.P.ny * W + p;
+    double r = 0.0;
+    if (valid) {
+        const T *Jr = mg + L.J + cc;
+        const T *Ur = mg + L.dU;
+        r = ld2(mg + L.rhs, c * n + cc);
+#pragma unroll
+        for (int b = 1; b < NB; b++) {
+            int di, dj;
+            stencil_off(NB, b, di, dj);
+            const int pi = i + di, pj = j + dj;
+            const bool ok = pi >= 0 && pi < L.nx && pj >= 0 && pj < L.ny;
+            const long long q = ok ? perm2d(L.P, pi, pj) : cc;
+            const double a = lds2<STREAM>(Jr + (b * 9 + c * 3 + 0) * n) * (double)Ur[q] +
+                             lds2<STREAM>(Jr + (b * 9 + c * 3 + 1) * n) * (double)Ur[n + q] +
+                             lds2<STREAM>(Jr + (b * 9 + c * 3 + 2) * n) * (double)Ur[2 * n + q];
+            if (ok) r = r + a;
+        }
+    }
+    sr[c][lane] = r;
+    __syncthreads();
+    if (!valid) return;
+    const double t = lds2<STREAM>(mg + L.Dinv + (c * 3 + 0) * n + cc) * sr[0][lane] +
+                     lds2<STREAM>(mg + L.Dinv + (c * 3 + 1) * n + cc) * sr[1][lane] +
+                     lds2<STREAM>(mg + L.Dinv + (c * 3 + 2) * n + cc) * sr[2][lane];
+    T d = mg[L.dU + c * n + cc];
+    for (int q = 0; q < reps; q++) d = (T)((1.0 - omega) * (double)d - omega * t);
+    mg[L.dU + c * n + cc] = d;
+}
+
 // eq. (24), right-hand side of coarse cell (I, Jq); also clears its dU.
 // rhs + J dU of fine cell (fi, fj), the summand of eq. (24)'s restriction
 template <typename T>
@@ -676,43 +731,50 @@ hipError_t launch_coarsen2d(void *mg, const Level2D &Lf, const Level2D &Lc, int 
     return hipGetLastError();
 }
 
+// The full stencil's passes take the three-lanes-per-cell form: a colour holds a ninth of the
+// cells, too few for one thread per cell to fill the chip, and a cell's 20 off-diagonal blocks
+// are a long chain of loads for one thread (measured on the 1024 x 512 wedge: 35 against 56 ms
+// per FP64 V-cycle, 30 against 62 ms in FP32).  The cross and five-point passes keep one thread
+// per cell, whose loads all issue up front (13.2 against 13.7 ms FP64, 8.3 against 10.8 ms FP32
+// per J9 V-cycle).  Both forms give identical results.
+template <typename T, int NB, bool STREAM>
+static void smooth2d_launch(T *mg, const Level2D &L, int colour, int reps, double omega, hipStream_t s)
+{
+    const long long slots = (long long)L.P.ny * L.P.W;
+    if constexpr (NB == 21) {
+        dim3 grid((unsigned)((slots + kSplitCells - 1) / kSplitCells));
+        hipLaunchKernelGGL((k_smooth2d_split<T, NB, STREAM>), grid, dim3(3 * kSplitCells), 0, s, mg, L, colour, omega, reps);
+    } else {
+        dim3 grid((unsigned)((slots + 255) / 256));
+        hipLaunchKernelGGL((k_smooth2d_pass<T, NB, STREAM>), grid, dim3(256), 0, s, mg, L, colour, omega, reps);
+    }
+}
+
 hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, int reps, double omega, int prec,
                                hipStream_t s)
 {
-    const long long slots = (long long)L.P.ny * L.P.W;
-    dim3 grid((unsigned)((slots + 255) / 256));
     if (L.P.C != (L.nb == 9 ? 3 : (L.nb == 21 ? 9 : 2))) return hipErrorInvalidValue;
+    const bool f32 = prec == NMG_FP32_MG;
+    const size_t vsz = f32 ? 4 : 8;
+    const bool big = (size_t)L.nb * 9 * (size_t)L.P.M * vsz > kMemCacheBytes;
+    // Operators larger than the memory-side cache: on the cross stencil the symmetric schedule
+    // returns to colour 1 every other run and to colours 0 and 2 every fourth, so colours 0 and 2
+    // stream their rows and leave the cache to colour 1's; with nine colours a colour's rows come
+    // back only after the eight others have streamed theirs, so every pass streams.
+    const bool stream = big && (L.nb == 21 || (L.nb == 9 && colour != 1));
     if (L.nb == 21) {
-        // nine colours: a colour's rows come back only after the eight others have streamed
-        // theirs, so when the operator exceeds the memory-side cache every pass streams
-        const size_t vsz = prec == NMG_FP32_MG ? 4 : 8;
-        const bool stream = (size_t)L.nb * 9 * (size_t)L.P.M * vsz > kMemCacheBytes;
-        if (prec == NMG_FP32_MG) {
-            if (stream) hipLaunchKernelGGL((k_smooth2d_pass<float, 21, true>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
-            else hipLaunchKernelGGL((k_smooth2d_pass<float, 21, false>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
-        } else {
-            if (stream) hipLaunchKernelGGL((k_smooth2d_pass<double, 21, true>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
-            else hipLaunchKernelGGL((k_smooth2d_pass<double, 21, false>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
-        }
+        if (f32) { if (stream) smooth2d_launch<float, 21, true>((float *)mg, L, colour, reps, omega, s);
+                   else smooth2d_launch<float, 21, false>((float *)mg, L, colour, reps, omega, s); }
+        else { if (stream) smooth2d_launch<double, 21, true>((double *)mg, L, colour, reps, omega, s);
+               else smooth2d_launch<double, 21, false>((double *)mg, L, colour, reps, omega, s); }
     } else if (L.nb == 9) {
-        // finest level: the symmetric schedule returns to colour 1 every other run and to colours
-        // 0 and 2 every fourth.  When the level's operator is larger than the memory-side cache,
-        // colours 0 and 2 are evicted before they come back, so their passes stream their rows
-        // and leave the cache to colour 1's
-        const size_t vsz = prec == NMG_FP32_MG ? 4 : 8;
-        const bool stream = colour != 1 && (size_t)L.nb * 9 * (size_t)L.P.M * vsz > kMemCacheBytes;
-        if (prec == NMG_FP32_MG) {
-            if (stream) hipLaunchKernelGGL((k_smooth2d_pass<float, 9, true>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
-            else hipLaunchKernelGGL((k_smooth2d_pass<float, 9, false>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
-        } else {
-            if (stream) hipLaunchKernelGGL((k_smooth2d_pass<double, 9, true>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
-            else hipLaunchKernelGGL((k_smooth2d_pass<double, 9, false>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
-        }
+        if (f32) { if (stream) smooth2d_launch<float, 9, true>((float *)mg, L, colour, reps, omega, s);
+                   else smooth2d_launch<float, 9, false>((float *)mg, L, colour, reps, omega, s); }
+        else { if (stream) smooth2d_launch<double, 9, true>((double *)mg, L, colour, reps, omega, s);
+               else smooth2d_launch<double, 9, false>((double *)mg, L, colour, reps, omega, s); }
     } else {
-        if (prec == NMG_FP32_MG)
-            hipLaunchKernelGGL((k_smooth2d_pass<float, 5, false>), grid, dim3(256), 0, s, (float *)mg, L, colour, omega, reps);
-        else
-            hipLaunchKernelGGL((k_smooth2d_pass<double, 5, false>), grid, dim3(256), 0, s, (double *)mg, L, colour, omega, reps);
+        if (f32) smooth2d_launch<float, 5, false>((float *)mg, L, colour, reps, omega, s);
+        else smooth2d_launch<double, 5, false>((double *)mg, L, colour, reps, omega, s);
     }
     return hipGetLastError();
 }
