@@ -537,7 +537,10 @@ struct Bottom2DArgs {
     const double *lu;
 };
 
-template <typename T>
+// NBF: the stencil of the bottom's first level (the finest level when the whole hierarchy fits
+// one workgroup, else a five-point level); the levels below it have five points.  Only the
+// passes a launch can meet are compiled into it, which keeps the kernel's registers down.
+template <typename T, int NBF>
 __device__ void bottom_smooth(T *mg, const Level2D &L, int nu, double omega)
 {
     const int C = L.P.C;
@@ -551,8 +554,7 @@ __device__ void bottom_smooth(T *mg, const Level2D &L, int nu, double omega)
                 if (!last && c == cur) { run++; continue; }
                 if (run > 0) {
                     for (long long p = threadIdx.x; p < slots; p += blockDim.x) {
-                        if (L.nb == 9) smooth_slot<T, 9>(mg, L, cur, omega, run, p);
-                        else if (L.nb == 21) smooth_slot<T, 21>(mg, L, cur, omega, run, p);
+                        if (NBF != 5 && L.nb == NBF) smooth_slot<T, NBF>(mg, L, cur, omega, run, p);
                         else smooth_slot<T, 5>(mg, L, cur, omega, run, p);
                     }
                     __syncthreads();
@@ -564,7 +566,7 @@ __device__ void bottom_smooth(T *mg, const Level2D &L, int nu, double omega)
     }
 }
 
-template <typename T>
+template <typename T, int NBF>
 __global__ void __launch_bounds__(512) k_bottom2d(T *mg, Bottom2DArgs B)
 {
     constexpr int MM = 3 * kMaxCoarse2D;
@@ -572,7 +574,7 @@ __global__ void __launch_bounds__(512) k_bottom2d(T *mg, Bottom2DArgs B)
     __shared__ double x[MM];
     const int last = B.levels - 1;
     for (int l = B.first; l < last; l++) {
-        bottom_smooth(mg, B.L[l], B.nu1, B.omega);
+        bottom_smooth<T, NBF>(mg, B.L[l], B.nu1, B.omega);
         const Level2D &Lc = B.L[l + 1];
         for (int e = threadIdx.x; e < Lc.nx * Lc.ny; e += blockDim.x) restrict_cell(mg, B.L[l], Lc, e % Lc.nx, e / Lc.nx);
         __syncthreads();
@@ -583,7 +585,7 @@ __global__ void __launch_bounds__(512) k_bottom2d(T *mg, Bottom2DArgs B)
         const Level2D &Lf = B.L[l];
         for (int e = threadIdx.x; e < Lf.nx * Lf.ny; e += blockDim.x) prolong_cell(mg, Lf, B.L[l + 1], e % Lf.nx, e / Lf.nx);
         __syncthreads();
-        bottom_smooth(mg, Lf, B.nu2, B.omega);
+        bottom_smooth<T, NBF>(mg, Lf, B.nu2, B.omega);
     }
 }
 
@@ -812,7 +814,20 @@ hipError_t launch_bottom2d(void *mg, const Level2D *levels, int first, int nlev,
     B.nu2 = nu2;
     B.omega = omega;
     B.lu = lu;
-    DISPATCH(prec, k_bottom2d, dim3(1), dim3(512), B);
+    const int nbf = levels[first].nb;
+    const bool f32 = prec == NMG_FP32_MG;
+    float *mf = (float *)mg;
+    double *md = (double *)mg;
+    if (nbf == 21) {
+        if (f32) hipLaunchKernelGGL((k_bottom2d<float, 21>), dim3(1), dim3(512), 0, s, mf, B);
+        else hipLaunchKernelGGL((k_bottom2d<double, 21>), dim3(1), dim3(512), 0, s, md, B);
+    } else if (nbf == 9) {
+        if (f32) hipLaunchKernelGGL((k_bottom2d<float, 9>), dim3(1), dim3(512), 0, s, mf, B);
+        else hipLaunchKernelGGL((k_bottom2d<double, 9>), dim3(1), dim3(512), 0, s, md, B);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_bottom2d<float, 5>), dim3(1), dim3(512), 0, s, mf, B);
+        else hipLaunchKernelGGL((k_bottom2d<double, 5>), dim3(1), dim3(512), 0, s, md, B);
+    }
     return hipGetLastError();
 }
 
