@@ -30,6 +30,16 @@
  *      normal momentum negated, STATE gives (h, h u, h v), DISCHARGE copies h and hv and sets the
  *      normal discharge, DEPTH sets h and copies the momenta.  The bottom side may be EXTRAP for
  *      cell centres x < wall_x and WALL beyond.
+ *  S1  Surface variant (recon = 1), so that still water is steady on any bottom: the WENO
+ *      reconstructions act on (eta, hu, hv) with eta = h + zbar (zbar the cell average of b; the
+ *      characteristic basis still at the mean of the two cells' (h, hu, hv)); the depth at a
+ *      face Gauss point is eta there minus b at that point; a ghost that copies the depth of a
+ *      grid cell copies its surface instead (h_g = h_src + zbar_src - zbar_g); the source of
+ *      each Gauss line is the exactly equal split form
+ *        -g [ int (eta_h - eta_ij) b_x + eta_ij (b_+ - b_-) - (b_+^2 - b_-^2) / 2 ]
+ *      (eta_h the cubic through the four face values of eta on that line, the integral by the
+ *      same two-point Gauss rule, b_-+ at the cell's faces on that line), summed over the two
+ *      Gauss lines with weight (cell width across) / 2.  With b = 0 it is the paper's scheme.
  *  Q5  Multicolour smoothing: colour (i + j) mod C, C = 3 on the cross stencil (offsets up to 2),
  *      2 on five-point levels; on the full 21-cell stencil, whose diagonal neighbours (1, -1)
  *      share (i + j) mod 3, nine colours (i mod 3) + 3 (j mod 3).  With these colourings no
@@ -55,6 +65,10 @@ typedef struct {
     int bc_kind[4];        /* left, right, bottom, top */
     double bc_q[4], bc_h[4], bc_u[4], bc_v[4];
     double wall_x;         /* bottom: EXTRAP for x < wall_x, WALL beyond (when wall_x > x0) */
+    int recon;             /* 0: reconstruct (h, hu, hv) (the paper); 1: the surface variant S1 */
+    const double *zavg;    /* recon 1: cell averages of b over cells -2..Nx+1 x -2..Ny+1, [Ny+4][Nx+4] */
+    const double *zfx;     /* recon 1: b at the Gauss points of the x faces, [Ny][Nx+1][2] */
+    const double *zfy;     /* recon 1: b at the Gauss points of the y faces, [Ny+1][Nx][2] */
 } or2d_prob;
 
 typedef struct {
@@ -68,6 +82,7 @@ typedef struct {
 static const double ZETA2 = 1e-6;
 
 #define UIDX(p, c, i, j) (((c) * (p)->Ny + (j)) * (p)->Nx + (i))
+#define ZAVG(p, i, j) ((p)->zavg[((j) + 2) * ((p)->Nx + 4) + (i) + 2])
 
 /* ---- ghost cells (reading Q4) ------------------------------------------------------------ */
 
@@ -117,6 +132,7 @@ void or2d_cell(const or2d_prob *p, const double *U, int i, int j, double out[3])
     out[2] = U[UIDX(p, 2, ii, jj)];
     if (flip_u) out[1] = -out[1];
     if (flip_v) out[2] = -out[2];
+    if (p->recon == 1 && (ii != i || jj != j)) out[0] = out[0] + ZAVG(p, ii, jj) - ZAVG(p, i, j);   /* S1 */
     if (set_h >= 0) out[0] = p->bc_h[set_h];
     if (set_q >= 0) {
         if (set_q < 2) out[1] = p->bc_q[set_q];
@@ -196,6 +212,9 @@ void or2d_face_state(const or2d_prob *p, const double *U, int dir, int k, int a,
     CELL(m, S[1]);
     CELL(m + 1, S[2]);
 #undef CELL
+    if (p->recon == 1)   /* S1: reconstruct the surface */
+        for (int s = 0; s < 3; s++)
+            S[s][0] = S[s][0] + (dir == 0 ? ZAVG(p, m - 1 + s, k) : ZAVG(p, k, m - 1 + s));
     double W[3][3], w[3];
     for (int s = 0; s < 3; s++)
         for (int f = 0; f < 3; f++)
@@ -264,12 +283,19 @@ void or2d_face_flux(const or2d_prob *p, const double *U, int dir, int line, int 
     }
     gauss_line(Vm[0], Vm[1], Vm[2], Pm);
     gauss_line(Vp[0], Vp[1], Vp[2], Pp);
+    if (hm) { hm[0] = Pm[0][0]; hm[1] = Pm[1][0]; }
+    if (hp) { hp[0] = Pp[0][0]; hp[1] = Pp[1][0]; }
+    if (p->recon == 1)   /* S1: the depth at each Gauss point is the surface minus b there */
+        for (int q = 0; q < 2; q++) {
+            double b = dir == 0 ? p->zfx[(line * (p->Nx + 1) + a + 1) * 2 + q]
+                                : p->zfy[((a + 1) * p->Nx + line) * 2 + q];
+            Pm[q][0] = Pm[q][0] - b;
+            Pp[q][0] = Pp[q][0] - b;
+        }
     double F0[3], F1[3];
     or2d_llf(Pm[0], Pp[0], dir, p->g, F0);
     or2d_llf(Pm[1], Pp[1], dir, p->g, F1);
     for (int c = 0; c < 3; c++) F[c] = 0.5 * (F0[c] + F1[c]);
-    if (hm) { hm[0] = Pm[0][0]; hm[1] = Pm[1][0]; }
-    if (hp) { hp[0] = Pp[0][0]; hp[1] = Pp[1][0]; }
 }
 
 /* depth of one face state at the two Gauss points along the face */
@@ -332,6 +358,34 @@ void or2d_local_residual(const or2d_prob *p, const double *U, int i, int j, doub
         }
     double S2 = -(p->dx * p->dy / 4.0) * s2;
     double S3 = -(p->dx * p->dy / 4.0) * s3;
+    if (p->recon == 1) {
+        /* S1: hx, hy hold the surface; the split form of the source */
+        double eta = U[UIDX(p, 0, i, j)] + ZAVG(p, i, j);
+        s2 = 0.0;
+        for (int be = 0; be < 2; be++)
+            for (int ga = 0; ga < 2; ga++) {
+                double e = Wt[ga][0] * hx[0][be] + Wt[ga][1] * hx[1][be] + Wt[ga][2] * hx[2][be] + Wt[ga][3] * hx[3][be];
+                s2 = s2 + p->g * (e - eta) * bx[2 * be + ga];
+            }
+        double e2 = 0.0;
+        for (int be = 0; be < 2; be++) {
+            double bm = p->zfx[(j * (p->Nx + 1) + i) * 2 + be], bp = p->zfx[(j * (p->Nx + 1) + i + 1) * 2 + be];
+            e2 = e2 + p->g * (eta * (bp - bm) - (bp * bp - bm * bm) / 2.0);
+        }
+        s3 = 0.0;
+        for (int ga = 0; ga < 2; ga++)
+            for (int be = 0; be < 2; be++) {
+                double e = Wt[be][0] * hy[0][ga] + Wt[be][1] * hy[1][ga] + Wt[be][2] * hy[2][ga] + Wt[be][3] * hy[3][ga];
+                s3 = s3 + p->g * (e - eta) * by[2 * be + ga];
+            }
+        double e3 = 0.0;
+        for (int ga = 0; ga < 2; ga++) {
+            double bm = p->zfy[(j * p->Nx + i) * 2 + ga], bp = p->zfy[((j + 1) * p->Nx + i) * 2 + ga];
+            e3 = e3 + p->g * (eta * (bp - bm) - (bp * bp - bm * bm) / 2.0);
+        }
+        S2 = -(p->dx * p->dy / 4.0) * s2 - (p->dy / 2.0) * e2;
+        S3 = -(p->dx * p->dy / 4.0) * s3 - (p->dx / 2.0) * e3;
+    }
     R[0] = (fxp[0] - fxm[0]) / p->dx + (fyp[0] - fym[0]) / p->dy;
     R[1] = (fxp[1] - fxm[1]) / p->dx + (fyp[1] - fym[1]) / p->dy - S2 / (p->dx * p->dy);
     R[2] = (fxp[2] - fxm[2]) / p->dx + (fyp[2] - fym[2]) / p->dy - S3 / (p->dx * p->dy);

@@ -18,7 +18,8 @@ class OrProb2D(C.Structure):
                 ("g", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
                 ("bx_gp", _dp), ("by_gp", _dp),
                 ("bc_kind", C.c_int * 4), ("bc_q", C.c_double * 4), ("bc_h", C.c_double * 4),
-                ("bc_u", C.c_double * 4), ("bc_v", C.c_double * 4), ("wall_x", C.c_double)]
+                ("bc_u", C.c_double * 4), ("bc_v", C.c_double * 4), ("wall_x", C.c_double),
+                ("recon", C.c_int), ("zavg", _dp), ("zfx", _dp), ("zfy", _dp)]
 
 
 class OrParams2D(C.Structure):
@@ -104,6 +105,11 @@ class Oracle2D:
         for k, bc in enumerate(prob.bc):
             c.bc_kind[k], c.bc_q[k], c.bc_h[k], c.bc_u[k], c.bc_v[k] = bc.kind, bc.q, bc.h, bc.u, bc.v
         c.wall_x = prob.wall_x
+        c.recon = getattr(prob, "recon", 0)
+        if c.recon == 1:
+            from swe_workloads import bottom_samples_2d
+            self.zavg, self.zfx, self.zfy = bottom_samples_2d(prob)
+            c.zavg, c.zfx, c.zfy = _ptr(self.zavg), _ptr(self.zfx), _ptr(self.zfy)
         self.c = c
         self.nx, self.ny = nx, ny
 

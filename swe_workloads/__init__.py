@@ -115,6 +115,8 @@ class Problem2D:
     init_state: Tuple[float, float, float] = (1.0, 1.0, 0.0)  # (h, hu, hv) initial guess
     g: float = G
     meta: dict = dataclasses.field(default_factory=dict)
+    recon: int = 0              # 0: reconstruct (h, hu, hv) (the paper); 1: the surface h + b
+    surface0: Optional[float] = None   # initial guess: still surface h + b = surface0 (when set)
 
     @property
     def dx(self) -> float:
@@ -129,6 +131,8 @@ class Problem2D:
         U[0] = self.init_state[0]
         U[1] = self.init_state[1]
         U[2] = self.init_state[2]
+        if self.surface0 is not None:
+            U[0] = self.surface0 - bottom_samples_2d(self)[0][2:-2, 2:-2]
         return U
 
 
@@ -498,6 +502,60 @@ def bottom_faces_and_averages(prob: Problem1D):
     zr, _ = prob.bottom(xc + r)
     za = (5.0 * zl + 8.0 * zc + 5.0 * zr) / 18.0
     return np.ascontiguousarray(zf, dtype=np.float64), np.ascontiguousarray(za, dtype=np.float64)
+
+
+def bottom_samples_2d(prob: Problem2D):
+    """Bottom samples for the 2D surface reconstruction: the cell averages of b over cells
+    -2..nx+1 x -2..ny+1 ([ny+4][nx+4], two cells beyond each side for the ghosts) by the 3 x 3
+    Gauss-Legendre rule; b at the two Gauss points y_j -+ dy/(2 sqrt 3) of every x face
+    x_{i-1/2}, i = 0..nx ([ny][nx+1][2]); b at the two Gauss points x_i -+ dx/(2 sqrt 3) of every
+    y face y_{j-1/2}, j = 0..ny ([ny+1][nx][2])."""
+    nx, ny, dx, dy = prob.nx, prob.ny, prob.dx, prob.dy
+    xc = prob.x0 + (np.arange(-2, nx + 2) + 0.5) * dx
+    yc = prob.y0 + (np.arange(-2, ny + 2) + 0.5) * dy
+    t = np.sqrt(0.6)
+    nodes = ((-t, 5.0 / 18.0), (0.0, 8.0 / 18.0), (t, 5.0 / 18.0))
+    za = np.zeros((ny + 4, nx + 4))
+    for sy, wy in nodes:
+        for sx, wx in nodes:
+            X, Y = np.meshgrid(xc + 0.5 * dx * sx, yc + 0.5 * dy * sy)
+            za = za + wx * wy * prob.bottom(X, Y)[0]
+    gx, gy = dx / (2.0 * np.sqrt(3.0)), dy / (2.0 * np.sqrt(3.0))
+    xf = prob.x0 + np.arange(nx + 1) * dx
+    yf = prob.y0 + np.arange(ny + 1) * dy
+    xi = prob.x0 + (np.arange(nx) + 0.5) * dx
+    yj = prob.y0 + (np.arange(ny) + 0.5) * dy
+    zfx = np.empty((ny, nx + 1, 2))
+    zfy = np.empty((ny + 1, nx, 2))
+    for q, s in enumerate((-1.0, 1.0)):
+        X, Y = np.meshgrid(xf, yj + s * gy)
+        zfx[:, :, q] = prob.bottom(X, Y)[0]
+        X, Y = np.meshgrid(xi + s * gx, yf)
+        zfy[:, :, q] = prob.bottom(X, Y)[0]
+    return (np.ascontiguousarray(za), np.ascontiguousarray(zfx), np.ascontiguousarray(zfy))
+
+
+def lake_at_rest_2d(nx: int = 32, ny: int = 16, surface: float = 1.0, amp: float = 0.3,
+                    levels: int = 3, recon: int = 1, sides: str = "walls") -> Problem2D:
+    """Still water (surface h + b = ``surface``, hu = hv = 0) on [0,4]x[0,2] over a smooth
+    bottom: a Gaussian mound of height ``amp`` plus a gentle tilted ripple.  sides = "walls":
+    reflective walls all round; "mixed": walls on the bottom and top, extrapolation on the left
+    and right.  The initial guess is the still state itself (cell averages of b subtracted)."""
+    def bottom(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        e = amp * np.exp(-((x - 1.7) ** 2 + (y - 1.1) ** 2) / 0.3)
+        r = 0.05 * np.sin(1.3 * x + 0.4) * np.cos(0.9 * y)
+        b = e + r
+        bx = -e * 2.0 * (x - 1.7) / 0.3 + 0.05 * 1.3 * np.cos(1.3 * x + 0.4) * np.cos(0.9 * y)
+        by = -e * 2.0 * (y - 1.1) / 0.3 - 0.05 * 0.9 * np.sin(1.3 * x + 0.4) * np.sin(0.9 * y)
+        return b, bx, by
+
+    bc = [BC(BC_WALL)] * 4 if sides == "walls" else [BC(BC_EXTRAP), BC(BC_EXTRAP), BC(BC_WALL), BC(BC_WALL)]
+    p = Params(eps=1e-6, omega=0.05, nu1=10, nu2=10, nu3=3)
+    return Problem2D("lake2d", 0.0, 4.0, 0.0, 2.0, nx, ny, levels, bottom, bc, p,
+                     init_state=(surface, 0.0, 0.0), recon=recon, surface0=surface,
+                     meta=dict(surface=surface))
 
 
 def lake_at_rest(n: int = 64, surface: float = 1.0, amp: float = 0.3, levels: int = 3,

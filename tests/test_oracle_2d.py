@@ -117,14 +117,17 @@ def test_y_invariant_flow_between_walls():
         assert np.all(R[c] == R[c][0:1, :])
 
 
-def test_residual_converges_to_cell_average_of_the_pde():
-    """R_ij -> (1/|I_ij|) int (F_x + G_y - S) at third order (interior cells, away from ghosts):
-    the exact average is computed by the divergence theorem with Gauss rules on the edges and
-    a tensor Gauss rule for the source."""
+@pytest.mark.parametrize("recon", [0, 1])
+def test_residual_converges_to_cell_average_of_the_pde(recon):
+    """R_ij -> (1/|I_ij|) int (F_x + G_y - S) at third order (interior cells, away from ghosts),
+    for the paper's reconstruction and for the surface variant: the exact average is computed by
+    the divergence theorem with Gauss rules on the edges and a tensor Gauss rule for the
+    source."""
+    import dataclasses
     bot = smooth_bottom(0.1)
     errs = []
     for n in (16, 32, 64):
-        p = _prob(n, n, bottom=bot, x0=0.0, x1=2.0, y0=0.0, y1=2.0)
+        p = dataclasses.replace(_prob(n, n, bottom=bot, x0=0.0, x1=2.0, y0=0.0, y1=2.0), recon=recon)
         U = cell_avg2(smooth_state, p)
         R = Oracle2D(p).residual(U)[0]
         t, w = np.polynomial.legendre.leggauss(6)
@@ -154,6 +157,57 @@ def test_residual_converges_to_cell_average_of_the_pde():
         errs.append(np.abs(R - ex)[:, 3:-3, 3:-3].max())
     orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
     assert orders[-1] > 2.5, (errs, orders)
+
+
+# ---------------------------------------------------------------------------------------
+# the surface variant (reading S1): still water on any bottom
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sides", ["walls", "mixed"])
+def test_surface_variant_keeps_a_lake_at_rest(sides):
+    """Still water over a mound and a ripple: the surface variant's residual vanishes to
+    rounding (walls all round, or extrapolation left and right), the paper's reconstruction
+    leaves an O(1) residual on the same bottom."""
+    from swe_workloads import lake_at_rest_2d
+    p1 = lake_at_rest_2d(32, 16, recon=1, sides=sides)
+    U = p1.initial_guess()
+    R1 = Oracle2D(p1).residual(U)[0]
+    assert np.abs(R1).max() < 1e-12
+    import dataclasses
+    R0 = Oracle2D(dataclasses.replace(p1, recon=0)).residual(U)[0]
+    assert np.abs(R0).max() > 0.1
+
+
+def test_surface_variant_is_the_paper_scheme_on_a_flat_bottom():
+    """With b = 0 the surface is the depth, the split source vanishes like the paper's, and
+    the ghosts copy the same values: the residual is the paper's bit for bit, at a generic state
+    with every boundary kind of the wedge."""
+    import dataclasses
+    p0 = wedge_problem(32, 16, n_bumps=0)
+    rng = np.random.default_rng(1)
+    U = p0.initial_guess() * (1 + 0.02 * rng.uniform(-1, 1, (3, 16, 32)))
+    R0 = Oracle2D(p0).residual(U)[0]
+    R1 = Oracle2D(dataclasses.replace(p0, recon=1)).residual(U)[0]
+    assert np.array_equal(R0, R1)
+
+
+def test_surface_variant_newton_stays_at_rest_and_reaches_a_flow():
+    """Newton from the still state ends after its first step with res at rounding level; on
+    the wedge (its seeded bumps on the bottom) the surface variant converges in the steps of the
+    paper's scheme, to a solution that differs from it at truncation level."""
+    from swe_workloads import lake_at_rest_2d
+    p = lake_at_rest_2d(16, 8, recon=1, levels=2)
+    U, it, res, _ = Oracle2D(p).newton_solve()
+    assert it == 1 and res < 1e-12
+    assert np.abs(U - p.initial_guess()).max() < 1e-12
+    import dataclasses
+    pw = dataclasses.replace(wedge_problem(32, 16), recon=1)
+    U1, it1, r1, _ = Oracle2D(pw).newton_solve()
+    U0, it0, r0, _ = Oracle2D(dataclasses.replace(pw, recon=0)).newton_solve()
+    assert r1 < 1e-10 and r0 < 1e-10
+    assert abs(it1 - it0) <= max(2, it0 // 5)
+    d = np.abs(U1 - U0).max()
+    assert 1e-6 < d < 0.1, d
 
 
 # ---------------------------------------------------------------------------------------
@@ -196,11 +250,17 @@ def test_j9_matches_closed_form_at_constant_state():
         assert np.allclose(J[j, i, b], exp, atol=3e-5 * np.abs(exp).max() + 1e-6), (di, dj, J[j, i, b], exp)
 
 
-def test_j9_is_j21_on_the_cross_and_brute_force_fd():
+@pytest.mark.parametrize("recon", [0, 1])
+def test_j9_is_j21_on_the_cross_and_brute_force_fd(recon):
+    """J21 holds every nonzero of the global difference quotient (brute force over all unknowns),
+    J9 is its cross, for the paper's reconstruction and the surface variant, with every boundary
+    kind but DISCHARGE in play."""
+    import dataclasses
     rng = np.random.default_rng(2)
     nx, ny, eps = 7, 6, 1e-4
     p = _prob(nx, ny, bottom=smooth_bottom(0.05), x1=1.75, y1=1.5, wall_x=0.6,
               bc=[BC(BC_STATE, h=1.0, u=2.0, v=-0.3), BC(BC_EXTRAP), BC(BC_WALL), BC(BC_DEPTH, h=1.1)])
+    p = dataclasses.replace(p, recon=recon)
     U = np.stack([1.0 + 0.1 * rng.random((ny, nx)), 1.5 + 0.1 * rng.random((ny, nx)),
                   -0.2 + 0.1 * rng.random((ny, nx))])
     o = Oracle2D(p)
