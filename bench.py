@@ -364,6 +364,32 @@ def wedge2d_form():
         errs[name] = {"max_abs_err_vs_oracle": float(np.abs(U.cpu().numpy() - Uo).max()),
                       "newton_steps": st.iters, "oracle_newton_steps": ito}
     out["oracle_check_wedge64x32"] = errs
+    # the surface reconstruction on the same grid: its residual and J9 launches on the wedge, and
+    # still water over a mound and a ripple on 1024 x 512 (max |R|: the paper's scheme against
+    # the surface variant)
+    import dataclasses
+    from swe_workloads import lake_at_rest_2d
+    ss = Solver2D(dataclasses.replace(prob, recon=1), device="cuda:0")
+    U = ss.state()
+    R, rn, _ = ss.residual(U)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(5):
+        ss.residual(U)
+    ev[1].record()
+    for _ in range(5):
+        ss.jacobian(U, R, rn)
+    ev[2].record()
+    torch.cuda.synchronize()
+    lake = lake_at_rest_2d(1024, 512, levels=8)
+    still = {}
+    for name, recon in (("paper", 0), ("surface", 1)):
+        sl = Solver2D(dataclasses.replace(lake, recon=recon), device="cuda:0")
+        still[name] = float(sl.residual(sl.state(lake.initial_guess()))[0].abs().max())
+    out["surface_reconstruction"] = {"residual_ms": ev[0].elapsed_time(ev[1]) / 5,
+                                     "jacobian_j9_ms": ev[1].elapsed_time(ev[2]) / 5,
+                                     "lake_at_rest_1024x512_max_abs_residual": still}
     return out
 
 

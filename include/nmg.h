@@ -90,7 +90,19 @@ typedef struct {
  *   same Gauss rule, eta_j = H_j + zbar_j), so a still surface is steady to rounding on any
  *   bottom.  Ghosts copy the surface where the conserved variant copies H (H_g = H_src +
  *   zbar_src - zbar_g).  It needs z_face [nx+1] (b at the faces) and z_avg [nx+4] (cell
- *   averages of b over cells -2..nx+1, ghosts included).  2D problems take recon = 0. */
+ *   averages of b over cells -2..nx+1, ghosts included).
+ * recon (2D): NMG_RECON_CONSERVED is the paper's scheme of section 4.1.  NMG_RECON_SURFACE: the
+ *   characteristic WENO3 reconstructs (eta, hu, hv) with eta = h + zbar (zbar the cell average
+ *   of b; the characteristic basis stays that of the two cells' (h, hu, hv)), the depth at a
+ *   face Gauss point is eta there minus b at that point, a ghost that copies a cell's depth
+ *   copies its surface instead (h_g = h_src + zbar_src - zbar_g), and the source of each Gauss
+ *   line takes the split form -g [int (eta_h - eta_ij) b_x + eta_ij (b_+ - b_-) - (b_+^2 -
+ *   b_-^2) / 2] (eta_h the cubic through the line's four face values of eta, b_-+ at the cell's
+ *   faces on the line), so still water is steady to rounding on any bottom; with b = 0 it is
+ *   the paper's scheme.  It needs z_avg [ny+4][nx+4] (cell averages of b over cells -2..nx+1 x
+ *   -2..ny+1) and z_face: b at the two Gauss points y_j -+ dy/(2 sqrt 3) of the x faces
+ *   x_{i-1/2}, i = 0..nx ([ny][nx+1][2]), followed by b at the two Gauss points
+ *   x_i -+ dx/(2 sqrt 3) of the y faces y_{j-1/2}, j = 0..ny ([ny+1][nx][2]). */
 #define NMG_RECON_CONSERVED 0
 #define NMG_RECON_SURFACE 1
 typedef struct {

@@ -54,8 +54,11 @@ nmg_status check2d(const nmg_desc *d, const nmg_params *p, bool need_geometry = 
         return set_error(NMG_EINVAL, "coarsest 2D level has more than 40 cells; add levels");
     if ((long long)d->nx * d->ny > (1LL << 28)) return set_error(NMG_EINVAL, "grid too large");
     if (d->jac != 9 && d->jac != 21) return set_error(NMG_EINVAL, "2D jac must be 9 or 21");
-    if (d->recon != NMG_RECON_CONSERVED) return set_error(NMG_EINVAL, "2D problems take recon = 0");
+    if (d->recon != NMG_RECON_CONSERVED && d->recon != NMG_RECON_SURFACE)
+        return set_error(NMG_EINVAL, "recon must be NMG_RECON_CONSERVED or NMG_RECON_SURFACE");
     if (need_geometry && (!d->bx_gp || !d->by_gp)) return set_error(NMG_EINVAL, "null geometry pointer");
+    if (need_geometry && d->recon == NMG_RECON_SURFACE && (!d->z_face || !d->z_avg))
+        return set_error(NMG_EINVAL, "recon = NMG_RECON_SURFACE needs z_face and z_avg");
     if (!(d->x1 > d->x0) || !(d->y1 > d->y0)) return set_error(NMG_EINVAL, "empty domain");
     for (int k = 0; k < 4; k++)
         if (d->bc[k].kind < NMG_BC_DISCHARGE || d->bc[k].kind > NMG_BC_STATE)
@@ -89,6 +92,12 @@ Inst2D make_inst2d(const nmg_desc *d, const nmg_params *p)
     I.wall_x = d->wall_x;
     I.bx = d->bx_gp;
     I.by = d->by_gp;
+    I.recon = d->recon;
+    if (d->recon == NMG_RECON_SURFACE) {
+        I.zavg = d->z_avg;
+        I.zfx = d->z_face;
+        I.zfy = d->z_face ? d->z_face + (long long)d->ny * (d->nx + 1) * 2 : nullptr;
+    }
     I.alpha = p ? p->alpha : 0.0;
     I.eps = p ? p->eps : 1.0;
     return I;

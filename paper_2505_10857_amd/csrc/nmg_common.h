@@ -107,6 +107,11 @@ struct Inst2D {
     const double *bx, *by;     // [Ny][Nx][2][2]: (y point beta, x point gamma)
     double *U, *R, *rn;        // U, R: [3][Ny][Nx]
     double alpha, eps;
+    // surface reconstruction (recon = NMG_RECON_SURFACE): cell averages of b over cells
+    // -2..Nx+1 x -2..Ny+1 ([Ny+4][Nx+4]), b at the two Gauss points of every x face
+    // ([Ny][Nx+1][2]) and of every y face ([Ny+1][Nx][2])
+    int recon;
+    const double *zavg, *zfx, *zfy;
 };
 
 // Colour-blocked cell order of a 2D level: the cells of one colour are stored together, row by

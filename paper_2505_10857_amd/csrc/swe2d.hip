@@ -20,6 +20,13 @@
 // two cells of a side, whose ghosts also follow the perturbed cell, take a separate kernel that
 // re-evaluates all 36 face states per column.
 //
+// Surface variant (recon = NMG_RECON_SURFACE, template flag SURF of the state accessors): the
+// reconstructions act on (eta, hu, hv), eta = h + zbar (zbar the cell average of b), in the
+// characteristic basis of the two cells' (h, hu, hv); a face Gauss point's depth is eta minus b
+// there; ghosts that copy a cell's depth copy its surface; each Gauss line's source takes the
+// split form -g [int (eta_h - eta_ij) b_x + eta_ij (b_+ - b_-) - (b_+^2 - b_-^2) / 2].  Still
+// water then has a zero residual to rounding on any bottom.
+//
 // Register discipline: every helper is force-inlined and passes values as small structs by
 // value, indexed only by compile-time constants; boundary data of a side is selected by
 // comparisons, never by a runtime array index.  The kernels keep their state in registers and
@@ -78,8 +85,11 @@ NMG2D_INL double weno_m2(double um, double u0, double up)
 // from the three consecutive cells S0, S1, S2 of the line that its stencil uses: cells a-1..a+1
 // for the minus state (W = 0, from cell a), a..a+2 for the plus state (W = 1, from cell a+1).
 // The basis is the eigensystem of the face-normal flux Jacobian at the mean of cells a, a+1.
-template <int DIR, int W>
-NMG2D_INL V3 face_state_core(const V3 &S0, const V3 &S1, const V3 &S2, double g)
+// SURF: the projection acts on the surfaces S_q.c[0] + z_q (z_q the cell average of b), the
+// basis on the depths.
+template <int DIR, int W, bool SURF = false>
+NMG2D_INL V3 face_state_core(const V3 &S0, const V3 &S1, const V3 &S2, double g, double z0 = 0.0,
+                             double z1 = 0.0, double z2 = 0.0)
 {
     const V3 &Ua = W ? S0 : S1;
     const V3 &Ub = W ? S1 : S2;
@@ -112,9 +122,10 @@ NMG2D_INL V3 face_state_core(const V3 &S0, const V3 &S1, const V3 &S2, double g)
 #pragma unroll
     for (int q = 0; q < 3; q++) {
         const V3 &Sq = q == 0 ? S0 : (q == 1 ? S1 : S2);
+        const double e = SURF ? Sq.c[0] + (q == 0 ? z0 : (q == 1 ? z1 : z2)) : Sq.c[0];
 #pragma unroll
         for (int f = 0; f < 3; f++)
-            Wc[q][f] = L[f][0] * Sq.c[0] + L[f][1] * Sq.c[1] + L[f][2] * Sq.c[2];
+            Wc[q][f] = L[f][0] * e + L[f][1] * Sq.c[1] + L[f][2] * Sq.c[2];
     }
 #pragma unroll
     for (int f = 0; f < 3; f++)
@@ -198,22 +209,28 @@ NMG2D_INL double cubic_at2(double h0, double h1, double h2, double h3)
 // state of side W of the face between cells A and A+1 (relative to the row cell along the
 // direction DIR) on the line at offset K across it.  bx, by: the cell's bottom slopes at its 2x2
 // Gauss points ([beta][gamma], beta the y point).
+// hm, hp: the first component of the two states at the Gauss points (the depth, or the surface
+// in the surface variant, whose depths are then those minus b0, b1, b at the two points)
 template <int DIR, int A, class FS>
-NMG2D_INL V3 face_flux_at(const FS &fs, double g, H2 &hm, H2 &hp)
+NMG2D_INL V3 face_flux_at(const FS &fs, double g, H2 &hm, H2 &hp, double b0 = 0.0, double b1 = 0.0)
 {
     const V3 Vm0 = fs.template get<DIR, 0, -1, A>(), Vm1 = fs.template get<DIR, 0, 0, A>(),
              Vm2 = fs.template get<DIR, 0, 1, A>();
     const V3 Vp0 = fs.template get<DIR, 1, -1, A>(), Vp1 = fs.template get<DIR, 1, 0, A>(),
              Vp2 = fs.template get<DIR, 1, 1, A>();
-    const V3 Pm0 = gauss_pt2<0>(Vm0, Vm1, Vm2), Pm1 = gauss_pt2<1>(Vm0, Vm1, Vm2);
-    const V3 Pp0 = gauss_pt2<0>(Vp0, Vp1, Vp2), Pp1 = gauss_pt2<1>(Vp0, Vp1, Vp2);
+    V3 Pm0 = gauss_pt2<0>(Vm0, Vm1, Vm2), Pm1 = gauss_pt2<1>(Vm0, Vm1, Vm2);
+    V3 Pp0 = gauss_pt2<0>(Vp0, Vp1, Vp2), Pp1 = gauss_pt2<1>(Vp0, Vp1, Vp2);
+    hm.g[0] = Pm0.c[0]; hm.g[1] = Pm1.c[0];
+    hp.g[0] = Pp0.c[0]; hp.g[1] = Pp1.c[0];
+    if constexpr (FS::surf) {
+        Pm0.c[0] = Pm0.c[0] - b0; Pp0.c[0] = Pp0.c[0] - b0;
+        Pm1.c[0] = Pm1.c[0] - b1; Pp1.c[0] = Pp1.c[0] - b1;
+    }
     const V3 F0 = llf2<DIR>(Pm0, Pp0, g);
     const V3 F1 = llf2<DIR>(Pm1, Pp1, g);
     V3 F;
 #pragma unroll
     for (int c = 0; c < 3; c++) F.c[c] = 0.5 * (F0.c[c] + F1.c[c]);
-    hm.g[0] = Pm0.c[0]; hm.g[1] = Pm1.c[0];
-    hp.g[0] = Pp0.c[0]; hp.g[1] = Pp1.c[0];
     return F;
 }
 
@@ -228,38 +245,62 @@ NMG2D_INL H2 face_depth_at(const FS &fs)
     return hg;
 }
 
+// (i, j): the row cell; h_own: its depth (perturbed when the column perturbs it), which the
+// surface variant's source needs.
 template <class FS>
-NMG2D_INL V3 assemble_residual(const FS &fs, const Inst2D &I, const double bx[4], const double by[4])
+NMG2D_INL V3 assemble_residual(const FS &fs, const Inst2D &I, const double bx[4], const double by[4], int i = 0,
+                               int j = 0, double h_own = 0.0)
 {
     H2 hx0, hx1, hx2, hx3, hy0, hy1, hy2, hy3, dum;
-    const V3 fxm = face_flux_at<0, -1>(fs, I.g, dum, hx1);    // x_{i-1/2}: plus state from cell i
-    const V3 fxp = face_flux_at<0, 0>(fs, I.g, hx2, dum);     // x_{i+1/2}: minus state from cell i
-    const V3 fym = face_flux_at<1, -1>(fs, I.g, dum, hy1);
-    const V3 fyp = face_flux_at<1, 0>(fs, I.g, hy2, dum);
+    // b at the Gauss points of the cell's four faces (surface variant)
+    double bxm0 = 0.0, bxm1 = 0.0, bxp0 = 0.0, bxp1 = 0.0, bym0 = 0.0, bym1 = 0.0, byp0 = 0.0, byp1 = 0.0;
+    if constexpr (FS::surf) {
+        const long long fx = ((long long)j * (I.Nx + 1) + i) * 2, fy = ((long long)j * I.Nx + i) * 2;
+        bxm0 = I.zfx[fx]; bxm1 = I.zfx[fx + 1]; bxp0 = I.zfx[fx + 2]; bxp1 = I.zfx[fx + 3];
+        bym0 = I.zfy[fy]; bym1 = I.zfy[fy + 1];
+        byp0 = I.zfy[fy + 2 * I.Nx]; byp1 = I.zfy[fy + 2 * I.Nx + 1];
+    }
+    const V3 fxm = face_flux_at<0, -1>(fs, I.g, dum, hx1, bxm0, bxm1);    // x_{i-1/2}: plus state from cell i
+    const V3 fxp = face_flux_at<0, 0>(fs, I.g, hx2, dum, bxp0, bxp1);     // x_{i+1/2}: minus state from cell i
+    const V3 fym = face_flux_at<1, -1>(fs, I.g, dum, hy1, bym0, bym1);
+    const V3 fyp = face_flux_at<1, 0>(fs, I.g, hy2, dum, byp0, byp1);
     hx0 = face_depth_at<0, 1, -2>(fs);                        // x_{i-3/2}: plus state, cell i-1
     hx3 = face_depth_at<0, 0, 1>(fs);                         // x_{i+3/2}: minus state, cell i+1
     hy0 = face_depth_at<1, 1, -2>(fs);
     hy3 = face_depth_at<1, 0, 1>(fs);
+    // the surface variant integrates (eta_h - eta_ij) b_x by Gauss points and the rest exactly
+    double eta = 0.0;
+    if constexpr (FS::surf) eta = h_own + I.zavg[((long long)j + 2) * (I.Nx + 4) + i + 2];
     // S2: the cubic in x along each y Gauss line beta at the x Gauss points gamma
     double s2 = 0.0;
 #pragma unroll
     for (int be = 0; be < 2; be++) {
         const double h0 = cubic_at2<0>(hx0.g[be], hx1.g[be], hx2.g[be], hx3.g[be]);
-        s2 = s2 + I.g * h0 * bx[2 * be + 0];
+        s2 = s2 + I.g * (FS::surf ? h0 - eta : h0) * bx[2 * be + 0];
         const double h1 = cubic_at2<1>(hx0.g[be], hx1.g[be], hx2.g[be], hx3.g[be]);
-        s2 = s2 + I.g * h1 * bx[2 * be + 1];
+        s2 = s2 + I.g * (FS::surf ? h1 - eta : h1) * bx[2 * be + 1];
     }
     // S3: the cubic in y along each x Gauss line gamma at the y Gauss points beta
     double s3 = 0.0;
 #pragma unroll
     for (int ga = 0; ga < 2; ga++) {
         const double h0 = cubic_at2<0>(hy0.g[ga], hy1.g[ga], hy2.g[ga], hy3.g[ga]);
-        s3 = s3 + I.g * h0 * by[0 + ga];
+        s3 = s3 + I.g * (FS::surf ? h0 - eta : h0) * by[0 + ga];
         const double h1 = cubic_at2<1>(hy0.g[ga], hy1.g[ga], hy2.g[ga], hy3.g[ga]);
-        s3 = s3 + I.g * h1 * by[2 + ga];
+        s3 = s3 + I.g * (FS::surf ? h1 - eta : h1) * by[2 + ga];
     }
-    const double S2 = -(I.dx * I.dy / 4.0) * s2;
-    const double S3 = -(I.dx * I.dy / 4.0) * s3;
+    double S2 = -(I.dx * I.dy / 4.0) * s2;
+    double S3 = -(I.dx * I.dy / 4.0) * s3;
+    if constexpr (FS::surf) {
+        double e2 = 0.0;
+        e2 = e2 + I.g * (eta * (bxp0 - bxm0) - (bxp0 * bxp0 - bxm0 * bxm0) / 2.0);
+        e2 = e2 + I.g * (eta * (bxp1 - bxm1) - (bxp1 * bxp1 - bxm1 * bxm1) / 2.0);
+        double e3 = 0.0;
+        e3 = e3 + I.g * (eta * (byp0 - bym0) - (byp0 * byp0 - bym0 * bym0) / 2.0);
+        e3 = e3 + I.g * (eta * (byp1 - bym1) - (byp1 * byp1 - bym1 * bym1) / 2.0);
+        S2 = -(I.dx * I.dy / 4.0) * s2 - (I.dy / 2.0) * e2;
+        S3 = -(I.dx * I.dy / 4.0) * s3 - (I.dx / 2.0) * e3;
+    }
     V3 R;
     R.c[0] = (fxp.c[0] - fxm.c[0]) / I.dx + (fyp.c[0] - fym.c[0]) / I.dy;
     R.c[1] = (fxp.c[1] - fxm.c[1]) / I.dx + (fyp.c[1] - fym.c[1]) / I.dy - S2 / (I.dx * I.dy);
@@ -275,25 +316,41 @@ NMG2D_INL double side4(int k, double a0, double a1, double a2, double a3)
     return k == 0 ? a0 : (k == 1 ? a1 : (k == 2 ? a2 : a3));
 }
 
-// state in LDS: s[c][y][x] for cells (i0 - 2 + x, j0 - 2 + y)
-struct LdsState {
-    const double *s;
+// state in LDS: s[c][y][x] for cells (i0 - 2 + x, j0 - 2 + y); SURF: z[y][x], the cell averages
+// of b of the same cells (ghosts included)
+template <bool SURF>
+struct LdsStateT {
+    static constexpr bool surf = SURF;
+    const double *s, *z;
     int i0, j0;
     NMG2D_INL double operator()(int c, int i, int j) const
     {
         NMG2D_CHECK(c >= 0 && c < 3 && j - j0 + 2 >= 0 && j - j0 + 2 < kSY && i - i0 + 2 >= 0 && i - i0 + 2 < kSX);
         return s[(c * kSY + (j - j0 + 2)) * kSX + (i - i0 + 2)];
     }
+    NMG2D_INL double zb(int i, int j) const
+    {
+        NMG2D_CHECK(j - j0 + 2 >= 0 && j - j0 + 2 < kSY && i - i0 + 2 >= 0 && i - i0 + 2 < kSX);
+        return z[(j - j0 + 2) * kSX + (i - i0 + 2)];
+    }
 };
+using LdsState = LdsStateT<false>;
 
-// state in global memory [3][Ny][Nx]
-struct GlobalState {
-    const double *U;
+// state in global memory [3][Ny][Nx]; SURF: zavg [Ny+4][Nx+4] (cells -2..Nx+1 x -2..Ny+1)
+template <bool SURF>
+struct GlobalStateT {
+    static constexpr bool surf = SURF;
+    const double *U, *zavg;
     int Nx, Ny;
     NMG2D_INL double operator()(int c, int i, int j) const
     {
         NMG2D_CHECK(c >= 0 && c < 3 && i >= 0 && i < Nx && j >= 0 && j < Ny);
         return U[((long long)c * Ny + j) * Nx + i];
+    }
+    NMG2D_INL double zb(int i, int j) const
+    {
+        NMG2D_CHECK(i >= -2 && i < Nx + 2 && j >= -2 && j < Ny + 2);
+        return zavg[((long long)j + 2) * (Nx + 4) + i + 2];
     }
 };
 
@@ -345,6 +402,8 @@ NMG2D_INL V3 cell2(const Inst2D &I, const ST &st, int i, int j, int pi, int pj, 
     }
     if (flip_u) out.c[1] = -out.c[1];
     if (flip_v) out.c[2] = -out.c[2];
+    if constexpr (ST::surf)      // a ghost that copies a depth copies the surface
+        if (ii != i || jj != j) out.c[0] = out.c[0] + st.zb(ii, jj) - st.zb(i, j);
     if (set_h >= 0) out.c[0] = side4(set_h, I.bc_h[0], I.bc_h[1], I.bc_h[2], I.bc_h[3]);
     if (set_q >= 0) {
         const double q = side4(set_q, I.bc_q[0], I.bc_q[1], I.bc_q[2], I.bc_q[3]);
@@ -360,12 +419,14 @@ template <int DIR, int W, class ST>
 NMG2D_INL V3 face_state_general(const Inst2D &I, const ST &st, int k, int a, int pi, int pj, int pm, double eps)
 {
     V3 S[3];
+    double z[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 3; q++) {
         const int t = a - 1 + W + q;
         S[q] = DIR == 0 ? cell2(I, st, t, k, pi, pj, pm, eps) : cell2(I, st, k, t, pi, pj, pm, eps);
+        if constexpr (ST::surf) z[q] = DIR == 0 ? st.zb(t, k) : st.zb(k, t);
     }
-    return face_state_core<DIR, W>(S[0], S[1], S[2], I.g);
+    return face_state_core<DIR, W, ST::surf>(S[0], S[1], S[2], I.g, z[0], z[1], z[2]);
 }
 
 // ---- face-state tables of a tile ----------------------------------------------------------
@@ -381,8 +442,9 @@ NMG2D_INL int ys_index(int c, int w, int line, int a)
     return ((c * 2 + w) * kYL + line) * kYA + a;
 }
 
-// thread t of n stages its share of the tile's state
-NMG2D_INL void stage_tile(const Inst2D &I, int i0, int j0, double *s, int t, int n)
+// thread t of n stages its share of the tile's state (and, for the surface variant, the cell
+// averages of b of the same cells, ghosts included, into z)
+NMG2D_INL void stage_tile(const Inst2D &I, int i0, int j0, double *s, int t, int n, double *z = nullptr)
 {
     for (int e = t; e < 3 * kSY * kSX; e += n) {
         const int c = e / (kSY * kSX), r = (e / kSX) % kSY, q = e % kSX;
@@ -390,13 +452,20 @@ NMG2D_INL void stage_tile(const Inst2D &I, int i0, int j0, double *s, int t, int
         const bool ok = i >= 0 && i < I.Nx && j >= 0 && j < I.Ny;
         s[e] = ok ? I.U[((long long)c * I.Ny + j) * I.Nx + i] : 0.0;
     }
+    if (z)
+        for (int e = t; e < kSY * kSX; e += n) {
+            const int r = e / kSX, q = e % kSX;
+            const int i = i0 - 2 + q, j = j0 - 2 + r;
+            const bool ok = i >= -2 && i < I.Nx + 2 && j >= -2 && j < I.Ny + 2;
+            z[e] = ok ? I.zavg[((long long)j + 2) * (I.Nx + 4) + i + 2] : 0.0;
+        }
 }
 
 // every face state the tile's cells use, unperturbed (after stage_tile and a barrier): the minus
 // states (W = 0) of faces i0-1 .. i0+kTX, the plus states (W = 1) of faces i0-2 .. i0+kTX-1 (and
 // the same along y), whose three cells all lie in the staged region
-template <int W>
-NMG2D_INL void face_tables_side(const Inst2D &I, const LdsState &st, double *xs, double *ys, int t, int n)
+template <int W, class ST>
+NMG2D_INL void face_tables_side(const Inst2D &I, const ST &st, double *xs, double *ys, int t, int n)
 {
     constexpr int xa = kXA - 1, ya = kYA - 1;      // faces per line used on this side
     for (int e = t; e < kXL * xa; e += n) {
@@ -413,14 +482,17 @@ NMG2D_INL void face_tables_side(const Inst2D &I, const LdsState &st, double *xs,
     }
 }
 
-NMG2D_INL void face_tables(const Inst2D &I, const LdsState &st, double *xs, double *ys, int t, int n)
+template <class ST>
+NMG2D_INL void face_tables(const Inst2D &I, const ST &st, double *xs, double *ys, int t, int n)
 {
     face_tables_side<0>(I, st, xs, ys, t, n);
     face_tables_side<1>(I, st, xs, ys, t, n);
 }
 
 // face states of the row cell (i, j) read from the tables
+template <bool SURF>
 struct TableFS {
+    static constexpr bool surf = SURF;
     const double *xs, *ys;
     int xi, xj;        // the row cell relative to the tables' origins: i - i0, j - j0
     template <int DIR, int W, int K, int A>
@@ -438,10 +510,11 @@ struct TableFS {
 // Face states of an interior row cell under a perturbation of component pm of the cell at the
 // offset (DX, DY) of the cross stencil: a state whose three cells include that cell is
 // recomputed from the staged state, every other one read from the tables.
-template <int DX, int DY>
+template <int DX, int DY, bool SURF>
 struct PerturbedFS {
-    TableFS tab;
-    LdsState st;
+    static constexpr bool surf = SURF;
+    TableFS<SURF> tab;
+    LdsStateT<SURF> st;
     int i, j, pm;
     double eps, g;
 
@@ -472,8 +545,15 @@ struct PerturbedFS {
     NMG2D_INL V3 get() const
     {
         if constexpr (hit<DIR, W, K, A>()) {
-            return face_state_core<DIR, W>(cell<DIR, W, K, A, 0>(), cell<DIR, W, K, A, 1>(),
-                                           cell<DIR, W, K, A, 2>(), g);
+            constexpr int t0 = A - 1 + W;
+            double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+            if constexpr (SURF) {
+                z0 = DIR == 0 ? st.zb(i + t0, j + K) : st.zb(i + K, j + t0);
+                z1 = DIR == 0 ? st.zb(i + t0 + 1, j + K) : st.zb(i + K, j + t0 + 1);
+                z2 = DIR == 0 ? st.zb(i + t0 + 2, j + K) : st.zb(i + K, j + t0 + 2);
+            }
+            return face_state_core<DIR, W, SURF>(cell<DIR, W, K, A, 0>(), cell<DIR, W, K, A, 1>(),
+                                                 cell<DIR, W, K, A, 2>(), g, z0, z1, z2);
         } else {
             return tab.template get<DIR, W, K, A>();
         }
@@ -492,16 +572,18 @@ NMG2D_INL void load_slopes(const Inst2D &I, int i, int j, double bx[4], double b
     }
 }
 
+template <bool SURF>
 __global__ void __launch_bounds__(kTX * kTY) k_residual2d(Inst2D I, double *partial)
 {
     __shared__ double s[3 * kSY * kSX];
+    __shared__ double zs[SURF ? kSY * kSX : 1];
     __shared__ double xs[kXS], ys[kYS];
     __shared__ double red[kTX * kTY / 64];
     const int i0 = blockIdx.x * kTX, j0 = blockIdx.y * kTY;
     const int tid = threadIdx.y * kTX + threadIdx.x;
-    stage_tile(I, i0, j0, s, tid, kTX * kTY);
+    stage_tile(I, i0, j0, s, tid, kTX * kTY, SURF ? zs : nullptr);
     __syncthreads();
-    const LdsState st{s, i0, j0};
+    const LdsStateT<SURF> st{s, zs, i0, j0};
     face_tables(I, st, xs, ys, tid, kTX * kTY);
     __syncthreads();
     const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
@@ -509,8 +591,8 @@ __global__ void __launch_bounds__(kTX * kTY) k_residual2d(Inst2D I, double *part
     if (i < I.Nx && j < I.Ny) {
         double bx[4], by[4];
         load_slopes(I, i, j, bx, by);
-        const TableFS fs{xs, ys, i - i0, j - j0};
-        const V3 R = assemble_residual(fs, I, bx, by);
+        const TableFS<SURF> fs{xs, ys, i - i0, j - j0};
+        const V3 R = assemble_residual(fs, I, bx, by, i, j, st(0, i, j));
         const long long n = (long long)I.Nx * I.Ny, cidx = (long long)j * I.Nx + i;
         I.R[cidx] = R.c[0];
         I.R[n + cidx] = R.c[1];
@@ -602,20 +684,26 @@ NMG2D_INL bool border_row(const Inst2D &I, int i, int j)
     return i < 2 || j < 2 || i >= I.Nx - 2 || j >= I.Ny - 2;
 }
 
-template <int B, typename T>
-NMG2D_INL void interior_column(T *J, const JacOut &o, const TableFS &tab, const LdsState &st, const Inst2D &I,
-                               int i, int j, int m, const double bx[4], const double by[4], double d[3])
+template <int B, typename T, bool SURF>
+NMG2D_INL void interior_column(T *J, const JacOut &o, const TableFS<SURF> &tab, const LdsStateT<SURF> &st,
+                               const Inst2D &I, int i, int j, int m, const double bx[4], const double by[4],
+                               double d[3])
 {
-    const PerturbedFS<stencil_dx(21, B), stencil_dy(21, B)> fs{tab, st, i, j, m, I.eps, I.g};
-    const V3 Rp = assemble_residual(fs, I, bx, by);
+    const PerturbedFS<stencil_dx(21, B), stencil_dy(21, B), SURF> fs{tab, st, i, j, m, I.eps, I.g};
+    double h_own = 0.0;
+    if constexpr (SURF) {
+        const double x = st(0, i, j);
+        h_own = (B == 0 && m == 0) ? x + I.eps : x;
+    }
+    const V3 Rp = assemble_residual(fs, I, bx, by, i, j, h_own);
     store_column(J, o, B, m, Rp, d);
 }
 
 // the 3 NB columns of the interior row (i, j) of a tile whose state and face tables are staged
 // (the first nine blocks of the full stencil are the cross, so one offset table serves both)
-template <typename T, int NB>
+template <typename T, int NB, bool SURF>
 NMG2D_INL void jacobian_interior_row(const Inst2D &I, const Perm2D &Pm, T *J, T *rhs, T *Dinv, const double *xs,
-                                     const double *ys, const LdsState &st, int i, int j)
+                                     const double *ys, const LdsStateT<SURF> &st, int i, int j)
 {
     const int i0 = st.i0, j0 = st.j0;
     const long long n = (long long)I.Nx * I.Ny, cidx = (long long)j * I.Nx + i;
@@ -635,7 +723,7 @@ NMG2D_INL void jacobian_interior_row(const Inst2D &I, const Perm2D &Pm, T *J, T 
     }
     double bx[4], by[4];
     load_slopes(I, i, j, bx, by);
-    const TableFS tab{xs, ys, i - i0, j - j0};
+    const TableFS<SURF> tab{xs, ys, i - i0, j - j0};
     double D[9];
 #pragma unroll
     for (int e = 0; e < 9; e++) D[e] = 0.0;
@@ -686,26 +774,29 @@ NMG2D_INL void jacobian_interior_row(const Inst2D &I, const Perm2D &Pm, T *J, T 
 // Finite-difference Jacobian (eq. 12, 13) of the rows at least two cells inside the grid, one
 // thread per row: for each component m, the NB columns of the stencil.  Optionally the finest
 // right-hand side (= R) and the inverse of the diagonal block.
-template <typename T, int NB>
+template <typename T, int NB, bool SURF>
 __global__ void __launch_bounds__(kTX * kTY) k_jacobian2d(Inst2D I, Perm2D Pm, T *J, T *rhs, T *Dinv)
 {
     __shared__ double s[3 * kSY * kSX];
+    __shared__ double zs[SURF ? kSY * kSX : 1];
     __shared__ double xs[kXS], ys[kYS];
     const int i0 = blockIdx.x * kTX, j0 = blockIdx.y * kTY;
     const int tid = threadIdx.y * kTX + threadIdx.x;
-    stage_tile(I, i0, j0, s, tid, kTX * kTY);
+    stage_tile(I, i0, j0, s, tid, kTX * kTY, SURF ? zs : nullptr);
     __syncthreads();
-    const LdsState st{s, i0, j0};
+    const LdsStateT<SURF> st{s, zs, i0, j0};
     face_tables(I, st, xs, ys, tid, kTX * kTY);
     __syncthreads();
     const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
     if (i >= I.Nx || j >= I.Ny || border_row(I, i, j)) return;
-    jacobian_interior_row<T, NB>(I, Pm, J, rhs, Dinv, xs, ys, st, i, j);
+    jacobian_interior_row<T, NB, SURF>(I, Pm, J, rhs, Dinv, xs, ys, st, i, j);
 }
 
 // Face states of a border row, full re-evaluation: the 36 states sit in per-thread LDS slots,
 // slot q at slots[(q*3 + c) * kBorderNT + lane].
+template <bool SURF>
 struct SlotFS {
+    static constexpr bool surf = SURF;
     const double *slots;
     int lane;
     // slot of a face state: per direction 18, in the order A = -1 (6: W, K), A = 0 (6),
@@ -771,7 +862,7 @@ long long border_rows2d(int Nx, int Ny)
 
 // column col (b*3 + m) of border row number r, its face states in the slot array at lane `lane`
 // (stride kBorderNT); d: the column's FP64 values.  Returns the row's output slot.
-template <typename T>
+template <typename T, bool SURF>
 NMG2D_INL long long jacobian_border_column(const Inst2D &I, const Perm2D &Pm, T *J, T *rhs, double *slots, int lane,
                                            long long r, int col, double d[3])
 {
@@ -798,7 +889,7 @@ NMG2D_INL long long jacobian_border_column(const Inst2D &I, const Perm2D &Pm, T 
         store_zero_column(J, o, b, m);
         return o.slot;
     }
-    const GlobalState st{I.U, I.Nx, I.Ny};
+    const GlobalStateT<SURF> st{I.U, I.zavg, I.Nx, I.Ny};
 #pragma unroll 1
     for (int q = 0; q < kSlots; q++) {
         const V3 v = slot_state(I, st, q, i, j, pi, pj, m, I.eps);
@@ -807,8 +898,13 @@ NMG2D_INL long long jacobian_border_column(const Inst2D &I, const Perm2D &Pm, T 
     }
     double bx[4], by[4];
     load_slopes(I, i, j, bx, by);
-    const SlotFS fs{slots, lane};
-    const V3 Rp = assemble_residual(fs, I, bx, by);
+    const SlotFS<SURF> fs{slots, lane};
+    double h_own = 0.0;
+    if constexpr (SURF) {
+        const double x = st(0, i, j);
+        h_own = (pi == i && pj == j && m == 0) ? x + I.eps : x;
+    }
+    const V3 Rp = assemble_residual(fs, I, bx, by, i, j, h_own);
     store_column(J, o, b, m, Rp, d);
     return o.slot;
 }
@@ -818,7 +914,7 @@ NMG2D_INL long long jacobian_border_column(const Inst2D &I, const Perm2D &Pm, T 
 // LPR lanes of a wavefront (32 for the 27 columns of J9, 64 for the 63 of J21), so the lanes of
 // its three diagonal-block columns can hand their FP64 values to the row's first lane, which
 // writes the inverse of the diagonal block.
-template <typename T, int NB>
+template <typename T, int NB, bool SURF>
 __global__ void __launch_bounds__(kBorderNT) k_jacobian2d_border(Inst2D I, Perm2D Pm, T *J, T *rhs, T *Dinv,
                                                                  long long nrows)
 {
@@ -831,7 +927,7 @@ __global__ void __launch_bounds__(kBorderNT) k_jacobian2d_border(Inst2D I, Perm2
     const bool active = r < nrows && col < 3 * NB;
     double d[3] = {0.0, 0.0, 0.0};
     long long slot = 0;
-    if (active) slot = jacobian_border_column(I, Pm, J, rhs, slots, threadIdx.x, r, col, d);
+    if (active) slot = jacobian_border_column<T, SURF>(I, Pm, J, rhs, slots, threadIdx.x, r, col, d);
     if (!Dinv) return;   // uniform over the launch
     // the diagonal block's columns m = 0, 1, 2 sit in lanes 0, 1, 2 of the row's LPR
     const int base = threadIdx.x & ~(LPR - 1);
@@ -848,7 +944,8 @@ __global__ void __launch_bounds__(kBorderNT) k_jacobian2d_border(Inst2D I, Perm2
 hipError_t launch_residual2d(const Inst2D &I, double *partial, hipStream_t s)
 {
     dim3 grid((I.Nx + kTX - 1) / kTX, (I.Ny + kTY - 1) / kTY);
-    hipLaunchKernelGGL(k_residual2d, grid, dim3(kTX, kTY), 0, s, I, partial);
+    if (I.recon == NMG_RECON_SURFACE) hipLaunchKernelGGL(k_residual2d<true>, grid, dim3(kTX, kTY), 0, s, I, partial);
+    else hipLaunchKernelGGL(k_residual2d<false>, grid, dim3(kTX, kTY), 0, s, I, partial);
     return hipGetLastError();
 }
 
@@ -861,31 +958,36 @@ hipError_t launch_res2d_finalize(const double *partial, int ntiles, long long nc
     return hipGetLastError();
 }
 
-template <typename T, int NB>
+template <typename T, int NB, bool SURF>
 static hipError_t jacobian2d_t(const Inst2D &I, const Perm2D &P, T *J, T *rhs, T *Dinv, hipStream_t s)
 {
     constexpr int LPR = NB == 9 ? 32 : 64;
     dim3 grid((I.Nx + kTX - 1) / kTX, (I.Ny + kTY - 1) / kTY);
-    hipLaunchKernelGGL((k_jacobian2d<T, NB>), grid, dim3(kTX, kTY), 0, s, I, P, J, rhs, Dinv);
+    hipLaunchKernelGGL((k_jacobian2d<T, NB, SURF>), grid, dim3(kTX, kTY), 0, s, I, P, J, rhs, Dinv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long nb = border_rows2d(I.Nx, I.Ny);
     const long long blocks = (nb * LPR + kBorderNT - 1) / kBorderNT;
-    hipLaunchKernelGGL((k_jacobian2d_border<T, NB>), dim3((unsigned)blocks), dim3(kBorderNT), 0, s, I, P, J, rhs,
-                       Dinv, nb);
+    hipLaunchKernelGGL((k_jacobian2d_border<T, NB, SURF>), dim3((unsigned)blocks), dim3(kBorderNT), 0, s, I, P, J,
+                       rhs, Dinv, nb);
     return hipGetLastError();
+}
+
+template <typename T, bool SURF>
+static hipError_t jacobian2d_nb(const Inst2D &I, const Perm2D &P, void *J, void *rhs, void *Dinv, int nb, hipStream_t s)
+{
+    if (nb == 21) return jacobian2d_t<T, 21, SURF>(I, P, (T *)J, (T *)rhs, (T *)Dinv, s);
+    return jacobian2d_t<T, 9, SURF>(I, P, (T *)J, (T *)rhs, (T *)Dinv, s);
 }
 
 hipError_t launch_jacobian2d(const Inst2D &I, const Perm2D &P, void *J, void *rhs, void *Dinv, int prec,
                              hipStream_t s, int nb)
 {
     if (nb != 9 && nb != 21) return hipErrorInvalidValue;
-    if (prec == NMG_FP32_MG) {
-        if (nb == 21) return jacobian2d_t<float, 21>(I, P, (float *)J, (float *)rhs, (float *)Dinv, s);
-        return jacobian2d_t<float, 9>(I, P, (float *)J, (float *)rhs, (float *)Dinv, s);
-    }
-    if (nb == 21) return jacobian2d_t<double, 21>(I, P, (double *)J, (double *)rhs, (double *)Dinv, s);
-    return jacobian2d_t<double, 9>(I, P, (double *)J, (double *)rhs, (double *)Dinv, s);
+    const bool surf = I.recon == NMG_RECON_SURFACE;
+    if (prec == NMG_FP32_MG)
+        return surf ? jacobian2d_nb<float, true>(I, P, J, rhs, Dinv, nb, s) : jacobian2d_nb<float, false>(I, P, J, rhs, Dinv, nb, s);
+    return surf ? jacobian2d_nb<double, true>(I, P, J, rhs, Dinv, nb, s) : jacobian2d_nb<double, false>(I, P, J, rhs, Dinv, nb, s);
 }
 
 }  // namespace nmg

@@ -303,6 +303,14 @@ class Problem2DDevice:
         d.wall_x = prob.wall_x
         d.bx_gp = self.bx_gp.data_ptr()
         d.by_gp = self.by_gp.data_ptr()
+        d.recon = getattr(prob, "recon", 0)
+        if d.recon == A.NMG_RECON_SURFACE:
+            from swe_workloads import bottom_samples_2d
+            za, zfx, zfy = bottom_samples_2d(prob)
+            self.z_avg = torch.tensor(za, **f64)
+            self.z_face = torch.tensor(np.concatenate([zfx.ravel(), zfy.ravel()]), **f64)
+            d.z_avg = self.z_avg.data_ptr()
+            d.z_face = self.z_face.data_ptr()
         self.desc = d
         self.device = device
 

@@ -178,3 +178,21 @@ def test_static_newton_solve_rejects_on_the_host():
     bad, pbad = _desc(abi, nx=60, levels=4)
     assert L.nmg_newton_solve_static(ctypes.byref(bad), ctypes.byref(pbad), ctypes.c_void_p(256),
                                      ctypes.byref(st), None, 0, None) == abi.NMG_EINVAL
+
+
+def test_2d_surface_reconstruction_needs_its_bottom_samples():
+    """recon = NMG_RECON_SURFACE in 2D needs z_avg and z_face; the check runs on the host before
+    any launch.  Other recon values are rejected."""
+    abi, L = _lib()
+    d = abi.nmg_desc()
+    d.dim, d.nx, d.ny, d.levels, d.jac, d.recon = 2, 32, 16, 3, 9, abi.NMG_RECON_SURFACE
+    d.x0, d.x1, d.y0, d.y1, d.g = 0.0, 4.0, 0.0, 2.0, 9.81
+    for k in range(4):
+        d.bc[k].kind = abi.NMG_BC_WALL
+    d.bx_gp = d.by_gp = 4096
+    U = ctypes.c_void_p(8192)
+    assert L.nmg_residual(ctypes.byref(d), U, U, U, None, None) == abi.NMG_EINVAL
+    assert b"z_face and z_avg" in L.nmg_last_error()
+    d.recon = 2
+    assert L.nmg_residual(ctypes.byref(d), U, U, U, None, None) == abi.NMG_EINVAL
+    assert b"recon" in L.nmg_last_error()
