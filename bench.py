@@ -320,6 +320,7 @@ def wedge2d_form():
     import torch
     import oracle.swe2d
     from paper_2505_10857_amd import NMG_FP32_MG, NMG_FP64, Solver2D
+    from paper_2505_10857_amd import _abi as A
     from swe_workloads import wedge_problem
     prob = wedge_problem(1024, 512)
     cells = prob.nx * prob.ny
@@ -356,6 +357,7 @@ def wedge2d_form():
     out["fp32mg"]["max_abs_diff_vs_fp64_gpu"] = float((states["fp32mg"] - states["fp64"]).abs().max())
     small = wedge_problem(64, 32)
     Uo, ito, reso, _ = oracle.swe2d.Oracle2D(small).newton_solve()
+    Uo_sw, _, _, _ = oracle.swe2d.Oracle2D(small).newton_solve(smoother=1)
     errs = {}
     for name, prec in (("fp64", NMG_FP64), ("fp32mg", NMG_FP32_MG)):
         s = Solver2D(small, device="cuda:0", precision=prec, check_every=8)
@@ -387,6 +389,19 @@ def wedge2d_form():
     for name, recon in (("paper", 0), ("surface", 1)):
         sl = Solver2D(dataclasses.replace(lake, recon=recon), device="cuda:0")
         still[name] = float(sl.residual(sl.state(lake.initial_guess()))[0].abs().max())
+    # the paper's smoother (directional sweeps D1-D4, one workgroup per level) against the
+    # multicolour one on the 64 x 32 wedge: Newton steps and time per solve
+    smoothers = {}
+    for name, lin in (("multicolour", A.NMG_LINEAR_MG), ("sweeps_d1_d4", A.NMG_LINEAR_MG_SWEEPS)):
+        s = Solver2D(small, device="cuda:0", check_every=8, linear=lin)
+        U = s.state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, _ = s.newton_solve(U)
+        torch.cuda.synchronize()
+        smoothers[name] = {"newton_steps": st.iters, "status": st.status, "seconds_per_solve": time.perf_counter() - t0,
+                           "max_abs_err_vs_oracle": float(np.abs(U.cpu().numpy() - (Uo if lin == A.NMG_LINEAR_MG else Uo_sw)).max())}
+    out["smoothers_wedge64x32"] = smoothers
     out["surface_reconstruction"] = {"residual_ms": ev[0].elapsed_time(ev[1]) / 5,
                                      "jacobian_j9_ms": ev[1].elapsed_time(ev[2]) / 5,
                                      "lake_at_rest_1024x512_max_abs_residual": still}

@@ -124,6 +124,13 @@ typedef struct {
  * smoothing steps, nu3 V-cycles per Newton step, tol on res = mean ||R_j||_1, n_max Newton
  * steps.  check_every: Newton steps between host reads of the convergence state in
  * nmg_newton_solve / nmg_plan_solve (>= 1).
+ * linear (2D): NMG_LINEAR_MG: nu3 V-cycles with the multicolour block SOR of eq. (22);
+ * NMG_LINEAR_MG_SWEEPS: the same V-cycles smoothed by the paper's four directional sweeps D1-D4
+ * of section 4.2 (x ascending with y ascending inside, x descending, both descending, y
+ * descending), each a lexicographic block SOR with the oracle's results; a sweep runs the
+ * hyperplanes i' + j' = h (3 i' + j' for jac = 21) of its order one after another in one
+ * workgroup per level, so it is meant for grids of at most 65536 cells (larger grids return
+ * NMG_EINVAL), for comparisons of Newton steps with the paper's smoother.
  * linear (1D): how each Newton step solves the regularised system.  NMG_LINEAR_MG: nu3 V-cycles
  * (Algorithm 2).  NMG_LINEAR_SOR / NMG_LINEAR_SOR_LEX: the Newton-SOR reference solver of
  * section 5.1.1 -- symmetric block SOR steps on the grid itself (multicolour, or the
@@ -134,6 +141,7 @@ typedef struct {
 #define NMG_LINEAR_MG 0
 #define NMG_LINEAR_SOR 1
 #define NMG_LINEAR_SOR_LEX 2
+#define NMG_LINEAR_MG_SWEEPS 3
 typedef struct {
     double alpha, tau, eps, omega, tol;
     int32_t nu1, nu2, nu3, n_max;

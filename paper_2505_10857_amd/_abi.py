@@ -31,6 +31,7 @@ NMG_RECON_SURFACE = 1
 NMG_LINEAR_MG = 0
 NMG_LINEAR_SOR = 1
 NMG_LINEAR_SOR_LEX = 2
+NMG_LINEAR_MG_SWEEPS = 3
 
 EXPORTS = [
     "nmg_workspace_bytes", "nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",

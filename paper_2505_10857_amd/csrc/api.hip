@@ -964,6 +964,7 @@ nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *w
 {
     if (desc && desc->dim == 2) return vcycle2d(desc, params, ws, ws_bytes, J, rhs, dU, setup, (hipStream_t)stream);
     if (!ws || !rhs || !dU || (setup && !J)) return fail(NMG_EINVAL, "null argument");
+    if (params && params->linear == NMG_LINEAR_MG_SWEEPS) return fail(NMG_EINVAL, "the directional sweeps are 2D only");
     if (params && params->linear != NMG_LINEAR_MG) return fail(NMG_EINVAL, "a V-cycle needs linear = NMG_LINEAR_MG");
     nmg_plan P;
     nmg_status st = build_plan(&P, desc, params, 1);

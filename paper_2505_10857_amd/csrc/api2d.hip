@@ -35,6 +35,7 @@ struct Plan2D {
     Inst2D I;
     int levels = 0, prec = NMG_FP64, nu1 = 0, nu2 = 0, nu3 = 1, n_max = 0, max_hist = 0, ntiles = 0;
     int check_every = 1;
+    int sweeps = 0;            // smoother: the directional sweeps D1-D4 (NMG_LINEAR_MG_SWEEPS)
     int bottom_first = 0;      // first level of the one-workgroup bottom (launch_bottom2d)
     double tau = 0.0, omega = 1.0, tol = 0.0;
     std::vector<Level2D> L;
@@ -68,6 +69,10 @@ nmg_status check2d(const nmg_desc *d, const nmg_params *p, bool need_geometry = 
         return set_error(NMG_EINVAL, "bad nu1/nu2/nu3/n_max");
     if (p->nu1 > 1000 || p->nu2 > 1000 || p->nu3 > 1000) return set_error(NMG_EINVAL, "nu above 1000");
     if (p->precision != NMG_FP64 && p->precision != NMG_FP32_MG) return set_error(NMG_EINVAL, "bad precision");
+    if (p->linear != NMG_LINEAR_MG && p->linear != NMG_LINEAR_MG_SWEEPS)
+        return set_error(NMG_EINVAL, "2D linear must be NMG_LINEAR_MG or NMG_LINEAR_MG_SWEEPS");
+    if (p->linear == NMG_LINEAR_MG_SWEEPS && (long long)d->nx * d->ny > 65536)
+        return set_error(NMG_EINVAL, "the directional sweeps take grids of at most 65536 cells");
     return NMG_OK;
 }
 
@@ -116,6 +121,7 @@ nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p, bool need_
     P.n_max = p->n_max;
     P.max_hist = std::min(std::max(p->n_max, 1), 100000);
     P.check_every = std::max(1, p->check_every);
+    P.sweeps = p->linear == NMG_LINEAR_MG_SWEEPS ? 1 : 0;
     P.tau = p->tau;
     P.omega = p->omega;
     P.tol = p->tol;
@@ -163,6 +169,10 @@ nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p, bool need_
 nmg_status smooth(const Plan2D &P, char *mgb, int l, int nu, hipStream_t s)
 {
     const Level2D &L = P.L[l];
+    if (P.sweeps) {
+        if (nu > 0) HIP_TRY2(launch_sweeps2d(mgb, L, nu, P.omega, P.prec, s));
+        return NMG_OK;
+    }
     const int C = L.P.C;
     int cur = -1, run = 0;
     for (int it = 0; it < nu; it++)
@@ -183,7 +193,7 @@ nmg_status vcycle_from(const Plan2D &P, char *mgb, int l, hipStream_t s)
 {
     if (l >= P.bottom_first) {
         HIP_TRY2(launch_bottom2d(mgb, P.L.data(), l, P.levels, P.nu1, P.nu2, P.omega,
-                                 (const double *)(mgb - P.off_mg + P.off_lu), P.prec, s));
+                                 (const double *)(mgb - P.off_mg + P.off_lu), P.prec, s, P.sweeps));
         return NMG_OK;
     }
     nmg_status st;

@@ -285,6 +285,77 @@ __global__ void __launch_bounds__(3 * kSplitCells) k_smooth2d_split(T *mg, Level
     mg[L.dU + c * n + cc] = d;
 }
 
+// ---- the four directional sweeps D1-D4 of section 4.2 (eq. 22 in a lexicographic order) ------
+
+// eq. (22) for cell (i, j) in place: r = rhs + the off-diagonal blocks (in stencil order) times the
+// current dU of the neighbours in the grid, dU <- (1 - omega) dU - omega D^{-1} r
+template <typename T, int NB>
+__device__ __forceinline__ void relax_cell(T *mg, const Level2D &L, int i, int j, double omega)
+{
+    const long long n = L.P.M, cc = perm2d(L.P, i, j);
+    const T *Jr = mg + L.J + cc;
+    const T *Ur = mg + L.dU;
+    double r[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) r[c] = ld2(mg + L.rhs, c * n + cc);
+    // a rolled loop: the sweeps wait on their hyperplanes' barriers, not on these loads, and an
+    // unrolled one would crowd the registers of the kernels it is inlined into
+#pragma unroll 1
+    for (int b = 1; b < NB; b++) {
+        int di, dj;
+        stencil_off(NB, b, di, dj);
+        const int pi = i + di, pj = j + dj;
+        if (pi < 0 || pi >= L.nx || pj < 0 || pj >= L.ny) continue;
+        const long long q = perm2d(L.P, pi, pj);
+        const double x0 = (double)Ur[q], x1 = (double)Ur[n + q], x2 = (double)Ur[2 * n + q];
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            r[c] = r[c] + ((double)Jr[(b * 9 + c * 3 + 0) * n] * x0 + (double)Jr[(b * 9 + c * 3 + 1) * n] * x1 +
+                           (double)Jr[(b * 9 + c * 3 + 2) * n] * x2);
+    }
+    double t[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+        t[c] = ld2(mg + L.Dinv, (c * 3 + 0) * n + cc) * r[0] + ld2(mg + L.Dinv, (c * 3 + 1) * n + cc) * r[1] +
+               ld2(mg + L.Dinv, (c * 3 + 2) * n + cc) * r[2];
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+        mg[L.dU + c * n + cc] = (T)((1.0 - omega) * ld2(mg + L.dU, c * n + cc) - omega * t[c]);
+}
+
+// nu smoothing iterations of the sweeps D1 (x ascending, y ascending inside), D2 (x descending),
+// D3 (both descending), D4 (y descending) on one level, by one workgroup.  In the coordinates
+// (i', j') of a sweep (i' the outer index) a cell needs the new values of the coupled cells with
+// A i' + j' smaller and the old ones of those with it larger (A = 1 for the cross and five-point
+// stencils, 3 for the full 21 cells, whose couplings reach (1, -2)); the cells of one hyperplane
+// A i' + j' = h are not coupled, so the hyperplanes run in order, each in parallel: the same
+// result as the sequential sweep, bit for bit.
+template <typename T, int NB>
+__device__ void sweeps_level(T *mg, const Level2D &L, int nu, double omega)
+{
+    constexpr int A = NB == 21 ? 3 : 1;
+    const int nx = L.nx, ny = L.ny, H = A * (nx - 1) + ny;
+    for (int it = 0; it < nu; it++)
+        for (int d = 0; d < 4; d++) {
+            const bool fi = d == 1 || d == 2, fj = d >= 2;
+            for (int h = 0; h < H; h++) {
+                const int lo = h - (ny - 1) > 0 ? (h - (ny - 1) + A - 1) / A : 0;
+                const int hi = nx - 1 < h / A ? nx - 1 : h / A;
+                for (int k = lo + (int)threadIdx.x; k <= hi; k += blockDim.x) {
+                    const int jp = h - A * k;
+                    relax_cell<T, NB>(mg, L, fi ? nx - 1 - k : k, fj ? ny - 1 - jp : jp, omega);
+                }
+                __syncthreads();
+            }
+        }
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(256) k_sweeps2d(T *mg, Level2D L, int nu, double omega)
+{
+    sweeps_level<T, NB>(mg, L, nu, omega);
+}
+
 // eq. (24), right-hand side of coarse cell (I, Jq); also clears its dU.
 // rhs + J dU of fine cell (fi, fj), the summand of eq. (24)'s restriction
 template <typename T>
@@ -535,14 +606,20 @@ struct Bottom2DArgs {
     int first, levels, nu1, nu2;
     double omega;
     const double *lu;
+    int sweeps;          // smoother: 0 the multicolour schedule, 1 the directional sweeps D1-D4
 };
 
 // NBF: the stencil of the bottom's first level (the finest level when the whole hierarchy fits
 // one workgroup, else a five-point level); the levels below it have five points.  Only the
 // passes a launch can meet are compiled into it, which keeps the kernel's registers down.
 template <typename T, int NBF>
-__device__ void bottom_smooth(T *mg, const Level2D &L, int nu, double omega)
+__device__ void bottom_smooth(T *mg, const Level2D &L, int nu, double omega, int sweeps)
 {
+    if (sweeps) {
+        if (NBF != 5 && L.nb == NBF) sweeps_level<T, NBF>(mg, L, nu, omega);
+        else sweeps_level<T, 5>(mg, L, nu, omega);
+        return;
+    }
     const int C = L.P.C;
     const long long slots = (long long)L.P.ny * L.P.W;
     int cur = -1, run = 0;
@@ -574,7 +651,7 @@ __global__ void __launch_bounds__(512) k_bottom2d(T *mg, Bottom2DArgs B)
     __shared__ double x[MM];
     const int last = B.levels - 1;
     for (int l = B.first; l < last; l++) {
-        bottom_smooth<T, NBF>(mg, B.L[l], B.nu1, B.omega);
+        bottom_smooth<T, NBF>(mg, B.L[l], B.nu1, B.omega, B.sweeps);
         const Level2D &Lc = B.L[l + 1];
         for (int e = threadIdx.x; e < Lc.nx * Lc.ny; e += blockDim.x) restrict_cell(mg, B.L[l], Lc, e % Lc.nx, e / Lc.nx);
         __syncthreads();
@@ -585,7 +662,7 @@ __global__ void __launch_bounds__(512) k_bottom2d(T *mg, Bottom2DArgs B)
         const Level2D &Lf = B.L[l];
         for (int e = threadIdx.x; e < Lf.nx * Lf.ny; e += blockDim.x) prolong_cell(mg, Lf, B.L[l + 1], e % Lf.nx, e / Lf.nx);
         __syncthreads();
-        bottom_smooth<T, NBF>(mg, Lf, B.nu2, B.omega);
+        bottom_smooth<T, NBF>(mg, Lf, B.nu2, B.omega, B.sweeps);
     }
 }
 
@@ -801,8 +878,24 @@ hipError_t launch_coarse_factor2d(void *mg, const Level2D &L, double *lu, int pr
     return hipGetLastError();
 }
 
+hipError_t launch_sweeps2d(void *mg, const Level2D &L, int nu, double omega, int prec, hipStream_t s)
+{
+    const bool f32 = prec == NMG_FP32_MG;
+    if (L.nb == 21) {
+        if (f32) hipLaunchKernelGGL((k_sweeps2d<float, 21>), dim3(1), dim3(256), 0, s, (float *)mg, L, nu, omega);
+        else hipLaunchKernelGGL((k_sweeps2d<double, 21>), dim3(1), dim3(256), 0, s, (double *)mg, L, nu, omega);
+    } else if (L.nb == 9) {
+        if (f32) hipLaunchKernelGGL((k_sweeps2d<float, 9>), dim3(1), dim3(256), 0, s, (float *)mg, L, nu, omega);
+        else hipLaunchKernelGGL((k_sweeps2d<double, 9>), dim3(1), dim3(256), 0, s, (double *)mg, L, nu, omega);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_sweeps2d<float, 5>), dim3(1), dim3(256), 0, s, (float *)mg, L, nu, omega);
+        else hipLaunchKernelGGL((k_sweeps2d<double, 5>), dim3(1), dim3(256), 0, s, (double *)mg, L, nu, omega);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_bottom2d(void *mg, const Level2D *levels, int first, int nlev, int nu1, int nu2, double omega,
-                           const double *lu, int prec, hipStream_t s)
+                           const double *lu, int prec, hipStream_t s, int sweeps)
 {
     if (first < 0 || first >= nlev || nlev > kMaxLevels) return hipErrorInvalidValue;
     Bottom2DArgs B;
@@ -814,6 +907,7 @@ hipError_t launch_bottom2d(void *mg, const Level2D *levels, int first, int nlev,
     B.nu2 = nu2;
     B.omega = omega;
     B.lu = lu;
+    B.sweeps = sweeps;
     const int nbf = levels[first].nb;
     const bool f32 = prec == NMG_FP32_MG;
     float *mf = (float *)mg;

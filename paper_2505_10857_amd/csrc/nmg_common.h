@@ -235,8 +235,11 @@ hipError_t launch_prolong2d(void *mg, const Level2D &Lf, const Level2D &Lc, int 
 // per operator; the solve with them runs in launch_bottom2d
 hipError_t launch_coarse_factor2d(void *mg, const Level2D &L, double *lu, int prec, hipStream_t s);
 // the levels first..nlev-1 of a V-cycle (down to the coarsest solve and back) in one workgroup
+// sweeps: the levels' smoother is the directional sweeps D1-D4 instead of the multicolour schedule
 hipError_t launch_bottom2d(void *mg, const Level2D *levels, int first, int nlev, int nu1, int nu2, double omega,
-                           const double *lu, int prec, hipStream_t s);
+                           const double *lu, int prec, hipStream_t s, int sweeps = 0);
+// nu iterations of the directional sweeps D1-D4 on one level (one workgroup)
+hipError_t launch_sweeps2d(void *mg, const Level2D &L, int nu, double omega, int prec, hipStream_t s);
 constexpr long long kBottom2DCells = 512;    // levels at most this size go to launch_bottom2d
 inline size_t coarse_lu_bytes(int M) { return sizeof(double) * (size_t)M * M + sizeof(int) * (size_t)M; }
 hipError_t launch_fill(void *p, int prec, long long n, hipStream_t s);

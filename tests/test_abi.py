@@ -196,3 +196,27 @@ def test_2d_surface_reconstruction_needs_its_bottom_samples():
     d.recon = 2
     assert L.nmg_residual(ctypes.byref(d), U, U, U, None, None) == abi.NMG_EINVAL
     assert b"recon" in L.nmg_last_error()
+
+
+def test_linear_solver_choices_per_dimension():
+    """NMG_LINEAR_MG_SWEEPS is 2D only and limited to 65536 cells; the Newton-SOR solvers are 1D
+    only.  Checked on the host before any launch."""
+    abi, L = _lib()
+    d, p = _desc(abi)
+    p.linear = abi.NMG_LINEAR_MG_SWEEPS
+    assert L.nmg_workspace_bytes(ctypes.byref(d), ctypes.byref(p)) == 0
+    d2 = abi.nmg_desc()
+    d2.dim, d2.nx, d2.ny, d2.levels, d2.jac = 2, 32, 16, 3, 9
+    d2.x0, d2.x1, d2.y0, d2.y1, d2.g = 0.0, 4.0, 0.0, 2.0, 9.81
+    for k in range(4):
+        d2.bc[k].kind = abi.NMG_BC_WALL
+    p2 = abi.nmg_params()
+    p2.eps, p2.nu1, p2.nu2, p2.nu3, p2.n_max = 1e-6, 2, 2, 1, 10
+    p2.linear = abi.NMG_LINEAR_MG_SWEEPS
+    assert L.nmg_workspace_bytes(ctypes.byref(d2), ctypes.byref(p2)) > 0
+    p2.linear = abi.NMG_LINEAR_SOR
+    assert L.nmg_workspace_bytes(ctypes.byref(d2), ctypes.byref(p2)) == 0
+    p2.linear = abi.NMG_LINEAR_MG_SWEEPS
+    d2.nx, d2.ny, d2.levels = 512, 256, 7
+    assert L.nmg_workspace_bytes(ctypes.byref(d2), ctypes.byref(p2)) == 0
+    assert b"65536" in L.nmg_last_error()
