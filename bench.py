@@ -92,6 +92,7 @@ def parse():
                     help="run one 256 MiB device copy first (counter calibration under rocprofv3)")
     ap.add_argument("--vcycle2d-only", action="store_true",
                     help="time only the 2D V-cycle form (1024 x 512 wedge configuration) and print it")
+    ap.add_argument("--served-only", action="store_true", help="run only the served forms")
     ap.add_argument("--nmgm21-only", action="store_true",
                     help="run only the NMGM-21 against NMGM-9 form (Table 5 assembly times, wedge solves)")
     ap.add_argument("--wedge2d-only", action="store_true",
@@ -258,8 +259,10 @@ def served(args, rate):
     from paper_2505_10857_amd import NMG_FP32_MG
     from paper_2505_10857_amd.serve import GpuEngine, Server, stream
     reqs = stream(args.served_requests, rate=rate, seed=0)
-    server = Server(GpuEngine("cuda:0", precision=NMG_FP32_MG), hbm_budget=args.served_budget_gib << 30,
-                    steps_per_tick=2, keep_states=True)
+    eng = GpuEngine("cuda:0", precision=NMG_FP32_MG)
+    # warm-up stream (first allocations, module loads), not reported
+    Server(eng, hbm_budget=args.served_budget_gib << 30, steps_per_tick=2).run(stream(16, rate=rate, seed=99))
+    server = Server(eng, hbm_budget=args.served_budget_gib << 30, steps_per_tick=2, keep_states=True)
     rep = server.run(reqs)
     out = rep.summary()
     out.update(rate_req_s=rate if rate < 1e6 else "all at t=0", requests=len(reqs),
@@ -270,6 +273,41 @@ def served(args, rate):
         Uo, _, _, _ = oracle.Oracle1D(reqs[r.rid].prob).newton_solve()
         errs.append(float(np.abs(r.state.cpu().numpy() - Uo).max()))
     out["max_abs_err_vs_fp64_oracle_two_smallest"] = max(errs) if errs else None
+    return out
+
+
+def served_mixed(args, rate=200.0, count=2000, frac_2d=0.0025):
+    """1D and 2D requests on one seeded Poisson stream (2D: the wedge on 64 x 32 to 512 x 256,
+    run on the server's second stream beside the 1D batch; FP32 multigrid); the 2D share is what
+    one GPU sustains (the 2D lane's measured service times are reported beside it)."""
+    import numpy as np
+    import torch
+    from paper_2505_10857_amd import NMG_FP32_MG
+    from paper_2505_10857_amd.serve import GpuEngine, Server, stream_mixed
+    from paper_2505_10857_amd.solver import Solver2D
+    from swe_workloads import SERVED_2D_GRIDS, wedge_problem
+    svc = {}
+    for nx, ny in SERVED_2D_GRIDS:
+        s = Solver2D(wedge_problem(nx, ny, seed=1), device="cuda:0", precision=NMG_FP32_MG, check_every=8)
+        U = s.state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, _ = s.newton_solve(U)
+        torch.cuda.synchronize()
+        svc[f"{nx}x{ny}"] = {"seconds": time.perf_counter() - t0, "newton_steps": st.iters}
+    mean_svc = float(np.mean([v["seconds"] for v in svc.values()]))
+    reqs = stream_mixed(count, rate=rate, frac_2d=frac_2d, seed=0)
+    eng = GpuEngine("cuda:0", precision=NMG_FP32_MG)
+    from paper_2505_10857_amd.serve import stream
+    Server(eng, hbm_budget=args.served_budget_gib << 30, steps_per_tick=2).run(stream(16, rate=rate, seed=99))
+    rep = Server(eng, hbm_budget=args.served_budget_gib << 30, steps_per_tick=2).run(reqs)
+    eng.close()
+    out = rep.summary()
+    out.update(rate_req_s=rate, requests=len(reqs), frac_2d=frac_2d,
+               requests_2d=sum(hasattr(r.prob, "ny") for r in reqs),
+               solo_2d_service_fp32mg=svc, mean_2d_service_s=mean_svc,
+               sustainable_2d_req_s=1.0 / mean_svc,
+               load_2d_at_30pct_of_200rps=0.3 * 200.0 * mean_svc)
     return out
 
 
@@ -474,6 +512,9 @@ def main():
         return
     if args.wedge2d_only:
         print(json.dumps({"wedge2d_1024x512": wedge2d_form()}))
+        return
+    if args.served_only:
+        print(json.dumps({"served_200rps": served(args, 200.0), "served_mixed_1d_2d": served_mixed(args)}))
         return
     if args.nmgm21_only:
         print(json.dumps({"nmgm21_vs_nmgm9": nmgm21_form()}))
@@ -698,6 +739,8 @@ def main():
         forms["served_200rps"] = served(args, 200.0)
         log("form served_saturated")
         forms["served_saturated"] = served(args, 1e7)
+        log("form served_mixed_1d_2d")
+        forms["served_mixed_1d_2d"] = served_mixed(args)
         out["forms"] = forms
 
     # ---- CPU oracle ----------------------------------------------------------------------------

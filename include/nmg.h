@@ -158,6 +158,14 @@ typedef struct {
     double res;        /* final res */
 } nmg_stats;
 
+/* The Newton state of a stepwise 2D solve as the device keeps it: res after the last step, the
+ * steps taken, whether the iteration is still running (1) and its status (NMG_NOT_CONVERGED
+ * while running, then NMG_OK, NMG_NOT_CONVERGED at n_max or NMG_ENONFINITE). */
+typedef struct {
+    double res;
+    int32_t iters, active, status, reserved;
+} nmg_newton_state;
+
 /* Bytes of device workspace nmg_mg_vcycle and nmg_newton_solve need for this problem
  * (multigrid hierarchy, Jacobian, residual buffers, tables).  Only sizes and parameters are
  * read: the geometry pointers may be null, so a caller can budget memory before uploading
@@ -197,6 +205,19 @@ nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *w
 nmg_status nmg_newton_solve(const nmg_desc *desc, const nmg_params *params, void *ws,
                             size_t ws_bytes, double *U, nmg_stats *stats, double *hist,
                             int32_t max_hist, void *stream);
+
+/* Algorithm 1 for one 2D problem in pieces, for callers that interleave it with other work on
+ * other streams (a server): nmg_newton2d_begin enqueues the residual of U (device) and the
+ * initial Newton state in the workspace (sized by nmg_workspace_bytes); nmg_newton2d_steps
+ * enqueues `steps` Newton steps (steps after the iteration has stopped leave U unchanged) and,
+ * when state_out (host; pinned memory keeps the copy asynchronous) is not NULL, a copy of the
+ * state after them.  Neither call waits for the device: synchronise `stream` (or an event
+ * recorded on it) before reading state_out.  The results equal nmg_newton_solve's bit for bit.
+ * Errors (bad arguments, NMG_ENOMEM_WS) are returned before anything is enqueued. */
+nmg_status nmg_newton2d_begin(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
+                              double *U, void *stream);
+nmg_status nmg_newton2d_steps(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
+                              double *U, int32_t steps, nmg_newton_state *state_out, void *stream);
 
 /* ---- Newton solve without allocation ----------------------------------------------------
  * For callers that cannot allocate memory: code next to HIP graph capture, tight serving loops

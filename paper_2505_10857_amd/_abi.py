@@ -41,6 +41,8 @@ EXPORTS = [
     "nmg_plan_get_options", "nmg_plan_autotune", "nmg_interp_coarse_to_fine",
     "nmg_nested_workspace_bytes", "nmg_nested_solve", "nmg_newton_solve_static",
     "nmg_interp2d_coarse_to_fine",
+    "nmg_newton2d_begin",
+    "nmg_newton2d_steps",
 ]
 
 NMG_STATIC_WS_MIB = 64
@@ -75,6 +77,11 @@ class nmg_params(C.Structure):
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("nu3", C.c_int32), ("n_max", C.c_int32),
                 ("precision", C.c_int32), ("check_every", C.c_int32),
                 ("linear", C.c_int32), ("sor_max", C.c_int32), ("sor_tol", C.c_double)]
+
+
+class nmg_newton_state(C.Structure):
+    _fields_ = [("res", C.c_double), ("iters", C.c_int32), ("active", C.c_int32), ("status", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class nmg_stats(C.Structure):
@@ -127,6 +134,8 @@ def load(path: str = LIB_PATH):
     L.nmg_plan_resume.argtypes = [vp, vp, sz, P(vp), P(C.c_int32), vp]
     L.nmg_interp_coarse_to_fine.argtypes = [vp, C.c_int32, vp, vp]
     L.nmg_interp2d_coarse_to_fine.argtypes = [vp, C.c_int32, C.c_int32, vp, vp]
+    L.nmg_newton2d_begin.argtypes = [P(nmg_desc), P(nmg_params), vp, sz, vp, vp]
+    L.nmg_newton2d_steps.argtypes = [P(nmg_desc), P(nmg_params), vp, sz, vp, C.c_int32, vp, vp]
     L.nmg_nested_workspace_bytes.argtypes = [P(nmg_desc), C.c_int32, P(nmg_params)]
     L.nmg_nested_workspace_bytes.restype = sz
     L.nmg_nested_solve.argtypes = [P(nmg_desc), C.c_int32, P(nmg_params), vp, sz, P(vp), P(nmg_stats), vp]
@@ -146,7 +155,7 @@ def load(path: str = LIB_PATH):
                "nmg_newton_solve", "nmg_newton_solve_static", "nmg_plan_create", "nmg_plan_solve", "nmg_plan_begin",
                "nmg_plan_steps", "nmg_plan_resume", "nmg_plan_set_options", "nmg_plan_get_options",
                "nmg_plan_autotune", "nmg_interp_coarse_to_fine", "nmg_interp2d_coarse_to_fine",
-               "nmg_nested_solve"):
+               "nmg_nested_solve", "nmg_newton2d_begin", "nmg_newton2d_steps"):
         getattr(L, nm).restype = C.c_int32
     _lib = L
     return L

@@ -12,8 +12,10 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "nmg_common.h"
@@ -113,6 +115,44 @@ Inst1D make_inst(const nmg_desc *d, const nmg_params *p)
 
 nmg_status nmg::set_error(nmg_status st, const char *msg) { return fail(st, msg); }
 
+// Pinned host blocks (a plan's staging of its instance table and its copy of the Newton states)
+// are kept for reuse when a plan is destroyed instead of being freed: freeing pinned memory
+// waits for the whole device, which would stall other streams' work every time a server
+// re-plans.  The pool holds at most what the plans alive at one time used.
+namespace {
+std::mutex g_pin_mu;
+std::multimap<size_t, void *> g_pin_free;          // size -> block
+std::unordered_map<void *, size_t> g_pin_size;     // every block the pool made
+
+hipError_t pinned_get(void **p, size_t bytes)
+{
+    bytes = (bytes + 4095) & ~size_t(4095);
+    {
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        auto it = g_pin_free.lower_bound(bytes);
+        if (it != g_pin_free.end() && it->first <= 4 * bytes) {
+            *p = it->second;
+            g_pin_free.erase(it);
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipHostMalloc(p, bytes);
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        g_pin_size[*p] = bytes;
+    }
+    return e;
+}
+
+void pinned_put(void *p)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto it = g_pin_size.find(p);
+    if (it != g_pin_size.end()) g_pin_free.insert({it->second, p});
+}
+}  // namespace
+
 struct nmg_plan {
     int n = 0;
     int prec = NMG_FP64;
@@ -158,6 +198,7 @@ struct nmg_plan {
     hipGraph_t graph = nullptr;
     void *g_ws = nullptr;
     hipStream_t own_stream = nullptr;
+    hipEvent_t order_ev = nullptr;            // orders own_stream after the caller's null-stream work
     NewtonState *host_state = nullptr;        // pinned
     char *host_tables = nullptr;              // pinned staging of the instance table
     bool host_borrowed = false;               // host_state / host_tables belong to the caller
@@ -176,8 +217,11 @@ struct nmg_plan {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (own_stream) (void)hipStreamDestroy(own_stream);
-        if (host_state && !host_borrowed) (void)hipHostFree(host_state);
-        if (host_tables && !host_borrowed) (void)hipHostFree(host_tables);
+        if (order_ev) (void)hipEventDestroy(order_ev);
+        if (!host_borrowed) {
+            pinned_put(host_state);
+            pinned_put(host_tables);
+        }
     }
 };
 
@@ -413,7 +457,7 @@ nmg_status upload_tables(nmg_plan *P, char *ws, double *const *U, hipStream_t s)
         P->tables_ws = ws;
     }
     const size_t isz = sizeof(Inst1D) * P->n;
-    if (!P->host_tables) HIP_TRY(hipHostMalloc((void **)&P->host_tables, isz));
+    if (!P->host_tables) HIP_TRY(pinned_get((void **)&P->host_tables, isz));
     else HIP_TRY(hipStreamSynchronize(s));   // the previous upload from this buffer has landed
     for (int k = 0; k < P->n; k++) {
         Inst1D I = P->insts[k];
@@ -598,7 +642,7 @@ nmg_status plan_begin(nmg_plan *P, char *ws, size_t ws_bytes, double *const *U, 
 
 nmg_status read_state(nmg_plan *P, char *ws, hipStream_t s)
 {
-    if (!P->host_state) HIP_TRY(hipHostMalloc((void **)&P->host_state, sizeof(NewtonState) * P->n));
+    if (!P->host_state) HIP_TRY(pinned_get((void **)&P->host_state, sizeof(NewtonState) * P->n));
     HIP_TRY(hipMemcpyAsync(P->host_state, ws + P->off_state, sizeof(NewtonState) * P->n,
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -610,10 +654,9 @@ nmg_status plan_steps(nmg_plan *P, char *ws, int steps, int use_graph, hipStream
     if (use_graph) {
         if (!P->gexec || P->g_ws != ws) {
             hipStream_t cs = s;
-            if (cs == nullptr) {
+            if (cs == nullptr) {   // the null stream cannot be captured: capture on the plan's own
                 if (!P->own_stream) HIP_TRY(hipStreamCreateWithFlags(&P->own_stream, hipStreamNonBlocking));
                 cs = P->own_stream;
-                HIP_TRY(hipDeviceSynchronize());
             }
             HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             nmg_status st = enqueue_step(P, ws, cs, true);
@@ -628,7 +671,13 @@ nmg_status plan_steps(nmg_plan *P, char *ws, int steps, int use_graph, hipStream
             P->g_ws = ws;
         }
         hipStream_t ls = s ? s : P->own_stream;
-        if (s == nullptr) HIP_TRY(hipDeviceSynchronize());
+        if (s == nullptr) {
+            // after the caller's work on the null stream (an event, not a device-wide wait: work
+            // of other streams, such as a server's 2D lane, goes on meanwhile)
+            if (!P->order_ev) HIP_TRY(hipEventCreateWithFlags(&P->order_ev, hipEventDisableTiming));
+            HIP_TRY(hipEventRecord(P->order_ev, nullptr));
+            HIP_TRY(hipStreamWaitEvent(ls, P->order_ev, 0));
+        }
         for (int k = 0; k < steps; k++) HIP_TRY(hipGraphLaunch(P->gexec, ls));
         if (s == nullptr) HIP_TRY(hipStreamSynchronize(ls));
         return NMG_OK;
@@ -1052,6 +1101,20 @@ nmg_status nmg_nested_solve(const nmg_desc *descs, int32_t ngrids, const nmg_par
         if (stats[g].status == NMG_ENONFINITE) return fail(NMG_ENONFINITE, "grid " + std::to_string(g) + " diverged");
     }
     return stats[0].status;
+}
+
+nmg_status nmg_newton2d_begin(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
+                              double *U, void *stream)
+{
+    if (!desc || desc->dim != 2) return fail(NMG_EINVAL, "nmg_newton2d_begin takes a 2D problem");
+    return newton2d_begin(desc, params, ws, ws_bytes, U, (hipStream_t)stream);
+}
+
+nmg_status nmg_newton2d_steps(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
+                              double *U, int32_t steps, nmg_newton_state *state_out, void *stream)
+{
+    if (!desc || desc->dim != 2) return fail(NMG_EINVAL, "nmg_newton2d_steps takes a 2D problem");
+    return newton2d_steps(desc, params, ws, ws_bytes, U, steps, state_out, (hipStream_t)stream);
 }
 
 nmg_status nmg_newton_solve(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,

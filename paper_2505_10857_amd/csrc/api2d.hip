@@ -12,6 +12,7 @@
 //              order (M_l slots, Perm2D); the caller's arrays stay in the natural order
 //   lu       : LU factors and row permutation of the coarsest operator (double [M][M], int [M])
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -304,6 +305,48 @@ nmg_status vcycle2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_
     HIP_TRY2(launch_permute2d(dU, P.prec, mgb + vsz * L0.dU, P.prec, L0, 3, 1, s));
     if ((st = vcycle_from(P, mgb, 0, s)) != NMG_OK) return st;
     HIP_TRY2(launch_permute2d(mgb + vsz * L0.dU, P.prec, dU, P.prec, L0, 3, 0, s));
+    return NMG_OK;
+}
+
+// Stepwise form of the Newton driver: begin evaluates the residual of U and initialises the
+// state in the workspace; steps enqueues `steps` Newton steps and an asynchronous copy of the
+// state to the host.  Neither waits for the device.
+static_assert(sizeof(NewtonState) == sizeof(nmg_newton_state), "nmg_newton_state mirrors the device state");
+static_assert(offsetof(NewtonState, n) == offsetof(nmg_newton_state, iters) &&
+                  offsetof(NewtonState, active) == offsetof(nmg_newton_state, active) &&
+                  offsetof(NewtonState, status) == offsetof(nmg_newton_state, status),
+              "nmg_newton_state mirrors the device state");
+
+nmg_status newton2d_begin(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, double *U, hipStream_t s)
+{
+    if (!ws || !U) return set_error(NMG_EINVAL, "null argument");
+    Plan2D P;
+    nmg_status st = build2d(P, d, p);
+    if (st != NMG_OK) return st;
+    if (ws_bytes < P.total) return set_error(NMG_ENOMEM_WS, "workspace too small");
+    char *w = (char *)ws;
+    const Inst2D I = bound_inst(P, w, U);
+    const long long n0 = (long long)P.L[0].nx * P.L[0].ny;
+    HIP_TRY2(launch_residual2d(I, (double *)(w + P.off_partial), s));
+    HIP_TRY2(launch_state2d((double *)(w + P.off_partial), P.ntiles, n0, P.tol, P.n_max,
+                            (NewtonState *)(w + P.off_state), nullptr, 0, 1, s));
+    return NMG_OK;
+}
+
+nmg_status newton2d_steps(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, double *U, int steps,
+                          nmg_newton_state *state_out, hipStream_t s)
+{
+    if (!ws || !U) return set_error(NMG_EINVAL, "null argument");
+    if (steps < 0) return set_error(NMG_EINVAL, "steps must be >= 0");
+    Plan2D P;
+    nmg_status st = build2d(P, d, p);
+    if (st != NMG_OK) return st;
+    if (ws_bytes < P.total) return set_error(NMG_ENOMEM_WS, "workspace too small");
+    char *w = (char *)ws;
+    for (int k = 0; k < steps; k++)
+        if ((st = newton_step(P, w, U, s)) != NMG_OK) return st;
+    if (state_out)
+        HIP_TRY2(hipMemcpyAsync(state_out, w + P.off_state, sizeof(NewtonState), hipMemcpyDeviceToHost, s));
     return NMG_OK;
 }
 

@@ -266,5 +266,8 @@ nmg_status vcycle2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_
                     const void *rhs, void *dU, int setup, hipStream_t s);
 nmg_status newton2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, double *U,
                     nmg_stats *stats, double *hist, int max_hist, hipStream_t s);
+nmg_status newton2d_begin(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, double *U, hipStream_t s);
+nmg_status newton2d_steps(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, double *U, int steps,
+                          nmg_newton_state *state_out, hipStream_t s);
 
 }  // namespace nmg

@@ -1,22 +1,32 @@
-"""Continuous-batching server for steady 1D solves (Algorithm 1 per request).
+"""Continuous-batching server for steady 1D and 2D solves (Algorithm 1 per request).
 
-Requests arrive over time; a request is admitted as soon as the device memory it needs fits in
-the HBM budget, and from then on its Newton iteration runs inside the same batched launches as
-every other admitted request (one plan over all of them, ``nmg_plan_*``).  The server works in
-ticks: each tick runs a few Newton steps on the current batch, reads the per-request convergence
-state, retires finished requests and admits waiting ones.  When the batch changes, a new plan is
-made over the new set and every continuing request resumes from its state on the device with its
-step count carried over (``nmg_plan_resume``): no request's arithmetic depends on its
+Requests arrive over time; a request is admitted, in arrival order, as soon as the device memory
+it needs fits in the HBM budget.  1D requests then run inside the same batched launches as every
+other admitted 1D request (one plan over all of them, ``nmg_plan_*``).  The server works in
+ticks: each tick runs a few Newton steps on the 1D batch and reads the per-request convergence
+state.  A request that converges is retired at once (its result recorded); its slot stays in the
+plan, skipped by every launch, until the plan is rebuilt, which happens when new requests join,
+when more than half of the slots are retired, or when the memory they hold is needed to admit the
+next request.  A rebuilt plan resumes every continuing request from its state on the device with
+its step count carried over (``nmg_plan_resume``): no request's arithmetic depends on its
 neighbours, so each result is bit for bit the result of solving it alone.
 
+2D requests run one at a time, in admission order, on a second stream driven by a worker thread
+(``nmg_newton_solve``; the library call releases the interpreter lock): a 2D Newton step is
+hundreds of launches, whose enqueueing can wait for queue space on the device, so it must not
+hold up the loop, which only polls for finished 2D requests.  The two lanes overlap on the
+device.
+
 The Newton and multigrid state of every request stays in device memory from admission to
-retirement; the host only sees the per-request convergence flags.  The engine (device side) is
-pluggable so that the scheduling logic can be exercised without a GPU.
+retirement; the host only sees the convergence flags.  The engine (device side) is pluggable so
+that the scheduling logic can be exercised without a GPU.
 """
 from __future__ import annotations
 
 import collections
 import dataclasses
+import queue
+import threading
 import time
 from typing import Any, Callable, Dict, List, Optional, Sequence
 
@@ -33,7 +43,7 @@ class Request:
 @dataclasses.dataclass
 class Result:
     rid: int
-    n: int                    # cells
+    n: int                    # cells (nx * ny in 2D)
     iters: int
     status: int
     res: float
@@ -42,6 +52,7 @@ class Result:
     finished: float
     footprint: int            # device bytes reserved for the request
     state: Any = None         # the final state (device tensor) when kept
+    dim: int = 1
 
     @property
     def latency(self) -> float:
@@ -63,17 +74,23 @@ class ServeReport:
     def solves_per_s(self) -> float:
         return len(self.results) / self.span if self.span > 0 else float("nan")
 
-    def latency_ms(self, q: float) -> float:
-        lat = np.array([r.latency for r in self.results]) * 1e3
+    def latency_ms(self, q: float, dim: Optional[int] = None) -> float:
+        lat = np.array([r.latency for r in self.results if dim is None or r.dim == dim]) * 1e3
         return float(np.percentile(lat, q)) if len(lat) else float("nan")
 
     def summary(self) -> Dict[str, Any]:
-        return dict(completed=len(self.results), rejected=len(self.rejected),
-                    solves_per_s=self.solves_per_s, p50_ms=self.latency_ms(50),
-                    p99_ms=self.latency_ms(99), ticks=self.ticks, plans=self.plans,
-                    max_batch=self.max_batch, mean_batch=self.mean_batch,
-                    peak_bytes=self.peak_bytes, span_s=self.span,
-                    converged=all(r.status == 0 for r in self.results))
+        out = dict(completed=len(self.results), rejected=len(self.rejected),
+                   solves_per_s=self.solves_per_s, p50_ms=self.latency_ms(50),
+                   p99_ms=self.latency_ms(99), ticks=self.ticks, plans=self.plans,
+                   max_batch=self.max_batch, mean_batch=self.mean_batch,
+                   peak_bytes=self.peak_bytes, span_s=self.span,
+                   converged=all(r.status == 0 for r in self.results))
+        n2 = sum(1 for r in self.results if r.dim == 2)
+        if n2:
+            out.update(completed_1d=len(self.results) - n2, completed_2d=n2,
+                       p50_ms_1d=self.latency_ms(50, 1), p99_ms_1d=self.latency_ms(99, 1),
+                       p50_ms_2d=self.latency_ms(50, 2), p99_ms_2d=self.latency_ms(99, 2))
+        return out
 
 
 class GpuEngine:
@@ -86,12 +103,31 @@ class GpuEngine:
         self.device = device
         self.precision = A.NMG_FP32_MG if precision is None else precision
         self.use_graph = use_graph
+        self._jobs2d: Optional[queue.Queue] = None
+        self._worker = None
+        self._stream1d = None
+
+    @staticmethod
+    def is2d(prob) -> bool:
+        return hasattr(prob, "ny")
 
     def footprint(self, prob) -> int:
         """Workspace of the request alone plus its state and geometry arrays (bytes)."""
         import ctypes as C
         from .solver import params_struct
         A = self.A
+        if self.is2d(prob):
+            d = A.nmg_desc()
+            d.dim, d.nx, d.ny, d.levels, d.jac, d.recon = 2, prob.nx, prob.ny, prob.levels, 9, getattr(prob, "recon", 0)
+            d.x0, d.x1, d.y0, d.y1, d.g = prob.x0, prob.x1, prob.y0, prob.y1, prob.g
+            for k, bc in enumerate(prob.bc):
+                d.bc[k].kind = bc.kind
+            p = params_struct(prob.params, self.precision)
+            ws = self.L.nmg_workspace_bytes(C.byref(d), C.byref(p))
+            if ws == 0:
+                raise A.NmgError(A.NMG_EINVAL, self.L.nmg_last_error().decode())
+            n = prob.nx * prob.ny
+            return int(ws) + 8 * 3 * n + 8 * 8 * n
         d = A.nmg_desc()
         d.dim, d.nx, d.ny, d.levels, d.jac = 1, prob.n, 1, prob.levels, 3
         d.x0, d.x1, d.y0, d.y1, d.g = prob.x0, prob.x1, 0.0, 1.0, prob.g
@@ -110,29 +146,91 @@ class GpuEngine:
                          device=self.device)
         return dict(prob=prob, dev=dev, U=U)
 
+    # ---- 2D lane: a worker thread solves the admitted 2D requests in order on its own stream
+
+    def _work2d(self):
+        import torch
+        from .solver import Solver2D
+        torch.cuda.set_device(self.device)
+        side = torch.cuda.Stream(self.device)
+        while True:
+            job = self._jobs2d.get()
+            if job is None:
+                return
+            try:
+                with torch.cuda.stream(side):
+                    s = Solver2D(job["prob"], device=self.device, precision=self.precision, check_every=4)
+                    U = s.state()
+                    st, _ = s.newton_solve(U)
+                side.synchronize()
+                job["U"] = U
+                job["out"] = (0, st.iters, st.status, st.res)
+            except Exception as e:         # reported by poll2d in the loop's thread
+                job["error"] = e
+            job["done"].set()
+
+    def prepare2d(self, prob):
+        return dict(prob=prob, done=threading.Event(), out=None, U=None)
+
+    def start2d(self, job):
+        if self._worker is None:
+            self._jobs2d = queue.Queue()
+            self._worker = threading.Thread(target=self._work2d, daemon=True)
+            self._worker.start()
+        self._jobs2d.put(job)
+
+    def poll2d(self, job):
+        """None while the request is queued or iterating; then (0, iters, status, res)."""
+        if not job["done"].is_set():
+            return None
+        if "error" in job:
+            raise job["error"]
+        return job["out"]
+
+    def state2d(self, job):
+        return job["U"]
+
+    def close(self):
+        if self._worker is not None:
+            self._jobs2d.put(None)
+            self._worker.join()
+            self._worker = None
+
     def batch(self, prepared: Sequence[dict]):
+        import torch
         from .solver import BatchSolver1D
-        return _GpuBatch(BatchSolver1D([p["prob"] for p in prepared], device=self.device,
-                                       precision=self.precision,
-                                       devs=[p["dev"] for p in prepared]),
-                         [p["U"] for p in prepared], self.use_graph)
+        # the 1D lane has a stream of its own (its plans then capture and replay their graphs on
+        # it, with no stream of their own to create); it starts after the geometry and states
+        # the loop's thread wrote on the current stream
+        if self._stream1d is None:
+            self._stream1d = torch.cuda.Stream(self.device)
+        self._stream1d.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(self._stream1d):
+            bs = BatchSolver1D([p["prob"] for p in prepared], device=self.device, precision=self.precision,
+                               devs=[p["dev"] for p in prepared])
+        return _GpuBatch(bs, [p["U"] for p in prepared], self.use_graph, self._stream1d)
 
     def state(self, prepared):
         return prepared["U"]
 
 
 class _GpuBatch:
-    def __init__(self, bs, Us, use_graph):
+    def __init__(self, bs, Us, use_graph, stream):
         self.bs = bs
         self.Us = Us
         self.use_graph = use_graph
+        self.stream = stream
         self.workspace_bytes = bs.ws_bytes
 
     def resume(self, n_done: Sequence[int]):
-        self.bs.resume(self.Us, n_done)
+        import torch
+        with torch.cuda.stream(self.stream):
+            self.bs.resume(self.Us, n_done)
 
     def steps(self, k: int):
-        return self.bs.steps(k, use_graph=self.use_graph)
+        import torch
+        with torch.cuda.stream(self.stream):
+            return self.bs.steps(k, use_graph=self.use_graph)
 
 
 class Server:
@@ -140,79 +238,143 @@ class Server:
     retire at convergence (or failure), report latency percentiles and throughput."""
 
     def __init__(self, engine, hbm_budget: int, steps_per_tick: int = 2,
-                 keep_states: bool = False):
+                 keep_states: bool = False, trace: bool = False):
         if steps_per_tick < 1:
             raise ValueError("steps_per_tick must be >= 1")
         self.engine = engine
         self.budget = int(hbm_budget)
         self.steps_per_tick = steps_per_tick
         self.keep_states = keep_states
+        self.trace = [] if trace else None      # (start, seconds, what) of the loop's phases
 
     def run(self, requests: Sequence[Request], clock: Optional[Callable[[], float]] = None,
-            sleep: Optional[Callable[[float], None]] = None) -> ServeReport:
+            sleep: Optional[Callable[[float], None]] = None, poll: float = 2e-4) -> ServeReport:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         if clock is None:
             t0 = time.perf_counter()
             clock = lambda: time.perf_counter() - t0          # noqa: E731
         if sleep is None:
             sleep = time.sleep
+        eng = self.engine
+        is2d = getattr(eng, "is2d", lambda prob: False)
         waiting: collections.deque = collections.deque()
-        active: List[dict] = []          # admitted, still iterating
+        plan_items: List[dict] = []      # the 1D plan's requests in plan order (retired ones kept
+        pending: List[dict] = []         # until it is rebuilt); admitted 1D requests not yet in it
+        active2d: List[dict] = []
         results: List[Result] = []
         rejected: List[int] = []
-        used = 0
+        used = held = 0                  # held: bytes of retired 1D requests still in the plan
         peak = 0
         nxt = 0
         batch = None
-        dirty = True
         ticks = plans = max_batch = 0
         batch_sum = 0
-        while nxt < len(reqs) or waiting or active:
+
+        def phase(what, t0):
+            if self.trace is not None:
+                self.trace.append((t0, clock() - t0, what))
+
+        def record(a, iters, status, res, t, state, dim, cells):
+            r = a["req"]
+            results.append(Result(r.rid, cells, iters, status, res, r.arrival, a["admitted"], t, a["fp"],
+                                  state if self.keep_states else None, dim))
+
+        while nxt < len(reqs) or waiting or pending or active2d or any(not a["retired"] for a in plan_items):
             now = clock()
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
                 r = reqs[nxt]
                 nxt += 1
-                fp = self.engine.footprint(r.prob)
+                fp = eng.footprint(r.prob)
                 if fp > self.budget:
                     rejected.append(r.rid)       # can never fit
                     continue
                 waiting.append((r, fp))
-            # admission in arrival order, while the budget allows
-            while waiting and used + waiting[0][1] <= self.budget:
-                r, fp = waiting.popleft()
-                active.append(dict(req=r, fp=fp, n_done=0, admitted=now,
-                                   prep=self.engine.prepare(r.prob)))
+            # admission in arrival order, while the budget allows; the memory of retired 1D slots
+            # is reclaimed (the plan rebuilt without them) when the next request needs it
+            while waiting:
+                r, fp = waiting[0]
+                if used + fp > self.budget:
+                    if held and used - held + fp <= self.budget:
+                        plan_items = [a for a in plan_items if not a["retired"]]
+                        used -= held
+                        held = 0
+                        batch = None
+                        pending = plan_items + pending
+                        plan_items = []
+                        continue
+                    break
+                waiting.popleft()
+                a = dict(req=r, fp=fp, n_done=0, admitted=now, retired=False)
+                t_a = clock()
+                if is2d(r.prob):
+                    a["prep"] = eng.prepare2d(r.prob)
+                    eng.start2d(a["prep"])
+                    active2d.append(a)
+                    phase("admit2d", t_a)
+                else:
+                    a["prep"] = eng.prepare(r.prob)
+                    pending.append(a)
+                    phase("admit1d", t_a)
                 used += fp
-                dirty = True
             peak = max(peak, used)
-            if not active:
-                if nxt < len(reqs):
-                    sleep(max(0.0, reqs[nxt].arrival - clock()))
-                continue
-            if dirty:
-                batch = None                     # release the old plan before making a new one
-                batch = self.engine.batch([a["prep"] for a in active])
-                batch.resume([a["n_done"] for a in active])
-                plans += 1
-                dirty = False
-            flags, stats = batch.steps(self.steps_per_tick)
-            ticks += 1
-            batch_sum += len(active)
-            max_batch = max(max_batch, len(active))
-            done_at = clock()
-            keep = []
-            for a, f, (iters, status, res) in zip(active, flags, stats):
-                a["n_done"] = iters
-                if f:
-                    keep.append(a)
+            # 2D lane: retire finished requests, keep the others' chunks going (never waits)
+            t_p = clock()
+            for a in list(active2d):
+                out = eng.poll2d(a["prep"])
+                if out is None:
                     continue
-                r = a["req"]
-                results.append(Result(r.rid, r.prob.n, iters, status, res, r.arrival, a["admitted"],
-                                      done_at, a["fp"],
-                                      self.engine.state(a["prep"]) if self.keep_states else None))
-                used -= a["fp"]
-                dirty = True
-            active = keep
+                act, iters, status, res = out
+                a["n_done"] = iters
+                if not act:
+                    p2 = a["req"].prob
+                    record(a, iters, status, res, clock(), eng.state2d(a["prep"]), 2, p2.nx * p2.ny)
+                    used -= a["fp"]
+                    active2d.remove(a)
+            if active2d:
+                phase("poll2d", t_p)
+            # 1D lane: rebuild the plan when requests join or most of its slots are retired
+            live = [a for a in plan_items if not a["retired"]]
+            if pending or (plan_items and 2 * len(live) < len(plan_items)):
+                plan_items = live + pending
+                pending = []
+                used -= held
+                held = 0
+                t_b = clock()
+                batch = None                     # release the old plan before making a new one
+                if plan_items:
+                    batch = eng.batch([a["prep"] for a in plan_items])
+                    batch.resume([a["n_done"] for a in plan_items])
+                    plans += 1
+                phase("plan", t_b)
+                live = plan_items
+            elif plan_items and not live:
+                plan_items = []                  # every slot retired: release the plan
+                used -= held
+                held = 0
+                batch = None
+            if live:
+                t_s = clock()
+                flags, stats = batch.steps(self.steps_per_tick)
+                phase("steps", t_s)
+                ticks += 1
+                batch_sum += len(live)
+                max_batch = max(max_batch, len(live))
+                done_at = clock()
+                for a, f, (iters, status, res) in zip(plan_items, flags, stats):
+                    if a["retired"]:
+                        continue
+                    a["n_done"] = iters
+                    if f:
+                        continue
+                    a["retired"] = True
+                    held += a["fp"]
+                    record(a, iters, status, res, done_at, eng.state(a["prep"]), 1, a["req"].prob.n)
+            elif active2d:
+                # only 2D chunks in flight: poll them, but wake for the next arrival
+                due = reqs[nxt].arrival - clock() if nxt < len(reqs) else poll
+                sleep(max(0.0, min(poll, due)))
+            elif nxt < len(reqs) and not waiting:
+                sleep(max(0.0, reqs[nxt].arrival - clock()))
         arrivals = [r.arrival for r in reqs]
         span = (max(r.finished for r in results) - min(arrivals)) if results else 0.0
         results.sort(key=lambda r: r.rid)
@@ -226,3 +388,15 @@ def stream(count: int, rate: float = 200.0, seed: int = 0, n_min: int = 512,
     from swe_workloads import served_arrivals, served_request
     t = served_arrivals(count, rate, seed)
     return [Request(i, served_request(i, seed, n_min, n_max), float(t[i])) for i in range(count)]
+
+
+def stream_mixed(count: int, rate: float = 200.0, frac_2d: float = 0.3, seed: int = 0, n_min: int = 512,
+                 n_max: int = 32768) -> List[Request]:
+    """A seeded Poisson stream of 1D and 2D requests: request i is 2D with probability frac_2d
+    (drawn from default_rng([8, seed])), a 2D request the jump over a wedge on a grid from 64 x 32
+    to 512 x 256 (swe_workloads.served_request_2d), a 1D one as in ``stream``."""
+    from swe_workloads import served_arrivals, served_request, served_request_2d
+    t = served_arrivals(count, rate, seed)
+    is2d = np.random.default_rng([8, seed]).random(count) < frac_2d
+    return [Request(i, served_request_2d(i, seed) if is2d[i] else served_request(i, seed, n_min, n_max),
+                    float(t[i])) for i in range(count)]

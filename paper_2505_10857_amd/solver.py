@@ -393,6 +393,50 @@ class Solver2D:
         return st, h
 
 
+class Stepper2D:
+    """Algorithm 1 for one 2D problem in pieces on a stream of the caller (nmg_newton2d_begin,
+    nmg_newton2d_steps): the state and the workspace stay on the device, each chunk of Newton
+    steps ends with a copy of the Newton state into pinned host memory and an event, so the
+    caller can poll instead of waiting.  The arithmetic is nmg_newton_solve's."""
+
+    def __init__(self, prob, device="cuda", precision: int = A.NMG_FP32_MG, stream=None, jac: int = 9,
+                 **param_overrides):
+        self.solver = Solver2D(prob, device=device, precision=precision, jac=jac, **param_overrides)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.U = self.solver.state()
+        self.ws = self.solver.workspace()
+        self._host = torch.zeros(C.sizeof(A.nmg_newton_state), dtype=torch.uint8).pin_memory()
+        self.event = None
+
+    def _call(self, fn, *args):
+        d = self.solver.dev.desc
+        A.check(fn(C.byref(d), C.byref(self.solver.params), _dptr(self.ws), self.ws.numel(),
+                   _dptr(self.U), *args, C.c_void_p(self.stream.cuda_stream)))
+
+    def begin(self):
+        # the state and geometry were written on the current stream
+        self.stream.wait_stream(torch.cuda.current_stream(self.U.device))
+        self._call(A.load().nmg_newton2d_begin)
+
+    def launch(self, steps: int):
+        """Enqueue `steps` Newton steps, the state copy and an event (returns at once)."""
+        self._call(A.load().nmg_newton2d_steps, steps, C.c_void_p(self._host.data_ptr()))
+        self.event = torch.cuda.Event()
+        self.event.record(self.stream)
+
+    def ready(self) -> bool:
+        return self.event is None or self.event.query()
+
+    def wait(self):
+        if self.event is not None:
+            self.event.synchronize()
+
+    def state(self):
+        """(active, iters, status, res) after the last completed chunk."""
+        s = A.nmg_newton_state.from_address(self._host.data_ptr())
+        return s.active, s.iters, s.status, s.res
+
+
 def interp_coarse_to_fine(Uc: torch.Tensor) -> torch.Tensor:
     """Appendix A interpolation of a device state [2, nc] to [2, 2 nc]."""
     Uc = Uc.contiguous()

@@ -345,6 +345,19 @@ def served_request(i: int, seed: int = 0, n_min: int = 512, n_max: int = 32768):
     return _uneven_instance(np.random.default_rng([5, seed, i]), f"req[{seed}:{i}]", n_min, n_max)
 
 
+SERVED_2D_GRIDS = ((64, 32), (128, 64), (256, 128), (512, 256))
+
+
+def served_request_2d(i: int, seed: int = 0):
+    """2D request i of a served stream: the jump over a wedge (config 3's geometry) on a grid
+    drawn from 64 x 32, 128 x 64, 256 x 128, 512 x 256, with its seeded bottom perturbations
+    (seed drawn per request) from default_rng([7, seed, i])."""
+    rng = np.random.default_rng([7, seed, i])
+    nx, ny = SERVED_2D_GRIDS[int(rng.integers(0, len(SERVED_2D_GRIDS)))]
+    p = wedge_problem(nx, ny, seed=int(rng.integers(0, 2 ** 31)))
+    return dataclasses.replace(p, name=f"req2d[{seed}:{i}]")
+
+
 def served_arrivals(count: int, rate: float = 200.0, seed: int = 0) -> np.ndarray:
     """Poisson arrival times (seconds from the start) of ``count`` requests at ``rate`` per
     second: cumulative exponential gaps from default_rng([6, seed])."""

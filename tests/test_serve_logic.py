@@ -117,14 +117,15 @@ def test_oversized_request_is_rejected_not_blocking():
     assert [r.rid for r in rep.results] == [1]
 
 
-def test_replanning_carries_step_counts_and_happens_on_membership_change():
+def test_replanning_carries_step_counts_and_happens_when_requests_join():
     ft = FakeTime()
     eng = FakeEngine(ft, tick=1e-3)
     # request 1 arrives while request 0 is mid-solve
     reqs = _requests([(0.0, 100, 8), (0.0025, 100, 4)])
     rep = Server(eng, hbm_budget=10**9, steps_per_tick=1).run(reqs, clock=ft.clock, sleep=ft.sleep)
-    # plans: {0}, {0,1} after the arrival, {0} after 1 retires
-    assert rep.plans == 3
+    # plans: {0}, {0,1} after the arrival; request 1 retires inside that plan (its slot skipped,
+    # half the slots still live), and the plan is released once 0 retires too
+    assert rep.plans == 2
     assert eng.resumes[0] == [(0, 0)]
     r0_steps_at_join = dict(eng.resumes[1])[0]
     assert r0_steps_at_join > 0 and dict(eng.resumes[1])[1] == 0
@@ -151,3 +152,99 @@ def test_latency_percentiles():
     assert rep.latency_ms(99) == pytest.approx(np.percentile(lat, 99))
     s = rep.summary()
     assert s["completed"] == 10 and s["converged"]
+
+
+def test_retired_slots_are_reclaimed_when_the_next_request_needs_their_memory():
+    """Budget for two requests: the third waits; when the first retires, its slot's memory is
+    held by the plan until the third needs it, then the plan is rebuilt without it."""
+    ft = FakeTime()
+    eng = FakeEngine(ft)
+    reqs = _requests([(0.0, 100, 2), (0.0, 100, 9), (0.0, 100, 3)])
+    rep = Server(eng, hbm_budget=2000, steps_per_tick=1).run(reqs, clock=ft.clock, sleep=ft.sleep)
+    assert [r.iters for r in rep.results] == [2, 9, 3]
+    assert rep.peak_bytes <= 2000 and rep.max_batch == 2
+    assert rep.plans == 2                      # {0, 1}, then {1, 2} after the reclaim
+    assert eng.resumes[1] == [(1, 2), (2, 0)]  # request 1 carries its two steps
+    assert rep.results[2].admitted >= rep.results[0].finished
+
+
+def test_most_slots_retired_triggers_a_rebuild():
+    ft = FakeTime()
+    eng = FakeEngine(ft)
+    reqs = _requests([(0.0, 10, 1), (0.0, 10, 1), (0.0, 10, 1), (0.0, 10, 8)])
+    rep = Server(eng, hbm_budget=10**9, steps_per_tick=1).run(reqs, clock=ft.clock, sleep=ft.sleep)
+    # three of four retire after one step: the plan is rebuilt over the survivor
+    assert rep.plans == 2 and eng.batches[-1] == 1
+    assert [r.iters for r in rep.results] == [1, 1, 1, 8]
+
+
+class FakeProb2D:
+    def __init__(self, nx, ny, need):
+        self.nx, self.ny, self.need = nx, ny, need
+
+
+class FakeStepper:
+    def __init__(self, eng, prob):
+        self.eng, self.need, self.steps, self.ready_at, self.chunks = eng, prob.need, 0, None, 0
+
+
+class FakeEngine2D(FakeEngine):
+    """1D as FakeEngine; a 2D request needs `need` Newton steps, taken `k` per chunk, each chunk
+    ready `chunk_time` seconds after it is enqueued."""
+
+    def __init__(self, time, tick=1e-3, k=4, chunk_time=5e-3):
+        super().__init__(time, tick)
+        self.k, self.chunk_time = k, chunk_time
+        self.started = []
+
+    def is2d(self, prob):
+        return hasattr(prob, "ny")
+
+    def footprint(self, prob):
+        return prob.nx * prob.ny * 10 if self.is2d(prob) else prob.n * 10
+
+    def prepare2d(self, prob):
+        return FakeStepper(self, prob)
+
+    def _launch(self, st):
+        st.ready_at = self.time.t + self.chunk_time
+        st.chunks += 1
+
+    def start2d(self, st):
+        self.started.append(self.time.t)
+        self._launch(st)
+
+    def poll2d(self, st):
+        if self.time.t < st.ready_at:
+            return None
+        st.steps = min(st.need, st.chunks * self.k)
+        act = st.steps < st.need
+        if act:
+            self._launch(st)
+        return (1 if act else 0), st.steps, 0, 1e-11
+
+    def state2d(self, st):
+        return ("2d", st.steps)
+
+
+def test_2d_requests_run_beside_the_1d_batch():
+    """A stream of 1D and 2D requests: every request completes with its own step count; a 2D
+    request's chunks are polled while 1D ticks go on, and only-2D periods do not spin forever."""
+    ft = FakeTime()
+    eng = FakeEngine2D(ft, tick=1e-3, k=4, chunk_time=5e-3)
+    reqs = []
+    for rid, (t, kind, size, need) in enumerate([(0.0, 1, 100, 6), (0.0, 2, (8, 4), 10),
+                                                  (0.002, 1, 50, 3), (0.004, 2, (16, 8), 5),
+                                                  (0.05, 2, (8, 4), 3)]):
+        p = FakeProb(size, need) if kind == 1 else FakeProb2D(size[0], size[1], need)
+        p.rid = rid
+        reqs.append(Request(rid, p, t))
+    rep = Server(eng, hbm_budget=10**9, steps_per_tick=1, keep_states=True).run(
+        reqs, clock=ft.clock, sleep=ft.sleep)
+    assert [r.iters for r in rep.results] == [6, 10, 3, 5, 3]
+    assert [r.dim for r in rep.results] == [1, 2, 1, 2, 1 + 1]
+    assert rep.results[1].state == ("2d", 10) and rep.results[1].n == 32
+    # the 10-step 2D request needs three chunks of four: done no earlier than 3 chunk times
+    assert rep.results[1].finished >= 3 * 5e-3 - 1e-12
+    s = rep.summary()
+    assert s["completed_2d"] == 3 and s["completed_1d"] == 2 and s["converged"]
