@@ -11,11 +11,12 @@ next request.  A rebuilt plan resumes every continuing request from its state on
 its step count carried over (``nmg_plan_resume``): no request's arithmetic depends on its
 neighbours, so each result is bit for bit the result of solving it alone.
 
-2D requests run one at a time, in admission order, on a second stream driven by a worker thread
+2D requests are solved in admission order by worker threads, each on a stream of its own
 (``nmg_newton_solve``; the library call releases the interpreter lock): a 2D Newton step is
 hundreds of launches, whose enqueueing can wait for queue space on the device, so it must not
-hold up the loop, which only polls for finished 2D requests.  The two lanes overlap on the
-device.
+hold up the loop, which only polls for finished 2D requests.  A small 2D grid keeps only a few
+compute units busy (its passes are short chains of dependent launches), so several 2D requests
+in flight at once, and the 1D lane beside them, share the device.
 
 The Newton and multigrid state of every request stays in device memory from admission to
 retirement; the host only sees the convergence flags.  The engine (device side) is pluggable so
@@ -96,7 +97,8 @@ class ServeReport:
 class GpuEngine:
     """Device side of the server: libnmg's batched plan over the admitted requests."""
 
-    def __init__(self, device="cuda:0", precision: Optional[int] = None, use_graph: bool = True):
+    def __init__(self, device="cuda:0", precision: Optional[int] = None, use_graph: bool = True,
+                 workers_2d: int = 3):
         from . import _abi as A
         self.A = A
         self.L = A.load()
@@ -104,7 +106,8 @@ class GpuEngine:
         self.precision = A.NMG_FP32_MG if precision is None else precision
         self.use_graph = use_graph
         self._jobs2d: Optional[queue.Queue] = None
-        self._worker = None
+        self._workers: List[threading.Thread] = []
+        self.workers_2d = max(1, workers_2d)
         self._stream1d = None
 
     @staticmethod
@@ -173,10 +176,12 @@ class GpuEngine:
         return dict(prob=prob, done=threading.Event(), out=None, U=None)
 
     def start2d(self, job):
-        if self._worker is None:
+        if not self._workers:
             self._jobs2d = queue.Queue()
-            self._worker = threading.Thread(target=self._work2d, daemon=True)
-            self._worker.start()
+            for _ in range(self.workers_2d):
+                t = threading.Thread(target=self._work2d, daemon=True)
+                t.start()
+                self._workers.append(t)
         self._jobs2d.put(job)
 
     def poll2d(self, job):
@@ -191,10 +196,11 @@ class GpuEngine:
         return job["U"]
 
     def close(self):
-        if self._worker is not None:
+        for _ in self._workers:
             self._jobs2d.put(None)
-            self._worker.join()
-            self._worker = None
+        for t in self._workers:
+            t.join()
+        self._workers = []
 
     def batch(self, prepared: Sequence[dict]):
         import torch
