@@ -150,7 +150,26 @@ typedef struct {
     int32_t linear;
     int32_t sor_max;
     double sor_tol;
+    int32_t schedule;   /* 2D launch schedule (NMG_SCHED2D_* bits, 0 the default); 1D ignores it */
+    int32_t reserved;
 } nmg_params;
+
+/* 2D launch schedules: every choice gives the same results bit for bit (the same operations on
+ * the same values in the same order); they differ in speed only, and nmg_autotune2d picks one.
+ *   NMG_SCHED2D_ALT_FINEST: the finest level's colour passes take the other of the two forms of
+ *     a pass (by default one thread per cell on the cross stencil, whose row loads then issue
+ *     together, and three lanes per cell on the 21-cell stencil, one per row of its blocks);
+ *   NMG_SCHED2D_ALT_COARSE: the same for the launched five-point levels;
+ *   NMG_SCHED2D_NO_STREAM: no non-temporal loads (by default the finest level's passes stream
+ *     the rows that the schedule evicts before it returns to them, when its operator is larger
+ *     than the memory-side cache);
+ *   NMG_SCHED2D_SMALL_BOTTOM: the one-workgroup bottom of the V-cycle starts at levels of at
+ *     most 128 cells instead of 512. */
+#define NMG_SCHED2D_ALT_FINEST 1
+#define NMG_SCHED2D_ALT_COARSE 2
+#define NMG_SCHED2D_NO_STREAM 4
+#define NMG_SCHED2D_SMALL_BOTTOM 8
+#define NMG_TUNE2D_CANDIDATES 16
 
 typedef struct {
     int32_t iters;     /* Newton steps taken */
@@ -197,6 +216,16 @@ nmg_status nmg_jacobian_assemble_simplified(const nmg_desc *desc, const nmg_para
  * device arrays in the U layout; precision NMG_FP32_MG makes rhs/dU float arrays. */
 nmg_status nmg_mg_vcycle(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
                          const void *J, const void *rhs, void *dU, int32_t setup, void *stream);
+
+/* Autotuner of the 2D launch schedule: with the operator J (FP64, the 2D layout above) and the
+ * right-hand side rhs (device, in params->precision) set up in the workspace once, every schedule
+ * 0..NMG_TUNE2D_CANDIDATES-1 (params->schedule is ignored) runs one warm-up V-cycle and then
+ * `cycles` timed V-cycles (HIP events on `stream`); ms[c] (host, NMG_TUNE2D_CANDIDATES entries)
+ * receives the milliseconds per V-cycle and *best the fastest schedule, to be passed in
+ * params->schedule.  2D only; synchronises `stream`; the workspace's correction is overwritten. */
+nmg_status nmg_autotune2d(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
+                          const double *J, const void *rhs, int32_t cycles, int32_t *best, double *ms,
+                          void *stream);
 
 /* Algorithm 1 driven to res < tol or n_max steps: each step assembles the Jacobian, runs nu3
  * V-cycles from dU = 0, updates U += tau dU (eq. 14) and re-evaluates res.  U (device) is the

@@ -32,6 +32,11 @@ NMG_LINEAR_MG = 0
 NMG_LINEAR_SOR = 1
 NMG_LINEAR_SOR_LEX = 2
 NMG_LINEAR_MG_SWEEPS = 3
+NMG_SCHED2D_ALT_FINEST = 1
+NMG_SCHED2D_ALT_COARSE = 2
+NMG_SCHED2D_NO_STREAM = 4
+NMG_SCHED2D_SMALL_BOTTOM = 8
+NMG_TUNE2D_CANDIDATES = 16
 
 EXPORTS = [
     "nmg_workspace_bytes", "nmg_residual", "nmg_jacobian_assemble_simplified", "nmg_mg_vcycle",
@@ -43,6 +48,7 @@ EXPORTS = [
     "nmg_interp2d_coarse_to_fine",
     "nmg_newton2d_begin",
     "nmg_newton2d_steps",
+    "nmg_autotune2d",
 ]
 
 NMG_STATIC_WS_MIB = 64
@@ -76,7 +82,8 @@ class nmg_params(C.Structure):
                 ("omega", C.c_double), ("tol", C.c_double),
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("nu3", C.c_int32), ("n_max", C.c_int32),
                 ("precision", C.c_int32), ("check_every", C.c_int32),
-                ("linear", C.c_int32), ("sor_max", C.c_int32), ("sor_tol", C.c_double)]
+                ("linear", C.c_int32), ("sor_max", C.c_int32), ("sor_tol", C.c_double),
+                ("schedule", C.c_int32), ("reserved", C.c_int32)]
 
 
 class nmg_newton_state(C.Structure):
@@ -136,6 +143,8 @@ def load(path: str = LIB_PATH):
     L.nmg_interp2d_coarse_to_fine.argtypes = [vp, C.c_int32, C.c_int32, vp, vp]
     L.nmg_newton2d_begin.argtypes = [P(nmg_desc), P(nmg_params), vp, sz, vp, vp]
     L.nmg_newton2d_steps.argtypes = [P(nmg_desc), P(nmg_params), vp, sz, vp, C.c_int32, vp, vp]
+    L.nmg_autotune2d.argtypes = [P(nmg_desc), P(nmg_params), vp, sz, vp, vp, C.c_int32, P(C.c_int32),
+                                 P(C.c_double), vp]
     L.nmg_nested_workspace_bytes.argtypes = [P(nmg_desc), C.c_int32, P(nmg_params)]
     L.nmg_nested_workspace_bytes.restype = sz
     L.nmg_nested_solve.argtypes = [P(nmg_desc), C.c_int32, P(nmg_params), vp, sz, P(vp), P(nmg_stats), vp]
@@ -155,7 +164,7 @@ def load(path: str = LIB_PATH):
                "nmg_newton_solve", "nmg_newton_solve_static", "nmg_plan_create", "nmg_plan_solve", "nmg_plan_begin",
                "nmg_plan_steps", "nmg_plan_resume", "nmg_plan_set_options", "nmg_plan_get_options",
                "nmg_plan_autotune", "nmg_interp_coarse_to_fine", "nmg_interp2d_coarse_to_fine",
-               "nmg_nested_solve", "nmg_newton2d_begin", "nmg_newton2d_steps"):
+               "nmg_nested_solve", "nmg_newton2d_begin", "nmg_newton2d_steps", "nmg_autotune2d"):
         getattr(L, nm).restype = C.c_int32
     _lib = L
     return L

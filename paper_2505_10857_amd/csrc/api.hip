@@ -1103,6 +1103,13 @@ nmg_status nmg_nested_solve(const nmg_desc *descs, int32_t ngrids, const nmg_par
     return stats[0].status;
 }
 
+nmg_status nmg_autotune2d(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
+                          const double *J, const void *rhs, int32_t cycles, int32_t *best, double *ms, void *stream)
+{
+    if (!desc || desc->dim != 2 || !params) return fail(NMG_EINVAL, "nmg_autotune2d takes a 2D problem");
+    return autotune2d(desc, params, ws, ws_bytes, J, rhs, cycles, best, ms, (hipStream_t)stream);
+}
+
 nmg_status nmg_newton2d_begin(const nmg_desc *desc, const nmg_params *params, void *ws, size_t ws_bytes,
                               double *U, void *stream)
 {

@@ -37,6 +37,7 @@ struct Plan2D {
     int levels = 0, prec = NMG_FP64, nu1 = 0, nu2 = 0, nu3 = 1, n_max = 0, max_hist = 0, ntiles = 0;
     int check_every = 1;
     int sweeps = 0;            // smoother: the directional sweeps D1-D4 (NMG_LINEAR_MG_SWEEPS)
+    int sched = 0;             // launch schedule (NMG_SCHED2D_* bits)
     int bottom_first = 0;      // first level of the one-workgroup bottom (launch_bottom2d)
     double tau = 0.0, omega = 1.0, tol = 0.0;
     std::vector<Level2D> L;
@@ -74,6 +75,7 @@ nmg_status check2d(const nmg_desc *d, const nmg_params *p, bool need_geometry = 
         return set_error(NMG_EINVAL, "2D linear must be NMG_LINEAR_MG or NMG_LINEAR_MG_SWEEPS");
     if (p->linear == NMG_LINEAR_MG_SWEEPS && (long long)d->nx * d->ny > 65536)
         return set_error(NMG_EINVAL, "the directional sweeps take grids of at most 65536 cells");
+    if (p->schedule < 0 || p->schedule >= NMG_TUNE2D_CANDIDATES) return set_error(NMG_EINVAL, "bad 2D schedule");
     return NMG_OK;
 }
 
@@ -109,6 +111,16 @@ Inst2D make_inst2d(const nmg_desc *d, const nmg_params *p)
     return I;
 }
 
+// the first level of the one-workgroup bottom: the levels of at most kBottom2DCells cells (128
+// with NMG_SCHED2D_SMALL_BOTTOM) down to the coarsest
+void set_bottom(Plan2D &P)
+{
+    const long long lim = (P.sched & NMG_SCHED2D_SMALL_BOTTOM) ? 128 : kBottom2DCells;
+    P.bottom_first = P.levels - 1;
+    while (P.bottom_first > 0 && (long long)P.L[P.bottom_first - 1].nx * P.L[P.bottom_first - 1].ny <= lim)
+        P.bottom_first--;
+}
+
 nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p, bool need_geometry = true)
 {
     nmg_status st = check2d(d, p, need_geometry);
@@ -123,6 +135,7 @@ nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p, bool need_
     P.max_hist = std::min(std::max(p->n_max, 1), 100000);
     P.check_every = std::max(1, p->check_every);
     P.sweeps = p->linear == NMG_LINEAR_MG_SWEEPS ? 1 : 0;
+    P.sched = p->schedule;
     P.tau = p->tau;
     P.omega = p->omega;
     P.tol = p->tol;
@@ -155,10 +168,7 @@ nmg_status build2d(Plan2D &P, const nmg_desc *d, const nmg_params *p, bool need_
     P.off_rn = o; o = al256(o + sizeof(double) * n0);
     P.off_mg = o; o = al256(o + vsz * (size_t)e);
     const Level2D &Lc = P.L.back();
-    P.bottom_first = P.levels - 1;
-    while (P.bottom_first > 0 &&
-           (long long)P.L[P.bottom_first - 1].nx * P.L[P.bottom_first - 1].ny <= kBottom2DCells)
-        P.bottom_first--;
+    set_bottom(P);
     P.off_lu = o; o = al256(o + coarse_lu_bytes(3 * Lc.nx * Lc.ny));
     P.total = o;
     return NMG_OK;
@@ -181,11 +191,11 @@ nmg_status smooth(const Plan2D &P, char *mgb, int l, int nu, hipStream_t s)
             for (int q = 0; q < C; q++) {
                 const int c = (half & 1) ? C - 1 - q : q;
                 if (c == cur) { run++; continue; }
-                if (run > 0) HIP_TRY2(launch_smooth2d_pass(mgb, L, cur, run, P.omega, P.prec, s));
+                if (run > 0) HIP_TRY2(launch_smooth2d_pass(mgb, L, cur, run, P.omega, P.prec, s, P.sched));
                 cur = c;
                 run = 1;
             }
-    if (run > 0) HIP_TRY2(launch_smooth2d_pass(mgb, L, cur, run, P.omega, P.prec, s));
+    if (run > 0) HIP_TRY2(launch_smooth2d_pass(mgb, L, cur, run, P.omega, P.prec, s, P.sched));
     return NMG_OK;
 }
 
@@ -347,6 +357,49 @@ nmg_status newton2d_steps(const nmg_desc *d, const nmg_params *p, void *ws, size
         if ((st = newton_step(P, w, U, s)) != NMG_OK) return st;
     if (state_out)
         HIP_TRY2(hipMemcpyAsync(state_out, w + P.off_state, sizeof(NewtonState), hipMemcpyDeviceToHost, s));
+    return NMG_OK;
+}
+
+nmg_status autotune2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, const double *J,
+                      const void *rhs, int cycles, int *best, double *ms, hipStream_t s)
+{
+    if (!ws || !J || !rhs || !best || !ms) return set_error(NMG_EINVAL, "null argument");
+    if (cycles < 1 || cycles > 1000) return set_error(NMG_EINVAL, "cycles must be in [1, 1000]");
+    nmg_params q = *p;
+    q.schedule = 0;
+    Plan2D P;
+    nmg_status st = build2d(P, d, &q);
+    if (st != NMG_OK) return st;
+    if (P.sweeps) return set_error(NMG_EINVAL, "the schedules concern the multicolour smoother");
+    if (ws_bytes < P.total) return set_error(NMG_ENOMEM_WS, "workspace too small");
+    char *mgb = (char *)ws + P.off_mg;
+    const size_t vsz = P.prec == NMG_FP32_MG ? 4 : 8;
+    const Level2D &L0 = P.L[0];
+    HIP_TRY2(launch_permute2d(J, NMG_FP64, mgb + vsz * L0.J, P.prec, L0, 9 * L0.nb, 1, s));
+    HIP_TRY2(launch_dinv2d(J, mgb + vsz * L0.Dinv, L0, P.prec, s));
+    if ((st = coarsen_all(P, mgb, s)) != NMG_OK) return st;
+    HIP_TRY2(launch_permute2d(rhs, P.prec, mgb + vsz * L0.rhs, P.prec, L0, 3, 1, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY2(hipEventCreate(&e0));
+    struct Ev { hipEvent_t &a, &b; ~Ev() { if (a) (void)hipEventDestroy(a); if (b) (void)hipEventDestroy(b); } } guard{e0, e1};
+    HIP_TRY2(hipEventCreate(&e1));
+    int b = 0;
+    for (int c = 0; c < NMG_TUNE2D_CANDIDATES; c++) {
+        P.sched = c;
+        set_bottom(P);
+        HIP_TRY2(launch_fill(mgb + vsz * L0.dU, P.prec, 3 * L0.P.M, s));
+        if ((st = vcycle_from(P, mgb, 0, s)) != NMG_OK) return st;          // warm-up
+        HIP_TRY2(hipEventRecord(e0, s));
+        for (int k = 0; k < cycles; k++)
+            if ((st = vcycle_from(P, mgb, 0, s)) != NMG_OK) return st;
+        HIP_TRY2(hipEventRecord(e1, s));
+        HIP_TRY2(hipEventSynchronize(e1));
+        float t = 0.0f;
+        HIP_TRY2(hipEventElapsedTime(&t, e0, e1));
+        ms[c] = t / cycles;
+        if (ms[c] < ms[b]) b = c;
+    }
+    *best = b;
     return NMG_OK;
 }
 

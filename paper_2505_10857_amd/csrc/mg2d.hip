@@ -815,12 +815,12 @@ hipError_t launch_coarsen2d(void *mg, const Level2D &Lf, const Level2D &Lc, int 
 // are a long chain of loads for one thread (measured on the 1024 x 512 wedge: 35 against 56 ms
 // per FP64 V-cycle, 30 against 62 ms in FP32).  The cross and five-point passes keep one thread
 // per cell, whose loads all issue up front (13.2 against 13.7 ms FP64, 8.3 against 10.8 ms FP32
-// per J9 V-cycle).  Both forms give identical results.
+// per J9 V-cycle).  Both forms give identical results; alt (a schedule choice) swaps them.
 template <typename T, int NB, bool STREAM>
-static void smooth2d_launch(T *mg, const Level2D &L, int colour, int reps, double omega, hipStream_t s)
+static void smooth2d_launch(T *mg, const Level2D &L, int colour, int reps, double omega, hipStream_t s, bool alt)
 {
     const long long slots = (long long)L.P.ny * L.P.W;
-    if constexpr (NB == 21) {
+    if ((NB == 21) != alt) {
         dim3 grid((unsigned)((slots + kSplitCells - 1) / kSplitCells));
         hipLaunchKernelGGL((k_smooth2d_split<T, NB, STREAM>), grid, dim3(3 * kSplitCells), 0, s, mg, L, colour, omega, reps);
     } else {
@@ -830,30 +830,31 @@ static void smooth2d_launch(T *mg, const Level2D &L, int colour, int reps, doubl
 }
 
 hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, int reps, double omega, int prec,
-                               hipStream_t s)
+                               hipStream_t s, int sched)
 {
     if (L.P.C != (L.nb == 9 ? 3 : (L.nb == 21 ? 9 : 2))) return hipErrorInvalidValue;
     const bool f32 = prec == NMG_FP32_MG;
     const size_t vsz = f32 ? 4 : 8;
-    const bool big = (size_t)L.nb * 9 * (size_t)L.P.M * vsz > kMemCacheBytes;
+    const bool alt = (sched & (L.nb == 5 ? NMG_SCHED2D_ALT_COARSE : NMG_SCHED2D_ALT_FINEST)) != 0;
+    const bool big = !(sched & NMG_SCHED2D_NO_STREAM) && (size_t)L.nb * 9 * (size_t)L.P.M * vsz > kMemCacheBytes;
     // Operators larger than the memory-side cache: on the cross stencil the symmetric schedule
     // returns to colour 1 every other run and to colours 0 and 2 every fourth, so colours 0 and 2
     // stream their rows and leave the cache to colour 1's; with nine colours a colour's rows come
     // back only after the eight others have streamed theirs, so every pass streams.
     const bool stream = big && (L.nb == 21 || (L.nb == 9 && colour != 1));
     if (L.nb == 21) {
-        if (f32) { if (stream) smooth2d_launch<float, 21, true>((float *)mg, L, colour, reps, omega, s);
-                   else smooth2d_launch<float, 21, false>((float *)mg, L, colour, reps, omega, s); }
-        else { if (stream) smooth2d_launch<double, 21, true>((double *)mg, L, colour, reps, omega, s);
-               else smooth2d_launch<double, 21, false>((double *)mg, L, colour, reps, omega, s); }
+        if (f32) { if (stream) smooth2d_launch<float, 21, true>((float *)mg, L, colour, reps, omega, s, alt);
+                   else smooth2d_launch<float, 21, false>((float *)mg, L, colour, reps, omega, s, alt); }
+        else { if (stream) smooth2d_launch<double, 21, true>((double *)mg, L, colour, reps, omega, s, alt);
+               else smooth2d_launch<double, 21, false>((double *)mg, L, colour, reps, omega, s, alt); }
     } else if (L.nb == 9) {
-        if (f32) { if (stream) smooth2d_launch<float, 9, true>((float *)mg, L, colour, reps, omega, s);
-                   else smooth2d_launch<float, 9, false>((float *)mg, L, colour, reps, omega, s); }
-        else { if (stream) smooth2d_launch<double, 9, true>((double *)mg, L, colour, reps, omega, s);
-               else smooth2d_launch<double, 9, false>((double *)mg, L, colour, reps, omega, s); }
+        if (f32) { if (stream) smooth2d_launch<float, 9, true>((float *)mg, L, colour, reps, omega, s, alt);
+                   else smooth2d_launch<float, 9, false>((float *)mg, L, colour, reps, omega, s, alt); }
+        else { if (stream) smooth2d_launch<double, 9, true>((double *)mg, L, colour, reps, omega, s, alt);
+               else smooth2d_launch<double, 9, false>((double *)mg, L, colour, reps, omega, s, alt); }
     } else {
-        if (f32) smooth2d_launch<float, 5, false>((float *)mg, L, colour, reps, omega, s);
-        else smooth2d_launch<double, 5, false>((double *)mg, L, colour, reps, omega, s);
+        if (f32) smooth2d_launch<float, 5, false>((float *)mg, L, colour, reps, omega, s, alt);
+        else smooth2d_launch<double, 5, false>((double *)mg, L, colour, reps, omega, s, alt);
     }
     return hipGetLastError();
 }

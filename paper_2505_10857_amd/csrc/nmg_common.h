@@ -227,8 +227,9 @@ hipError_t launch_jacobian2d(const Inst2D &I, const Perm2D &P, void *J, void *rh
                              hipStream_t s, int nb = 9);
 hipError_t launch_coarsen2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
 // `reps` consecutive passes of one colour (the same neighbour values), one launch
+// sched: NMG_SCHED2D_* bits (the pass form and the streaming hints; results are the same)
 hipError_t launch_smooth2d_pass(void *mg, const Level2D &L, int colour, int reps, double omega, int prec,
-                               hipStream_t s);
+                               hipStream_t s, int sched = 0);
 hipError_t launch_restrict2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
 hipError_t launch_prolong2d(void *mg, const Level2D &Lf, const Level2D &Lc, int prec, hipStream_t s);
 // coarsest level: LU factors with row permutation (M*M doubles then M ints, M = 3 cells) once
@@ -267,6 +268,8 @@ nmg_status vcycle2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_
 nmg_status newton2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, double *U,
                     nmg_stats *stats, double *hist, int max_hist, hipStream_t s);
 nmg_status newton2d_begin(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, double *U, hipStream_t s);
+nmg_status autotune2d(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, const double *J,
+                      const void *rhs, int cycles, int *best, double *ms, hipStream_t s);
 nmg_status newton2d_steps(const nmg_desc *d, const nmg_params *p, void *ws, size_t ws_bytes, double *U, int steps,
                           nmg_newton_state *state_out, hipStream_t s);
 

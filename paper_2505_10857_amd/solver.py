@@ -33,6 +33,7 @@ def params_struct(p, precision: int = A.NMG_FP64, check_every: int = 4) -> A.nmg
     s.linear = getattr(p, "linear", A.NMG_LINEAR_MG)
     s.sor_max = getattr(p, "sor_max", 10)
     s.sor_tol = getattr(p, "sor_tol", 1e-7)
+    s.schedule = getattr(p, "schedule", 0)
     return s
 
 
@@ -378,6 +379,17 @@ class Solver2D:
                                      ws.numel(), _dptr(J) if J is not None else None, _dptr(rhs),
                                      _dptr(dU), 1 if setup else 0, C.c_void_p(_stream_ptr())))
         return dU
+
+    def autotune(self, J: torch.Tensor, rhs: torch.Tensor, cycles: int = 2):
+        """Time one V-cycle under every 2D launch schedule (nmg_autotune2d) on this operator;
+        returns (the fastest schedule, {schedule: ms per V-cycle}).  Pass the schedule as
+        schedule=... to later solvers of this problem (results are the same under every one)."""
+        ws = self.workspace()
+        best = C.c_int32()
+        ms = (C.c_double * A.NMG_TUNE2D_CANDIDATES)()
+        A.check(self.L.nmg_autotune2d(C.byref(self.dev.desc), C.byref(self.params), _dptr(ws), ws.numel(),
+                                      _dptr(J), _dptr(rhs), cycles, C.byref(best), ms, C.c_void_p(_stream_ptr())))
+        return best.value, {c: ms[c] for c in range(A.NMG_TUNE2D_CANDIDATES)}
 
     def newton_solve(self, U: torch.Tensor, max_hist: int = 0):
         """Algorithm 1 in place on U.  Returns (stats, history ndarray)."""

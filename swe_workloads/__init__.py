@@ -57,6 +57,7 @@ class Params:
     linear: int = 0
     sor_max: int = 10
     sor_tol: float = 1e-7
+    schedule: int = 0           # 2D launch schedule (speed only; results are the same)
 
 
 @dataclasses.dataclass

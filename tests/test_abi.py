@@ -40,7 +40,7 @@ def test_struct_sizes_match_header_layout():
     abi, _ = _lib()
     assert ctypes.sizeof(abi.nmg_bc) == 40
     assert ctypes.sizeof(abi.nmg_desc) == 24 + 40 + 4 * 40 + 8 + 7 * 8
-    assert ctypes.sizeof(abi.nmg_params) == 5 * 8 + 8 * 4 + 8
+    assert ctypes.sizeof(abi.nmg_params) == 5 * 8 + 8 * 4 + 8 + 2 * 4
     assert ctypes.sizeof(abi.nmg_plan_options) == 8 * 4
     assert abi.NMG_TUNE_CANDIDATES == 32
 
@@ -220,3 +220,24 @@ def test_linear_solver_choices_per_dimension():
     d2.nx, d2.ny, d2.levels = 512, 256, 7
     assert L.nmg_workspace_bytes(ctypes.byref(d2), ctypes.byref(p2)) == 0
     assert b"65536" in L.nmg_last_error()
+
+
+def test_2d_schedule_is_checked():
+    abi, L = _lib()
+    d = abi.nmg_desc()
+    d.dim, d.nx, d.ny, d.levels, d.jac = 2, 32, 16, 3, 9
+    d.x0, d.x1, d.y0, d.y1, d.g = 0.0, 4.0, 0.0, 2.0, 9.81
+    for k in range(4):
+        d.bc[k].kind = abi.NMG_BC_WALL
+    p = abi.nmg_params()
+    p.eps, p.nu1, p.nu2, p.nu3, p.n_max = 1e-6, 2, 2, 1, 10
+    for c in range(abi.NMG_TUNE2D_CANDIDATES):
+        p.schedule = c
+        assert L.nmg_workspace_bytes(ctypes.byref(d), ctypes.byref(p)) > 0
+    p.schedule = abi.NMG_TUNE2D_CANDIDATES
+    assert L.nmg_workspace_bytes(ctypes.byref(d), ctypes.byref(p)) == 0
+    p.schedule = 0
+    best = ctypes.c_int32()
+    ms = (ctypes.c_double * abi.NMG_TUNE2D_CANDIDATES)()
+    assert L.nmg_autotune2d(ctypes.byref(d), ctypes.byref(p), None, 0, None, None, 1, ctypes.byref(best), ms,
+                            None) == abi.NMG_EINVAL
