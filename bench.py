@@ -730,6 +730,25 @@ def main():
             "newton_steps_finest": [min(x[0] for x in fin), max(x[0] for x in fin)],
             "newton_steps_per_grid_instance0": [r[0][0] for r in rep[-1]],
             "converged": all(x[1] == 0 and x[2] < 1e-10 for x in fin)}
+        del nb_, sets
+        # the same with the full Jacobian J5 on every multigrid grid (the coarsest, solved
+        # directly, keeps J3): full against simplified Jacobian on the transcritical variant
+        nb5 = NestedBatch(tprobs, device="cuda:0", precision=NMG_FP64, jac=5)
+        sets = [nb5.states() for _ in range(3)]
+        torch.cuda.synchronize()
+        nb5.solve(sets[0], use_graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep5 = [nb5.solve(sets[k], use_graph) for k in (1, 2)]
+        torch.cuda.synchronize()
+        et5 = time.perf_counter() - t0
+        fin5 = rep5[-1][-1]
+        forms["fp64_batch_trans_nested_J5"] = {
+            "solves_per_s": 2 * args.batch / et5, "batch": args.batch,
+            "newton_steps_finest": [min(x[0] for x in fin5), max(x[0] for x in fin5)],
+            "newton_steps_per_grid_instance0": [r[0][0] for r in rep5[-1]],
+            "converged": all(x[1] == 0 and x[2] < 1e-10 for x in fin5)}
+        del nb5, sets
         # uneven batch: 512 instances, N log-uniform in [256, 16384], FP32 multigrid, one plan
         from swe_workloads import config4_instance
         uprobs = [config4_instance(i) for i in range(512)]

@@ -528,7 +528,9 @@ class NestedBatch:
     Each instance's result equals its own nested solve (no cross-instance arithmetic)."""
 
     def __init__(self, probs: Sequence, ngrids: Optional[int] = None, device="cuda",
-                 precision: int = A.NMG_FP64, check_every: int = 4):
+                 precision: int = A.NMG_FP64, check_every: int = 4, jac: int = 3):
+        """jac: 3 or 5 on the grids solved by the Newton multigrid iteration; the coarsest grid,
+        solved directly (a one-level hierarchy, block tridiagonal), always takes J3."""
         from swe_workloads import nested_grids
         A.load()
         self.grids = [nested_grids(p, ngrids) for p in probs]      # [instance][grid]
@@ -539,7 +541,8 @@ class NestedBatch:
         self.n = len(probs)
         self.device = device
         self.plans = [BatchSolver1D([g[k] for g in self.grids], device=device, precision=precision,
-                                    check_every=check_every) for k in range(ng)]
+                                    check_every=check_every, jac=(3 if self.grids[0][k].levels == 1 else jac))
+                      for k in range(ng)]
 
     def states(self):
         """Fresh per-grid state buffers with the coarsest initial guesses filled in."""

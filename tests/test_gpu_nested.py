@@ -106,3 +106,30 @@ def test_nested_solve_2d_matches_the_oracle():
     for (nx, ny, it, _, _), (nxo, nyo, ito, _) in zip(rep, rep_o[::-1]):
         assert (nx, ny) == (nxo, nyo) and abs(it - ito) <= 1
     assert err <= 1e-10
+
+
+def test_nested_batch_with_the_full_jacobian_matches_the_oracle():
+    """Transcritical hump, 800 cells, 4 grids, J5 on the multigrid grids (the coarsest, solved
+    directly, keeps J3): the oracle run grid by grid with the same Jacobians gives the same
+    Newton steps (within one) and the same finest state."""
+    from paper_2505_10857_amd.solver import NestedBatch
+    from swe_workloads import nested_grids
+    prob = config2(0, "trans", n=800, levels=4)
+    nb = NestedBatch([prob], device=DEV, jac=5)
+    Us = nb.states()
+    rep = nb.solve(Us, use_graph=True)
+    grids = nested_grids(prob)
+    U = grids[-1].initial_guess()
+    steps = []
+    for g in range(len(grids) - 1, -1, -1):
+        if g < len(grids) - 1:
+            U = oracle.interp_a2(U)
+        U, it, res, _ = oracle.Oracle1D(grids[g]).newton_solve(U0=U, nb=3 if g == len(grids) - 1 else 5,
+                                                               levels=len(grids) - g)
+        steps.append(it)
+    gpu_steps = [r[0][0] for r in rep]
+    err = np.abs(Us[0][0].cpu().numpy() - U).max()
+    print("J5 nested: gpu", gpu_steps, "oracle", steps, f"|dU| {err:.2e}", flush=True)
+    assert all(r[0][1] == 0 for r in rep)
+    assert all(abs(a - b) <= 1 for a, b in zip(gpu_steps, steps))
+    assert err <= 1e-10
