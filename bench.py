@@ -273,6 +273,7 @@ def served(args, rate):
         Uo, _, _, _ = oracle.Oracle1D(reqs[r.rid].prob).newton_solve()
         errs.append(float(np.abs(r.state.cpu().numpy() - Uo).max()))
     out["max_abs_err_vs_fp64_oracle_two_smallest"] = max(errs) if errs else None
+    eng.close()
     return out
 
 
@@ -308,6 +309,33 @@ def served_mixed(args, rate=200.0, count=2000, frac_2d=0.005):
                requests_2d=sum(hasattr(r.prob, "ny") for r in reqs), workers_2d=eng.workers_2d,
                solo_2d_service_fp32mg=svc, mean_2d_service_s=mean_svc,
                one_lane_2d_req_s=1.0 / mean_svc)
+    return out
+
+
+def served_overload(args, rate=200.0, frac_2d=0.3, arrive_s=5.0, stop_s=10.0, workers_2d=3, lanes_2d_busy=None):
+    """The 70 % 1D / 30 % 2D Poisson stream at 200 req/s (FP32 multigrid, HBM budget 80 % of the
+    free device memory), which asks for far more 2D solves than the device completes: arrivals
+    for arrive_s seconds, the server stopped at stop_s; the 1D latencies, the 2D completion rate
+    (the 2D lane saturated) and the requests left waiting are reported."""
+    import torch
+    from paper_2505_10857_amd import NMG_FP32_MG
+    from paper_2505_10857_amd.serve import GpuEngine, Server, stream, stream_mixed
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    count = int(rate * arrive_s)
+    reqs = stream_mixed(count, rate=rate, frac_2d=frac_2d, seed=5)
+    eng = GpuEngine("cuda:0", precision=NMG_FP32_MG, workers_2d=workers_2d)
+    Server(eng, hbm_budget=budget, steps_per_tick=2).run(stream(16, rate=rate, seed=99))
+    Server(eng, hbm_budget=budget, steps_per_tick=2).run(stream_mixed(6, rate=rate, frac_2d=0.5, seed=98))
+    rep = Server(eng, hbm_budget=budget, steps_per_tick=2, lanes_2d_busy=lanes_2d_busy).run(reqs, stop_after=stop_s)
+    eng.close()
+    out = rep.summary()
+    n2 = sum(hasattr(r.prob, "ny") for r in reqs)
+    out.update(rate_req_s=rate, frac_2d=frac_2d, arrivals_s=arrive_s, stopped_at_s=stop_s,
+               requests=count, requests_1d=count - n2, requests_2d=n2, workers_2d=eng.workers_2d,
+               lanes_2d_while_1d_busy=lanes_2d_busy,
+               hbm_budget_gib=budget / 2**30,
+               completed_2d_per_s=out.get("completed_2d", 0) / stop_s)
     return out
 
 
@@ -531,7 +559,8 @@ def main():
         print(json.dumps({"wedge2d_1024x512": wedge2d_form()}))
         return
     if args.served_only:
-        print(json.dumps({"served_200rps": served(args, 200.0), "served_mixed_1d_2d": served_mixed(args)}))
+        print(json.dumps({"served_200rps": served(args, 200.0), "served_mixed_1d_2d": served_mixed(args),
+                          "served_overload_70_30": served_overload(args)}))
         return
     if args.nmgm21_only:
         print(json.dumps({"nmgm21_vs_nmgm9": nmgm21_form()}))
@@ -777,6 +806,8 @@ def main():
         forms["served_saturated"] = served(args, 1e7)
         log("form served_mixed_1d_2d")
         forms["served_mixed_1d_2d"] = served_mixed(args)
+        log("form served_overload_70_30")
+        forms["served_overload_70_30"] = served_overload(args)
         out["forms"] = forms
 
     # ---- CPU oracle ----------------------------------------------------------------------------

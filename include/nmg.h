@@ -379,6 +379,18 @@ nmg_status nmg_plan_autotune(nmg_plan *plan, void *ws, size_t ws_bytes, double *
                              int32_t trial_steps, int32_t use_graph, nmg_plan_options *best,
                              double *times_ms, void *stream);
 
+/* A stream for one lane of a server (the batched 1D lane, each 2D worker) on a hardware queue
+ * of its own.  The runtime spreads ordinary streams over a few hardware queues (four by
+ * default), so two streams can share one and the kernels of one then wait behind those of the
+ * other: a long 2D solve would hold up every launch of the latency-bound 1D batch.  A stream
+ * made with a compute-unit mask gets a queue that no other stream shares; the mask here enables
+ * every compute unit of the current device, so the stream runs anywhere on the GPU.  Like a
+ * blocking stream it orders with the null stream: a lane should not share work with the null
+ * stream.  *stream (host) receives the handle, owned by the caller and released with
+ * nmg_lane_stream_destroy (which waits for its work).  NMG_EHIP if the runtime refuses. */
+nmg_status nmg_lane_stream_create(void **stream);
+nmg_status nmg_lane_stream_destroy(void *stream);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char *nmg_last_error(void);
 

@@ -49,6 +49,8 @@ EXPORTS = [
     "nmg_newton2d_begin",
     "nmg_newton2d_steps",
     "nmg_autotune2d",
+    "nmg_lane_stream_create",
+    "nmg_lane_stream_destroy",
 ]
 
 NMG_STATIC_WS_MIB = 64
@@ -145,6 +147,8 @@ def load(path: str = LIB_PATH):
     L.nmg_newton2d_steps.argtypes = [P(nmg_desc), P(nmg_params), vp, sz, vp, C.c_int32, vp, vp]
     L.nmg_autotune2d.argtypes = [P(nmg_desc), P(nmg_params), vp, sz, vp, vp, C.c_int32, P(C.c_int32),
                                  P(C.c_double), vp]
+    L.nmg_lane_stream_create.argtypes = [P(vp)]
+    L.nmg_lane_stream_destroy.argtypes = [vp]
     L.nmg_nested_workspace_bytes.argtypes = [P(nmg_desc), C.c_int32, P(nmg_params)]
     L.nmg_nested_workspace_bytes.restype = sz
     L.nmg_nested_solve.argtypes = [P(nmg_desc), C.c_int32, P(nmg_params), vp, sz, P(vp), P(nmg_stats), vp]
@@ -164,7 +168,8 @@ def load(path: str = LIB_PATH):
                "nmg_newton_solve", "nmg_newton_solve_static", "nmg_plan_create", "nmg_plan_solve", "nmg_plan_begin",
                "nmg_plan_steps", "nmg_plan_resume", "nmg_plan_set_options", "nmg_plan_get_options",
                "nmg_plan_autotune", "nmg_interp_coarse_to_fine", "nmg_interp2d_coarse_to_fine",
-               "nmg_nested_solve", "nmg_newton2d_begin", "nmg_newton2d_steps", "nmg_autotune2d"):
+               "nmg_nested_solve", "nmg_newton2d_begin", "nmg_newton2d_steps", "nmg_autotune2d",
+               "nmg_lane_stream_create", "nmg_lane_stream_destroy"):
         getattr(L, nm).restype = C.c_int32
     _lib = L
     return L

@@ -801,6 +801,30 @@ extern "C" {
 
 const char *nmg_last_error(void) { return g_err.c_str(); }
 
+nmg_status nmg_lane_stream_create(void **stream)
+{
+    if (!stream) return fail(NMG_EINVAL, "null argument");
+    *stream = nullptr;
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (cus <= 0 || cus > 1024) return fail(NMG_EHIP, "unexpected compute-unit count");
+    std::vector<uint32_t> mask((cus + 31) / 32, 0xFFFFFFFFu);
+    if (cus % 32) mask.back() = (1u << (cus % 32)) - 1u;
+    hipStream_t s = nullptr;
+    HIP_TRY(hipExtStreamCreateWithCUMask(&s, (uint32_t)mask.size(), mask.data()));
+    *stream = s;
+    return NMG_OK;
+}
+
+nmg_status nmg_lane_stream_destroy(void *stream)
+{
+    if (!stream) return fail(NMG_EINVAL, "null stream");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    HIP_TRY(hipStreamDestroy((hipStream_t)stream));
+    return NMG_OK;
+}
+
 nmg_status nmg_plan_create(const nmg_desc *descs, const nmg_params *params, int32_t n, nmg_plan **out)
 {
     if (!descs || !params || !out) return fail(NMG_EINVAL, "null argument");

@@ -1,7 +1,9 @@
 """Continuous-batching server for steady 1D and 2D solves (Algorithm 1 per request).
 
-Requests arrive over time; a request is admitted, in arrival order, as soon as the device memory
-it needs fits in the HBM budget.  1D requests then run inside the same batched launches as every
+Requests arrive over time and wait in one queue per lane (1D, 2D); a request is admitted, in
+arrival order within its lane, as soon as the device memory it needs fits in the HBM budget (a
+2D request also needs a free 2D worker), so a large 2D request that must wait never holds up the
+1D requests behind it.  1D requests then run inside the same batched launches as every
 other admitted 1D request (one plan over all of them, ``nmg_plan_*``).  The server works in
 ticks: each tick runs a few Newton steps on the 1D batch and reads the per-request convergence
 state.  A request that converges is retired at once (its result recorded); its slot stays in the
@@ -33,6 +35,8 @@ from typing import Any, Callable, Dict, List, Optional, Sequence
 
 import numpy as np
 
+from ._abi import NMG_ENONFINITE
+
 
 @dataclasses.dataclass
 class Request:
@@ -54,6 +58,7 @@ class Result:
     footprint: int            # device bytes reserved for the request
     state: Any = None         # the final state (device tensor) when kept
     dim: int = 1
+    retries: int = 0          # 1 when the result is the retry's (smaller SOR weight)
 
     @property
     def latency(self) -> float:
@@ -70,6 +75,7 @@ class ServeReport:
     peak_bytes: int
     span: float               # first arrival to last completion, seconds
     rejected: List[int]
+    unfinished: int = 0       # requests still waiting or iterating when the run was stopped
 
     @property
     def solves_per_s(self) -> float:
@@ -80,12 +86,17 @@ class ServeReport:
         return float(np.percentile(lat, q)) if len(lat) else float("nan")
 
     def summary(self) -> Dict[str, Any]:
-        out = dict(completed=len(self.results), rejected=len(self.rejected),
+        out = dict(completed=len(self.results), rejected=len(self.rejected), unfinished=self.unfinished,
                    solves_per_s=self.solves_per_s, p50_ms=self.latency_ms(50),
                    p99_ms=self.latency_ms(99), ticks=self.ticks, plans=self.plans,
                    max_batch=self.max_batch, mean_batch=self.mean_batch,
                    peak_bytes=self.peak_bytes, span_s=self.span,
-                   converged=all(r.status == 0 for r in self.results))
+                   converged=all(r.status == 0 for r in self.results),
+                   retried=sum(r.retries for r in self.results))
+        bad = [r for r in self.results if r.status != 0]
+        if bad:
+            out["not_converged"] = [dict(rid=r.rid, dim=r.dim, n=r.n, status=r.status, iters=r.iters,
+                                         res=r.res) for r in bad[:8]]
         n2 = sum(1 for r in self.results if r.dim == 2)
         if n2:
             out.update(completed_1d=len(self.results) - n2, completed_2d=n2,
@@ -95,20 +106,44 @@ class ServeReport:
 
 
 class GpuEngine:
-    """Device side of the server: libnmg's batched plan over the admitted requests."""
+    """Device side of the server: libnmg's batched plan over the admitted requests.
+
+    Each lane (the 1D batch, every 2D worker) works on a stream of its own, by default one on a
+    hardware queue of its own (nmg_lane_stream_create): on ordinary streams, which the runtime
+    spreads over four hardware queues, a 2D worker could share the 1D lane's queue (or the null
+    stream's) and every 1D launch would then wait behind its solve.  The engine's device work
+    (geometry and state uploads included) stays on the lanes, none on the null stream."""
 
     def __init__(self, device="cuda:0", precision: Optional[int] = None, use_graph: bool = True,
-                 workers_2d: int = 3):
+                 workers_2d: int = 3, dedicated_queues: bool = True):
         from . import _abi as A
         self.A = A
         self.L = A.load()
         self.device = device
         self.precision = A.NMG_FP32_MG if precision is None else precision
         self.use_graph = use_graph
+        self.dedicated_queues = dedicated_queues
         self._jobs2d: Optional[queue.Queue] = None
         self._workers: List[threading.Thread] = []
         self.workers_2d = max(1, workers_2d)
         self._stream1d = None
+        self._handle1d = None
+
+    def _new_lane(self):
+        """(torch stream, handle to destroy or None) for one lane, on the engine's device."""
+        import ctypes as C
+        import torch
+        if not self.dedicated_queues:
+            return torch.cuda.Stream(self.device), None
+        with torch.cuda.device(self.device):
+            h = C.c_void_p()
+            self.A.check(self.L.nmg_lane_stream_create(C.byref(h)))
+        return torch.cuda.ExternalStream(h.value, device=self.device), h.value
+
+    def _lane1d(self):
+        if self._stream1d is None:
+            self._stream1d, self._handle1d = self._new_lane()
+        return self._stream1d
 
     @staticmethod
     def is2d(prob) -> bool:
@@ -144,9 +179,10 @@ class GpuEngine:
     def prepare(self, prob):
         import torch
         from .solver import Problem1DDevice
-        dev = Problem1DDevice(prob, self.device, 3)
-        U = torch.tensor(np.ascontiguousarray(prob.initial_guess()), dtype=torch.float64,
-                         device=self.device)
+        with torch.cuda.stream(self._lane1d()):
+            dev = Problem1DDevice(prob, self.device, 3)
+            U = torch.tensor(np.ascontiguousarray(prob.initial_guess()), dtype=torch.float64,
+                             device=self.device)
         return dict(prob=prob, dev=dev, U=U)
 
     # ---- 2D lane: a worker thread solves the admitted 2D requests in order on its own stream
@@ -155,10 +191,12 @@ class GpuEngine:
         import torch
         from .solver import Solver2D
         torch.cuda.set_device(self.device)
-        side = torch.cuda.Stream(self.device)
+        side, handle = self._new_lane()
         while True:
             job = self._jobs2d.get()
             if job is None:
+                if handle is not None:
+                    self.A.check(self.L.nmg_lane_stream_destroy(handle))
                 return
             try:
                 with torch.cuda.stream(side):
@@ -196,22 +234,28 @@ class GpuEngine:
         return job["U"]
 
     def close(self):
+        """Stop the 2D workers: jobs still queued are dropped, running solves are waited for."""
+        if self._jobs2d is not None:
+            while True:
+                try:
+                    self._jobs2d.get_nowait()
+                except queue.Empty:
+                    break
         for _ in self._workers:
             self._jobs2d.put(None)
         for t in self._workers:
             t.join()
         self._workers = []
+        if self._handle1d is not None:
+            self.A.check(self.L.nmg_lane_stream_destroy(self._handle1d))
+        self._stream1d = self._handle1d = None
 
     def batch(self, prepared: Sequence[dict]):
         import torch
         from .solver import BatchSolver1D
-        # the 1D lane has a stream of its own (its plans then capture and replay their graphs on
-        # it, with no stream of their own to create); it starts after the geometry and states
-        # the loop's thread wrote on the current stream
-        if self._stream1d is None:
-            self._stream1d = torch.cuda.Stream(self.device)
-        self._stream1d.wait_stream(torch.cuda.current_stream(self.device))
-        with torch.cuda.stream(self._stream1d):
+        # the 1D lane's stream (its plans capture and replay their graphs on it, with no stream
+        # of their own to create) already holds the uploads of prepare(), in order
+        with torch.cuda.stream(self._lane1d()):
             bs = BatchSolver1D([p["prob"] for p in prepared], device=self.device, precision=self.precision,
                                devs=[p["dev"] for p in prepared])
         return _GpuBatch(bs, [p["U"] for p in prepared], self.use_graph, self._stream1d)
@@ -241,20 +285,43 @@ class _GpuBatch:
 
 class Server:
     """Request loop: admit by HBM footprint, batch every admitted request into each launch,
-    retire at convergence (or failure), report latency percentiles and throughput."""
+    retire at convergence (or failure), report latency percentiles and throughput.
+
+    lanes_2d_busy, when set, caps the 2D solves running while 1D requests are waiting or iterating
+    (the engine's worker count applies otherwise): a policy for engines whose 2D solves slow the
+    1D batch down (their lanes sharing its hardware queue, or the device full).  retry_omega: a request whose iteration breaks
+    down (a non-finite residual or a non-positive depth) is queued once more, at its arrival, with
+    this SOR weight when its own is larger (a V-cycle that diverges at the larger weight on a
+    strongly varying channel converges at the smaller one); None turns retries off."""
 
     def __init__(self, engine, hbm_budget: int, steps_per_tick: int = 2,
-                 keep_states: bool = False, trace: bool = False):
+                 keep_states: bool = False, trace: bool = False, lanes_2d_busy: Optional[int] = None,
+                 retry_omega: Optional[float] = 0.6):
         if steps_per_tick < 1:
             raise ValueError("steps_per_tick must be >= 1")
+        if lanes_2d_busy is not None and lanes_2d_busy < 1:
+            raise ValueError("lanes_2d_busy must be >= 1")
         self.engine = engine
         self.budget = int(hbm_budget)
         self.steps_per_tick = steps_per_tick
         self.keep_states = keep_states
         self.trace = [] if trace else None      # (start, seconds, what) of the loop's phases
+        self.lanes_2d_busy = lanes_2d_busy
+        self.retry_omega = retry_omega
+
+    def _retried(self, prob):
+        """The request's problem with the retry's SOR weight, or None when there is no retry."""
+        par = getattr(prob, "params", None)
+        if self.retry_omega is None or par is None or not dataclasses.is_dataclass(prob) \
+                or par.omega <= self.retry_omega:
+            return None
+        return dataclasses.replace(prob, params=dataclasses.replace(par, omega=self.retry_omega))
 
     def run(self, requests: Sequence[Request], clock: Optional[Callable[[], float]] = None,
-            sleep: Optional[Callable[[float], None]] = None, poll: float = 2e-4) -> ServeReport:
+            sleep: Optional[Callable[[float], None]] = None, poll: float = 2e-4,
+            stop_after: Optional[float] = None) -> ServeReport:
+        """Serve the stream; stop_after (seconds from the start) ends the run early, counting the
+        requests not completed by then as unfinished."""
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         if clock is None:
             t0 = time.perf_counter()
@@ -263,12 +330,15 @@ class Server:
             sleep = time.sleep
         eng = self.engine
         is2d = getattr(eng, "is2d", lambda prob: False)
-        waiting: collections.deque = collections.deque()
+        lanes_2d = getattr(eng, "workers_2d", 1 << 30)
+        waiting: collections.deque = collections.deque()      # 1D
+        waiting2: collections.deque = collections.deque()     # 2D
         plan_items: List[dict] = []      # the 1D plan's requests in plan order (retired ones kept
         pending: List[dict] = []         # until it is rebuilt); admitted 1D requests not yet in it
         active2d: List[dict] = []
         results: List[Result] = []
         rejected: List[int] = []
+        retried: set = set()
         used = held = 0                  # held: bytes of retired 1D requests still in the plan
         peak = 0
         nxt = 0
@@ -282,11 +352,23 @@ class Server:
 
         def record(a, iters, status, res, t, state, dim, cells):
             r = a["req"]
+            if status == NMG_ENONFINITE and not a.get("retry"):
+                prob = self._retried(r.prob)
+                if prob is not None:
+                    # admitted before every request still waiting in its lane: first in line
+                    (waiting2 if dim == 2 else waiting).appendleft((Request(r.rid, prob, r.arrival), a["fp"]))
+                    retried.add(r.rid)
+                    return
             results.append(Result(r.rid, cells, iters, status, res, r.arrival, a["admitted"], t, a["fp"],
-                                  state if self.keep_states else None, dim))
+                                  state if self.keep_states else None, dim, int(r.rid in retried)))
 
-        while nxt < len(reqs) or waiting or pending or active2d or any(not a["retired"] for a in plan_items):
+        stopped = False
+        while nxt < len(reqs) or waiting or waiting2 or pending or active2d or \
+                any(not a["retired"] for a in plan_items):
             now = clock()
+            if stop_after is not None and now >= stop_after:
+                stopped = True
+                break
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
                 r = reqs[nxt]
                 nxt += 1
@@ -294,11 +376,21 @@ class Server:
                 if fp > self.budget:
                     rejected.append(r.rid)       # can never fit
                     continue
-                waiting.append((r, fp))
-            # admission in arrival order, while the budget allows; the memory of retired 1D slots
-            # is reclaimed (the plan rebuilt without them) when the next request needs it
-            while waiting:
-                r, fp = waiting[0]
+                (waiting2 if is2d(r.prob) else waiting).append((r, fp))
+            # admission in arrival order within each lane, while the budget allows; the memory of
+            # retired 1D slots is reclaimed (the plan rebuilt without them) when a request needs it
+            while True:
+                heads = []
+                if waiting:
+                    heads.append(waiting)
+                busy1d = waiting or pending or any(not a["retired"] for a in plan_items)
+                cap2 = min(lanes_2d, self.lanes_2d_busy) if busy1d and self.lanes_2d_busy else lanes_2d
+                if waiting2 and len(active2d) < cap2:
+                    heads.append(waiting2)
+                if not heads:
+                    break
+                q = min(heads, key=lambda d: d[0][0].arrival)
+                r, fp = q[0]
                 if used + fp > self.budget:
                     if held and used - held + fp <= self.budget:
                         plan_items = [a for a in plan_items if not a["retired"]]
@@ -308,9 +400,15 @@ class Server:
                         pending = plan_items + pending
                         plan_items = []
                         continue
-                    break
-                waiting.popleft()
-                a = dict(req=r, fp=fp, n_done=0, admitted=now, retired=False)
+                    # this lane's head waits; the other lane may still admit
+                    others = [d for d in heads if d is not q]
+                    if others and used + others[0][0][1] <= self.budget:
+                        q = others[0]
+                        r, fp = q[0]
+                    else:
+                        break
+                q.popleft()
+                a = dict(req=r, fp=fp, n_done=0, admitted=now, retired=False, retry=r.rid in retried)
                 t_a = clock()
                 if is2d(r.prob):
                     a["prep"] = eng.prepare2d(r.prob)
@@ -380,12 +478,16 @@ class Server:
                 due = reqs[nxt].arrival - clock() if nxt < len(reqs) else poll
                 sleep(max(0.0, min(poll, due)))
             elif nxt < len(reqs) and not waiting:
-                sleep(max(0.0, reqs[nxt].arrival - clock()))
+                due = reqs[nxt].arrival - clock()
+                sleep(max(0.0, due if not waiting2 else min(poll, due)))
+            elif waiting2:
+                sleep(poll)                      # 2D requests wait for memory or a worker
         arrivals = [r.arrival for r in reqs]
         span = (max(r.finished for r in results) - min(arrivals)) if results else 0.0
         results.sort(key=lambda r: r.rid)
+        unfinished = len(reqs) - len(results) - len(rejected) if stopped else 0
         return ServeReport(results, ticks, plans, max_batch,
-                           batch_sum / ticks if ticks else 0.0, peak, span, rejected)
+                           batch_sum / ticks if ticks else 0.0, peak, span, rejected, unfinished)
 
 
 def stream(count: int, rate: float = 200.0, seed: int = 0, n_min: int = 512,

@@ -4,6 +4,8 @@ The stand-in engine converges request r after a known number of Newton steps and
 the server asks of it, so the tests check admission by footprint, arrival order, re-planning
 with carried step counts, retirement and the latency statistics without a GPU.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -248,3 +250,123 @@ def test_2d_requests_run_beside_the_1d_batch():
     assert rep.results[1].finished >= 3 * 5e-3 - 1e-12
     s = rep.summary()
     assert s["completed_2d"] == 3 and s["completed_1d"] == 2 and s["converged"]
+
+
+def _req(rid, p, t):
+    p.rid = rid
+    return Request(rid, p, t)
+
+
+def test_a_waiting_2d_request_does_not_hold_up_1d_requests():
+    """Budget 500: a 1D request (footprint 300) is running when a 2D request (footprint 320) and
+    then a small 1D request (footprint 100) arrive.  The 2D request waits for memory; the 1D
+    request behind it is admitted at once, and the 2D request once the first 1D request ends."""
+    ft = FakeTime()
+    eng = FakeEngine2D(ft, tick=1e-3, k=4, chunk_time=5e-3)
+    reqs = [_req(0, FakeProb(30, 20), 0.0), _req(1, FakeProb2D(8, 4, 4), 0.001), _req(2, FakeProb(10, 2), 0.002)]
+    rep = Server(eng, hbm_budget=500, steps_per_tick=1).run(reqs, clock=ft.clock, sleep=ft.sleep)
+    r0, r1, r2 = rep.results
+    assert r2.admitted < r0.finished                 # the small 1D request did not wait
+    assert r1.admitted >= r0.finished - 1e-12        # the 2D request waited for memory
+    assert rep.peak_bytes <= 500 and rep.summary()["converged"]
+
+
+def test_2d_requests_beyond_the_workers_wait_without_memory():
+    """With two 2D workers, a third 2D request is admitted (its memory reserved) only when one
+    of the first two is done."""
+    ft = FakeTime()
+    eng = FakeEngine2D(ft, tick=1e-3, k=4, chunk_time=5e-3)
+    eng.workers_2d = 2
+    reqs = [_req(i, FakeProb2D(8, 4, 8), 0.0) for i in range(3)]
+    rep = Server(eng, hbm_budget=10**6, steps_per_tick=1).run(reqs, clock=ft.clock, sleep=ft.sleep)
+    r = rep.results
+    assert r[2].admitted >= min(r[0].finished, r[1].finished) - 1e-12
+    assert rep.peak_bytes == 2 * 8 * 4 * 10
+
+
+def test_stop_after_counts_unfinished_requests():
+    """A stream longer than the run: requests not completed when it is stopped are reported as
+    unfinished, not dropped silently."""
+    ft = FakeTime()
+    eng = FakeEngine2D(ft, tick=1e-3, k=4, chunk_time=5e-3)
+    reqs = [_req(i, FakeProb(10, 5), 0.01 * i) for i in range(20)]
+    rep = Server(eng, hbm_budget=10**6, steps_per_tick=1).run(
+        reqs, clock=ft.clock, sleep=ft.sleep, stop_after=0.1)
+    s = rep.summary()
+    assert s["unfinished"] == 20 - s["completed"] > 0
+    assert all(r.finished <= 0.1 + 1e-2 for r in rep.results)
+
+
+@dataclasses.dataclass
+class _W:
+    omega: float
+
+
+@dataclasses.dataclass
+class BreakingProb:
+    """A 1D stand-in whose iteration breaks down at an SOR weight above 0.7 after `fail_at` steps
+    and converges after `need` steps otherwise."""
+    n: int
+    need: int
+    fail_at: int
+    params: _W
+    rid: int = 0
+
+
+class FakeEngineBreak(FakeEngine2D):
+    def prepare(self, prob):
+        d = dict(rid=prob.rid, need=prob.need, steps=0)
+        if getattr(prob, "params", None) is not None and prob.params.omega > 0.7:
+            d["need"] = prob.fail_at
+            d["breaks"] = True
+        return d
+
+    def batch(self, prepared):
+        return FakeBatchBreak(self, list(prepared))
+
+
+class FakeBatchBreak(FakeBatch):
+    def steps(self, k):
+        flags, stats = super().steps(k)
+        return flags, [(it, -4 if item.get("breaks") and not f else st, res)
+                       for (it, st, res), f, item in zip(stats, flags, self.items)]
+
+
+def test_a_broken_down_request_is_retried_once_at_the_smaller_weight():
+    ft = FakeTime()
+    eng = FakeEngineBreak(ft)
+    reqs = [_req(0, BreakingProb(10, 7, 3, _W(0.8)), 0.0), _req(1, FakeProb(10, 4), 0.0),
+            _req(2, BreakingProb(10, 5, 2, _W(0.6)), 0.0)]
+    rep = Server(eng, hbm_budget=10**6, steps_per_tick=1).run(reqs, clock=ft.clock, sleep=ft.sleep)
+    r0, r1, r2 = rep.results
+    assert (r0.status, r0.iters, r0.retries) == (0, 7, 1)     # retried at 0.6, then converged
+    assert (r1.status, r1.retries) == (0, 0)
+    assert (r2.status, r2.iters, r2.retries) == (0, 5, 0)     # already at 0.6: never broke
+    s = rep.summary()
+    assert s["retried"] == 1 and s["converged"]
+    off = Server(eng, hbm_budget=10**6, steps_per_tick=1, retry_omega=None).run(
+        [_req(0, BreakingProb(10, 7, 3, _W(0.8)), ft.t)], clock=ft.clock, sleep=ft.sleep)
+    assert off.results[0].status == -4 and off.results[0].retries == 0
+
+
+def test_2d_lanes_are_capped_while_1d_requests_run():
+    """Three 2D workers and lanes_2d_busy = 1: while a 1D request iterates only one 2D solve runs
+    at a time; once it is done, up to three run together.  Without the cap all three start."""
+    ft = FakeTime()
+    eng = FakeEngine2D(ft, tick=1e-3, k=4, chunk_time=5e-3)
+    eng.workers_2d = 3
+    reqs = [_req(0, FakeProb(10, 12), 0.0)] + [_req(i, FakeProb2D(8, 4, 4), 0.0) for i in range(1, 7)]
+    rep = Server(eng, hbm_budget=10**6, steps_per_tick=1, lanes_2d_busy=1).run(
+        reqs, clock=ft.clock, sleep=ft.sleep)
+    r = rep.results
+    t1d = r[0].finished
+
+    def running(t):
+        return sum(1 for x in r[1:] if x.admitted <= t < x.finished)
+
+    assert max(running(x.admitted) for x in r[1:] if x.admitted < t1d) == 1
+    assert max(running(x.admitted) for x in r[1:]) == 3
+    many = Server(eng, hbm_budget=10**6, steps_per_tick=1).run(
+        [_req(0, FakeProb(10, 30), ft.t)] + [_req(i, FakeProb2D(8, 4, 4), ft.t) for i in range(1, 4)],
+        clock=ft.clock, sleep=ft.sleep)
+    assert len({round(x.admitted, 9) for x in many.results}) == 1
