@@ -287,40 +287,62 @@ __global__ void __launch_bounds__(3 * kSplitCells) k_smooth2d_split(T *mg, Level
 
 // ---- the four directional sweeps D1-D4 of section 4.2 (eq. 22 in a lexicographic order) ------
 
-// eq. (22) for cell (i, j) in place: r = rhs + the off-diagonal blocks (in stencil order) times the
-// current dU of the neighbours in the grid, dU <- (1 - omega) dU - omega D^{-1} r
-template <typename T, int NB>
-__device__ __forceinline__ void relax_cell(T *mg, const Level2D &L, int i, int j, double omega)
+// eq. (22) for cell (i, j) in place, by a team of TEAM lanes (TEAM >= NB - 1, a power of two
+// within one wavefront): lane m loads off-diagonal block b = m + 1 and the current dU of that
+// neighbour and forms its product, all lanes at once (the loads of a hyperplane are one round
+// trip, not NB - 1 of them); lane 0 of the team then adds the products to rhs in stencil order,
+// skipping neighbours outside the grid, exactly the sequential sum, and writes
+// dU <- (1 - omega) dU - omega D^{-1} r
+template <typename T, int NB, int TEAM>
+__device__ __forceinline__ void relax_cell_team(T *mg, const Level2D &L, int i, int j, double omega, int m)
 {
     const long long n = L.P.M, cc = perm2d(L.P, i, j);
-    const T *Jr = mg + L.J + cc;
-    const T *Ur = mg + L.dU;
-    double r[3];
-#pragma unroll
-    for (int c = 0; c < 3; c++) r[c] = ld2(mg + L.rhs, c * n + cc);
-    // a rolled loop: the sweeps wait on their hyperplanes' barriers, not on these loads, and an
-    // unrolled one would crowd the registers of the kernels it is inlined into
-#pragma unroll 1
-    for (int b = 1; b < NB; b++) {
+    const int b = m + 1;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (b < NB) {
         int di, dj;
         stencil_off(NB, b, di, dj);
         const int pi = i + di, pj = j + dj;
-        if (pi < 0 || pi >= L.nx || pj < 0 || pj >= L.ny) continue;
-        const long long q = perm2d(L.P, pi, pj);
-        const double x0 = (double)Ur[q], x1 = (double)Ur[n + q], x2 = (double)Ur[2 * n + q];
-#pragma unroll
-        for (int c = 0; c < 3; c++)
-            r[c] = r[c] + ((double)Jr[(b * 9 + c * 3 + 0) * n] * x0 + (double)Jr[(b * 9 + c * 3 + 1) * n] * x1 +
-                           (double)Jr[(b * 9 + c * 3 + 2) * n] * x2);
+        if (pi >= 0 && pi < L.nx && pj >= 0 && pj < L.ny) {
+            const T *Jr = mg + L.J + cc;
+            const T *Ur = mg + L.dU;
+            const long long q = perm2d(L.P, pi, pj);
+            const double x0 = (double)Ur[q], x1 = (double)Ur[n + q], x2 = (double)Ur[2 * n + q];
+            a0 = (double)Jr[(b * 9 + 0) * n] * x0 + (double)Jr[(b * 9 + 1) * n] * x1 + (double)Jr[(b * 9 + 2) * n] * x2;
+            a1 = (double)Jr[(b * 9 + 3) * n] * x0 + (double)Jr[(b * 9 + 4) * n] * x1 + (double)Jr[(b * 9 + 5) * n] * x2;
+            a2 = (double)Jr[(b * 9 + 6) * n] * x0 + (double)Jr[(b * 9 + 7) * n] * x1 + (double)Jr[(b * 9 + 8) * n] * x2;
+        }
     }
-    double t[3];
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0, Di[9], d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    if (m == 0) {
+        r0 = ld2(mg + L.rhs, cc);
+        r1 = ld2(mg + L.rhs, n + cc);
+        r2 = ld2(mg + L.rhs, 2 * n + cc);
 #pragma unroll
-    for (int c = 0; c < 3; c++)
-        t[c] = ld2(mg + L.Dinv, (c * 3 + 0) * n + cc) * r[0] + ld2(mg + L.Dinv, (c * 3 + 1) * n + cc) * r[1] +
-               ld2(mg + L.Dinv, (c * 3 + 2) * n + cc) * r[2];
+        for (int e = 0; e < 9; e++) Di[e] = ld2(mg + L.Dinv, e * n + cc);
+        d0 = ld2(mg + L.dU, cc);
+        d1 = ld2(mg + L.dU, n + cc);
+        d2 = ld2(mg + L.dU, 2 * n + cc);
+    }
 #pragma unroll
-    for (int c = 0; c < 3; c++)
-        mg[L.dU + c * n + cc] = (T)((1.0 - omega) * ld2(mg + L.dU, c * n + cc) - omega * t[c]);
+    for (int bb = 1; bb < NB; bb++) {
+        const double v0 = __shfl(a0, bb - 1, TEAM), v1 = __shfl(a1, bb - 1, TEAM), v2 = __shfl(a2, bb - 1, TEAM);
+        int di, dj;
+        stencil_off(NB, bb, di, dj);
+        const int pi = i + di, pj = j + dj;
+        if (pi >= 0 && pi < L.nx && pj >= 0 && pj < L.ny) {
+            r0 = r0 + v0;
+            r1 = r1 + v1;
+            r2 = r2 + v2;
+        }
+    }
+    if (m != 0) return;
+    const double t0 = Di[0] * r0 + Di[1] * r1 + Di[2] * r2;
+    const double t1 = Di[3] * r0 + Di[4] * r1 + Di[5] * r2;
+    const double t2 = Di[6] * r0 + Di[7] * r1 + Di[8] * r2;
+    mg[L.dU + cc] = (T)((1.0 - omega) * d0 - omega * t0);
+    mg[L.dU + n + cc] = (T)((1.0 - omega) * d1 - omega * t1);
+    mg[L.dU + 2 * n + cc] = (T)((1.0 - omega) * d2 - omega * t2);
 }
 
 // nu smoothing iterations of the sweeps D1 (x ascending, y ascending inside), D2 (x descending),
@@ -328,22 +350,25 @@ __device__ __forceinline__ void relax_cell(T *mg, const Level2D &L, int i, int j
 // (i', j') of a sweep (i' the outer index) a cell needs the new values of the coupled cells with
 // A i' + j' smaller and the old ones of those with it larger (A = 1 for the cross and five-point
 // stencils, 3 for the full 21 cells, whose couplings reach (1, -2)); the cells of one hyperplane
-// A i' + j' = h are not coupled, so the hyperplanes run in order, each in parallel: the same
-// result as the sequential sweep, bit for bit.
+// A i' + j' = h are not coupled, so the hyperplanes run in order, each in parallel (a team of
+// lanes per cell): the same result as the sequential sweep, bit for bit.
 template <typename T, int NB>
 __device__ void sweeps_level(T *mg, const Level2D &L, int nu, double omega)
 {
     constexpr int A = NB == 21 ? 3 : 1;
+    constexpr int TEAM = NB == 21 ? 32 : (NB == 9 ? 8 : 4);
+    static_assert(TEAM >= NB - 1 && 64 % TEAM == 0, "a team per cell inside one wavefront");
     const int nx = L.nx, ny = L.ny, H = A * (nx - 1) + ny;
+    const int team = (int)threadIdx.x / TEAM, m = (int)threadIdx.x % TEAM, teams = (int)blockDim.x / TEAM;
     for (int it = 0; it < nu; it++)
         for (int d = 0; d < 4; d++) {
             const bool fi = d == 1 || d == 2, fj = d >= 2;
             for (int h = 0; h < H; h++) {
                 const int lo = h - (ny - 1) > 0 ? (h - (ny - 1) + A - 1) / A : 0;
                 const int hi = nx - 1 < h / A ? nx - 1 : h / A;
-                for (int k = lo + (int)threadIdx.x; k <= hi; k += blockDim.x) {
+                for (int k = lo + team; k <= hi; k += teams) {
                     const int jp = h - A * k;
-                    relax_cell<T, NB>(mg, L, fi ? nx - 1 - k : k, fj ? ny - 1 - jp : jp, omega);
+                    relax_cell_team<T, NB, TEAM>(mg, L, fi ? nx - 1 - k : k, fj ? ny - 1 - jp : jp, omega, m);
                 }
                 __syncthreads();
             }
@@ -351,7 +376,7 @@ __device__ void sweeps_level(T *mg, const Level2D &L, int nu, double omega)
 }
 
 template <typename T, int NB>
-__global__ void __launch_bounds__(256) k_sweeps2d(T *mg, Level2D L, int nu, double omega)
+__global__ void __launch_bounds__(1024) k_sweeps2d(T *mg, Level2D L, int nu, double omega)
 {
     sweeps_level<T, NB>(mg, L, nu, omega);
 }
@@ -883,14 +908,14 @@ hipError_t launch_sweeps2d(void *mg, const Level2D &L, int nu, double omega, int
 {
     const bool f32 = prec == NMG_FP32_MG;
     if (L.nb == 21) {
-        if (f32) hipLaunchKernelGGL((k_sweeps2d<float, 21>), dim3(1), dim3(256), 0, s, (float *)mg, L, nu, omega);
-        else hipLaunchKernelGGL((k_sweeps2d<double, 21>), dim3(1), dim3(256), 0, s, (double *)mg, L, nu, omega);
+        if (f32) hipLaunchKernelGGL((k_sweeps2d<float, 21>), dim3(1), dim3(1024), 0, s, (float *)mg, L, nu, omega);
+        else hipLaunchKernelGGL((k_sweeps2d<double, 21>), dim3(1), dim3(1024), 0, s, (double *)mg, L, nu, omega);
     } else if (L.nb == 9) {
-        if (f32) hipLaunchKernelGGL((k_sweeps2d<float, 9>), dim3(1), dim3(256), 0, s, (float *)mg, L, nu, omega);
-        else hipLaunchKernelGGL((k_sweeps2d<double, 9>), dim3(1), dim3(256), 0, s, (double *)mg, L, nu, omega);
+        if (f32) hipLaunchKernelGGL((k_sweeps2d<float, 9>), dim3(1), dim3(1024), 0, s, (float *)mg, L, nu, omega);
+        else hipLaunchKernelGGL((k_sweeps2d<double, 9>), dim3(1), dim3(1024), 0, s, (double *)mg, L, nu, omega);
     } else {
-        if (f32) hipLaunchKernelGGL((k_sweeps2d<float, 5>), dim3(1), dim3(256), 0, s, (float *)mg, L, nu, omega);
-        else hipLaunchKernelGGL((k_sweeps2d<double, 5>), dim3(1), dim3(256), 0, s, (double *)mg, L, nu, omega);
+        if (f32) hipLaunchKernelGGL((k_sweeps2d<float, 5>), dim3(1), dim3(1024), 0, s, (float *)mg, L, nu, omega);
+        else hipLaunchKernelGGL((k_sweeps2d<double, 5>), dim3(1), dim3(1024), 0, s, (double *)mg, L, nu, omega);
     }
     return hipGetLastError();
 }
