@@ -122,6 +122,13 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libnmg.so not found at {path}: build it with "
                            "`python -m paper_2505_10857_amd.build` (there is no CPU fallback)")
+    # the library binds the HIP runtime by its soname; torch ships its own copy, and importing
+    # torch after the library would put a second runtime in the process (with no devices of its
+    # own to share with the first): torch first, so that the library binds to torch's runtime
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     vp, sz = C.c_void_p, C.c_size_t
     P = C.POINTER

@@ -2,9 +2,11 @@
 // Jacobian (section 3.2-3.3, eq. 12-13) for gfx950.
 //
 // One thread per cell; a 256-cell tile stages U (+2 halo cells per side) in LDS so that the
-// five-cell stencil of eq. (10) is read from HBM once.  Each thread keeps its stencil in
-// registers and evaluates the local residual R_j for the base state and for every column
-// perturbation of the kept blocks.  FP64 division is the costly operation here (a reciprocal
+// five-cell stencil of eq. (10) is read from HBM once.  The residual kernel evaluates R_j per
+// thread; the Jacobian kernel evaluates one face per thread (the unperturbed state and every
+// column perturbation that reaches it) and assembles each row from its faces, taken from the
+// neighbouring lanes (rows within two cells of a side re-evaluate their own stencil with
+// ghosts).  FP64 division is the costly operation here (a reciprocal
 // and several dependent FMAs each), so the formulas are evaluated in algebraically equal forms
 // with few divisions: one per WENO3 reconstruction (the normalised weights combined over a
 // common denominator), one reciprocal per depth and wave-speed difference in the HLL flux,
@@ -104,15 +106,16 @@ __device__ __forceinline__ void hll(double HL, double QL, double HR, double QR, 
     const double sr1 = uL + cL, sr2 = uR + cR;
     const double SL = sl1 < sl2 ? sl1 : sl2;
     const double SR = sr1 > sr2 ? sr1 : sr2;
-    if (SL >= 0.0) {
-        F0 = FL0; F1 = FL1;
-    } else if (SR <= 0.0) {
-        F0 = FR0; F1 = FR1;
-    } else {
-        const double iw = qrcp(SR - SL);
-        F0 = (SR * FL0 - SL * FR0 + SL * SR * (HR - HL)) * iw;
-        F1 = (SR * FL1 - SL * FR1 + SL * SR * (QR - QL)) * iw;
-    }
+    // the HLL average is formed whatever the wave speeds (SR > SL since the celerities are
+    // positive) and the upwind cases select: no branch, so that independent fluxes interleave.
+    // The empty asm statement (no instruction) takes the average as its operand, which keeps
+    // the compiler from moving its evaluation into a branch of its own.
+    const double iw = qrcp(SR - SL);
+    double G0 = (SR * FL0 - SL * FR0 + SL * SR * (HR - HL)) * iw;
+    double G1 = (SR * FL1 - SL * FR1 + SL * SR * (QR - QL)) * iw;
+    asm("" : "+v"(G0), "+v"(G1));
+    F0 = SL >= 0.0 ? FL0 : (SR <= 0.0 ? FR0 : G0);
+    F1 = SL >= 0.0 ? FL1 : (SR <= 0.0 ? FR1 : G1);
 }
 
 // Lagrange weights of the cubic through x_{j-3/2}, x_{j-1/2}, x_{j+1/2}, x_{j+3/2} at the two
@@ -463,6 +466,185 @@ __global__ void __launch_bounds__(64) k_res_finalize(const Inst1D *insts, int ni
 // ---- Jacobian --------------------------------------------------------------------------
 // Column (i, m) of eq. (12) perturbs component m of cell i; the kernel evaluates the local
 // residual of each row for each column of its stencil.
+//
+// Away from the boundaries (no ghost moves with a perturbation) the rows share their faces: the
+// face k+1/2 between cells k and k+1 reads the four cells k-1..k+2 (its left state is cell k's
+// minus reconstruction over k-1..k+1, its right state cell k+1's plus reconstruction over
+// k..k+2), and the rows of cells k and k+1 both need its flux for the unperturbed state and for
+// a perturbation of any of those cells (a column of either row), with identical operands.  So
+// one lane evaluates one face, for the unperturbed state and each of the eight perturbations
+// (four cells, two components), and each row is assembled from its two faces' fluxes and, for
+// the source of eq. (9), the H states of four faces, taken from the neighbouring lanes.  Every
+// flux, state and source is formed from the same operands by the same operations as when a row
+// re-evaluates its own stencil, so the rows are those of the per-row evaluation bit for bit,
+// with 9 instead of 14 flux evaluations and 16 instead of 40 reconstructions per row (J3).
+
+// Fluxes and H states of one face k+1/2.
+struct FaceVals {
+    double fb0, fb1;     // flux, unperturbed
+    double fh[4][2];     // flux with H of cell k-1+o perturbed, o = 0..3
+    double fq[4][2];     // flux with Q of cell k-1+o perturbed
+    double hl[4];        // left H state: unperturbed, then with cell k-1+o perturbed (index 1+o, o = 0..2)
+    double hr[4];        // right H state: unperturbed, then with cell k-1+o perturbed (index o, o = 1..3)
+};
+
+// cells k-1..k+2 of face k+1/2 from the staged tile (cells a-2 .. a+kTile+1; zeros beyond);
+// SURF: surface values H + zbar
+template <bool SURF>
+__device__ __forceinline__ void face_stencil(const Inst1D &I, const double *sH, const double *sQ, int a, int k,
+                                             double h[4], double q[4])
+{
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
+        const int st = k - 1 + p - (a - 2);
+        const bool in = st >= 0 && st < kTile + 4;
+        h[p] = in ? sH[st] : 0.0;
+        q[p] = in ? sQ[st] : 0.0;
+        if (SURF) {
+            const int z = k + 1 + p;   // z_avg holds cells -2..N+1 at index cell + 2
+            h[p] = h[p] + ((z >= 0 && z <= I.N + 3) ? I.z_avg[z] : 0.0);
+        }
+    }
+}
+
+// width (and its reciprocal) or bottom of face k+1/2 (face k+1 of the face arrays)
+template <bool SURF>
+__device__ __forceinline__ void face_geom(const Inst1D &I, int k, double &sig, double &isig, double &zf)
+{
+    const int f = k + 1;
+    const bool in = f >= 0 && f <= I.N;
+    if (SURF) {
+        sig = isig = 1.0;
+        zf = in ? I.z_face[f] : 0.0;
+    } else {
+        sig = in ? I.sig_face[f] : 1.0;
+        isig = qrcp(sig);
+        zf = 0.0;
+    }
+}
+
+template <bool SURF>
+__device__ __forceinline__ void face_flux(double hl, double ql, double hr, double qr, double sig, double isig,
+                                          double zf, double g, double &f0, double &f1)
+{
+    if (SURF) hll(hl - zf, ql, hr - zf, qr, 1.0, 1.0, g, f0, f1);
+    else hll(hl, ql, hr, qr, sig, isig, g, f0, f1);
+}
+
+template <bool SURF>
+__device__ __forceinline__ void face_eval(const double h[4], const double q[4], double sig, double isig, double zf,
+                                          double eps, double g, FaceVals &F)
+{
+    const double HL = weno_minus(h[0], h[1], h[2]), HR = weno_plus(h[1], h[2], h[3]);
+    const double QL = weno_minus(q[0], q[1], q[2]), QR = weno_plus(q[1], q[2], q[3]);
+    face_flux<SURF>(HL, QL, HR, QR, sig, isig, zf, g, F.fb0, F.fb1);
+    F.hl[0] = HL;
+    F.hr[0] = HR;
+#pragma unroll
+    for (int o = 0; o < 4; o++) {
+        double x[4];
+#pragma unroll
+        for (int p = 0; p < 4; p++) x[p] = p == o ? h[p] + eps : h[p];
+        const double hl = o <= 2 ? weno_minus(x[0], x[1], x[2]) : HL;
+        const double hr = o >= 1 ? weno_plus(x[1], x[2], x[3]) : HR;
+        if (o <= 2) F.hl[1 + o] = hl;
+        if (o >= 1) F.hr[o] = hr;
+        face_flux<SURF>(hl, QL, hr, QR, sig, isig, zf, g, F.fh[o][0], F.fh[o][1]);
+    }
+#pragma unroll
+    for (int o = 0; o < 4; o++) {
+        double y[4];
+#pragma unroll
+        for (int p = 0; p < 4; p++) y[p] = p == o ? q[p] + eps : q[p];
+        const double ql = o <= 2 ? weno_minus(y[0], y[1], y[2]) : QL;
+        const double qr = o >= 1 ? weno_plus(y[1], y[2], y[3]) : QR;
+        face_flux<SURF>(HL, ql, HR, qr, sig, isig, zf, g, F.fq[o][0], F.fq[o][1]);
+    }
+}
+
+// Faces a tile needs beyond one per lane: the right face of its last cell (k = a+255, all nine
+// states), the left H states of face a+256 and the right H states of face a-2 (the outer nodes of
+// the first and last cells' source cubics).  Item 0..8: face a+255 unperturbed, H of cell k-1+o
+// perturbed (items 1..4), Q perturbed (5..8); items 9..12: left H state of face a+256,
+// unperturbed then o = 0..2; items 13..16: right H state of face a-2, unperturbed then o = 1..3.
+// Every item runs the same operations (four reconstructions and one flux), each lane one item.
+constexpr int kFaceExtras = 17;
+
+template <bool SURF>
+__device__ __forceinline__ void face_extra(const Inst1D &I, const double *sH, const double *sQ, int a, int item,
+                                           double eps, FaceVals &last, double *hl_after, double *hr_before)
+{
+    int k, oh = -1, oq = -1;
+    if (item <= 8) {
+        k = a + kTile - 1;
+        if (item >= 1 && item <= 4) oh = item - 1;
+        else if (item >= 5) oq = item - 5;
+    } else if (item <= 12) {
+        k = a + kTile;
+        if (item >= 10) oh = item - 10;
+    } else {
+        k = a - 2;
+        if (item >= 14) oh = item - 13;
+    }
+    double h[4], q[4], x[4], y[4];
+    face_stencil<SURF>(I, sH, sQ, a, k, h, q);
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
+        x[p] = p == oh ? h[p] + eps : h[p];
+        y[p] = p == oq ? q[p] + eps : q[p];
+    }
+    const double HL = weno_minus(x[0], x[1], x[2]), HR = weno_plus(x[1], x[2], x[3]);
+    const double QL = weno_minus(y[0], y[1], y[2]), QR = weno_plus(y[1], y[2], y[3]);
+    double sig, isig, zf, f0, f1;
+    face_geom<SURF>(I, k, sig, isig, zf);
+    face_flux<SURF>(HL, QL, HR, QR, sig, isig, zf, I.g, f0, f1);
+    if (item == 0) {
+        last.fb0 = f0; last.fb1 = f1; last.hl[0] = HL; last.hr[0] = HR;
+    } else if (item <= 4) {
+        last.fh[oh][0] = f0; last.fh[oh][1] = f1;
+        if (oh <= 2) last.hl[1 + oh] = HL;
+        if (oh >= 1) last.hr[oh] = HR;
+    } else if (item <= 8) {
+        last.fq[oq][0] = f0; last.fq[oq][1] = f1;
+    } else if (item <= 12) {
+        hl_after[item - 9] = HL;
+    } else {
+        hr_before[item - 13] = HR;
+    }
+}
+
+// a wavefront-wide shift of v by one lane with a DPP move on each 32-bit half: CTRL 0x130 gives
+// every lane the value of lane + 1, 0x138 that of lane - 1 (the lane past the end receives 0)
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// the value v of lane + 1 of the wavefront (its last lane: `edge`, the next face kept in LDS)
+__device__ __forceinline__ double from_right(double v, int lane, double edge)
+{
+    const double s = wave_shift<0x130>(v);
+    return lane == 63 ? edge : s;
+}
+
+// the value of lane + 2 (lanes 62 and 63: the next two faces' values from LDS)
+__device__ __forceinline__ double from_right2(double v, int lane, double edge1, double edge2)
+{
+    const double s = wave_shift<0x130>(wave_shift<0x130>(v));
+    return lane == 62 ? edge1 : (lane == 63 ? edge2 : s);
+}
+
+// the value of lane - 1 (lane 0: the previous face's value from LDS)
+__device__ __forceinline__ double from_left(double v, int lane, double edge)
+{
+    const double s = wave_shift<0x138>(v);
+    return lane == 0 ? edge : s;
+}
+
 
 __device__ __forceinline__ void inv2d(const double A[4], double B[4])
 {
@@ -506,81 +688,130 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
     __shared__ double sH[kTile + 4], sQ[kTile + 4];
     __shared__ double rows[kTile * NB * 4];
     __shared__ double red[kTile / 64];
+    __shared__ FaceVals next_face[kTile / 64];       // the face after each wavefront's last face
+    __shared__ double next_hl2[kTile / 64][4];       // left H states of the face after that
+    __shared__ double prev_hr[kTile / 64][4];        // right H states of the face before the first
     stage_state<true>(I, a, sH, sQ);   // the state, geometry and residual: last use this step
     __syncthreads();
     const int t = threadIdx.x;
     const int j = a + t;
+    const int lane = t & 63, wv = t >> 6;
     constexpr int HW = NB / 2;
     double *myrow = &rows[t * NB * 4];   // this cell's block row, in LDS
 #pragma unroll
     for (int e = 0; e < NB * 4; e++) myrow[e] = 0.0;
+    const double eps = I.eps, ieps = 1.0 / I.eps;
+
+    // every lane evaluates the face to the left of its cell (k = j - 1); the extra faces of the
+    // tile go to the lanes of the last wavefront
+    FaceVals F;
+    double h2;   // H (SURF: surface) of this lane's cell
+    {
+        double h[4], q[4], sig, isig, zf;
+        face_stencil<SURF>(I, sH, sQ, a, j - 1, h, q);
+        face_geom<SURF>(I, j - 1, sig, isig, zf);
+        face_eval<SURF>(h, q, sig, isig, zf, eps, I.g, F);
+        h2 = h[2];
+    }
+    if (wv >= 1 && lane == 0) next_face[wv - 1] = F;
+    if (wv >= 1 && lane == 1) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) next_hl2[wv - 1][e] = F.hl[e];
+    }
+    if (wv + 1 < kTile / 64 && lane == 63) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) prev_hr[wv + 1][e] = F.hr[e];
+    }
+    if (wv == kTile / 64 - 1 && lane < kFaceExtras)
+        face_extra<SURF>(I, sH, sQ, a, lane, eps, next_face[kTile / 64 - 1], next_hl2[kTile / 64 - 1], prev_hr[0]);
+    __syncthreads();
+
+    const bool valid = j < I.N;
+    const bool interior = j >= 2 && j <= I.N - 3;
+    const CellGeom G = load_geom<SURF, true>(I, valid ? j : I.N - 1);
+    const CubicGauss W;
+    double R0 = 0.0, R1 = 0.0, rn = 0.0;
+    if (!FUSED && valid) {
+        R0 = ldg<true>(&I.R[j]);
+        R1 = ldg<true>(&I.R[I.N + j]);
+        rn = ldg<true>(&I.rn[j]);
+    }
     double n1 = 0.0;   // ||R_j||_1 of this row (FUSED)
-    if (j < I.N) {
-        double H[5], Q[5];
-#pragma unroll
-        for (int p = 0; p < 5; p++) { H[p] = sH[t + p]; Q[p] = sQ[t + p]; }
-        const CellGeom G = load_geom<SURF, true>(I, j);
-        const CubicGauss W;
-        double R0 = 0.0, R1 = 0.0, rn = 0.0;
-        if (!FUSED) {
-            R0 = ldg<true>(&I.R[j]);
-            R1 = ldg<true>(&I.R[I.N + j]);
-            rn = ldg<true>(&I.rn[j]);
+
+    // rows of the interior cells from the faces j-3/2 (lane - 1), j-1/2 (this lane), j+1/2
+    // (lane + 1) and j+3/2 (lane + 2); every lane takes part in the exchanges
+    {
+        const FaceVals &E = next_face[wv];
+        const double Pfb0 = from_right(F.fb0, lane, E.fb0), Pfb1 = from_right(F.fb1, lane, E.fb1);
+        const double Phl0 = from_right(F.hl[0], lane, E.hl[0]);
+        const double PPhl0 = from_right2(F.hl[0], lane, E.hl[0], next_hl2[wv][0]);
+        const double LLhr0 = from_left(F.hr[0], lane, prev_hr[wv][0]);
+        const double S0 = source_term<SURF>(LLhr0, F.hr[0], Phl0, PPhl0, G, W, I.dx, I.g, h2);
+        if (FUSED) {
+            R0 = Pfb0 - F.fb0;
+            R1 = Pfb1 - F.fb1 - S0;
+            n1 = (valid && interior) ? fabs(R0) + fabs(R1) : 0.0;
+            rn = n1;
         }
-        const double eps = I.eps, ieps = 1.0 / I.eps;
-        const bool interior = j >= 2 && j <= I.N - 3;
-        if (interior) {
-            // Away from the boundaries the ghosts do not move: a column of H leaves every Q
-            // reconstruction unchanged and a column of Q every H reconstruction and the
-            // source, so each is formed once for its three (five) columns.  The values are
-            // those of a full re-evaluation, and only one component's reconstructions are
-            // live at a time (register pressure sets the occupancy of this ALU-bound kernel).
-            if (SURF) to_surface(H, I, j);
-            Recon r;
-            recon_Q(Q, r);
-            // the H columns' perturbed residuals, kept in the row until R is known
-#pragma unroll 1
-            for (int b = 0; b < NB; b++) {
-                const int pp = 2 + b - HW;
-                double X[5];
 #pragma unroll
-                for (int p = 0; p < 5; p++) X[p] = p == pp ? H[p] + eps : H[p];
-                recon_H(X, r);
-                const double S = source_term<SURF>(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, I.dx, I.g, X[2]);
-                double P0, P1;
-                assemble_residual<SURF>(r, S, G, I.g, P0, P1);
-                myrow[(b * 2 + 0) * 2 + 0] = P0;
-                myrow[(b * 2 + 1) * 2 + 0] = P1;
+        for (int b = 0; b < NB; b++) {
+            const int d = b - HW;
+            // column (j+d, H): the own face has cell j+d at o = d+2, the right face at o = d+1
+            const double m0 = d + 2 <= 3 ? F.fh[d + 2 < 0 ? 0 : d + 2][0] : F.fb0;
+            const double m1 = d + 2 <= 3 ? F.fh[d + 2 < 0 ? 0 : d + 2][1] : F.fb1;
+            double p0 = Pfb0, p1 = Pfb1;
+            if (d + 1 >= 0) {
+                const int o = d + 1 > 3 ? 3 : d + 1;
+                p0 = from_right(F.fh[o][0], lane, E.fh[o][0]);
+                p1 = from_right(F.fh[o][1], lane, E.fh[o][1]);
             }
-            recon_H(H, r);
-            const double S0 = source_term<SURF>(r.Hp_ll, r.Hp_l, r.Hm_r, r.Hm_rr, G, W, I.dx, I.g, H[2]);
-            if (FUSED) {   // the unperturbed reconstructions and source give R itself
-                assemble_residual<SURF>(r, S0, G, I.g, R0, R1);
-                n1 = fabs(R0) + fabs(R1);
-                rn = n1;
-            }
-#pragma unroll
-            for (int b = 0; b < NB; b++) {
-                double e0 = (myrow[(b * 2 + 0) * 2 + 0] - R0) * ieps, e1 = (myrow[(b * 2 + 1) * 2 + 0] - R1) * ieps;
-                if (b == HW) e0 += I.alpha * rn;
+            // the source's four face states with cell j+d perturbed
+            const double sll = (d + 3 >= 1 && d + 3 <= 3) ? from_left(F.hr[d + 3 < 1 ? 1 : (d + 3 > 3 ? 3 : d + 3)], lane,
+                                                                      prev_hr[wv][d + 3 < 1 ? 1 : (d + 3 > 3 ? 3 : d + 3)])
+                                                          : LLhr0;
+            const double spl = (d + 2 >= 1 && d + 2 <= 3) ? F.hr[d + 2 < 1 ? 1 : (d + 2 > 3 ? 3 : d + 2)] : F.hr[0];
+            const double smr = (d + 2 >= 1 && d + 2 <= 3) ? from_right(F.hl[d + 2 < 1 ? 1 : (d + 2 > 3 ? 3 : d + 2)], lane,
+                                                                       E.hl[d + 2 < 1 ? 1 : (d + 2 > 3 ? 3 : d + 2)])
+                                                          : Phl0;
+            const double smrr = (d + 1 >= 1 && d + 1 <= 3)
+                                    ? from_right2(F.hl[d + 1 < 1 ? 1 : (d + 1 > 3 ? 3 : d + 1)], lane,
+                                                  E.hl[d + 1 < 1 ? 1 : (d + 1 > 3 ? 3 : d + 1)],
+                                                  next_hl2[wv][d + 1 < 1 ? 1 : (d + 1 > 3 ? 3 : d + 1)])
+                                    : PPhl0;
+            const double S = source_term<SURF>(sll, spl, smr, smrr, G, W, I.dx, I.g, d == 0 ? h2 + eps : h2);
+            const double P0 = p0 - m0, P1 = p1 - m1 - S;
+            double e0 = (P0 - R0) * ieps, e1 = (P1 - R1) * ieps;
+            if (d == 0) e0 += I.alpha * rn;
+            if (valid && interior) {
                 myrow[(b * 2 + 0) * 2 + 0] = e0;
                 myrow[(b * 2 + 1) * 2 + 0] = e1;
             }
-#pragma unroll 1
-            for (int b = 0; b < NB; b++) {
-                const int pp = 2 + b - HW;
-                double X[5];
+        }
 #pragma unroll
-                for (int p = 0; p < 5; p++) X[p] = p == pp ? Q[p] + eps : Q[p];
-                recon_Q(X, r);
-                double P0, P1;
-                assemble_residual<SURF>(r, S0, G, I.g, P0, P1);
-                double e0 = (P0 - R0) * ieps, e1 = (P1 - R1) * ieps;
-                if (b == HW) e1 += I.alpha * rn;
+        for (int b = 0; b < NB; b++) {
+            const int d = b - HW;
+            const double m0 = d + 2 <= 3 ? F.fq[d + 2 < 0 ? 0 : d + 2][0] : F.fb0;
+            const double m1 = d + 2 <= 3 ? F.fq[d + 2 < 0 ? 0 : d + 2][1] : F.fb1;
+            double p0 = Pfb0, p1 = Pfb1;
+            if (d + 1 >= 0) {
+                const int o = d + 1 > 3 ? 3 : d + 1;
+                p0 = from_right(F.fq[o][0], lane, E.fq[o][0]);
+                p1 = from_right(F.fq[o][1], lane, E.fq[o][1]);
+            }
+            const double P0 = p0 - m0, P1 = p1 - m1 - S0;
+            double e0 = (P0 - R0) * ieps, e1 = (P1 - R1) * ieps;
+            if (d == 0) e1 += I.alpha * rn;
+            if (valid && interior) {
                 myrow[(b * 2 + 0) * 2 + 1] = e0;
                 myrow[(b * 2 + 1) * 2 + 1] = e1;
             }
-        } else {
+        }
+    }
+    if (valid) {
+        if (!interior) {   // within two cells of a side: full re-evaluation with ghosts
+            double H[5], Q[5];
+#pragma unroll
+            for (int p = 0; p < 5; p++) { H[p] = sH[t + p]; Q[p] = sQ[t + p]; }
             if (FUSED) {   // R from the ghost-complete unperturbed stencil
                 double Hb[5], Qb[5];
 #pragma unroll
