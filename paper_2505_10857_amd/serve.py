@@ -18,7 +18,11 @@ neighbours, so each result is bit for bit the result of solving it alone.
 hundreds of launches, whose enqueueing can wait for queue space on the device, so it must not
 hold up the loop, which only polls for finished 2D requests.  A small 2D grid keeps only a few
 compute units busy (its passes are short chains of dependent launches), so several 2D requests
-in flight at once, and the 1D lane beside them, share the device.
+in flight at once, and the 1D lane beside them, share the device.  Every lane's stream sits on a
+hardware queue of its own, so that no 1D launch waits behind a 2D solve.
+
+A request whose iteration breaks down is retried once with a smaller SOR weight; a run can be
+stopped at a given time, the requests then unfinished being counted.
 
 The Newton and multigrid state of every request stays in device memory from admission to
 retirement; the host only sees the convergence flags.  The engine (device side) is pluggable so
@@ -289,10 +293,12 @@ class Server:
 
     lanes_2d_busy, when set, caps the 2D solves running while 1D requests are waiting or iterating
     (the engine's worker count applies otherwise): a policy for engines whose 2D solves slow the
-    1D batch down (their lanes sharing its hardware queue, or the device full).  retry_omega: a request whose iteration breaks
-    down (a non-finite residual or a non-positive depth) is queued once more, at its arrival, with
-    this SOR weight when its own is larger (a V-cycle that diverges at the larger weight on a
-    strongly varying channel converges at the smaller one); None turns retries off."""
+    1D batch down (their lanes sharing its hardware queue, or the device full).
+
+    retry_omega: a request whose iteration breaks down (a non-finite residual or a non-positive
+    depth) is queued once more, at its arrival, with this SOR weight when its own is larger (a
+    V-cycle that diverges at the larger weight on a strongly varying channel converges at the
+    smaller one); None turns retries off."""
 
     def __init__(self, engine, hbm_budget: int, steps_per_tick: int = 2,
                  keep_states: bool = False, trace: bool = False, lanes_2d_busy: Optional[int] = None,
