@@ -134,8 +134,8 @@ typedef struct {
  * linear (1D): how each Newton step solves the regularised system.  NMG_LINEAR_MG: nu3 V-cycles
  * (Algorithm 2).  NMG_LINEAR_SOR / NMG_LINEAR_SOR_LEX: the Newton-SOR reference solver of
  * section 5.1.1 -- symmetric block SOR steps on the grid itself (multicolour, or the
- * lexicographic forward + backward sweep, which runs one thread per instance and is meant for
- * iteration-count comparisons), stopped once the l1 norm of the change of dU between two
+ * lexicographic forward + backward sweep, which runs one workgroup per instance: one lane sweeps
+ * through LDS chunks that the other lanes stage, for iteration-count comparisons), stopped once the l1 norm of the change of dU between two
  * successive steps (summed over cells and components) falls below sor_tol, or after sor_max
  * steps; levels is then ignored. */
 #define NMG_LINEAR_MG 0

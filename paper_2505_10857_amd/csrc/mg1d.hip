@@ -709,68 +709,151 @@ __global__ void __launch_bounds__(64) k_sor_finalize(const Inst1D *insts, int ni
     if (threadIdx.x == 0 && v < tol) S.sor_done = 1;
 }
 
-// the lexicographic symmetric step (forward then backward sweep) of one instance per thread,
-// with its own stopping test
+// The lexicographic symmetric step (forward then backward sweep, eq. 19) of one instance per
+// workgroup, with its own stopping test.  The sweep is sequential (a cell uses the new values of
+// the cells before it), so one lane performs it, reading from LDS: the workgroup stages it in
+// chunks of kLexChunk cells in sweep order (the off-diagonal blocks, the inverse of the diagonal
+// block -- formed by the loading lanes, not on the sweep's critical path -- the right-hand side
+// and the current dU, plus the dU of HW cells ahead), three wavefronts loading the next chunk
+// into the other buffer while the first lane sweeps the current one.  The sweeping lane keeps
+// the new dU of the last HW cells in registers (the cells behind the next one, also across a
+// chunk edge), and each swept chunk is written back before its buffer is refilled.  The change
+// norm is summed in cell order by one lane from per-cell terms formed in parallel.  Every value
+// and every sum is formed as the sequential sweep over global memory forms it, so the results
+// are the same bit for bit.
+constexpr int kLexChunk = 256;
+
 template <typename T, int NB>
-__global__ void __launch_bounds__(64) k_sor_lex(MGArgs mg, int ninst, int zero_init, double tol)
+__device__ __forceinline__ void lex_load_chunk(const T *base, const Level1D &L, int n, int k, bool fwd, int t0,
+                                               int nt, double (*bJ)[kLexChunk + NB - 1],
+                                               double (*bR)[kLexChunk + NB - 1], double (*bU)[kLexChunk + NB - 1])
 {
     constexpr int HW = NB / 2;
-    const int k = blockIdx.x * 64 + threadIdx.x;
-    if (k >= ninst) return;
-    const Inst1D &I = mg.insts[k];
+    for (int sl = HW + t0; sl < kLexChunk + 2 * HW; sl += nt) {   // the chunk and HW cells ahead
+        const int q = k * kLexChunk - HW + sl;
+        if (q >= n) continue;
+        const int j = fwd ? q : n - 1 - q;
+        bU[0][sl] = ld(base + L.dU, j);
+        bU[1][sl] = ld(base + L.dU, n + (long long)j);
+        if (sl < HW + kLexChunk) {
+            bR[0][sl] = ld(base + L.rhs, j);
+            bR[1][sl] = ld(base + L.rhs, n + (long long)j);
+            double Jd[4], D[4];
+#pragma unroll
+            for (int e = 0; e < NB * 4; e++) {
+                const double v = ld(base + L.J, e * (long long)n + j);
+                if (e >= HW * 4 && e < HW * 4 + 4) Jd[e - HW * 4] = v;
+                else bJ[e][sl] = v;
+            }
+            inv2(Jd, D);   // the diagonal block's slots hold its inverse
+#pragma unroll
+            for (int e = 0; e < 4; e++) bJ[HW * 4 + e][sl] = D[e];
+        }
+    }
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(256) k_sor_lex(MGArgs mg, int zero_init, double tol)
+{
+    constexpr int HW = NB / 2, SL = kLexChunk + 2 * HW;
+    __shared__ double bJ[2][NB * 4][SL], bR[2][2][SL], bU[2][2][SL];
+    const Inst1D &I = mg.insts[blockIdx.x];
     NewtonState *S = mg.state ? &mg.state[I.active_idx] : nullptr;
     if (S && (!S->active || S->sor_done)) return;
     const Level1D L = mg.levs[I.lev0];
     if (L.nb != NB) return;
     T *base = reinterpret_cast<T *>(mg.mg);
-    const int n = L.n;
+    const int n = L.n, t = threadIdx.x;
     const double w = I.omega;
     // keep the iterate before this step in aux (zero at the first step of a Newton step)
-    for (int j = 0; j < n; j++) {
+    for (int j = t; j < n; j += blockDim.x) {
         const double d0 = zero_init ? 0.0 : ld(base + L.dU, j);
         const double d1 = zero_init ? 0.0 : ld(base + L.dU, n + (long long)j);
         base[L.aux + j] = (T)d0;
         base[L.aux + n + (long long)j] = (T)d1;
         if (zero_init) { base[L.dU + j] = (T)0.0; base[L.dU + n + (long long)j] = (T)0.0; }
     }
+    __syncthreads();
+    const int nch = (n + kLexChunk - 1) / kLexChunk;
     for (int pass = 0; pass < 2; pass++) {
-        for (int q = 0; q < n; q++) {
-            const int j = pass == 0 ? q : n - 1 - q;
-            double a0 = ld(base + L.rhs, j), a1 = ld(base + L.rhs, n + (long long)j);
-            double Jd[4];
+        const bool fwd = pass == 0;
+        lex_load_chunk<T, NB>(base, L, n, 0, fwd, t, blockDim.x, bJ[0], bR[0], bU[0]);
+        __syncthreads();
+        // lane 0: the new dU of the last HW cells swept, p[m] at m + 1 positions behind the next
+        double p0[HW], p1[HW];
 #pragma unroll
-            for (int b = 0; b < NB; b++) {
-                const int i = j + b - HW;
-                if (b == HW) {
+        for (int m = 0; m < HW; m++) p0[m] = p1[m] = 0.0;
+        for (int k = 0; k < nch; k++) {
+            const int b = k & 1;
+            if (t == 0) {
+                const int q1 = min(n, (k + 1) * kLexChunk);
+                // unrolled: the loads of the next cells issue while this cell's chain runs
+#pragma unroll 4
+                for (int q = k * kLexChunk; q < q1; q++) {
+                    const int j = fwd ? q : n - 1 - q;
+                    const int sl = q - k * kLexChunk + HW;
+                    double a0 = bR[b][0][sl], a1 = bR[b][1][sl];
 #pragma unroll
-                    for (int e = 0; e < 4; e++) Jd[e] = ld(base + L.J, (b * 4 + e) * (long long)n + j);
-                    continue;
+                    for (int bb = 0; bb < NB; bb++) {
+                        const int i = j + bb - HW;
+                        if (bb == HW || i < 0 || i >= n) continue;
+                        const int off = fwd ? bb - HW : HW - bb;   // position of cell i relative to q
+                        double x0, x1;
+                        if (off < 0) { x0 = p0[-off - 1]; x1 = p1[-off - 1]; }   // swept: its new value
+                        else { x0 = bU[b][0][sl + off]; x1 = bU[b][1][sl + off]; }
+                        a0 = a0 + (bJ[b][bb * 4 + 0][sl] * x0 + bJ[b][bb * 4 + 1][sl] * x1);
+                        a1 = a1 + (bJ[b][bb * 4 + 2][sl] * x0 + bJ[b][bb * 4 + 3][sl] * x1);
+                    }
+                    const double D0 = bJ[b][HW * 4 + 0][sl], D1 = bJ[b][HW * 4 + 1][sl];
+                    const double D2 = bJ[b][HW * 4 + 2][sl], D3 = bJ[b][HW * 4 + 3][sl];
+                    const double t0 = D0 * a0 + D1 * a1;
+                    const double t1 = D2 * a0 + D3 * a1;
+                    const double d0 = bU[b][0][sl], d1 = bU[b][1][sl];
+                    // rounded to the storage type, as the value a sweep over global memory reads back
+                    const double n0 = (double)(T)((1.0 - w) * d0 - w * t0);
+                    const double n1 = (double)(T)((1.0 - w) * d1 - w * t1);
+                    bU[b][0][sl] = n0;
+                    bU[b][1][sl] = n1;
+#pragma unroll
+                    for (int m = HW - 1; m > 0; m--) { p0[m] = p0[m - 1]; p1[m] = p1[m - 1]; }
+                    p0[0] = n0;
+                    p1[0] = n1;
                 }
-                if (i < 0 || i >= n) continue;
-                const double x0 = ld(base + L.dU, i), x1 = ld(base + L.dU, n + (long long)i);
-                a0 = a0 + (ld(base + L.J, (b * 4 + 0) * (long long)n + j) * x0 +
-                           ld(base + L.J, (b * 4 + 1) * (long long)n + j) * x1);
-                a1 = a1 + (ld(base + L.J, (b * 4 + 2) * (long long)n + j) * x0 +
-                           ld(base + L.J, (b * 4 + 3) * (long long)n + j) * x1);
+            } else if (t >= 64 && k + 1 < nch) {
+                lex_load_chunk<T, NB>(base, L, n, k + 1, fwd, t - 64, blockDim.x - 64, bJ[b ^ 1], bR[b ^ 1], bU[b ^ 1]);
             }
-            double D[4];
-            inv2(Jd, D);
-            const double t0 = D[0] * a0 + D[1] * a1;
-            const double t1 = D[2] * a0 + D[3] * a1;
-            const double d0 = ld(base + L.dU, j), d1 = ld(base + L.dU, n + (long long)j);
-            const double n0 = (1.0 - w) * d0 - w * t0;
-            const double n1 = (1.0 - w) * d1 - w * t1;
-            base[L.dU + j] = (T)n0;
-            base[L.dU + n + (long long)j] = (T)n1;
+            __syncthreads();
+            for (int sl = HW + t; sl < HW + kLexChunk; sl += blockDim.x) {   // write the swept chunk back
+                const int q = k * kLexChunk - HW + sl;
+                if (q >= n) continue;
+                const int j = fwd ? q : n - 1 - q;
+                base[L.dU + j] = (T)bU[b][0][sl];
+                base[L.dU + n + (long long)j] = (T)bU[b][1][sl];
+            }
+            __syncthreads();
         }
     }
     // l1 norm of the change over the whole step, cells in order, components interleaved
     double v = 0.0;
-    for (int j = 0; j < n; j++) {
-        v += fabs(ld(base + L.dU, j) - ld(base + L.aux, j));
-        v += fabs(ld(base + L.dU, n + (long long)j) - ld(base + L.aux, n + (long long)j));
+    for (int k = 0; k < nch; k++) {
+        for (int c = t; c < kLexChunk; c += blockDim.x) {
+            const int j = k * kLexChunk + c;
+            if (j < n) {
+                bR[0][0][c] = fabs(ld(base + L.dU, j) - ld(base + L.aux, j));
+                bR[0][1][c] = fabs(ld(base + L.dU, n + (long long)j) - ld(base + L.aux, n + (long long)j));
+            }
+        }
+        __syncthreads();
+        if (t == 0) {
+            const int c1 = min(kLexChunk, n - k * kLexChunk);
+            for (int c = 0; c < c1; c++) {
+                v += bR[0][0][c];
+                v += bR[0][1][c];
+            }
+        }
+        __syncthreads();
     }
-    if (S && v < tol) S->sor_done = 1;
+    if (t == 0 && S && v < tol) S->sor_done = 1;
 }
 
 // eq. (14) after the Newton-SOR steps: U <- U + tau dU on level 0 of every active instance
@@ -844,13 +927,13 @@ hipError_t launch_sor_finalize(const Inst1D *insts, int ninst, NewtonState *stat
 hipError_t launch_sor_lex(const MGArgs &mg, int ninst, int nb_max, int zero_init, double tol, int prec,
                           hipStream_t s)
 {
-    const dim3 grid((ninst + 63) / 64);
+    const dim3 grid(ninst);   // one workgroup per instance
     if (prec == NMG_FP32_MG) {
-        hipLaunchKernelGGL((k_sor_lex<float, 3>), grid, dim3(64), 0, s, mg, ninst, zero_init, tol);
-        if (nb_max == 5) hipLaunchKernelGGL((k_sor_lex<float, 5>), grid, dim3(64), 0, s, mg, ninst, zero_init, tol);
+        hipLaunchKernelGGL((k_sor_lex<float, 3>), grid, dim3(256), 0, s, mg, zero_init, tol);
+        if (nb_max == 5) hipLaunchKernelGGL((k_sor_lex<float, 5>), grid, dim3(256), 0, s, mg, zero_init, tol);
     } else {
-        hipLaunchKernelGGL((k_sor_lex<double, 3>), grid, dim3(64), 0, s, mg, ninst, zero_init, tol);
-        if (nb_max == 5) hipLaunchKernelGGL((k_sor_lex<double, 5>), grid, dim3(64), 0, s, mg, ninst, zero_init, tol);
+        hipLaunchKernelGGL((k_sor_lex<double, 3>), grid, dim3(256), 0, s, mg, zero_init, tol);
+        if (nb_max == 5) hipLaunchKernelGGL((k_sor_lex<double, 5>), grid, dim3(256), 0, s, mg, zero_init, tol);
     }
     return hipGetLastError();
 }

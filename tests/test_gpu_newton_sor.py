@@ -73,3 +73,42 @@ def test_newton_sor_batch_equals_single():
     for k in range(len(probs)):
         assert rs[k][0] == alone[k][1][0]
         assert torch.equal(Us[k], alone[k][0])
+
+
+@pytest.mark.parametrize("n,jac", [(600, 3), (768, 5), (1100, 3)])
+def test_lexicographic_newton_sor_over_several_chunks(n, jac):
+    """The lexicographic sweep staged through LDS in chunks of 256 cells: grids of two to five
+    chunks (ragged last chunks; the five-block stencil carries two cells across each chunk edge);
+    eight Newton-SOR steps, state and residual history against the oracle's within 1e-10."""
+    from paper_2505_10857_amd import Solver1D
+    prob = _sor_problem(e1_problem(n), 2)
+    s = Solver1D(prob, device=DEV, jac=jac, check_every=1, n_max=8)
+    U = s.state()
+    st, hist = s.newton_solve(U, max_hist=8)
+    Uo, ito, reso, hist_o = oracle.Oracle1D(prob).newton_solve(nb=jac, linear=1, smoother=1, sor_max=10,
+                                                            sor_tol=1e-7, n_max=8)
+    err = np.abs(U.cpu().numpy() - Uo).max() / np.abs(Uo).max()
+    print(f"lex Newton-SOR N={n} J{jac}: {st.iters} steps, rel err {err:.2e}, res {hist[-1]:.3e} vs {hist_o[-1]:.3e}")
+    assert st.iters == ito == 8
+    assert err <= 1e-10
+    assert np.all(np.abs(hist - hist_o) <= 1e-10 * np.abs(hist_o) + 1e-14)
+
+
+def test_lexicographic_newton_sor_batch_equals_single():
+    """Instances of different sizes (one and four chunks) in one plan: each result equals its
+    solve alone, bit for bit."""
+    from paper_2505_10857_amd import BatchSolver1D
+    probs = [_sor_problem(e1_problem(n), 2) for n in (96, 1000, 384)]
+    probs = [dataclasses.replace(p, params=dataclasses.replace(p.params, n_max=6)) for p in probs]
+    alone = []
+    for p in probs:
+        b = BatchSolver1D([p], device=DEV)
+        Us = b.states()
+        r = b.solve(Us, use_graph=False)
+        alone.append((Us[0].clone(), r[0]))
+    mix = BatchSolver1D(probs, device=DEV)
+    Us = mix.states()
+    rs = mix.solve(Us, use_graph=True)
+    for k in range(len(probs)):
+        assert rs[k][0] == alone[k][1][0]
+        assert torch.equal(Us[k], alone[k][0])
