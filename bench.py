@@ -97,6 +97,8 @@ def parse():
                     help="run only the NMGM-21 against NMGM-9 form (Table 5 assembly times, wedge solves)")
     ap.add_argument("--wedge2d-only", action="store_true",
                     help="run only the end-to-end 2D wedge form and print it")
+    ap.add_argument("--table2-only", action="store_true",
+                    help="run only the Table 2 form (E1, NMGM-3 / NMGM-5 / lexicographic Newton-SOR)")
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--served-budget-gib", type=int, default=16)
     return ap.parse_args()
@@ -491,6 +493,48 @@ def wedge2d_form():
     return out
 
 
+def table2_form():
+    """Section 5.1.1's Table 2 setting on the GPU: E1 (smooth subcritical flow over the bump of
+    eq. 26) on 96, 192, 384 and 768 cells, each grid started from the Appendix A interpolation of
+    the steady state on half as many cells, solved to res < 1e-11 by NMGM-3, NMGM-5 (4 levels,
+    nu1 = nu2 = nu3 = 2, omega = 1, multicolour block SOR) and Newton-SOR with the lexicographic
+    symmetric sweep (at most 10 steps per Newton step, stopped at an l1 change below 1e-7):
+    Newton steps and milliseconds per solve, beside the printed counts (FP64)."""
+    import dataclasses
+    import torch
+    from paper_2505_10857_amd import NMG_FP64, Solver1D
+    from paper_2505_10857_amd.solver import interp_coarse_to_fine
+    from swe_workloads import e1_problem
+    printed = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "e1_table2.txt")):
+        if line.strip() and not line.startswith("#"):
+            v = line.split()
+            printed[int(v[0])] = {"newton_sor": int(v[1]), "nmgm5": int(v[2]), "nmgm3": int(v[3])}
+    solvers = {"nmgm3": (3, {}), "nmgm5": (5, {}),
+               "newton_sor_lex": (3, dict(linear=2, sor_max=10, sor_tol=1e-7))}
+    out = {}
+    for n in (96, 192, 384, 768):
+        sc = Solver1D(e1_problem(n // 2), device="cuda:0", precision=NMG_FP64, check_every=1)
+        Uc = sc.state()
+        stc, _ = sc.newton_solve(Uc)
+        U0 = interp_coarse_to_fine(Uc)
+        row = {"coarse_steps": stc.iters, "printed_newton_steps": printed.get(n)}
+        for name, (jac, over) in solvers.items():
+            prob = e1_problem(n)
+            prob = dataclasses.replace(prob, params=dataclasses.replace(prob.params, **over))
+            s = Solver1D(prob, device="cuda:0", jac=jac, precision=NMG_FP64, check_every=1)
+            U = U0.clone()
+            s.newton_solve(U.clone())                      # warm-up (allocations, module loads)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, _ = s.newton_solve(U)
+            torch.cuda.synchronize()
+            row[name] = {"newton_steps": st.iters, "status": st.status, "res": st.res,
+                         "ms_per_solve": (time.perf_counter() - t0) * 1e3}
+        out[str(n)] = row
+    return out
+
+
 def nmgm21_form():
     """NMGM-21 against NMGM-9 (section 4.1, Table 5's comparison): the time of one Jacobian
     assembly, full J21 against simplified J9, on the parabolic bump at Table 5's three grids and on
@@ -564,6 +608,9 @@ def main():
         return
     if args.nmgm21_only:
         print(json.dumps({"nmgm21_vs_nmgm9": nmgm21_form()}))
+        return
+    if args.table2_only:
+        print(json.dumps({"table2_e1": table2_form()}))
         return
     use_graph = not args.no_graph
     probs = make_batch(args.batch, args.n, args.levels, args.variant)
@@ -739,6 +786,8 @@ def main():
             del sb
         log("form fp64_cfg1_nmgm3_vs_newton_sor")
         forms["fp64_cfg1_nmgm3_vs_newton_sor"] = cmp1
+        log("form table2_e1")
+        forms["table2_e1"] = table2_form()
         # transcritical hump (q = 1.53, h_out = 0.66): out of reach of plain Newton from the flat
         # surface; nested iteration (Algorithm 3) over the 8 grids 100 .. 12800, batched per grid
         from paper_2505_10857_amd.solver import NestedBatch

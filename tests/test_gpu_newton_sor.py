@@ -112,3 +112,32 @@ def test_lexicographic_newton_sor_batch_equals_single():
     for k in range(len(probs)):
         assert rs[k][0] == alone[k][1][0]
         assert torch.equal(Us[k], alone[k][0])
+
+
+@pytest.mark.parametrize("n", [96, 192])
+def test_table2_setting_step_counts_match_the_oracle(n):
+    """Table 2's setting (E1, the Appendix A start from the steady state on n/2 cells, res <
+    1e-11): NMGM-3 with the multicolour smoother and Newton-SOR with the lexicographic sweep take
+    the oracle's Newton steps (within one) and reach its state within 1e-10."""
+    from paper_2505_10857_amd import Solver1D
+    from paper_2505_10857_amd.solver import interp_coarse_to_fine
+    sc = Solver1D(e1_problem(n // 2), device=DEV, check_every=1)
+    Uc = sc.state()
+    sc.newton_solve(Uc)
+    U0 = interp_coarse_to_fine(Uc)
+    Uc_o, _, rc, _ = oracle.Oracle1D(e1_problem(n // 2)).newton_solve()
+    U0_o = oracle.interp_a2(Uc_o)
+    assert np.abs(U0.cpu().numpy() - U0_o).max() <= 1e-10
+    for lin, kw in ((0, dict(smoother=0)), (2, dict(smoother=1, linear=1, sor_max=10, sor_tol=1e-7))):
+        prob = e1_problem(n)
+        if lin:
+            prob = _sor_problem(prob, lin)
+        s = Solver1D(prob, device=DEV, check_every=1)
+        U = U0.clone()
+        st, _ = s.newton_solve(U)
+        Uo, ito, reso, _ = oracle.Oracle1D(prob).newton_solve(U0=U0_o, **kw)
+        err = np.abs(U.cpu().numpy() - Uo).max()
+        print(f"N={n} linear={lin}: GPU {st.iters} steps, oracle {ito}; |dU| {err:.2e}")
+        assert st.status == 0 and reso < 1e-11
+        assert abs(st.iters - ito) <= 1
+        assert err <= 1e-10
