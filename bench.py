@@ -36,12 +36,18 @@ RIDGE_FLOP_PER_BYTE = FP64_VECTOR_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
 # and sqrt counts one): ten WENO3 reconstructions (22 each), two HLL fluxes (46 each), the
 # two-point Gauss source (36) and the final differences (3).
 FLOPS_LOCAL_RESIDUAL = 10 * 22 + 2 * 46 + 36 + 3
-# FP64 operations the J3 Jacobian kernel performs per interior cell: the H columns (three) each
-# reconstruct H six times, form the source and two HLL fluxes, the Q reconstructions being formed
-# once (4 x 22); the H reconstructions and the source then once more (6 x 22 + 36) for the Q
-# columns, which each reconstruct Q four times and form two fluxes; four operations per column
-# form the difference quotients.  Boundary cells (four per instance) re-evaluate everything.
-FLOPS_JACOBIAN_J3 = (4 * 22) + 3 * (6 * 22 + 36 + 2 * 46 + 3 + 4) + (6 * 22 + 36) + 3 * (4 * 22 + 2 * 46 + 3 + 4)
+# FP64 operations the J3 Jacobian kernel performs per interior cell, as its source states them
+# (the compiler shares more: a Q-perturbed flux reuses both sides' depths and celerities).  Each
+# lane evaluates one face: 16 WENO3 reconstructions (the unperturbed four, then one or two per
+# perturbation of the four cells k-1..k+2, two components), 9 HLL fluxes and the reciprocal of the
+# face width; the tile's 17 extra face items (four reconstructions and a flux each) are shared by
+# its 256 cells.  The row then forms the unperturbed source (36) and, per H column, a perturbed
+# source, the two flux differences (3) and the two difference quotients (4); per Q column the
+# differences and quotients; and the alpha ||R_j||_1 term.  Boundary cells (four per instance)
+# re-evaluate everything.
+FLOPS_FACE = 16 * 22 + 9 * 46 + 1
+FLOPS_FACE_EXTRAS = 17 * (4 * 22 + 46 + 1) / 256
+FLOPS_JACOBIAN_J3 = FLOPS_FACE + FLOPS_FACE_EXTRAS + 36 + 3 * (36 + 3 + 4) + 3 * (3 + 4) + 2
 # residual kernel: read U 16 and the geometry 56, write R 16 and rn 8 per cell
 BYTES_RESIDUAL = 16 + 56 + 16 + 8
 # Algorithmic HBM bytes per cell and launch (FP64, J3):
@@ -50,10 +56,10 @@ BYTES_RESIDUAL = 16 + 56 + 16 + 8
 #   l = 1..8 of 2^-l coarse cells per fine cell)
 BYTES_JACOBIAN_J3 = 16 + 16 + 8 + 56 + 96 + 16 + 96 * (1.0 - 2.0 ** -8)
 # the Jacobian launch that also evaluates the residual (the plan's default order): R and rn are
-# not read, and the unperturbed reconstructions and source give R with one more pair of HLL
-# fluxes and the norm
+# not read, and the unperturbed fluxes of the row's two faces and the source give R (3) and its
+# norm (1)
 BYTES_JACOBIAN_J3_FUSED = BYTES_JACOBIAN_J3 - 16 - 8
-FLOPS_JACOBIAN_J3_FUSED = FLOPS_JACOBIAN_J3 + (2 * 46 + 3) + 2
+FLOPS_JACOBIAN_J3_FUSED = FLOPS_JACOBIAN_J3 + 3 + 1
 # HBM traffic of the Jacobian kernel measured with rocprofv3 counters (profiles/), valid while
 # the kernel source is the one it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobian_j3_fp64_hump12800_batch256_traffic.txt")
