@@ -634,12 +634,110 @@ struct Bottom2DArgs {
     int sweeps;          // smoother: 0 the multicolour schedule, 1 the directional sweeps D1-D4
 };
 
+// The merged colour passes of one five-point level of at most blockDim.x slots, with each
+// thread's operator row (the four neighbour blocks, D^{-1} and the right-hand side) held in
+// registers for all of them and dU in LDS (su, [3][M], each value rounded to the storage type as
+// in memory): a pass then reads its neighbours from LDS instead of the level's arrays.  The
+// operations of smooth_slot, in its order, so the results are the same bit for bit.
+template <typename T>
+__device__ void bottom_smooth5_resident(T *mg, const Level2D &L, int nu, double omega, double *su)
+{
+    constexpr int C = 2;
+    const int W = L.P.W;
+    const long long n = L.P.M, slots = (long long)L.P.ny * W;
+    const int t = threadIdx.x;
+    const int colour = (int)(t / slots);
+    const long long p = t - colour * slots;
+    const int j = (int)(p / W), k = (int)(p - (long long)j * W);
+    const int i = ((colour - j) % C + C) % C + C * k;
+    const bool mine = t < n && i < L.nx;
+    const long long cc = t;   // colour * ny * W + p
+    double Jb[5][9], Di[9], rh[3];
+    int q[5];
+    bool ok[5];
+    if (mine) {
+#pragma unroll
+        for (int b = 1; b < 5; b++) {
+            int di, dj;
+            stencil_off(5, b, di, dj);
+            const int pi = i + di, pj = j + dj;
+            ok[b] = pi >= 0 && pi < L.nx && pj >= 0 && pj < L.ny;
+            const int c2 = ((pi + pj) % C + C) % C;
+            const int ic = ((c2 - pj) % C + C) % C;
+            q[b] = ok[b] ? (int)((long long)c2 * L.ny * W + (long long)pj * W + (pi - ic) / C) : (int)cc;
+#pragma unroll
+            for (int e = 0; e < 9; e++) Jb[b][e] = ld2(mg + L.J, (b * 9 + e) * n + cc);
+        }
+#pragma unroll
+        for (int e = 0; e < 9; e++) Di[e] = ld2(mg + L.Dinv, e * n + cc);
+#pragma unroll
+        for (int c = 0; c < 3; c++) rh[c] = ld2(mg + L.rhs, c * n + cc);
+    }
+    for (long long e = t; e < 3 * n; e += blockDim.x) su[e] = ld2(mg + L.dU, e);
+    __syncthreads();
+    int cur = -1, run = 0;
+    for (int it = 0; it <= nu; it++) {
+        for (int half = 0; half < 4; half++)
+            for (int qq = 0; qq < C; qq++) {
+                const bool last = it == nu;
+                const int c = (half & 1) ? C - 1 - qq : qq;
+                if (!last && c == cur) { run++; continue; }
+                if (run > 0) {
+                    if (mine && colour == cur) {
+                        double x[5][3], a[5][3];
+#pragma unroll
+                        for (int b = 1; b < 5; b++)
+#pragma unroll
+                            for (int cm = 0; cm < 3; cm++) x[b][cm] = su[cm * n + q[b]];
+#pragma unroll
+                        for (int b = 1; b < 5; b++)
+#pragma unroll
+                            for (int cm = 0; cm < 3; cm++)
+                                a[b][cm] = Jb[b][cm * 3 + 0] * x[b][0] + Jb[b][cm * 3 + 1] * x[b][1] + Jb[b][cm * 3 + 2] * x[b][2];
+                        double r[3];
+#pragma unroll
+                        for (int cm = 0; cm < 3; cm++) {
+                            r[cm] = rh[cm];
+#pragma unroll
+                            for (int b = 1; b < 5; b++)
+                                if (ok[b]) r[cm] = r[cm] + a[b][cm];
+                        }
+#pragma unroll
+                        for (int cm = 0; cm < 3; cm++) {
+                            const double tt = Di[cm * 3 + 0] * r[0] + Di[cm * 3 + 1] * r[1] + Di[cm * 3 + 2] * r[2];
+                            T d = (T)su[cm * n + cc];
+                            for (int rr = 0; rr < run; rr++) d = (T)((1.0 - omega) * (double)d - omega * tt);
+                            su[cm * n + cc] = (double)d;
+                        }
+                    }
+                    __syncthreads();
+                }
+                if (last) {
+                    for (long long e = t; e < 3 * n; e += blockDim.x) mg[L.dU + e] = (T)su[e];
+                    __syncthreads();
+                    return;
+                }
+                cur = c;
+                run = 1;
+            }
+    }
+}
+
 // NBF: the stencil of the bottom's first level (the finest level when the whole hierarchy fits
 // one workgroup, else a five-point level); the levels below it have five points.  Only the
 // passes a launch can meet are compiled into it, which keeps the kernel's registers down.
+// Five-point levels that fit the workgroup keep their operator in registers (su: LDS for dU),
+// except in the kernel whose first level has the full 21-cell stencil, whose registers that
+// would overflow.
 template <typename T, int NBF>
-__device__ void bottom_smooth(T *mg, const Level2D &L, int nu, double omega, int sweeps)
+__device__ void bottom_smooth(T *mg, const Level2D &L, int nu, double omega, int sweeps, double *su)
 {
+    if constexpr (NBF != 21) {
+        if (!sweeps && L.nb == 5 && L.P.M <= (long long)blockDim.x) {
+            bottom_smooth5_resident<T>(mg, L, nu, omega, su);
+            return;
+        }
+    }
     if (sweeps) {
         if (NBF != 5 && L.nb == NBF) sweeps_level<T, NBF>(mg, L, nu, omega);
         else sweeps_level<T, 5>(mg, L, nu, omega);
@@ -674,9 +772,10 @@ __global__ void __launch_bounds__(512) k_bottom2d(T *mg, Bottom2DArgs B)
     constexpr int MM = 3 * kMaxCoarse2D;
     __shared__ double A[MM * MM];
     __shared__ double x[MM];
+    __shared__ double su[3 * 512];   // dU of a five-point level held in LDS (at most 512 slots)
     const int last = B.levels - 1;
     for (int l = B.first; l < last; l++) {
-        bottom_smooth<T, NBF>(mg, B.L[l], B.nu1, B.omega, B.sweeps);
+        bottom_smooth<T, NBF>(mg, B.L[l], B.nu1, B.omega, B.sweeps, su);
         const Level2D &Lc = B.L[l + 1];
         for (int e = threadIdx.x; e < Lc.nx * Lc.ny; e += blockDim.x) restrict_cell(mg, B.L[l], Lc, e % Lc.nx, e / Lc.nx);
         __syncthreads();
@@ -687,7 +786,7 @@ __global__ void __launch_bounds__(512) k_bottom2d(T *mg, Bottom2DArgs B)
         const Level2D &Lf = B.L[l];
         for (int e = threadIdx.x; e < Lf.nx * Lf.ny; e += blockDim.x) prolong_cell(mg, Lf, B.L[l + 1], e % Lf.nx, e / Lf.nx);
         __syncthreads();
-        bottom_smooth<T, NBF>(mg, Lf, B.nu2, B.omega, B.sweeps);
+        bottom_smooth<T, NBF>(mg, Lf, B.nu2, B.omega, B.sweeps, su);
     }
 }
 
