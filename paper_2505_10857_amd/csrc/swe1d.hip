@@ -675,6 +675,27 @@ __device__ __forceinline__ void coarse_from_children(const double *f0, const dou
     }
 }
 
+// v of the lane d places up in the same row of 16 lanes (DPP row shift; d = 1, 2, 4 or 8)
+__device__ __forceinline__ double row_shift_down(double v, int d)
+{
+    switch (d) {
+    case 1: return wave_shift<0x101>(v);
+    case 2: return wave_shift<0x102>(v);
+    case 4: return wave_shift<0x104>(v);
+    default: return wave_shift<0x108>(v);
+    }
+}
+
+// one coarse row (W, D, E blocks) into the level's operator [3][2][2][n] at cell jc
+template <typename T>
+__device__ __forceinline__ void put_coarse_row(const double r[12], T *Jc, int n, int jc, bool lead)
+{
+    if (lead && jc < n) {
+#pragma unroll
+        for (int e = 0; e < 12; e++) __builtin_nontemporal_store((T)r[e], &Jc[e * (long long)n + jc]);
+    }
+}
+
 // Jacobian rows of one tile.  With `mg` levels (batched path) the tile also writes the finest
 // right-hand side and the coarse operators of all levels that lie inside the tile (up to
 // eight: 256 -> 1 cells).  FUSED: the tile evaluates the residual R_j of its rows itself (the
@@ -692,6 +713,25 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
     __shared__ double next_hl2[kTile / 64][4];       // left H states of the face after that
     __shared__ double prev_hr[kTile / 64][4];        // right H states of the face before the first
     stage_state<true>(I, a, sH, sQ);   // the state, geometry and residual: last use this step
+    int lev_n[8];
+    long long lev_J[8];
+    int nlev = 0;   // coarse levels present (1 .. 8 below the finest, up to the coarsest)
+    {
+        int c = (mg && !L0->coarsest) ? L0->child : -1;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            if (c >= 0) {
+                const Level1D &Lx = mg->levs[c];
+                lev_n[i] = Lx.n;
+                lev_J[i] = Lx.J;
+                nlev = i + 1;
+                c = Lx.coarsest ? -1 : Lx.child;
+            } else {
+                lev_n[i] = 0;
+                lev_J[i] = 0;
+            }
+        }
+    }
     __syncthreads();
     const int t = threadIdx.x;
     const int j = a + t;
@@ -866,52 +906,60 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
     }
     if (!mg || L0->coarsest) return;
 
-    // coarse operators of the levels inside this tile (eq. 17), reduced in LDS; stored with
-    // non-temporal hints: they are read only after the finest level's first smoothing pass,
-    // which should find this tile's fine rows, not these, in the memory-side cache
-    __syncthreads();
+    // coarse operators of the levels inside this tile (eq. 17), stored with non-temporal hints:
+    // they are read only after the finest level's first smoothing pass, which should find this
+    // tile's fine rows, not these, in the memory-side cache.  Levels 1-5 in the first two
+    // wavefronts: thread t forms coarse cell t of level 1 from two fine rows in LDS, and each
+    // further level l pairs the lanes 2^(l-2) apart, the upper lane's row brought over by a DPP
+    // row shift (the pairs stay within rows of 16 lanes); levels 6-8 in the first wavefront from
+    // the eight level-5 rows, passed through LDS.
+    __syncthreads();   // every fine row in LDS
     T *base_mg = reinterpret_cast<T *>(mg->mg);
-    Level1D Lc = mg->levs[L0->child];
-    int cnt = kTile / 2, cstart = a / 2;
-    {
-        const int jc = cstart + t;
-        const bool mine = t < cnt && jc < Lc.n;
-        double Wc[4], Dc[4], Ec[4];
-        if (mine)
-            coarse_from_children<NB>(&rows[(2 * t) * NB * 4], &rows[(2 * t + 1) * NB * 4], Wc, Dc, Ec);
-        __syncthreads();
-        if (mine) {
+    __shared__ double lev5[8 * 12];
+    if (t < 128) {
+        double r[12];
+        coarse_from_children<NB>(&rows[(2 * t) * NB * 4], &rows[(2 * t + 1) * NB * 4], &r[0], &r[4], &r[8]);
+        put_coarse_row(r, base_mg + lev_J[0], lev_n[0], (a >> 1) + t, true);
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                rows[t * 12 + e] = Wc[e]; rows[t * 12 + 4 + e] = Dc[e]; rows[t * 12 + 8 + e] = Ec[e];
-                __builtin_nontemporal_store((T)Wc[e], &base_mg[Lc.J + (0 * 4 + e) * (long long)Lc.n + jc]);
-                __builtin_nontemporal_store((T)Dc[e], &base_mg[Lc.J + (1 * 4 + e) * (long long)Lc.n + jc]);
-                __builtin_nontemporal_store((T)Ec[e], &base_mg[Lc.J + (2 * 4 + e) * (long long)Lc.n + jc]);
+        for (int l = 1; l < 5; l++) {   // level l + 1
+            if (l < nlev) {
+                const int d = 1 << (l - 1);
+                double p[12], q[12];
+#pragma unroll
+                for (int e = 0; e < 12; e++) p[e] = row_shift_down(r[e], d);
+                coarse_from_children<3>(r, p, &q[0], &q[4], &q[8]);
+#pragma unroll
+                for (int e = 0; e < 12; e++) r[e] = q[e];
+                put_coarse_row(r, base_mg + lev_J[l], lev_n[l], (a >> (l + 1)) + (t >> l), (t & (2 * d - 1)) == 0);
             }
         }
-        __syncthreads();
+        if (nlev > 5 && (t & 15) == 0) {
+#pragma unroll
+            for (int e = 0; e < 12; e++) lev5[(t >> 4) * 12 + e] = r[e];
+        }
     }
-    while (!Lc.coarsest && cnt >= 2) {
-        const Level1D Ln = mg->levs[Lc.child];
-        const int nstart = cstart / 2, ncnt = cnt / 2;
-        const int jc = nstart + t;
-        const bool mine = t < ncnt && jc < Ln.n;
-        double Wc[4], Dc[4], Ec[4];
-        if (mine) coarse_from_children<3>(&rows[(2 * t) * 12], &rows[(2 * t + 1) * 12], Wc, Dc, Ec);
-        __syncthreads();
-        if (mine) {
+    if (nlev <= 5) return;
+    __syncthreads();
+    if (t >= 64) return;
+    {
+        const int c = t < 4 ? t : 3;
+        double r[12];
+        coarse_from_children<3>(&lev5[(2 * c) * 12], &lev5[(2 * c + 1) * 12], &r[0], &r[4], &r[8]);
+        put_coarse_row(r, base_mg + lev_J[5], lev_n[5], (a >> 6) + t, t < 4);
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                rows[t * 12 + e] = Wc[e]; rows[t * 12 + 4 + e] = Dc[e]; rows[t * 12 + 8 + e] = Ec[e];
-                __builtin_nontemporal_store((T)Wc[e], &base_mg[Ln.J + (0 * 4 + e) * (long long)Ln.n + jc]);
-                __builtin_nontemporal_store((T)Dc[e], &base_mg[Ln.J + (1 * 4 + e) * (long long)Ln.n + jc]);
-                __builtin_nontemporal_store((T)Ec[e], &base_mg[Ln.J + (2 * 4 + e) * (long long)Ln.n + jc]);
+        for (int l = 6; l < 8; l++) {   // levels 7 and 8
+            if (l < nlev) {
+                const int d = 1 << (l - 6);
+                double p[12], q[12];
+#pragma unroll
+                for (int e = 0; e < 12; e++) p[e] = row_shift_down(r[e], d);
+                coarse_from_children<3>(r, p, &q[0], &q[4], &q[8]);
+#pragma unroll
+                for (int e = 0; e < 12; e++) r[e] = q[e];
+                put_coarse_row(r, base_mg + lev_J[l], lev_n[l], (a >> (l + 1)) + (t >> (l - 5)),
+                               t < 4 && (t & (2 * d - 1)) == 0);
             }
         }
-        __syncthreads();
-        Lc = Ln;
-        cnt = ncnt;
-        cstart = nstart;
     }
 }
 
