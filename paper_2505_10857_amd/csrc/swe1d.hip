@@ -619,8 +619,8 @@ template <int CTRL>
 __device__ __forceinline__ double wave_shift(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
@@ -713,24 +713,16 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
     __shared__ double next_hl2[kTile / 64][4];       // left H states of the face after that
     __shared__ double prev_hr[kTile / 64][4];        // right H states of the face before the first
     stage_state<true>(I, a, sH, sQ);   // the state, geometry and residual: last use this step
+    // the coarse levels inside the tile (up to eight below the finest; an instance's levels are
+    // consecutive in the level table, level l holding N / 2^l cells): their sizes and operator
+    // offsets
+    const int nlev = (mg && !L0->coarsest) ? (I.levels - 1 < 8 ? I.levels - 1 : 8) : 0;
     int lev_n[8];
     long long lev_J[8];
-    int nlev = 0;   // coarse levels present (1 .. 8 below the finest, up to the coarsest)
-    {
-        int c = (mg && !L0->coarsest) ? L0->child : -1;
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            if (c >= 0) {
-                const Level1D &Lx = mg->levs[c];
-                lev_n[i] = Lx.n;
-                lev_J[i] = Lx.J;
-                nlev = i + 1;
-                c = Lx.coarsest ? -1 : Lx.child;
-            } else {
-                lev_n[i] = 0;
-                lev_J[i] = 0;
-            }
-        }
+    for (int i = 0; i < 8; i++) {
+        lev_n[i] = I.N >> (i + 1);
+        lev_J[i] = i < nlev ? mg->levs[I.lev0 + 1 + i].J : 0;
     }
     __syncthreads();
     const int t = threadIdx.x;
