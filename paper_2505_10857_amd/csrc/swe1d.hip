@@ -624,27 +624,34 @@ __device__ __forceinline__ double wave_shift(double v)
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
-// the value v of lane + 1 of the wavefront (its last lane: `edge`, the next face kept in LDS)
-__device__ __forceinline__ double from_right(double v, int lane, double edge)
+// the same shift with the lane past the end keeping `edge` instead (a DPP move whose source lane
+// does not exist leaves its destination as it was)
+template <int CTRL>
+__device__ __forceinline__ double wave_shift_or(double v, double edge)
 {
-    const double s = wave_shift<0x130>(v);
-    return lane == 63 ? edge : s;
+    const long long b = __double_as_longlong(v), e = __double_as_longlong(edge);
+    const int lo = __builtin_amdgcn_update_dpp((int)e, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(e >> 32), (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// the value v of lane + 1 of the wavefront (its last lane: `edge`, the next face kept in LDS)
+__device__ __forceinline__ double from_right(double v, double edge)
+{
+    return wave_shift_or<0x130>(v, edge);
 }
 
 // the value of lane + 2 (lanes 62 and 63: the next two faces' values from LDS)
-__device__ __forceinline__ double from_right2(double v, int lane, double edge1, double edge2)
+__device__ __forceinline__ double from_right2(double v, double edge1, double edge2)
 {
-    const double s = wave_shift<0x130>(wave_shift<0x130>(v));
-    return lane == 62 ? edge1 : (lane == 63 ? edge2 : s);
+    return wave_shift_or<0x130>(wave_shift_or<0x130>(v, edge1), edge2);
 }
 
 // the value of lane - 1 (lane 0: the previous face's value from LDS)
-__device__ __forceinline__ double from_left(double v, int lane, double edge)
+__device__ __forceinline__ double from_left(double v, double edge)
 {
-    const double s = wave_shift<0x138>(v);
-    return lane == 0 ? edge : s;
+    return wave_shift_or<0x138>(v, edge);
 }
-
 
 __device__ __forceinline__ void inv2d(const double A[4], double B[4])
 {
@@ -774,10 +781,10 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
     // (lane + 1) and j+3/2 (lane + 2); every lane takes part in the exchanges
     {
         const FaceVals &E = next_face[wv];
-        const double Pfb0 = from_right(F.fb0, lane, E.fb0), Pfb1 = from_right(F.fb1, lane, E.fb1);
-        const double Phl0 = from_right(F.hl[0], lane, E.hl[0]);
-        const double PPhl0 = from_right2(F.hl[0], lane, E.hl[0], next_hl2[wv][0]);
-        const double LLhr0 = from_left(F.hr[0], lane, prev_hr[wv][0]);
+        const double Pfb0 = from_right(F.fb0, E.fb0), Pfb1 = from_right(F.fb1, E.fb1);
+        const double Phl0 = from_right(F.hl[0], E.hl[0]);
+        const double PPhl0 = from_right2(F.hl[0], E.hl[0], next_hl2[wv][0]);
+        const double LLhr0 = from_left(F.hr[0], prev_hr[wv][0]);
         const double S0 = source_term<SURF>(LLhr0, F.hr[0], Phl0, PPhl0, G, W, I.dx, I.g, h2);
         if (FUSED) {
             R0 = Pfb0 - F.fb0;
@@ -794,19 +801,19 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
             double p0 = Pfb0, p1 = Pfb1;
             if (d + 1 >= 0) {
                 const int o = d + 1 > 3 ? 3 : d + 1;
-                p0 = from_right(F.fh[o][0], lane, E.fh[o][0]);
-                p1 = from_right(F.fh[o][1], lane, E.fh[o][1]);
+                p0 = from_right(F.fh[o][0], E.fh[o][0]);
+                p1 = from_right(F.fh[o][1], E.fh[o][1]);
             }
             // the source's four face states with cell j+d perturbed
-            const double sll = (d + 3 >= 1 && d + 3 <= 3) ? from_left(F.hr[d + 3 < 1 ? 1 : (d + 3 > 3 ? 3 : d + 3)], lane,
+            const double sll = (d + 3 >= 1 && d + 3 <= 3) ? from_left(F.hr[d + 3 < 1 ? 1 : (d + 3 > 3 ? 3 : d + 3)],
                                                                       prev_hr[wv][d + 3 < 1 ? 1 : (d + 3 > 3 ? 3 : d + 3)])
                                                           : LLhr0;
             const double spl = (d + 2 >= 1 && d + 2 <= 3) ? F.hr[d + 2 < 1 ? 1 : (d + 2 > 3 ? 3 : d + 2)] : F.hr[0];
-            const double smr = (d + 2 >= 1 && d + 2 <= 3) ? from_right(F.hl[d + 2 < 1 ? 1 : (d + 2 > 3 ? 3 : d + 2)], lane,
+            const double smr = (d + 2 >= 1 && d + 2 <= 3) ? from_right(F.hl[d + 2 < 1 ? 1 : (d + 2 > 3 ? 3 : d + 2)],
                                                                        E.hl[d + 2 < 1 ? 1 : (d + 2 > 3 ? 3 : d + 2)])
                                                           : Phl0;
             const double smrr = (d + 1 >= 1 && d + 1 <= 3)
-                                    ? from_right2(F.hl[d + 1 < 1 ? 1 : (d + 1 > 3 ? 3 : d + 1)], lane,
+                                    ? from_right2(F.hl[d + 1 < 1 ? 1 : (d + 1 > 3 ? 3 : d + 1)],
                                                   E.hl[d + 1 < 1 ? 1 : (d + 1 > 3 ? 3 : d + 1)],
                                                   next_hl2[wv][d + 1 < 1 ? 1 : (d + 1 > 3 ? 3 : d + 1)])
                                     : PPhl0;
@@ -827,8 +834,8 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
             double p0 = Pfb0, p1 = Pfb1;
             if (d + 1 >= 0) {
                 const int o = d + 1 > 3 ? 3 : d + 1;
-                p0 = from_right(F.fq[o][0], lane, E.fq[o][0]);
-                p1 = from_right(F.fq[o][1], lane, E.fq[o][1]);
+                p0 = from_right(F.fq[o][0], E.fq[o][0]);
+                p1 = from_right(F.fq[o][1], E.fq[o][1]);
             }
             const double P0 = p0 - m0, P1 = p1 - m1 - S0;
             double e0 = (P0 - R0) * ieps, e1 = (P1 - R1) * ieps;
