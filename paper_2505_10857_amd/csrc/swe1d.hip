@@ -489,15 +489,16 @@ struct FaceVals {
 };
 
 // cells k-1..k+2 of face k+1/2 from the staged tile (cells a-2 .. a+kTile+1; zeros beyond);
-// SURF: surface values H + zbar
-template <bool SURF>
+// SURF: surface values H + zbar.  CHECK = false: the caller's faces lie inside the staged cells
+// (a lane's own face, k = a + threadIdx.x - 1, reads staged cells threadIdx.x .. threadIdx.x + 3)
+template <bool SURF, bool CHECK = true>
 __device__ __forceinline__ void face_stencil(const Inst1D &I, const double *sH, const double *sQ, int a, int k,
                                              double h[4], double q[4])
 {
 #pragma unroll
     for (int p = 0; p < 4; p++) {
         const int st = k - 1 + p - (a - 2);
-        const bool in = st >= 0 && st < kTile + 4;
+        const bool in = !CHECK || (st >= 0 && st < kTile + 4);
         h[p] = in ? sH[st] : 0.0;
         q[p] = in ? sQ[st] : 0.0;
         if (SURF) {
@@ -747,7 +748,7 @@ __device__ void jacobian_tile(const Inst1D &I, int a, T *J, int stride, T *rhs,
     double h2;   // H (SURF: surface) of this lane's cell
     {
         double h[4], q[4], sig, isig, zf;
-        face_stencil<SURF>(I, sH, sQ, a, j - 1, h, q);
+        face_stencil<SURF, false>(I, sH, sQ, a, j - 1, h, q);
         face_geom<SURF>(I, j - 1, sig, isig, zf);
         face_eval<SURF>(h, q, sig, isig, zf, eps, I.g, F);
         h2 = h[2];
