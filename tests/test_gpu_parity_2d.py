@@ -53,11 +53,24 @@ def _ragged_channel(nx=56, ny=24):
                      Params(eps=1e-6, omega=0.1, nu1=4, nu2=4, nu3=2), init_state=(1.0, 0.8, 0.0))
 
 
+def _closed_basin(nx=40, ny=24):
+    """Walls on all four sides over a Gaussian mound, flow along both axes: every face of the
+    grid's border takes the wall ghosts; 40 x 24 spans partial residual tiles."""
+    def bottom(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        e = 0.1 * np.exp(-((x - 1.3) ** 2 + (y - 0.9) ** 2))
+        return e, -2.0 * (x - 1.3) * e, -2.0 * (y - 0.9) * e
+    return Problem2D("basin", 0.0, 3.0, 0.0, 2.0, nx, ny, 4, bottom, [BC(BC_WALL)] * 4,
+                     Params(eps=1e-6, omega=0.1, nu1=4, nu2=4, nu3=2), init_state=(1.0, 0.2, -0.1))
+
+
 def _cases():
     yield "wedge32x16", wedge_problem(32, 16)
     yield "wedge64x32", wedge_problem(64, 32, seed=3)
     yield "bump16x8", parabolic_bump_2d(16, 8)
     yield "ragged56x24", _ragged_channel()
+    yield "basin40x24", _closed_basin()
 
 
 CASES = list(_cases())

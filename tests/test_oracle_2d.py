@@ -117,6 +117,32 @@ def test_y_invariant_flow_between_walls():
         assert np.all(R[c] == R[c][0:1, :])
 
 
+def _basin_bottom(x, y):
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    e = 0.1 * np.exp(-((x - 1.3) ** 2 + (y - 0.9) ** 2))
+    return e, -2.0 * (x - 1.3) * e, -2.0 * (y - 0.9) * e
+
+
+def test_mass_rows_telescope_in_a_closed_basin():
+    """Eq. (20) is a flux difference per cell: summed over a grid closed by walls on all four
+    sides (mirrored ghosts, so the mass flux through every wall face is zero), the mass rows
+    R^h_ij dx dy cancel to rounding for any state, on any bottom (the mass equation has no
+    source).  With the right side open the same sum is the outflow through it, far from zero,
+    so the identity is not met by accident.  A flux taken from the wrong face, a sign, or a
+    face length applied to one side only breaks the cancellation."""
+    rng = np.random.default_rng(5)
+    nx, ny = 20, 12
+    U = np.stack([1.0 + 0.2 * rng.uniform(-1, 1, (ny, nx)), 0.3 * rng.uniform(-1, 1, (ny, nx)),
+                  0.3 * rng.uniform(-1, 1, (ny, nx))])
+    closed = _prob(nx, ny, bottom=_basin_bottom, bc=[BC(BC_WALL)] * 4)
+    R = Oracle2D(closed).residual(U)[0]
+    assert abs(R[0].sum()) <= 1e-13 * np.abs(R[0]).sum()
+    open_right = _prob(nx, ny, bottom=_basin_bottom, bc=[BC(BC_WALL), BC(BC_EXTRAP), BC(BC_WALL), BC(BC_WALL)])
+    Ro = Oracle2D(open_right).residual(U)[0]
+    assert abs(Ro[0].sum()) >= 1e-3 * np.abs(Ro[0]).sum()
+
+
 @pytest.mark.parametrize("recon", [0, 1])
 def test_residual_converges_to_cell_average_of_the_pde(recon):
     """R_ij -> (1/|I_ij|) int (F_x + G_y - S) at third order (interior cells, away from ghosts),
